@@ -1,0 +1,103 @@
+"""Oracle geometry: voxel and detector grids, angles, ray samples, kept bins.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Readings of the paper used here (each listed in the design doc):
+* Voxel centres X_i = i - (Nx-1)/2, Y_j = j - (Ny-1)/2 in voxel units; the
+  FFL rotates about z (Sec. 2.2), so the volume is a stack of independent
+  z-slices and z-line k of every angle is voxel row k.
+* Detector (fast-axis) samples u_p = p - (Nu-1)/2.
+* Angles theta_m = m pi / M, equally spaced over [0, 180) (Sec. 3.1).
+* The line integral of eq. ptheta2 is a unit-step Riemann sum over ray samples
+  y_q = q - (Nr-1)/2, Nr the smallest integer >= sqrt(Nx^2+Ny^2) with the
+  parity of Ny, so that at theta = 0 every sample falls on a voxel centre.
+* Kept bins (eq. bcompress, Appendix A's set S): for harmonics k = k_lo..k_hi
+  and offsets d = -D..D, omega_{k,d} = floor(k P + 1/2) + d, ordered k-major,
+  positive frequencies only (the data are a real signal's spectrum).
+"""
+from dataclasses import dataclass, field
+import math
+import numpy as np
+
+
+@dataclass
+class Geometry:
+    nx: int
+    ny: int
+    nz: int
+    n_angles: int
+    n_t: int
+    drive_cycles: float
+    psf_width: float
+    harm_lo: int
+    harm_hi: int
+    half_band: int
+    op_scale: float = 1.0
+    drive_amp: float = None          # default Nu/2: the sweep spans the fast axis
+    n_u: int = None                  # default Nx
+    theta: np.ndarray = None         # default m*pi/M
+    rx_filter: np.ndarray = None     # complex D_Gamma on the kept bins, None = 1
+
+    def __post_init__(self):
+        if self.n_u is None:
+            self.n_u = self.nx
+        if self.drive_amp is None:
+            self.drive_amp = self.n_u / 2.0
+        if self.theta is None:
+            self.theta = np.arange(self.n_angles, dtype=np.float64) * np.pi / self.n_angles
+        self.theta = np.asarray(self.theta, dtype=np.float64)
+        assert self.theta.shape == (self.n_angles,)
+
+    # ---- derived sizes -------------------------------------------------
+    @property
+    def n_lines(self):
+        return self.n_angles * self.nz
+
+    @property
+    def n_bins(self):
+        return (self.harm_hi - self.harm_lo + 1) * (2 * self.half_band + 1)
+
+    @property
+    def n_vox(self):
+        return self.nx * self.ny * self.nz
+
+    def with_scale(self, op_scale):
+        g = Geometry(**{k: getattr(self, k) for k in self.__dataclass_fields__})
+        g.op_scale = float(op_scale)
+        return g
+
+    def slice_geometry(self):
+        """The same scan on a single z-slice (A is the same matrix on every slice)."""
+        g = Geometry(**{k: getattr(self, k) for k in self.__dataclass_fields__})
+        g.nz = 1
+        return g
+
+
+def voxel_centres(n):
+    return np.arange(n, dtype=np.float64) - (n - 1) / 2.0
+
+
+def detector_grid(g):
+    return np.arange(g.n_u, dtype=np.float64) - (g.n_u - 1) / 2.0
+
+
+def ray_samples(g):
+    nr = int(math.ceil(math.sqrt(g.nx * g.nx + g.ny * g.ny)))
+    while nr * nr < g.nx * g.nx + g.ny * g.ny:
+        nr += 1
+    if (nr - g.ny) % 2:
+        nr += 1
+    return np.arange(nr, dtype=np.float64) - (nr - 1) / 2.0
+
+
+def kept_bins(g):
+    """omega_{k,d} = floor(k P + 1/2) + d, k-major; validated to lie in (0, T/2) and be distinct."""
+    out = []
+    for k in range(g.harm_lo, g.harm_hi + 1):
+        c = math.floor(k * g.drive_cycles + 0.5)
+        for d in range(-g.half_band, g.half_band + 1):
+            out.append(c + d)
+    out = np.asarray(out, dtype=np.int64)
+    if out.min() <= 0 or out.max() >= g.n_t // 2 or len(set(out.tolist())) != len(out):
+        raise ValueError("kept bins must be distinct and inside (0, T/2)")
+    return out

@@ -1,0 +1,131 @@
+"""Oracle full operator A = blockdiag(A_DC) [P_theta1; ...; P_thetaM], FP64.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+* ``forward``  -- eq. modelF1 / the definition of A in Sec. 3.3: project every
+                  angle, then apply A_DC (eq. DCmodel) to every FFL line.
+* ``adjoint``  -- A^T = Re(A^H), the exact transpose in <u,v> = Re(u^H v).
+* ``op_norm``  -- ||A||_2 by FP64 power iteration on A^T A.  The paper needs
+                  ||A* A||_2 for its step size (after eq. iters) but does not
+                  say how it is found.  A is the same matrix on every z-slice
+                  (the projector acts slice by slice and every line shares one
+                  scan sequence), so the norm is taken on one slice.
+* ``make_data`` -- synthetic compressed data: clean time signal of a phantom,
+                  plus white Gaussian noise in the time domain with standard
+                  deviation level * max|s_clean|, then compression.
+
+Pins (tests/test_oracle_operator.py): adjoint identity to 1e-12; brute-force
+dense A on 8^3 written from the element formula; precomposed vs time-domain;
+exact z-separability; the one-slice norm equals the full-volume norm.
+"""
+import numpy as np
+
+from . import projector, signal
+
+
+def forward(g, x, precomposed=False):
+    rt = projector.project(g, x).reshape(g.n_lines, g.n_u)
+    if precomposed:
+        return (rt @ signal.line_matrix(g).T).reshape(g.n_angles, g.nz, g.n_bins)
+    return signal.forward(g, rt).reshape(g.n_angles, g.nz, g.n_bins)
+
+
+def adjoint(g, y, precomposed=False):
+    y = np.asarray(y, dtype=np.complex128).reshape(g.n_lines, g.n_bins)
+    if precomposed:
+        lines = np.real(y @ np.conj(signal.line_matrix(g)))
+    else:
+        lines = signal.adjoint(g, y)
+    return projector.backproject(g, lines.reshape(g.n_angles, g.nz, g.n_u))
+
+
+class Operator:
+    """A with its tables built once (C precomposed optional)."""
+
+    def __init__(self, g, precomposed=False):
+        self.g = g
+        self.precomposed = precomposed
+        if precomposed:
+            self.C = signal.line_matrix(g)
+        else:
+            self.K = signal.kernel(g)
+            self.E = signal.dft_matrix(g)
+            # real and imaginary parts kept apart so real signals meet real matrices
+            self.E_re = np.ascontiguousarray(self.E.real)
+            self.E_im = np.ascontiguousarray(self.E.imag)
+
+    def _lines_fwd(self, rt):
+        if self.precomposed:
+            return rt @ self.C.T
+        out = np.empty((rt.shape[0], self.g.n_bins), dtype=np.complex128)
+        for a in range(0, rt.shape[0], 512):
+            s = rt[a:a + 512] @ self.K.T
+            out[a:a + 512] = (s @ self.E_re) + 1j * (s @ self.E_im)
+        return out
+
+    def _lines_adj(self, y):
+        if self.precomposed:
+            return np.real(y @ np.conj(self.C))
+        out = np.empty((y.shape[0], self.g.n_u), dtype=np.float64)
+        for a in range(0, y.shape[0], 512):
+            yb = y[a:a + 512]
+            # Re(y conj(E)^T); contiguous copies keep numpy on its BLAS path
+            h = np.ascontiguousarray(yb.real) @ self.E_re.T + np.ascontiguousarray(yb.imag) @ self.E_im.T
+            out[a:a + 512] = h @ self.K
+        return out
+
+    def forward(self, x):
+        g = self.g
+        rt = projector.project(g, x).reshape(g.n_lines, g.n_u)
+        return self._lines_fwd(rt).reshape(g.n_angles, g.nz, g.n_bins)
+
+    def adjoint(self, y):
+        g = self.g
+        y = np.asarray(y, dtype=np.complex128).reshape(g.n_lines, g.n_bins)
+        lines = self._lines_adj(y)
+        return projector.backproject(g, lines.reshape(g.n_angles, g.nz, g.n_u))
+
+
+def op_norm(g, iters_min=100, iters_max=3000, rtol=1e-10, seed=12345, one_slice=True):
+    """||A||_2 by power iteration on A^T A in FP64 (precomposed lines for speed)."""
+    gs = g.slice_geometry() if one_slice else g
+    op = Operator(gs, precomposed=True)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((gs.nz, gs.ny, gs.nx))
+    x /= np.linalg.norm(x)
+    lam_old = 0.0
+    for it in range(iters_max):
+        y = op.adjoint(op.forward(x))
+        lam = float(np.vdot(x, y).real)
+        x = y / np.linalg.norm(y)
+        if it + 1 >= iters_min and abs(lam - lam_old) <= rtol * abs(lam):
+            break
+        lam_old = lam
+    return float(np.sqrt(lam))
+
+
+def normalised(g, **kw):
+    """The geometry with c_A chosen so that ||A||_2 = 1."""
+    return g.with_scale(1.0 / op_norm(g.with_scale(1.0), **kw))
+
+
+def make_data(g, phantom, noise_level, noise_seed):
+    """Compressed data b (M, Nz, nb) of a phantom with time-domain white noise.
+
+    Also returns the noise standard deviation used.  Noise is drawn line block
+    by line block from one PCG64 stream, in line order, so the result does
+    not depend on the block size.
+    """
+    op = Operator(g)
+    rt = projector.project(g, phantom).reshape(g.n_lines, g.n_u)
+    s_max = 0.0
+    for a in range(0, g.n_lines, 512):
+        s_max = max(s_max, float(np.abs(rt[a:a + 512] @ op.K.T).max()))
+    sigma = noise_level * s_max
+    rng = np.random.default_rng(noise_seed)
+    b = np.empty((g.n_lines, g.n_bins), dtype=np.complex128)
+    for a in range(0, g.n_lines, 512):
+        s = rt[a:a + 512] @ op.K.T
+        s = s + sigma * rng.standard_normal(s.shape)
+        b[a:a + 512] = (s @ op.E_re) + 1j * (s @ op.E_im)
+    return b.reshape(g.n_angles, g.nz, g.n_bins), sigma

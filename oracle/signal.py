@@ -1,0 +1,106 @@
+"""Oracle signal model and harmonic compression, FP64.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Per FFL line l = (angle m, z-row k) with projection rho_theta[l, :]:
+
+1. Time signal (eq. stheta1 with the collinear PSF of Appendix B eq. PSF,
+   B = I):  s[l, n] = c_A v_n sum_p rho_theta[l, p] L'((xi_n - u_p)/w) / w.
+2. Compression (eq. bcompress, eq. DCmodel, Appendix A):
+   b[l, j] = D_Gamma[j] T^{-1/2} sum_n s[l, n] exp(+2 pi i omega_j n / T),
+   the unitary DFT of Appendix A (plus sign, 1/sqrt(N)) restricted to the
+   kept bins, with the receive filter as a diagonal on the kept bins.
+3. Adjoint: the exact transpose of 1-2 in the real inner product
+   <u, v> = Re(u^H v); the paper's projection onto real values (Sec. 3.3,
+   after eq. iters) is what taking Re amounts to.
+
+The DFT phase is formed from the exact integer product (omega_j n) mod T so no
+large float argument reaches sin/cos.
+
+``line_matrix`` precomposes C = D_Gamma F_S V K (shape nb x Nu) -- the same
+operator associated differently -- used only to cross-check the time-domain
+path and to speed up long FP64 reference solves; callers that use it say so.
+
+Pins (tests/test_oracle_signal.py): DFT = sqrt(T) * numpy.fft.ifft; Parseval
+over the full spectrum; |Re(F_S^H z)|^2 = |z|^2 / 2; half-wave symmetry
+(even harmonics vanish) and empty side bins at integer P; adjoint identity;
+precomposed vs time-domain path.
+"""
+import numpy as np
+
+from .geometry import detector_grid, kept_bins
+from .physics import psf_kernel
+
+_LINE_BLOCK = 512  # lines per block, bounds the (lines x T) temporaries
+
+
+def dft_matrix(g, bins=None):
+    """E[n, j] = D_j exp(+2 pi i ((omega_j n) mod T) / T) / sqrt(T), shape (T, nb).
+
+    ``bins`` overrides the kept set (used by the Parseval pin, which needs all
+    T frequencies); the receive filter then is not applied.
+    """
+    w = kept_bins(g) if bins is None else np.asarray(bins, dtype=np.int64)
+    n = np.arange(g.n_t, dtype=np.int64)
+    phase = (n[:, None] * w[None, :]) % g.n_t
+    e = np.exp(2j * np.pi * phase / g.n_t) / np.sqrt(g.n_t)
+    if bins is None and g.rx_filter is not None:
+        e = e * np.asarray(g.rx_filter, dtype=np.complex128)[None, :]
+    return e
+
+
+def kernel(g):
+    return psf_kernel(g.n_t, g.drive_cycles, g.drive_amp, g.psf_width, detector_grid(g), g.op_scale)
+
+
+def time_signal(g, rho_theta, K=None):
+    """s[l, n] for every line, shape (L, T)."""
+    K = kernel(g) if K is None else K
+    return np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u) @ K.T
+
+
+def compress(g, s, E=None):
+    """b[l, j] = sum_n s[l, n] E[n, j]."""
+    E = dft_matrix(g) if E is None else E
+    return np.asarray(s, dtype=np.float64) @ E
+
+
+def forward(g, rho_theta):
+    """Lines (L, Nu) -> compressed data (L, nb), time-domain path, block over lines."""
+    r = np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u)
+    K, E = kernel(g), dft_matrix(g)
+    out = np.empty((r.shape[0], g.n_bins), dtype=np.complex128)
+    for a in range(0, r.shape[0], _LINE_BLOCK):
+        out[a:a + _LINE_BLOCK] = compress(g, time_signal(g, r[a:a + _LINE_BLOCK], K), E)
+    return out
+
+
+def adjoint(g, y):
+    """Compressed data (L, nb) -> lines (L, Nu): Re of the Hermitian transpose."""
+    y = np.asarray(y, dtype=np.complex128).reshape(-1, g.n_bins)
+    K, E = kernel(g), dft_matrix(g)
+    out = np.empty((y.shape[0], g.n_u), dtype=np.float64)
+    for a in range(0, y.shape[0], _LINE_BLOCK):
+        h = np.real(y[a:a + _LINE_BLOCK] @ np.ascontiguousarray(np.conj(E).T))  # transpose of compress
+        out[a:a + _LINE_BLOCK] = h @ K                     # transpose of time_signal
+    return out
+
+
+def line_matrix(g):
+    """C[j, p] = sum_n E[n, j] K[n, p]: the per-line operator, precomposed."""
+    return dft_matrix(g).T @ kernel(g)
+
+
+def information_retained(s, bins):
+    """I(s, S) = sqrt(sum_{w in S} |s_hat_w|^2) / |s| per row (Appendix A).
+
+    Counts both the kept positive bins and their conjugate mirrors, which a
+    real signal carries with the same magnitude.
+    """
+    s = np.atleast_2d(np.asarray(s, dtype=np.float64))
+    n = s.shape[1]
+    sh = np.fft.ifft(s, axis=1) * np.sqrt(n)
+    kept = np.zeros(n, dtype=bool)
+    kept[np.asarray(bins)] = True
+    kept[(n - np.asarray(bins)) % n] = True
+    return np.sqrt((np.abs(sh[:, kept]) ** 2).sum(axis=1)) / np.linalg.norm(s, axis=1)

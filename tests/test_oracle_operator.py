@@ -1,0 +1,127 @@
+"""Pins for oracle.operator: the full A and A^T."""
+import math
+
+import mpmath
+import numpy as np
+
+from oracle import operator, projector
+from oracle.geometry import Geometry
+
+mpmath.mp.dps = 30
+
+
+def _small():
+    # 8^3 volume, 4 angles, T = 256 with P = 5.3333 and bands k = 1..6, +-1
+    return Geometry(nx=8, ny=8, nz=8, n_angles=4, n_t=256, drive_cycles=5.3333, psf_width=1.5,
+                    harm_lo=1, harm_hi=6, half_band=1, op_scale=0.8,
+                    rx_filter=np.exp(0.3j * np.arange(18)) * (1 + 0.05 * np.arange(18)))
+
+
+def _hat(t):
+    return np.maximum(0.0, 1.0 - np.abs(t))
+
+
+def _element_matrix(g):
+    """A[(m,k,j), (k',y,x)] = delta_{kk'} sum_p W_m(p; x, y) C[j, p], written from scratch:
+
+    W_m(p; x, y) = sum_q hat(X_pq - X_x) hat(Y_pq - Y_y)         (bilinear Riemann sum)
+    C[j, p] = D_j T^{-1/2} sum_n e^{+2 pi i w_j n / T} c_A v_n L'((xi_n - u_p)/w)/w
+    with L' from mpmath and the bins floor(k P + 1/2) + d.
+    """
+    n = g.nx
+    nr = 12
+    yq = np.arange(nr) - (nr - 1) / 2
+    u = np.arange(n) - (n - 1) / 2
+    W = []
+    for t in g.theta:
+        X = u[:, None] * math.cos(t) + yq[None, :] * math.sin(t)
+        Y = -u[:, None] * math.sin(t) + yq[None, :] * math.cos(t)
+        W.append(np.einsum("pqi,pqj->pji", _hat(X[:, :, None] - u[None, None, :]),
+                           _hat(Y[:, :, None] - u[None, None, :])).reshape(n, n * n))
+    T, P, a, w = g.n_t, g.drive_cycles, g.drive_amp, g.psf_width
+    bins = [math.floor(k * P + 0.5) + d for k in range(g.harm_lo, g.harm_hi + 1)
+            for d in range(-g.half_band, g.half_band + 1)]
+    C = np.zeros((len(bins), n), dtype=complex)
+    for nn in range(T):
+        ph = 2 * math.pi * P * nn / T
+        xi, v = a * math.sin(ph), a * 2 * math.pi * P / T * math.cos(ph)
+        k_row = np.array([float(1 / mpmath.mpf((xi - up) / w) ** 2 - 1 / mpmath.sinh((xi - up) / w) ** 2)
+                          if abs(xi - up) > 1e-12 else 1 / 3 for up in u])
+        k_row *= g.op_scale * v / w
+        e = np.exp(2j * math.pi * ((np.array(bins) * nn) % T) / T) / math.sqrt(T)
+        C += e[:, None] * k_row[None, :]
+    C *= np.asarray(g.rx_filter)[:, None]
+    nb = len(bins)
+    A = np.zeros((g.n_angles, g.nz, nb, g.nz, n * n), dtype=complex)
+    for m in range(g.n_angles):
+        blk = C @ W[m]                                   # (nb, n*n)
+        for k in range(g.nz):
+            A[m, k, :, k, :] = blk
+    return A.reshape(g.n_angles * g.nz * nb, g.nz * n * n)
+
+
+def test_brute_force_dense_forward_and_adjoint():
+    g = _small()
+    A = _element_matrix(g)
+    op = operator.Operator(g)
+    cols = np.empty_like(A)
+    for c in range(A.shape[1]):
+        e = np.zeros(A.shape[1])
+        e[c] = 1.0
+        cols[:, c] = op.forward(e.reshape(g.nz, g.ny, g.nx)).ravel()
+    assert np.max(np.abs(cols - A)) <= 1e-13 * np.max(np.abs(A))
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    want = np.real(np.conj(A).T @ y)
+    got = op.adjoint(y.reshape(g.n_angles, g.nz, g.n_bins)).ravel()
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+def test_adjoint_identity_1e12():
+    """<A x, y> = <x, A^T y> in the inner product Re(u^H v)."""
+    for g in (_small(),
+              Geometry(nx=32, ny=32, nz=32, n_angles=8, n_t=2048, drive_cycles=2048 / 256 + 1 / 3,
+                       psf_width=2.0, harm_lo=1, harm_hi=15, half_band=2, op_scale=0.02)):
+        rng = np.random.default_rng(21)
+        x = rng.standard_normal((g.nz, g.ny, g.nx))
+        y = rng.standard_normal((g.n_angles, g.nz, g.n_bins)) + 1j * rng.standard_normal((g.n_angles, g.nz, g.n_bins))
+        lhs = np.vdot(operator.forward(g, x), y).real
+        rhs = np.vdot(x, operator.adjoint(g, y))
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_precomposed_equals_time_domain():
+    g = _small()
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((g.nz, g.ny, g.nx))
+    a = operator.forward(g, x)
+    b = operator.forward(g, x, precomposed=True)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
+def test_z_separability_exact_zeros():
+    g = _small()
+    x = np.zeros((g.nz, g.ny, g.nx))
+    x[3] = np.random.default_rng(5).uniform(0, 1, (g.ny, g.nx))
+    b = operator.forward(g, x)
+    assert np.all(b[:, [0, 1, 2, 4, 5, 6, 7], :] == 0)
+    assert np.all(np.abs(b[:, 3, :]) > 0)
+
+
+def test_one_slice_norm_equals_full_norm():
+    g = _small()
+    a = operator.op_norm(g, one_slice=True)
+    b = operator.op_norm(g, one_slice=False)
+    assert abs(a - b) <= 1e-9 * a
+    gn = operator.normalised(g)
+    assert abs(operator.op_norm(gn) - 1.0) <= 1e-9
+
+
+def test_make_data_noise_free_equals_forward():
+    g = _small()
+    rng = np.random.default_rng(6)
+    x = rng.uniform(0, 1, (g.nz, g.ny, g.nx))
+    b, sigma = operator.make_data(g, x, 0.0, 1)
+    assert sigma == 0.0
+    a = operator.forward(g, x)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))

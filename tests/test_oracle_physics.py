@@ -1,0 +1,97 @@
+"""Pins for oracle.physics: Langevin L, L', trajectory/velocity, PSF shape."""
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import physics, signal
+from oracle.geometry import Geometry, detector_grid
+
+mpmath.mp.dps = 40
+
+
+def _mp_L(x):
+    x = mpmath.mpf(x)
+    if x == 0:
+        return mpmath.mpf(0)
+    return mpmath.coth(x) - 1 / x
+
+
+def _mp_Lp(x):
+    x = mpmath.mpf(x)
+    if x == 0:
+        return mpmath.mpf(1) / 3
+    return 1 / x ** 2 - 1 / mpmath.sinh(x) ** 2
+
+
+GRID = np.concatenate([
+    np.linspace(-30, 30, 601),
+    [0.0, 1e-12, -1e-9, 1e-6, -1e-6, 3e-4, 0.0999999, 0.1, 0.1000001, 0.5, 0.999999, 1.0, 1.000001, 700.0, -800.0],
+    np.geomspace(1e-8, 25, 97),
+])
+
+
+def test_langevin_derivative_vs_mpmath():
+    got = physics.langevin_deriv(GRID)
+    want = np.array([float(_mp_Lp(x)) for x in GRID])
+    rel = np.abs(got - want) / np.abs(want)
+    assert rel.max() <= 1e-14, (GRID[rel.argmax()], rel.max())
+
+
+def test_langevin_vs_mpmath():
+    grid = GRID[np.abs(GRID) > 0]
+    got = physics.langevin(grid)
+    want = np.array([float(_mp_L(x)) for x in grid])
+    rel = np.abs(got - want) / np.abs(want)
+    assert rel.max() <= 1e-14, (grid[rel.argmax()], rel.max())
+
+
+def test_langevin_is_odd_derivative_is_even():
+    x = np.linspace(0.01, 20, 333)
+    assert np.array_equal(physics.langevin(-x), -physics.langevin(x))
+    assert np.array_equal(physics.langevin_deriv(-x), physics.langevin_deriv(x))
+
+
+def test_velocity_psf_chain_is_time_derivative_of_magnetisation():
+    """s_n must equal dm/dt at t_n, m(t) = c_A sum_p rho_p L((xi(t)-u_p)/w).
+
+    Complex-step derivative: Im m(t + i h) / h is exact to rounding, so this
+    checks v = xi' (velocity operator V), the 1/w PSF scale and L' against L.
+    """
+    g = Geometry(nx=24, ny=24, nz=1, n_angles=1, n_t=512, drive_cycles=3.7, psf_width=2.5,
+                 harm_lo=1, harm_hi=5, half_band=1, op_scale=1.7)
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.0, 1.0, g.n_u)
+    u = detector_grid(g)
+    s = signal.time_signal(g, rho[None, :])[0]
+    h = 1e-30
+    t = np.arange(g.n_t) + 1j * h
+    dm = physics.magnetisation(t, g.drive_cycles, g.n_t, g.drive_amp, g.psf_width, u, rho,
+                               g.op_scale).imag / h
+    assert np.max(np.abs(s - dm)) <= 1e-12 * np.max(np.abs(dm))
+
+
+def test_psf_single_source_and_fwhm():
+    """A single source gives s_n / v_n = c_A L'((xi_n - u)/w)/w; FWHM of L' is 4.1610 w."""
+    w = 2.0
+    x_half = mpmath.findroot(lambda x: _mp_Lp(x) - mpmath.mpf(1) / 6, 2.0)
+    fwhm = 2 * float(x_half)
+    assert abs(fwhm - 4.1610) < 1e-4
+    # the oracle's L' agrees with the half-maximum point to 1e-14
+    assert abs(physics.langevin_deriv(np.array([float(x_half)]))[0] - 1 / 6) < 1e-14
+    g = Geometry(nx=16, ny=16, nz=1, n_angles=1, n_t=1024, drive_cycles=4.3333, psf_width=w,
+                 harm_lo=1, harm_hi=3, half_band=1, op_scale=0.9)
+    rho = np.zeros(g.n_u)
+    rho[5] = 1.0
+    s = signal.time_signal(g, rho[None, :])[0]
+    xi, v = physics.trajectory(g.n_t, g.drive_cycles, g.drive_amp)
+    u5 = detector_grid(g)[5]
+    ok = np.abs(v) > 1e-3
+    want = g.op_scale * np.array([float(_mp_Lp((a - u5) / w)) for a in xi[ok]]) / w
+    assert np.max(np.abs(s[ok] / v[ok] - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_trajectory_sweep():
+    xi, v = physics.trajectory(4096, 16.0, 8.0)
+    assert abs(xi.max() - 8.0) < 1e-12 and abs(xi.min() + 8.0) < 1e-12
+    # closed-form velocity: a * 2 pi P / T at phase 0
+    assert abs(v[0] - 8.0 * 2 * np.pi * 16.0 / 4096) < 1e-15
