@@ -1,0 +1,225 @@
+/*
+ * mpi3d.h -- C ABI of libmpi3d.so: the compressed 3D field-free-line (FFL)
+ * MPI forward operator A, its adjoint A^T and the Tikhonov solve, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operator (paper Sec. 3.3, the definition of A; eq. modelF1):
+ *
+ *   A = blockdiag(A_DC, ..., A_DC) [P_theta1; ...; P_thetaM]
+ *
+ *   P_theta   parallel-beam projection of the volume along the FFL direction
+ *             rotated by theta about z (Sec. 2.2, eq. qtheta, eq. ptheta2,
+ *             eq. ptheta1): unit-step bilinear ray sums inside each z-slice.
+ *   A_DC      compressed FFL signal model S D_Gamma F V E H B (eq. DCmodel):
+ *             per FFL line, the time signal
+ *               s_n = c_A v_n sum_p rho_theta[p] L'((xi_n - u_p)/w) / w
+ *             (eq. reals0 with the collinear PSF of Appendix B eq. PSF,
+ *             xi_n = a sin(2 pi P n / T), v_n = xi'), followed by the unitary
+ *             DFT of Appendix A (+i sign, T^{-1/2}) restricted to the kept
+ *             harmonic bands (eq. bcompress) and the receive transfer
+ *             function D_Gamma on those bins.
+ *
+ * and the objective solved (Sec. 3.3, eq. nummodel, with T = I):
+ *
+ *   min_x ||A x - b||^2 + lambda ||x||^2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: 0 on success, a negative MPI3D_E* code otherwise.  Functions
+ *   never throw, abort or print.  Argument errors are detected on the host
+ *   before anything is enqueued (MPI3D_EINVAL); a HIP error surfaces as
+ *   MPI3D_EDEVICE.
+ * - Pointers named *_dev are device pointers on the plan's device; all other
+ *   pointers are host pointers.  The caller owns every buffer it passes; the
+ *   library keeps no caller pointer beyond the call, except that a serving
+ *   state (mpi3d_state_create) keeps b, x and the workspace until destroyed.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Work is enqueued asynchronously on it; the call returns before the GPU
+ *   finishes unless stated otherwise.
+ * - No entry point allocates device memory except mpi3d_plan_create (its
+ *   tables).  Operator and solver scratch comes from a caller workspace whose
+ *   size mpi3d_plan_query reports, so an HBM footprint is known up front.
+ * - Layouts.  Volume x: float32 [nz][ny][nx], x index fastest.  Data b:
+ *   complex64 as interleaved float pairs (re, im), [n_angles][nz][n_bins];
+ *   kept bins ordered harmonic-major, offset-minor (see mpi3d_geometry).
+ *   The volume is real, so the adjoint returns Re(A^H b) (the exact transpose
+ *   in the real inner product <u, v> = Re(u^H v)).
+ * - Thread safety.  A plan is read-only after creation and may be used from
+ *   several host threads and streams at once, provided each concurrent call
+ *   has its own workspace.
+ */
+#ifndef MPI3D_H
+#define MPI3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MPI3D_OK = 0,
+    MPI3D_EINVAL = -1,     /* bad argument (sizes, pointers, bins, precision) */
+    MPI3D_ENOMEM = -2,     /* device allocation failed (plan tables), or workspace too small */
+    MPI3D_EDEVICE = -3,    /* a HIP runtime call failed */
+    MPI3D_ENOTSUP = -4,    /* geometry outside the compiled kernel variants */
+    MPI3D_ENONFINITE = -5  /* a solver norm became NaN or infinite */
+};
+
+/* Operator precision.  FP32: projection in fp32, signal contractions on fp32
+ * MFMA.  MIXED: projection gathers read bf16 copies of the volume and of the
+ * line data, the signal contractions run on fp16 MFMA with fp32 accumulation,
+ * per-line power-of-two scaling and per-harmonic-band scaling. */
+enum { MPI3D_FP32 = 0, MPI3D_MIXED = 1 };
+
+/*
+ * Scan geometry and physics (copied at plan creation).
+ *
+ * Volume grid: voxel (i, j, k) centred at (i - (nx-1)/2, j - (ny-1)/2) in the
+ * xy-plane of slice k; the FFL rotates about z (Sec. 2.2), so FFL line
+ * (m, k) of angle m reads slice k.  Detector samples u_p = p - (n_u-1)/2.
+ * Ray samples: unit steps y_q = q - (n_r-1)/2, n_r the smallest integer
+ * >= sqrt(nx^2 + ny^2) with the parity of ny.
+ *
+ * Kept bins: omega_{k,d} = floor(k * drive_cycles + 1/2) + d for
+ * k = harm_lo..harm_hi and d = -half_band..half_band, stored k-major; they
+ * must be distinct and inside (0, n_t/2), else MPI3D_EINVAL.
+ */
+typedef struct {
+    int32_t nx, ny, nz;          /* volume size in voxels, each >= 2 */
+    int32_t n_angles;            /* M >= 1 */
+    const double *theta_rad;     /* host, n_angles FFL angles; NULL = m*pi/M */
+    int32_t n_u;                 /* fast-axis samples per line; 0 = nx */
+    int32_t n_t;                 /* time samples per FFL line T, >= 32 */
+    double drive_cycles;         /* drive periods per line P (> 0) */
+    double drive_amp;            /* drive amplitude a in voxels; 0 = n_u/2 */
+    double psf_width;            /* PSF scale w = H_sat/G0 in voxels (> 0) */
+    int32_t harm_lo, harm_hi;    /* kept harmonics, 1 <= harm_lo <= harm_hi */
+    int32_t half_band;           /* D >= 0: bins omega_k - D .. omega_k + D */
+    const float *rx_filter;      /* host, 2*n_bins floats (re, im) of D_Gamma on
+                                    the kept bins; NULL = 1 */
+    double op_scale;             /* c_A, the global signal scale (> 0) */
+    int32_t precisions;          /* bit mask of (1 << MPI3D_FP32) | (1 << MPI3D_MIXED):
+                                    which operator variants get tables; 0 = FP32 only */
+} mpi3d_geometry;
+
+typedef struct mpi3d_plan mpi3d_plan;
+
+/* Sizes a caller needs to allocate buffers for a plan. */
+typedef struct {
+    int64_t n_vox;              /* nx*ny*nz floats in a volume */
+    int64_t n_lines;            /* n_angles*nz FFL lines */
+    int64_t n_bins;             /* kept bins per line */
+    int64_t n_data_floats;      /* 2*n_lines*n_bins floats in b */
+    int64_t n_proj_floats;      /* n_lines*n_u floats in a projection (mpi3d_project) */
+    int64_t op_ws_bytes;        /* workspace of mpi3d_forward/adjoint/signal_* */
+    int64_t solve_ws_bytes;     /* workspace of mpi3d_solve / a serving state */
+    int64_t table_bytes;        /* device memory held by the plan itself */
+    int64_t history_doubles;    /* per iteration doubles written to a solve history */
+    int32_t n_r;                /* ray samples per projection ray */
+} mpi3d_plan_info;
+
+/* Validates the geometry, builds the FP64 host tables (angles, trajectory,
+ * PSF kernel, bins, twiddles, receive filter, band scales), and uploads them
+ * to `device`.  *out receives the plan; the plan owns its tables. */
+int mpi3d_plan_create(const mpi3d_geometry *geom, int device, mpi3d_plan **out);
+void mpi3d_plan_destroy(mpi3d_plan *plan);
+int mpi3d_plan_query(const mpi3d_plan *plan, mpi3d_plan_info *info);
+
+/* b_dev = A x_dev (complex64, interleaved).  `precision` is MPI3D_FP32 or
+ * MPI3D_MIXED (the latter needs the plan to hold the mixed tables).  ws_dev:
+ * at least op_ws_bytes of device memory, 256-byte aligned. */
+int mpi3d_forward(const mpi3d_plan *plan, int32_t precision, const float *x_dev, float *b_dev,
+                  void *ws_dev, size_t ws_bytes, void *stream);
+
+/* x_dev = A^T b_dev = Re(A^H b_dev).  Same workspace rule as mpi3d_forward. */
+int mpi3d_adjoint(const mpi3d_plan *plan, int32_t precision, const float *b_dev, float *x_dev,
+                  void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Stage entry points, the operator's factors one at a time (FP32 only):
+ *   project      rho_dev[n_angles][nz][n_u] = P x_dev          (eq. ptheta1)
+ *   backproject  x_dev = P^T rho_dev
+ *   signal_fwd   b_dev = A_DC rho_dev, line by line           (eq. DCmodel)
+ *   signal_adj   rho_dev = Re(A_DC^H b_dev)
+ * signal_* need op_ws_bytes of workspace; project/backproject need none. */
+int mpi3d_project(const mpi3d_plan *plan, const float *x_dev, float *rho_dev, void *stream);
+int mpi3d_backproject(const mpi3d_plan *plan, const float *rho_dev, float *x_dev, void *stream);
+int mpi3d_signal_fwd(const mpi3d_plan *plan, int32_t precision, const float *rho_dev, float *b_dev,
+                     void *ws_dev, size_t ws_bytes, void *stream);
+int mpi3d_signal_adj(const mpi3d_plan *plan, int32_t precision, const float *b_dev, float *rho_dev,
+                     void *ws_dev, size_t ws_bytes, void *stream);
+
+/*
+ * Tikhonov least squares by CGLS (the solver of eq. nummodel; T = I):
+ *   r = b - A x, s = A^T r - lambda x, p = s, gamma = |s|^2, then per
+ *   iteration q = A p, alpha = gamma / (|q|^2 + lambda |p|^2),
+ *   x += alpha p, r -= alpha q, s = A^T r - lambda x, beta = |s|^2 / gamma,
+ *   p = s + beta p.
+ * Inner products, alpha, beta and norms are float64 on the device; no host
+ * synchronisation happens between iterations.
+ *
+ * Variants selected by the options:
+ *   clamp_every > 0   after every clamp_every iterations (and after the last)
+ *                     x <- max(x, 0) and CGLS restarts from it (the paper's
+ *                     nonnegativity, Sec. 3.3 after eq. iters).
+ *   precision MIXED   iterative refinement: refine_sweeps sweeps; each starts
+ *                     from the current x with the residual b - A x and the
+ *                     gradient formed by the FP32 operator, then runs
+ *                     inner_iters CGLS iterations with the mixed operator.
+ */
+typedef struct {
+    double lambda;          /* Tikhonov weight (>= 0) */
+    int32_t iters;          /* FP32: total iterations (>= 0) */
+    int32_t clamp_every;    /* 0 = never clamp */
+    int32_t precision;      /* MPI3D_FP32 or MPI3D_MIXED */
+    int32_t refine_sweeps;  /* MIXED only: number of sweeps (>= 1) */
+    int32_t inner_iters;    /* MIXED only: CGLS iterations per sweep (>= 1) */
+    int32_t x0_is_zero;     /* 1: ignore x_dev on entry and start from 0 */
+} mpi3d_solve_opts;
+
+typedef struct {
+    int32_t iters_done;     /* CGLS iterations run */
+    int32_t status;         /* MPI3D_OK or MPI3D_ENONFINITE */
+    double gamma0;          /* |A^T b - lambda x0|^2 at the first start */
+    double gamma;           /* |A^T r - lambda x|^2 at the end (inner operator) */
+} mpi3d_solve_report;
+
+/* x_dev: in = x0 (unless x0_is_zero), out = solution.  ws_dev: at least
+ * solve_ws_bytes.  history_dev: NULL, or device doubles of length
+ * history_doubles * (iterations + restarts + 1) receiving per-iteration
+ * (gamma, delta, alpha, beta) records.  report: NULL, or a host struct filled
+ * after the call synchronises the stream (only then does the call block). */
+int mpi3d_solve(const mpi3d_plan *plan, const float *b_dev, float *x_dev, const mpi3d_solve_opts *opts,
+                void *ws_dev, size_t ws_bytes, double *history_dev, mpi3d_solve_report *report,
+                void *stream);
+
+/*
+ * Serving: one CGLS solve per state, advanced one iteration at a time so a
+ * scheduler can interleave requests that arrive while others run.  A state
+ * keeps its plan, b, x and workspace (all caller-owned) until destroyed; its
+ * vectors and float64 scalars stay on the device for its whole life.
+ *
+ * mpi3d_batch_step runs one iteration (or the restart step that opens a
+ * refinement sweep) of every state in `states`, sharing kernel launches
+ * between states whose plans have the same line geometry (n_u, n_t, bins,
+ * psf, drive): their FFL lines are concatenated into one launch.  Each
+ * line's arithmetic does not depend on which other states share the launch,
+ * so a request's result is bitwise the same alone or batched.
+ */
+typedef struct mpi3d_state mpi3d_state;
+int mpi3d_state_create(const mpi3d_plan *plan, const float *b_dev, float *x_dev,
+                       const mpi3d_solve_opts *opts, void *ws_dev, size_t ws_bytes, mpi3d_state **out);
+int mpi3d_batch_step(mpi3d_state *const *states, int32_t n_states, void *stream);
+/* Host-side progress of a state: steps enqueued so far and whether the
+ * schedule is complete (results final once the stream reaches that point). */
+int mpi3d_state_progress(const mpi3d_state *state, int32_t *iters_done, int32_t *done);
+void mpi3d_state_destroy(mpi3d_state *state);
+
+/* Static description of a status code. */
+const char *mpi3d_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPI3D_H */

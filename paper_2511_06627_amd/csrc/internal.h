@@ -1,0 +1,160 @@
+// Internal declarations of libmpi3d: plan layout, kernel argument blocks and
+// the launch functions each .hip file provides.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/mpi3d.h"
+
+namespace mpi3d {
+
+// ---------------------------------------------------------------------------
+// Fixed tiling constants of the signal kernels.
+//   A wave owns 32 FFL lines (one 32-row MFMA tile); a block of 4 waves owns
+//   128 lines.  Time is consumed in chunks of 32 samples (one MFMA tile of
+//   the time dimension).  Columns of the band table come in tiles of 32.
+// ---------------------------------------------------------------------------
+constexpr int kRowsPerWave = 32;
+constexpr int kWaves = 4;
+constexpr int kRowsPerBlock = kRowsPerWave * kWaves;
+constexpr int kChunk = 32;
+constexpr int kColTile = 32;
+constexpr int kMaxJobs = 16;
+
+// Norm partial slots: every kernel that emits float64 partial sums writes at
+// most this many, one per block.
+constexpr int kMaxNormParts = 4096;
+
+// One batch segment of FFL lines sharing the same line tables.
+struct SigJob {
+    const void *in;        // fwd: projections [rows][nup] (f32); adj: data [rows][2nb] (f32)
+    float *part;           // partial sums, see kernels
+    float *row_scale;      // mixed: per-row power-of-two scale (written by the kernel)
+    int rows;              // FFL lines of this job
+    int tile0;             // first block-row tile of this job in the launch
+    int in_stride;         // floats between consecutive input rows
+    long part_stride;      // floats between consecutive split (x group) partial blocks
+};
+
+struct SigArgs {
+    // tables (device)
+    const float *kf, *ff, *fa, *ka;               // fp32 swizzled tables
+    const __half *kf16, *ff16, *fa16, *ka16;      // fp16 swizzled tables
+    const float *band_scale;                      // [nbp2] adjoint per-column scale (mixed)
+    int nu, nup, nb2, nbp2, nct;                  // sizes (nup, nbp2 padded to 32)
+    int nchunks, cps, nsplit, ngroups, gct;       // chunking and column groups
+    int total_tiles;
+    int njobs;
+    SigJob jobs[kMaxJobs];
+};
+
+// ---------------------------------------------------------------------------
+// Projection argument block.
+// ---------------------------------------------------------------------------
+struct ProjArgs {
+    const float *x;             // volume [nz][ny][nx]
+    const uint16_t *xb;         // mixed: bf16 bits of the volume (or null)
+    float *rt;                  // projections [M][nz][nup]
+    const float *rt_in;         // adjoint input projections [M][nz][nup]
+    float *xo;                  // adjoint output volume
+    const float *x_sub;         // adjoint epilogue: out = acc - lambda * x_sub (null = none)
+    double *norm_parts;         // adjoint epilogue: per-block sum of out^2 (null = none)
+    double lambda;
+    const float2 *cs;           // [M] (cos, sin)
+    const float *ax;            // [M][nu] forward x-coordinate bases
+    const float *ay;            // [M][nu] forward y-coordinate bases
+    int nx, ny, nz, M, nu, nup, nr;
+    int angles_per_block, n_angle_groups, band_rows, n_bands;
+    int kz, n_zgroups, tiles_x, tiles_y;
+    float half_nr, half_nu, cx, cy;
+};
+
+}  // namespace mpi3d
+
+// The plan.  Host copy of the geometry plus device tables and the layout of
+// the caller's workspaces.
+struct mpi3d_plan {
+    int device;
+    int nx, ny, nz, M, nu, nt, nr, nb;
+    int harm_lo, harm_hi, half_band;
+    double P, a, w, op_scale;
+    int precisions;
+    // padded sizes
+    int nup;        // n_u padded to 32
+    int ntp;        // n_t padded to 32
+    int nb2;        // 2*nb real columns
+    int nbp2;       // nb2 padded to 32
+    int nct;        // nbp2 / 32
+    long L;         // lines
+    long nvox;
+    // signal kernel configuration
+    int nchunks, cps, nsplit, ngroups, gct;
+    // projection configuration
+    int angles_per_block, band_rows, n_bands, kz;
+    // device tables (one allocation)
+    void *tables;
+    size_t table_bytes;
+    float2 *cs;
+    float *ax, *ay;
+    float *kf, *ff, *fa, *ka;
+    __half *kf16, *ff16, *fa16, *ka16;
+    float *col_scale;     // [nbp2] mixed forward output scale per column
+    float *band_scale;    // [nbp2] mixed adjoint input scale per column
+    float adj_scale16;    // mixed adjoint output scale
+    // operator workspace layout (bytes from ws base)
+    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, op_ws_bytes;
+    // solver workspace layout
+    size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, solve_ws_bytes;
+};
+
+namespace mpi3d {
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt,
+                          hipStream_t st);
+hipError_t launch_backproject(const mpi3d_plan *pl, const float *rt, float *xo, const float *x_sub,
+                              double lambda, double *norm_parts, int *nparts, hipStream_t st);
+hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
+hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
+int sig_fwd_supported(int nup, int gct, int precision);
+int sig_adj_supported(int nup, int gct, int precision);
+
+// Reductions and vector kernels (vec.hip)
+hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
+                             const float *row_scale, const float *col_scale, const float *b_sub, float *out,
+                             double *norm_parts, int *nnorm, hipStream_t st);
+hipError_t launch_reduce_lines(long rows, int nu, int nup, int nparts, long part_stride, const float *part,
+                               const float *row_scale, float scale, float *out, hipStream_t st);
+hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
+                                       const float *part, const float *row_scale, float scale, float *out,
+                                       hipStream_t st);
+hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st);
+
+// CGLS scalar and vector steps.  `scal` holds the solve's float64 scalars.
+int scal_slots();
+int scal_slot_bad();
+int scal_slot_gamma();
+int scal_slot_gamma0();
+hipError_t launch_scal_init(double *scal, hipStream_t st);
+hipError_t launch_alpha(double *scal, const double *parts_q, int nq, const double *parts_p, int np, double lambda,
+                        double *hist, int step, hipStream_t st);
+hipError_t launch_beta(double *scal, const double *parts_s, int ns, int restart, int first, double *hist, int step,
+                       hipStream_t st);
+hipError_t launch_update_xr2(float *x, const float *p, float *r, const float *q, long nvox, long ndata,
+                             const double *scal, hipStream_t st);
+hipError_t launch_update_p2(float *p, const float *s, uint16_t *pb, long n, const double *scal, double *parts_p,
+                            int *np_out, int init, hipStream_t st);
+hipError_t launch_clamp(float *x, long n, hipStream_t st);
+hipError_t launch_fill(float *x, long n, float v, hipStream_t st);
+hipError_t launch_copy(float *dst, const float *src, long n, hipStream_t st);
+
+// Strided projection launchers (public stage entry points use stride n_u).
+hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st);
+hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,
+                                      const float *x_sub, double lambda, double *norm_parts, int *nparts,
+                                      hipStream_t st);
+
+}  // namespace mpi3d

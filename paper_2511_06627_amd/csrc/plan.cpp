@@ -1,0 +1,482 @@
+// Plan creation: validation, float64 host tables, upload, workspace layout,
+// and the operator entry points of the C ABI (forward, adjoint, stages).
+//
+// Tables follow the paper's factors:
+//   cos/sin of the FFL angles           Sec. 2.2, eq. qtheta
+//   ray-sample coordinate bases          eq. ptheta2 (unit-step Riemann sum)
+//   PSF kernel K[n][p]                   eq. reals0 + Appendix B eq. PSF
+//       = c_A v_n L'((xi_n - u_p)/w) / w, xi_n = a sin(2 pi P n / T), v = xi'
+//   band DFT F[n][2j], F[n][2j+1]        Appendix A (+i, 1/sqrt(T)) on the kept
+//       = Re/Im(D_j e^{+2 pi i (omega_j n mod T)/T}) / sqrt(T)   bins (eq. bcompress,
+//                                        eq. DCmodel)
+// All table values are computed in float64 and rounded once.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mpi3d;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// L'(x) = 1/x^2 - 1/sinh^2 x.  For |x| < 0.5 the Maclaurin series
+// sum_{n>=1} 2^{2n} B_{2n} (2n-1) x^{2n-2} / (2n)! (Bernoulli numbers B_{2n});
+// for larger |x| the closed form, written with e^{-2|x|} so nothing overflows.
+double langevin_deriv(double x)
+{
+    x = std::fabs(x);
+    if (x < 0.5) {
+        static const double bern[] = {1.0 / 6, -1.0 / 30, 1.0 / 42, -1.0 / 30, 5.0 / 66, -691.0 / 2730,
+                                      7.0 / 6, -3617.0 / 510, 43867.0 / 798, -174611.0 / 330};
+        double coef[10];
+        double fact = 1.0, pow4 = 1.0;
+        for (int n = 1; n <= 10; ++n) {
+            fact *= (2.0 * n - 1) * (2.0 * n);
+            pow4 *= 4.0;
+            coef[n - 1] = pow4 * bern[n - 1] * (2.0 * n - 1) / fact;
+        }
+        double x2 = x * x, acc = 0.0;
+        for (int n = 9; n >= 0; --n) acc = acc * x2 + coef[n];
+        return acc;
+    }
+    double e = std::exp(-2.0 * x);
+    return 1.0 / (x * x) - 4.0 * e / ((1.0 - e) * (1.0 - e));
+}
+
+// double -> fp16, rounded once (clang's _Float16 conversion is correctly rounded)
+inline _Float16 to_f16(double v) { return (_Float16)v; }
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Ray samples: smallest n >= sqrt(nx^2 + ny^2) with the parity of ny.
+int ray_count(int nx, int ny)
+{
+    long d2 = (long)nx * nx + (long)ny * ny;
+    int n = (int)std::floor(std::sqrt((double)d2));
+    while ((long)n * n < d2) ++n;
+    while (n > 0 && (long)(n - 1) * (n - 1) >= d2) --n;
+    if ((n - ny) % 2) ++n;
+    return n;
+}
+
+// Choose the T-split so that (row tiles x splits x groups) blocks fill the
+// 256 compute units in as few rounds as possible (one block per CU).
+void choose_split(mpi3d_plan *pl)
+{
+    const int cus = 256;
+    long tiles = (pl->L + kRowsPerBlock - 1) / kRowsPerBlock;
+    int best_s = 1;
+    double best = 1e30;
+    for (int s = 1; s <= pl->nchunks; ++s) {
+        int cps = (pl->nchunks + s - 1) / s;
+        int used = (pl->nchunks + cps - 1) / cps;  // splits actually non-empty
+        long blocks = tiles * used * pl->ngroups;
+        long rounds = (blocks + cus - 1) / cus;
+        // cost: rounds x chunks per block, plus a small charge per split for
+        // the partial-sum traffic
+        double cost = (double)rounds * cps * (1.0 + 0.002 * used);
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_s = used;
+        }
+    }
+    pl->cps = (pl->nchunks + best_s - 1) / best_s;
+    pl->nsplit = (pl->nchunks + pl->cps - 1) / pl->cps;
+}
+
+template <class T>
+T *carve(char *base, size_t &off, size_t count)
+{
+    off = align256(off);
+    T *p = reinterpret_cast<T *>(base + off);
+    off += count * sizeof(T);
+    return p;
+}
+
+}  // namespace
+
+extern "C" const char *mpi3d_strerror(int status)
+{
+    switch (status) {
+    case MPI3D_OK: return "ok";
+    case MPI3D_EINVAL: return "invalid argument";
+    case MPI3D_ENOMEM: return "out of device memory or workspace too small";
+    case MPI3D_EDEVICE: return "HIP runtime error";
+    case MPI3D_ENOTSUP: return "geometry not supported by the compiled kernels";
+    case MPI3D_ENONFINITE: return "non-finite value in a solver norm";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan **out)
+{
+    if (!g || !out) return MPI3D_EINVAL;
+    *out = nullptr;
+    if (g->nx < 2 || g->ny < 2 || g->nz < 1 || g->n_angles < 1 || g->n_t < 32) return MPI3D_EINVAL;
+    if (g->nx > 4096 || g->ny > 4096 || g->nz > 65535 || g->n_angles > 4096 || g->n_t > (1 << 22)) return MPI3D_EINVAL;
+    int nu = g->n_u ? g->n_u : g->nx;
+    if (nu < 2 || nu > 256) return MPI3D_ENOTSUP;
+    if (!(g->drive_cycles > 0) || !(g->psf_width > 0) || !(g->op_scale > 0)) return MPI3D_EINVAL;
+    if (!(g->drive_amp >= 0)) return MPI3D_EINVAL;
+    if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
+    int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
+    if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED))) return MPI3D_EINVAL;
+
+    // kept bins, validated
+    std::vector<long> bins;
+    for (int k = g->harm_lo; k <= g->harm_hi; ++k) {
+        long c = (long)std::floor(k * g->drive_cycles + 0.5);
+        for (int d = -g->half_band; d <= g->half_band; ++d) bins.push_back(c + d);
+    }
+    for (size_t i = 0; i < bins.size(); ++i) {
+        if (bins[i] <= 0 || bins[i] >= g->n_t / 2) return MPI3D_EINVAL;
+        if (i && bins[i] <= bins[i - 1]) return MPI3D_EINVAL;  // increasing => distinct
+    }
+    if (bins.size() > 2048) return MPI3D_ENOTSUP;
+
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return MPI3D_EINVAL;
+
+    mpi3d_plan *pl = new (std::nothrow) mpi3d_plan();
+    if (!pl) return MPI3D_ENOMEM;
+    pl->device = device;
+    pl->nx = g->nx; pl->ny = g->ny; pl->nz = g->nz; pl->M = g->n_angles;
+    pl->nu = nu; pl->nt = g->n_t; pl->nr = ray_count(g->nx, g->ny);
+    pl->nb = (int)bins.size();
+    pl->harm_lo = g->harm_lo; pl->harm_hi = g->harm_hi; pl->half_band = g->half_band;
+    pl->P = g->drive_cycles;
+    pl->a = g->drive_amp > 0 ? g->drive_amp : nu / 2.0;
+    pl->w = g->psf_width;
+    pl->op_scale = g->op_scale;
+    pl->precisions = precisions;
+    pl->nup = round_up(nu, 32);
+    pl->ntp = round_up(g->n_t, kChunk);
+    pl->nb2 = 2 * pl->nb;
+    pl->nbp2 = round_up(pl->nb2, kColTile);
+    pl->nct = pl->nbp2 / kColTile;
+    pl->L = (long)pl->M * pl->nz;
+    pl->nvox = (long)pl->nx * pl->ny * pl->nz;
+    pl->nchunks = pl->ntp / kChunk;
+
+    // column groups: as many 32-wide column tiles per block as registers allow
+    int gmax = pl->nup <= 192 ? 14 : 11;
+    pl->ngroups = (pl->nct + gmax - 1) / gmax;
+    pl->gct = (pl->nct + pl->ngroups - 1) / pl->ngroups;
+    if (!sig_fwd_supported(pl->nup, pl->gct, MPI3D_FP32) || !sig_adj_supported(pl->nup, pl->gct, MPI3D_FP32) ||
+        ((precisions & (1 << MPI3D_MIXED)) &&
+         (!sig_fwd_supported(pl->nup, pl->gct, MPI3D_MIXED) || !sig_adj_supported(pl->nup, pl->gct, MPI3D_MIXED)))) {
+        delete pl;
+        return MPI3D_ENOTSUP;
+    }
+    choose_split(pl);
+
+    // projection configuration
+    {
+        const size_t lds = 160 * 1024;
+        size_t row_bytes = (size_t)(pl->nx + 2) * sizeof(float);
+        int max_rows = (int)(lds / row_bytes) - 1;  // LDS rows = band_rows + 1
+        if (max_rows < 2) { delete pl; return MPI3D_ENOTSUP; }
+        int bases = pl->ny + 1;                     // base rows -1 .. ny-1
+        pl->n_bands = (bases + max_rows - 1) / max_rows;
+        pl->band_rows = (bases + pl->n_bands - 1) / pl->n_bands;
+        // angles per block: enough blocks to cover the GPU about twice
+        int groups_wanted = std::max(1, (int)((512 + pl->nz - 1) / pl->nz));
+        int apb = std::max(1, (pl->M + groups_wanted - 1) / groups_wanted);
+        while (apb > 1 && (long)apb * pl->nu > 256L * 8) --apb;  // rays per thread <= 8
+        pl->angles_per_block = apb;
+        pl->kz = std::min(32, pl->nz);
+    }
+
+    // ---- float64 host tables ------------------------------------------------
+    const int M = pl->M, NU = pl->nu, NUP = pl->nup, T = pl->nt, TP = pl->ntp, NB = pl->nb;
+    const int NBP2 = pl->nbp2, NCT = pl->nct, NC = pl->nchunks;
+    std::vector<double> theta(M);
+    for (int m = 0; m < M; ++m) theta[m] = g->theta_rad ? g->theta_rad[m] : m * kPi / M;
+    for (int m = 0; m < M; ++m)
+        if (!std::isfinite(theta[m])) { delete pl; return MPI3D_EINVAL; }
+    const double cx = 0.5 * (pl->nx - 1), cy = 0.5 * (pl->ny - 1), cu = 0.5 * (NU - 1);
+
+    std::vector<float2> cs(M);
+    std::vector<float> ax((size_t)M * NU), ay((size_t)M * NU);
+    for (int m = 0; m < M; ++m) {
+        double c = std::cos(theta[m]), s = std::sin(theta[m]);
+        cs[m] = make_float2((float)c, (float)s);
+        for (int p = 0; p < NU; ++p) {
+            double up = p - cu;
+            // sample (p, q) sits at x = u_p c + y_q s, y = -u_p s + y_q c; the
+            // kernels add y_q times (s, c) to these bases (LDS column 0 holds
+            // grid column -1, hence the +1).
+            ax[(size_t)m * NU + p] = (float)(up * c + cx + 1.0);
+            ay[(size_t)m * NU + p] = (float)(-up * s + cy);
+        }
+    }
+
+    // PSF kernel K[n][p] (n < T, p < NU; zero padding elsewhere)
+    std::vector<double> K((size_t)TP * NUP, 0.0);
+    {
+        const double om = 2.0 * kPi * pl->P / T;
+        for (int n = 0; n < T; ++n) {
+            double ph = om * n;
+            double xi = pl->a * std::sin(ph), v = pl->a * om * std::cos(ph);
+            for (int p = 0; p < NU; ++p)
+                K[(size_t)n * NUP + p] = pl->op_scale * v * langevin_deriv((xi - (p - cu)) / pl->w) / pl->w;
+        }
+    }
+    // band DFT F[n][c] (real columns: 2j = Re, 2j+1 = Im)
+    std::vector<double> F((size_t)TP * NBP2, 0.0);
+    {
+        const double inv = 1.0 / std::sqrt((double)T);
+        for (int j = 0; j < NB; ++j) {
+            double dre = 1.0, dim = 0.0;
+            if (g->rx_filter) { dre = g->rx_filter[2 * j]; dim = g->rx_filter[2 * j + 1]; }
+            if (!std::isfinite(dre) || !std::isfinite(dim)) { delete pl; return MPI3D_EINVAL; }
+            for (int n = 0; n < T; ++n) {
+                long ph = (long)(((unsigned long long)bins[j] * (unsigned long long)n) % (unsigned long long)T);
+                double a = 2.0 * kPi * (double)ph / T;
+                double c = std::cos(a), s = std::sin(a);
+                F[(size_t)n * NBP2 + 2 * j] = (dre * c - dim * s) * inv;
+                F[(size_t)n * NBP2 + 2 * j + 1] = (dre * s + dim * c) * inv;
+            }
+        }
+    }
+
+    // ---- table layout in one device allocation -----------------------------
+    bool mixed = precisions & (1 << MPI3D_MIXED);
+    size_t off = 0;
+    char *nullbase = nullptr;
+    size_t o_cs, o_ax, o_ay, o_kf, o_ff, o_fa, o_ka, o_kf16 = 0, o_ff16 = 0, o_fa16 = 0, o_ka16 = 0, o_cols = 0, o_bands = 0;
+    auto place = [&](size_t bytes) { off = align256(off); size_t o = off; off += bytes; return o; };
+    o_cs = place(sizeof(float2) * M);
+    o_ax = place(sizeof(float) * M * NU);
+    o_ay = place(sizeof(float) * M * NU);
+    o_kf = place(sizeof(float) * (size_t)TP * NUP);
+    o_ff = place(sizeof(float) * (size_t)TP * NBP2);
+    o_fa = place(sizeof(float) * (size_t)TP * NBP2);
+    o_ka = place(sizeof(float) * (size_t)TP * NUP);
+    if (mixed) {
+        o_kf16 = place(sizeof(__half) * (size_t)TP * NUP);
+        o_ff16 = place(sizeof(__half) * (size_t)TP * NBP2);
+        o_fa16 = place(sizeof(__half) * (size_t)TP * NBP2);
+        o_ka16 = place(sizeof(__half) * (size_t)TP * NUP);
+        o_cols = place(sizeof(float) * NBP2);
+        o_bands = place(sizeof(float) * NBP2);
+    }
+    (void)nullbase;
+    pl->table_bytes = align256(off);
+
+    // Swizzled fp32 tables: every MFMA operand a lane needs for 4 consecutive
+    // steps is one 16-byte load, and a wave's 64 loads are contiguous.
+    //  kf: fwd GEMM1 A operand  K[t = 32c + l%32][p = 2st + l/32]    [c][st/4][l][st%4]
+    //  ff: fwd GEMM2 B operand  F[t = 32c + tperm(s, l/32)][32ct + l%32]  [c][ct][s/4][l][s%4]
+    //  fa: adj GEMM1 A operand  F[t = 32c + l%32][col = 2st + l/32]  [c][st/4][l][st%4]
+    //  ka: adj GEMM2 B operand  K[t = 32c + tperm(s, l/32)][32pt + l%32]  [c][pt][s/4][l][s%4]
+    // tperm(s, h) = 8(s/4) + 4h + s%4 is the time index that the 32x32 MFMA
+    // result layout leaves in register s of lane half h.
+    std::vector<float> kf((size_t)TP * NUP), ff((size_t)TP * NBP2), fa((size_t)TP * NBP2), ka((size_t)TP * NUP);
+    auto tperm = [](int s, int h) { return 8 * (s / 4) + 4 * h + (s % 4); };
+    for (int c = 0; c < NC; ++c) {
+        for (int st = 0; st < NUP / 2; ++st)
+            for (int l = 0; l < 64; ++l)
+                kf[(((size_t)c * (NUP / 8) + st / 4) * 64 + l) * 4 + st % 4] =
+                    (float)K[(size_t)(32 * c + l % 32) * NUP + 2 * st + l / 32];
+        for (int ct = 0; ct < NCT; ++ct)
+            for (int s = 0; s < 16; ++s)
+                for (int l = 0; l < 64; ++l)
+                    ff[((((size_t)c * NCT + ct) * 4 + s / 4) * 64 + l) * 4 + s % 4] =
+                        (float)F[(size_t)(32 * c + tperm(s, l / 32)) * NBP2 + 32 * ct + l % 32];
+        for (int st = 0; st < NBP2 / 2; ++st)
+            for (int l = 0; l < 64; ++l)
+                fa[(((size_t)c * (NBP2 / 8) + st / 4) * 64 + l) * 4 + st % 4] =
+                    (float)F[(size_t)(32 * c + l % 32) * NBP2 + 2 * st + l / 32];
+        for (int pt = 0; pt < NUP / 32; ++pt)
+            for (int s = 0; s < 16; ++s)
+                for (int l = 0; l < 64; ++l)
+                    ka[((((size_t)c * (NUP / 32) + pt) * 4 + s / 4) * 64 + l) * 4 + s % 4] =
+                        (float)K[(size_t)(32 * c + tperm(s, l / 32)) * NUP + 32 * pt + l % 32];
+    }
+
+    // Mixed (fp16) tables with power-of-two scales.
+    std::vector<_Float16> kf16, ff16, fa16, ka16;
+    std::vector<float> col_scale, band_scale;
+    if (mixed) {
+        double kmax = 0, fmax = 0;
+        for (double v : K) kmax = std::max(kmax, std::fabs(v));
+        for (double v : F) fmax = std::max(fmax, std::fabs(v));
+        int ek, ef;
+        std::frexp(kmax > 0 ? kmax : 1.0, &ek);
+        std::frexp(fmax > 0 ? fmax : 1.0, &ef);
+        double ks = std::ldexp(1.0, -ek), fs = std::ldexp(1.0, -ef);  // scaled max in [0.5, 1)
+        // Per-band adjoint scale: a band's share of the operator, measured as
+        // its response to a unit source at each of a few detector positions.
+        std::vector<double> bnorm(NB / (2 * pl->half_band + 1), 0.0);
+        int nbands = (int)bnorm.size(), bw = 2 * pl->half_band + 1;
+        for (int probe = 1; probe <= 3; ++probe) {
+            int p = probe * NU / 4;
+            for (int j = 0; j < NB; ++j) {
+                double re = 0, im = 0;
+                for (int n = 0; n < T; ++n) {
+                    double kv = K[(size_t)n * NUP + p];
+                    re += kv * F[(size_t)n * NBP2 + 2 * j];
+                    im += kv * F[(size_t)n * NBP2 + 2 * j + 1];
+                }
+                bnorm[j / bw] = std::max(bnorm[j / bw], std::sqrt(re * re + im * im));
+            }
+        }
+        double bmax = *std::max_element(bnorm.begin(), bnorm.end());
+        col_scale.assign(NBP2, (float)(1.0 / (ks * fs)));
+        pl->adj_scale16 = (float)(1.0 / (ks * fs));
+        band_scale.assign(NBP2, 1.0f);
+        std::vector<double> fcol(NBP2, fs);
+        for (int b = 0; b < nbands; ++b) {
+            double rel = bnorm[b] > 0 && bmax > 0 ? bnorm[b] / bmax : 1.0;
+            int e;
+            std::frexp(rel, &e);                       // rel in [2^(e-1), 2^e)
+            double bs = std::ldexp(1.0, std::min(-(e - 1), 14));  // lifts the band to [1, 2) x max
+            for (int d = 0; d < bw; ++d)
+                for (int h = 0; h < 2; ++h) {
+                    int col = 2 * (b * bw + d) + h;
+                    band_scale[col] = (float)bs;
+                    fcol[col] = fs / bs;
+                }
+        }
+        // fp16 layouts (8 halves per lane per MFMA step, 32x32x16):
+        //  kf16: fwd GEMM1 A: K[t = 32c + l%32][p = 16st + 8(l/32) + e]          [c][st][l][e]
+        //  ff16: fwd GEMM2 B: F[t = 32c + 16h + tperm16(e, l/32)][32ct + l%32]   [c][ct][h][l][e]
+        //  fa16: adj GEMM1 A: F[t = 32c + l%32][col = 16st + 8(l/32) + e]        [c][st][l][e]
+        //  ka16: adj GEMM2 B: K[t = 32c + 16h + tperm16(e, l/32)][32pt + l%32]   [c][pt][h][l][e]
+        // tperm16(e, h) = 8(e/4) + 4h + e%4.
+        auto tp16 = [](int e, int h) { return 8 * (e / 4) + 4 * h + (e % 4); };
+        kf16.resize((size_t)TP * NUP);
+        ff16.resize((size_t)TP * NBP2);
+        fa16.resize((size_t)TP * NBP2);
+        ka16.resize((size_t)TP * NUP);
+        for (int c = 0; c < NC; ++c) {
+            for (int st = 0; st < NUP / 16; ++st)
+                for (int l = 0; l < 64; ++l)
+                    for (int e2 = 0; e2 < 8; ++e2)
+                        kf16[(((size_t)c * (NUP / 16) + st) * 64 + l) * 8 + e2] =
+                            to_f16(K[(size_t)(32 * c + l % 32) * NUP + 16 * st + 8 * (l / 32) + e2] * ks);
+            for (int ct = 0; ct < NCT; ++ct)
+                for (int h = 0; h < 2; ++h)
+                    for (int l = 0; l < 64; ++l)
+                        for (int e2 = 0; e2 < 8; ++e2)
+                            ff16[((((size_t)c * NCT + ct) * 2 + h) * 64 + l) * 8 + e2] = to_f16(
+                                F[(size_t)(32 * c + 16 * h + tp16(e2, l / 32)) * NBP2 + 32 * ct + l % 32] * fs);
+            for (int st = 0; st < NBP2 / 16; ++st)
+                for (int l = 0; l < 64; ++l)
+                    for (int e2 = 0; e2 < 8; ++e2) {
+                        int col = 16 * st + 8 * (l / 32) + e2;
+                        fa16[(((size_t)c * (NBP2 / 16) + st) * 64 + l) * 8 + e2] =
+                            to_f16(F[(size_t)(32 * c + l % 32) * NBP2 + col] * fcol[col]);
+                    }
+            for (int pt = 0; pt < NUP / 32; ++pt)
+                for (int h = 0; h < 2; ++h)
+                    for (int l = 0; l < 64; ++l)
+                        for (int e2 = 0; e2 < 8; ++e2)
+                            ka16[((((size_t)c * (NUP / 32) + pt) * 2 + h) * 64 + l) * 8 + e2] = to_f16(
+                                K[(size_t)(32 * c + 16 * h + tp16(e2, l / 32)) * NUP + 32 * pt + l % 32] * ks);
+        }
+        // undo factors applied to the adjoint: result = acc / (fs * ks * row_scale)
+        (void)ef;
+    }
+
+    // ---- upload ------------------------------------------------------------
+    e = hipMalloc(&pl->tables, pl->table_bytes);
+    if (e != hipSuccess) { delete pl; return MPI3D_ENOMEM; }
+    char *tb = (char *)pl->tables;
+    pl->cs = (float2 *)(tb + o_cs);
+    pl->ax = (float *)(tb + o_ax);
+    pl->ay = (float *)(tb + o_ay);
+    pl->kf = (float *)(tb + o_kf);
+    pl->ff = (float *)(tb + o_ff);
+    pl->fa = (float *)(tb + o_fa);
+    pl->ka = (float *)(tb + o_ka);
+    bool ok = hipMemcpy(pl->cs, cs.data(), sizeof(float2) * M, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->ax, ax.data(), sizeof(float) * ax.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->ay, ay.data(), sizeof(float) * ay.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->kf, kf.data(), sizeof(float) * kf.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->ff, ff.data(), sizeof(float) * ff.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->fa, fa.data(), sizeof(float) * fa.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (mixed) {
+        pl->kf16 = (__half *)(tb + o_kf16);
+        pl->ff16 = (__half *)(tb + o_ff16);
+        pl->fa16 = (__half *)(tb + o_fa16);
+        pl->ka16 = (__half *)(tb + o_ka16);
+        pl->col_scale = (float *)(tb + o_cols);
+        pl->band_scale = (float *)(tb + o_bands);
+        ok = ok && hipMemcpy(pl->kf16, kf16.data(), sizeof(_Float16) * kf16.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(pl->ff16, ff16.data(), sizeof(_Float16) * ff16.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(pl->fa16, fa16.data(), sizeof(_Float16) * fa16.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(pl->ka16, ka16.data(), sizeof(_Float16) * ka16.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(pl->col_scale, col_scale.data(), sizeof(float) * NBP2, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(pl->band_scale, band_scale.data(), sizeof(float) * NBP2, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipFree(pl->tables);
+        delete pl;
+        return MPI3D_EDEVICE;
+    }
+
+    // ---- workspace layouts -------------------------------------------------
+    {
+        size_t o = 0;
+        auto put = [&](size_t bytes) { o = align256(o); size_t r = o; o += bytes; return r; };
+        long parts_rows = std::max<long>(pl->nbp2, pl->nup);
+        pl->ws_rt = put(sizeof(float) * pl->L * pl->nup);
+        pl->ws_part = put(sizeof(float) * (size_t)pl->nsplit * pl->ngroups * pl->L * parts_rows);
+        pl->ws_norm = put(sizeof(double) * kMaxNormParts);
+        pl->ws_rowscale = put(sizeof(float) * pl->L);
+        pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
+        pl->op_ws_bytes = align256(o);
+    }
+    {
+        size_t o = 0;
+        auto put = [&](size_t bytes) { o = align256(o); size_t r = o; o += bytes; return r; };
+        long ndata = 2 * pl->L * pl->nb;
+        pl->sw_op = put(pl->op_ws_bytes);
+        pl->sw_r = put(sizeof(float) * ndata);
+        pl->sw_q = put(sizeof(float) * ndata);
+        pl->sw_s = put(sizeof(float) * pl->nvox);
+        pl->sw_p = put(sizeof(float) * pl->nvox);
+        pl->sw_scal = put(sizeof(double) * 64);
+        pl->sw_parts = put(sizeof(double) * 3 * kMaxNormParts);
+        pl->solve_ws_bytes = align256(o);
+    }
+    *out = pl;
+    return MPI3D_OK;
+}
+
+extern "C" void mpi3d_plan_destroy(mpi3d_plan *pl)
+{
+    if (!pl) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(pl->device);
+    (void)hipFree(pl->tables);
+    (void)hipSetDevice(prev);
+    delete pl;
+}
+
+extern "C" int mpi3d_plan_query(const mpi3d_plan *pl, mpi3d_plan_info *info)
+{
+    if (!pl || !info) return MPI3D_EINVAL;
+    info->n_vox = pl->nvox;
+    info->n_lines = pl->L;
+    info->n_bins = pl->nb;
+    info->n_data_floats = 2 * pl->L * pl->nb;
+    info->n_proj_floats = pl->L * pl->nu;
+    info->op_ws_bytes = (int64_t)pl->op_ws_bytes;
+    info->solve_ws_bytes = (int64_t)pl->solve_ws_bytes;
+    info->table_bytes = (int64_t)pl->table_bytes;
+    info->history_doubles = 4;
+    info->n_r = pl->nr;
+    return MPI3D_OK;
+}

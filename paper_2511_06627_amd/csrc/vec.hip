@@ -1,0 +1,313 @@
+// Split reductions of the signal kernels and the CGLS vector/scalar steps.
+//
+// Every float64 norm is formed the same way: each block sums its elements'
+// squares in float64 (fixed per-thread order, then a fixed tree), writes one
+// partial, and a single-block scalar kernel adds the partials in index
+// order.  Results therefore do not depend on timing, and the CGLS scalars
+// (Sec. 3.3 solve of eq. nummodel; see the header for the recurrences) stay
+// on the device: no host round trip per iteration.
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace mpi3d {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kVecBlocks = 1024;   // grid of the grid-stride vector kernels
+
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kThreads / 64; ++i) t += red[i];
+    return t;  // valid in thread 0
+}
+
+// out[row][c] = sign * sum_s part[s][row][c] * col_scale[c] / row_scale[row] (+ b_sub)
+__global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2, int nbp2, int nparts,
+                                                               long part_stride, const float *__restrict__ part,
+                                                               const float *__restrict__ row_scale,
+                                                               const float *__restrict__ col_scale,
+                                                               const float *__restrict__ b_sub, float *out,
+                                                               double *norm_parts)
+{
+    __shared__ double red[kThreads / 64];
+    const long n = rows * nb2;
+    double sq = 0.0;
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        const long row = idx / nb2;
+        const int c = (int)(idx - row * nb2);
+        const float *pp = part + row * nbp2 + c;
+        double v = 0.0;
+        for (int s = 0; s < nparts; ++s) v += (double)pp[(long)s * part_stride];
+        if (col_scale) v *= (double)col_scale[c];
+        if (row_scale) v /= (double)row_scale[row];
+        if (b_sub) v = (double)b_sub[idx] - v;
+        const float o = (float)v;
+        out[idx] = o;
+        sq += (double)o * (double)o;
+    }
+    if (norm_parts) {
+        const double t = block_sum(sq, red);
+        if (threadIdx.x == 0) norm_parts[blockIdx.x] = t;
+    }
+}
+
+// out[row][p] = scale * sum_s part[s][row][p] / row_scale[row]   (p < nu)
+__global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int nu, int nup, int out_stride,
+                                                                 int nparts, long part_stride,
+                                                                 const float *__restrict__ part,
+                                                                 const float *__restrict__ row_scale, float scale,
+                                                                 float *out)
+{
+    const long n = rows * out_stride;
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        const long row = idx / out_stride;
+        const int p = (int)(idx - row * out_stride);
+        float o = 0.f;
+        if (p < nu) {
+            const float *pp = part + row * nup + p;
+            double v = 0.0;
+            for (int s = 0; s < nparts; ++s) v += (double)pp[(long)s * part_stride];
+            v *= (double)scale;
+            if (row_scale) v /= (double)row_scale[row];
+            o = (float)v;
+        }
+        out[idx] = o;
+    }
+}
+
+// Scalar slots (doubles) of one solve.
+enum { S_GAMMA = 0, S_DELTA, S_ALPHA, S_BETA, S_BAD, S_GAMMA0, S_STEP, S_NSLOTS };
+
+__device__ double sum_parts(const double *parts, int n, double *red)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) v += parts[i];
+    return block_sum(v, red);
+}
+
+// delta = |q|^2 + lambda |p|^2, alpha = gamma / delta
+__global__ __launch_bounds__(kThreads) void alpha_kernel(double *scal, const double *parts_q, int nq,
+                                                          const double *parts_p, int np, double lambda,
+                                                          double *hist, int step)
+{
+    __shared__ double red[kThreads / 64];
+    const double qq = sum_parts(parts_q, nq, red);
+    __syncthreads();
+    const double pp = sum_parts(parts_p, np, red);
+    if (threadIdx.x == 0) {
+        const double delta = qq + lambda * pp;
+        const double alpha = scal[S_GAMMA] / delta;
+        scal[S_DELTA] = delta;
+        scal[S_ALPHA] = alpha;
+        if (!isfinite(alpha)) scal[S_BAD] = 1.0;
+        if (hist) {
+            hist[4 * step + 0] = scal[S_GAMMA];
+            hist[4 * step + 1] = delta;
+            hist[4 * step + 2] = alpha;
+        }
+    }
+}
+
+// gamma' = |s|^2; beta = gamma'/gamma (restart: beta = 0, and on the first
+// start gamma0 = gamma')
+__global__ __launch_bounds__(kThreads) void beta_kernel(double *scal, const double *parts_s, int ns, int restart,
+                                                         int first, double *hist, int step)
+{
+    __shared__ double red[kThreads / 64];
+    const double g = sum_parts(parts_s, ns, red);
+    if (threadIdx.x == 0) {
+        double beta = 0.0;
+        if (!restart) beta = g / scal[S_GAMMA];
+        if (first) scal[S_GAMMA0] = g;
+        scal[S_GAMMA] = g;
+        scal[S_BETA] = beta;
+        if (!isfinite(g) || !isfinite(beta)) scal[S_BAD] = 1.0;
+        if (hist && !restart) hist[4 * step + 3] = beta;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void update_xr_kernel(float *__restrict__ x, const float *__restrict__ p,
+                                                              float *__restrict__ r, const float *__restrict__ q,
+                                                              long nvox, long ndata, const double *scal)
+{
+    const double alpha = scal[S_ALPHA];
+    const float af = (float)alpha;
+    const long n = nvox + ndata;
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        if (idx < nvox) x[idx] = fmaf(af, p[idx], x[idx]);
+        else {
+            const long j = idx - nvox;
+            r[j] = fmaf(-af, q[j], r[j]);
+        }
+    }
+}
+
+// p = s + beta p (beta from scal), optional bf16 shadow, partial |p|^2
+__global__ __launch_bounds__(kThreads) void update_p_kernel(float *__restrict__ p, const float *__restrict__ s,
+                                                             uint16_t *pb, long n, const double *scal,
+                                                             double *parts_p, int init)
+{
+    __shared__ double red[kThreads / 64];
+    const float bf = (float)scal[S_BETA];
+    double sq = 0.0;
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        const float v = init ? s[idx] : fmaf(bf, p[idx], s[idx]);
+        p[idx] = v;
+        sq += (double)v * (double)v;
+        if (pb) {
+            // round to nearest even bf16
+            uint32_t u = __float_as_uint(v);
+            u += 0x7fffu + ((u >> 16) & 1u);
+            pb[idx] = (uint16_t)(u >> 16);
+        }
+    }
+    const double t = block_sum(sq, red);
+    if (threadIdx.x == 0) parts_p[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void to_bf16_kernel(long n, const float *x, uint16_t *xb)
+{
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        uint32_t u = __float_as_uint(x[idx]);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        xb[idx] = (uint16_t)(u >> 16);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void clamp_kernel(float *x, long n)
+{
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads)
+        x[idx] = fmaxf(x[idx], 0.f);
+}
+
+__global__ __launch_bounds__(kThreads) void fill_kernel(float *x, long n, float v)
+{
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads)
+        x[idx] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void copy_kernel(float *dst, const float *src, long n)
+{
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads)
+        dst[idx] = src[idx];
+}
+
+__global__ void scal_init_kernel(double *scal)
+{
+    if (threadIdx.x < S_NSLOTS) scal[threadIdx.x] = 0.0;
+}
+
+int grid_for(long n)
+{
+    long b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > kVecBlocks) b = kVecBlocks;
+    return (int)b;
+}
+
+}  // namespace
+
+int scal_slots() { return S_NSLOTS; }
+int scal_slot_bad() { return S_BAD; }
+int scal_slot_gamma() { return S_GAMMA; }
+int scal_slot_gamma0() { return S_GAMMA0; }
+
+hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
+                             const float *row_scale, const float *col_scale, const float *b_sub, float *out,
+                             double *norm_parts, int *nnorm, hipStream_t st)
+{
+    const int g = grid_for(rows * nb2);
+    if (nnorm) *nnorm = g;
+    hipLaunchKernelGGL(reduce_fwd_kernel, dim3(g), dim3(kThreads), 0, st, rows, nb2, nbp2, nparts, part_stride,
+                       part, row_scale, col_scale, b_sub, out, norm_parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
+                                       const float *part, const float *row_scale, float scale, float *out,
+                                       hipStream_t st)
+{
+    const int g = grid_for(rows * out_stride);
+    hipLaunchKernelGGL(reduce_lines_kernel, dim3(g), dim3(kThreads), 0, st, rows, nu, nup, out_stride, nparts,
+                       part_stride, part, row_scale, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_lines(long rows, int nu, int nup, int nparts, long part_stride, const float *part,
+                               const float *row_scale, float scale, float *out, hipStream_t st)
+{
+    return launch_reduce_lines_strided(rows, nu, nup, nup, nparts, part_stride, part, row_scale, scale, out, st);
+}
+
+hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st)
+{
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, xb);
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha(double *scal, const double *parts_q, int nq, const double *parts_p, int np, double lambda,
+                        double *hist, int step, hipStream_t st)
+{
+    hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(kThreads), 0, st, scal, parts_q, nq, parts_p, np, lambda, hist,
+                       step);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta(double *scal, const double *parts_s, int ns, int restart, int first, double *hist, int step,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(kThreads), 0, st, scal, parts_s, ns, restart, first, hist, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xr2(float *x, const float *p, float *r, const float *q, long nvox, long ndata,
+                             const double *scal, hipStream_t st)
+{
+    hipLaunchKernelGGL(update_xr_kernel, dim3(grid_for(nvox + ndata)), dim3(kThreads), 0, st, x, p, r, q, nvox,
+                       ndata, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p2(float *p, const float *s, uint16_t *pb, long n, const double *scal, double *parts_p,
+                            int *np_out, int init, hipStream_t st)
+{
+    const int g = grid_for(n);
+    if (np_out) *np_out = g;
+    hipLaunchKernelGGL(update_p_kernel, dim3(g), dim3(kThreads), 0, st, p, s, pb, n, scal, parts_p, init);
+    return hipGetLastError();
+}
+
+hipError_t launch_scal_init(double *scal, hipStream_t st)
+{
+    hipLaunchKernelGGL(scal_init_kernel, dim3(1), dim3(64), 0, st, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_clamp(float *x, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(clamp_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *x, long n, float v, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, x, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace mpi3d

@@ -1,0 +1,174 @@
+"""Torch-facing wrapper of the libmpi3d C ABI.
+
+``Plan`` owns one ``mpi3d_plan`` (device tables for one scan geometry) and
+calls the library's entry points with torch device buffers.  PyTorch only
+provides memory and the stream; every operator step is a HIP kernel of the
+library.  Layouts match the C header: volumes float32 (nz, ny, nx), data
+complex64 (n_angles, nz, n_bins), projections float32 (n_angles, nz, n_u).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MPI3D_FP32, MPI3D_MIXED, check
+
+PRECISION = {"fp32": MPI3D_FP32, "mixed": MPI3D_MIXED}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    def __init__(self, nx, ny, nz, n_angles, n_t, drive_cycles, psf_width, harm_lo, harm_hi, half_band,
+                 op_scale, theta=None, n_u=0, drive_amp=0.0, rx_filter=None, precisions=("fp32",), device=0):
+        lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        g = _lib.Geometry()
+        g.nx, g.ny, g.nz, g.n_angles = nx, ny, nz, n_angles
+        self._theta = None
+        if theta is not None:
+            self._theta = np.ascontiguousarray(theta, dtype=np.float64)
+            g.theta_rad = self._theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.n_u = n_u
+        g.n_t = n_t
+        g.drive_cycles = drive_cycles
+        g.drive_amp = drive_amp
+        g.psf_width = psf_width
+        g.harm_lo, g.harm_hi, g.half_band = harm_lo, harm_hi, half_band
+        self._rx = None
+        if rx_filter is not None:
+            self._rx = np.ascontiguousarray(np.stack([np.real(rx_filter), np.imag(rx_filter)], -1),
+                                            dtype=np.float32).ravel()
+            g.rx_filter = self._rx.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        g.op_scale = op_scale
+        mask = 0
+        for p in precisions:
+            mask |= 1 << PRECISION[p]
+        g.precisions = mask
+        self.precisions = tuple(precisions)
+        handle = ctypes.c_void_p()
+        check("mpi3d_plan_create", lib.mpi3d_plan_create(ctypes.byref(g), device, ctypes.byref(handle)))
+        self._h = handle
+        info = _lib.PlanInfo()
+        check("mpi3d_plan_query", lib.mpi3d_plan_query(self._h, ctypes.byref(info)))
+        self.info = info
+        self.shape = (nz, ny, nx)
+        self.n_u = n_u or nx
+        self.data_shape = (n_angles, nz, int(info.n_bins))
+        self.proj_shape = (n_angles, nz, self.n_u)
+        self._ws = None
+
+    @classmethod
+    def from_config(cls, cfg, op_scale, precisions=("fp32",), device=0):
+        return cls(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width,
+                   cfg.harm_lo, cfg.harm_hi, cfg.half_band, op_scale, precisions=precisions, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().mpi3d_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- buffers -----------------------------------------------------------
+    def workspace(self, kind="op"):
+        n = self.info.op_ws_bytes if kind == "op" else self.info.solve_ws_bytes
+        return torch.empty(int(n), dtype=torch.uint8, device=self.device)
+
+    def _op_ws(self, ws):
+        if ws is None:
+            if self._ws is None:
+                self._ws = self.workspace("op")
+            ws = self._ws
+        return ws
+
+    def _check_vol(self, x):
+        if x.dtype != torch.float32 or x.device != self.device or not x.is_contiguous() or x.numel() != self.info.n_vox:
+            raise ValueError("volume must be a contiguous float32 tensor of %s on %s" % (self.shape, self.device))
+
+    def _check_data(self, b):
+        if b.dtype != torch.complex64 or b.device != self.device or not b.is_contiguous() or \
+                b.numel() * 2 != self.info.n_data_floats:
+            raise ValueError("data must be a contiguous complex64 tensor of %s on %s" % (self.data_shape, self.device))
+
+    # ---- operator ------------------------------------------------------------
+    def forward(self, x, precision="fp32", out=None, ws=None, stream=None):
+        self._check_vol(x)
+        out = torch.empty(self.data_shape, dtype=torch.complex64, device=self.device) if out is None else out
+        self._check_data(out)
+        ws = self._op_ws(ws)
+        check("mpi3d_forward", _lib.load().mpi3d_forward(self._h, PRECISION[precision], _ptr(x), _ptr(out),
+                                                          _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def adjoint(self, b, precision="fp32", out=None, ws=None, stream=None):
+        self._check_data(b)
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device) if out is None else out
+        self._check_vol(out)
+        ws = self._op_ws(ws)
+        check("mpi3d_adjoint", _lib.load().mpi3d_adjoint(self._h, PRECISION[precision], _ptr(b), _ptr(out),
+                                                          _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def project(self, x, out=None, stream=None):
+        self._check_vol(x)
+        out = torch.empty(self.proj_shape, dtype=torch.float32, device=self.device) if out is None else out
+        check("mpi3d_project", _lib.load().mpi3d_project(self._h, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def backproject(self, rho, out=None, stream=None):
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device) if out is None else out
+        self._check_vol(out)
+        rho = rho.contiguous()
+        check("mpi3d_backproject", _lib.load().mpi3d_backproject(self._h, _ptr(rho), _ptr(out), _stream(stream)))
+        return out
+
+    def signal_fwd(self, rho, precision="fp32", out=None, ws=None, stream=None):
+        out = torch.empty(self.data_shape, dtype=torch.complex64, device=self.device) if out is None else out
+        ws = self._op_ws(ws)
+        rho = rho.contiguous()
+        check("mpi3d_signal_fwd", _lib.load().mpi3d_signal_fwd(self._h, PRECISION[precision], _ptr(rho), _ptr(out),
+                                                                _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def signal_adj(self, b, precision="fp32", out=None, ws=None, stream=None):
+        self._check_data(b)
+        out = torch.empty(self.proj_shape, dtype=torch.float32, device=self.device) if out is None else out
+        ws = self._op_ws(ws)
+        check("mpi3d_signal_adj", _lib.load().mpi3d_signal_adj(self._h, PRECISION[precision], _ptr(b), _ptr(out),
+                                                                _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    # ---- solve ---------------------------------------------------------------
+    def solve(self, b, lam, iters=0, x=None, precision="fp32", clamp_every=0, refine_sweeps=0, inner_iters=0,
+              ws=None, history=None, report=True, stream=None):
+        """CGLS on min |Ax - b|^2 + lam |x|^2.  Returns (x, report or None)."""
+        self._check_data(b)
+        x0_zero = x is None
+        if x is None:
+            x = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        self._check_vol(x)
+        ws = self.workspace("solve") if ws is None else ws
+        o = _lib.SolveOpts()
+        o.lam, o.iters, o.clamp_every = lam, iters, clamp_every
+        o.precision = PRECISION[precision]
+        o.refine_sweeps, o.inner_iters = refine_sweeps, inner_iters
+        o.x0_is_zero = 1 if x0_zero else 0
+        rep = _lib.SolveReport() if report else None
+        hptr = _ptr(history) if history is not None else ctypes.c_void_p()
+        check("mpi3d_solve", _lib.load().mpi3d_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), _ptr(ws), ws.numel(),
+                                                      hptr, ctypes.byref(rep) if rep is not None else None,
+                                                      _stream(stream)))
+        return x, rep
