@@ -1,0 +1,262 @@
+"""Benchmark of the compressed 3D FFL operator on one MI355X.
+
+Default run (python bench.py [--steps K] [--warmup W]):
+  workload  the realistic scan: 192 x 192 x 96 voxels, 36 FFL angles,
+            96 lines x 8192 time samples per angle, harmonics 1-31 +/- 3 bins
+  step      one application of A followed by A^T (mpi3d_forward then
+            mpi3d_adjoint), FP32 path, inputs resident in HBM
+  value     A^T A applications per second (K steps timed between two device
+            synchronisations)
+Also reported: per-kernel device times from HIP events, the roofline of the
+dominant kernel, the CGLS iteration rate of the 50-iteration solve, the
+32^3 time-to-solve at 1e-4 relative error against the FP64 minimiser, and
+the FP64 CPU oracle timed on this host (cpu_baseline leg).
+
+--tts     also time-to-solve on the realistic scan (its FP64 minimiser takes
+          several CPU minutes).
+One GPU only: --gpus N with N > 1 exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# CPU leg: the FP64 oracle.  Everything that touches oracle/ lives here: the
+# workload's normalisation constant and data (inputs for the GPU leg), the
+# FP64 minimisers that time-to-solve is measured against, and the timed
+# oracle A^T A applications (cpu_baseline).
+# ---------------------------------------------------------------------------
+def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=None):
+    import numpy as np
+    from oracle import operator as oop, solvers
+    from oracle.geometry import Geometry
+
+    def geom(c):
+        g = Geometry(nx=c.nx, ny=c.ny, nz=c.nz, n_angles=c.n_angles, n_t=c.n_t, drive_cycles=c.drive_cycles,
+                     psf_width=c.psf_width, harm_lo=c.harm_lo, harm_hi=c.harm_hi, half_band=c.half_band)
+        return oop.normalised(g, iters_min=30, rtol=1e-9)
+
+    from paper_2511_06627_amd import configs
+    out = {}
+    t0 = time.time()
+    g = geom(cfg)
+    phantom = configs.make_phantom(cfg)
+    b, _ = oop.make_data(g, phantom, cfg.noise, cfg.noise_seed)
+    out["op_scale"] = g.op_scale
+    out["b"] = b.astype(np.complex64)
+    out["phantom"] = phantom
+    log("oracle setup %.1fs" % (time.time() - t0))
+
+    # timed oracle A^T A at the full workload (time-domain path, as defined)
+    op = oop.Operator(g)
+    x = phantom
+    n = 0
+    t0 = time.time()
+    while True:
+        x = op.adjoint(op.forward(x))
+        x /= np.linalg.norm(x)
+        n += 1
+        if n >= 2 and time.time() - t0 >= sample_seconds:
+            break
+    dt = time.time() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    out["cpu_baseline"] = {"value": n / dt, "unit": "A^T A applies/s", "cores": threads, "kind": "oracle",
+                           "sample": "%d applications of A then A^T (FP64 time-domain oracle, C projector with "
+                                     "OpenMP, BLAS contractions) at the full %s workload, %.1f s"
+                                     % (n, cfg.name, dt)}
+    log("oracle A^T A: %.3f /s on %d threads" % (n / dt, threads))
+
+    if small_cfg is not None:
+        gs = geom(small_cfg)
+        ph = configs.make_phantom(small_cfg)
+        bs, _ = oop.make_data(gs, ph, small_cfg.noise, small_cfg.noise_seed)
+        bs = bs.astype(np.complex64)
+        xs, it = solvers.reference_minimiser(oop.Operator(gs, precomposed=True), bs.astype(np.complex128),
+                                             small_cfg.lam, tol=1e-12)
+        out["small"] = {"op_scale": gs.op_scale, "b": bs, "xstar": xs, "xstar_iters": it}
+    if want_minimiser:
+        t0 = time.time()
+        xs, it = solvers.reference_minimiser(oop.Operator(g, precomposed=True), out["b"].astype(np.complex128),
+                                             cfg.lam, tol=1e-9)
+        out["xstar"], out["xstar_iters"] = xs, it
+        log("oracle minimiser: %d CGLS iterations, %.1fs" % (it, time.time() - t0))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# GPU leg
+# ---------------------------------------------------------------------------
+def signal_flops(cfg):
+    """Algorithmic flops of one signal contraction (forward or adjoint) over all lines:
+    2 L (Nu T + 2 nb T): the PSF contraction plus the band DFT, real arithmetic."""
+    L = cfg.n_lines
+    return 2.0 * L * (cfg.n_u * cfg.n_t + 2 * cfg.n_bins * cfg.n_t)
+
+
+def projection_bytes(cfg):
+    """Per-angle-stream byte model of one projection: every angle reads the whole
+    volume once and writes its lines (fp32)."""
+    nvox = cfg.nx * cfg.ny * cfg.nz
+    return 4.0 * (cfg.n_angles * nvox + cfg.n_lines * cfg.n_u)
+
+
+def time_to_solve(plan, torch, b, xstar, lam, max_iters, check_every, precision="fp32"):
+    """Smallest iteration count whose iterate is within 1e-4 of x*, and the
+    device time of a solve with that many iterations (median of 3)."""
+    import numpy as np
+    bd = torch.from_numpy(b).cuda()
+    xn = np.linalg.norm(xstar)
+    hit = None
+    errs = []
+    for it in range(check_every, max_iters + 1, check_every):
+        x, _ = plan.solve(bd, lam, iters=it, report=False) if precision == "fp32" else \
+            plan.solve(bd, lam, precision="mixed", refine_sweeps=it // 20, inner_iters=20, report=False)
+        err = float(np.linalg.norm(x.cpu().numpy() - xstar) / xn)
+        errs.append((it, err))
+        if err <= 1e-4:
+            hit = it
+            break
+    if hit is None:
+        return {"iters": None, "seconds": None, "errors": errs}
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(bd, lam, iters=hit, report=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return {"iters": hit, "seconds": sorted(ts)[1], "rel_err": errs[-1][1]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tts", action="store_true", help="time-to-solve on the realistic scan (slow oracle)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip-small", action="store_true",
+                    help="skip the 32^3 time-to-solve (keeps a profile to the realistic scan)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the operator is measured on one MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2511_06627_amd import configs
+    cfg = configs.REALISTIC_192
+    small = configs.PARITY_32
+    cpu = cpu_baseline_leg(cfg, want_minimiser=args.tts, sample_seconds=args.cpu_seconds,
+                           small_cfg=None if args.skip_small else small)
+
+    import numpy as np
+    import torch
+    from paper_2511_06627_amd.plan import Plan
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    plan = Plan.from_config(cfg, cpu["op_scale"])
+    x = torch.from_numpy(cpu["phantom"]).float().cuda()
+    b = torch.from_numpy(cpu["b"]).cuda()
+    yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
+    xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    ws = plan.workspace("op")
+
+    def step():
+        plan.forward(x, out=yb, ws=ws)
+        plan.adjoint(yb, out=xo, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    log("A^T A: %.3f ms/step" % ms_step)
+
+    # per-kernel device times (HIP events inside the library, on this stream)
+    kt = {k: plan.time_kernel(k, repeats=10, x=x, b=b, ws=ws)
+          for k in ("project", "signal_fwd", "signal_adj", "backproject")}
+    log("kernels (ms): " + ", ".join("%s %.3f" % kv for kv in kt.items()))
+    fl = signal_flops(cfg)
+    dom = max(("signal_fwd", "signal_adj"), key=lambda k: kt[k])
+    achieved = fl / (kt[dom] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": fl}
+    kernels = {}
+    for k in ("signal_fwd", "signal_adj"):
+        a = fl / (kt[k] * 1e-3) / 1e12
+        kernels[k] = {"ms": round(kt[k], 4), "tflops": round(a, 2), "mfma_frac": round(a / FP32_PEAK_TFLOPS, 4)}
+    pb = projection_bytes(cfg)
+    for k in ("project", "backproject"):
+        gbs = pb / (kt[k] * 1e-3) / 1e9
+        kernels[k] = {"ms": round(kt[k], 4), "per_angle_stream_GBs": round(gbs, 1),
+                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    # CGLS iteration rate of the configured 50-iteration solve
+    swk = plan.workspace("solve")
+    plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, rep = plan.solve(b, cfg.lam, iters=cfg.iters, ws=swk)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
+
+    # time-to-solve at 1e-4 relative error against the FP64 minimiser
+    tts = {}
+    if not args.skip_small:
+        sm = cpu["small"]
+        psmall = Plan.from_config(small, sm["op_scale"])
+        tts["parity_32cube"] = time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, 400, 5)
+    if args.tts:
+        tts[cfg.name] = time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, 600, 25)
+
+    value = args.steps / dt
+    line = {
+        "metric": "A^T A applies/s + time-to-solve at 1e-4 rel err vs FP64; p50/p99 latency",
+        "value": round(value, 3),
+        "unit": "A^T A applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "realistic_192x192x96: 36 angles, 96 lines x 8192 samples per angle, "
+                               "harmonics 1-31 +/-3 bins, 40 blobs + ellipsoid phantom, 0.5% noise",
+                   "step": "A then A^T, FP32 path", "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu["cpu_baseline"],
+        "kernels": kernels,
+        "cgls": {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
+                 "status": rep.status},
+        "time_to_solve": tts,
+        "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -216,6 +216,20 @@ int mpi3d_batch_step(mpi3d_state *const *states, int32_t n_states, void *stream)
 int mpi3d_state_progress(const mpi3d_state *state, int32_t *iters_done, int32_t *done);
 void mpi3d_state_destroy(mpi3d_state *state);
 
+/*
+ * Benchmark support.  Enqueues `repeats` back-to-back launches of one kernel
+ * of the operator on `stream` between two HIP events, synchronises, and
+ * stores the mean time per launch (milliseconds) in *avg_ms.
+ *   kernel 0  projection            reads x_dev, writes the workspace
+ *   kernel 1  backprojection        reads the workspace, writes x_dev
+ *   kernel 2  signal forward contraction (time signal + band DFT)
+ *   kernel 3  signal adjoint contraction, reads b_dev
+ * The kernels' work does not depend on the values they read.  x_dev holds
+ * n_vox floats, b_dev n_data_floats, ws_dev op_ws_bytes.
+ */
+int mpi3d_time_kernel(const mpi3d_plan *plan, int32_t kernel, int32_t precision, int32_t repeats, float *x_dev,
+                      const float *b_dev, void *ws_dev, size_t ws_bytes, void *stream, float *avg_ms);
+
 /* Static description of a status code. */
 const char *mpi3d_strerror(int status);
 

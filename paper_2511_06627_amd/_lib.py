@@ -79,6 +79,8 @@ _SIGS = {
     "mpi3d_batch_step": (_I, [ctypes.POINTER(_VP), ctypes.c_int32, _VP]),
     "mpi3d_state_progress": (_I, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mpi3d_state_destroy": (None, [_VP]),
+    "mpi3d_time_kernel": (_I, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t,
+                               _VP, ctypes.POINTER(ctypes.c_float)]),
     "mpi3d_strerror": (ctypes.c_char_p, [_I]),
 }
 

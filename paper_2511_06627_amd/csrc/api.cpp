@@ -331,3 +331,55 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
     }
     return MPI3D_OK;
 }
+
+extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t precision, int32_t repeats, float *x,
+                                 const float *b, void *ws, size_t ws_bytes, void *stream, float *avg_ms)
+{
+    if (!pl || !x || !b || !ws || !avg_ms || repeats < 1 || kernel < 0 || kernel > 3) return MPI3D_EINVAL;
+    if (int rc = check_prec(pl, precision)) return rc;
+    if (ws_bytes < pl->op_ws_bytes) return MPI3D_ENOMEM;
+    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    DeviceGuard dg(pl->device);
+    hipStream_t st = (hipStream_t)stream;
+    OpWs w = carve_op(pl, ws);
+    hipEvent_t e0, e1;
+    TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MPI3D_EDEVICE;
+    }
+    SigArgs a = sig_args(pl);
+    a.njobs = 1;
+    a.jobs[0].row_scale = w.rowscale;
+    a.jobs[0].rows = (int)pl->L;
+    a.jobs[0].tile0 = 0;
+    a.jobs[0].part = w.part;
+    a.total_tiles = (int)((pl->L + kRowsPerBlock - 1) / kRowsPerBlock);
+    if (kernel == 2) {
+        a.jobs[0].in = w.rt;
+        a.jobs[0].in_stride = pl->nup;
+        a.jobs[0].part_stride = pl->L * pl->nbp2;
+    } else if (kernel == 3) {
+        a.jobs[0].in = b;
+        a.jobs[0].in_stride = pl->nb2;
+        a.jobs[0].part_stride = pl->L * pl->nup;
+    }
+    hipError_t err = hipEventRecord(e0, st);
+    for (int i = 0; err == hipSuccess && i < repeats; ++i) {
+        switch (kernel) {
+        case 0: err = launch_project(pl, x, nullptr, w.rt, st); break;
+        case 1: err = launch_backproject(pl, w.rt, x, nullptr, 0.0, nullptr, nullptr, st); break;
+        case 2: err = launch_sig_fwd(pl, precision, a, st); break;
+        default: err = launch_sig_adj(pl, precision, a, st); break;
+        }
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return MPI3D_EDEVICE;
+    *avg_ms = ms / repeats;
+    return MPI3D_OK;
+}

@@ -13,13 +13,14 @@ namespace mpi3d {
 
 // ---------------------------------------------------------------------------
 // Fixed tiling constants of the signal kernels.
-//   A wave owns 32 FFL lines (one 32-row MFMA tile); a block of 4 waves owns
-//   128 lines.  Time is consumed in chunks of 32 samples (one MFMA tile of
+//   A pair of waves owns 32 FFL lines (one 32-row MFMA tile); a block of 4
+//   pairs owns 128 lines.  Time is consumed in chunks of 32 samples (one MFMA tile of
 //   the time dimension).  Columns of the band table come in tiles of 32.
 // ---------------------------------------------------------------------------
-constexpr int kRowsPerWave = 32;
-constexpr int kWaves = 4;
+constexpr int kRowsPerWave = 32;                      // lines per wave pair
+constexpr int kWaves = 4;                             // wave pairs per block
 constexpr int kRowsPerBlock = kRowsPerWave * kWaves;
+constexpr int kSigThreads = 2 * 64 * kWaves;          // 8 waves
 constexpr int kChunk = 32;
 constexpr int kColTile = 32;
 constexpr int kMaxJobs = 16;
@@ -83,7 +84,7 @@ struct mpi3d_plan {
     double P, a, w, op_scale;
     int precisions;
     // padded sizes
-    int nup;        // n_u padded to 32
+    int nup;        // n_u padded to 64
     int ntp;        // n_t padded to 32
     int nb2;        // 2*nb real columns
     int nbp2;       // nb2 padded to 32
@@ -93,7 +94,7 @@ struct mpi3d_plan {
     // signal kernel configuration
     int nchunks, cps, nsplit, ngroups, gct;
     // projection configuration
-    int angles_per_block, band_rows, n_bands, kz;
+    int angles_per_block, n_angle_groups, band_rows, n_bands, kz;
     // device tables (one allocation)
     void *tables;
     size_t table_bytes;

@@ -70,7 +70,7 @@ int ray_count(int nx, int ny)
 // 256 compute units in as few rounds as possible (one block per CU).
 void choose_split(mpi3d_plan *pl)
 {
-    const int cus = 256;
+    const int cus = 512;   // two 8-wave blocks per CU
     long tiles = (pl->L + kRowsPerBlock - 1) / kRowsPerBlock;
     int best_s = 1;
     double best = 1e30;
@@ -156,7 +156,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->w = g->psf_width;
     pl->op_scale = g->op_scale;
     pl->precisions = precisions;
-    pl->nup = round_up(nu, 32);
+    pl->nup = round_up(nu, 64);
     pl->ntp = round_up(g->n_t, kChunk);
     pl->nb2 = 2 * pl->nb;
     pl->nbp2 = round_up(pl->nb2, kColTile);
@@ -165,10 +165,21 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->nvox = (long)pl->nx * pl->ny * pl->nz;
     pl->nchunks = pl->ntp / kChunk;
 
-    // column groups: as many 32-wide column tiles per block as registers allow
-    int gmax = pl->nup <= 192 ? 14 : 11;
-    pl->ngroups = (pl->nct + gmax - 1) / gmax;
-    pl->gct = (pl->nct + pl->ngroups - 1) / pl->ngroups;
+    // Column groups: as many 32-wide column tiles per block as registers
+    // allow.  The tile count per group is one of the compiled widths, and the
+    // band tables are zero-padded so every group is full (no per-tile guards
+    // in the kernels).
+    {
+        static const int widths[] = {6, 8, 12, 14};
+        int gmax = 14;
+        pl->ngroups = (pl->nct + gmax - 1) / gmax;
+        int want = (pl->nct + pl->ngroups - 1) / pl->ngroups;
+        pl->gct = 0;
+        for (int wdt : widths)
+            if (!pl->gct && wdt >= want) pl->gct = wdt;
+        pl->nct = pl->ngroups * pl->gct;
+        pl->nbp2 = pl->nct * kColTile;
+    }
     if (!sig_fwd_supported(pl->nup, pl->gct, MPI3D_FP32) || !sig_adj_supported(pl->nup, pl->gct, MPI3D_FP32) ||
         ((precisions & (1 << MPI3D_MIXED)) &&
          (!sig_fwd_supported(pl->nup, pl->gct, MPI3D_MIXED) || !sig_adj_supported(pl->nup, pl->gct, MPI3D_MIXED)))) {
@@ -186,11 +197,23 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         int bases = pl->ny + 1;                     // base rows -1 .. ny-1
         pl->n_bands = (bases + max_rows - 1) / max_rows;
         pl->band_rows = (bases + pl->n_bands - 1) / pl->n_bands;
-        // angles per block: enough blocks to cover the GPU about twice
-        int groups_wanted = std::max(1, (int)((512 + pl->nz - 1) / pl->nz));
-        int apb = std::max(1, (pl->M + groups_wanted - 1) / groups_wanted);
-        while (apb > 1 && (long)apb * pl->nu > 256L * 8) --apb;  // rays per thread <= 8
-        pl->angles_per_block = apb;
+        // Angle groups per slice: one block (1024 threads, one slice in LDS)
+        // per CU at a time; minimise rounds x (angles per block + about two
+        // angles' worth of staging), with at most 4 rays per thread.
+        int best_g = 1;
+        double best = 1e30;
+        for (int gcount = 1; gcount <= pl->M; ++gcount) {
+            int apb = (pl->M + gcount - 1) / gcount;
+            if ((long)apb * pl->nu > 4096) continue;
+            long rounds = ((long)pl->nz * gcount + 255) / 256;
+            double cost = (double)rounds * (apb + 2.0 * pl->n_bands);
+            if (cost < best - 1e-9) {
+                best = cost;
+                best_g = gcount;
+            }
+        }
+        pl->n_angle_groups = best_g;
+        pl->angles_per_block = (pl->M + best_g - 1) / best_g;
         pl->kz = std::min(32, pl->nz);
     }
 

@@ -39,19 +39,41 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
     return xcd * per + min(xcd, rem) + slot;
 }
 
-constexpr int kMaxRaysPerThread = 8;
+constexpr int kFwdThreads = 1024;
+constexpr int kMaxRaysPerThread = 4;
 
-__global__ __launch_bounds__(256) void proj_fwd_kernel(ProjArgs a, int out_stride)
+// One bilinear sample of the staged band.  Branch-free: a sample whose 2x2
+// footprint lies outside the band reads a safe LDS address and contributes 0.
+__device__ __forceinline__ float sample(const float *lds, int W, int nx, int nbase, int jb0, float bx, float by,
+                                        float s, float c, float y)
+{
+    const float fx = fmaf(y, s, bx), fy = fmaf(y, c, by);
+    const float ix = floorf(fx), iy = floorf(fy);
+    int i0 = (int)ix, j0 = (int)iy - jb0;
+    const bool ok = (unsigned)i0 <= (unsigned)nx && (unsigned)j0 < (unsigned)nbase;
+    i0 = ok ? i0 : 0;
+    j0 = ok ? j0 : 0;
+    const float wx = fx - ix, wy = fy - iy;
+    const float *l0 = lds + j0 * W + i0;
+    const float v00 = l0[0], v10 = l0[1], v01 = l0[W], v11 = l0[W + 1];
+    const float top = fmaf(wx, v10 - v00, v00);
+    const float bot = fmaf(wx, v11 - v01, v01);
+    return ok ? fmaf(wy, bot - top, top) : 0.f;
+}
+
+__global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int out_stride)
 {
     extern __shared__ float lds[];
     const int nb = gridDim.x;
     const int lb = xcd_logical(blockIdx.x, nb);
     const int k = lb / a.n_angle_groups;
     const int mg = lb % a.n_angle_groups;
-    const int m0 = mg * a.angles_per_block;
+    // angles split as evenly as possible over the groups
+    const int m0 = (mg * a.M) / a.n_angle_groups;
+    const int m1 = ((mg + 1) * a.M) / a.n_angle_groups;
     const int W = a.nx + 2;
     const int tid = threadIdx.x;
-    const int nrays = min(a.angles_per_block, a.M - m0) * a.nu;
+    const int nrays = (m1 - m0) * a.nu;
 
     float acc[kMaxRaysPerThread];
 #pragma unroll
@@ -64,7 +86,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(ProjArgs a, int out_strid
         const int nbase = jb1 - jb0;
         const int rows = nbase + 1;                            // LDS rows: grid rows jb0..jb1
         __syncthreads();
-        for (int idx = tid; idx < rows * W; idx += 256) {
+        for (int idx = tid; idx < rows * W; idx += kFwdThreads) {
             int r = idx / W, col = idx - r * W;
             int gj = jb0 + r, gi = col - 1;
             float v = 0.f;
@@ -74,7 +96,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(ProjArgs a, int out_strid
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kMaxRaysPerThread; ++i) {
-            const int ray = tid + 256 * i;
+            const int ray = tid + kFwdThreads * i;
             if (ray >= nrays) continue;
             const int m = m0 + ray / a.nu, p = ray % a.nu;
             const float2 csv = a.cs[m];
@@ -86,6 +108,8 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(ProjArgs a, int out_strid
             // belongs to this band when its base row floor(fy) is in [jb0, jb1);
             // fy does not depend on the band, so every sample lands in exactly
             // one band.  Samples with floor(fx) outside [0, nx] touch no voxel.
+            // The q range below is a slightly widened superset; the exact test
+            // is per sample.
             float ylo = -a.half_nr, yhi = a.half_nr;
             if (s > 0.f) {
                 ylo = fmaxf(ylo, (0.f - bx) / s);
@@ -100,26 +124,23 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(ProjArgs a, int out_strid
             }
             const int q0 = max(0, (int)floorf(ylo + a.half_nr) - 1);
             const int q1 = min(a.nr - 1, (int)ceilf(yhi + a.half_nr) + 1);
-            float sum = 0.f;
-            for (int q = q0; q <= q1; ++q) {
+            // four independent partial sums keep several LDS reads in flight
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+            int q = q0;
+            for (; q + 3 <= q1; q += 4) {
                 const float y = (float)q - a.half_nr;
-                const float fx = fmaf(y, s, bx), fy = fmaf(y, c, by);
-                const float ix = floorf(fx), iy = floorf(fy);
-                const int i0 = (int)ix, j0 = (int)iy - jb0;
-                if (i0 < 0 || i0 > a.nx || j0 < 0 || j0 >= nbase) continue;
-                const float wx = fx - ix, wy = fy - iy;
-                const float *l0 = lds + j0 * W + i0;
-                const float v00 = l0[0], v10 = l0[1], v01 = l0[W], v11 = l0[W + 1];
-                const float top = fmaf(wx, v10 - v00, v00);
-                const float bot = fmaf(wx, v11 - v01, v01);
-                sum += fmaf(wy, bot - top, top);
+                s0 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, y);
+                s1 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, y + 1.f);
+                s2 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, y + 2.f);
+                s3 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, y + 3.f);
             }
-            acc[i] += sum;
+            for (; q <= q1; ++q) s0 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, (float)q - a.half_nr);
+            acc[i] += (s0 + s1) + (s2 + s3);
         }
     }
 #pragma unroll
     for (int i = 0; i < kMaxRaysPerThread; ++i) {
-        const int ray = tid + 256 * i;
+        const int ray = tid + kFwdThreads * i;
         if (ray >= nrays) continue;
         const int m = m0 + ray / a.nu, p = ray % a.nu;
         a.rt[((size_t)m * a.nz + k) * out_stride + p] = acc[i];
@@ -127,8 +148,8 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(ProjArgs a, int out_strid
     // zero the padding columns of the lines this block owns
     if (out_stride > a.nu) {
         const int pad = out_stride - a.nu;
-        const int nm = min(a.angles_per_block, a.M - m0);
-        for (int idx = tid; idx < nm * pad; idx += 256) {
+        const int nm = m1 - m0;
+        for (int idx = tid; idx < nm * pad; idx += kFwdThreads) {
             const int m = m0 + idx / pad, p = a.nu + idx % pad;
             a.rt[((size_t)m * a.nz + k) * out_stride + p] = 0.f;
         }
@@ -245,7 +266,7 @@ static ProjArgs base_args(const mpi3d_plan *pl)
     a.ay = pl->ay;
     a.nx = pl->nx; a.ny = pl->ny; a.nz = pl->nz; a.M = pl->M; a.nu = pl->nu; a.nup = pl->nup; a.nr = pl->nr;
     a.angles_per_block = pl->angles_per_block;
-    a.n_angle_groups = (pl->M + pl->angles_per_block - 1) / pl->angles_per_block;
+    a.n_angle_groups = pl->n_angle_groups;
     a.band_rows = pl->band_rows;
     a.n_bands = pl->n_bands;
     a.kz = pl->kz;
@@ -271,7 +292,7 @@ hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *r
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(proj_fwd_kernel, dim3(blocks), dim3(256), lds, st, a, out_stride);
+    hipLaunchKernelGGL(proj_fwd_kernel, dim3(blocks), dim3(kFwdThreads), lds, st, a, out_stride);
     return hipGetLastError();
 }
 

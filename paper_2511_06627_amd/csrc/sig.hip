@@ -8,21 +8,28 @@
 //   r[p]  = sum_t g[t] K[t][p]
 //
 // Both are two chained contractions whose intermediate is the time signal of
-// the line.  The time signal never leaves the chip: a wave owns 32 lines and
-// walks time in chunks of 32 samples; the first contraction produces the
-// 32 x 32 (time x line) tile in MFMA accumulators, and those same registers
-// feed the second contraction as its A operand -- the result layout of the
-// 32x32 MFMA holds, in register s of lane l, line l%32 at time
-// 8(s/4) + 4(l/32) + s%4, which is exactly an A-operand column pair, so the
-// tables of the second contraction are stored with their time index permuted
-// to match.  All tables are pre-swizzled so every operand fetch is one
-// coalesced 16-byte load per lane.
+// the line, and the time signal never leaves the chip.  Time is walked in
+// chunks of 32 samples.  The first contraction leaves a 32 x 32 (time x line)
+// tile in MFMA result registers; the 32x32 MFMA result layout holds, in
+// register s of lane l, line l%32 at time 8(s/4) + 4(l/32) + s%4, which is an
+// A-operand column pair of the next MFMA, so those registers feed the second
+// contraction directly and its tables are stored with the time index permuted
+// to match.  Every table is pre-swizzled so an operand fetch is one coalesced
+// 16-byte load per lane.
 //
-// Time is split across blocks (fixed chunk ranges per split) so that a scan
-// with few lines still fills 256 CUs; each block writes fp32 partial sums of
-// its split, and a reduction kernel adds the splits in a fixed order.  A
-// line's arithmetic is independent of the other lines in its block, which is
-// what makes batching requests bitwise invariant.
+// Wave pairs.  A block is 8 waves = 4 pairs; a pair owns 32 lines.  The two
+// waves of a pair split the reduction of the first contraction (half the
+// detector samples, or half the bins) and the output columns of the second,
+// and swap their partial time tiles through LDS once per chunk: no work is
+// duplicated, and each wave holds only half of the per-line operand and half
+// of the accumulators, which leaves registers for a ring of table loads kept
+// eight deep in flight.
+//
+// Time is also split across blocks (fixed chunk ranges) so a scan with few
+// lines still fills 256 CUs; blocks write fp32 partial sums per split and a
+// reduction kernel adds the splits in a fixed order.  A line's arithmetic does
+// not depend on the other lines of its block, which makes batching requests
+// bitwise invariant.
 
 #include "internal.h"
 
@@ -33,6 +40,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+constexpr int kRing = 8;   // table loads in flight per wave
+
 __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
 {
     const int nx = 8;
@@ -42,7 +51,7 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
 }
 
 struct BlockPos {
-    int job, row0, split, group;
+    int job, row0, split, group, half, pair;
 };
 
 __device__ __forceinline__ BlockPos locate(const SigArgs &a)
@@ -57,69 +66,105 @@ __device__ __forceinline__ BlockPos locate(const SigArgs &a)
     for (int j = 1; j < a.njobs; ++j)
         if (tile >= a.jobs[j].tile0) jb = j;
     bp.job = jb;
-    bp.row0 = (tile - a.jobs[jb].tile0) * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
+    const int w = threadIdx.x >> 6;
+    bp.pair = w >> 1;
+    bp.half = w & 1;
+    bp.row0 = (tile - a.jobs[jb].tile0) * kRowsPerBlock + bp.pair * kRowsPerWave;
     return bp;
 }
 
 #define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
 
-template <int NUP, int G>
-__global__ __launch_bounds__(256, 1) void sig_fwd_f32(SigArgs a)
+// Swap partial time tiles within a pair: write mine, barrier, read the
+// partner's, and return lo + hi (the same operand order on both waves).
+__device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
 {
+    float *slot = xs + ((parity * 4 + pair) * 2) * 16 * 64;
+    float *own = slot + half * 16 * 64;
+    const float *other = slot + (1 - half) * 16 * 64;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) own[j * 64 + lane] = mine[j];
+    __syncthreads();
+    f32x16 r;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const float o = other[j * 64 + lane];
+        r[j] = half == 0 ? mine[j] + o : o + mine[j];
+    }
+    return r;
+}
+
+// Forward.  Per pair: GEMM1 over this wave's half of the detector samples,
+// pair exchange, GEMM2 over this wave's GH column tiles.
+template <int NUP, int GH>
+__global__ __launch_bounds__(512) void sig_fwd_f32(SigArgs a)
+{
+    __shared__ float xs[2 * 4 * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
-    if (bp.row0 >= job.rows) return;
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
+    constexpr int NK = NUP / 16;          // K float4 loads per chunk (this half)
+    constexpr int NF = 4 * GH;            // F float4 loads per chunk
+    constexpr int NL = NK + NF;
+    static_assert(NL >= kRing, "stream shorter than the load ring");
 
-    // B operand of the first contraction: rho_theta[r][2 st + h], kept for the whole block
-    float R[NUP / 2];
+    // B operand of GEMM1: rho[r][p0 + 2 st + h], p0 = half * NUP/2
+    float R[NUP / 4];
     {
-        const float *rin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride + h;
+        const int p0 = bp.half * (NUP / 2);
+        const float *rin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride + p0 + h;
 #pragma unroll
-        for (int st = 0; st < NUP / 2; ++st) R[st] = (rok && 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
+        for (int st = 0; st < NUP / 4; ++st) R[st] = (rok && p0 + 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
     }
-    f32x16 acc[G];
+    f32x16 acc[GH];
 #pragma unroll
-    for (int g = 0; g < G; ++g) acc[g] = 0.f;
+    for (int g = 0; g < GH; ++g) acc[g] = 0.f;
 
-    const int ct0 = bp.group * a.gct;
-    const int nctg = min(a.gct, a.nct - ct0);
+    const int ctb = bp.group * 2 * GH + bp.half * GH;     // first column tile of this wave
+    const int kst0 = bp.half * (NUP / 16);                 // first K float4 step of this half
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
-    const f32x4 *kf = (const f32x4 *)a.kf;
-    const f32x4 *ff = (const f32x4 *)a.ff;
+    const f32x4 *kf = (const f32x4 *)a.kf + lane;
+    const f32x4 *ff = (const f32x4 *)a.ff + lane;
+    auto load = [&](int cc, int i) -> f32x4 {
+        if (i < NK) return kf[((size_t)cc * (NUP / 8) + kst0 + i) * 64];
+        const int j = i - NK, s4 = j / GH, g = j % GH;
+        return ff[(((size_t)cc * a.nct + ctb + g) * 4 + s4) * 64];
+    };
+    f32x4 ring[kRing];
+    const int cfirst = min(c0, a.nchunks - 1);
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) ring[d] = load(cfirst, d);
+
     for (int c = c0; c < c1; ++c) {
-        // time signal tile S^T[t][line] = sum_p K[t][p] rho[line][p]
+        const int cnext = min(c + 1, c1 - 1);
         f32x16 S = 0.f;
-        const f32x4 *kp = kf + (size_t)c * (NUP / 8) * 64 + lane;
+        f32x16 Sf;
 #pragma unroll
-        for (int st4 = 0; st4 < NUP / 8; ++st4) {
-            const f32x4 kv = kp[st4 * 64];
-            S = MFMA32(kv[0], R[4 * st4 + 0], S);
-            S = MFMA32(kv[1], R[4 * st4 + 1], S);
-            S = MFMA32(kv[2], R[4 * st4 + 2], S);
-            S = MFMA32(kv[3], R[4 * st4 + 3], S);
-        }
-        // bands: acc[line][col] += sum_t S[line][t] F[t][col]
-        const f32x4 *fp = ff + ((size_t)c * a.nct + ct0) * 4 * 64 + lane;
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            f32x4 fv[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) fv[g] = (g < nctg) ? fp[(g * 4 + s4) * 64] : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int g = 0; g < G; ++g)
-                    if (g < nctg) acc[g] = MFMA32(S[4 * s4 + e], fv[g][e], acc[g]);
+        for (int i = 0; i < NL; ++i) {
+            const f32x4 v = ring[i % kRing];
+            ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
+            if (i < NK) {
+                S = MFMA32(v[0], R[4 * i + 0], S);
+                S = MFMA32(v[1], R[4 * i + 1], S);
+                S = MFMA32(v[2], R[4 * i + 2], S);
+                S = MFMA32(v[3], R[4 * i + 3], S);
+            } else {
+                if (i == NK) Sf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, S);
+                const int j = i - NK, s4 = j / GH, g = j % GH;
+                acc[g] = MFMA32(Sf[4 * s4 + 0], v[0], acc[g]);
+                acc[g] = MFMA32(Sf[4 * s4 + 1], v[1], acc[g]);
+                acc[g] = MFMA32(Sf[4 * s4 + 2], v[2], acc[g]);
+                acc[g] = MFMA32(Sf[4 * s4 + 3], v[3], acc[g]);
+            }
         }
     }
+    if (bp.row0 >= job.rows) return;
     float *out = job.part + (size_t)bp.split * job.part_stride;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        if (g >= nctg) continue;
-        const int col = (ct0 + g) * 32 + (lane & 31);
+    for (int g = 0; g < GH; ++g) {
+        const int col = (ctb + g) * 32 + (lane & 31);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
@@ -128,67 +173,80 @@ __global__ __launch_bounds__(256, 1) void sig_fwd_f32(SigArgs a)
     }
 }
 
-template <int NUP, int G>
-__global__ __launch_bounds__(256, 1) void sig_adj_f32(SigArgs a)
+// Adjoint.  Per pair: GEMM1 over this wave's GH column tiles (half the bins of
+// the group), pair exchange, GEMM2 over this wave's half of the detector tiles.
+template <int NUP, int GH>
+__global__ __launch_bounds__(512) void sig_adj_f32(SigArgs a)
 {
+    __shared__ float xs[2 * 4 * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
-    if (bp.row0 >= job.rows) return;
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
-    const int ct0 = bp.group * a.gct;
-    const int nctg = min(a.gct, a.nct - ct0);
-    const int colbase = ct0 * 32;
+    constexpr int PTH = NUP / 64;         // detector tiles per half
+    constexpr int NF = 4 * GH;            // F float4 loads per chunk (GEMM1)
+    constexpr int NK = 4 * PTH;           // K float4 loads per chunk (GEMM2)
+    constexpr int NL = NF + NK;
+    static_assert(NL >= kRing, "stream shorter than the load ring");
+    const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;   // first column of this wave
+    const int pt0 = bp.half * PTH;
 
-    // B operand of the first contraction: y[r][colbase + 2 st + h]
-    float Y[16 * G];
+    // B operand of GEMM1: y[r][colbase + 2 st + h]
+    float Y[16 * GH];
     {
         const float *yin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride + colbase + h;
 #pragma unroll
-        for (int st = 0; st < 16 * G; ++st) {
+        for (int st = 0; st < 16 * GH; ++st) {
             const int col = colbase + 2 * st + h;
-            Y[st] = (rok && col < a.nb2 && st < 16 * nctg) ? yin[2 * st] : 0.f;
+            Y[st] = (rok && col < a.nb2) ? yin[2 * st] : 0.f;
         }
     }
-    f32x16 racc[NUP / 32];
+    f32x16 racc[PTH];
 #pragma unroll
-    for (int pt = 0; pt < NUP / 32; ++pt) racc[pt] = 0.f;
+    for (int pt = 0; pt < PTH; ++pt) racc[pt] = 0.f;
 
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
-    const f32x4 *fa = (const f32x4 *)a.fa;
-    const f32x4 *ka = (const f32x4 *)a.ka;
-    for (int c = c0; c < c1; ++c) {
-        // time tile G^T[t][line] = sum_col F[t][col] y[line][col]
-        f32x16 Gt = 0.f;
-        const f32x4 *fp = fa + ((size_t)c * (a.nbp2 / 8) + colbase / 8) * 64 + lane;
+    const f32x4 *fa = (const f32x4 *)a.fa + lane;
+    const f32x4 *ka = (const f32x4 *)a.ka + lane;
+    auto load = [&](int cc, int i) -> f32x4 {
+        if (i < NF) return fa[((size_t)cc * (a.nbp2 / 8) + colbase / 8 + i) * 64];
+        const int j = i - NF, s4 = j / PTH, pt = j % PTH;
+        return ka[(((size_t)cc * (NUP / 32) + pt0 + pt) * 4 + s4) * 64];
+    };
+    f32x4 ring[kRing];
+    const int cfirst = min(c0, a.nchunks - 1);
 #pragma unroll
-        for (int st4 = 0; st4 < 4 * G; ++st4) {
-            if (st4 < 4 * nctg) {
-                const f32x4 fv = fp[st4 * 64];
-                Gt = MFMA32(fv[0], Y[4 * st4 + 0], Gt);
-                Gt = MFMA32(fv[1], Y[4 * st4 + 1], Gt);
-                Gt = MFMA32(fv[2], Y[4 * st4 + 2], Gt);
-                Gt = MFMA32(fv[3], Y[4 * st4 + 3], Gt);
+    for (int d = 0; d < kRing; ++d) ring[d] = load(cfirst, d);
+
+    for (int c = c0; c < c1; ++c) {
+        const int cnext = min(c + 1, c1 - 1);
+        f32x16 Gt = 0.f;
+        f32x16 Gf;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const f32x4 v = ring[i % kRing];
+            ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
+            if (i < NF) {
+                Gt = MFMA32(v[0], Y[4 * i + 0], Gt);
+                Gt = MFMA32(v[1], Y[4 * i + 1], Gt);
+                Gt = MFMA32(v[2], Y[4 * i + 2], Gt);
+                Gt = MFMA32(v[3], Y[4 * i + 3], Gt);
+            } else {
+                if (i == NF) Gf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, Gt);
+                const int j = i - NF, s4 = j / PTH, pt = j % PTH;
+                racc[pt] = MFMA32(Gf[4 * s4 + 0], v[0], racc[pt]);
+                racc[pt] = MFMA32(Gf[4 * s4 + 1], v[1], racc[pt]);
+                racc[pt] = MFMA32(Gf[4 * s4 + 2], v[2], racc[pt]);
+                racc[pt] = MFMA32(Gf[4 * s4 + 3], v[3], racc[pt]);
             }
         }
-        // racc[line][p] += sum_t G[line][t] K[t][p]
-        const f32x4 *kp = ka + (size_t)c * (NUP / 32) * 4 * 64 + lane;
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            f32x4 kv[NUP / 32];
-#pragma unroll
-            for (int pt = 0; pt < NUP / 32; ++pt) kv[pt] = kp[(pt * 4 + s4) * 64];
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int pt = 0; pt < NUP / 32; ++pt) racc[pt] = MFMA32(Gt[4 * s4 + e], kv[pt][e], racc[pt]);
-        }
     }
+    if (bp.row0 >= job.rows) return;
     float *out = job.part + (size_t)(bp.split * a.ngroups + bp.group) * job.part_stride;
 #pragma unroll
-    for (int pt = 0; pt < NUP / 32; ++pt) {
-        const int col = pt * 32 + (lane & 31);
+    for (int pt = 0; pt < PTH; ++pt) {
+        const int col = (pt0 + pt) * 32 + (lane & 31);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
@@ -199,32 +257,27 @@ __global__ __launch_bounds__(256, 1) void sig_adj_f32(SigArgs a)
 
 typedef void (*SigKernel)(SigArgs);
 
-constexpr int kNups[] = {32, 64, 128, 192, 256};
-constexpr int kGs[] = {5, 8, 11, 14};
+constexpr int kNups[] = {64, 128, 192, 256};
+constexpr int kGHs[] = {3, 4, 6, 7};
 
-template <int NUP, int G>
-SigKernel pick_fwd() { return sig_fwd_f32<NUP, G>; }
-template <int NUP, int G>
-SigKernel pick_adj() { return sig_adj_f32<NUP, G>; }
-
-int g_slot(int gct)
+int gh_slot(int gct)
 {
     for (int i = 0; i < 4; ++i)
-        if (gct <= kGs[i]) return i;
+        if (gct == 2 * kGHs[i]) return i;
     return -1;
 }
 int nup_slot(int nup)
 {
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (nup == kNups[i]) return i;
     return -1;
 }
 
-#define ROW(NUP, F) {F<NUP, 5>, F<NUP, 8>, F<NUP, 11>, F<NUP, 14>}
-const SigKernel kFwd[5][4] = {ROW(32, sig_fwd_f32), ROW(64, sig_fwd_f32), ROW(128, sig_fwd_f32),
-                              ROW(192, sig_fwd_f32), ROW(256, sig_fwd_f32)};
-const SigKernel kAdj[5][4] = {ROW(32, sig_adj_f32), ROW(64, sig_adj_f32), ROW(128, sig_adj_f32),
-                              ROW(192, sig_adj_f32), ROW(256, sig_adj_f32)};
+#define ROW(NUP, F) {F<NUP, 3>, F<NUP, 4>, F<NUP, 6>, F<NUP, 7>}
+const SigKernel kFwd[4][4] = {ROW(64, sig_fwd_f32), ROW(128, sig_fwd_f32), ROW(192, sig_fwd_f32),
+                              ROW(256, sig_fwd_f32)};
+const SigKernel kAdj[4][4] = {ROW(64, sig_adj_f32), ROW(128, sig_adj_f32), ROW(192, sig_adj_f32),
+                              ROW(256, sig_adj_f32)};
 #undef ROW
 
 }  // namespace
@@ -237,27 +290,27 @@ int sig16_supported(int nup, int gct);
 int sig_fwd_supported(int nup, int gct, int precision)
 {
     if (precision == MPI3D_MIXED) return sig16_supported(nup, gct);
-    return nup_slot(nup) >= 0 && g_slot(gct) >= 0;
+    return nup_slot(nup) >= 0 && gh_slot(gct) >= 0;
 }
 int sig_adj_supported(int nup, int gct, int precision) { return sig_fwd_supported(nup, gct, precision); }
 
 hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st)
 {
     if (precision == MPI3D_MIXED) return launch_sig_fwd16(pl, a, st);
-    const int ns = nup_slot(pl->nup), gs = g_slot(pl->gct);
+    const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
     if (ns < 0 || gs < 0) return hipErrorInvalidValue;
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;
-    hipLaunchKernelGGL(kFwd[ns][gs], dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(kFwd[ns][gs], dim3(blocks), dim3(kSigThreads), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st)
 {
     if (precision == MPI3D_MIXED) return launch_sig_adj16(pl, a, st);
-    const int ns = nup_slot(pl->nup), gs = g_slot(pl->gct);
+    const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
     if (ns < 0 || gs < 0) return hipErrorInvalidValue;
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;
-    hipLaunchKernelGGL(kAdj[ns][gs], dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(kAdj[ns][gs], dim3(blocks), dim3(kSigThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -151,6 +151,19 @@ class Plan:
                                                                 _ptr(ws), ws.numel(), _stream(stream)))
         return out
 
+    KERNELS = {"project": 0, "backproject": 1, "signal_fwd": 2, "signal_adj": 3}
+
+    def time_kernel(self, kernel, repeats=10, precision="fp32", x=None, b=None, ws=None, stream=None):
+        """Mean device time (ms) of one launch of an operator kernel, from HIP events."""
+        x = torch.zeros(self.shape, dtype=torch.float32, device=self.device) if x is None else x
+        b = torch.zeros(self.data_shape, dtype=torch.complex64, device=self.device) if b is None else b
+        ws = self._op_ws(ws)
+        ms = ctypes.c_float()
+        check("mpi3d_time_kernel", _lib.load().mpi3d_time_kernel(
+            self._h, self.KERNELS[kernel], PRECISION[precision], repeats, _ptr(x), _ptr(b), _ptr(ws), ws.numel(),
+            _stream(stream), ctypes.byref(ms)))
+        return float(ms.value)
+
     # ---- solve ---------------------------------------------------------------
     def solve(self, b, lam, iters=0, x=None, precision="fp32", clamp_every=0, refine_sweeps=0, inner_iters=0,
               ws=None, history=None, report=True, stream=None):

@@ -36,3 +36,35 @@ def random_data(g, seed):
     rng = np.random.default_rng(seed)
     shape = (g.n_angles, g.nz, g.n_bins)
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+class PerturbedOperator:
+    """The oracle operator with every output multiplied by (1 + eps * N(0,1)),
+    independently per element and per call: a model of an implementation that
+    rounds each operator result at relative precision eps."""
+
+    def __init__(self, op, eps, seed):
+        self.op = op
+        self.g = op.g
+        self.eps = eps
+        self.rng = np.random.default_rng(seed)
+
+    def forward(self, x):
+        y = self.op.forward(x)
+        return y * (1.0 + self.eps * self.rng.standard_normal(y.shape))
+
+    def adjoint(self, y):
+        x = self.op.adjoint(y)
+        return x * (1.0 + self.eps * self.rng.standard_normal(x.shape))
+
+
+FP32_EPS = 2.0 ** -24
+
+
+def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_EPS):
+    """Largest relative deviation between run(op) and run(perturbed op) over a
+    few seeds: how far any faithful FP32 implementation can drift from the FP64
+    iterate on this schedule."""
+    ref = run(op)
+    dev = max(rel_l2(run(PerturbedOperator(op, eps, s)), ref) for s in seeds)
+    return ref, dev
