@@ -169,7 +169,7 @@ def main():
     from paper_2511_06627_amd.plan import Plan
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
-    plan = Plan.from_config(cfg, cpu["op_scale"])
+    plan = Plan.from_config(cfg, cpu["op_scale"], precisions=("fp32", "mixed"))
     x = torch.from_numpy(cpu["phantom"]).float().cuda()
     b = torch.from_numpy(cpu["b"]).cuda()
     yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
@@ -211,6 +211,27 @@ def main():
         kernels[k] = {"ms": round(kt[k], 4), "per_angle_stream_GBs": round(gbs, 1),
                       "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
+    # mixed operator: A^T A rate and fp16 kernel times
+    def step16():
+        plan.forward(x, precision="mixed", out=yb, ws=ws)
+        plan.adjoint(yb, precision="mixed", out=xo, ws=ws)
+
+    for _ in range(args.warmup):
+        step16()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step16()
+    torch.cuda.synchronize()
+    dt16 = time.perf_counter() - t0
+    kt16 = {k: plan.time_kernel(k, repeats=10, precision="mixed", x=x, b=b, ws=ws)
+            for k in ("signal_fwd", "signal_adj")}
+    mixed = {"applies_per_s": round(args.steps / dt16, 2), "ms_per_step": round(1e3 * dt16 / args.steps, 4)}
+    for k, v in kt16.items():
+        a16 = fl / (v * 1e-3) / 1e12
+        mixed[k] = {"ms": round(v, 4), "tflops": round(a16, 1), "mfma_frac_fp16": round(a16 / FP16_PEAK_TFLOPS, 4)}
+    log("mixed A^T A: %.3f ms/step; kernels %s" % (1e3 * dt16 / args.steps, kt16))
+
     # CGLS iteration rate of the configured 50-iteration solve
     swk = plan.workspace("solve")
     plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
@@ -220,6 +241,25 @@ def main():
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
     log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
+
+    # mixed refinement solve (3 sweeps x 20 inner) against the 60-iteration FP32 solve
+    m2 = configs.MIXED_192
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xm, repm = plan.solve(b, m2.lam, precision="mixed", refine_sweeps=m2.refine_sweeps, inner_iters=m2.inner_iters,
+                          ws=swk)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    x60, _ = plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t_fp32_60 = time.perf_counter() - t0
+    dm = float(torch.linalg.vector_norm(xm - x60) / torch.linalg.vector_norm(x60))
+    mixed["solve_3x20"] = {"seconds": round(t_mixed, 4), "fp32_60_seconds": round(t_fp32_60, 4),
+                           "rel_l2_vs_fp32_60": dm, "status": repm.status}
+    log("mixed 3x20 solve %.4f s (fp32 60 its %.4f s), rel diff vs fp32 %.2e" % (t_mixed, t_fp32_60, dm))
 
     # time-to-solve at 1e-4 relative error against the FP64 minimiser
     tts = {}
@@ -253,6 +293,7 @@ def main():
         "cgls": {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
                  "status": rep.status},
         "time_to_solve": tts,
+        "mixed": mixed,
         "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1),
     }
     print(json.dumps(line), flush=True)

@@ -94,6 +94,7 @@ int signal_forward(const mpi3d_plan *pl, int prec, const float *rho, int in_stri
     a.jobs[0].rows = (int)pl->L;
     a.jobs[0].tile0 = 0;
     a.total_tiles = (int)((pl->L + kRowsPerBlock - 1) / kRowsPerBlock);
+    if (prec == MPI3D_MIXED) TRY(launch_row_scale(pl->L, pl->nu, in_stride, rho, nullptr, w.rowscale, st));
     TRY(launch_sig_fwd(pl, prec, a, st));
     const bool mixed = prec == MPI3D_MIXED;
     TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->nsplit, pl->L * pl->nbp2, w.part, mixed ? w.rowscale : nullptr,
@@ -115,6 +116,7 @@ int signal_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *rho, i
     a.jobs[0].rows = (int)pl->L;
     a.jobs[0].tile0 = 0;
     a.total_tiles = (int)((pl->L + kRowsPerBlock - 1) / kRowsPerBlock);
+    if (prec == MPI3D_MIXED) TRY(launch_row_scale(pl->L, pl->nb2, pl->nb2, y, pl->band_scale, w.rowscale, st));
     TRY(launch_sig_adj(pl, prec, a, st));
     const bool mixed = prec == MPI3D_MIXED;
     TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride, pl->nsplit * pl->ngroups, pl->L * pl->nup,
@@ -122,10 +124,19 @@ int signal_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *rho, i
     return MPI3D_OK;
 }
 
+// xb: bf16 copy of x for the mixed path (null: convert x into the workspace)
 int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *out, const float *b_sub, double *norm_parts,
-                  int *nnorm, const OpWs &w, hipStream_t st)
+                  int *nnorm, const OpWs &w, hipStream_t st, const uint16_t *xb = nullptr)
 {
-    TRY(launch_project(pl, x, nullptr, w.rt, st));
+    if (prec == MPI3D_MIXED) {
+        if (!xb) {
+            TRY(launch_to_bf16(pl->nvox, x, w.xb, st));
+            xb = w.xb;
+        }
+        TRY(launch_project(pl, nullptr, xb, w.rt, st));
+    } else {
+        TRY(launch_project(pl, x, nullptr, w.rt, st));
+    }
     return signal_forward(pl, prec, w.rt, pl->nup, out, b_sub, norm_parts, nnorm, w, st);
 }
 
@@ -213,6 +224,7 @@ struct Cgls {
     float *x, *r, *q, *s, *p;
     double *scal, *parts_q, *parts_p, *parts_s;
     double *hist;
+    uint16_t *pb = nullptr;     // bf16 shadow of p for the mixed operator
     OpWs w;
     double lambda;
     int nq = 0, np = 0, ns = 0;
@@ -254,7 +266,7 @@ struct Cgls {
         int rc = apply_adjoint(pl, MPI3D_FP32, r, s, x, lambda, parts_s, &ns, w, st);
         if (rc) return rc;
         TRY(launch_beta(scal, parts_s, ns, 1, started ? 0 : 1, hist, step, st));
-        TRY(launch_update_p2(p, s, nullptr, pl->nvox, scal, parts_p, &np, 1, st));
+        TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 1, st));
         started = true;
         return MPI3D_OK;
     }
@@ -262,14 +274,14 @@ struct Cgls {
     int iterate(int prec, hipStream_t st)
     {
         const long ndata = 2 * pl->L * pl->nb;
-        int rc = apply_forward(pl, prec, p, q, nullptr, parts_q, &nq, w, st);
+        int rc = apply_forward(pl, prec, p, q, nullptr, parts_q, &nq, w, st, prec == MPI3D_MIXED ? pb : nullptr);
         if (rc) return rc;
         TRY(launch_alpha(scal, parts_q, nq, parts_p, np, lambda, hist, step, st));
         TRY(launch_update_xr2(x, p, r, q, pl->nvox, ndata, scal, st));
         rc = apply_adjoint(pl, prec, r, s, x, lambda, parts_s, &ns, w, st);
         if (rc) return rc;
         TRY(launch_beta(scal, parts_s, ns, 0, 0, hist, step, st));
-        TRY(launch_update_p2(p, s, nullptr, pl->nvox, scal, parts_p, &np, 0, st));
+        TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 0, st));
         ++step;
         return MPI3D_OK;
     }
@@ -299,6 +311,7 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
     hipStream_t st = (hipStream_t)stream;
     Cgls cg;
     cg.init(pl, b, x, ws, o->lambda, hist);
+    if (o->precision == MPI3D_MIXED) cg.pb = cg.w.xb;
     bool xz = o->x0_is_zero != 0;
     if (xz) TRY(launch_fill(x, pl->nvox, 0.f, st));
     int rc = MPI3D_OK;

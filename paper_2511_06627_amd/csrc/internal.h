@@ -133,6 +133,8 @@ hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_strid
                                        const float *part, const float *row_scale, float scale, float *out,
                                        hipStream_t st);
 hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st);
+hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
+                            hipStream_t st);
 
 // CGLS scalar and vector steps.  `scal` holds the solve's float64 scalars.
 int scal_slots();

@@ -22,6 +22,8 @@
 // <= 32 rays) are staged in LDS.  The epilogue optionally forms
 // out = acc - lambda * x_sub and a float64 partial sum of out^2 (CGLS).
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mpi3d {
@@ -42,9 +44,13 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
 constexpr int kFwdThreads = 1024;
 constexpr int kMaxRaysPerThread = 4;
 
+__device__ __forceinline__ float ld(const float *p, int i) { return p[i]; }
+__device__ __forceinline__ float ld(const uint16_t *p, int i) { return __uint_as_float((uint32_t)p[i] << 16); }
+
 // One bilinear sample of the staged band.  Branch-free: a sample whose 2x2
 // footprint lies outside the band reads a safe LDS address and contributes 0.
-__device__ __forceinline__ float sample(const float *lds, int W, int nx, int nbase, int jb0, float bx, float by,
+template <typename T>
+__device__ __forceinline__ float sample(const T *lds, int W, int nx, int nbase, int jb0, float bx, float by,
                                         float s, float c, float y)
 {
     const float fx = fmaf(y, s, bx), fy = fmaf(y, c, by);
@@ -54,16 +60,20 @@ __device__ __forceinline__ float sample(const float *lds, int W, int nx, int nba
     i0 = ok ? i0 : 0;
     j0 = ok ? j0 : 0;
     const float wx = fx - ix, wy = fy - iy;
-    const float *l0 = lds + j0 * W + i0;
-    const float v00 = l0[0], v10 = l0[1], v01 = l0[W], v11 = l0[W + 1];
+    const T *l0 = lds + j0 * W + i0;
+    const float v00 = ld(l0, 0), v10 = ld(l0, 1), v01 = ld(l0, W), v11 = ld(l0, W + 1);
     const float top = fmaf(wx, v10 - v00, v00);
     const float bot = fmaf(wx, v11 - v01, v01);
     return ok ? fmaf(wy, bot - top, top) : 0.f;
 }
 
+// T = float: the fp32 path.  T = uint16_t: bf16 bits, the mixed path's
+// gathers (half the LDS footprint and staging traffic; weights and sums fp32).
+template <typename T>
 __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int out_stride)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
     const int nb = gridDim.x;
     const int lb = xcd_logical(blockIdx.x, nb);
     const int k = lb / a.n_angle_groups;
@@ -79,7 +89,7 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
 #pragma unroll
     for (int i = 0; i < kMaxRaysPerThread; ++i) acc[i] = 0.f;
 
-    const float *slice = a.x + (size_t)k * a.nx * a.ny;
+    const T *slice = (std::is_same<T, float>::value ? (const T *)a.x : (const T *)a.xb) + (size_t)k * a.nx * a.ny;
     for (int band = 0; band < a.n_bands; ++band) {
         const int jb0 = -1 + band * a.band_rows;               // first base row
         const int jb1 = min(jb0 + a.band_rows, a.ny);          // one past last base row
@@ -89,7 +99,7 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
         for (int idx = tid; idx < rows * W; idx += kFwdThreads) {
             int r = idx / W, col = idx - r * W;
             int gj = jb0 + r, gi = col - 1;
-            float v = 0.f;
+            T v = 0;
             if (gj >= 0 && gj < a.ny && gi >= 0 && gi < a.nx) v = slice[(size_t)gj * a.nx + gi];
             lds[idx] = v;
         }
@@ -280,25 +290,35 @@ static ProjArgs base_args(const mpi3d_plan *pl)
     return a;
 }
 
-hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st)
+template <typename T>
+static hipError_t launch_fwd(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt, int out_stride,
+                             hipStream_t st)
 {
     ProjArgs a = base_args(pl);
     a.x = x;
+    a.xb = xb;
     a.rt = rt;
     const int blocks = pl->nz * a.n_angle_groups;
-    const size_t lds = (size_t)(a.band_rows + 1) * (pl->nx + 2) * sizeof(float);
+    const size_t lds = (size_t)(a.band_rows + 1) * (pl->nx + 2) * sizeof(T);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)proj_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+        hipError_t e = hipFuncSetAttribute((const void *)proj_fwd_kernel<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(proj_fwd_kernel, dim3(blocks), dim3(kFwdThreads), lds, st, a, out_stride);
+    hipLaunchKernelGGL(proj_fwd_kernel<T>, dim3(blocks), dim3(kFwdThreads), lds, st, a, out_stride);
     return hipGetLastError();
 }
 
-hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *, float *rt, hipStream_t st)
+hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st)
 {
-    return launch_project_strided(pl, x, rt, pl->nup, st);
+    return launch_fwd<float>(pl, x, nullptr, rt, out_stride, st);
+}
+
+// xb non-null: gather from the bf16 copy (mixed path)
+hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt, hipStream_t st)
+{
+    if (xb) return launch_fwd<uint16_t>(pl, nullptr, xb, rt, pl->nup, st);
+    return launch_fwd<float>(pl, x, nullptr, rt, pl->nup, st);
 }
 
 hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,

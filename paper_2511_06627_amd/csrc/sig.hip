@@ -40,7 +40,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kRing = 8;   // table loads in flight per wave
+// Table loads kept in flight per wave.  The ring slot of stream element i is
+// i % ring, and the stream restarts every chunk, so the ring size must divide
+// the per-chunk stream length: the largest divisor of it not above a cap.
+constexpr int ring_size(int nl, int cap)
+{
+    for (int r = cap; r > 1; --r)
+        if (nl % r == 0) return r;
+    return 1;
+}
 
 __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
 {
@@ -108,7 +116,8 @@ __global__ __launch_bounds__(512) void sig_fwd_f32(SigArgs a)
     constexpr int NK = NUP / 16;          // K float4 loads per chunk (this half)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk
     constexpr int NL = NK + NF;
-    static_assert(NL >= kRing, "stream shorter than the load ring");
+    constexpr int kRing = ring_size(NL, 8);
+    static_assert(NL % kRing == 0, "ring size must divide the stream");
 
     // B operand of GEMM1: rho[r][p0 + 2 st + h], p0 = half * NUP/2
     float R[NUP / 4];
@@ -188,7 +197,8 @@ __global__ __launch_bounds__(512) void sig_adj_f32(SigArgs a)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk (GEMM1)
     constexpr int NK = 4 * PTH;           // K float4 loads per chunk (GEMM2)
     constexpr int NL = NF + NK;
-    static_assert(NL >= kRing, "stream shorter than the load ring");
+    constexpr int kRing = ring_size(NL, 8);
+    static_assert(NL % kRing == 0, "ring size must divide the stream");
     const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;   // first column of this wave
     const int pt0 = bp.half * PTH;
 

@@ -84,6 +84,32 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
     }
 }
 
+// Power-of-two line scales for the fp16 contractions: for each row,
+// s = 2^-e with max_c |in[row][c] * col_scale[c]| in [2^(e-1), 2^e), so the
+// scaled row's largest entry lies in [0.5, 1); 1 for an all-zero row.  One
+// wave per row.
+__global__ __launch_bounds__(kThreads) void row_scale_kernel(long rows, int ncols, int in_stride,
+                                                              const float *__restrict__ in,
+                                                              const float *__restrict__ col_scale, float *out)
+{
+    const int lane = threadIdx.x & 63;
+    const long row = (long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    const float *p = in + row * in_stride;
+    float m = 0.f;
+    for (int c = lane; c < ncols; c += 64) m = fmaxf(m, fabsf(col_scale ? p[c] * col_scale[c] : p[c]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) {
+        float s = 1.f;
+        if (m > 0.f && isfinite(m)) {
+            int e;
+            frexpf(m, &e);
+            s = ldexpf(1.f, -e);
+        }
+        out[row] = s;
+    }
+}
+
 // Scalar slots (doubles) of one solve.
 enum { S_GAMMA = 0, S_DELTA, S_ALPHA, S_BETA, S_BAD, S_GAMMA0, S_STEP, S_NSLOTS };
 
@@ -246,6 +272,15 @@ hipError_t launch_reduce_lines(long rows, int nu, int nup, int nparts, long part
                                const float *row_scale, float scale, float *out, hipStream_t st)
 {
     return launch_reduce_lines_strided(rows, nu, nup, nup, nparts, part_stride, part, row_scale, scale, out, st);
+}
+
+hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
+                            hipStream_t st)
+{
+    const long blocks = (rows + kThreads / 64 - 1) / (kThreads / 64);
+    hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, rows, ncols, in_stride, in,
+                       col_scale, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st)

@@ -2,8 +2,8 @@
 
 Calls only the oracle.  For each (workload, schedule) it runs the FP64 CGLS
 and three runs whose operator outputs carry independent random relative
-errors of size 2^-24 (the FP32 unit roundoff) and records the largest
-relative L2 deviation of the final iterate.  GPU tests compare their FP32
+errors of size 1e-6 (the FP32 operator's error level, see tests/helpers.py)
+and records the largest relative L2 deviation of the final iterate.  GPU tests compare their FP32
 iterate against the FP64 one with max(1e-5, 4 x envelope).
 
 Usage: python tests/golden/make_envelopes.py

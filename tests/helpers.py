@@ -58,13 +58,16 @@ class PerturbedOperator:
         return x * (1.0 + self.eps * self.rng.standard_normal(x.shape))
 
 
-FP32_EPS = 2.0 ** -24
+# Relative error level of an FP32 operator application: the FP32 operator
+# parity tests hold A and A^T to it (measured 1e-7 to 3e-6 relative L2; long
+# fp32 sums over T samples and bilinear weights from fp32 coordinates).
+FP32_OP_EPS = 1e-6
 
 
-def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_EPS):
+def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_OP_EPS):
     """Largest relative deviation between run(op) and run(perturbed op) over a
-    few seeds: how far any faithful FP32 implementation can drift from the FP64
-    iterate on this schedule."""
+    few seeds: how far an implementation whose operator is accurate to about
+    eps can drift from the FP64 iterate on this schedule."""
     ref = run(op)
     dev = max(rel_l2(run(PerturbedOperator(op, eps, s)), ref) for s in seeds)
     return ref, dev
