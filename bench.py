@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tts", action="store_true", help="time-to-solve on the realistic scan (slow oracle)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=512,
+                    help="size of a plain device copy run once, the reference for HBM byte counters")
     ap.add_argument("--skip-small", action="store_true",
                     help="skip the 32^3 time-to-solve (keeps a profile to the realistic scan)")
     args = ap.parse_args()
@@ -169,6 +171,14 @@ def main():
     from paper_2511_06627_amd.plan import Plan
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: under rocprofv3 --pmc its FETCH_SIZE and
+        # WRITE_SIZE calibrate the counters against known bytes
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     plan = Plan.from_config(cfg, cpu["op_scale"], precisions=("fp32", "mixed"))
     x = torch.from_numpy(cpu["phantom"]).float().cuda()
     b = torch.from_numpy(cpu["b"]).cuda()

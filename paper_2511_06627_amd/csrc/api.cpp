@@ -14,13 +14,46 @@ using namespace mpi3d;
 
 namespace {
 
-struct OpWs {
-    float *rt;        // projections [L][nup]
-    float *part;      // split partials
-    double *norm;     // spare norm partials
-    float *rowscale;  // [L] mixed per-line scales
-    uint16_t *xb;     // mixed bf16 shadow of a volume
+inline int herr(hipError_t e) { return e == hipSuccess ? MPI3D_OK : MPI3D_EDEVICE; }
+
+#define TRY(expr)                                   \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return MPI3D_EDEVICE; \
+    } while (0)
+
+#define TRYRC(expr)               \
+    do {                          \
+        int _rc = (expr);         \
+        if (_rc) return _rc;      \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
 };
+
+int ws_ok(const void *ws, size_t bytes, size_t need)
+{
+    if (!ws) return MPI3D_EINVAL;
+    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (bytes < need) return MPI3D_ENOMEM;
+    return MPI3D_OK;
+}
+
+}  // namespace
+
+namespace mpi3d {
 
 OpWs carve_op(const mpi3d_plan *pl, void *ws)
 {
@@ -34,17 +67,6 @@ OpWs carve_op(const mpi3d_plan *pl, void *ws)
     return w;
 }
 
-SigArgs sig_args(const mpi3d_plan *pl)
-{
-    SigArgs a{};
-    a.kf = pl->kf; a.ff = pl->ff; a.fa = pl->fa; a.ka = pl->ka;
-    a.kf16 = pl->kf16; a.ff16 = pl->ff16; a.fa16 = pl->fa16; a.ka16 = pl->ka16;
-    a.band_scale = pl->band_scale;
-    a.nu = pl->nu; a.nup = pl->nup; a.nb2 = pl->nb2; a.nbp2 = pl->nbp2; a.nct = pl->nct;
-    a.nchunks = pl->nchunks; a.cps = pl->cps; a.nsplit = pl->nsplit; a.ngroups = pl->ngroups; a.gct = pl->gct;
-    return a;
-}
-
 int check_prec(const mpi3d_plan *pl, int32_t precision)
 {
     if (precision != MPI3D_FP32 && precision != MPI3D_MIXED) return MPI3D_EINVAL;
@@ -52,81 +74,88 @@ int check_prec(const mpi3d_plan *pl, int32_t precision)
     return MPI3D_OK;
 }
 
-inline int herr(hipError_t e) { return e == hipSuccess ? MPI3D_OK : MPI3D_EDEVICE; }
-
-#define TRY(expr)                                   \
-    do {                                            \
-        hipError_t _e = (expr);                     \
-        if (_e != hipSuccess) return MPI3D_EDEVICE; \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        hipGetDevice(&prev);
-        if (prev != dev) hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        hipGetDevice(&cur);
-        if (prev >= 0 && cur != prev) hipSetDevice(prev);
-    }
-};
-
-}  // namespace
-
-namespace mpi3d {
-
-// Lines (stride in_stride) -> data (interleaved complex, L x nb), optionally
-// out = b_sub - A_DC rho, with float64 partial norms of `out`.
-int signal_forward(const mpi3d_plan *pl, int prec, const float *rho, int in_stride, float *out, const float *b_sub,
-                   double *norm_parts, int *nnorm, const OpWs &w, hipStream_t st)
+static SigArgs sig_args(const mpi3d_plan *pl, bool serve)
 {
-    SigArgs a = sig_args(pl);
-    a.njobs = 1;
-    a.jobs[0].in = rho;
-    a.jobs[0].in_stride = in_stride;
-    a.jobs[0].part = w.part;
-    a.jobs[0].part_stride = pl->L * pl->nbp2;
-    a.jobs[0].row_scale = w.rowscale;
-    a.jobs[0].rows = (int)pl->L;
-    a.jobs[0].tile0 = 0;
-    a.total_tiles = (int)((pl->L + kRowsPerBlock - 1) / kRowsPerBlock);
-    if (prec == MPI3D_MIXED) TRY(launch_row_scale(pl->L, pl->nu, in_stride, rho, nullptr, w.rowscale, st));
-    TRY(launch_sig_fwd(pl, prec, a, st));
-    const bool mixed = prec == MPI3D_MIXED;
-    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->nsplit, pl->L * pl->nbp2, w.part, mixed ? w.rowscale : nullptr,
-                          mixed ? pl->col_scale : nullptr, b_sub, out, norm_parts, nnorm, st));
+    SigArgs a{};
+    a.kf = pl->kf; a.ff = pl->ff; a.fa = pl->fa; a.ka = pl->ka;
+    a.kf16 = pl->kf16; a.ff16 = pl->ff16; a.fa16 = pl->fa16; a.ka16 = pl->ka16;
+    a.band_scale = pl->band_scale;
+    a.nu = pl->nu; a.nup = pl->nup; a.nb2 = pl->nb2; a.nbp2 = pl->nbp2; a.nct = pl->nct;
+    a.nchunks = pl->nchunks;
+    a.cps = serve ? pl->serve_cps : pl->cps;
+    a.nsplit = serve ? pl->serve_nsplit : pl->nsplit;
+    a.ngroups = pl->ngroups; a.gct = pl->gct;
+    return a;
+}
+
+static int nsplit_of(const mpi3d_plan *pl, bool serve) { return serve ? pl->serve_nsplit : pl->nsplit; }
+
+static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
+{
+    if (n < 1 || n > kMaxJobs) return MPI3D_EINVAL;
+    const mpi3d_plan *pl = jobs[0].pl;
+    SigArgs a = sig_args(pl, serve);
+    int tiles = 0;
+    for (int j = 0; j < n; ++j) {
+        const mpi3d_plan *pj = jobs[j].pl;
+        if (pj->line_key != pl->line_key) return MPI3D_EINVAL;
+        if (prec == MPI3D_MIXED) {
+            // per-line power-of-two scales for the fp16 operands
+            if (fwd) TRY(launch_row_scale(pj->L, pj->nu, jobs[j].in_stride, jobs[j].in, nullptr, jobs[j].w->rowscale, st));
+            else TRY(launch_row_scale(pj->L, pj->nb2, jobs[j].in_stride, jobs[j].in, pj->band_scale,
+                                      jobs[j].w->rowscale, st));
+        }
+        SigJob &sj = a.jobs[j];
+        sj.in = jobs[j].in;
+        sj.in_stride = jobs[j].in_stride;
+        sj.part = jobs[j].w->part;
+        sj.part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
+        sj.row_scale = jobs[j].w->rowscale;
+        sj.rows = (int)pj->L;
+        sj.tile0 = tiles;
+        tiles += (int)((pj->L + kRowsPerBlock - 1) / kRowsPerBlock);
+    }
+    a.njobs = n;
+    a.total_tiles = tiles;
+    TRY(fwd ? launch_sig_fwd(pl, prec, a, st) : launch_sig_adj(pl, prec, a, st));
     return MPI3D_OK;
 }
 
-// Data -> lines (stride out_stride): Re(A_DC^H y).
-int signal_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *rho, int out_stride, const OpWs &w,
-                   hipStream_t st)
+int sig_forward_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
 {
-    SigArgs a = sig_args(pl);
-    a.njobs = 1;
-    a.jobs[0].in = y;
-    a.jobs[0].in_stride = pl->nb2;
-    a.jobs[0].part = w.part;
-    a.jobs[0].part_stride = pl->L * pl->nup;
-    a.jobs[0].row_scale = w.rowscale;
-    a.jobs[0].rows = (int)pl->L;
-    a.jobs[0].tile0 = 0;
-    a.total_tiles = (int)((pl->L + kRowsPerBlock - 1) / kRowsPerBlock);
-    if (prec == MPI3D_MIXED) TRY(launch_row_scale(pl->L, pl->nb2, pl->nb2, y, pl->band_scale, w.rowscale, st));
-    TRY(launch_sig_adj(pl, prec, a, st));
+    return sig_jobs(true, prec, jobs, n, serve, st);
+}
+int sig_adjoint_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
+{
+    return sig_jobs(false, prec, jobs, n, serve, st);
+}
+
+// Split sums -> data: out = c_A * sum (or b_sub - c_A * sum), float64 norms.
+static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool serve, float *out, const float *b_sub,
+                          double *norm_parts, int *nnorm, hipStream_t st)
+{
     const bool mixed = prec == MPI3D_MIXED;
-    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride, pl->nsplit * pl->ngroups, pl->L * pl->nup,
-                                    w.part, mixed ? w.rowscale : nullptr, mixed ? pl->adj_scale16 : 1.0f, rho, st));
+    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, nsplit_of(pl, serve), pl->L * pl->nbp2, w.part,
+                          mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
+                          norm_parts, nnorm, st));
     return MPI3D_OK;
 }
 
-// xb: bf16 copy of x for the mixed path (null: convert x into the workspace)
-int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *out, const float *b_sub, double *norm_parts,
-                  int *nnorm, const OpWs &w, hipStream_t st, const uint16_t *xb = nullptr)
+// Split sums -> lines (stride out_stride): c_A * Re(A_DC^H y).
+static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool serve, float *out, int out_stride,
+                          hipStream_t st)
+{
+    const bool mixed = prec == MPI3D_MIXED;
+    const double scale = pl->op_scale * (mixed ? (double)pl->adj_scale16 : 1.0);
+    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride, nsplit_of(pl, serve) * pl->ngroups,
+                                    pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st));
+    return MPI3D_OK;
+}
+
+// P x into the workspace lines; the mixed path gathers from a bf16 copy
+// (xb, or x converted into the workspace when xb is null).
+static int project_into(const mpi3d_plan *pl, int prec, const float *x, const uint16_t *xb, const OpWs &w,
+                        hipStream_t st)
 {
     if (prec == MPI3D_MIXED) {
         if (!xb) {
@@ -137,42 +166,156 @@ int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *out, co
     } else {
         TRY(launch_project(pl, x, nullptr, w.rt, st));
     }
-    return signal_forward(pl, prec, w.rt, pl->nup, out, b_sub, norm_parts, nnorm, w, st);
+    return MPI3D_OK;
 }
 
-int apply_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *xo, const float *x_sub, double lambda,
-                  double *norm_parts, int *nparts, const OpWs &w, hipStream_t st)
+static int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *out, const OpWs &w, hipStream_t st)
 {
-    int rc = signal_adjoint(pl, prec, y, w.rt, pl->nup, w, st);
-    if (rc) return rc;
-    TRY(launch_backproject(pl, w.rt, xo, x_sub, lambda, norm_parts, nparts, st));
+    TRYRC(project_into(pl, prec, x, nullptr, w, st));
+    LineJob j{pl, w.rt, pl->nup, &w};
+    TRYRC(sig_forward_jobs(prec, &j, 1, false, st));
+    return reduce_forward(pl, prec, w, false, out, nullptr, nullptr, nullptr, st);
+}
+
+static int apply_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *xo, const OpWs &w, hipStream_t st)
+{
+    LineJob j{pl, y, pl->nb2, &w};
+    TRYRC(sig_adjoint_jobs(prec, &j, 1, false, st));
+    TRYRC(reduce_adjoint(pl, prec, w, false, w.rt, pl->nup, st));
+    TRY(launch_backproject(pl, w.rt, xo, nullptr, 0.0, nullptr, nullptr, st));
+    return MPI3D_OK;
+}
+
+// ---- CGLS -------------------------------------------------------------------
+
+void Cgls::init(const mpi3d_plan *plan, const float *b_, float *x_, void *ws, double lam, double *h)
+{
+    pl = plan;
+    b = b_;
+    x = x_;
+    lambda = lam;
+    hist = h;
+    char *base = (char *)ws;
+    w = carve_op(pl, base + pl->sw_op);
+    r = (float *)(base + pl->sw_r);
+    q = (float *)(base + pl->sw_q);
+    s = (float *)(base + pl->sw_s);
+    p = (float *)(base + pl->sw_p);
+    scal = (double *)(base + pl->sw_scal);
+    parts_q = (double *)(base + pl->sw_parts);
+    parts_p = parts_q + kMaxNormParts;
+    parts_s = parts_p + kMaxNormParts;
+}
+
+int Cgls::restart_a(bool x_zero, hipStream_t st)
+{
+    if (!started) TRY(launch_scal_init(scal, st));
+    if (x_zero) {
+        TRY(launch_copy(r, b, 2 * pl->L * pl->nb, st));
+        return MPI3D_OK;
+    }
+    return project_into(pl, MPI3D_FP32, x, nullptr, w, st);
+}
+
+int Cgls::restart_b(bool x_zero, hipStream_t st)
+{
+    if (x_zero) return MPI3D_OK;
+    return reduce_forward(pl, MPI3D_FP32, w, serve, r, b, nullptr, nullptr, st);
+}
+
+int Cgls::restart_c(hipStream_t st)
+{
+    TRYRC(reduce_adjoint(pl, MPI3D_FP32, w, serve, w.rt, pl->nup, st));
+    TRY(launch_backproject(pl, w.rt, s, x, lambda, parts_s, &ns, st));
+    TRY(launch_beta(scal, parts_s, ns, 1, started ? 0 : 1, hist, step, st));
+    TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 1, st));
+    started = true;
+    return MPI3D_OK;
+}
+
+int Cgls::iter_a(int prec, hipStream_t st)
+{
+    return project_into(pl, prec, p, prec == MPI3D_MIXED ? pb : nullptr, w, st);
+}
+
+int Cgls::iter_b(int prec, hipStream_t st)
+{
+    TRYRC(reduce_forward(pl, prec, w, serve, q, nullptr, parts_q, &nq, st));
+    TRY(launch_alpha(scal, parts_q, nq, parts_p, np, lambda, hist, step, st));
+    TRY(launch_update_xr2(x, p, r, q, pl->nvox, 2 * pl->L * pl->nb, scal, st));
+    return MPI3D_OK;
+}
+
+int Cgls::iter_c(int prec, hipStream_t st)
+{
+    TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
+    TRY(launch_backproject(pl, w.rt, s, x, lambda, parts_s, &ns, st));
+    TRY(launch_beta(scal, parts_s, ns, 0, 0, hist, step, st));
+    TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 0, st));
+    ++step;
+    return MPI3D_OK;
+}
+
+int Cgls::restart(bool x_zero, hipStream_t st)
+{
+    TRYRC(restart_a(x_zero, st));
+    if (!x_zero) {
+        LineJob j{pl, w.rt, pl->nup, &w};
+        TRYRC(sig_forward_jobs(MPI3D_FP32, &j, 1, serve, st));
+    }
+    TRYRC(restart_b(x_zero, st));
+    LineJob j{pl, r, pl->nb2, &w};
+    TRYRC(sig_adjoint_jobs(MPI3D_FP32, &j, 1, serve, st));
+    return restart_c(st);
+}
+
+int Cgls::iterate(int prec, hipStream_t st)
+{
+    TRYRC(iter_a(prec, st));
+    LineJob jf{pl, w.rt, pl->nup, &w};
+    TRYRC(sig_forward_jobs(prec, &jf, 1, serve, st));
+    TRYRC(iter_b(prec, st));
+    LineJob ja{pl, r, pl->nb2, &w};
+    TRYRC(sig_adjoint_jobs(prec, &ja, 1, serve, st));
+    return iter_c(prec, st);
+}
+
+int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o)
+{
+    if (!o) return MPI3D_EINVAL;
+    if (!(o->lambda >= 0.0)) return MPI3D_EINVAL;
+    if (o->clamp_every < 0) return MPI3D_EINVAL;
+    if (check_prec(pl, o->precision)) return MPI3D_EINVAL;
+    if (o->precision == MPI3D_FP32 && o->iters < 0) return MPI3D_EINVAL;
+    if (o->precision == MPI3D_MIXED && (o->refine_sweeps < 1 || o->inner_iters < 1)) return MPI3D_EINVAL;
+    if (o->precision == MPI3D_MIXED && !(pl->precisions & (1 << MPI3D_FP32))) return MPI3D_EINVAL;
     return MPI3D_OK;
 }
 
 }  // namespace mpi3d
 
+// ---- operator entry points ---------------------------------------------------
+
 extern "C" int mpi3d_forward(const mpi3d_plan *pl, int32_t precision, const float *x, float *b, void *ws,
                              size_t ws_bytes, void *stream)
 {
-    if (!pl || !x || !b || !ws) return MPI3D_EINVAL;
-    if (int rc = check_prec(pl, precision)) return rc;
-    if (ws_bytes < pl->op_ws_bytes) return MPI3D_ENOMEM;
-    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (!pl || !x || !b) return MPI3D_EINVAL;
+    TRYRC(check_prec(pl, precision));
+    TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
     OpWs w = carve_op(pl, ws);
-    return apply_forward(pl, precision, x, b, nullptr, nullptr, nullptr, w, (hipStream_t)stream);
+    return apply_forward(pl, precision, x, b, w, (hipStream_t)stream);
 }
 
 extern "C" int mpi3d_adjoint(const mpi3d_plan *pl, int32_t precision, const float *b, float *x, void *ws,
                              size_t ws_bytes, void *stream)
 {
-    if (!pl || !x || !b || !ws) return MPI3D_EINVAL;
-    if (int rc = check_prec(pl, precision)) return rc;
-    if (ws_bytes < pl->op_ws_bytes) return MPI3D_ENOMEM;
-    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (!pl || !x || !b) return MPI3D_EINVAL;
+    TRYRC(check_prec(pl, precision));
+    TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
     OpWs w = carve_op(pl, ws);
-    return apply_adjoint(pl, precision, b, x, nullptr, 0.0, nullptr, nullptr, w, (hipStream_t)stream);
+    return apply_adjoint(pl, precision, b, x, w, (hipStream_t)stream);
 }
 
 extern "C" int mpi3d_project(const mpi3d_plan *pl, const float *x, float *rho, void *stream)
@@ -192,121 +335,39 @@ extern "C" int mpi3d_backproject(const mpi3d_plan *pl, const float *rho, float *
 extern "C" int mpi3d_signal_fwd(const mpi3d_plan *pl, int32_t precision, const float *rho, float *b, void *ws,
                                 size_t ws_bytes, void *stream)
 {
-    if (!pl || !rho || !b || !ws) return MPI3D_EINVAL;
-    if (int rc = check_prec(pl, precision)) return rc;
-    if (ws_bytes < pl->op_ws_bytes) return MPI3D_ENOMEM;
-    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (!pl || !rho || !b) return MPI3D_EINVAL;
+    TRYRC(check_prec(pl, precision));
+    TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
+    hipStream_t st = (hipStream_t)stream;
     OpWs w = carve_op(pl, ws);
-    return signal_forward(pl, precision, rho, pl->nu, b, nullptr, nullptr, nullptr, w, (hipStream_t)stream);
+    LineJob j{pl, rho, pl->nu, &w};
+    TRYRC(sig_forward_jobs(precision, &j, 1, false, st));
+    return reduce_forward(pl, precision, w, false, b, nullptr, nullptr, nullptr, st);
 }
 
 extern "C" int mpi3d_signal_adj(const mpi3d_plan *pl, int32_t precision, const float *b, float *rho, void *ws,
                                 size_t ws_bytes, void *stream)
 {
-    if (!pl || !rho || !b || !ws) return MPI3D_EINVAL;
-    if (int rc = check_prec(pl, precision)) return rc;
-    if (ws_bytes < pl->op_ws_bytes) return MPI3D_ENOMEM;
-    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (!pl || !rho || !b) return MPI3D_EINVAL;
+    TRYRC(check_prec(pl, precision));
+    TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
+    hipStream_t st = (hipStream_t)stream;
     OpWs w = carve_op(pl, ws);
-    return signal_adjoint(pl, precision, b, rho, pl->nu, w, (hipStream_t)stream);
+    LineJob j{pl, b, pl->nb2, &w};
+    TRYRC(sig_adjoint_jobs(precision, &j, 1, false, st));
+    return reduce_adjoint(pl, precision, w, false, rho, pl->nu, st);
 }
 
-// ---------------------------------------------------------------------------
-// CGLS
-// ---------------------------------------------------------------------------
-namespace mpi3d {
-
-struct Cgls {
-    const mpi3d_plan *pl;
-    const float *b;
-    float *x, *r, *q, *s, *p;
-    double *scal, *parts_q, *parts_p, *parts_s;
-    double *hist;
-    uint16_t *pb = nullptr;     // bf16 shadow of p for the mixed operator
-    OpWs w;
-    double lambda;
-    int nq = 0, np = 0, ns = 0;
-    int step = 0;
-    bool started = false;
-
-    int init(const mpi3d_plan *plan, const float *b_, float *x_, void *ws, double lam, double *h)
-    {
-        pl = plan;
-        b = b_;
-        x = x_;
-        lambda = lam;
-        hist = h;
-        char *base = (char *)ws;
-        w = carve_op(pl, base + pl->sw_op);
-        r = (float *)(base + pl->sw_r);
-        q = (float *)(base + pl->sw_q);
-        s = (float *)(base + pl->sw_s);
-        p = (float *)(base + pl->sw_p);
-        scal = (double *)(base + pl->sw_scal);
-        parts_q = (double *)(base + pl->sw_parts);
-        parts_p = parts_q + kMaxNormParts;
-        parts_s = parts_p + kMaxNormParts;
-        return MPI3D_OK;
-    }
-
-    // r = b - A32 x (or b when x is known zero), s = A32^T r - lambda x,
-    // gamma = |s|^2, p = s.
-    int restart(hipStream_t st, bool x_zero)
-    {
-        const long ndata = 2 * pl->L * pl->nb;
-        if (!started) TRY(launch_scal_init(scal, st));
-        if (x_zero) {
-            TRY(launch_copy(r, b, ndata, st));
-        } else {
-            int rc = apply_forward(pl, MPI3D_FP32, x, r, b, nullptr, nullptr, w, st);
-            if (rc) return rc;
-        }
-        int rc = apply_adjoint(pl, MPI3D_FP32, r, s, x, lambda, parts_s, &ns, w, st);
-        if (rc) return rc;
-        TRY(launch_beta(scal, parts_s, ns, 1, started ? 0 : 1, hist, step, st));
-        TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 1, st));
-        started = true;
-        return MPI3D_OK;
-    }
-
-    int iterate(int prec, hipStream_t st)
-    {
-        const long ndata = 2 * pl->L * pl->nb;
-        int rc = apply_forward(pl, prec, p, q, nullptr, parts_q, &nq, w, st, prec == MPI3D_MIXED ? pb : nullptr);
-        if (rc) return rc;
-        TRY(launch_alpha(scal, parts_q, nq, parts_p, np, lambda, hist, step, st));
-        TRY(launch_update_xr2(x, p, r, q, pl->nvox, ndata, scal, st));
-        rc = apply_adjoint(pl, prec, r, s, x, lambda, parts_s, &ns, w, st);
-        if (rc) return rc;
-        TRY(launch_beta(scal, parts_s, ns, 0, 0, hist, step, st));
-        TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 0, st));
-        ++step;
-        return MPI3D_OK;
-    }
-};
-
-int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o)
-{
-    if (!o) return MPI3D_EINVAL;
-    if (!(o->lambda >= 0.0)) return MPI3D_EINVAL;
-    if (o->clamp_every < 0) return MPI3D_EINVAL;
-    if (check_prec(pl, o->precision)) return MPI3D_EINVAL;
-    if (o->precision == MPI3D_FP32 && o->iters < 0) return MPI3D_EINVAL;
-    if (o->precision == MPI3D_MIXED && (o->refine_sweeps < 1 || o->inner_iters < 1)) return MPI3D_EINVAL;
-    return MPI3D_OK;
-}
-
-}  // namespace mpi3d
+// ---- solve -------------------------------------------------------------------
 
 extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const mpi3d_solve_opts *o, void *ws,
                            size_t ws_bytes, double *hist, mpi3d_solve_report *report, void *stream)
 {
-    if (!pl || !b || !x || !ws) return MPI3D_EINVAL;
-    if (int rc = validate_opts(pl, o)) return rc;
-    if (ws_bytes < pl->solve_ws_bytes) return MPI3D_ENOMEM;
-    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (!pl || !b || !x) return MPI3D_EINVAL;
+    TRYRC(validate_opts(pl, o));
+    TRYRC(ws_ok(ws, ws_bytes, pl->solve_ws_bytes));
     DeviceGuard dg(pl->device);
     hipStream_t st = (hipStream_t)stream;
     Cgls cg;
@@ -314,25 +375,23 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
     if (o->precision == MPI3D_MIXED) cg.pb = cg.w.xb;
     bool xz = o->x0_is_zero != 0;
     if (xz) TRY(launch_fill(x, pl->nvox, 0.f, st));
-    int rc = MPI3D_OK;
     if (o->precision == MPI3D_FP32) {
-        rc = cg.restart(st, xz);
-        for (int it = 0; !rc && it < o->iters; ++it) {
-            rc = cg.iterate(MPI3D_FP32, st);
+        TRYRC(cg.restart(xz, st));
+        for (int it = 0; it < o->iters; ++it) {
+            TRYRC(cg.iterate(MPI3D_FP32, st));
             const bool last = it + 1 == o->iters;
-            if (!rc && o->clamp_every > 0 && ((it + 1) % o->clamp_every == 0 || last)) {
+            if (o->clamp_every > 0 && ((it + 1) % o->clamp_every == 0 || last)) {
                 TRY(launch_clamp(x, pl->nvox, st));
-                if (!last) rc = cg.restart(st, false);
+                if (!last) TRYRC(cg.restart(false, st));
             }
         }
     } else {
-        for (int sw = 0; !rc && sw < o->refine_sweeps; ++sw) {
-            rc = cg.restart(st, xz && sw == 0);
-            for (int it = 0; !rc && it < o->inner_iters; ++it) rc = cg.iterate(MPI3D_MIXED, st);
-            if (!rc && o->clamp_every > 0) TRY(launch_clamp(x, pl->nvox, st));
+        for (int sw = 0; sw < o->refine_sweeps; ++sw) {
+            TRYRC(cg.restart(xz && sw == 0, st));
+            for (int it = 0; it < o->inner_iters; ++it) TRYRC(cg.iterate(MPI3D_MIXED, st));
+            if (o->clamp_every > 0) TRY(launch_clamp(x, pl->nvox, st));
         }
     }
-    if (rc) return rc;
     if (report) {
         double sc[16];
         TRY(hipMemcpyAsync(sc, cg.scal, sizeof(double) * scal_slots(), hipMemcpyDeviceToHost, st));
@@ -345,13 +404,14 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
     return MPI3D_OK;
 }
 
+// ---- benchmark support ----------------------------------------------------------
+
 extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t precision, int32_t repeats, float *x,
                                  const float *b, void *ws, size_t ws_bytes, void *stream, float *avg_ms)
 {
-    if (!pl || !x || !b || !ws || !avg_ms || repeats < 1 || kernel < 0 || kernel > 3) return MPI3D_EINVAL;
-    if (int rc = check_prec(pl, precision)) return rc;
-    if (ws_bytes < pl->op_ws_bytes) return MPI3D_ENOMEM;
-    if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
+    if (!pl || !x || !b || !avg_ms || repeats < 1 || kernel < 0 || kernel > 3) return MPI3D_EINVAL;
+    TRYRC(check_prec(pl, precision));
+    TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
     hipStream_t st = (hipStream_t)stream;
     OpWs w = carve_op(pl, ws);
@@ -361,7 +421,7 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         (void)hipEventDestroy(e0);
         return MPI3D_EDEVICE;
     }
-    SigArgs a = sig_args(pl);
+    SigArgs a = sig_args(pl, false);
     a.njobs = 1;
     a.jobs[0].row_scale = w.rowscale;
     a.jobs[0].rows = (int)pl->L;

@@ -93,6 +93,8 @@ struct mpi3d_plan {
     long nvox;
     // signal kernel configuration
     int nchunks, cps, nsplit, ngroups, gct;
+    int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
+    uint64_t line_key;             // equal keys <=> identical line tables
     // projection configuration
     int angles_per_block, n_angle_groups, band_rows, n_bands, kz;
     // device tables (one allocation)
@@ -125,12 +127,10 @@ int sig_adj_supported(int nup, int gct, int precision);
 
 // Reductions and vector kernels (vec.hip)
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
-                             const float *row_scale, const float *col_scale, const float *b_sub, float *out,
-                             double *norm_parts, int *nnorm, hipStream_t st);
-hipError_t launch_reduce_lines(long rows, int nu, int nup, int nparts, long part_stride, const float *part,
-                               const float *row_scale, float scale, float *out, hipStream_t st);
+                             const float *row_scale, const float *col_scale, double scale, const float *b_sub,
+                             float *out, double *norm_parts, int *nnorm, hipStream_t st);
 hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
-                                       const float *part, const float *row_scale, float scale, float *out,
+                                       const float *part, const float *row_scale, double scale, float *out,
                                        hipStream_t st);
 hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st);
 hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
@@ -159,5 +159,67 @@ hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *r
 hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,
                                       const float *x_sub, double lambda, double *norm_parts, int *nparts,
                                       hipStream_t st);
+
+}  // namespace mpi3d
+
+// ---------------------------------------------------------------------------
+// Operator and CGLS building blocks shared by the solve and serving paths
+// (api.cpp).
+// ---------------------------------------------------------------------------
+namespace mpi3d {
+
+struct OpWs {
+    float *rt;        // projections [L][nup]
+    float *part;      // split partial sums
+    double *norm;     // spare norm partials
+    float *rowscale;  // [L] per-line scales of the fp16 path
+    uint16_t *xb;     // bf16 copy of a volume (mixed path)
+};
+OpWs carve_op(const mpi3d_plan *pl, void *ws);
+int check_prec(const mpi3d_plan *pl, int32_t precision);
+
+// One request's lines in a merged signal launch.
+struct LineJob {
+    const mpi3d_plan *pl;
+    const float *in;      // fwd: projections, adj: data
+    int in_stride;
+    const OpWs *w;
+};
+// Signal contraction over the lines of n jobs (n <= kMaxJobs) sharing one
+// line class, in one launch; `serve` selects the class-fixed time split.
+int sig_forward_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st);
+int sig_adjoint_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st);
+
+// CGLS state of one solve, advanced in phases so several solves can share the
+// signal launches between them (see serve.cpp).  Scalars stay on the device.
+struct Cgls {
+    const mpi3d_plan *pl = nullptr;
+    const float *b = nullptr;
+    float *x = nullptr, *r = nullptr, *q = nullptr, *s = nullptr, *p = nullptr;
+    double *scal = nullptr, *parts_q = nullptr, *parts_p = nullptr, *parts_s = nullptr;
+    double *hist = nullptr;
+    uint16_t *pb = nullptr;     // bf16 shadow of p for the mixed operator
+    OpWs w{};
+    double lambda = 0.0;
+    int nq = 0, np = 0, ns = 0;
+    int step = 0;
+    bool started = false;
+    bool serve = false;         // class-fixed time split (merged launches)
+
+    void init(const mpi3d_plan *plan, const float *b_, float *x_, void *ws, double lam, double *h);
+    // restart: r = b - A32 x (or b when x is zero), s = A32^T r - lambda x,
+    // gamma = |s|^2, p = s.  Phases around the two signal launches:
+    int restart_a(bool x_zero, hipStream_t st);       // projection of x (or r = b)
+    int restart_b(bool x_zero, hipStream_t st);       // r = b - (A x)
+    int restart_c(hipStream_t st);                    // s, gamma, p
+    // one iteration: q = A p; alpha; x, r; s = A^T r - lambda x; beta; p
+    int iter_a(int prec, hipStream_t st);             // projection of p
+    int iter_b(int prec, hipStream_t st);             // q, alpha, x += alpha p, r -= alpha q
+    int iter_c(int prec, hipStream_t st);             // s, beta, p
+    // whole steps, no merging
+    int restart(bool x_zero, hipStream_t st);
+    int iterate(int prec, hipStream_t st);
+};
+int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o);
 
 }  // namespace mpi3d

@@ -5,7 +5,9 @@
 //   cos/sin of the FFL angles           Sec. 2.2, eq. qtheta
 //   ray-sample coordinate bases          eq. ptheta2 (unit-step Riemann sum)
 //   PSF kernel K[n][p]                   eq. reals0 + Appendix B eq. PSF
-//       = c_A v_n L'((xi_n - u_p)/w) / w, xi_n = a sin(2 pi P n / T), v = xi'
+//       = v_n L'((xi_n - u_p)/w) / w, xi_n = a sin(2 pi P n / T), v = xi'
+//       (the global scale c_A is applied in fp64 when split sums are reduced,
+//       so scans that differ only in c_A share identical line tables)
 //   band DFT F[n][2j], F[n][2j+1]        Appendix A (+i, 1/sqrt(T)) on the kept
 //       = Re/Im(D_j e^{+2 pi i (omega_j n mod T)/T}) / sqrt(T)   bins (eq. bcompress,
 //                                        eq. DCmodel)
@@ -66,11 +68,14 @@ int ray_count(int nx, int ny)
     return n;
 }
 
-// Choose the T-split so that (row tiles x splits x groups) blocks fill the
-// 256 compute units in as few rounds as possible (one block per CU).
+// Choose the T-split: (line tiles x splits x groups) blocks, two resident per
+// CU.  Cost in units of one block's time per chunk: rounds of blocks times
+// chunks per block, plus each split's partial sums written and read back by
+// the reduction (measured on MI355X at about a tenth of a chunk per split for
+// the 192 x 192 x 96 scan).
 void choose_split(mpi3d_plan *pl)
 {
-    const int cus = 512;   // two 8-wave blocks per CU
+    const int slots = 512;
     long tiles = (pl->L + kRowsPerBlock - 1) / kRowsPerBlock;
     int best_s = 1;
     double best = 1e30;
@@ -78,10 +83,8 @@ void choose_split(mpi3d_plan *pl)
         int cps = (pl->nchunks + s - 1) / s;
         int used = (pl->nchunks + cps - 1) / cps;  // splits actually non-empty
         long blocks = tiles * used * pl->ngroups;
-        long rounds = (blocks + cus - 1) / cus;
-        // cost: rounds x chunks per block, plus a small charge per split for
-        // the partial-sum traffic
-        double cost = (double)rounds * cps * (1.0 + 0.002 * used);
+        long rounds = (blocks + slots - 1) / slots;
+        double cost = (double)rounds * cps + 0.1 * used;
         if (cost < best - 1e-9) {
             best = cost;
             best_s = used;
@@ -187,6 +190,11 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         return MPI3D_ENOTSUP;
     }
     choose_split(pl);
+    // Serving launches merge the lines of several requests, so their time
+    // split must not depend on the line count: a fixed split per line class.
+    pl->serve_nsplit = std::min(pl->nchunks, 16);
+    pl->serve_cps = (pl->nchunks + pl->serve_nsplit - 1) / pl->serve_nsplit;
+    pl->serve_nsplit = (pl->nchunks + pl->serve_cps - 1) / pl->serve_cps;
 
     // projection configuration
     {
@@ -249,7 +257,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             double ph = om * n;
             double xi = pl->a * std::sin(ph), v = pl->a * om * std::cos(ph);
             for (int p = 0; p < NU; ++p)
-                K[(size_t)n * NUP + p] = pl->op_scale * v * langevin_deriv((xi - (p - cu)) / pl->w) / pl->w;
+                K[(size_t)n * NUP + p] = v * langevin_deriv((xi - (p - cu)) / pl->w) / pl->w;
         }
     }
     // band DFT F[n][c] (real columns: 2j = Re, 2j+1 = Im)
@@ -454,7 +462,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         auto put = [&](size_t bytes) { o = align256(o); size_t r = o; o += bytes; return r; };
         long parts_rows = std::max<long>(pl->nbp2, pl->nup);
         pl->ws_rt = put(sizeof(float) * pl->L * pl->nup);
-        pl->ws_part = put(sizeof(float) * (size_t)pl->nsplit * pl->ngroups * pl->L * parts_rows);
+        pl->ws_part = put(sizeof(float) * (size_t)std::max(pl->nsplit, pl->serve_nsplit) * pl->ngroups * pl->L *
+                          parts_rows);
         pl->ws_norm = put(sizeof(double) * kMaxNormParts);
         pl->ws_rowscale = put(sizeof(float) * pl->L);
         pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
@@ -472,6 +481,21 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->sw_scal = put(sizeof(double) * 64);
         pl->sw_parts = put(sizeof(double) * 3 * kMaxNormParts);
         pl->solve_ws_bytes = align256(o);
+    }
+    {
+        // FNV-1a over the parameters that determine the line tables
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](const void *p, size_t n) {
+            const unsigned char *c = (const unsigned char *)p;
+            for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+        };
+        int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2, pl->ngroups,
+                      pl->gct, precisions};
+        double dbl[] = {pl->P, pl->a, pl->w};
+        mix(ints, sizeof(ints));
+        mix(dbl, sizeof(dbl));
+        if (g->rx_filter) mix(g->rx_filter, sizeof(float) * 2 * pl->nb);
+        pl->line_key = h;
     }
     *out = pl;
     return MPI3D_OK;

@@ -44,8 +44,26 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
 constexpr int kFwdThreads = 1024;
 constexpr int kMaxRaysPerThread = 4;
 
-__device__ __forceinline__ float ld(const float *p, int i) { return p[i]; }
-__device__ __forceinline__ float ld(const uint16_t *p, int i) { return __uint_as_float((uint32_t)p[i] << 16); }
+// Staged slice element (LDS column col = grid column col - 1):
+//  fp32 path: the voxel value;
+//  bf16 path (the mixed operator's gathers): a pair-packed word, low half the
+//  bf16 voxel and high half its right neighbour, so the two horizontal
+//  neighbours of a bilinear sample arrive in one 32-bit LDS read.
+__device__ __forceinline__ void corners(const float *l0, int W, float &v00, float &v10, float &v01, float &v11)
+{
+    v00 = l0[0];
+    v10 = l0[1];
+    v01 = l0[W];
+    v11 = l0[W + 1];
+}
+__device__ __forceinline__ void corners(const uint32_t *l0, int W, float &v00, float &v10, float &v01, float &v11)
+{
+    const uint32_t a = l0[0], b = l0[W];
+    v00 = __uint_as_float(a << 16);
+    v10 = __uint_as_float(a & 0xffff0000u);
+    v01 = __uint_as_float(b << 16);
+    v11 = __uint_as_float(b & 0xffff0000u);
+}
 
 // One bilinear sample of the staged band.  Branch-free: a sample whose 2x2
 // footprint lies outside the band reads a safe LDS address and contributes 0.
@@ -60,15 +78,20 @@ __device__ __forceinline__ float sample(const T *lds, int W, int nx, int nbase, 
     i0 = ok ? i0 : 0;
     j0 = ok ? j0 : 0;
     const float wx = fx - ix, wy = fy - iy;
-    const T *l0 = lds + j0 * W + i0;
-    const float v00 = ld(l0, 0), v10 = ld(l0, 1), v01 = ld(l0, W), v11 = ld(l0, W + 1);
+    float v00, v10, v01, v11;
+    corners(lds + j0 * W + i0, W, v00, v10, v01, v11);
     const float top = fmaf(wx, v10 - v00, v00);
     const float bot = fmaf(wx, v11 - v01, v01);
     return ok ? fmaf(wy, bot - top, top) : 0.f;
 }
 
-// T = float: the fp32 path.  T = uint16_t: bf16 bits, the mixed path's
-// gathers (half the LDS footprint and staging traffic; weights and sums fp32).
+__device__ __forceinline__ uint32_t bf16_at(const uint16_t *slice, int nx, int ny, int gj, int gi)
+{
+    return (gj >= 0 && gj < ny && gi >= 0 && gi < nx) ? (uint32_t)slice[(size_t)gj * nx + gi] : 0u;
+}
+
+// T = float: the fp32 path (reads x).  T = uint32_t: the bf16 path (reads the
+// bf16 copy xb, stages pair-packed words); weights and sums stay fp32.
 template <typename T>
 __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int out_stride)
 {
@@ -89,7 +112,8 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
 #pragma unroll
     for (int i = 0; i < kMaxRaysPerThread; ++i) acc[i] = 0.f;
 
-    const T *slice = (std::is_same<T, float>::value ? (const T *)a.x : (const T *)a.xb) + (size_t)k * a.nx * a.ny;
+    const float *slice = a.x ? a.x + (size_t)k * a.nx * a.ny : nullptr;
+    const uint16_t *sliceb = a.xb ? a.xb + (size_t)k * a.nx * a.ny : nullptr;
     for (int band = 0; band < a.n_bands; ++band) {
         const int jb0 = -1 + band * a.band_rows;               // first base row
         const int jb1 = min(jb0 + a.band_rows, a.ny);          // one past last base row
@@ -99,9 +123,13 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
         for (int idx = tid; idx < rows * W; idx += kFwdThreads) {
             int r = idx / W, col = idx - r * W;
             int gj = jb0 + r, gi = col - 1;
-            T v = 0;
-            if (gj >= 0 && gj < a.ny && gi >= 0 && gi < a.nx) v = slice[(size_t)gj * a.nx + gi];
-            lds[idx] = v;
+            if constexpr (std::is_same<T, float>::value) {
+                float v = 0.f;
+                if (gj >= 0 && gj < a.ny && gi >= 0 && gi < a.nx) v = slice[(size_t)gj * a.nx + gi];
+                lds[idx] = v;
+            } else {
+                lds[idx] = bf16_at(sliceb, a.nx, a.ny, gj, gi) | (bf16_at(sliceb, a.nx, a.ny, gj, gi + 1) << 16);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -317,7 +345,7 @@ hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *r
 // xb non-null: gather from the bf16 copy (mixed path)
 hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt, hipStream_t st)
 {
-    if (xb) return launch_fwd<uint16_t>(pl, nullptr, xb, rt, pl->nup, st);
+    if (xb) return launch_fwd<uint32_t>(pl, nullptr, xb, rt, pl->nup, st);
     return launch_fwd<float>(pl, x, nullptr, rt, pl->nup, st);
 }
 

@@ -30,11 +30,28 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return t;  // valid in thread 0
 }
 
+// sum_s pp[s * stride] in float64, in split order; four loads in flight
+__device__ __forceinline__ double sum_splits(const float *__restrict__ pp, int n, long stride)
+{
+    double v = 0.0;
+    int s = 0;
+    for (; s + 4 <= n; s += 4) {
+        const float a0 = pp[(long)s * stride], a1 = pp[(long)(s + 1) * stride];
+        const float a2 = pp[(long)(s + 2) * stride], a3 = pp[(long)(s + 3) * stride];
+        v += (double)a0;
+        v += (double)a1;
+        v += (double)a2;
+        v += (double)a3;
+    }
+    for (; s < n; ++s) v += (double)pp[(long)s * stride];
+    return v;
+}
+
 // out[row][c] = sign * sum_s part[s][row][c] * col_scale[c] / row_scale[row] (+ b_sub)
 __global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2, int nbp2, int nparts,
                                                                long part_stride, const float *__restrict__ part,
                                                                const float *__restrict__ row_scale,
-                                                               const float *__restrict__ col_scale,
+                                                               const float *__restrict__ col_scale, double scale,
                                                                const float *__restrict__ b_sub, float *out,
                                                                double *norm_parts)
 {
@@ -44,9 +61,8 @@ __global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2
     for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
         const long row = idx / nb2;
         const int c = (int)(idx - row * nb2);
-        const float *pp = part + row * nbp2 + c;
-        double v = 0.0;
-        for (int s = 0; s < nparts; ++s) v += (double)pp[(long)s * part_stride];
+        const double v0 = sum_splits(part + row * nbp2 + c, nparts, part_stride);
+        double v = v0 * scale;
         if (col_scale) v *= (double)col_scale[c];
         if (row_scale) v /= (double)row_scale[row];
         if (b_sub) v = (double)b_sub[idx] - v;
@@ -64,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2
 __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int nu, int nup, int out_stride,
                                                                  int nparts, long part_stride,
                                                                  const float *__restrict__ part,
-                                                                 const float *__restrict__ row_scale, float scale,
+                                                                 const float *__restrict__ row_scale, double scale,
                                                                  float *out)
 {
     const long n = rows * out_stride;
@@ -73,10 +89,8 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
         const int p = (int)(idx - row * out_stride);
         float o = 0.f;
         if (p < nu) {
-            const float *pp = part + row * nup + p;
-            double v = 0.0;
-            for (int s = 0; s < nparts; ++s) v += (double)pp[(long)s * part_stride];
-            v *= (double)scale;
+            double v = sum_splits(part + row * nup + p, nparts, part_stride);
+            v *= scale;
             if (row_scale) v /= (double)row_scale[row];
             o = (float)v;
         }
@@ -232,13 +246,15 @@ __global__ void scal_init_kernel(double *scal)
     if (threadIdx.x < S_NSLOTS) scal[threadIdx.x] = 0.0;
 }
 
-int grid_for(long n)
+int grid_for(long n, int cap = kVecBlocks)
 {
     long b = (n + kThreads - 1) / kThreads;
     if (b < 1) b = 1;
-    if (b > kVecBlocks) b = kVecBlocks;
+    if (b > cap) b = cap;
     return (int)b;
 }
+
+constexpr int kReduceBlocks = kMaxNormParts;   // the split reductions want many loads in flight
 
 }  // namespace
 
@@ -248,31 +264,27 @@ int scal_slot_gamma() { return S_GAMMA; }
 int scal_slot_gamma0() { return S_GAMMA0; }
 
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
-                             const float *row_scale, const float *col_scale, const float *b_sub, float *out,
-                             double *norm_parts, int *nnorm, hipStream_t st)
+                             const float *row_scale, const float *col_scale, double scale, const float *b_sub,
+                             float *out, double *norm_parts, int *nnorm, hipStream_t st)
 {
-    const int g = grid_for(rows * nb2);
+    const int g = grid_for(rows * nb2, kReduceBlocks);
     if (nnorm) *nnorm = g;
     hipLaunchKernelGGL(reduce_fwd_kernel, dim3(g), dim3(kThreads), 0, st, rows, nb2, nbp2, nparts, part_stride,
-                       part, row_scale, col_scale, b_sub, out, norm_parts);
+                       part, row_scale, col_scale, scale, b_sub, out, norm_parts);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
-                                       const float *part, const float *row_scale, float scale, float *out,
+                                       const float *part, const float *row_scale, double scale, float *out,
                                        hipStream_t st)
 {
-    const int g = grid_for(rows * out_stride);
+    const int g = grid_for(rows * out_stride, kReduceBlocks);
     hipLaunchKernelGGL(reduce_lines_kernel, dim3(g), dim3(kThreads), 0, st, rows, nu, nup, out_stride, nparts,
                        part_stride, part, row_scale, scale, out);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_lines(long rows, int nu, int nup, int nparts, long part_stride, const float *part,
-                               const float *row_scale, float scale, float *out, hipStream_t st)
-{
-    return launch_reduce_lines_strided(rows, nu, nup, nup, nparts, part_stride, part, row_scale, scale, out, st);
-}
+
 
 hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
                             hipStream_t st)

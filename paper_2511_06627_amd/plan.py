@@ -185,3 +185,55 @@ class Plan:
                                                       hptr, ctypes.byref(rep) if rep is not None else None,
                                                       _stream(stream)))
         return x, rep
+
+
+class State:
+    """One CGLS solve advanced a step at a time by ``batch_step`` (serving).
+
+    Owns (references) its data b, its volume x and its solver workspace; all
+    of them stay on the device for the state's whole life.
+    """
+
+    def __init__(self, plan, b, lam, precision="fp32", iters=0, refine_sweeps=0, inner_iters=0, clamp_every=0,
+                 x=None, ws=None):
+        plan._check_data(b)
+        self.plan = plan
+        self.b = b
+        self.x0_zero = x is None
+        self.x = torch.empty(plan.shape, dtype=torch.float32, device=plan.device) if x is None else x
+        plan._check_vol(self.x)
+        self.ws = plan.workspace("solve") if ws is None else ws
+        o = _lib.SolveOpts()
+        o.lam, o.iters, o.clamp_every = lam, iters, clamp_every
+        o.precision = PRECISION[precision]
+        o.refine_sweeps, o.inner_iters = refine_sweeps, inner_iters
+        o.x0_is_zero = 1 if self.x0_zero else 0
+        h = ctypes.c_void_p()
+        check("mpi3d_state_create", _lib.load().mpi3d_state_create(plan._h, _ptr(b), _ptr(self.x), ctypes.byref(o),
+                                                                    _ptr(self.ws), self.ws.numel(), ctypes.byref(h)))
+        self._h = h
+
+    def progress(self):
+        it = ctypes.c_int32()
+        done = ctypes.c_int32()
+        check("mpi3d_state_progress", _lib.load().mpi3d_state_progress(self._h, ctypes.byref(it), ctypes.byref(done)))
+        return int(it.value), bool(done.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().mpi3d_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_step(states, stream=None):
+    """One step (an iteration, or the restart opening a sweep) of every state."""
+    if not states:
+        return
+    arr = (ctypes.c_void_p * len(states))(*[s._h for s in states])
+    check("mpi3d_batch_step", _lib.load().mpi3d_batch_step(arr, len(states), _stream(stream)))
