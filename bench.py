@@ -115,32 +115,214 @@ def projection_bytes(cfg):
     return 4.0 * (cfg.n_angles * nvox + cfg.n_lines * cfg.n_u)
 
 
-def time_to_solve(plan, torch, b, xstar, lam, max_iters, check_every, precision="fp32"):
-    """Smallest iteration count whose iterate is within 1e-4 of x*, and the
-    device time of a solve with that many iterations (median of 3)."""
+def kernel_source_hash():
+    """sha256 over the library's kernel and launch sources: HBM traffic taken
+    from counters is only valid for the code it was measured on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2511_06627_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
+    or None when the sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
+def time_to_solve(plan, torch, b, xstar, lam, precision="fp32"):
+    """Cheapest schedule whose result is within 1e-4 relative L2 of x*, and the
+    wall time of a solve with it (median of 3, device synchronised).  FP32:
+    iteration counts in steps of 5; mixed: the refinement schedules in
+    MIXED_CANDIDATES, in order of total iterations."""
     import numpy as np
     bd = torch.from_numpy(b).cuda()
     xn = np.linalg.norm(xstar)
+    if precision == "fp32":
+        cands = [dict(iters=i) for i in range(5, 401, 5)]
+    else:
+        cands = [dict(precision="mixed", refine_sweeps=sw, inner_iters=n) for sw, n in MIXED_CANDIDATES]
     hit = None
     errs = []
-    for it in range(check_every, max_iters + 1, check_every):
-        x, _ = plan.solve(bd, lam, iters=it, report=False) if precision == "fp32" else \
-            plan.solve(bd, lam, precision="mixed", refine_sweeps=it // 20, inner_iters=20, report=False)
+    for kw in cands:
+        x, _ = plan.solve(bd, lam, report=False, **kw)
         err = float(np.linalg.norm(x.cpu().numpy() - xstar) / xn)
-        errs.append((it, err))
+        errs.append(err)
         if err <= 1e-4:
-            hit = it
+            hit = kw
             break
     if hit is None:
-        return {"iters": None, "seconds": None, "errors": errs}
+        return {"schedule": None, "seconds": None, "errors": errs}
     ts = []
     for _ in range(3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan.solve(bd, lam, iters=hit, report=False)
+        plan.solve(bd, lam, report=False, **hit)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
-    return {"iters": hit, "seconds": sorted(ts)[1], "rel_err": errs[-1][1]}
+    return {"schedule": hit, "seconds": round(sorted(ts)[1], 5), "rel_err": errs[-1]}
+
+
+# ---------------------------------------------------------------------------
+# Serving leg: the request stream, solved by the continuous batcher
+# ---------------------------------------------------------------------------
+MIXED_CANDIDATES = ((1, 40), (2, 25), (2, 30), (2, 40), (3, 30), (3, 40), (4, 40), (5, 40))
+
+
+def device_data(torch, plan, phantom, noise, seed):
+    """b = A x_phantom by the plan's FP32 operator, plus complex Gaussian noise
+    in the kept bins, standard deviation noise * max|b| per bin (seeded)."""
+    import numpy as np
+    x = torch.from_numpy(phantom).float().cuda()
+    b = plan.forward(x).cpu().numpy()
+    nrng = np.random.default_rng(seed)
+    sigma = noise * float(np.abs(b).max())
+    b = b + sigma / np.sqrt(2.0) * (nrng.standard_normal(b.shape) + 1j * nrng.standard_normal(b.shape))
+    return b.astype(np.complex64)
+
+
+def serve_requests(torch, n_requests):
+    """The seeded request stream: Poisson arrivals, geometry classes drawn
+    uniformly, each request's data made on the device.
+
+    Data: b = A x_phantom by the FP32 operator of the request's plan (c_A
+    estimated by the plan, op_scale = 0), plus complex Gaussian noise in the
+    kept bins with standard deviation (noise level) x max|b| per bin, drawn
+    from the request's own seed.  Returns (requests, plans, build seconds)."""
+    import numpy as np
+    from paper_2511_06627_amd import configs
+    from paper_2511_06627_amd.plan import Plan
+    from paper_2511_06627_amd.serve import Request
+    rng = np.random.default_rng(configs.SERVE_ARRIVAL_SEED)
+    draws = []
+    t = 0.0
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / configs.SERVE_RATE_HZ)
+        vol = configs.SERVE_VOLUMES[rng.integers(len(configs.SERVE_VOLUMES))]
+        m = configs.SERVE_ANGLES[rng.integers(len(configs.SERVE_ANGLES))]
+        nt = configs.SERVE_T[rng.integers(len(configs.SERVE_T))]
+        draws.append((t, vol, m, nt))
+    plans = {}
+    t0 = time.perf_counter()
+    for _, vol, m, nt in draws:
+        key = (vol, m, nt)
+        if key not in plans:
+            c = configs.serve_config(vol[0], vol[1], vol[2], m, nt, 0)
+            plans[key] = Plan.from_config(c, 0.0, precisions=("fp32", "mixed"))
+    torch.cuda.synchronize()
+    t_plans = time.perf_counter() - t0
+    reqs = []
+    for i, (t, vol, m, nt) in enumerate(draws):
+        c = configs.serve_config(vol[0], vol[1], vol[2], m, nt, i)
+        p = plans[(vol, m, nt)]
+        b = device_data(torch, p, configs.make_phantom(c), c.noise, c.noise_seed)
+        geo = dict(nx=c.nx, ny=c.ny, nz=c.nz, n_angles=c.n_angles, n_t=c.n_t, drive_cycles=c.drive_cycles,
+                   psf_width=c.psf_width, harm_lo=c.harm_lo, harm_hi=c.harm_hi, half_band=c.half_band,
+                   op_scale=p.op_scale)
+        reqs.append((Request(i, t, geo, b, c.lam, {}), (vol, m, nt)))
+    return reqs, plans, t_plans
+
+
+def serve_leg(torch, n_requests=None, stream=True):
+    """The C3 stream (mixed path, 2 x 20) with p50/p99 latency, then closed-loop
+    capacity of the FP32 and mixed paths with per-class schedules that reach
+    1e-4 relative error against a converged reference."""
+    import numpy as np
+    from paper_2511_06627_amd import configs
+    from paper_2511_06627_amd.serve import ContinuousBatcher, GpuExecutor, Request, summarize
+    n_requests = n_requests or configs.SERVE_REQUESTS
+    t0 = time.perf_counter()
+    reqs, plans, t_plans = serve_requests(torch, n_requests)
+    log("serve: %d requests, %d plans (%.1fs), data %.1fs"
+        % (len(reqs), len(plans), t_plans, time.perf_counter() - t0))
+    ex = GpuExecutor()
+    for r, key in reqs:        # share the stream's plans (same geometry keys)
+        ex.plans.setdefault(tuple(sorted(r.geometry.items())), plans[key])
+    out = {"requests": len(reqs), "rate_hz": configs.SERVE_RATE_HZ, "classes": len(plans),
+           "plan_build_s": round(t_plans, 2), "budget_bytes": configs.SERVE_BUDGET_BYTES}
+
+    def with_sched(sched, arrival=None):
+        return [Request(r.rid, r.arrival_s if arrival is None else arrival, r.geometry, r.b, r.lam, dict(sched[k]))
+                for r, k in reqs]
+
+    def run(rq, max_active=32):
+        bat = ContinuousBatcher(ex, budget_bytes=configs.SERVE_BUDGET_BYTES, max_active=max_active)
+        res = bat.run(rq)
+        return res, summarize(res)
+
+    # warm the executor's code paths once
+    run(with_sched({k: dict(precision="mixed", refine_sweeps=1, inner_iters=2) for _, k in reqs}, 0.0)[:4])
+
+    # (1) the stream as configured: Poisson arrivals, mixed path, 2 sweeps x 20
+    if stream:
+        cfg_sched = {k: dict(precision="mixed", refine_sweeps=2, inner_iters=20) for _, k in reqs}
+        res, summ = run(with_sched(cfg_sched))
+        out["stream_mixed_2x20"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}
+        log("serve stream (mixed 2x20): %s" % out["stream_mixed_2x20"])
+
+    # (2) per-class schedules at 1e-4 against a converged FP32 reference
+    # (150 CGLS iterations: the FP32 path's own accuracy floor, about 1e-6
+    # of the FP64 minimiser on the realistic scan)
+    ref = {}
+    for r, k in reqs:
+        p = plans[k]
+        bd = torch.from_numpy(r.b).cuda()
+        x, _ = p.solve(bd, r.lam, iters=150, report=False)
+        ref[r.rid] = x
+    first = {}
+    for r, k in reqs:
+        first.setdefault(k, r)
+
+    def err(p, r, **kw):
+        bd = torch.from_numpy(r.b).cuda()
+        x, _ = p.solve(bd, r.lam, report=False, **kw)
+        return float(torch.linalg.vector_norm(x - ref[r.rid]) / torch.linalg.vector_norm(ref[r.rid]))
+
+    sched32, sched16 = {}, {}
+    for k, r in first.items():
+        p = plans[k]
+        lo, hi = 10, 150            # smallest FP32 iteration count at 1e-4 (bisection)
+        while hi - lo > 2:
+            mid = (lo + hi) // 2
+            if err(p, r, iters=mid) <= 1e-4:
+                hi = mid
+            else:
+                lo = mid
+        sched32[k] = dict(precision="fp32", iters=hi)
+        sched16[k] = dict(precision="mixed", refine_sweeps=5, inner_iters=40)
+        for sw, inner in MIXED_CANDIDATES:
+            if err(p, r, precision="mixed", refine_sweeps=sw, inner_iters=inner) <= 1e-4:
+                sched16[k] = dict(precision="mixed", refine_sweeps=sw, inner_iters=inner)
+                break
+    cap = {}
+    for name, sched in (("fp32", sched32), ("mixed", sched16)):
+        run(with_sched(sched, 0.0)[:8])
+        res, summ = run(with_sched(sched, 0.0))
+        errs = [float(np.linalg.norm(o.x - ref[o.rid].cpu().numpy()) / np.linalg.norm(ref[o.rid].cpu().numpy()))
+                for o in res]
+        iters = [sched[k].get("iters", sched[k].get("refine_sweeps", 0) * sched[k].get("inner_iters", 0))
+                 for _, k in reqs]
+        cap[name] = {"solves_per_s": round(summ["solves_per_s"], 2), "makespan_s": round(summ["span_s"], 4),
+                     "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4),
+                     "mean_iters": round(float(np.mean(iters)), 1),
+                     "rel_err_max": float(max(errs)), "rel_err_median": float(np.median(errs))}
+        log("serve closed loop %s: %s" % (name, cap[name]))
+    out["closed_loop_at_1e-4"] = cap
+    out["mixed_over_fp32"] = round(cap["mixed"]["solves_per_s"] / cap["fp32"]["solves_per_s"], 3)
+    out["reference"] = "FP32 CGLS, 150 iterations, per request"
+    return out
 
 
 def main():
@@ -154,6 +336,11 @@ def main():
                     help="size of a plain device copy run once, the reference for HBM byte counters")
     ap.add_argument("--skip-small", action="store_true",
                     help="skip the 32^3 time-to-solve (keeps a profile to the realistic scan)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream and closed-loop capacity")
+    ap.add_argument("--serve-requests", type=int, default=0, help="requests in the serving stream (default 64)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="no oracle leg (for profiling runs): c_A estimated by the plan, data made on the device, "
+                         "no cpu_baseline and no time-to-solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the operator is measured on one MI355X "
@@ -163,8 +350,10 @@ def main():
     from paper_2511_06627_amd import configs
     cfg = configs.REALISTIC_192
     small = configs.PARITY_32
-    cpu = cpu_baseline_leg(cfg, want_minimiser=args.tts, sample_seconds=args.cpu_seconds,
-                           small_cfg=None if args.skip_small else small)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_leg(cfg, want_minimiser=args.tts, sample_seconds=args.cpu_seconds,
+                               small_cfg=None if args.skip_small else small)
 
     import numpy as np
     import torch
@@ -179,9 +368,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    plan = Plan.from_config(cfg, cpu["op_scale"], precisions=("fp32", "mixed"))
-    x = torch.from_numpy(cpu["phantom"]).float().cuda()
-    b = torch.from_numpy(cpu["b"]).cuda()
+    if cpu is not None:
+        plan = Plan.from_config(cfg, cpu["op_scale"], precisions=("fp32", "mixed"))
+        x = torch.from_numpy(cpu["phantom"]).float().cuda()
+        b = torch.from_numpy(cpu["b"]).cuda()
+    else:
+        plan = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"))
+        phantom = configs.make_phantom(cfg)
+        x = torch.from_numpy(phantom).float().cuda()
+        b = torch.from_numpy(device_data(torch, plan, phantom, cfg.noise, cfg.noise_seed)).cuda()
     yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
     xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
     ws = plan.workspace("op")
@@ -209,8 +404,8 @@ def main():
     dom = max(("signal_fwd", "signal_adj"), key=lambda k: kt[k])
     achieved = fl / (kt[dom] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "flops_per_launch": fl}
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dom), "flops_per_launch": fl}
     kernels = {}
     for k in ("signal_fwd", "signal_adj"):
         a = fl / (kt[k] * 1e-3) / 1e12
@@ -273,12 +468,18 @@ def main():
 
     # time-to-solve at 1e-4 relative error against the FP64 minimiser
     tts = {}
-    if not args.skip_small:
+    if cpu is not None and not args.skip_small:
         sm = cpu["small"]
-        psmall = Plan.from_config(small, sm["op_scale"])
-        tts["parity_32cube"] = time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, 400, 5)
-    if args.tts:
-        tts[cfg.name] = time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, 600, 25)
+        psmall = Plan.from_config(small, sm["op_scale"], precisions=("fp32", "mixed"))
+        tts["parity_32cube"] = {p: time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, p)
+                                for p in ("fp32", "mixed")}
+    if cpu is not None and args.tts:
+        tts[cfg.name] = {p: time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, p)
+                         for p in ("fp32", "mixed")}
+
+    serve = None
+    if not args.no_serve:
+        serve = serve_leg(torch, args.serve_requests or None)
 
     value = args.steps / dt
     line = {
@@ -298,13 +499,14 @@ def main():
                                "harmonics 1-31 +/-3 bins, 40 blobs + ellipsoid phantom, 0.5% noise",
                    "step": "A then A^T, FP32 path", "global_batch": 1, "parallelism": "single GPU"},
         "roofline": roofline,
-        "cpu_baseline": cpu["cpu_baseline"],
+        "cpu_baseline": cpu["cpu_baseline"] if cpu is not None else None,
         "kernels": kernels,
         "cgls": {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
                  "status": rep.status},
         "time_to_solve": tts,
         "mixed": mixed,
-        "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1),
+        "serving": serve,
+        "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1) if cpu is not None else None,
     }
     print(json.dumps(line), flush=True)
 

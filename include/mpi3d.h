@@ -99,7 +99,12 @@ typedef struct {
     int32_t half_band;           /* D >= 0: bins omega_k - D .. omega_k + D */
     const float *rx_filter;      /* host, 2*n_bins floats (re, im) of D_Gamma on
                                     the kept bins; NULL = 1 */
-    double op_scale;             /* c_A, the global signal scale (> 0) */
+    double op_scale;             /* c_A, the global signal scale (> 0); 0 = estimate it
+                                    at plan creation so that ||A||_2 = 1 (Sec. 3.3): power
+                                    iteration on A^T A with the FP32 operator on the device,
+                                    from the constant vector, until the estimate of ||A||^2
+                                    moves by at most 1e-6 (relative) over 10 iterations,
+                                    at most 1000 iterations */
     int32_t precisions;          /* bit mask of (1 << MPI3D_FP32) | (1 << MPI3D_MIXED):
                                     which operator variants get tables; 0 = FP32 only */
 } mpi3d_geometry;
@@ -118,6 +123,8 @@ typedef struct {
     int64_t table_bytes;        /* device memory held by the plan itself */
     int64_t history_doubles;    /* per iteration doubles written to a solve history */
     int32_t n_r;                /* ray samples per projection ray */
+    int32_t norm_iters;         /* power iterations that estimated op_scale; 0 = given */
+    double op_scale;            /* c_A in use */
 } mpi3d_plan_info;
 
 /* Validates the geometry, builds the FP64 host tables (angles, trajectory,
@@ -163,10 +170,15 @@ int mpi3d_signal_adj(const mpi3d_plan *plan, int32_t precision, const float *b_d
  *   clamp_every > 0   after every clamp_every iterations (and after the last)
  *                     x <- max(x, 0) and CGLS restarts from it (the paper's
  *                     nonnegativity, Sec. 3.3 after eq. iters).
- *   precision MIXED   iterative refinement: refine_sweeps sweeps; each starts
- *                     from the current x with the residual b - A x and the
- *                     gradient formed by the FP32 operator, then runs
- *                     inner_iters CGLS iterations with the mixed operator.
+ *   precision MIXED   iterative refinement: refine_sweeps sweeps.  A sweep
+ *                     forms r0 = b - A x and g0 = A^T r0 - lambda x with the
+ *                     FP32 operator, runs inner_iters CGLS iterations with the
+ *                     mixed operator A~ on the correction d of
+ *                       min |A~ d - r0|^2 + lambda |x + d|^2   (d = 0 at the start),
+ *                     whose gradient is g0 - A~^T A~ d - lambda d (A~ only ever
+ *                     acts on d and its residual, never on r0, so its error
+ *                     shrinks with the correction), then sets x += d (and
+ *                     clamps at 0 when clamp_every > 0).
  */
 typedef struct {
     double lambda;          /* Tikhonov weight (>= 0) */

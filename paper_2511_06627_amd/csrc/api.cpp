@@ -5,8 +5,10 @@
 // CGLS on eq. nummodel with T = I; see include/mpi3d.h for the recurrences.
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -205,6 +207,9 @@ void Cgls::init(const mpi3d_plan *plan, const float *b_, float *x_, void *ws, do
     parts_q = (double *)(base + pl->sw_parts);
     parts_p = parts_q + kMaxNormParts;
     parts_s = parts_p + kMaxNormParts;
+    const bool mixed = (pl->precisions & (1 << MPI3D_MIXED)) != 0;
+    d = mixed ? (float *)(base + pl->sw_d) : nullptr;
+    g0 = mixed ? (float *)(base + pl->sw_g) : nullptr;
 }
 
 int Cgls::restart_a(bool x_zero, hipStream_t st)
@@ -225,11 +230,23 @@ int Cgls::restart_b(bool x_zero, hipStream_t st)
 
 int Cgls::restart_c(hipStream_t st)
 {
+    float *grad = corr ? g0 : s;
     TRYRC(reduce_adjoint(pl, MPI3D_FP32, w, serve, w.rt, pl->nup, st));
-    TRY(launch_backproject(pl, w.rt, s, x, lambda, parts_s, &ns, st));
+    TRY(launch_backproject(pl, w.rt, grad, x, lambda, parts_s, &ns, st));
     TRY(launch_beta(scal, parts_s, ns, 1, started ? 0 : 1, hist, step, st));
-    TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 1, st));
+    TRY(launch_update_p2(p, grad, pb, pl->nvox, scal, parts_p, &np, 1, st));
+    if (corr) {
+        TRY(launch_fill(d, pl->nvox, 0.f, st));
+        TRY(launch_fill(r, 2 * pl->L * pl->nb, 0.f, st));
+    }
     started = true;
+    return MPI3D_OK;
+}
+
+int Cgls::finish_sweep(bool clamp, hipStream_t st)
+{
+    if (corr) TRY(launch_add_to(x, d, pl->nvox, clamp ? 1 : 0, st));
+    else if (clamp) TRY(launch_clamp(x, pl->nvox, st));
     return MPI3D_OK;
 }
 
@@ -242,14 +259,14 @@ int Cgls::iter_b(int prec, hipStream_t st)
 {
     TRYRC(reduce_forward(pl, prec, w, serve, q, nullptr, parts_q, &nq, st));
     TRY(launch_alpha(scal, parts_q, nq, parts_p, np, lambda, hist, step, st));
-    TRY(launch_update_xr2(x, p, r, q, pl->nvox, 2 * pl->L * pl->nb, scal, st));
+    TRY(launch_update_xr2(corr ? d : x, p, r, q, pl->nvox, 2 * pl->L * pl->nb, scal, st));
     return MPI3D_OK;
 }
 
 int Cgls::iter_c(int prec, hipStream_t st)
 {
     TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
-    TRY(launch_backproject(pl, w.rt, s, x, lambda, parts_s, &ns, st));
+    TRY(launch_backproject(pl, w.rt, s, corr ? d : x, lambda, parts_s, &ns, st, corr ? g0 : nullptr));
     TRY(launch_beta(scal, parts_s, ns, 0, 0, hist, step, st));
     TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 0, st));
     ++step;
@@ -278,6 +295,79 @@ int Cgls::iterate(int prec, hipStream_t st)
     LineJob ja{pl, r, pl->nb2, &w};
     TRYRC(sig_adjoint_jobs(prec, &ja, 1, serve, st));
     return iter_c(prec, st);
+}
+
+// ||A||_2 of the operator without its global scale, by power iteration on
+// A^T A with the FP32 operator (the scale c_A that makes ||A||_2 = 1,
+// Sec. 3.3).  Start: the constant unit vector.  Each iteration records
+// |A^T A v| (v of unit norm) in float64 on the device; every 10 iterations
+// the host reads the records and stops once the estimate moved by at most
+// 10 * rtol (relative) over the last 10.  The estimate of lambda_max is
+// nondecreasing, so it approaches ||A||^2 from below.
+int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out)
+{
+    const double keep = pl->op_scale;
+    pl->op_scale = 1.0;
+    size_t o = 0;
+    auto put = [&](size_t bytes) { o = (o + 255) & ~(size_t)255; size_t r = o; o += bytes; return r; };
+    const size_t o_ws = put(pl->op_ws_bytes);
+    const size_t o_v = put(sizeof(float) * pl->nvox);
+    const size_t o_z = put(sizeof(float) * pl->nvox);
+    const size_t o_y = put(sizeof(float) * 2 * pl->L * pl->nb);
+    const size_t o_n = put(sizeof(double) * max_iters);
+    const size_t o_p = put(sizeof(double) * kMaxNormParts);
+    char *buf = nullptr;
+    if (hipMalloc(&buf, o) != hipSuccess) {
+        pl->op_scale = keep;
+        return MPI3D_ENOMEM;
+    }
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(buf);
+        pl->op_scale = keep;
+        return MPI3D_EDEVICE;
+    }
+    OpWs w = carve_op(pl, buf + o_ws);
+    float *v = (float *)(buf + o_v), *z = (float *)(buf + o_z), *y = (float *)(buf + o_y);
+    double *norms = (double *)(buf + o_n), *parts = (double *)(buf + o_p);
+    std::vector<double> host(max_iters);
+    int rc = MPI3D_OK, done = 0;
+    double est = 0.0;
+    if (launch_fill(v, pl->nvox, (float)(1.0 / std::sqrt((double)pl->nvox)), st) != hipSuccess) rc = MPI3D_EDEVICE;
+    for (int k = 0; rc == MPI3D_OK && k < max_iters; ++k) {
+        rc = apply_forward(pl, MPI3D_FP32, v, y, w, st);
+        LineJob j{pl, y, pl->nb2, &w};
+        if (rc == MPI3D_OK) rc = sig_adjoint_jobs(MPI3D_FP32, &j, 1, false, st);
+        if (rc == MPI3D_OK) rc = reduce_adjoint(pl, MPI3D_FP32, w, false, w.rt, pl->nup, st);
+        int np = 0;
+        if (rc == MPI3D_OK && (launch_backproject(pl, w.rt, z, nullptr, 0.0, parts, &np, st) != hipSuccess ||
+                               launch_norm_record(parts, np, norms, k, st) != hipSuccess ||
+                               launch_scale_by(v, z, pl->nvox, norms, k, st) != hipSuccess))
+            rc = MPI3D_EDEVICE;
+        if (rc != MPI3D_OK) break;
+        if ((k + 1) % 10 == 0 || k + 1 == max_iters) {
+            if (hipMemcpyAsync(host.data(), norms, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                rc = MPI3D_EDEVICE;
+                break;
+            }
+            est = host[k];
+            done = k + 1;
+            if (!std::isfinite(est) || !(est > 0.0)) {
+                rc = MPI3D_ENONFINITE;
+                break;
+            }
+            if (k + 1 >= 20 && std::fabs(est - host[k - 10]) <= 10.0 * rtol * est) break;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    (void)hipFree(buf);
+    pl->op_scale = keep;
+    if (rc != MPI3D_OK) return rc;
+    *norm_out = std::sqrt(est);
+    *iters_out = done;
+    return MPI3D_OK;
 }
 
 int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o)
@@ -372,7 +462,10 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
     hipStream_t st = (hipStream_t)stream;
     Cgls cg;
     cg.init(pl, b, x, ws, o->lambda, hist);
-    if (o->precision == MPI3D_MIXED) cg.pb = cg.w.xb;
+    if (o->precision == MPI3D_MIXED) {
+        cg.pb = cg.w.xb;
+        cg.corr = true;
+    }
     bool xz = o->x0_is_zero != 0;
     if (xz) TRY(launch_fill(x, pl->nvox, 0.f, st));
     if (o->precision == MPI3D_FP32) {
@@ -389,7 +482,7 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
         for (int sw = 0; sw < o->refine_sweeps; ++sw) {
             TRYRC(cg.restart(xz && sw == 0, st));
             for (int it = 0; it < o->inner_iters; ++it) TRYRC(cg.iterate(MPI3D_MIXED, st));
-            if (o->clamp_every > 0) TRY(launch_clamp(x, pl->nvox, st));
+            TRYRC(cg.finish_sweep(o->clamp_every > 0, st));
         }
     }
     if (report) {

@@ -61,7 +61,8 @@ struct ProjArgs {
     float *rt;                  // projections [M][nz][nup]
     const float *rt_in;         // adjoint input projections [M][nz][nup]
     float *xo;                  // adjoint output volume
-    const float *x_sub;         // adjoint epilogue: out = acc - lambda * x_sub (null = none)
+    const float *x_sub;         // adjoint epilogue: out = acc + x_add - lambda * x_sub (null = none)
+    const float *x_add;         // (null = none)
     double *norm_parts;         // adjoint epilogue: per-block sum of out^2 (null = none)
     double lambda;
     const float2 *cs;           // [M] (cos, sin)
@@ -82,6 +83,7 @@ struct mpi3d_plan {
     int nx, ny, nz, M, nu, nt, nr, nb;
     int harm_lo, harm_hi, half_band;
     double P, a, w, op_scale;
+    int norm_iters;               // power iterations that set op_scale (0: given)
     int precisions;
     // padded sizes
     int nup;        // n_u padded to 64
@@ -110,7 +112,7 @@ struct mpi3d_plan {
     // operator workspace layout (bytes from ws base)
     size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, op_ws_bytes;
     // solver workspace layout
-    size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, solve_ws_bytes;
+    size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, solve_ws_bytes;
 };
 
 namespace mpi3d {
@@ -119,7 +121,8 @@ namespace mpi3d {
 hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt,
                           hipStream_t st);
 hipError_t launch_backproject(const mpi3d_plan *pl, const float *rt, float *xo, const float *x_sub,
-                              double lambda, double *norm_parts, int *nparts, hipStream_t st);
+                              double lambda, double *norm_parts, int *nparts, hipStream_t st,
+                              const float *x_add = nullptr);
 hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
 int sig_fwd_supported(int nup, int gct, int precision);
@@ -153,12 +156,15 @@ hipError_t launch_update_p2(float *p, const float *s, uint16_t *pb, long n, cons
 hipError_t launch_clamp(float *x, long n, hipStream_t st);
 hipError_t launch_fill(float *x, long n, float v, hipStream_t st);
 hipError_t launch_copy(float *dst, const float *src, long n, hipStream_t st);
+hipError_t launch_norm_record(const double *parts, int n, double *norms, int k, hipStream_t st);
+hipError_t launch_scale_by(float *v, const float *z, long n, const double *norms, int k, hipStream_t st);
+hipError_t launch_add_to(float *x, const float *d, long n, int clamp, hipStream_t st);
 
 // Strided projection launchers (public stage entry points use stride n_u).
 hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st);
 hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,
                                       const float *x_sub, double lambda, double *norm_parts, int *nparts,
-                                      hipStream_t st);
+                                      hipStream_t st, const float *x_add = nullptr);
 
 }  // namespace mpi3d
 
@@ -199,6 +205,12 @@ struct Cgls {
     double *scal = nullptr, *parts_q = nullptr, *parts_p = nullptr, *parts_s = nullptr;
     double *hist = nullptr;
     uint16_t *pb = nullptr;     // bf16 shadow of p for the mixed operator
+    // correction form (mixed refinement): within a sweep x stays fixed and
+    // CGLS runs on the correction d, min |A~ d - r0|^2 + lambda |x + d|^2,
+    // with r holding -A~ d and the gradient s = g0 + A~^T r - lambda d, where
+    // g0 = A^T r0 - lambda x comes from the FP32 operator at the sweep start.
+    bool corr = false;
+    float *d = nullptr, *g0 = nullptr;
     OpWs w{};
     double lambda = 0.0;
     int nq = 0, np = 0, ns = 0;
@@ -211,7 +223,8 @@ struct Cgls {
     // gamma = |s|^2, p = s.  Phases around the two signal launches:
     int restart_a(bool x_zero, hipStream_t st);       // projection of x (or r = b)
     int restart_b(bool x_zero, hipStream_t st);       // r = b - (A x)
-    int restart_c(hipStream_t st);                    // s, gamma, p
+    int restart_c(hipStream_t st);                    // s (or g0), gamma, p; corr: d = 0, r = 0
+    int finish_sweep(bool clamp, hipStream_t st);     // corr: x += d (then clamp); else clamp
     // one iteration: q = A p; alpha; x, r; s = A^T r - lambda x; beta; p
     int iter_a(int prec, hipStream_t st);             // projection of p
     int iter_b(int prec, hipStream_t st);             // q, alpha, x += alpha p, r -= alpha q
@@ -221,5 +234,6 @@ struct Cgls {
     int iterate(int prec, hipStream_t st);
 };
 int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o);
+int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out);
 
 }  // namespace mpi3d

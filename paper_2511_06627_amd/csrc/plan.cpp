@@ -126,7 +126,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (g->nx > 4096 || g->ny > 4096 || g->nz > 65535 || g->n_angles > 4096 || g->n_t > (1 << 22)) return MPI3D_EINVAL;
     int nu = g->n_u ? g->n_u : g->nx;
     if (nu < 2 || nu > 256) return MPI3D_ENOTSUP;
-    if (!(g->drive_cycles > 0) || !(g->psf_width > 0) || !(g->op_scale > 0)) return MPI3D_EINVAL;
+    if (!(g->drive_cycles > 0) || !(g->psf_width > 0) || !(g->op_scale >= 0)) return MPI3D_EINVAL;
     if (!(g->drive_amp >= 0)) return MPI3D_EINVAL;
     if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
     int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
@@ -480,6 +480,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->sw_p = put(sizeof(float) * pl->nvox);
         pl->sw_scal = put(sizeof(double) * 64);
         pl->sw_parts = put(sizeof(double) * 3 * kMaxNormParts);
+        pl->sw_d = put(mixed ? sizeof(float) * pl->nvox : 0);   // refinement correction
+        pl->sw_g = put(mixed ? sizeof(float) * pl->nvox : 0);   // FP32 gradient at the sweep start
         pl->solve_ws_bytes = align256(o);
     }
     {
@@ -496,6 +498,20 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         mix(dbl, sizeof(dbl));
         if (g->rx_filter) mix(g->rx_filter, sizeof(float) * 2 * pl->nb);
         pl->line_key = h;
+    }
+    pl->norm_iters = 0;
+    if (g->op_scale == 0.0) {
+        // c_A = 1 / ||A||_2, estimated on the device
+        double nrm = 0.0;
+        int its = 0;
+        const int rc = estimate_op_norm(pl, 1e-7, 1000, &nrm, &its);
+        if (rc != MPI3D_OK) {
+            (void)hipFree(pl->tables);
+            delete pl;
+            return rc;
+        }
+        pl->op_scale = 1.0 / nrm;
+        pl->norm_iters = its;
     }
     *out = pl;
     return MPI3D_OK;
@@ -525,5 +541,7 @@ extern "C" int mpi3d_plan_query(const mpi3d_plan *pl, mpi3d_plan_info *info)
     info->table_bytes = (int64_t)pl->table_bytes;
     info->history_doubles = 4;
     info->n_r = pl->nr;
+    info->norm_iters = pl->norm_iters;
+    info->op_scale = pl->op_scale;
     return MPI3D_OK;
 }

@@ -20,7 +20,7 @@
 // so one block covers a 16x16 voxel tile for a group of kz slices and reuses
 // the weights kz times; the projections it needs for one angle (kz lines x
 // <= 32 rays) are staged in LDS.  The epilogue optionally forms
-// out = acc - lambda * x_sub and a float64 partial sum of out^2 (CGLS).
+// out = acc + x_add - lambda * x_sub and a float64 partial sum of out^2 (CGLS).
 
 #include <type_traits>
 
@@ -279,7 +279,12 @@ __global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride
             if (kk < kn) {
                 const size_t idx = ((size_t)(k0 + kk) * a.ny + j) * a.nx + i;
                 float v = acc[kk];
-                if (a.x_sub) v = (float)((double)v - a.lambda * (double)a.x_sub[idx]);
+                if (a.x_sub || a.x_add) {
+                    double t = (double)v;
+                    if (a.x_add) t += (double)a.x_add[idx];
+                    if (a.x_sub) t -= a.lambda * (double)a.x_sub[idx];
+                    v = (float)t;
+                }
                 a.xo[idx] = v;
                 sq += (double)v * (double)v;
             }
@@ -351,12 +356,13 @@ hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *
 
 hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,
                                       const float *x_sub, double lambda, double *norm_parts, int *nparts,
-                                      hipStream_t st)
+                                      hipStream_t st, const float *x_add)
 {
     ProjArgs a = base_args(pl);
     a.rt_in = rt;
     a.xo = xo;
     a.x_sub = x_sub;
+    a.x_add = x_add;
     a.lambda = lambda;
     a.norm_parts = norm_parts;
     const int blocks = a.tiles_x * a.tiles_y * a.n_zgroups;
@@ -367,9 +373,9 @@ hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int
 }
 
 hipError_t launch_backproject(const mpi3d_plan *pl, const float *rt, float *xo, const float *x_sub, double lambda,
-                              double *norm_parts, int *nparts, hipStream_t st)
+                              double *norm_parts, int *nparts, hipStream_t st, const float *x_add)
 {
-    return launch_backproject_strided(pl, rt, pl->nup, xo, x_sub, lambda, norm_parts, nparts, st);
+    return launch_backproject_strided(pl, rt, pl->nup, xo, x_sub, lambda, norm_parts, nparts, st, x_add);
 }
 
 }  // namespace mpi3d

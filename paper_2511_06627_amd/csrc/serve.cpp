@@ -73,7 +73,7 @@ struct mpi3d_state {
         } else {
             ++inner;
             if (inner == o.inner_iters) {
-                if (o.clamp_every > 0) TRY(launch_clamp(cg.x, pl->nvox, st));
+                TRYRC(cg.finish_sweep(o.clamp_every > 0, st));
                 inner = 0;
                 ++sweep;
                 if (sweep == o.refine_sweeps) done = true;
@@ -106,7 +106,10 @@ extern "C" int mpi3d_state_create(const mpi3d_plan *pl, const float *b, float *x
     s->o = *o;
     s->cg.init(pl, b, x, ws, o->lambda, nullptr);
     s->cg.serve = true;
-    if (o->precision == MPI3D_MIXED) s->cg.pb = s->cg.w.xb;
+    if (o->precision == MPI3D_MIXED) {
+        s->cg.pb = s->cg.w.xb;
+        s->cg.corr = true;
+    }
     *out = s;
     return MPI3D_OK;
 }

@@ -229,6 +229,16 @@ __global__ __launch_bounds__(kThreads) void clamp_kernel(float *x, long n)
         x[idx] = fmaxf(x[idx], 0.f);
 }
 
+// x = x + d (refinement sweep end), optionally clamped at 0
+__global__ __launch_bounds__(kThreads) void add_to_kernel(float *__restrict__ x, const float *__restrict__ d, long n,
+                                                           int clamp)
+{
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        const float v = x[idx] + d[idx];
+        x[idx] = clamp ? fmaxf(v, 0.f) : v;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void fill_kernel(float *x, long n, float v)
 {
     for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads)
@@ -239,6 +249,23 @@ __global__ __launch_bounds__(kThreads) void copy_kernel(float *dst, const float 
 {
     for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads)
         dst[idx] = src[idx];
+}
+
+// Power iteration on A^T A: norms[k] = |z| from the partials of |z|^2.
+__global__ __launch_bounds__(kThreads) void norm_record_kernel(const double *parts, int n, double *norms, int k)
+{
+    __shared__ double red[kThreads / 64];
+    const double t = sum_parts(parts, n, red);
+    if (threadIdx.x == 0) norms[k] = sqrt(t);
+}
+
+// v = z / norms[k]
+__global__ __launch_bounds__(kThreads) void scale_by_kernel(float *__restrict__ v, const float *__restrict__ z, long n,
+                                                             const double *norms, int k)
+{
+    const float inv = (float)(1.0 / norms[k]);
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads)
+        v[idx] = z[idx] * inv;
 }
 
 __global__ void scal_init_kernel(double *scal)
@@ -354,6 +381,24 @@ hipError_t launch_fill(float *x, long n, float v, hipStream_t st)
 hipError_t launch_copy(float *dst, const float *src, long n, hipStream_t st)
 {
     hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_to(float *x, const float *d, long n, int clamp, hipStream_t st)
+{
+    hipLaunchKernelGGL(add_to_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, x, d, n, clamp);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_record(const double *parts, int n, double *norms, int k, hipStream_t st)
+{
+    hipLaunchKernelGGL(norm_record_kernel, dim3(1), dim3(kThreads), 0, st, parts, n, norms, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_by(float *v, const float *z, long n, const double *norms, int k, hipStream_t st)
+{
+    hipLaunchKernelGGL(scale_by_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, v, z, n, norms, k);
     return hipGetLastError();
 }
 

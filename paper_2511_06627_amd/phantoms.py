@@ -7,7 +7,8 @@ Volumes are float64 arrays of shape (Nz, Ny, Nx), x fastest.  Index
 coordinates: voxel (i, j, k) sits at (i, j, k).  All draws come from one
 numpy PCG64 stream per phantom, in a fixed order, so a seed fixes the volume.
 
-* Gaussian blobs: a * exp(-|r - c|^2 / (2 sigma^2)), point-sampled; centre
+* Gaussian blobs: a * exp(-|r - c|^2 / (2 sigma^2)), point-sampled (as a
+  product of its x, y and z factors); centre
   uniform in [lo*N, hi*N] per axis; sigma uniform; amplitude log-uniform.
 * Ellipsoid: hard-edged indicator of amplitude ``amp`` with semi-axes
   U[0.12, 0.25] * (Nx, Ny, Nz) and centre uniform over the inner half.
@@ -24,22 +25,25 @@ def _grid(shape):
                        np.arange(nx, dtype=np.float64), indexing="ij")
 
 
-def _blob(zz, yy, xx, c, sigma, amp):
-    d2 = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2
-    return amp * np.exp(-d2 / (2.0 * sigma * sigma))
+def _blob(shape, c, sigma, amp):
+    """Point-sampled isotropic Gaussian, evaluated as the outer product of its
+    three axis factors (the same function, a fraction of the work)."""
+    nz, ny, nx = shape
+    f = [np.exp(-(np.arange(n, dtype=np.float64) - ci) ** 2 / (2.0 * sigma * sigma)) for n, ci in
+         ((nx, c[0]), (ny, c[1]), (nz, c[2]))]
+    return amp * (f[2][:, None, None] * (f[1][:, None] * f[0][None, :])[None, :, :])
 
 
 def gaussian_blobs(shape, n_blobs, sigma_range, amp_log10_range, seed, centre_frac=(0.1, 0.9)):
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)
-    zz, yy, xx = _grid(shape)
     vol = np.zeros(shape)
     dims = np.array([nx, ny, nz], dtype=np.float64)
     for _ in range(n_blobs):
         c = rng.uniform(centre_frac[0], centre_frac[1], size=3) * dims
         sigma = rng.uniform(*sigma_range)
         amp = 10.0 ** rng.uniform(*amp_log10_range)
-        vol += _blob(zz, yy, xx, c, sigma, amp)
+        vol += _blob(shape, c, sigma, amp)
     return vol
 
 
@@ -64,7 +68,6 @@ def organ_with_satellites(shape, n_blobs, sigma_range, amp_log10_range, gap_rang
     """
     vol, centre, axes = ellipsoid(shape, seed)
     rng = np.random.default_rng(seed + 7919)
-    zz, yy, xx = _grid(shape)
     blobs = []
     for _ in range(n_blobs):
         d = rng.standard_normal(3)
@@ -77,7 +80,7 @@ def organ_with_satellites(shape, n_blobs, sigma_range, amp_log10_range, gap_rang
         sigma = rng.uniform(*sigma_range)
         amp = 10.0 ** rng.uniform(*amp_log10_range)
         c = surf + gap * normal
-        vol += _blob(zz, yy, xx, c, sigma, amp)
+        vol += _blob(shape, c, sigma, amp)
         blobs.append((c, sigma, amp))
     return vol, blobs
 

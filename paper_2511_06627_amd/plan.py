@@ -60,6 +60,8 @@ class Plan:
         info = _lib.PlanInfo()
         check("mpi3d_plan_query", lib.mpi3d_plan_query(self._h, ctypes.byref(info)))
         self.info = info
+        self.op_scale = float(info.op_scale)      # c_A in use (estimated when 0 was passed)
+        self.norm_iters = int(info.norm_iters)
         self.shape = (nz, ny, nx)
         self.n_u = n_u or nx
         self.data_shape = (n_angles, nz, int(info.n_bins))

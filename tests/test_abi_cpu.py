@@ -29,14 +29,36 @@ def test_library_exports_every_declared_symbol():
         assert name in _lib._SIGS, name
 
 
-def test_struct_layouts_match_header_sizes():
-    """ctypes mirrors of the ABI structs have the C sizes (alignment included)."""
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the ABI structs have the C compiler's size and field
+    offsets (a C program built from the header prints them)."""
+    import shutil
+    import subprocess
+    import tempfile
     from paper_2511_06627_amd import _lib
-    # computed from the header's field list with natural alignment on x86-64
-    assert ctypes.sizeof(_lib.Geometry) == 96
-    assert ctypes.sizeof(_lib.PlanInfo) == 80
-    assert ctypes.sizeof(_lib.SolveOpts) == 32
-    assert ctypes.sizeof(_lib.SolveReport) == 24
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mpi3d_geometry": _lib.Geometry, "mpi3d_plan_info": _lib.PlanInfo,
+               "mpi3d_solve_opts": _lib.SolveOpts, "mpi3d_solve_report": _lib.SolveReport}
+    cname_of = {"lam": "lambda"}      # a Python keyword in C
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpi3d.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, cname_of.get(f, f)))
+    lines += ["return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_strerror_is_host_only():

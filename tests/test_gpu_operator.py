@@ -180,3 +180,18 @@ def test_realistic_adjoint_sampled(realistic, torch_mod, slices):
         err = rel_l2(got[k], want)
         _log("realistic adjoint slice %d rel err %.3e" % (k, err))
         assert err <= TOL32
+
+
+@pytest.mark.parametrize("name", ["parity_32", "ragged"])
+def test_device_normalisation_matches_oracle(name, torch_mod):
+    """op_scale = 0 asks the plan to find c_A (||A||_2 = 1) by power iteration
+    on the device; it agrees with the oracle's FP64 power iteration."""
+    from paper_2511_06627_amd.plan import Plan
+    nx, ny, nz, M, T, P, w, klo, khi, D = CASES[name]
+    g = oop.normalised(oracle_geometry(nx, ny, nz, M, T, P, w, klo, khi, D), iters_min=30, rtol=1e-12)
+    plan = Plan(nx, ny, nz, M, T, P, w, klo, khi, D, 0.0)
+    rel = abs(plan.op_scale - g.op_scale) / g.op_scale
+    _log("%s device c_A %.9e (%d iterations), oracle %.9e, rel %.2e"
+         % (name, plan.op_scale, plan.norm_iters, g.op_scale, rel))
+    assert plan.norm_iters > 0
+    assert rel <= 1e-5

@@ -91,7 +91,7 @@ def test_served_solve_matches_oracle(torch_mod, plans, reqs):
 
 
 def test_continuous_batching_loop(torch_mod, reqs):
-    """End to end: Poisson arrivals, admission under a small forced budget,
+    """End to end: a burst of requests, admission under a small forced budget,
     results equal to the same requests solved alone."""
     from paper_2511_06627_amd.serve import ContinuousBatcher, GpuExecutor, Request, summarize
     rng = np.random.default_rng(3000)
@@ -100,7 +100,7 @@ def test_continuous_batching_loop(torch_mod, reqs):
     rq = []
     t = 0.0
     for i, n in enumerate(names):
-        t += rng.exponential(0.01)
+        t += rng.exponential(1e-4)          # a burst: all arrive before the first can finish
         g, geo, b = reqs[n]
         rq.append(Request(i, t, geo, b, 1e-3, sched))
     ex = GpuExecutor()
@@ -110,9 +110,9 @@ def test_continuous_batching_loop(torch_mod, reqs):
     out = bat.run(rq)
     s = summarize(out)
     _log("serve loop: %s" % s)
-    # resident footprint never above the budget, and the budget did bind
+    # resident footprint never above the budget, and the budget did bind:
+    # some request was admitted only after another retired
     used = peak = 0
-    waited = False
     for _, ev, rid in bat.log:
         if ev == "admit":
             used += fps[rid]
@@ -120,7 +120,8 @@ def test_continuous_batching_loop(torch_mod, reqs):
             used -= fps[rid]
         peak = max(peak, used)
     assert peak <= budget
-    assert any(o.admit_s > o.arrival_s + 1e-3 for o in out) or peak > budget / 2
+    events = [ev for _, ev, _ in bat.log]
+    assert "admit" in events[events.index("retire"):]
     from paper_2511_06627_amd.plan import Plan
     for r, o in zip(rq, out):
         p = Plan(precisions=("fp32", "mixed"), **r.geometry)

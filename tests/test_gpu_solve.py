@@ -164,3 +164,25 @@ def test_realistic_cgls_50(torch_mod):
     tol = max(TOL32, 4 * env["%s/cgls%d" % (cfg.name, cfg.iters)])
     _log("realistic cgls 50 rel err %.3e (tol %.3e)" % (err, tol))
     assert err <= tol
+
+
+def test_serving_reference_is_converged(torch_mod):
+    """150 FP32 CGLS iterations -- the reference the serving benchmark measures
+    its schedules against -- reach the FP64 minimiser to 1e-5 on a serving
+    class (64^3, 12 angles, T = 4096, harmonics 1-31 +/- 3, c_A found by the
+    plan itself)."""
+    from paper_2511_06627_amd.plan import Plan
+    cfg = configs.serve_config(64, 64, 64, 12, 4096, 5)
+    _log("case serve_64cube_m12_t4096 reference")
+    g = config_geometry(cfg)
+    b, _ = oop.make_data(g, configs.make_phantom(cfg), cfg.noise, cfg.noise_seed)
+    b32 = b.astype(np.complex64)
+    xs, _ = solvers.reference_minimiser(oop.Operator(g, precomposed=True), b32.astype(np.complex128), cfg.lam,
+                                        tol=1e-12)
+    plan = Plan.from_config(cfg, 0.0)
+    assert abs(plan.op_scale - g.op_scale) <= 1e-6 * g.op_scale
+    plan = Plan.from_config(cfg, g.op_scale)
+    x, rep = plan.solve(torch_mod.from_numpy(b32).cuda(), cfg.lam, iters=150)
+    err = rel_l2(x.cpu().numpy(), xs)
+    _log("serve class 64^3 m12: fp32 150 its vs x* %.3e" % err)
+    assert rep.status == 0 and err <= TOL32
