@@ -205,8 +205,8 @@ void Cgls::init(const mpi3d_plan *plan, const float *b_, float *x_, void *ws, do
     p = (float *)(base + pl->sw_p);
     scal = (double *)(base + pl->sw_scal);
     parts_q = (double *)(base + pl->sw_parts);
-    parts_p = parts_q + kMaxNormParts;
-    parts_s = parts_p + kMaxNormParts;
+    parts_p = parts_q + pl->max_parts;
+    parts_s = parts_p + pl->max_parts;
     const bool mixed = (pl->precisions & (1 << MPI3D_MIXED)) != 0;
     d = mixed ? (float *)(base + pl->sw_d) : nullptr;
     g0 = mixed ? (float *)(base + pl->sw_g) : nullptr;
@@ -315,7 +315,7 @@ int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_ou
     const size_t o_z = put(sizeof(float) * pl->nvox);
     const size_t o_y = put(sizeof(float) * 2 * pl->L * pl->nb);
     const size_t o_n = put(sizeof(double) * max_iters);
-    const size_t o_p = put(sizeof(double) * kMaxNormParts);
+    const size_t o_p = put(sizeof(double) * pl->max_parts);
     char *buf = nullptr;
     if (hipMalloc(&buf, o) != hipSuccess) {
         pl->op_scale = keep;

@@ -69,8 +69,8 @@ struct ProjArgs {
     const float *ax;            // [M][nu] forward x-coordinate bases
     const float *ay;            // [M][nu] forward y-coordinate bases
     int nx, ny, nz, M, nu, nup, nr;
-    int angles_per_block, n_angle_groups, band_rows, n_bands;
-    int kz, n_zgroups, tiles_x, tiles_y;
+    int band_rows, n_bands;
+    int kz, n_zgroups, tiles_x, tiles_y, adj_chunk;
     float half_nr, half_nu, cx, cy;
 };
 
@@ -98,7 +98,8 @@ struct mpi3d_plan {
     int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
     uint64_t line_key;             // equal keys <=> identical line tables
     // projection configuration
-    int angles_per_block, n_angle_groups, band_rows, n_bands, kz;
+    int fwd_blocks, band_rows, n_bands, kz, adj_chunk;
+    int max_parts;                 // float64 norm partials a launch may write (>= kMaxNormParts)
     // device tables (one allocation)
     void *tables;
     size_t table_bytes;

@@ -205,24 +205,33 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         int bases = pl->ny + 1;                     // base rows -1 .. ny-1
         pl->n_bands = (bases + max_rows - 1) / max_rows;
         pl->band_rows = (bases + pl->n_bands - 1) / pl->n_bands;
-        // Angle groups per slice: one block (1024 threads, one slice in LDS)
-        // per CU at a time; minimise rounds x (angles per block + about two
-        // angles' worth of staging), with at most 4 rays per thread.
-        int best_g = 1;
-        double best = 1e30;
-        for (int gcount = 1; gcount <= pl->M; ++gcount) {
-            int apb = (pl->M + gcount - 1) / gcount;
-            if ((long)apb * pl->nu > 4096) continue;
-            long rounds = ((long)pl->nz * gcount + 255) / 256;
-            double cost = (double)rounds * (apb + 2.0 * pl->n_bands);
-            if (cost < best - 1e-9) {
-                best = cost;
-                best_g = gcount;
+        // Forward: the nz * M (slice, angle) units are split into equal
+        // contiguous ranges, one per block (1024 threads, one slice in LDS, at
+        // most 4 rays per thread), in whole rounds of 256 blocks.
+        {
+            const long units = (long)pl->nz * pl->M;
+            const long umax = std::max<long>(1, 4096 / pl->nu);
+            long nb = (units + umax - 1) / umax;
+            nb = ((nb + 255) / 256) * 256;
+            pl->fwd_blocks = (int)std::min(nb, units);
+        }
+        // Backprojection: 16 x 16 voxel tiles times kz slices per block.  The
+        // ray weights are formed once per voxel and angle and reused over kz
+        // slices, so take the largest kz that still gives about three blocks
+        // per CU; angles are staged in LDS in chunks of at most 40 KB.
+        const long tiles = (long)((pl->nx + 15) / 16) * ((pl->ny + 15) / 16);
+        pl->kz = 8;
+        for (int kz : {32, 16}) {
+            if (tiles * ((pl->nz + kz - 1) / kz) >= 768) {
+                pl->kz = kz;
+                break;
             }
         }
-        pl->n_angle_groups = best_g;
-        pl->angles_per_block = (pl->M + best_g - 1) / best_g;
-        pl->kz = std::min(32, pl->nz);
+        const int chunk_max = std::max(1, (40 * 1024) / (pl->kz * 32 * (int)sizeof(float)));
+        const int nchunk = (pl->M + chunk_max - 1) / chunk_max;
+        pl->adj_chunk = (pl->M + nchunk - 1) / nchunk;
+        const long adj_blocks = tiles * ((pl->nz + pl->kz - 1) / pl->kz);
+        pl->max_parts = (int)std::max<long>(kMaxNormParts, adj_blocks);
     }
 
     // ---- float64 host tables ------------------------------------------------
@@ -464,7 +473,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->ws_rt = put(sizeof(float) * pl->L * pl->nup);
         pl->ws_part = put(sizeof(float) * (size_t)std::max(pl->nsplit, pl->serve_nsplit) * pl->ngroups * pl->L *
                           parts_rows);
-        pl->ws_norm = put(sizeof(double) * kMaxNormParts);
+        pl->ws_norm = put(sizeof(double) * pl->max_parts);
         pl->ws_rowscale = put(sizeof(float) * pl->L);
         pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
         pl->op_ws_bytes = align256(o);
@@ -479,7 +488,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->sw_s = put(sizeof(float) * pl->nvox);
         pl->sw_p = put(sizeof(float) * pl->nvox);
         pl->sw_scal = put(sizeof(double) * 64);
-        pl->sw_parts = put(sizeof(double) * 3 * kMaxNormParts);
+        pl->sw_parts = put(sizeof(double) * 3 * pl->max_parts);
         pl->sw_d = put(mixed ? sizeof(float) * pl->nvox : 0);   // refinement correction
         pl->sw_g = put(mixed ? sizeof(float) * pl->nvox : 0);   // FP32 gradient at the sweep start
         pl->solve_ws_bytes = align256(o);
