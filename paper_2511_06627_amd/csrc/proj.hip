@@ -89,6 +89,7 @@ __device__ __forceinline__ float sample(const T *lds, int W, int nx, int nbase, 
 // columns, fyb in band rows.  floor() via fract, exact for positive values;
 // the element index iy * W + ix is formed exactly in float.
 constexpr float kEdge = 1.0f / 64.0f;
+constexpr float kRange = 1.0f / 1024.0f;
 
 template <typename T>
 __device__ __forceinline__ float sample_in(const T *lds, int W, float bx, float byb, float s, float c, float y)
@@ -193,8 +194,11 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
                 // belongs to this band when its base row floor(fy) is in [jb0, jb1);
                 // fy does not depend on the band, so every sample lands in exactly
                 // one band.  Samples with floor(fx) outside [0, nx] touch no voxel.
-                // [q0, q1] is a slightly widened superset of the samples in the
-                // band (each checked exactly); inside it, [qa, qb] holds samples
+                // [q0, q1] is a widened superset of the samples in the band (each
+                // checked exactly): the edges are moved out by kRange in fx and fy,
+                // beyond the rounding of fx and fy themselves, so a ray that runs
+                // along a band edge (|c| tiny, fy rounding onto the edge row) keeps
+                // all its samples; inside it, [qa, qb] holds samples
                 // at least kEdge away from every edge in both coordinates, which
                 // need no test: there the band-relative row fy - jb0 lies in
                 // [kEdge, nbase - kEdge] and fx in [kEdge, nx + 1 - kEdge].
@@ -202,21 +206,21 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
                 float ylo = -a.half_nr, yhi = a.half_nr;
                 float ilo = -a.half_nr, ihi = a.half_nr;
                 if (s > 0.f) {
-                    ylo = fmaxf(ylo, (0.f - bx) / s);
-                    yhi = fminf(yhi, ((float)(a.nx + 1) - bx) / s);
+                    ylo = fmaxf(ylo, (-kRange - bx) / s);
+                    yhi = fminf(yhi, ((float)(a.nx + 1) + kRange - bx) / s);
                     ilo = fmaxf(ilo, (kEdge - bx) / s);
                     ihi = fminf(ihi, ((float)(a.nx + 1) - kEdge - bx) / s);
                 } else if (bx < kEdge || bx > (float)(a.nx + 1) - kEdge) {
                     ihi = ilo - 2.f;
                 }
                 if (c > 0.f) {
-                    ylo = fmaxf(ylo, ((float)jb0 - by) / c);
-                    yhi = fminf(yhi, ((float)jb1 - by) / c);
+                    ylo = fmaxf(ylo, ((float)jb0 - kRange - by) / c);
+                    yhi = fminf(yhi, ((float)jb1 + kRange - by) / c);
                     ilo = fmaxf(ilo, (kEdge - byb) / c);
                     ihi = fminf(ihi, ((float)nbase - kEdge - byb) / c);
                 } else if (c < 0.f) {
-                    ylo = fmaxf(ylo, ((float)jb1 - by) / c);
-                    yhi = fminf(yhi, ((float)jb0 - by) / c);
+                    ylo = fmaxf(ylo, ((float)jb1 + kRange - by) / c);
+                    yhi = fminf(yhi, ((float)jb0 - kRange - by) / c);
                     ilo = fmaxf(ilo, ((float)nbase - kEdge - byb) / c);
                     ihi = fminf(ihi, (kEdge - byb) / c);
                 } else if (byb < kEdge || byb > (float)nbase - kEdge) {

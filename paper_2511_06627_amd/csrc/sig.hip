@@ -87,7 +87,7 @@ __device__ __forceinline__ BlockPos locate(const SigArgs &a)
 // partner's, and return lo + hi (the same operand order on both waves).
 __device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
 {
-    float *slot = xs + ((parity * 4 + pair) * 2) * 16 * 64;
+    float *slot = xs + ((parity * kWaves + pair) * 2) * 16 * 64;
     float *own = slot + half * 16 * 64;
     const float *other = slot + (1 - half) * 16 * 64;
 #pragma unroll
@@ -105,9 +105,9 @@ __device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int 
 // Forward.  Per pair: GEMM1 over this wave's half of the detector samples,
 // pair exchange, GEMM2 over this wave's GH column tiles.
 template <int NUP, int GH>
-__global__ __launch_bounds__(512) void sig_fwd_f32(SigArgs a)
+__global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
 {
-    __shared__ float xs[2 * 4 * 2 * 16 * 64];
+    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -185,9 +185,9 @@ __global__ __launch_bounds__(512) void sig_fwd_f32(SigArgs a)
 // Adjoint.  Per pair: GEMM1 over this wave's GH column tiles (half the bins of
 // the group), pair exchange, GEMM2 over this wave's half of the detector tiles.
 template <int NUP, int GH>
-__global__ __launch_bounds__(512) void sig_adj_f32(SigArgs a)
+__global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
 {
-    __shared__ float xs[2 * 4 * 2 * 16 * 64];
+    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -242,6 +242,8 @@ __global__ __launch_bounds__(512) void sig_adj_f32(SigArgs a)
                 Gt = MFMA32(v[1], Y[4 * i + 1], Gt);
                 Gt = MFMA32(v[2], Y[4 * i + 2], Gt);
                 Gt = MFMA32(v[3], Y[4 * i + 3], Gt);
+                // keep this load's issue point: later ring slots stay in flight
+                __builtin_amdgcn_sched_barrier(0);
             } else {
                 if (i == NF) Gf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, Gt);
                 const int j = i - NF, s4 = j / PTH, pt = j % PTH;

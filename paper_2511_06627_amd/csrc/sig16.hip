@@ -75,7 +75,7 @@ __device__ __forceinline__ BlockPos locate(const SigArgs &a)
 
 __device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
 {
-    float *slot = xs + ((parity * 4 + pair) * 2) * 16 * 64;
+    float *slot = xs + ((parity * kWaves + pair) * 2) * 16 * 64;
     float *own = slot + half * 16 * 64;
     const float *other = slot + (1 - half) * 16 * 64;
 #pragma unroll
@@ -99,9 +99,9 @@ __device__ __forceinline__ f16x8 to_f16x8(const f32x16 &v, int base)
 }
 
 template <int NUP, int GH>
-__global__ __launch_bounds__(512) void sig_fwd_f16(SigArgs a)
+__global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 {
-    __shared__ float xs[2 * 4 * 2 * 16 * 64];
+    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -157,6 +157,8 @@ __global__ __launch_bounds__(512) void sig_fwd_f16(SigArgs a)
             ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
             if (i < NKS) {
                 S = MFMA16(v, R[i], S);
+                // keep this load's issue point: later ring slots stay in flight
+                __builtin_amdgcn_sched_barrier(0);
             } else {
                 if (i == NKS) {
                     const f32x16 Sf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, S);
@@ -182,9 +184,9 @@ __global__ __launch_bounds__(512) void sig_fwd_f16(SigArgs a)
 }
 
 template <int NUP, int GH>
-__global__ __launch_bounds__(512) void sig_adj_f16(SigArgs a)
+__global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
 {
-    __shared__ float xs[2 * 4 * 2 * 16 * 64];
+    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -237,6 +239,8 @@ __global__ __launch_bounds__(512) void sig_adj_f16(SigArgs a)
             ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
             if (i < NF) {
                 Gt = MFMA16(v, Y[i], Gt);
+                // keep this load's issue point: later ring slots stay in flight
+                __builtin_amdgcn_sched_barrier(0);
             } else {
                 if (i == NF) {
                     const f32x16 Gf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, Gt);

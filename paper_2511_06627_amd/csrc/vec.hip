@@ -116,9 +116,11 @@ __global__ __launch_bounds__(kThreads) void row_scale_kernel(long rows, int ncol
     if (lane == 0) {
         float s = 1.f;
         if (m > 0.f && isfinite(m)) {
+            // 2^-e brings the row maximum into [0.5, 1); capped so that rows
+            // of subnormal size get a finite scale (and a normal 1/scale)
             int e;
             frexpf(m, &e);
-            s = ldexpf(1.f, -e);
+            s = ldexpf(1.f, min(-e, 120));
         }
         out[row] = s;
     }

@@ -1,0 +1,114 @@
+"""The high-dynamic-range scan on the GPU: 256 x 256 x 128 voxels, 60 angles,
+128 lines x 16384 samples per angle, harmonics 1-47 +/- 3 bins, a bright
+ellipsoid with 30 faint satellite blobs (amplitudes 1e-4..1e-2), 0.1% noise.
+
+Operator parity on sampled slices (A is the same on every slice, so one
+oracle slice is the exact reference for the GPU's lines of that slice), and
+the nonnegative solve -- CGLS, 100 iterations, clamped and restarted every
+10 -- in FP32 and in mixed precision (10 refinement sweeps of 10, clamped
+after each), against the FP64 oracle's solve stored in
+tests/golden/hdr_reference.json (tests/golden/make_hdr.py): the iterate on
+4096 sample voxels and each faint blob's recovered amplitude.  CGLS is
+chaotic mid-run, so the bars are max(1e-5, 4 x envelope), the envelope being
+the oracle's own drift under operator errors of the FP32 (1e-6) or mixed
+(2e-4) level.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import operator as oop
+from paper_2511_06627_amd import configs, phantoms
+from helpers import config_geometry, rel_l2, random_data
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+TOL_OP16 = 5e-3
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hdr_reference.json")
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hdr(torch_mod):
+    from paper_2511_06627_amd.plan import Plan
+    cfg = configs.HDR_256
+    _log("case hdr_256x256x128 setup")
+    ref = json.load(open(GOLDEN))
+    g = config_geometry(cfg)
+    assert abs(g.op_scale - ref["op_scale"]) <= 1e-9 * ref["op_scale"]
+    ph = configs.make_phantom(cfg)
+    b, _ = oop.make_data(g, ph, cfg.noise, cfg.noise_seed)
+    plan = Plan.from_config(cfg, g.op_scale, precisions=("fp32", "mixed"))
+    return cfg, g, plan, ph, b.astype(np.complex64), ref
+
+
+def _amplitudes(x, ref, shape):
+    out = []
+    for bl in ref["blobs"]:
+        gb = phantoms._blob(shape, bl["centre_xyz"], bl["sigma"], 1.0)
+        out.append(float(np.vdot(x, gb) / np.vdot(gb, gb)))
+    return np.array(out)
+
+
+def test_hdr_operator_sampled(hdr, torch_mod):
+    cfg, g, plan, ph, b, ref = hdr
+    gs = g.slice_geometry()
+    xd = torch_mod.from_numpy(ph).float().cuda()
+    y = random_data(g, 41)
+    yd = torch_mod.from_numpy(y).to(torch_mod.complex64).cuda()
+    mass = ph.sum(axis=(1, 2))
+    nonzero = np.flatnonzero(mass > 1e-3 * mass.max())
+    ks = (int(np.argmax(mass)), int(nonzero[len(nonzero) // 5]))   # the organ's middle, and near its edge
+    for prec, tol in (("fp32", TOL32), ("mixed", TOL_OP16)):
+        got = plan.forward(xd, precision=prec).cpu().numpy()
+        for k in ks:
+            err = rel_l2(got[:, k, :], oop.forward(gs, ph[k:k + 1])[:, 0, :])
+            _log("hdr %s forward slice %d rel err %.3e" % (prec, k, err))
+            assert err <= tol
+        got = plan.adjoint(yd, precision=prec).cpu().numpy()
+        for k in (9, 120):
+            err = rel_l2(got[k], oop.adjoint(gs, y[:, k:k + 1, :])[0])
+            _log("hdr %s adjoint slice %d rel err %.3e" % (prec, k, err))
+            assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_hdr_nonnegative_solve(hdr, torch_mod, prec):
+    cfg, g, plan, ph, b, ref = hdr
+    bd = torch_mod.from_numpy(b).cuda()
+    if prec == "fp32":
+        x, rep = plan.solve(bd, cfg.lam, iters=cfg.iters, clamp_every=cfg.clamp_every)
+    else:
+        x, rep = plan.solve(bd, cfg.lam, precision="mixed", refine_sweeps=cfg.iters // cfg.clamp_every,
+                            inner_iters=cfg.clamp_every, clamp_every=cfg.clamp_every)
+    assert rep.status == 0
+    x = x.cpu().numpy().astype(np.float64)
+    assert x.min() >= 0.0
+    idx = np.array(ref["sample_index"])
+    want = np.array(ref["sample_value"])
+    env = ref["envelope"][prec]
+    err = rel_l2(x.ravel()[idx], want)
+    tol = max(TOL32, 4 * env["samples_rel_l2"])
+    amp = _amplitudes(x, ref, cfg.shape)
+    amp_ref = np.array([bl["amp_oracle"] for bl in ref["blobs"]])
+    amp_true = np.array([bl["amp_true"] for bl in ref["blobs"]])
+    aerr = float(np.max(np.abs(amp - amp_ref) / np.abs(amp_ref)))
+    atol = max(TOL32, 4 * env["amp_max_rel"])
+    _log("hdr %s solve: samples rel err %.3e (tol %.3e); faint-blob amplitude max rel err vs oracle %.3e "
+         "(tol %.3e); recovered/true median %.3f" % (prec, err, tol, aerr, atol, float(np.median(amp / amp_true))))
+    assert err <= tol
+    assert aerr <= atol

@@ -85,6 +85,24 @@ def test_mixed_adjoint_sees_weak_bands(case, torch_mod):
     assert rel_l2(got_full, oop.adjoint(g, y)) <= TOL_OP16
 
 
+def test_mixed_subnormal_rows_stay_finite(case, torch_mod):
+    """Lines whose values are subnormal in fp32 (a faint blob's far tail): the
+    per-line fp16 scale stays finite, so the outputs do too, and every other
+    line keeps its accuracy."""
+    name, g, plan = case
+    y = random_data(g, 35)
+    y[:, 0, :] *= 1e-40
+    got = plan.adjoint(_dev(torch_mod, y, torch_mod.complex64), precision="mixed").cpu().numpy()
+    assert np.isfinite(got).all()
+    want = oop.adjoint(g, y)
+    assert rel_l2(got[1:], want[1:]) <= TOL_OP16
+    x = random_volume(g, 36)
+    x[0] *= 1e-40
+    got = plan.forward(_dev(torch_mod, x, torch_mod.float32), precision="mixed").cpu().numpy()
+    assert np.isfinite(got).all()
+    assert rel_l2(got[:, 1:], oop.forward(g, x)[:, 1:]) <= TOL_OP16
+
+
 @pytest.fixture(scope="module")
 def parity_problem(torch_mod):
     from paper_2511_06627_amd.plan import Plan

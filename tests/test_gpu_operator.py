@@ -25,6 +25,9 @@ CASES = {
     "ragged": (40, 36, 5, 7, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1),
     # several line tiles with a ragged last one, 7 column tiles, non-square slice
     "multi_tile": (64, 48, 20, 9, 4096, 4096 / 256 + 1 / 3, 3.0, 1, 20, 2),
+    # a slice too large for LDS (staged in two row bands), with the 90 degree
+    # angle whose central rays run exactly along the band edge
+    "banded": (220, 220, 3, 6, 1024, 1024 / 256 + 1 / 3, 2.0, 1, 7, 1),
     # enough lines that each block walks several time chunks (540 lines, 128
     # chunks), with a per-chunk operand stream that is not a multiple of 8
     "many_lines": (64, 64, 60, 9, 4096, 4096 / 256 + 1 / 3, 3.0, 1, 20, 2),
