@@ -98,6 +98,21 @@ def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=N
     return out
 
 
+def oracle_hdr_inputs():
+    """c_A and data of the high-dynamic-range scan from the oracle (same
+    recipe as its stored FP64 solve in tests/golden/hdr_reference.json)."""
+    import numpy as np
+    from oracle import operator as oop
+    from oracle.geometry import Geometry
+    from paper_2511_06627_amd import configs
+    c = configs.HDR_256
+    g = Geometry(nx=c.nx, ny=c.ny, nz=c.nz, n_angles=c.n_angles, n_t=c.n_t, drive_cycles=c.drive_cycles,
+                 psf_width=c.psf_width, harm_lo=c.harm_lo, harm_hi=c.harm_hi, half_band=c.half_band)
+    g = oop.normalised(g, iters_min=30, rtol=1e-9)
+    b, _ = oop.make_data(g, configs.make_phantom(c), c.noise, c.noise_seed)
+    return {"op_scale": g.op_scale, "b": b.astype(np.complex64)}
+
+
 # ---------------------------------------------------------------------------
 # GPU leg
 # ---------------------------------------------------------------------------
@@ -175,10 +190,53 @@ def time_to_solve(plan, torch, b, xstar, lam, precision="fp32"):
     return {"schedule": hit, "seconds": round(sorted(ts)[1], 5), "rel_err": errs[-1]}
 
 
+def hdr_leg(torch, inputs):
+    """The high-dynamic-range scan, FP32 (100 CGLS iterations, clamp + restart
+    every 10) and mixed (10 sweeps of 10, clamp after each): solve time, and
+    the faint blobs' recovered amplitudes against the FP64 oracle's solve."""
+    import numpy as np
+    from paper_2511_06627_amd import configs, phantoms
+    from paper_2511_06627_amd.plan import Plan
+    cfg = configs.HDR_256
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "hdr_reference.json")))
+    plan = Plan.from_config(cfg, inputs["op_scale"], precisions=("fp32", "mixed"))
+    bd = torch.from_numpy(inputs["b"]).cuda()
+    idx = np.array(ref["sample_index"])
+    want = np.array(ref["sample_value"])
+    amp_ref = np.array([bl["amp_oracle"] for bl in ref["blobs"]])
+    amp_true = np.array([bl["amp_true"] for bl in ref["blobs"]])
+    profiles = [phantoms._blob(cfg.shape, bl["centre_xyz"], bl["sigma"], 1.0) for bl in ref["blobs"]]
+    out = {"workload": "hdr_256x256x128: 60 angles, 128 lines x 16384 samples, harmonics 1-47 +/-3, "
+                       "bright ellipsoid + 30 faint blobs (1e-4..1e-2), 0.1% noise"}
+    schedules = {"fp32": dict(iters=cfg.iters, clamp_every=cfg.clamp_every),
+                 "mixed": dict(precision="mixed", refine_sweeps=cfg.iters // cfg.clamp_every,
+                               inner_iters=cfg.clamp_every, clamp_every=cfg.clamp_every)}
+    for prec, kw in schedules.items():
+        plan.solve(bd, cfg.lam, report=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, rep = plan.solve(bd, cfg.lam, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xn = x.cpu().numpy().astype(np.float64)
+        amp = np.array([float(np.vdot(xn, gb) / np.vdot(gb, gb)) for gb in profiles])
+        out[prec] = {"schedule": kw, "seconds": round(dt, 4), "status": rep.status,
+                     "samples_rel_l2_vs_oracle": float(np.linalg.norm(xn.ravel()[idx] - want) / np.linalg.norm(want)),
+                     "faint_amp_max_rel_err_vs_oracle": float(np.max(np.abs(amp - amp_ref) / np.abs(amp_ref))),
+                     "faint_amp_median_rel_err_vs_oracle": float(np.median(np.abs(amp - amp_ref) / np.abs(amp_ref))),
+                     "faint_amp_recovered_over_true_median": float(np.median(amp / amp_true))}
+        log("hdr %s: %s" % (prec, out[prec]))
+    out["oracle_envelope"] = ref["envelope"]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Serving leg: the request stream, solved by the continuous batcher
 # ---------------------------------------------------------------------------
-MIXED_CANDIDATES = ((1, 40), (2, 25), (2, 30), (2, 40), (3, 30), (3, 40), (4, 40), (5, 40))
+# Refinement schedules (sweeps, inner iterations), in order of cost: a sweep's
+# FP32 restart costs about two mixed iterations.
+MIXED_CANDIDATES = ((2, 25), (2, 30), (3, 20), (2, 35), (3, 25), (4, 20), (3, 30), (4, 25), (3, 40), (5, 30),
+                    (6, 30))
 
 
 def device_data(torch, plan, phantom, noise, seed):
@@ -301,7 +359,7 @@ def serve_leg(torch, n_requests=None, stream=True):
             else:
                 lo = mid
         sched32[k] = dict(precision="fp32", iters=hi)
-        sched16[k] = dict(precision="mixed", refine_sweeps=5, inner_iters=40)
+        sched16[k] = dict(precision="mixed", refine_sweeps=6, inner_iters=30)
         for sw, inner in MIXED_CANDIDATES:
             if err(p, r, precision="mixed", refine_sweeps=sw, inner_iters=inner) <= 1e-4:
                 sched16[k] = dict(precision="mixed", refine_sweeps=sw, inner_iters=inner)
@@ -338,6 +396,7 @@ def main():
                     help="skip the 32^3 time-to-solve (keeps a profile to the realistic scan)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream and closed-loop capacity")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests in the serving stream (default 64)")
+    ap.add_argument("--no-hdr", action="store_true", help="skip the high-dynamic-range scan")
     ap.add_argument("--no-cpu", action="store_true",
                     help="no oracle leg (for profiling runs): c_A estimated by the plan, data made on the device, "
                          "no cpu_baseline and no time-to-solve")
@@ -354,6 +413,8 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline_leg(cfg, want_minimiser=args.tts, sample_seconds=args.cpu_seconds,
                                small_cfg=None if args.skip_small else small)
+        if not args.no_hdr:
+            cpu["hdr"] = oracle_hdr_inputs()
 
     import numpy as np
     import torch
@@ -430,9 +491,12 @@ def main():
     torch.cuda.synchronize()
     dt16 = time.perf_counter() - t0
     kt16 = {k: plan.time_kernel(k, repeats=10, precision="mixed", x=x, b=b, ws=ws)
-            for k in ("signal_fwd", "signal_adj")}
+            for k in ("project", "signal_fwd", "signal_adj")}
     mixed = {"applies_per_s": round(args.steps / dt16, 2), "ms_per_step": round(1e3 * dt16 / args.steps, 4)}
     for k, v in kt16.items():
+        if k == "project":
+            mixed["project_bf16"] = {"ms": round(v, 4), "per_angle_stream_GBs": round(pb / (v * 1e-3) / 1e9, 1)}
+            continue
         a16 = fl / (v * 1e-3) / 1e12
         mixed[k] = {"ms": round(v, 4), "tflops": round(a16, 1), "mfma_frac_fp16": round(a16 / FP16_PEAK_TFLOPS, 4)}
     log("mixed A^T A: %.3f ms/step; kernels %s" % (1e3 * dt16 / args.steps, kt16))
@@ -477,6 +541,10 @@ def main():
         tts[cfg.name] = {p: time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, p)
                          for p in ("fp32", "mixed")}
 
+    hdr = None
+    if cpu is not None and not args.no_hdr:
+        hdr = hdr_leg(torch, cpu["hdr"])
+
     serve = None
     if not args.no_serve:
         serve = serve_leg(torch, args.serve_requests or None)
@@ -506,6 +574,7 @@ def main():
         "time_to_solve": tts,
         "mixed": mixed,
         "serving": serve,
+        "hdr": hdr,
         "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1) if cpu is not None else None,
     }
     print(json.dumps(line), flush=True)

@@ -232,7 +232,10 @@ void mpi3d_state_destroy(mpi3d_state *state);
  * Benchmark support.  Enqueues `repeats` back-to-back launches of one kernel
  * of the operator on `stream` between two HIP events, synchronises, and
  * stores the mean time per launch (milliseconds) in *avg_ms.
- *   kernel 0  projection            reads x_dev, writes the workspace
+ *   kernel 0  projection            reads x_dev, writes the workspace (MIXED:
+ *                                   x_dev is first converted to bf16 once,
+ *                                   outside the timed launches, and the bf16
+ *                                   gather variant is timed)
  *   kernel 1  backprojection        reads the workspace, writes x_dev
  *   kernel 2  signal forward contraction (time signal + band DFT)
  *   kernel 3  signal adjoint contraction, reads b_dev

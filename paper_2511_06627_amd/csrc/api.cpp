@@ -530,10 +530,13 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         a.jobs[0].in_stride = pl->nb2;
         a.jobs[0].part_stride = pl->L * pl->nup;
     }
-    hipError_t err = hipEventRecord(e0, st);
+    const bool mixed = precision == MPI3D_MIXED;
+    hipError_t err = mixed && kernel == 0 ? launch_to_bf16(pl->nvox, x, w.xb, st) : hipSuccess;
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
     for (int i = 0; err == hipSuccess && i < repeats; ++i) {
         switch (kernel) {
-        case 0: err = launch_project(pl, x, nullptr, w.rt, st); break;
+        case 0: err = mixed ? launch_project(pl, nullptr, w.xb, w.rt, st) : launch_project(pl, x, nullptr, w.rt, st);
+            break;
         case 1: err = launch_backproject(pl, w.rt, x, nullptr, 0.0, nullptr, nullptr, st); break;
         case 2: err = launch_sig_fwd(pl, precision, a, st); break;
         default: err = launch_sig_adj(pl, precision, a, st); break;

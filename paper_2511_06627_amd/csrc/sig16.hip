@@ -30,16 +30,6 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-// Table loads kept in flight per wave.  The ring slot of stream element i is
-// i % ring, and the stream restarts every chunk, so the ring size must divide
-// the per-chunk stream length: the largest divisor of it not above a cap.
-constexpr int ring_size(int nl, int cap)
-{
-    for (int r = cap; r > 1; --r)
-        if (nl % r == 0) return r;
-    return 1;
-}
-
 __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
 {
     const int nx = 8;
@@ -98,20 +88,63 @@ __device__ __forceinline__ f16x8 to_f16x8(const f32x16 &v, int base)
     return r;
 }
 
+// Per-chunk table staging.  The block copies each time chunk's table slices
+// (GEMM1's and GEMM2's) from HBM/L2 into LDS once, with every thread moving a
+// few 16-byte units; the waves then read their operand fragments from LDS.
+// Without it each of the four pairs would fetch the same slices itself.
+//   A slice (GEMM1 operands), double-buffered: chunk c+1 is written before the
+//     pair barrier of chunk c, whose GEMM1 no longer reads that buffer (it
+//     last served chunk c-1, finished before the barrier of chunk c-1).
+//   B slice (GEMM2 operands), double-buffered: chunk c+1 is written after the
+//     pair barrier of chunk c; that buffer last served GEMM2 of chunk c-1,
+//     which every wave finished before reaching the barrier of chunk c.
+// The barrier of chunk c+1 then publishes both before they are read.
+template <int UNITS>
+struct Slice {
+    static constexpr int kPer = (UNITS + kSigThreads - 1) / kSigThreads;
+    f16x8 v[kPer];
+    __device__ __forceinline__ void load(const f16x8 *src, int tid)
+    {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int u = tid + j * kSigThreads;
+            if (u < UNITS) v[j] = src[u];
+        }
+    }
+    __device__ __forceinline__ void store(f16x8 *dst, int tid) const
+    {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int u = tid + j * kSigThreads;
+            if (u < UNITS) dst[u] = v[j];
+        }
+    }
+};
+
+constexpr int kXsBytes = 2 * kWaves * 2 * 16 * 64 * (int)sizeof(float);
+
+template <int NUP, int GH>
+constexpr int sig16_lds_bytes()
+{
+    return kXsBytes + 2 * 16 * (4 * NUP + 256 * GH);
+}
+
 template <int NUP, int GH>
 __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 {
-    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xs = reinterpret_cast<float *>(smem);
+    constexpr int UA = 4 * NUP;           // K slice: NUP/16 fragments of 64 lanes
+    constexpr int UB = 256 * GH;          // F slice of the group: 2 GH tiles x 2 halves
+    f16x8 *la = reinterpret_cast<f16x8 *>(smem + kXsBytes);
+    f16x8 *lb = la + 2 * UA;
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
     constexpr int NKS = NUP / 32;         // fp16 K steps per half (16 detector samples each)
-    constexpr int NF = 2 * GH;            // F loads per chunk (two 16-sample halves per tile)
-    constexpr int NL = NKS + NF;
-    constexpr int kRing = ring_size(NL, 12);
-    static_assert(NL % kRing == 0, "ring size must divide the stream");
 
     // this wave's half of the line, scaled by the line's power-of-two scale
     // (row_scale kernel), as fp16 B operands
@@ -132,46 +165,46 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 #pragma unroll
     for (int g = 0; g < GH; ++g) acc[g] = 0.f;
 
-    const int ctb = bp.group * 2 * GH + bp.half * GH;
-    const int kst0 = bp.half * NKS;
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
-    const f16x8 *kf = (const f16x8 *)a.kf16 + lane;
-    const f16x8 *ff = (const f16x8 *)a.ff16 + lane;
-    auto load = [&](int cc, int i) -> f16x8 {
-        if (i < NKS) return kf[((size_t)cc * (NUP / 16) + kst0 + i) * 64];
-        const int j = i - NKS, hh = j / GH, g = j % GH;
-        return ff[(((size_t)cc * a.nct + ctb + g) * 2 + hh) * 64];
-    };
-    f16x8 ring[kRing];
-    const int cfirst = min(c0, a.nchunks - 1);
-#pragma unroll
-    for (int d = 0; d < kRing; ++d) ring[d] = load(cfirst, d);
+    const f16x8 *kg = (const f16x8 *)a.kf16;
+    const f16x8 *fg = (const f16x8 *)a.ff16 + (size_t)bp.group * UB;
+    const size_t fstride = (size_t)a.nct * 128;
+    Slice<UA> sa;
+    Slice<UB> sb;
+    if (c0 < c1) {
+        sa.load(kg + (size_t)c0 * UA, tid);
+        sb.load(fg + (size_t)c0 * fstride, tid);
+        sa.store(la + (c0 & 1) * UA, tid);
+        sb.store(lb + (c0 & 1) * UB, tid);
+    }
+    __syncthreads();
+    const int ka0 = bp.half * NKS * 64 + lane;           // this wave's first K fragment
+    const int fb0 = bp.half * GH * 128 + lane;           // this wave's first F fragment
 
     for (int c = c0; c < c1; ++c) {
-        const int cnext = min(c + 1, c1 - 1);
-        f32x16 S = 0.f;
-        f16x8 S16[2];
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const f16x8 v = ring[i % kRing];
-            ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
-            if (i < NKS) {
-                S = MFMA16(v, R[i], S);
-                // keep this load's issue point: later ring slots stay in flight
-                __builtin_amdgcn_sched_barrier(0);
-            } else {
-                if (i == NKS) {
-                    const f32x16 Sf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, S);
-                    S16[0] = to_f16x8(Sf, 0);
-                    S16[1] = to_f16x8(Sf, 8);
-                }
-                const int j = i - NKS, hh = j / GH, g = j % GH;
-                acc[g] = MFMA16(S16[hh], v, acc[g]);
-            }
+        const int buf = c & 1;
+        const bool more = c + 1 < c1;
+        if (more) {
+            sa.load(kg + (size_t)(c + 1) * UA, tid);
+            sb.load(fg + (size_t)(c + 1) * fstride, tid);
         }
+        const f16x8 *ka = la + buf * UA + ka0;
+        f32x16 S = 0.f;
+#pragma unroll
+        for (int i = 0; i < NKS; ++i) S = MFMA16(ka[i * 64], R[i], S);
+        if (more) sa.store(la + (buf ^ 1) * UA, tid);
+        const f32x16 Sf = pair_sum(xs, buf, bp.pair, bp.half, lane, S);
+        if (more) sb.store(lb + (buf ^ 1) * UB, tid);
+        const f16x8 S16[2] = {to_f16x8(Sf, 0), to_f16x8(Sf, 8)};
+        const f16x8 *fb = lb + buf * UB + fb0;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int g = 0; g < GH; ++g) acc[g] = MFMA16(S16[hh], fb[(g * 2 + hh) * 64], acc[g]);
     }
     if (bp.row0 >= job.rows) return;
     float *out = job.part + (size_t)bp.split * job.part_stride;
+    const int ctb = bp.group * 2 * GH + bp.half * GH;
 #pragma unroll
     for (int g = 0; g < GH; ++g) {
         const int col = (ctb + g) * 32 + (lane & 31);
@@ -186,18 +219,20 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 template <int NUP, int GH>
 __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
 {
-    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xs = reinterpret_cast<float *>(smem);
+    constexpr int UA = 256 * GH;          // F slice of the group (GEMM1)
+    constexpr int UB = 4 * NUP;           // K slice (GEMM2)
+    f16x8 *la = reinterpret_cast<f16x8 *>(smem + kXsBytes);
+    f16x8 *lb = la + 2 * UA;
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
     constexpr int PTH = NUP / 64;
     constexpr int NF = 2 * GH;            // fp16 F steps per chunk (16 columns each)
-    constexpr int NK = 2 * PTH;           // K loads per chunk
-    constexpr int NL = NF + NK;
-    constexpr int kRing = ring_size(NL, 12);
-    static_assert(NL % kRing == 0, "ring size must divide the stream");
     const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;
     const int pt0 = bp.half * PTH;
 
@@ -217,40 +252,41 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     for (int pt = 0; pt < PTH; ++pt) racc[pt] = 0.f;
 
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
-    const f16x8 *fa = (const f16x8 *)a.fa16 + lane;
-    const f16x8 *ka = (const f16x8 *)a.ka16 + lane;
-    auto load = [&](int cc, int i) -> f16x8 {
-        if (i < NF) return fa[((size_t)cc * (a.nbp2 / 16) + colbase / 16 + i) * 64];
-        const int j = i - NF, hh = j / PTH, pt = j % PTH;
-        return ka[(((size_t)cc * (NUP / 32) + pt0 + pt) * 2 + hh) * 64];
-    };
-    f16x8 ring[kRing];
-    const int cfirst = min(c0, a.nchunks - 1);
-#pragma unroll
-    for (int d = 0; d < kRing; ++d) ring[d] = load(cfirst, d);
+    const size_t fstride = (size_t)a.nct * 128;
+    const f16x8 *fg = (const f16x8 *)a.fa16 + (size_t)bp.group * UA;
+    const f16x8 *kg = (const f16x8 *)a.ka16;
+    Slice<UA> sa;
+    Slice<UB> sb;
+    if (c0 < c1) {
+        sa.load(fg + (size_t)c0 * fstride, tid);
+        sb.load(kg + (size_t)c0 * UB, tid);
+        sa.store(la + (c0 & 1) * UA, tid);
+        sb.store(lb + (c0 & 1) * UB, tid);
+    }
+    __syncthreads();
+    const int fa0 = bp.half * NF * 64 + lane;            // this wave's first F fragment
+    const int kb0 = pt0 * 128 + lane;                    // this wave's first K fragment
 
     for (int c = c0; c < c1; ++c) {
-        const int cnext = min(c + 1, c1 - 1);
-        f32x16 Gt = 0.f;
-        f16x8 G16[2];
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const f16x8 v = ring[i % kRing];
-            ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
-            if (i < NF) {
-                Gt = MFMA16(v, Y[i], Gt);
-                // keep this load's issue point: later ring slots stay in flight
-                __builtin_amdgcn_sched_barrier(0);
-            } else {
-                if (i == NF) {
-                    const f32x16 Gf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, Gt);
-                    G16[0] = to_f16x8(Gf, 0);
-                    G16[1] = to_f16x8(Gf, 8);
-                }
-                const int j = i - NF, hh = j / PTH, pt = j % PTH;
-                racc[pt] = MFMA16(G16[hh], v, racc[pt]);
-            }
+        const int buf = c & 1;
+        const bool more = c + 1 < c1;
+        if (more) {
+            sa.load(fg + (size_t)(c + 1) * fstride, tid);
+            sb.load(kg + (size_t)(c + 1) * UB, tid);
         }
+        const f16x8 *fa = la + buf * UA + fa0;
+        f32x16 Gt = 0.f;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) Gt = MFMA16(fa[i * 64], Y[i], Gt);
+        if (more) sa.store(la + (buf ^ 1) * UA, tid);
+        const f32x16 Gf = pair_sum(xs, buf, bp.pair, bp.half, lane, Gt);
+        if (more) sb.store(lb + (buf ^ 1) * UB, tid);
+        const f16x8 G16[2] = {to_f16x8(Gf, 0), to_f16x8(Gf, 8)};
+        const f16x8 *kb = lb + buf * UB + kb0;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int pt = 0; pt < PTH; ++pt) racc[pt] = MFMA16(G16[hh], kb[(pt * 2 + hh) * 64], racc[pt]);
     }
     if (bp.row0 >= job.rows) return;
     float *out = job.part + (size_t)(bp.split * a.ngroups + bp.group) * job.part_stride;
@@ -283,6 +319,11 @@ int nup_slot(int nup)
     return -1;
 }
 
+#define LROW(NUP) {sig16_lds_bytes<NUP, 3>(), sig16_lds_bytes<NUP, 4>(), sig16_lds_bytes<NUP, 6>(), \
+                   sig16_lds_bytes<NUP, 7>()}
+const int kLds[4][4] = {LROW(64), LROW(128), LROW(192), LROW(256)};
+#undef LROW
+
 #define ROW(NUP, F) {F<NUP, 3>, F<NUP, 4>, F<NUP, 6>, F<NUP, 7>}
 const SigKernel kFwd[4][4] = {ROW(64, sig_fwd_f16), ROW(128, sig_fwd_f16), ROW(192, sig_fwd_f16),
                               ROW(256, sig_fwd_f16)};
@@ -294,12 +335,21 @@ const SigKernel kAdj[4][4] = {ROW(64, sig_adj_f16), ROW(128, sig_adj_f16), ROW(1
 
 int sig16_supported(int nup, int gct) { return nup_slot(nup) >= 0 && gh_slot(gct) >= 0; }
 
+// Dynamic LDS above 64 KB has to be allowed per kernel.
+static hipError_t allow_lds(const void *kernel, int bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 hipError_t launch_sig_fwd16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st)
 {
     const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
     if (ns < 0 || gs < 0 || !pl->kf16) return hipErrorInvalidValue;
+    hipError_t e = allow_lds((const void *)kFwd[ns][gs], kLds[ns][gs]);
+    if (e != hipSuccess) return e;
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;
-    hipLaunchKernelGGL(kFwd[ns][gs], dim3(blocks), dim3(kSigThreads), 0, st, a);
+    hipLaunchKernelGGL(kFwd[ns][gs], dim3(blocks), dim3(kSigThreads), kLds[ns][gs], st, a);
     return hipGetLastError();
 }
 
@@ -307,8 +357,10 @@ hipError_t launch_sig_adj16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st)
 {
     const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
     if (ns < 0 || gs < 0 || !pl->ka16) return hipErrorInvalidValue;
+    hipError_t e = allow_lds((const void *)kAdj[ns][gs], kLds[ns][gs]);
+    if (e != hipSuccess) return e;
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;
-    hipLaunchKernelGGL(kAdj[ns][gs], dim3(blocks), dim3(kSigThreads), 0, st, a);
+    hipLaunchKernelGGL(kAdj[ns][gs], dim3(blocks), dim3(kSigThreads), kLds[ns][gs], st, a);
     return hipGetLastError();
 }
 
