@@ -86,6 +86,18 @@ def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=N
         ph = configs.make_phantom(small_cfg)
         bs, _ = oop.make_data(gs, ph, small_cfg.noise, small_cfg.noise_seed)
         bs = bs.astype(np.complex64)
+        # oracle beside the GPU on the small scan: A^T A rate (time-domain form)
+        # and the configured CGLS solve
+        ops = oop.Operator(gs)
+        n, t0 = 0, time.time()
+        while n < 3 or time.time() - t0 < 2.0:
+            ops.adjoint(ops.forward(ph))
+            n += 1
+        t_small = (time.time() - t0) / n
+        t0 = time.time()
+        solvers.cgls(ops, bs.astype(np.complex128), small_cfg.lam, small_cfg.iters)
+        out["oracle_small"] = {"workload": small_cfg.name, "AtA_per_s": round(1.0 / t_small, 2),
+                               "cgls_%d_seconds" % small_cfg.iters: round(time.time() - t0, 3)}
         xs, it = solvers.reference_minimiser(oop.Operator(gs, precomposed=True), bs.astype(np.complex128),
                                              small_cfg.lam, tol=1e-12)
         out["small"] = {"op_scale": gs.op_scale, "b": bs, "xstar": xs, "xstar_iters": it}
@@ -110,7 +122,15 @@ def oracle_hdr_inputs():
                  psf_width=c.psf_width, harm_lo=c.harm_lo, harm_hi=c.harm_hi, half_band=c.half_band)
     g = oop.normalised(g, iters_min=30, rtol=1e-9)
     b, _ = oop.make_data(g, configs.make_phantom(c), c.noise, c.noise_seed)
-    return {"op_scale": g.op_scale, "b": b.astype(np.complex64)}
+    # one oracle A^T A at this size, on its precomposed per-line form (the
+    # time-domain form takes minutes per application here); labelled so
+    op = oop.Operator(g, precomposed=True)
+    x = np.ones((c.nz, c.ny, c.nx))
+    t0 = time.time()
+    op.adjoint(op.forward(x))
+    t_ata = time.time() - t0
+    return {"op_scale": g.op_scale, "b": b.astype(np.complex64),
+            "oracle": {"workload": c.name, "AtA_per_s_precomposed": round(1.0 / t_ata, 4)}}
 
 
 # ---------------------------------------------------------------------------
@@ -128,6 +148,19 @@ def projection_bytes(cfg):
     volume once and writes its lines (fp32)."""
     nvox = cfg.nx * cfg.ny * cfg.nz
     return 4.0 * (cfg.n_angles * nvox + cfg.n_lines * cfg.n_u)
+
+
+def step_times(torch, step, n=20):
+    """Per-step device times (ms) from events on the current stream: median and p99."""
+    import numpy as np
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for e0, e1 in ev:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    ts = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return {"median": round(float(np.median(ts)), 4), "p99": round(float(np.percentile(ts, 99)), 4), "n": n}
 
 
 def kernel_source_hash():
@@ -227,6 +260,7 @@ def hdr_leg(torch, inputs):
                      "faint_amp_recovered_over_true_median": float(np.median(amp / amp_true))}
         log("hdr %s: %s" % (prec, out[prec]))
     out["oracle_envelope"] = ref["envelope"]
+    out["oracle_timing"] = inputs["oracle"]
     return out
 
 
@@ -456,6 +490,7 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     log("A^T A: %.3f ms/step" % ms_step)
+    st32 = step_times(torch, step)
 
     # per-kernel device times (HIP events inside the library, on this stream)
     kt = {k: plan.time_kernel(k, repeats=10, x=x, b=b, ws=ws)
@@ -492,7 +527,8 @@ def main():
     dt16 = time.perf_counter() - t0
     kt16 = {k: plan.time_kernel(k, repeats=10, precision="mixed", x=x, b=b, ws=ws)
             for k in ("project", "signal_fwd", "signal_adj")}
-    mixed = {"applies_per_s": round(args.steps / dt16, 2), "ms_per_step": round(1e3 * dt16 / args.steps, 4)}
+    mixed = {"applies_per_s": round(args.steps / dt16, 2), "ms_per_step": round(1e3 * dt16 / args.steps, 4),
+             "step_ms": step_times(torch, step16)}
     for k, v in kt16.items():
         if k == "project":
             mixed["project_bf16"] = {"ms": round(v, 4), "per_angle_stream_GBs": round(pb / (v * 1e-3) / 1e9, 1)}
@@ -566,6 +602,7 @@ def main():
         "config": {"workload": "realistic_192x192x96: 36 angles, 96 lines x 8192 samples per angle, "
                                "harmonics 1-31 +/-3 bins, 40 blobs + ellipsoid phantom, 0.5% noise",
                    "step": "A then A^T, FP32 path", "global_batch": 1, "parallelism": "single GPU"},
+        "step_ms": st32,
         "roofline": roofline,
         "cpu_baseline": cpu["cpu_baseline"] if cpu is not None else None,
         "kernels": kernels,
@@ -575,6 +612,7 @@ def main():
         "mixed": mixed,
         "serving": serve,
         "hdr": hdr,
+        "oracle_small": cpu.get("oracle_small") if cpu is not None else None,
         "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1) if cpu is not None else None,
     }
     print(json.dumps(line), flush=True)

@@ -68,14 +68,15 @@ int ray_count(int nx, int ny)
     return n;
 }
 
-// Choose the T-split: (line tiles x splits x groups) blocks, eight wave
-// pairs resident per CU.  Cost in units of one block's time per chunk: rounds of blocks times
+// Choose the T-split: (line tiles x splits x groups) blocks; the signal
+// kernels need about 250 VGPRs, so two waves per SIMD (four wave pairs) are
+// resident per CU.  Cost in units of one block's time per chunk: rounds of blocks times
 // chunks per block, plus each split's partial sums written and read back by
 // the reduction (measured on MI355X at about a tenth of a chunk per split for
 // the 192 x 192 x 96 scan).
 void choose_split(mpi3d_plan *pl)
 {
-    const int slots = 256 * 8 / kWaves;
+    const int slots = 256 * 4 / kWaves;
     long tiles = (pl->L + kRowsPerBlock - 1) / kRowsPerBlock;
     int best_s = 1;
     double best = 1e30;
