@@ -198,3 +198,28 @@ def test_device_normalisation_matches_oracle(name, torch_mod):
          % (name, plan.op_scale, plan.norm_iters, g.op_scale, rel))
     assert plan.norm_iters > 0
     assert rel <= 1e-5
+
+
+def test_receive_filter_and_harmonics_from_two(torch_mod):
+    """A receive filter D_Gamma on the kept bins (eq. DCmodel) -- here the
+    response of an inductive receive coil, growing with frequency and with a
+    group delay -- and the paper's harmonic set from 2 (the fundamental notched
+    out): FP32 and mixed operators against the oracle."""
+    from paper_2511_06627_amd.plan import Plan
+    from oracle.geometry import kept_bins
+    nx, ny, nz, M, T = 48, 40, 6, 7, 2048
+    P = T / 256 + 1 / 3
+    base = oracle_geometry(nx, ny, nz, M, T, P, 2.0, 2, 12, 2)
+    om = np.asarray(kept_bins(base), dtype=np.float64)
+    d = (om / om.max()) * np.exp(-2j * np.pi * om * 3.5 / T)
+    g = oop.normalised(oracle_geometry(nx, ny, nz, M, T, P, 2.0, 2, 12, 2, rx_filter=d), iters_min=30, rtol=1e-9)
+    plan = Plan(nx, ny, nz, M, T, P, 2.0, 2, 12, 2, g.op_scale, rx_filter=d, precisions=("fp32", "mixed"))
+    x = random_volume(g, 51)
+    y = random_data(g, 52)
+    for prec, tol in (("fp32", TOL32), ("mixed", 5e-3)):
+        got = plan.forward(_to_dev(torch_mod, x, torch_mod.float32), precision=prec).cpu().numpy()
+        ef = rel_l2(got, oop.forward(g, x))
+        got = plan.adjoint(_to_dev(torch_mod, y, torch_mod.complex64), precision=prec).cpu().numpy()
+        ea = rel_l2(got, oop.adjoint(g, y))
+        _log("receive filter %s: forward rel err %.3e, adjoint rel err %.3e" % (prec, ef, ea))
+        assert ef <= tol and ea <= tol
