@@ -547,6 +547,19 @@ def main():
     t_solve = time.perf_counter() - t0
     log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
 
+    # the paper's own solver (eq. iters): momentum gradient, finite-difference
+    # T, projection onto x >= 0 every iteration, 150 iterations as in its
+    # reconstructions; tau from power iteration on the device
+    plan.solve(b, cfg.lam, iters=2, solver="momentum", reg="fd", clamp_every=1, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, repm_p = plan.solve(b, cfg.lam, iters=150, solver="momentum", reg="fd", clamp_every=1, ws=swk)
+    torch.cuda.synchronize()
+    t_paper = time.perf_counter() - t0
+    paper_solver = {"iters": 150, "reg": "finite differences", "lambda": cfg.lam, "seconds_incl_tau": round(t_paper, 4),
+                    "status": repm_p.status}
+    log("paper solver (momentum, FD, 150 its): %.3f s" % t_paper)
+
     # mixed refinement solve (3 sweeps x 20 inner) against the 60-iteration FP32 solve
     m2 = configs.MIXED_192
     torch.cuda.synchronize()
@@ -609,6 +622,7 @@ def main():
         "cgls": {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
                  "status": rep.status},
         "time_to_solve": tts,
+        "paper_solver": paper_solver,
         "mixed": mixed,
         "serving": serve,
         "hdr": hdr,

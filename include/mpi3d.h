@@ -179,7 +179,23 @@ int mpi3d_signal_adj(const mpi3d_plan *plan, int32_t precision, const float *b_d
  *                     acts on d and its residual, never on r0, so its error
  *                     shrinks with the correction), then sets x += d (and
  *                     clamps at 0 when clamp_every > 0).
+ *
+ * solver MOMENTUM selects the paper's own iteration instead (eq. iters):
+ *   y = x_k + (k-1)/(k+2) (x_k - x_{k-1}),
+ *   x_{k+1} = P(y - tau [A^T (A y - b) + lambda T^T T y]),   k = 1..iters,
+ * P = clamp at 0 when clamp_every > 0 (every iteration), else identity; FP32
+ * operator only.  reg selects T: IDENTITY, or FD -- forward differences along
+ * x, y and z with no term across the volume boundary, so T^T T is the 7-point
+ * Laplacian with reflecting ends (FD is available with MOMENTUM only).
+ * tau > 0 is used as given; tau <= 0 asks for the paper's
+ * tau = 1/(||A^T A||_2 + lambda ||T^T T||_2), with ||A^T A||_2 from power
+ * iteration on the device in the solve workspace (up to 1000 FP32 A^T A
+ * applications, host-synchronised every 10) and ||T^T T||_2 in closed form.
+ * The report's gamma0 / gamma are |x_2 - y_1|^2 and the last step's
+ * |x_{k+1} - y|^2; no history is written.
  */
+enum { MPI3D_SOLVER_CGLS = 0, MPI3D_SOLVER_MOMENTUM = 1 };
+enum { MPI3D_REG_IDENTITY = 0, MPI3D_REG_FD = 1 };
 typedef struct {
     double lambda;          /* Tikhonov weight (>= 0) */
     int32_t iters;          /* FP32: total iterations (>= 0) */
@@ -188,6 +204,9 @@ typedef struct {
     int32_t refine_sweeps;  /* MIXED only: number of sweeps (>= 1) */
     int32_t inner_iters;    /* MIXED only: CGLS iterations per sweep (>= 1) */
     int32_t x0_is_zero;     /* 1: ignore x_dev on entry and start from 0 */
+    int32_t solver;         /* MPI3D_SOLVER_CGLS or MPI3D_SOLVER_MOMENTUM */
+    int32_t reg;            /* MPI3D_REG_IDENTITY or MPI3D_REG_FD (MOMENTUM only) */
+    double tau;             /* MOMENTUM step; <= 0: the paper's 1/(||A^T A|| + lambda ||T^T T||) */
 } mpi3d_solve_opts;
 
 typedef struct {
@@ -217,7 +236,8 @@ int mpi3d_solve(const mpi3d_plan *plan, const float *b_dev, float *x_dev, const 
  * between states whose plans have the same line geometry (n_u, n_t, bins,
  * psf, drive): their FFL lines are concatenated into one launch.  Each
  * line's arithmetic does not depend on which other states share the launch,
- * so a request's result is bitwise the same alone or batched.
+ * so a request's result is bitwise the same alone or batched.  States run CGLS
+ * schedules (solver MOMENTUM is MPI3D_ENOTSUP here).
  */
 typedef struct mpi3d_state mpi3d_state;
 int mpi3d_state_create(const mpi3d_plan *plan, const float *b_dev, float *x_dev,

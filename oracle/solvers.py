@@ -22,7 +22,8 @@ here with T = I.  Norms of complex data are sums of squared moduli.
 * ``momentum_gradient`` -- the paper's own method, eq. iters: fixed step
                        tau = 1/(||A*A|| + lam ||T*T||) with the momentum
                        weight (k-1)/(k+2), projecting onto real nonnegative
-                       values every iteration.
+                       values every iteration; T = I or the finite
+                       differences of ``oracle.regularizer``.
 * ``reference_minimiser`` -- x* = argmin, from CGLS run until
                        |s_k| <= tol |s_0|.
 
@@ -108,21 +109,32 @@ def reference_minimiser(op, b, lam, tol=1e-13, max_iters=5000):
     return x, it
 
 
-def momentum_gradient(op, b, lam, iters, tau, x0=None, nonneg=True):
-    """The paper's iteration (eq. iters) with T = I.
+def momentum_gradient(op, b, lam, iters, tau, x0=None, nonneg=True, reg="identity"):
+    """The paper's iteration (eq. iters).
 
     y^{k+1} = x^k + (k-1)/(k+2) (x^k - x^{k-1})
-    x^{k+1} = P( y^{k+1} - tau [A^*(A y^{k+1} - b) + lam y^{k+1}] )
+    x^{k+1} = P( y^{k+1} - tau [A^*(A y^{k+1} - b) + lam T^*T y^{k+1}] )
     where P keeps the real part (A^T = Re A^H already) and, if ``nonneg``,
     clamps to >= 0.  Iterations are numbered k = 1, 2, ...; x^0 = x^1 = x0.
+    ``reg``: "identity" (T = I) or "fd" (the finite differences of
+    oracle.regularizer).
     """
+    from .regularizer import fd_normal
     x = np.zeros((op.g.nz, op.g.ny, op.g.nx)) if x0 is None else np.array(x0, dtype=np.float64)
     x_prev = x.copy()
     for k in range(1, iters + 1):
         y = x + (k - 1.0) / (k + 2.0) * (x - x_prev)
-        grad = op.adjoint(op.forward(y) - b) + lam * y
+        ty = y if reg == "identity" else fd_normal(y)
+        grad = op.adjoint(op.forward(y) - b) + lam * ty
         x_new = y - tau * grad
         if nonneg:
             x_new = np.maximum(x_new, 0.0)
         x_prev, x = x, x_new
     return x
+
+
+def paper_tau(ata_norm, lam, reg, shape):
+    """tau = 1 / (||A^*A||_2 + lam ||T^*T||_2) (after eq. iters)."""
+    from .regularizer import fd_normal_norm
+    tt = 1.0 if reg == "identity" else fd_normal_norm(shape)
+    return 1.0 / (ata_norm + lam * tt)

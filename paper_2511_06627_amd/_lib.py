@@ -49,6 +49,7 @@ class SolveOpts(ctypes.Structure):
         ("lam", ctypes.c_double),
         ("iters", ctypes.c_int32), ("clamp_every", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("refine_sweeps", ctypes.c_int32), ("inner_iters", ctypes.c_int32), ("x0_is_zero", ctypes.c_int32),
+        ("solver", ctypes.c_int32), ("reg", ctypes.c_int32), ("tau", ctypes.c_double),
     ]
 
 

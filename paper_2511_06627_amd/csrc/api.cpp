@@ -297,39 +297,15 @@ int Cgls::iterate(int prec, hipStream_t st)
     return iter_c(prec, st);
 }
 
-// ||A||_2 of the operator without its global scale, by power iteration on
-// A^T A with the FP32 operator (the scale c_A that makes ||A||_2 = 1,
-// Sec. 3.3).  Start: the constant unit vector.  Each iteration records
-// |A^T A v| (v of unit norm) in float64 on the device; every 10 iterations
-// the host reads the records and stops once the estimate moved by at most
-// 10 * rtol (relative) over the last 10.  The estimate of lambda_max is
-// nondecreasing, so it approaches ||A||^2 from below.
-int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out)
+// ||A||_2 by power iteration on A^T A with the FP32 operator, from the
+// constant unit vector.  Each iteration records |A^T A v| (v of unit norm) in
+// float64 on the device; every 10 iterations the host reads the records and
+// stops once the estimate moved by at most 10 * rtol (relative) over the last
+// 10.  The estimate of lambda_max is nondecreasing, so it approaches ||A||^2
+// from below.
+int power_norm(const mpi3d_plan *pl, const OpWs &w, float *v, float *z, float *y, double *norms, double *parts,
+               double rtol, int max_iters, hipStream_t st, double *norm_out, int *iters_out)
 {
-    const double keep = pl->op_scale;
-    pl->op_scale = 1.0;
-    size_t o = 0;
-    auto put = [&](size_t bytes) { o = (o + 255) & ~(size_t)255; size_t r = o; o += bytes; return r; };
-    const size_t o_ws = put(pl->op_ws_bytes);
-    const size_t o_v = put(sizeof(float) * pl->nvox);
-    const size_t o_z = put(sizeof(float) * pl->nvox);
-    const size_t o_y = put(sizeof(float) * 2 * pl->L * pl->nb);
-    const size_t o_n = put(sizeof(double) * max_iters);
-    const size_t o_p = put(sizeof(double) * pl->max_parts);
-    char *buf = nullptr;
-    if (hipMalloc(&buf, o) != hipSuccess) {
-        pl->op_scale = keep;
-        return MPI3D_ENOMEM;
-    }
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipFree(buf);
-        pl->op_scale = keep;
-        return MPI3D_EDEVICE;
-    }
-    OpWs w = carve_op(pl, buf + o_ws);
-    float *v = (float *)(buf + o_v), *z = (float *)(buf + o_z), *y = (float *)(buf + o_y);
-    double *norms = (double *)(buf + o_n), *parts = (double *)(buf + o_p);
     std::vector<double> host(max_iters);
     int rc = MPI3D_OK, done = 0;
     double est = 0.0;
@@ -360,13 +336,119 @@ int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_ou
             if (k + 1 >= 20 && std::fabs(est - host[k - 10]) <= 10.0 * rtol * est) break;
         }
     }
+    if (rc != MPI3D_OK) return rc;
+    *norm_out = std::sqrt(est);
+    *iters_out = done;
+    return MPI3D_OK;
+}
+
+// ||A||_2 of the operator without its global scale (the c_A that makes
+// ||A||_2 = 1, Sec. 3.3), in a temporary allocation (plan creation only).
+int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out)
+{
+    const double keep = pl->op_scale;
+    pl->op_scale = 1.0;
+    size_t o = 0;
+    auto put = [&](size_t bytes) { o = (o + 255) & ~(size_t)255; size_t r = o; o += bytes; return r; };
+    const size_t o_ws = put(pl->op_ws_bytes);
+    const size_t o_v = put(sizeof(float) * pl->nvox);
+    const size_t o_z = put(sizeof(float) * pl->nvox);
+    const size_t o_y = put(sizeof(float) * 2 * pl->L * pl->nb);
+    const size_t o_n = put(sizeof(double) * max_iters);
+    const size_t o_p = put(sizeof(double) * pl->max_parts);
+    char *buf = nullptr;
+    if (hipMalloc(&buf, o) != hipSuccess) {
+        pl->op_scale = keep;
+        return MPI3D_ENOMEM;
+    }
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(buf);
+        pl->op_scale = keep;
+        return MPI3D_EDEVICE;
+    }
+    const int rc = power_norm(pl, carve_op(pl, buf + o_ws), (float *)(buf + o_v), (float *)(buf + o_z),
+                              (float *)(buf + o_y), (double *)(buf + o_n), (double *)(buf + o_p), rtol, max_iters, st,
+                              norm_out, iters_out);
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
     (void)hipFree(buf);
     pl->op_scale = keep;
-    if (rc != MPI3D_OK) return rc;
-    *norm_out = std::sqrt(est);
-    *iters_out = done;
+    return rc;
+}
+
+// ||T^T T||_2 of the finite differences, closed form: the Kronecker sum of 1D
+// reflecting second differences, whose largest eigenvalue per axis of n
+// points is 2 - 2 cos(pi (n - 1) / n).
+static double fd_normal_norm(const mpi3d_plan *pl)
+{
+    double t = 0.0;
+    for (int n : {pl->nx, pl->ny, pl->nz})
+        if (n > 1) t += 2.0 - 2.0 * std::cos(M_PI * (n - 1) / n);
+    return t;
+}
+
+// The paper's solver (eq. iters): gradient steps of fixed length tau with the
+// momentum weight (k-1)/(k+2), each followed by the projection onto x >= 0.
+// Four volumes rotate: x_k, x_{k-1}, the momentum point y and the gradient
+// g (which the update overwrites with the next y).
+static int momentum_solve(const mpi3d_plan *pl, const float *b, float *x, const mpi3d_solve_opts *o, char *ws,
+                          double *hist, mpi3d_solve_report *report, hipStream_t st)
+{
+    OpWs w = carve_op(pl, ws + pl->sw_op);
+    float *r = (float *)(ws + pl->sw_r);
+    double *scal = (double *)(ws + pl->sw_scal);
+    double *parts = (double *)(ws + pl->sw_parts);
+    float *bufs[3] = {(float *)(ws + pl->sw_s), (float *)(ws + pl->sw_p), (float *)(ws + pl->sw_v)};
+    const double tt = o->reg == MPI3D_REG_FD ? fd_normal_norm(pl) : 1.0;
+    double tau = o->tau;
+    if (!(tau > 0.0)) {
+        // ||A^T A||_2 by power iteration in the workspace (q holds A v)
+        double nrm = 0.0;
+        int its = 0;
+        TRYRC(power_norm(pl, w, bufs[0], bufs[1], (float *)(ws + pl->sw_q), parts + pl->max_parts, parts, 1e-7,
+                         std::min(1000, pl->max_parts), st, &nrm, &its));
+        tau = 1.0 / (nrm * nrm + o->lambda * tt);
+    }
+    TRY(launch_scal_init(scal, st));
+    float *xk = x, *xprev = bufs[0], *y = bufs[1], *g = bufs[2];
+    if (o->x0_is_zero) TRY(launch_fill(x, pl->nvox, 0.f, st));
+    TRY(launch_copy(xprev, x, pl->nvox, st));
+    TRY(launch_copy(y, x, pl->nvox, st));
+    for (int k = 1; k <= o->iters; ++k) {
+        // r = b - A y ; g = A^T r = -(A^T (A y - b))
+        TRYRC(project_into(pl, MPI3D_FP32, y, nullptr, w, st));
+        LineJob jf{pl, w.rt, pl->nup, &w};
+        TRYRC(sig_forward_jobs(MPI3D_FP32, &jf, 1, false, st));
+        TRYRC(reduce_forward(pl, MPI3D_FP32, w, false, r, b, nullptr, nullptr, st));
+        LineJob ja{pl, r, pl->nb2, &w};
+        TRYRC(sig_adjoint_jobs(MPI3D_FP32, &ja, 1, false, st));
+        TRYRC(reduce_adjoint(pl, MPI3D_FP32, w, false, w.rt, pl->nup, st));
+        TRY(launch_backproject(pl, w.rt, g, nullptr, 0.0, nullptr, nullptr, st));
+        // x_{k+1} into x_{k-1}'s buffer, y_{k+1} over g; beta of step k+1
+        const float beta = (float)((double)k / (double)(k + 3));
+        int np = 0;
+        TRY(launch_momentum(y, g, xk, xprev, g, pl->nx, pl->ny, pl->nz, (float)tau, (float)(tau * o->lambda), beta,
+                            o->reg == MPI3D_REG_FD ? 1 : 0, o->clamp_every > 0 ? 1 : 0, parts, &np, st));
+        TRY(launch_step_norm(scal, parts, np, k == 1 ? 1 : 0, st));
+        float *xn = xprev;
+        xprev = xk;
+        xk = xn;
+        float *yn = g;
+        g = y;
+        y = yn;
+    }
+    if (xk != x) TRY(launch_copy(x, xk, pl->nvox, st));
+    if (report) {
+        double sc[16];
+        TRY(hipMemcpyAsync(sc, scal, sizeof(double) * scal_slots(), hipMemcpyDeviceToHost, st));
+        TRY(hipStreamSynchronize(st));
+        report->iters_done = o->iters;
+        report->gamma = sc[scal_slot_gamma()];
+        report->gamma0 = sc[scal_slot_gamma0()];
+        report->status = sc[scal_slot_bad()] != 0.0 ? MPI3D_ENONFINITE : MPI3D_OK;
+    }
+    (void)hist;
     return MPI3D_OK;
 }
 
@@ -379,6 +461,11 @@ int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o)
     if (o->precision == MPI3D_FP32 && o->iters < 0) return MPI3D_EINVAL;
     if (o->precision == MPI3D_MIXED && (o->refine_sweeps < 1 || o->inner_iters < 1)) return MPI3D_EINVAL;
     if (o->precision == MPI3D_MIXED && !(pl->precisions & (1 << MPI3D_FP32))) return MPI3D_EINVAL;
+    if (o->solver != MPI3D_SOLVER_CGLS && o->solver != MPI3D_SOLVER_MOMENTUM) return MPI3D_EINVAL;
+    if (o->reg != MPI3D_REG_IDENTITY && o->reg != MPI3D_REG_FD) return MPI3D_EINVAL;
+    if (o->solver == MPI3D_SOLVER_CGLS && o->reg != MPI3D_REG_IDENTITY) return MPI3D_ENOTSUP;
+    if (o->solver == MPI3D_SOLVER_MOMENTUM && o->precision != MPI3D_FP32) return MPI3D_ENOTSUP;
+    if (!std::isfinite(o->tau)) return MPI3D_EINVAL;
     return MPI3D_OK;
 }
 
@@ -460,6 +547,7 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
     TRYRC(ws_ok(ws, ws_bytes, pl->solve_ws_bytes));
     DeviceGuard dg(pl->device);
     hipStream_t st = (hipStream_t)stream;
+    if (o->solver == MPI3D_SOLVER_MOMENTUM) return momentum_solve(pl, b, x, o, (char *)ws, hist, report, st);
     Cgls cg;
     cg.init(pl, b, x, ws, o->lambda, hist);
     if (o->precision == MPI3D_MIXED) {

@@ -113,7 +113,7 @@ struct mpi3d_plan {
     // operator workspace layout (bytes from ws base)
     size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, op_ws_bytes;
     // solver workspace layout
-    size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, solve_ws_bytes;
+    size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, sw_v, solve_ws_bytes;
 };
 
 namespace mpi3d {
@@ -160,6 +160,10 @@ hipError_t launch_copy(float *dst, const float *src, long n, hipStream_t st);
 hipError_t launch_norm_record(const double *parts, int n, double *norms, int k, hipStream_t st);
 hipError_t launch_scale_by(float *v, const float *z, long n, const double *norms, int k, hipStream_t st);
 hipError_t launch_add_to(float *x, const float *d, long n, int clamp, hipStream_t st);
+hipError_t launch_momentum(const float *y, const float *g, const float *x, float *x_new, float *y_new, int nx,
+                           int ny, int nz, float tau, float taulam, float beta, int fd, int nonneg, double *parts,
+                           int *nparts, hipStream_t st);
+hipError_t launch_step_norm(double *scal, const double *parts, int n, int first, hipStream_t st);
 
 // Strided projection launchers (public stage entry points use stride n_u).
 hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st);
@@ -236,5 +240,10 @@ struct Cgls {
 };
 int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o);
 int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out);
+// ||A||_2 with the plan's current scale, by power iteration in caller buffers:
+// v, z volumes, y data, norms (max_iters doubles), parts (max_parts doubles),
+// w an operator workspace.
+int power_norm(const mpi3d_plan *pl, const OpWs &w, float *v, float *z, float *y, double *norms, double *parts,
+               double rtol, int max_iters, hipStream_t st, double *norm_out, int *iters_out);
 
 }  // namespace mpi3d

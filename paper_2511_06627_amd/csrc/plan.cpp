@@ -492,6 +492,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->sw_parts = put(sizeof(double) * 3 * pl->max_parts);
         pl->sw_d = put(mixed ? sizeof(float) * pl->nvox : 0);   // refinement correction
         pl->sw_g = put(mixed ? sizeof(float) * pl->nvox : 0);   // FP32 gradient at the sweep start
+        pl->sw_v = put(sizeof(float) * pl->nvox);                 // momentum solver: fourth volume
         pl->solve_ws_bytes = align256(o);
     }
     {

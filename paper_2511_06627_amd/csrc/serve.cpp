@@ -98,6 +98,7 @@ extern "C" int mpi3d_state_create(const mpi3d_plan *pl, const float *b, float *x
     *out = nullptr;
     if (!pl || !b || !x || !ws) return MPI3D_EINVAL;
     TRYRC(validate_opts(pl, o));
+    if (o->solver != MPI3D_SOLVER_CGLS) return MPI3D_ENOTSUP;   // states step CGLS schedules
     if ((uintptr_t)ws & 255) return MPI3D_EINVAL;
     if (ws_bytes < pl->solve_ws_bytes) return MPI3D_ENOMEM;
     mpi3d_state *s = new (std::nothrow) mpi3d_state();

@@ -253,6 +253,63 @@ __global__ __launch_bounds__(kThreads) void copy_kernel(float *dst, const float 
         dst[idx] = src[idx];
 }
 
+// One step of the paper's iteration (eq. iters) after g = A^T (b - A y):
+//   x_new = P(y + tau g - tau lambda T^T T y),  P = clamp at 0 when nonneg
+//   y_new = x_new + beta (x_new - x)            (the next momentum point)
+// T^T T y is the 7-point finite-difference Laplacian with no term across the
+// volume boundary (fd = 1) or y itself (fd = 0).  y_new may alias g: every
+// thread reads g only at its own voxel before writing y_new there.  A block
+// partial of |x_new - y|^2 (the step) goes to parts.
+__global__ __launch_bounds__(kThreads) void momentum_kernel(const float *__restrict__ y, const float *g,
+                                                             const float *__restrict__ x, float *__restrict__ x_new,
+                                                             float *y_new, int nx, int ny, int nz, float tau,
+                                                             float taulam, float beta, int fd, int nonneg,
+                                                             double *parts)
+{
+    __shared__ double red[kThreads / 64];
+    const long n = (long)nx * ny * nz;
+    const long sxy = (long)nx * ny;
+    double sq = 0.0;
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        const float yc = y[idx];
+        float ty = yc;
+        if (fd) {
+            const int i = (int)(idx % nx);
+            const int j = (int)((idx / nx) % ny);
+            const int k = (int)(idx / sxy);
+            float acc = 0.f;
+            if (i > 0) acc += yc - y[idx - 1];
+            if (i + 1 < nx) acc += yc - y[idx + 1];
+            if (j > 0) acc += yc - y[idx - nx];
+            if (j + 1 < ny) acc += yc - y[idx + nx];
+            if (k > 0) acc += yc - y[idx - sxy];
+            if (k + 1 < nz) acc += yc - y[idx + sxy];
+            ty = acc;
+        }
+        float v = fmaf(tau, g[idx], fmaf(-taulam, ty, yc));
+        if (nonneg) v = fmaxf(v, 0.f);
+        const float xo = x[idx];
+        x_new[idx] = v;
+        y_new[idx] = fmaf(beta, v - xo, v);
+        const double dv = (double)v - (double)yc;
+        sq += dv * dv;
+    }
+    const double t = block_sum(sq, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = t;
+}
+
+// scal[S_GAMMA] = sum of the step partials (and S_GAMMA0 on the first step)
+__global__ __launch_bounds__(kThreads) void step_norm_kernel(double *scal, const double *parts, int n, int first)
+{
+    __shared__ double red[kThreads / 64];
+    const double t = sum_parts(parts, n, red);
+    if (threadIdx.x == 0) {
+        scal[S_GAMMA] = t;
+        if (first) scal[S_GAMMA0] = t;
+        if (!isfinite(t)) scal[S_BAD] = 1.0;
+    }
+}
+
 // Power iteration on A^T A: norms[k] = |z| from the partials of |z|^2.
 __global__ __launch_bounds__(kThreads) void norm_record_kernel(const double *parts, int n, double *norms, int k)
 {
@@ -389,6 +446,24 @@ hipError_t launch_copy(float *dst, const float *src, long n, hipStream_t st)
 hipError_t launch_add_to(float *x, const float *d, long n, int clamp, hipStream_t st)
 {
     hipLaunchKernelGGL(add_to_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, x, d, n, clamp);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum(const float *y, const float *g, const float *x, float *x_new, float *y_new, int nx,
+                           int ny, int nz, float tau, float taulam, float beta, int fd, int nonneg, double *parts,
+                           int *nparts, hipStream_t st)
+{
+    const long n = (long)nx * ny * nz;
+    const int b = grid_for(n);
+    if (nparts) *nparts = b;
+    hipLaunchKernelGGL(momentum_kernel, dim3(b), dim3(kThreads), 0, st, y, g, x, x_new, y_new, nx, ny, nz, tau,
+                       taulam, beta, fd, nonneg, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_norm(double *scal, const double *parts, int n, int first, hipStream_t st)
+{
+    hipLaunchKernelGGL(step_norm_kernel, dim3(1), dim3(kThreads), 0, st, scal, parts, n, first);
     return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ from . import _lib
 from ._lib import MPI3D_FP32, MPI3D_MIXED, check
 
 PRECISION = {"fp32": MPI3D_FP32, "mixed": MPI3D_MIXED}
+SOLVER = {"cgls": 0, "momentum": 1}
+REG = {"identity": 0, "fd": 1}
 
 
 def _ptr(t):
@@ -168,8 +170,9 @@ class Plan:
 
     # ---- solve ---------------------------------------------------------------
     def solve(self, b, lam, iters=0, x=None, precision="fp32", clamp_every=0, refine_sweeps=0, inner_iters=0,
-              ws=None, history=None, report=True, stream=None):
-        """CGLS on min |Ax - b|^2 + lam |x|^2.  Returns (x, report or None)."""
+              solver="cgls", reg="identity", tau=0.0, ws=None, history=None, report=True, stream=None):
+        """min |Ax - b|^2 + lam |T x|^2 by CGLS (T = I) or the paper's momentum
+        iteration (T = I or finite differences).  Returns (x, report or None)."""
         self._check_data(b)
         x0_zero = x is None
         if x is None:
@@ -181,6 +184,7 @@ class Plan:
         o.precision = PRECISION[precision]
         o.refine_sweeps, o.inner_iters = refine_sweeps, inner_iters
         o.x0_is_zero = 1 if x0_zero else 0
+        o.solver, o.reg, o.tau = SOLVER[solver], REG[reg], tau
         rep = _lib.SolveReport() if report else None
         hptr = _ptr(history) if history is not None else ctypes.c_void_p()
         check("mpi3d_solve", _lib.load().mpi3d_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), _ptr(ws), ws.numel(),

@@ -97,3 +97,25 @@ def test_momentum_gradient_projection_keeps_nonnegative(problem):
     g, op, A, b, lam, xs = problem
     x = solvers.momentum_gradient(op, b, lam, 50, 1.0 / (1.0 + lam), nonneg=True)
     assert x.min() >= 0.0
+
+
+def test_momentum_gradient_with_finite_differences(problem):
+    """With T the finite differences of oracle.regularizer the paper's iteration
+    heads to the minimiser of ||Ax-b||^2 + lam ||Tx||^2, written out densely."""
+    from oracle import regularizer
+    g, op, A, b, lam, _ = problem
+    n = g.n_vox
+    cols = []
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        cols.append(regularizer.fd_normal(e.reshape(g.nz, g.ny, g.nx)).ravel())
+    TT = np.stack(cols, axis=1)
+    lam_fd = 1e-2
+    N = np.real(np.conj(A).T @ A) + lam_fd * TT
+    xs = np.linalg.solve(N, np.real(np.conj(A).T @ b.ravel())).reshape(g.nz, g.ny, g.nx)
+    tau = solvers.paper_tau(1.0, lam_fd, "fd", (g.nz, g.ny, g.nx))
+    assert tau == 1.0 / (1.0 + lam_fd * regularizer.fd_normal_norm((g.nz, g.ny, g.nx)))
+    e = [np.linalg.norm(solvers.momentum_gradient(op, b, lam_fd, k, tau, nonneg=False, reg="fd") - xs)
+         / np.linalg.norm(xs) for k in (200, 2000)]
+    assert e[1] <= 1e-3 and e[1] < 0.2 * e[0], e
