@@ -537,6 +537,32 @@ def main():
         mixed[k] = {"ms": round(v, 4), "tflops": round(a16, 1), "mfma_frac_fp16": round(a16 / FP16_PEAK_TFLOPS, 4)}
     log("mixed A^T A: %.3f ms/step; kernels %s" % (1e3 * dt16 / args.steps, kt16))
 
+    # the precomposed-line operator (same map, signal stage as two float32
+    # GEMMs with G = F^T K): A^T A rate and the GEMM times
+    planp = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"))
+    wsp = planp.workspace("op")
+
+    def stepp():
+        planp.forward(x, precision="precomposed", out=yb, ws=wsp)
+        planp.adjoint(yb, precision="precomposed", out=xo, ws=wsp)
+
+    for _ in range(args.warmup):
+        stepp()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stepp()
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t0
+    gemm_flops = 2.0 * cfg.n_lines * cfg.n_u * 2 * cfg.n_bins
+    ktp = {k: planp.time_kernel(k, repeats=10, precision="precomposed", x=x, b=b, ws=wsp)
+           for k in ("signal_fwd", "signal_adj")}
+    precomposed = {"applies_per_s": round(args.steps / dtp, 2), "ms_per_step": round(1e3 * dtp / args.steps, 4),
+                   "gemm_flops": gemm_flops,
+                   "gemm_fwd_ms": round(ktp["signal_fwd"], 4), "gemm_adj_ms": round(ktp["signal_adj"], 4)}
+    log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * dtp / args.steps, ktp))
+    del planp, wsp
+
     # CGLS iteration rate of the configured 50-iteration solve
     swk = plan.workspace("solve")
     plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
@@ -624,6 +650,7 @@ def main():
         "time_to_solve": tts,
         "paper_solver": paper_solver,
         "mixed": mixed,
+        "precomposed": precomposed,
         "serving": serve,
         "hdr": hdr,
         "oracle_small": cpu.get("oracle_small") if cpu is not None else None,

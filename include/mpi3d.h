@@ -70,8 +70,17 @@ enum {
 /* Operator precision.  FP32: projection in fp32, signal contractions on fp32
  * MFMA.  MIXED: projection gathers read bf16 copies of the volume and of the
  * line data, the signal contractions run on fp16 MFMA with fp32 accumulation,
- * per-line power-of-two scaling and per-harmonic-band scaling. */
-enum { MPI3D_FP32 = 0, MPI3D_MIXED = 1 };
+ * per-line power-of-two scaling and per-harmonic-band scaling.  PRECOMPOSED:
+ * every FFL line shares one trajectory, so A_DC = S D_Gamma F V E H B is one
+ * real 2n_bins x n_u matrix G; the plan forms G = F^T K once in float64 on the
+ * host, and the signal stage becomes a float32 library GEMM (rocBLAS) of the
+ * projections with G (or its transpose) -- the same operator without forming
+ * time signals, about (n_t (n_u + 2 n_bins)) / (2 n_bins n_u) times fewer
+ * flops.  PRECOMPOSED serves mpi3d_forward, mpi3d_adjoint, mpi3d_signal_* and
+ * mpi3d_time_kernel; mpi3d_solve and serving states reject it
+ * (MPI3D_ENOTSUP).  Calls with PRECOMPOSED on one plan must not run
+ * concurrently from several host threads (they share the plan's GEMM handle). */
+enum { MPI3D_FP32 = 0, MPI3D_MIXED = 1, MPI3D_PRECOMPOSED = 2 };
 
 /*
  * Scan geometry and physics (copied at plan creation).
@@ -105,8 +114,9 @@ typedef struct {
                                     from the constant vector, until the estimate of ||A||^2
                                     moves by at most 1e-6 (relative) over 10 iterations,
                                     at most 1000 iterations */
-    int32_t precisions;          /* bit mask of (1 << MPI3D_FP32) | (1 << MPI3D_MIXED):
-                                    which operator variants get tables; 0 = FP32 only */
+    int32_t precisions;          /* bit mask of (1 << MPI3D_FP32) | (1 << MPI3D_MIXED) |
+                                    (1 << MPI3D_PRECOMPOSED): which operator variants get
+                                    tables; 0 = FP32 only */
 } mpi3d_geometry;
 
 typedef struct mpi3d_plan mpi3d_plan;

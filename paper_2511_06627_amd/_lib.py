@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libmpi3d.so")
 
 MPI3D_FP32 = 0
 MPI3D_MIXED = 1
+MPI3D_PRECOMPOSED = 2
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSUP", -5: "ENONFINITE"}
 

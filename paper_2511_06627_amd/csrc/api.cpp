@@ -71,7 +71,7 @@ OpWs carve_op(const mpi3d_plan *pl, void *ws)
 
 int check_prec(const mpi3d_plan *pl, int32_t precision)
 {
-    if (precision != MPI3D_FP32 && precision != MPI3D_MIXED) return MPI3D_EINVAL;
+    if (precision != MPI3D_FP32 && precision != MPI3D_MIXED && precision != MPI3D_PRECOMPOSED) return MPI3D_EINVAL;
     if (!(pl->precisions & (1 << precision))) return MPI3D_EINVAL;
     return MPI3D_OK;
 }
@@ -171,8 +171,38 @@ static int project_into(const mpi3d_plan *pl, int prec, const float *x, const ui
     return MPI3D_OK;
 }
 
+// Precomposed signal stage: data[L][2nb] = c_A * lines[L][ld_in] G^T, or
+// lines[L][ld_out] = c_A * data[L][2nb] G (plain float32 GEMMs).
+static int gemm_signal_fwd(const mpi3d_plan *pl, const float *lines, int ld_in, float *data, hipStream_t st)
+{
+    if (!pl->blas) return MPI3D_EINVAL;
+    const float alpha = (float)pl->op_scale, beta = 0.f;
+    if (rocblas_set_stream(pl->blas, st) != rocblas_status_success) return MPI3D_EDEVICE;
+    // column-major: data^T (2nb x L) = Gt (2nb x n_u, ld 2nb) * lines^T (n_u x L, ld ld_in)
+    if (rocblas_sgemm(pl->blas, rocblas_operation_none, rocblas_operation_none, pl->nb2, (int)pl->L, pl->nu, &alpha,
+                      pl->gt, pl->nb2, lines, ld_in, &beta, data, pl->nb2) != rocblas_status_success)
+        return MPI3D_EDEVICE;
+    return MPI3D_OK;
+}
+
+static int gemm_signal_adj(const mpi3d_plan *pl, const float *data, float *lines, int ld_out, hipStream_t st)
+{
+    if (!pl->blas) return MPI3D_EINVAL;
+    const float alpha = (float)pl->op_scale, beta = 0.f;
+    if (rocblas_set_stream(pl->blas, st) != rocblas_status_success) return MPI3D_EDEVICE;
+    // column-major: lines^T (n_u x L) = Gt^T (n_u x 2nb) * data^T (2nb x L)
+    if (rocblas_sgemm(pl->blas, rocblas_operation_transpose, rocblas_operation_none, pl->nu, (int)pl->L, pl->nb2,
+                      &alpha, pl->gt, pl->nb2, data, pl->nb2, &beta, lines, ld_out) != rocblas_status_success)
+        return MPI3D_EDEVICE;
+    return MPI3D_OK;
+}
+
 static int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *out, const OpWs &w, hipStream_t st)
 {
+    if (prec == MPI3D_PRECOMPOSED) {
+        TRY(launch_project(pl, x, nullptr, w.rt, st));
+        return gemm_signal_fwd(pl, w.rt, pl->nup, out, st);
+    }
     TRYRC(project_into(pl, prec, x, nullptr, w, st));
     LineJob j{pl, w.rt, pl->nup, &w};
     TRYRC(sig_forward_jobs(prec, &j, 1, false, st));
@@ -181,6 +211,13 @@ static int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *
 
 static int apply_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *xo, const OpWs &w, hipStream_t st)
 {
+    if (prec == MPI3D_PRECOMPOSED) {
+        // the pad columns n_u..n_up of the lines stay as the projection left them (zero)
+        TRY(launch_fill(w.rt, pl->L * pl->nup, 0.f, st));
+        TRYRC(gemm_signal_adj(pl, y, w.rt, pl->nup, st));
+        TRY(launch_backproject(pl, w.rt, xo, nullptr, 0.0, nullptr, nullptr, st));
+        return MPI3D_OK;
+    }
     LineJob j{pl, y, pl->nb2, &w};
     TRYRC(sig_adjoint_jobs(prec, &j, 1, false, st));
     TRYRC(reduce_adjoint(pl, prec, w, false, w.rt, pl->nup, st));
@@ -461,6 +498,7 @@ int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o)
     if (o->precision == MPI3D_FP32 && o->iters < 0) return MPI3D_EINVAL;
     if (o->precision == MPI3D_MIXED && (o->refine_sweeps < 1 || o->inner_iters < 1)) return MPI3D_EINVAL;
     if (o->precision == MPI3D_MIXED && !(pl->precisions & (1 << MPI3D_FP32))) return MPI3D_EINVAL;
+    if (o->precision == MPI3D_PRECOMPOSED) return MPI3D_ENOTSUP;
     if (o->solver != MPI3D_SOLVER_CGLS && o->solver != MPI3D_SOLVER_MOMENTUM) return MPI3D_EINVAL;
     if (o->reg != MPI3D_REG_IDENTITY && o->reg != MPI3D_REG_FD) return MPI3D_EINVAL;
     if (o->solver == MPI3D_SOLVER_CGLS && o->reg != MPI3D_REG_IDENTITY) return MPI3D_ENOTSUP;
@@ -517,6 +555,7 @@ extern "C" int mpi3d_signal_fwd(const mpi3d_plan *pl, int32_t precision, const f
     TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
     hipStream_t st = (hipStream_t)stream;
+    if (precision == MPI3D_PRECOMPOSED) return gemm_signal_fwd(pl, rho, pl->nu, b, st);
     OpWs w = carve_op(pl, ws);
     LineJob j{pl, rho, pl->nu, &w};
     TRYRC(sig_forward_jobs(precision, &j, 1, false, st));
@@ -531,6 +570,7 @@ extern "C" int mpi3d_signal_adj(const mpi3d_plan *pl, int32_t precision, const f
     TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
     hipStream_t st = (hipStream_t)stream;
+    if (precision == MPI3D_PRECOMPOSED) return gemm_signal_adj(pl, b, rho, pl->nu, st);
     OpWs w = carve_op(pl, ws);
     LineJob j{pl, b, pl->nb2, &w};
     TRYRC(sig_adjoint_jobs(precision, &j, 1, false, st));
@@ -626,8 +666,18 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         case 0: err = mixed ? launch_project(pl, nullptr, w.xb, w.rt, st) : launch_project(pl, x, nullptr, w.rt, st);
             break;
         case 1: err = launch_backproject(pl, w.rt, x, nullptr, 0.0, nullptr, nullptr, st); break;
-        case 2: err = launch_sig_fwd(pl, precision, a, st); break;
-        default: err = launch_sig_adj(pl, precision, a, st); break;
+        case 2:
+            if (precision == MPI3D_PRECOMPOSED)
+                err = gemm_signal_fwd(pl, w.rt, pl->nup, w.part, st) == MPI3D_OK ? hipSuccess : hipErrorUnknown;
+            else
+                err = launch_sig_fwd(pl, precision, a, st);
+            break;
+        default:
+            if (precision == MPI3D_PRECOMPOSED)
+                err = gemm_signal_adj(pl, b, w.rt, pl->nup, st) == MPI3D_OK ? hipSuccess : hipErrorUnknown;
+            else
+                err = launch_sig_adj(pl, precision, a, st);
+            break;
         }
     }
     if (err == hipSuccess) err = hipEventRecord(e1, st);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
+#include <rocblas/rocblas.h>
 #include <cstddef>
 #include <cstdint>
 
@@ -110,6 +111,8 @@ struct mpi3d_plan {
     float *col_scale;     // [nbp2] mixed forward output scale per column
     float *band_scale;    // [nbp2] mixed adjoint input scale per column
     float adj_scale16;    // mixed adjoint output scale
+    float *gt = nullptr;  // precomposed: [n_up][2 nb] line matrix G^T (row-major)
+    rocblas_handle blas = nullptr;   // precomposed: GEMM handle
     // operator workspace layout (bytes from ws base)
     size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, op_ws_bytes;
     // solver workspace layout

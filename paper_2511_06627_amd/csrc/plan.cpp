@@ -131,7 +131,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (!(g->drive_amp >= 0)) return MPI3D_EINVAL;
     if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
     int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
-    if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED))) return MPI3D_EINVAL;
+    if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED) | (1 << MPI3D_PRECOMPOSED))) return MPI3D_EINVAL;
 
     // kept bins, validated
     std::vector<long> bins;
@@ -288,6 +288,25 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         }
     }
 
+    // precomposed line matrix Gt[p][c] = sum_n K[n][p] F[n][c] (the whole
+    // A_DC of one line, c_A aside), float64 accumulation
+    const bool precomp = precisions & (1 << MPI3D_PRECOMPOSED);
+    std::vector<float> gt;
+    if (precomp) {
+        const int NB2 = 2 * NB;
+        std::vector<double> acc((size_t)NUP * NB2, 0.0);
+        for (int n = 0; n < T; ++n) {
+            const double *fr = &F[(size_t)n * NBP2];
+            for (int p = 0; p < NU; ++p) {
+                const double k = K[(size_t)n * NUP + p];
+                double *row = &acc[(size_t)p * NB2];
+                for (int c = 0; c < NB2; ++c) row[c] += k * fr[c];
+            }
+        }
+        gt.resize(acc.size());
+        for (size_t i = 0; i < acc.size(); ++i) gt[i] = (float)acc[i];
+    }
+
     // ---- table layout in one device allocation -----------------------------
     bool mixed = precisions & (1 << MPI3D_MIXED);
     size_t off = 0;
@@ -301,6 +320,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     o_ff = place(sizeof(float) * (size_t)TP * NBP2);
     o_fa = place(sizeof(float) * (size_t)TP * NBP2);
     o_ka = place(sizeof(float) * (size_t)TP * NUP);
+    const size_t o_gt = precomp ? place(sizeof(float) * gt.size()) : 0;
     if (mixed) {
         o_kf16 = place(sizeof(__half) * (size_t)TP * NUP);
         o_ff16 = place(sizeof(__half) * (size_t)TP * NBP2);
@@ -446,6 +466,11 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     ok = ok && hipMemcpy(pl->ff, ff.data(), sizeof(float) * ff.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(pl->fa, fa.data(), sizeof(float) * fa.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(pl->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (precomp) {
+        pl->gt = (float *)(tb + o_gt);
+        ok = ok && hipMemcpy(pl->gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && rocblas_create_handle(&pl->blas) == rocblas_status_success;
+    }
     if (mixed) {
         pl->kf16 = (__half *)(tb + o_kf16);
         pl->ff16 = (__half *)(tb + o_ff16);
@@ -461,6 +486,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         ok = ok && hipMemcpy(pl->band_scale, band_scale.data(), sizeof(float) * NBP2, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
+        if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
         (void)hipFree(pl->tables);
         delete pl;
         return MPI3D_EDEVICE;
@@ -517,6 +543,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         int its = 0;
         const int rc = estimate_op_norm(pl, 1e-7, 1000, &nrm, &its);
         if (rc != MPI3D_OK) {
+            if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
             (void)hipFree(pl->tables);
             delete pl;
             return rc;
@@ -534,6 +561,7 @@ extern "C" void mpi3d_plan_destroy(mpi3d_plan *pl)
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(pl->device);
+    if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
     (void)hipFree(pl->tables);
     (void)hipSetDevice(prev);
     delete pl;

@@ -12,9 +12,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import MPI3D_FP32, MPI3D_MIXED, check
+from ._lib import MPI3D_FP32, MPI3D_MIXED, MPI3D_PRECOMPOSED, check
 
-PRECISION = {"fp32": MPI3D_FP32, "mixed": MPI3D_MIXED}
+PRECISION = {"fp32": MPI3D_FP32, "mixed": MPI3D_MIXED, "precomposed": MPI3D_PRECOMPOSED}
 SOLVER = {"cgls": 0, "momentum": 1}
 REG = {"identity": 0, "fd": 1}
 

@@ -25,6 +25,8 @@ CASES = {
     "ragged": (40, 36, 5, 7, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1),
     # several line tiles with a ragged last one, 7 column tiles, non-square slice
     "multi_tile": (64, 48, 20, 9, 4096, 4096 / 256 + 1 / 3, 3.0, 1, 20, 2),
+    # n_u = 128 (the remaining compiled detector width) with 13 harmonics
+    "mid_128": (128, 96, 4, 5, 2048, 2048 / 256 + 1 / 3, 2.5, 1, 13, 2),
     # a slice too large for LDS (staged in two row bands), with the 90 degree
     # angle whose central rays run exactly along the band edge
     "banded": (220, 220, 3, 6, 1024, 1024 / 256 + 1 / 3, 2.0, 1, 7, 1),
@@ -223,3 +225,25 @@ def test_receive_filter_and_harmonics_from_two(torch_mod):
         ea = rel_l2(got, oop.adjoint(g, y))
         _log("receive filter %s: forward rel err %.3e, adjoint rel err %.3e" % (prec, ef, ea))
         assert ef <= tol and ea <= tol
+
+
+@pytest.mark.parametrize("name", ["parity_32", "ragged", "mid_128"])
+def test_precomposed_operator(name, torch_mod):
+    """The precomposed-line operator (G = F^T K formed once per plan, the signal
+    stage as float32 GEMMs) is the same linear map: A, A^T and the signal stages
+    against the oracle's time-domain definition."""
+    from paper_2511_06627_amd.plan import Plan
+    nx, ny, nz, M, T, P, w, klo, khi, D = CASES[name]
+    g = oop.normalised(oracle_geometry(nx, ny, nz, M, T, P, w, klo, khi, D), iters_min=30, rtol=1e-9)
+    plan = Plan(nx, ny, nz, M, T, P, w, klo, khi, D, g.op_scale, precisions=("fp32", "precomposed"))
+    x = random_volume(g, 61)
+    y = random_data(g, 62)
+    got = plan.forward(_to_dev(torch_mod, x, torch_mod.float32), precision="precomposed").cpu().numpy()
+    ef = rel_l2(got, oop.forward(g, x))
+    got = plan.adjoint(_to_dev(torch_mod, y, torch_mod.complex64), precision="precomposed").cpu().numpy()
+    ea = rel_l2(got, oop.adjoint(g, y))
+    rho = oproj.project(g, x)
+    got = plan.signal_fwd(_to_dev(torch_mod, rho, torch_mod.float32), precision="precomposed").cpu().numpy()
+    es = rel_l2(got, osig.forward(g, rho.reshape(-1, g.n_u)).reshape(g.n_angles, g.nz, g.n_bins))
+    _log("%s precomposed: forward %.3e adjoint %.3e signal %.3e" % (name, ef, ea, es))
+    assert ef <= TOL32 and ea <= TOL32 and es <= TOL32
