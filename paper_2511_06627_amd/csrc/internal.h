@@ -29,6 +29,10 @@ constexpr int kMaxJobs = 16;
 // Norm partial slots: every kernel that emits float64 partial sums writes at
 // most this many, one per block.
 constexpr int kMaxNormParts = 4096;
+constexpr int kFwdThreads = 1024;                     // forward projection block
+// Rays a forward-projection thread owns: 4 with one slice per texel, 2 with
+// two (twice the accumulators and LDS operands per sample).
+constexpr int fwd_rays_per_thread(int slices) { return slices == 1 ? 4 : 2; }
 
 // One batch segment of FFL lines sharing the same line tables.
 struct SigJob {
@@ -56,9 +60,12 @@ struct SigArgs {
 // ---------------------------------------------------------------------------
 // Projection argument block.
 // ---------------------------------------------------------------------------
+// Forward projection launch: slices per staged texel, row bands, blocks.
+struct FwdConfig {
+    int slices, band_rows, n_bands, blocks;
+};
+
 struct ProjArgs {
-    const float *x;             // volume [nz][ny][nx]
-    const uint16_t *xb;         // mixed: bf16 bits of the volume (or null)
     float *rt;                  // projections [M][nz][nup]
     const float *rt_in;         // adjoint input projections [M][nz][nup]
     float *xo;                  // adjoint output volume
@@ -99,7 +106,8 @@ struct mpi3d_plan {
     int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
     uint64_t line_key;             // equal keys <=> identical line tables
     // projection configuration
-    int fwd_blocks, band_rows, n_bands, kz, adj_chunk;
+    mpi3d::FwdConfig fwd32, fwd16;  // forward projection, fp32 and bf16 gathers
+    int kz, adj_chunk;
     int max_parts;                 // float64 norm partials a launch may write (>= kMaxNormParts)
     // device tables (one allocation)
     void *tables;

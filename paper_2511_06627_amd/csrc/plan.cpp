@@ -199,23 +199,34 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
 
     // projection configuration
     {
-        const size_t lds = 160 * 1024;
-        size_t row_bytes = (size_t)(pl->nx + 2) * sizeof(float);
-        int max_rows = (int)(lds / row_bytes) - 1;  // LDS rows = band_rows + 1
-        if (max_rows < 2) { delete pl; return MPI3D_ENOTSUP; }
-        int bases = pl->ny + 1;                     // base rows -1 .. ny-1
-        pl->n_bands = (bases + max_rows - 1) / max_rows;
-        pl->band_rows = (bases + pl->n_bands - 1) / pl->n_bands;
-        // Forward: the nz * M (slice, angle) units are split into equal
-        // contiguous ranges, one per block (1024 threads, one slice in LDS, at
-        // most 4 rays per thread), in whole rounds of 256 blocks.
-        {
-            const long units = (long)pl->nz * pl->M;
-            const long umax = std::max<long>(1, 4096 / pl->nu);
+        // Forward: a staged texel holds one or two slices (4 bytes: one fp32
+        // slice or two bf16 slices; 8 bytes: two fp32 slices); a slice group
+        // too large for 160 KB of LDS is staged in row bands (LDS rows =
+        // band_rows + 1).  The fp32 path takes slice pairs only when a pair
+        // fits in one band, since a band edge splits a wave's rays unevenly.
+        // The ceil(nz / slices) * M (slice group, angle) units are split into
+        // equal contiguous ranges, one per block (a block holds kFwdThreads *
+        // fwd_rays_per_thread rays, nu per unit), in whole rounds of 256
+        // blocks.
+        auto fwd_config = [&](int slices, int texel_bytes, mpi3d::FwdConfig &fc) {
+            const size_t lds = 160 * 1024;
+            const int bases = pl->ny + 1;           // base rows -1 .. ny-1
+            const int max_rows = (int)(lds / ((size_t)(pl->nx + 2) * texel_bytes)) - 1;
+            if (max_rows < 2) return false;
+            fc.slices = slices;
+            fc.n_bands = (bases + max_rows - 1) / max_rows;
+            fc.band_rows = (bases + fc.n_bands - 1) / fc.n_bands;
+            const long units = (long)((pl->nz + slices - 1) / slices) * pl->M;
+            const long umax = std::max<long>(1, kFwdThreads * fwd_rays_per_thread(slices) / pl->nu);
             long nb = (units + umax - 1) / umax;
             nb = ((nb + 255) / 256) * 256;
-            pl->fwd_blocks = (int)std::min(nb, units);
+            fc.blocks = (int)std::min(nb, units);
+            return true;
+        };
+        if (!fwd_config(2, 8, pl->fwd32) || pl->fwd32.n_bands > 1) {
+            if (!fwd_config(1, 4, pl->fwd32)) { delete pl; return MPI3D_ENOTSUP; }
         }
+        if (!fwd_config(2, 4, pl->fwd16)) { delete pl; return MPI3D_ENOTSUP; }
         // Backprojection: 16 x 16 voxel tiles times kz slices per block.  The
         // ray weights are formed once per voxel and angle and reused over kz
         // slices, so take the largest kz that still gives about three blocks

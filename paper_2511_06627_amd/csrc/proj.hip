@@ -41,35 +41,116 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
     return xcd * per + min(xcd, rem) + slot;
 }
 
-constexpr int kFwdThreads = 1024;
-constexpr int kMaxRaysPerThread = 4;
-
-// Staged slice element (LDS column col = grid column col - 1):
-//  fp32 path: the voxel value;
-//  bf16 path (the mixed operator's gathers): a pair-packed word, low half the
-//  bf16 voxel and high half its right neighbour, so the two horizontal
-//  neighbours of a bilinear sample arrive in one 32-bit LDS read.
-__device__ __forceinline__ void corners(const float *l0, int W, float &v00, float &v10, float &v01, float &v11)
-{
-    v00 = l0[0];
-    v10 = l0[1];
-    v01 = l0[W];
-    v11 = l0[W + 1];
-}
-__device__ __forceinline__ void corners(const uint32_t *l0, int W, float &v00, float &v10, float &v01, float &v11)
-{
-    const uint32_t a = l0[0], b = l0[W];
-    v00 = __uint_as_float(a << 16);
-    v10 = __uint_as_float(a & 0xffff0000u);
-    v01 = __uint_as_float(b << 16);
-    v11 = __uint_as_float(b & 0xffff0000u);
-}
-
-// One bilinear sample of the staged band.  Branch-free: a sample whose 2x2
-// footprint lies outside the band reads a safe LDS address and contributes 0.
+// A ray sample's 2x2 footprint is the same in every z-slice, so a unit of
+// work may cover NS consecutive slices k0 .. k0 + NS - 1 whose values share
+// one staged texel (LDS column col = grid column col - 1): every address and
+// bilinear weight is then formed once for all of them.  Texel types:
+//  float    fp32, one slice;
+//  float2   fp32, two slices {x[k0], x[k0 + 1]} (when a slice pair fits in LDS
+//           in one band: row bands split the rays of a wave unevenly);
+//  uint32_t bf16 (the mixed operator's gathers), two slices: low half the
+//           bf16 voxel of k0, high half that of k0 + 1.
+// A missing last slice (odd nz) is staged as zeros and never stored.
 template <typename T>
-__device__ __forceinline__ float sample(const T *lds, int W, int nx, int nbase, int jb0, float bx, float by,
-                                        float s, float c, float y)
+struct Texel;
+template <>
+struct Texel<float> {
+    static constexpr int NS = 1;
+    using V = float;
+};
+template <>
+struct Texel<float2> {
+    static constexpr int NS = 2;
+    using V = float;
+};
+template <>
+struct Texel<uint32_t> {
+    static constexpr int NS = 2;
+    using V = uint16_t;
+};
+
+__device__ __forceinline__ void load(const float *p, float (&v)[1]) { v[0] = *p; }
+
+__device__ __forceinline__ void load(const float2 *p, float (&v)[2])
+{
+    const float2 q = *p;
+    v[0] = q.x;
+    v[1] = q.y;
+}
+
+__device__ __forceinline__ void load(const uint32_t *p, float (&v)[2])
+{
+    const uint32_t w = *p;
+    v[0] = __uint_as_float(w << 16);
+    v[1] = __uint_as_float(w & 0xffff0000u);
+}
+
+// The 2x2 footprint whose corner (0,0) is the texel at p: t[0] = (0,0),
+// t[1] = (1,0), t[2] = (0,1), t[3] = (1,1).
+template <typename T, int NS>
+__device__ __forceinline__ void fetch(const T *p, int W, float (&t)[4][NS])
+{
+    load(p, t[0]);
+    load(p + 1, t[1]);
+    load(p + W, t[2]);
+    load(p + W + 1, t[3]);
+}
+
+__device__ __forceinline__ float voxel(const float *slice, int nx, int ny, int gj, int gi)
+{
+    return (slice && gj >= 0 && gj < ny && gi >= 0 && gi < nx) ? slice[(size_t)gj * nx + gi] : 0.f;
+}
+
+__device__ __forceinline__ uint32_t voxel(const uint16_t *slice, int nx, int ny, int gj, int gi)
+{
+    return (slice && gj >= 0 && gj < ny && gi >= 0 && gi < nx) ? (uint32_t)slice[(size_t)gj * nx + gi] : 0u;
+}
+
+__device__ __forceinline__ void stage(float *d, const float *s0, const float *, int nx, int ny, int gj, int gi)
+{
+    *d = voxel(s0, nx, ny, gj, gi);
+}
+
+__device__ __forceinline__ void stage(float2 *d, const float *s0, const float *s1, int nx, int ny, int gj, int gi)
+{
+    *d = make_float2(voxel(s0, nx, ny, gj, gi), voxel(s1, nx, ny, gj, gi));
+}
+
+__device__ __forceinline__ void stage(uint32_t *d, const uint16_t *s0, const uint16_t *s1, int nx, int ny, int gj,
+                                      int gi)
+{
+    *d = voxel(s0, nx, ny, gj, gi) | (voxel(s1, nx, ny, gj, gi) << 16);
+}
+
+// Adds the bilinear interpolant of the footprint t at fractional offsets
+// (wx, wy) to acc.  One slice: the three-lerp form.  Two slices: the corner
+// weights (1-wx)(1-wy), wx(1-wy), (1-wx)wy, wx wy, formed once in five
+// operations and shared.
+template <int NS>
+__device__ __forceinline__ void accum(float (&acc)[NS], const float (&t)[4][NS], float wx, float wy)
+{
+    if constexpr (NS == 1) {
+        const float top = fmaf(wx, t[1][0] - t[0][0], t[0][0]);
+        const float bot = fmaf(wx, t[3][0] - t[2][0], t[2][0]);
+        acc[0] += fmaf(wy, bot - top, top);
+    } else {
+        const float w11 = wx * wy, w10 = wx - w11, w01 = wy - w11, w00 = (1.f - wx) - w01;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            acc[k] = fmaf(t[0][k], w00, acc[k]);
+            acc[k] = fmaf(t[1][k], w10, acc[k]);
+            acc[k] = fmaf(t[2][k], w01, acc[k]);
+            acc[k] = fmaf(t[3][k], w11, acc[k]);
+        }
+    }
+}
+
+// One bilinear sample of the staged band, tested.  Branch-free: a sample whose
+// 2x2 footprint lies outside the band reads a safe LDS address with zero
+// weights.
+template <typename T, int NS>
+__device__ __forceinline__ void sample(const T *lds, int W, int nx, int nbase, int jb0, float bx, float by, float s,
+                                       float c, float y, float (&acc)[NS])
 {
     const float fx = fmaf(y, s, bx), fy = fmaf(y, c, by);
     const float ix = floorf(fx), iy = floorf(fy);
@@ -77,91 +158,98 @@ __device__ __forceinline__ float sample(const T *lds, int W, int nx, int nbase, 
     const bool ok = (unsigned)i0 <= (unsigned)nx && (unsigned)j0 < (unsigned)nbase;
     i0 = ok ? i0 : 0;
     j0 = ok ? j0 : 0;
-    const float wx = fx - ix, wy = fy - iy;
-    float v00, v10, v01, v11;
-    corners(lds + j0 * W + i0, W, v00, v10, v01, v11);
-    const float top = fmaf(wx, v10 - v00, v00);
-    const float bot = fmaf(wx, v11 - v01, v01);
-    return ok ? fmaf(wy, bot - top, top) : 0.f;
+    float t[4][NS];
+    fetch(lds + j0 * W + i0, W, t);
+    float v[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = 0.f;
+    accum(v, t, fx - ix, fy - iy);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] += ok ? v[k] : 0.f;
 }
 
-// A sample known to lie kEdge inside the staged band (no test): fx in LDS
-// columns, fyb in band rows.  floor() via fract, exact for positive values;
-// the element index iy * W + ix is formed exactly in float.
+// Samples known to lie kEdge inside the staged band need no test: there fx
+// (in LDS columns) and fyb (in band rows) are positive, so floor is the
+// truncating conversion of the value and the fraction is fract().
 constexpr float kEdge = 1.0f / 64.0f;
 constexpr float kRange = 1.0f / 1024.0f;
 
+// The texel at (column fx, band row fyb), both positive.  Wb = W * sizeof(T).
 template <typename T>
-__device__ __forceinline__ float sample_in(const T *lds, int W, float bx, float byb, float s, float c, float y)
+__device__ __forceinline__ const T *texel_at(const T *lds, unsigned Wb, float fx, float fyb)
 {
-    const float fx = fmaf(y, s, bx), fy = fmaf(y, c, byb);
-    const float wx = __builtin_amdgcn_fractf(fx), wy = __builtin_amdgcn_fractf(fy);
-    const int e = (int)fmaf(fy - wy, (float)W, fx - wx);
-    float v00, v10, v01, v11;
-    corners(lds + e, W, v00, v10, v01, v11);
-    const float top = fmaf(wx, v10 - v00, v00);
-    const float bot = fmaf(wx, v11 - v01, v01);
-    return fmaf(wy, bot - top, top);
+    const unsigned off = __umul24((unsigned)fyb, Wb) + (unsigned)fx * (unsigned)sizeof(T);
+    return reinterpret_cast<const T *>(reinterpret_cast<const unsigned char *>(lds) + off);
 }
 
 // Four consecutive interior samples y, y+1, y+2, y+3: all LDS reads are
 // issued before any is used.
-template <typename T>
-__device__ __forceinline__ float sample_in4(const T *lds, int W, float bx, float byb, float s, float c, float y)
+template <typename T, int NS>
+__device__ __forceinline__ void sample_in4(const T *lds, int W, unsigned Wb, float bx, float byb, float s, float c,
+                                           float y, float (&acc)[NS])
 {
-    float wx[4], wy[4], v[4][4];
-    int e[4];
+    float wx[4], wy[4];
+    const T *p[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const float fx = fmaf(y + (float)j, s, bx), fy = fmaf(y + (float)j, c, byb);
         wx[j] = __builtin_amdgcn_fractf(fx);
         wy[j] = __builtin_amdgcn_fractf(fy);
-        e[j] = (int)fmaf(fy - wy[j], (float)W, fx - wx[j]);
+        p[j] = texel_at(lds, Wb, fx, fy);
     }
+    float t[4][4][NS];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) corners(lds + e[j], W, v[j][0], v[j][1], v[j][2], v[j][3]);
-    float r[4];
+    for (int j = 0; j < 4; ++j) fetch(p[j], W, t[j]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float top = fmaf(wx[j], v[j][1] - v[j][0], v[j][0]);
-        const float bot = fmaf(wx[j], v[j][3] - v[j][2], v[j][2]);
-        r[j] = fmaf(wy[j], bot - top, top);
-    }
-    return (r[0] + r[1]) + (r[2] + r[3]);
+    for (int j = 0; j < 4; ++j) accum(acc, t[j], wx[j], wy[j]);
 }
 
-__device__ __forceinline__ uint32_t bf16_at(const uint16_t *slice, int nx, int ny, int gj, int gi)
+template <typename T, int NS>
+__device__ __forceinline__ void sample_in(const T *lds, int W, unsigned Wb, float bx, float byb, float s, float c,
+                                          float y, float (&acc)[NS])
 {
-    return (gj >= 0 && gj < ny && gi >= 0 && gi < nx) ? (uint32_t)slice[(size_t)gj * nx + gi] : 0u;
+    const float fx = fmaf(y, s, bx), fy = fmaf(y, c, byb);
+    float t[4][NS];
+    fetch(texel_at(lds, Wb, fx, fy), W, t);
+    accum(acc, t, __builtin_amdgcn_fractf(fx), __builtin_amdgcn_fractf(fy));
 }
 
-// T = float: the fp32 path (reads x).  T = uint32_t: the bf16 path (reads the
-// bf16 copy xb, stages pair-packed words); weights and sums stay fp32.
+// T: the texel type above; weights and sums are fp32.
 template <typename T>
-__global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int out_stride)
+__global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, const typename Texel<T>::V *vol,
+                                                               int out_stride)
 {
+    using V = typename Texel<T>::V;
+    constexpr int NS = Texel<T>::NS;
+    constexpr int kMaxRaysPerThread = fwd_rays_per_thread(NS);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
     const int nb = gridDim.x;
     const int lb = xcd_logical(blockIdx.x, nb);
-    // The (slice, angle) units k * M + m are dealt to the blocks in equal
-    // contiguous ranges: a block stages each slice its range touches once and
-    // projects that slice for its angles there.
-    const long U = (long)a.nz * a.M;
+    // The (slice group, angle) units g * M + m are dealt to the blocks in equal
+    // contiguous ranges: a block stages each slice group its range touches
+    // once and projects that group for its angles there.
+    const int ng = (a.nz + NS - 1) / NS;
+    const long U = (long)ng * a.M;
     const long u0 = (long)lb * U / nb, u1 = (long)(lb + 1) * U / nb;
     const int W = a.nx + 2;
+    const unsigned Wb = (unsigned)(W * sizeof(T));
     const int tid = threadIdx.x;
     for (long ku = u0; ku < u1;) {
-        const int k = (int)(ku / a.M);
-        const int m0 = (int)(ku - (long)k * a.M);
-        const int m1 = (int)min((long)a.M, u1 - (long)k * a.M);
-        ku = (long)k * a.M + m1;
+        const int g = (int)(ku / a.M);
+        const int m0 = (int)(ku - (long)g * a.M);
+        const int m1 = (int)min((long)a.M, u1 - (long)g * a.M);
+        ku = (long)g * a.M + m1;
+        const int k0 = NS * g;
+        const int ns = min(NS, a.nz - k0);     // slices present in the group
         const int nrays = (m1 - m0) * a.nu;
-        float acc[kMaxRaysPerThread];
+        float acc[kMaxRaysPerThread][NS];
 #pragma unroll
-        for (int r = 0; r < kMaxRaysPerThread; ++r) acc[r] = 0.f;
-        const float *slice = a.x ? a.x + (size_t)k * a.nx * a.ny : nullptr;
-        const uint16_t *sliceb = a.xb ? a.xb + (size_t)k * a.nx * a.ny : nullptr;
+        for (int r = 0; r < kMaxRaysPerThread; ++r)
+#pragma unroll
+            for (int k = 0; k < NS; ++k) acc[r][k] = 0.f;
+        const V *s0 = vol + (size_t)k0 * a.nx * a.ny;
+        const V *s1 = ns > 1 ? s0 + (size_t)a.nx * a.ny : nullptr;
         for (int band = 0; band < a.n_bands; ++band) {
             const int jb0 = -1 + band * a.band_rows;               // first base row
             const int jb1 = min(jb0 + a.band_rows, a.ny);          // one past last base row
@@ -169,15 +257,8 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
             const int rows = nbase + 1;                            // LDS rows: grid rows jb0..jb1
             __syncthreads();
             for (int idx = tid; idx < rows * W; idx += kFwdThreads) {
-                int r = idx / W, col = idx - r * W;
-                int gj = jb0 + r, gi = col - 1;
-                if constexpr (std::is_same<T, float>::value) {
-                    float v = 0.f;
-                    if (gj >= 0 && gj < a.ny && gi >= 0 && gi < a.nx) v = slice[(size_t)gj * a.nx + gi];
-                    lds[idx] = v;
-                } else {
-                    lds[idx] = bf16_at(sliceb, a.nx, a.ny, gj, gi) | (bf16_at(sliceb, a.nx, a.ny, gj, gi + 1) << 16);
-                }
+                const int r = idx / W, col = idx - r * W;
+                stage(lds + idx, s0, s1, a.nx, a.ny, jb0 + r, col - 1);
             }
             __syncthreads();
 #pragma unroll
@@ -198,31 +279,32 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
                 // checked exactly): the edges are moved out by kRange in fx and fy,
                 // beyond the rounding of fx and fy themselves, so a ray that runs
                 // along a band edge (|c| tiny, fy rounding onto the edge row) keeps
-                // all its samples; inside it, [qa, qb] holds samples
-                // at least kEdge away from every edge in both coordinates, which
-                // need no test: there the band-relative row fy - jb0 lies in
-                // [kEdge, nbase - kEdge] and fx in [kEdge, nx + 1 - kEdge].
+                // all its samples; inside it, [qa, qb] holds samples at least kEdge
+                // away from every edge in both coordinates, which need no test:
+                // there the band-relative row fy - jb0 lies in [kEdge, nbase - kEdge]
+                // and fx in [kEdge, nx + 1 - kEdge].  The bounds are solved with one
+                // reciprocal per direction; its relative error (a few ulp, so below
+                // 1e-4 samples over any ray) is far inside both margins.
                 const float byb = by - (float)jb0;
                 float ylo = -a.half_nr, yhi = a.half_nr;
                 float ilo = -a.half_nr, ihi = a.half_nr;
                 if (s > 0.f) {
-                    ylo = fmaxf(ylo, (-kRange - bx) / s);
-                    yhi = fminf(yhi, ((float)(a.nx + 1) + kRange - bx) / s);
-                    ilo = fmaxf(ilo, (kEdge - bx) / s);
-                    ihi = fminf(ihi, ((float)(a.nx + 1) - kEdge - bx) / s);
+                    const float rs = 1.f / s;
+                    ylo = fmaxf(ylo, (-kRange - bx) * rs);
+                    yhi = fminf(yhi, ((float)(a.nx + 1) + kRange - bx) * rs);
+                    ilo = fmaxf(ilo, (kEdge - bx) * rs);
+                    ihi = fminf(ihi, ((float)(a.nx + 1) - kEdge - bx) * rs);
                 } else if (bx < kEdge || bx > (float)(a.nx + 1) - kEdge) {
                     ihi = ilo - 2.f;
                 }
-                if (c > 0.f) {
-                    ylo = fmaxf(ylo, ((float)jb0 - kRange - by) / c);
-                    yhi = fminf(yhi, ((float)jb1 + kRange - by) / c);
-                    ilo = fmaxf(ilo, (kEdge - byb) / c);
-                    ihi = fminf(ihi, ((float)nbase - kEdge - byb) / c);
-                } else if (c < 0.f) {
-                    ylo = fmaxf(ylo, ((float)jb1 + kRange - by) / c);
-                    yhi = fminf(yhi, ((float)jb0 - kRange - by) / c);
-                    ilo = fmaxf(ilo, ((float)nbase - kEdge - byb) / c);
-                    ihi = fminf(ihi, (kEdge - byb) / c);
+                if (c != 0.f) {
+                    const float rc = 1.f / c;
+                    const float e0 = ((float)jb0 - kRange - by) * rc, e1 = ((float)jb1 + kRange - by) * rc;
+                    const float i0 = (kEdge - byb) * rc, i1 = ((float)nbase - kEdge - byb) * rc;
+                    ylo = fmaxf(ylo, fminf(e0, e1));
+                    yhi = fminf(yhi, fmaxf(e0, e1));
+                    ilo = fmaxf(ilo, fminf(i0, i1));
+                    ihi = fminf(ihi, fmaxf(i0, i1));
                 } else if (byb < kEdge || byb > (float)nbase - kEdge) {
                     ihi = ilo - 2.f;
                 }
@@ -234,15 +316,18 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
                     qa = q1 + 1;
                     qb = q1;
                 }
-                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-                for (int q = q0; q < qa; ++q) s0 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, (float)q - a.half_nr);
+                float sa[NS], sb[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) sa[k] = sb[k] = 0.f;
+                for (int q = q0; q < qa; ++q) sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, (float)q - a.half_nr, sa);
                 // interior, four samples at a time with their LDS reads in flight together
                 int q = qa;
-                for (; q + 3 <= qb; q += 4) s3 += sample_in4(lds, W, bx, byb, s, c, (float)q - a.half_nr);
-                for (; q <= qb; ++q) s1 += sample_in(lds, W, bx, byb, s, c, (float)q - a.half_nr);
+                for (; q + 3 <= qb; q += 4) sample_in4(lds, W, Wb, bx, byb, s, c, (float)q - a.half_nr, sb);
+                for (; q <= qb; ++q) sample_in(lds, W, Wb, bx, byb, s, c, (float)q - a.half_nr, sb);
                 for (q = max(qb + 1, qa); q <= q1; ++q)
-                    s2 += sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, (float)q - a.half_nr);
-                acc[i] += (s0 + s1) + (s2 + s3);
+                    sample(lds, W, a.nx, nbase, jb0, bx, by, s, c, (float)q - a.half_nr, sa);
+#pragma unroll
+                for (int k = 0; k < NS; ++k) acc[i][k] += sa[k] + sb[k];
             }
         }
 #pragma unroll
@@ -250,14 +335,18 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, int o
             const int ray = tid + kFwdThreads * i;
             if (ray >= nrays) continue;
             const int m = m0 + ray / a.nu, p = ray % a.nu;
-            a.rt[((size_t)m * a.nz + k) * out_stride + p] = acc[i];
+            float *o = a.rt + ((size_t)m * a.nz + k0) * out_stride + p;
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                if (k < ns) o[(size_t)k * out_stride] = acc[i][k];
         }
         // zero the padding columns of the lines this block owns
         if (out_stride > a.nu) {
             const int pad = out_stride - a.nu;
-            const int nm = m1 - m0;
-            for (int idx = tid; idx < nm * pad; idx += kFwdThreads) {
-                const int m = m0 + idx / pad, p = a.nu + idx % pad;
+            const int nl = (m1 - m0) * ns;
+            for (int idx = tid; idx < nl * pad; idx += kFwdThreads) {
+                const int l = idx / pad;
+                const int m = m0 + l / ns, k = k0 + l % ns, p = a.nu + idx % pad;
                 a.rt[((size_t)m * a.nz + k) * out_stride + p] = 0.f;
             }
         }
@@ -399,8 +488,6 @@ static ProjArgs base_args(const mpi3d_plan *pl)
     a.ax = pl->ax;
     a.ay = pl->ay;
     a.nx = pl->nx; a.ny = pl->ny; a.nz = pl->nz; a.M = pl->M; a.nu = pl->nu; a.nup = pl->nup; a.nr = pl->nr;
-    a.band_rows = pl->band_rows;
-    a.n_bands = pl->n_bands;
     a.kz = pl->kz;
     a.adj_chunk = pl->adj_chunk;
     a.n_zgroups = (pl->nz + pl->kz - 1) / pl->kz;
@@ -414,34 +501,39 @@ static ProjArgs base_args(const mpi3d_plan *pl)
 }
 
 template <typename T>
-static hipError_t launch_fwd(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt, int out_stride,
-                             hipStream_t st)
+static hipError_t launch_fwd(const mpi3d_plan *pl, const typename Texel<T>::V *vol, const FwdConfig &fc, float *rt,
+                             int out_stride, hipStream_t st)
 {
     ProjArgs a = base_args(pl);
-    a.x = x;
-    a.xb = xb;
     a.rt = rt;
-    const int blocks = pl->fwd_blocks;
-    const size_t lds = (size_t)(a.band_rows + 1) * (pl->nx + 2) * sizeof(T);
+    a.band_rows = fc.band_rows;
+    a.n_bands = fc.n_bands;
+    const size_t lds = (size_t)(fc.band_rows + 1) * (pl->nx + 2) * sizeof(T);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)proj_fwd_kernel<T>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(proj_fwd_kernel<T>, dim3(blocks), dim3(kFwdThreads), lds, st, a, out_stride);
+    hipLaunchKernelGGL(proj_fwd_kernel<T>, dim3(fc.blocks), dim3(kFwdThreads), lds, st, a, vol, out_stride);
     return hipGetLastError();
+}
+
+static hipError_t launch_fwd32(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st)
+{
+    if (pl->fwd32.slices == 2) return launch_fwd<float2>(pl, x, pl->fwd32, rt, out_stride, st);
+    return launch_fwd<float>(pl, x, pl->fwd32, rt, out_stride, st);
 }
 
 hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *rt, int out_stride, hipStream_t st)
 {
-    return launch_fwd<float>(pl, x, nullptr, rt, out_stride, st);
+    return launch_fwd32(pl, x, rt, out_stride, st);
 }
 
 // xb non-null: gather from the bf16 copy (mixed path)
 hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt, hipStream_t st)
 {
-    if (xb) return launch_fwd<uint32_t>(pl, nullptr, xb, rt, pl->nup, st);
-    return launch_fwd<float>(pl, x, nullptr, rt, pl->nup, st);
+    if (xb) return launch_fwd<uint32_t>(pl, xb, pl->fwd16, rt, pl->nup, st);
+    return launch_fwd32(pl, x, rt, pl->nup, st);
 }
 
 hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,
