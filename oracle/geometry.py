@@ -11,6 +11,10 @@ Readings of the paper used here (each listed in the design doc):
 * The line integral of eq. ptheta2 is a unit-step Riemann sum over ray samples
   y_q = q - (Nr-1)/2, Nr the smallest integer >= sqrt(Nx^2+Ny^2) with the
   parity of Ny, so that at theta = 0 every sample falls on a voxel centre.
+* Raster trajectory classes: every angle repeats one scan sequence (Sec. 2.2,
+  before eq. modelF1); under a zig-zag raster (Sec. 3.1) the sweep direction
+  alternates from line to line, so z-row k sweeps forward when k is even and
+  backward when k is odd.
 * Kept bins (eq. bcompress, Appendix A's set S): for harmonics k = k_lo..k_hi
   and offsets d = -D..D, omega_{k,d} = floor(k P + 1/2) + d, ordered k-major,
   positive frequencies only (the data are a real signal's spectrum).
@@ -37,6 +41,7 @@ class Geometry:
     n_u: int = None                  # default Nx
     theta: np.ndarray = None         # default m*pi/M
     rx_filter: np.ndarray = None     # complex D_Gamma on the kept bins, None = 1
+    raster_sweep: float = 0.0        # focus-field shift per line in voxels (0 = none)
 
     def __post_init__(self):
         if self.n_u is None:
@@ -67,10 +72,18 @@ class Geometry:
         return g
 
     def slice_geometry(self):
-        """The same scan on a single z-slice (A is the same matrix on every slice)."""
+        """The same scan on the fewest z-slices that hold every distinct slice
+        operator: one slice, or two under a raster (even and odd rows sweep in
+        opposite directions)."""
         g = Geometry(**{k: getattr(self, k) for k in self.__dataclass_fields__})
-        g.nz = 1
+        g.nz = min(self.nz, 2) if self.raster_sweep else 1
         return g
+
+
+def line_classes(g):
+    """Trajectory class of every line l = m*Nz + k: k mod 2 under a raster, else 0."""
+    k = np.tile(np.arange(g.nz, dtype=np.int64), g.n_angles)
+    return k % 2 if g.raster_sweep else np.zeros_like(k)
 
 
 def voxel_centres(n):

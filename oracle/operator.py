@@ -7,9 +7,10 @@ Test infrastructure only (see ``oracle/__init__``).
 * ``adjoint``  -- A^T = Re(A^H), the exact transpose in <u,v> = Re(u^H v).
 * ``op_norm``  -- ||A||_2 by FP64 power iteration on A^T A.  The paper needs
                   ||A* A||_2 for its step size (after eq. iters) but does not
-                  say how it is found.  A is the same matrix on every z-slice
-                  (the projector acts slice by slice and every line shares one
-                  scan sequence), so the norm is taken on one slice.
+                  say how it is found.  A is block diagonal over z-slices (the
+                  projector acts slice by slice) with the same block on every
+                  slice of one trajectory class, so the norm is taken on one
+                  slice, or on two under a raster.
 * ``make_data`` -- synthetic compressed data: clean time signal of a phantom,
                   plus white Gaussian noise in the time domain with standard
                   deviation level * max|s_clean|, then compression.
@@ -23,56 +24,77 @@ import numpy as np
 from . import projector, signal
 
 
+def _per_class(g, rows_in, fn):
+    """Apply fn(class, rows of that class) line by line class."""
+    cl = signal.row_classes(g, rows_in.shape[0])
+    out = None
+    for c in signal.classes_present(g):
+        idx = np.flatnonzero(cl == c)
+        part = fn(c, rows_in[idx])
+        if out is None:
+            out = np.empty((rows_in.shape[0],) + part.shape[1:], dtype=part.dtype)
+        out[idx] = part
+    return out
+
+
 def forward(g, x, precomposed=False):
     rt = projector.project(g, x).reshape(g.n_lines, g.n_u)
     if precomposed:
-        return (rt @ signal.line_matrix(g).T).reshape(g.n_angles, g.nz, g.n_bins)
+        b = _per_class(g, rt, lambda c, r: r @ signal.line_matrix(g, c).T)
+        return b.reshape(g.n_angles, g.nz, g.n_bins)
     return signal.forward(g, rt).reshape(g.n_angles, g.nz, g.n_bins)
 
 
 def adjoint(g, y, precomposed=False):
     y = np.asarray(y, dtype=np.complex128).reshape(g.n_lines, g.n_bins)
     if precomposed:
-        lines = np.real(y @ np.conj(signal.line_matrix(g)))
+        lines = _per_class(g, y, lambda c, r: np.real(r @ np.conj(signal.line_matrix(g, c))))
     else:
         lines = signal.adjoint(g, y)
     return projector.backproject(g, lines.reshape(g.n_angles, g.nz, g.n_u))
 
 
 class Operator:
-    """A with its tables built once (C precomposed optional)."""
+    """A with its tables built once (C precomposed optional), per trajectory class."""
 
     def __init__(self, g, precomposed=False):
         self.g = g
         self.precomposed = precomposed
+        self.classes = signal.classes_present(g)
         if precomposed:
-            self.C = signal.line_matrix(g)
+            self.C = {c: signal.line_matrix(g, c) for c in self.classes}
         else:
-            self.K = signal.kernel(g)
+            self.K = {c: signal.kernel(g, c) for c in self.classes}
             self.E = signal.dft_matrix(g)
             # real and imaginary parts kept apart so real signals meet real matrices
             self.E_re = np.ascontiguousarray(self.E.real)
             self.E_im = np.ascontiguousarray(self.E.imag)
 
-    def _lines_fwd(self, rt):
+    def _lines_fwd_class(self, c, rt):
         if self.precomposed:
-            return rt @ self.C.T
+            return rt @ self.C[c].T
         out = np.empty((rt.shape[0], self.g.n_bins), dtype=np.complex128)
         for a in range(0, rt.shape[0], 512):
-            s = rt[a:a + 512] @ self.K.T
+            s = rt[a:a + 512] @ self.K[c].T
             out[a:a + 512] = (s @ self.E_re) + 1j * (s @ self.E_im)
         return out
 
-    def _lines_adj(self, y):
+    def _lines_adj_class(self, c, y):
         if self.precomposed:
-            return np.real(y @ np.conj(self.C))
+            return np.real(y @ np.conj(self.C[c]))
         out = np.empty((y.shape[0], self.g.n_u), dtype=np.float64)
         for a in range(0, y.shape[0], 512):
             yb = y[a:a + 512]
             # Re(y conj(E)^T); contiguous copies keep numpy on its BLAS path
             h = np.ascontiguousarray(yb.real) @ self.E_re.T + np.ascontiguousarray(yb.imag) @ self.E_im.T
-            out[a:a + 512] = h @ self.K
+            out[a:a + 512] = h @ self.K[c]
         return out
+
+    def _lines_fwd(self, rt):
+        return _per_class(self.g, rt, self._lines_fwd_class)
+
+    def _lines_adj(self, y):
+        return _per_class(self.g, y, self._lines_adj_class)
 
     def forward(self, x):
         g = self.g
@@ -118,14 +140,23 @@ def make_data(g, phantom, noise_level, noise_seed):
     """
     op = Operator(g)
     rt = projector.project(g, phantom).reshape(g.n_lines, g.n_u)
+    cl = signal.row_classes(g, g.n_lines)
+
+    def clean(a):   # time signals of lines a .. a+511, each through its class's K
+        s = np.empty((min(512, g.n_lines - a), g.n_t))
+        for c in op.classes:
+            m = cl[a:a + 512] == c
+            s[m] = rt[a:a + 512][m] @ op.K[c].T
+        return s
+
     s_max = 0.0
     for a in range(0, g.n_lines, 512):
-        s_max = max(s_max, float(np.abs(rt[a:a + 512] @ op.K.T).max()))
+        s_max = max(s_max, float(np.abs(clean(a)).max()))
     sigma = noise_level * s_max
     rng = np.random.default_rng(noise_seed)
     b = np.empty((g.n_lines, g.n_bins), dtype=np.complex128)
     for a in range(0, g.n_lines, 512):
-        s = rt[a:a + 512] @ op.K.T
+        s = clean(a)
         s = s + sigma * rng.standard_normal(s.shape)
         b[a:a + 512] = (s @ op.E_re) + 1j * (s @ op.E_im)
     return b.reshape(g.n_angles, g.nz, g.n_bins), sigma

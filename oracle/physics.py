@@ -14,6 +14,11 @@ Passages followed
   h(u) = L'(u/w)/w with w = H_sat/G0 in voxels (collinear reduction).
 * Sinusoidal drive H_D = A sin(2 pi f0 t): eq. HD; FFL position
   xi(t) = a sin(phi(t)) follows from eq. H1 (H = G(xi - x)).
+* Raster (Sec. 3.1, the scanner's acquisition): a slow focus field moves the
+  line across the field of view in a zig-zag, back and forth along the fast
+  axis.  Reading: during one FFL line the centre moves at constant speed over
+  ``sweep`` voxels, c(t) = direction * sweep * (t/T - 1/2), in the direction
+  that alternates from line to line, and adds to the drive.
 
 Pins (tests/test_oracle_physics.py): L and L' against mpmath at 40 digits;
 the velocity and PSF chain against a complex-step derivative of the
@@ -110,37 +115,41 @@ def langevin_deriv(x):
     return out
 
 
-def trajectory(n_t, drive_cycles, drive_amp):
+def trajectory(n_t, drive_cycles, drive_amp, sweep=0.0, direction=1.0):
     """FFL position xi_n and velocity v_n at samples n = 0..T-1.
 
     phi_n = 2 pi P n / T, xi_n = a sin(phi_n), v_n = a (2 pi P / T) cos(phi_n):
     the sinusoidal drive of eq. HD moves the line as xi(t) (eq. H1), and the
     velocity multiplier V of Table 1 is v = xi' (eq. reals0), with time in
-    units of one sample.
+    units of one sample.  A raster adds the focus-field shift
+    c_n = direction * sweep * (n/T - 1/2) to xi_n and its constant speed
+    direction * sweep / T to v_n.
     """
     n = np.arange(n_t, dtype=np.float64)
     omega = 2.0 * np.pi * drive_cycles / n_t
-    return drive_amp * np.sin(omega * n), drive_amp * omega * np.cos(omega * n)
+    xi = drive_amp * np.sin(omega * n) + direction * sweep * (n / n_t - 0.5)
+    v = drive_amp * omega * np.cos(omega * n) + direction * sweep / n_t
+    return xi, v
 
 
-def psf_kernel(n_t, drive_cycles, drive_amp, psf_width, u, op_scale):
+def psf_kernel(n_t, drive_cycles, drive_amp, psf_width, u, op_scale, sweep=0.0, direction=1.0):
     """K[n, p] = c_A * v_n * L'((xi_n - u_p)/w) / w, shape (T, Nu).
 
     The matrix of the fused E H V operators of eq. svecHPF restricted to one
     FFL row (collinear PSF), with B = I and all physical constants in c_A.
     """
-    xi, v = trajectory(n_t, drive_cycles, drive_amp)
+    xi, v = trajectory(n_t, drive_cycles, drive_amp, sweep, direction)
     arg = (xi[:, None] - np.asarray(u, dtype=np.float64)[None, :]) / psf_width
     return op_scale * v[:, None] * langevin_deriv(arg) / psf_width
 
 
-def magnetisation(t, drive_cycles, n_t, drive_amp, psf_width, u, rho_line, op_scale):
+def magnetisation(t, drive_cycles, n_t, drive_amp, psf_width, u, rho_line, op_scale, sweep=0.0, direction=1.0):
     """m(t) = c_A * sum_p rho_p L((xi(t) - u_p)/w), t real or complex.
 
     Used only to pin the signal chain: s0 = dm/dt (eq. s01 -> eq. reals0).
     """
     t = np.asarray(t)
     omega = 2.0 * np.pi * drive_cycles / n_t
-    xi = drive_amp * np.sin(omega * t)
+    xi = drive_amp * np.sin(omega * t) + direction * sweep * (t / n_t - 0.5)
     arg = (xi[..., None] - np.asarray(u)[None, :]) / psf_width
     return op_scale * (langevin(arg) * np.asarray(rho_line)[None, :]).sum(axis=-1)

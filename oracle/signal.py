@@ -5,7 +5,9 @@ Test infrastructure only (see ``oracle/__init__``).
 Per FFL line l = (angle m, z-row k) with projection rho_theta[l, :]:
 
 1. Time signal (eq. stheta1 with the collinear PSF of Appendix B eq. PSF,
-   B = I):  s[l, n] = c_A v_n sum_p rho_theta[l, p] L'((xi_n - u_p)/w) / w.
+   B = I):  s[l, n] = c_A v_n sum_p rho_theta[l, p] L'((xi_n - u_p)/w) / w,
+   with xi and v those of the line's trajectory class (one class, or two
+   under a raster: ``geometry.line_classes``).
 2. Compression (eq. bcompress, eq. DCmodel, Appendix A):
    b[l, j] = D_Gamma[j] T^{-1/2} sum_n s[l, n] exp(+2 pi i omega_j n / T),
    the unitary DFT of Appendix A (plus sign, 1/sqrt(N)) restricted to the
@@ -28,7 +30,7 @@ precomposed vs time-domain path.
 """
 import numpy as np
 
-from .geometry import detector_grid, kept_bins
+from .geometry import detector_grid, kept_bins, line_classes
 from .physics import psf_kernel
 
 _LINE_BLOCK = 512  # lines per block, bounds the (lines x T) temporaries
@@ -49,14 +51,39 @@ def dft_matrix(g, bins=None):
     return e
 
 
-def kernel(g):
-    return psf_kernel(g.n_t, g.drive_cycles, g.drive_amp, g.psf_width, detector_grid(g), g.op_scale)
+def kernel(g, cls=0):
+    """K of trajectory class cls (1: the raster's backward sweep)."""
+    direction = -1.0 if cls == 1 else 1.0
+    return psf_kernel(g.n_t, g.drive_cycles, g.drive_amp, g.psf_width, detector_grid(g), g.op_scale,
+                      g.raster_sweep, direction)
+
+
+def classes_present(g):
+    return (0, 1) if g.raster_sweep and g.nz > 1 else (0,)
+
+
+def row_classes(g, n_rows):
+    """Class of each of n_rows line rows: any number of rows of a one-class
+    scan, or all L lines of a raster scan in line order."""
+    if len(classes_present(g)) == 1:
+        return np.zeros(n_rows, dtype=np.int64)
+    assert n_rows == g.n_lines, "a raster scan's lines must be passed together"
+    return line_classes(g)
 
 
 def time_signal(g, rho_theta, K=None):
-    """s[l, n] for every line, shape (L, T)."""
-    K = kernel(g) if K is None else K
-    return np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u) @ K.T
+    """s[l, n], shape (rows, T): with K given, every row through K; else every
+    line of the scan through its own class's K (rows must be all L lines when
+    the scan has a raster)."""
+    r = np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u)
+    if K is not None:
+        return r @ K.T
+    cl = row_classes(g, r.shape[0])
+    out = np.empty((r.shape[0], g.n_t))
+    for c in classes_present(g):
+        idx = np.flatnonzero(cl == c)
+        out[idx] = r[idx] @ kernel(g, c).T
+    return out
 
 
 def compress(g, s, E=None):
@@ -68,27 +95,37 @@ def compress(g, s, E=None):
 def forward(g, rho_theta):
     """Lines (L, Nu) -> compressed data (L, nb), time-domain path, block over lines."""
     r = np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u)
-    K, E = kernel(g), dft_matrix(g)
+    cl = row_classes(g, r.shape[0])
+    E = dft_matrix(g)
     out = np.empty((r.shape[0], g.n_bins), dtype=np.complex128)
-    for a in range(0, r.shape[0], _LINE_BLOCK):
-        out[a:a + _LINE_BLOCK] = compress(g, time_signal(g, r[a:a + _LINE_BLOCK], K), E)
+    for c in classes_present(g):
+        K = kernel(g, c)
+        idx = np.flatnonzero(cl == c)
+        for a in range(0, idx.size, _LINE_BLOCK):
+            rows = idx[a:a + _LINE_BLOCK]
+            out[rows] = compress(g, time_signal(g, r[rows], K), E)
     return out
 
 
 def adjoint(g, y):
     """Compressed data (L, nb) -> lines (L, Nu): Re of the Hermitian transpose."""
     y = np.asarray(y, dtype=np.complex128).reshape(-1, g.n_bins)
-    K, E = kernel(g), dft_matrix(g)
+    cl = row_classes(g, y.shape[0])
+    E = dft_matrix(g)
     out = np.empty((y.shape[0], g.n_u), dtype=np.float64)
-    for a in range(0, y.shape[0], _LINE_BLOCK):
-        h = np.real(y[a:a + _LINE_BLOCK] @ np.ascontiguousarray(np.conj(E).T))  # transpose of compress
-        out[a:a + _LINE_BLOCK] = h @ K                     # transpose of time_signal
+    for c in classes_present(g):
+        K = kernel(g, c)
+        idx = np.flatnonzero(cl == c)
+        for a in range(0, idx.size, _LINE_BLOCK):
+            rows = idx[a:a + _LINE_BLOCK]
+            h = np.real(y[rows] @ np.ascontiguousarray(np.conj(E).T))  # transpose of compress
+            out[rows] = h @ K                                         # transpose of time_signal
     return out
 
 
-def line_matrix(g):
-    """C[j, p] = sum_n E[n, j] K[n, p]: the per-line operator, precomposed."""
-    return dft_matrix(g).T @ kernel(g)
+def line_matrix(g, cls=0):
+    """C[j, p] = sum_n E[n, j] K[n, p]: the per-line operator of class cls, precomposed."""
+    return dft_matrix(g).T @ kernel(g, cls)
 
 
 def information_retained(s, bins):

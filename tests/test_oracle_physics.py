@@ -6,7 +6,12 @@ import pytest
 from oracle import physics, signal
 from oracle.geometry import Geometry, detector_grid
 
-mpmath.mp.dps = 40
+
+@pytest.fixture(autouse=True)
+def _mp_precision():
+    """40-digit mpmath for every test of this module, whatever other modules set."""
+    with mpmath.workdps(40):
+        yield
 
 
 def _mp_L(x):
@@ -95,3 +100,36 @@ def test_trajectory_sweep():
     assert abs(xi.max() - 8.0) < 1e-12 and abs(xi.min() + 8.0) < 1e-12
     # closed-form velocity: a * 2 pi P / T at phase 0
     assert abs(v[0] - 8.0 * 2 * np.pi * 16.0 / 4096) < 1e-15
+
+
+def test_raster_velocity_psf_chain_is_time_derivative_of_magnetisation():
+    """With the raster's focus-field shift c(t) = +-S (t/T - 1/2) added to the
+    drive, s_n must still be dm/dt (complex step): this pins the shift and its
+    constant speed +-S/T in v, for both sweep directions."""
+    for direction in (1.0, -1.0):
+        g = Geometry(nx=24, ny=24, nz=1, n_angles=1, n_t=512, drive_cycles=3.7, psf_width=2.5,
+                     harm_lo=1, harm_hi=5, half_band=1, op_scale=1.3, drive_amp=4.0, raster_sweep=17.0)
+        rng = np.random.default_rng(11)
+        rho = rng.uniform(0.0, 1.0, g.n_u)
+        u = detector_grid(g)
+        K = physics.psf_kernel(g.n_t, g.drive_cycles, g.drive_amp, g.psf_width, u, g.op_scale,
+                               g.raster_sweep, direction)
+        s = rho @ K.T
+        h = 1e-30
+        t = np.arange(g.n_t) + 1j * h
+        dm = physics.magnetisation(t, g.drive_cycles, g.n_t, g.drive_amp, g.psf_width, u, rho,
+                                   g.op_scale, g.raster_sweep, direction).imag / h
+        assert np.max(np.abs(s - dm)) <= 1e-12 * np.max(np.abs(dm))
+
+
+def test_raster_trajectory_closed_form():
+    """Centre -S/2 at n = 0 moving at S/T per sample (forward), mirrored backward."""
+    T, S = 4096, 40.0
+    xi0, v0 = physics.trajectory(T, 16.0, 8.0)
+    xi_f, v_f = physics.trajectory(T, 16.0, 8.0, S, 1.0)
+    xi_b, v_b = physics.trajectory(T, 16.0, 8.0, S, -1.0)
+    n = np.arange(T)
+    assert np.max(np.abs(xi_f - xi0 - S * (n / T - 0.5))) < 1e-12
+    assert np.max(np.abs(xi_b - xi0 + S * (n / T - 0.5))) < 1e-12
+    assert abs(xi_f[0] - (xi0[0] - S / 2)) < 1e-12
+    assert np.max(np.abs(v_f - v0 - S / T)) < 1e-15 and np.max(np.abs(v_b - v0 + S / T)) < 1e-15

@@ -121,3 +121,41 @@ def test_information_retained_in_unit_interval():
     s = signal.time_signal(g, rng.uniform(0, 1, (4, g.n_u)))
     info = signal.information_retained(s, kept_bins(g))
     assert np.all(info > 0.9) and np.all(info <= 1.0)
+
+
+def test_raster_lines_follow_their_own_sweep_direction():
+    """Every line's time signal is the derivative of its own magnetisation, with
+    the sweep forward on even z-rows and backward on odd ones (the zig-zag,
+    repeated for every angle): pins the class of each line independently of
+    the kernel tables."""
+    from oracle import physics
+    g = _geom(nz=3, n_angles=2, n_t=512, drive_cycles=3.7, harm_hi=5, half_band=1,
+              drive_amp=6.0, raster_sweep=11.0, op_scale=0.8)
+    rng = np.random.default_rng(12)
+    rho = rng.uniform(0.0, 1.0, (g.n_lines, g.n_u))
+    s = signal.time_signal(g, rho)
+    u = detector_grid(g)
+    h = 1e-30
+    t = np.arange(g.n_t) + 1j * h
+    for line in range(g.n_lines):
+        k = line % g.nz
+        direction = 1.0 if k % 2 == 0 else -1.0
+        dm = physics.magnetisation(t, g.drive_cycles, g.n_t, g.drive_amp, g.psf_width, u, rho[line],
+                                   g.op_scale, g.raster_sweep, direction).imag / h
+        assert np.max(np.abs(s[line] - dm)) <= 1e-12 * np.max(np.abs(dm))
+    # the two directions really differ
+    assert np.max(np.abs(signal.kernel(g, 0) - signal.kernel(g, 1))) > 1e-3 * np.max(np.abs(signal.kernel(g, 0)))
+
+
+def test_raster_signal_adjoint_identity_and_precomposed():
+    g = _geom(nz=4, n_angles=2, raster_sweep=9.0, op_scale=0.6)
+    rng = np.random.default_rng(13)
+    r = rng.standard_normal((g.n_lines, g.n_u))
+    y = rng.standard_normal((g.n_lines, g.n_bins)) + 1j * rng.standard_normal((g.n_lines, g.n_bins))
+    fr = signal.forward(g, r)
+    lhs = np.vdot(fr, y).real
+    rhs = np.vdot(r, signal.adjoint(g, y))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    cl = np.tile(np.arange(g.nz) % 2, g.n_angles)
+    pre = np.where((cl == 0)[:, None], r @ signal.line_matrix(g, 0).T, r @ signal.line_matrix(g, 1).T)
+    assert np.max(np.abs(fr - pre)) <= 1e-13 * np.max(np.abs(fr))
