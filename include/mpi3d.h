@@ -117,6 +117,15 @@ typedef struct {
     int32_t precisions;          /* bit mask of (1 << MPI3D_FP32) | (1 << MPI3D_MIXED) |
                                     (1 << MPI3D_PRECOMPOSED): which operator variants get
                                     tables; 0 = FP32 only */
+    double raster_sweep;         /* S, the focus-field shift over one FFL line in voxels
+                                    (finite; 0 = none).  The zig-zag raster of Sec. 3.1:
+                                    during line (m, k) the line centre moves at constant
+                                    speed, c_n = +-S (n/T - 1/2), forward (+) when z-row k
+                                    is even and backward (-) when it is odd, the same
+                                    sequence for every angle (Sec. 2.2), so
+                                    xi_n = a sin(2 pi P n/T) + c_n and v_n = xi' gains
+                                    +-S/T.  With S != 0 and nz >= 2 the plan holds two
+                                    PSF tables; MPI3D_PRECOMPOSED is then MPI3D_ENOTSUP */
 } mpi3d_geometry;
 
 typedef struct mpi3d_plan mpi3d_plan;

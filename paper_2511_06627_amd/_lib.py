@@ -32,6 +32,7 @@ class Geometry(ctypes.Structure):
         ("rx_filter", ctypes.POINTER(ctypes.c_float)),
         ("op_scale", ctypes.c_double),
         ("precisions", ctypes.c_int32),
+        ("raster_sweep", ctypes.c_double),
     ]
 
 

@@ -79,8 +79,8 @@ int check_prec(const mpi3d_plan *pl, int32_t precision)
 static SigArgs sig_args(const mpi3d_plan *pl, bool serve)
 {
     SigArgs a{};
-    a.kf = pl->kf; a.ff = pl->ff; a.fa = pl->fa; a.ka = pl->ka;
-    a.kf16 = pl->kf16; a.ff16 = pl->ff16; a.fa16 = pl->fa16; a.ka16 = pl->ka16;
+    a.ff = pl->ff; a.fa = pl->fa;
+    a.ff16 = pl->ff16; a.fa16 = pl->fa16;
     a.band_scale = pl->band_scale;
     a.nu = pl->nu; a.nup = pl->nup; a.nb2 = pl->nb2; a.nbp2 = pl->nbp2; a.nct = pl->nct;
     a.nchunks = pl->nchunks;
@@ -92,12 +92,59 @@ static SigArgs sig_args(const mpi3d_plan *pl, bool serve)
 
 static int nsplit_of(const mpi3d_plan *pl, bool serve) { return serve ? pl->serve_nsplit : pl->nsplit; }
 
+// The kernel jobs of one line job, one per trajectory class: class c holds the
+// lines (m, k) with k % n_classes == c, i.e. per angle ceil((nz - c) /
+// n_classes) lines n_classes apart, and that class's PSF tables.
+static int class_jobs(const LineJob &lj, bool fwd, SigJob *out)
+{
+    const mpi3d_plan *pj = lj.pl;
+    const int nc = pj->n_classes;
+    for (int c = 0; c < nc; ++c) {
+        SigJob &sj = out[c];
+        sj = SigJob{};
+        sj.in = lj.in;
+        sj.in_stride = lj.in_stride;
+        sj.part = lj.w->part;
+        sj.part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
+        sj.row_scale = lj.w->rowscale;
+        const size_t ko = (size_t)c * pj->k_elems;
+        sj.kf = pj->kf + ko;
+        sj.ka = pj->ka + ko;
+        sj.kf16 = pj->kf16 ? pj->kf16 + ko : nullptr;
+        sj.ka16 = pj->ka16 ? pj->ka16 + ko : nullptr;
+        if (nc == 1) {
+            sj.rows = (int)pj->L;
+            sj.map_per = std::max(1, sj.rows);
+            sj.map_nz = 0;
+            sj.map_off = 0;
+            sj.map_step = 1;
+        } else {
+            const int per = (pj->nz - c + nc - 1) / nc;
+            sj.rows = pj->M * per;
+            sj.map_per = per;
+            sj.map_nz = pj->nz;
+            sj.map_off = c;
+            sj.map_step = nc;
+        }
+    }
+    return nc;
+}
+
 static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
 {
-    if (n < 1 || n > kMaxJobs) return MPI3D_EINVAL;
+    if (n < 1) return MPI3D_EINVAL;
     const mpi3d_plan *pl = jobs[0].pl;
     SigArgs a = sig_args(pl, serve);
-    int tiles = 0;
+    int tiles = 0, nj = 0;
+    auto flush = [&]() -> int {
+        if (nj == 0) return MPI3D_OK;
+        a.njobs = nj;
+        a.total_tiles = tiles;
+        TRY(fwd ? launch_sig_fwd(pl, prec, a, st) : launch_sig_adj(pl, prec, a, st));
+        nj = 0;
+        tiles = 0;
+        return MPI3D_OK;
+    };
     for (int j = 0; j < n; ++j) {
         const mpi3d_plan *pj = jobs[j].pl;
         if (pj->line_key != pl->line_key) return MPI3D_EINVAL;
@@ -107,20 +154,16 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
             else TRY(launch_row_scale(pj->L, pj->nb2, jobs[j].in_stride, jobs[j].in, pj->band_scale,
                                       jobs[j].w->rowscale, st));
         }
-        SigJob &sj = a.jobs[j];
-        sj.in = jobs[j].in;
-        sj.in_stride = jobs[j].in_stride;
-        sj.part = jobs[j].w->part;
-        sj.part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
-        sj.row_scale = jobs[j].w->rowscale;
-        sj.rows = (int)pj->L;
-        sj.tile0 = tiles;
-        tiles += (int)((pj->L + kRowsPerBlock - 1) / kRowsPerBlock);
+        if (nj + pj->n_classes > kMaxJobs) TRYRC(flush());
+        SigJob cj[2];
+        const int nc = class_jobs(jobs[j], fwd, cj);
+        for (int c = 0; c < nc; ++c) {
+            cj[c].tile0 = tiles;
+            tiles += (cj[c].rows + kRowsPerBlock - 1) / kRowsPerBlock;
+            a.jobs[nj++] = cj[c];
+        }
     }
-    a.njobs = n;
-    a.total_tiles = tiles;
-    TRY(fwd ? launch_sig_fwd(pl, prec, a, st) : launch_sig_adj(pl, prec, a, st));
-    return MPI3D_OK;
+    return flush();
 }
 
 int sig_forward_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
@@ -642,21 +685,19 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         (void)hipEventDestroy(e0);
         return MPI3D_EDEVICE;
     }
+    // signal kernels: every line in one launch, one job per trajectory class
     SigArgs a = sig_args(pl, false);
-    a.njobs = 1;
-    a.jobs[0].row_scale = w.rowscale;
-    a.jobs[0].rows = (int)pl->L;
-    a.jobs[0].tile0 = 0;
-    a.jobs[0].part = w.part;
-    a.total_tiles = (int)((pl->L + kRowsPerBlock - 1) / kRowsPerBlock);
-    if (kernel == 2) {
-        a.jobs[0].in = w.rt;
-        a.jobs[0].in_stride = pl->nup;
-        a.jobs[0].part_stride = pl->L * pl->nbp2;
-    } else if (kernel == 3) {
-        a.jobs[0].in = b;
-        a.jobs[0].in_stride = pl->nb2;
-        a.jobs[0].part_stride = pl->L * pl->nup;
+    {
+        const bool fwd = kernel == 2;
+        const LineJob lj{pl, fwd ? w.rt : b, fwd ? pl->nup : pl->nb2, &w};
+        SigJob cj[2];
+        a.njobs = class_jobs(lj, fwd, cj);
+        a.total_tiles = 0;
+        for (int c = 0; c < a.njobs; ++c) {
+            cj[c].tile0 = a.total_tiles;
+            a.total_tiles += (cj[c].rows + kRowsPerBlock - 1) / kRowsPerBlock;
+            a.jobs[c] = cj[c];
+        }
     }
     const bool mixed = precision == MPI3D_MIXED;
     hipError_t err = mixed && kernel == 0 ? launch_to_bf16(pl->nvox, x, w.xb, st) : hipSuccess;

@@ -36,19 +36,30 @@ constexpr int fwd_rays_per_thread(int slices) { return slices == 1 ? 4 : 2; }
 
 // One batch segment of FFL lines sharing the same line tables.
 struct SigJob {
-    const void *in;        // fwd: projections [rows][nup] (f32); adj: data [rows][2nb] (f32)
-    float *part;           // partial sums, see kernels
-    float *row_scale;      // mixed: per-row power-of-two scale (written by the kernel)
+    const void *in;        // fwd: projections [lines][nup] (f32); adj: data [lines][2nb] (f32)
+    float *part;           // partial sums per line, see kernels
+    float *row_scale;      // mixed: per-line power-of-two scale (row_scale kernel)
+    const float *kf, *ka;  // this job's PSF tables (fp32; its lines' trajectory class)
+    const __half *kf16, *ka16;   // (fp16)
     int rows;              // FFL lines of this job
     int tile0;             // first block-row tile of this job in the launch
-    int in_stride;         // floats between consecutive input rows
+    int in_stride;         // floats between consecutive input lines
     long part_stride;      // floats between consecutive split (x group) partial blocks
+    // Job row r is line (r / map_per) * map_nz + map_off + map_step * (r % map_per)
+    // of the buffers above (identity: map_per >= rows, map_off 0, map_step 1).
+    int map_per, map_nz, map_off, map_step;
 };
 
+__host__ __device__ inline long job_line(const SigJob &j, int r)
+{
+    const int g = r / j.map_per;
+    return (long)g * j.map_nz + j.map_off + (long)j.map_step * (r - g * j.map_per);
+}
+
 struct SigArgs {
-    // tables (device)
-    const float *kf, *ff, *fa, *ka;               // fp32 swizzled tables
-    const __half *kf16, *ff16, *fa16, *ka16;      // fp16 swizzled tables
+    // tables (device); the PSF tables are per job
+    const float *ff, *fa;                         // fp32 swizzled DFT tables
+    const __half *ff16, *fa16;                    // fp16 swizzled DFT tables
     const float *band_scale;                      // [nbp2] adjoint per-column scale (mixed)
     int nu, nup, nb2, nbp2, nct;                  // sizes (nup, nbp2 padded to 32)
     int nchunks, cps, nsplit, ngroups, gct;       // chunking and column groups
@@ -114,8 +125,13 @@ struct mpi3d_plan {
     size_t table_bytes;
     float2 *cs;
     float *ax, *ay;
+    // PSF tables kf, ka (kf16, ka16): n_classes consecutive copies of k_elems
+    // elements, one per trajectory class (two under a raster)
     float *kf, *ff, *fa, *ka;
     __half *kf16, *ff16, *fa16, *ka16;
+    int n_classes;
+    size_t k_elems;
+    double raster_sweep;
     float *col_scale;     // [nbp2] mixed forward output scale per column
     float *band_scale;    // [nbp2] mixed adjoint input scale per column
     float adj_scale16;    // mixed adjoint output scale
@@ -207,8 +223,10 @@ struct LineJob {
     int in_stride;
     const OpWs *w;
 };
-// Signal contraction over the lines of n jobs (n <= kMaxJobs) sharing one
-// line class, in one launch; `serve` selects the class-fixed time split.
+// Signal contraction over the lines of n line jobs whose plans have equal line
+// tables (line_key), in as few launches as the kernel's job table allows (a
+// line job takes one kernel job per trajectory class); `serve` selects the
+// fixed time split of merged serving launches.
 int sig_forward_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st);
 int sig_adjoint_jobs(int prec, const LineJob *jobs, int n, bool serve, hipStream_t st);
 

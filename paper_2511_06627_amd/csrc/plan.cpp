@@ -129,9 +129,13 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (nu < 2 || nu > 256) return MPI3D_ENOTSUP;
     if (!(g->drive_cycles > 0) || !(g->psf_width > 0) || !(g->op_scale >= 0)) return MPI3D_EINVAL;
     if (!(g->drive_amp >= 0)) return MPI3D_EINVAL;
+    if (!std::isfinite(g->raster_sweep)) return MPI3D_EINVAL;
+    const int n_classes = (g->raster_sweep != 0.0 && g->nz >= 2) ? 2 : 1;
     if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
     int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
     if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED) | (1 << MPI3D_PRECOMPOSED))) return MPI3D_EINVAL;
+    // the precomposed line matrix assumes one trajectory shared by every line
+    if (n_classes > 1 && (precisions & (1 << MPI3D_PRECOMPOSED))) return MPI3D_ENOTSUP;
 
     // kept bins, validated
     std::vector<long> bins;
@@ -160,6 +164,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->w = g->psf_width;
     pl->op_scale = g->op_scale;
     pl->precisions = precisions;
+    pl->n_classes = n_classes;
+    pl->raster_sweep = g->raster_sweep;
     pl->nup = round_up(nu, 64);
     pl->ntp = round_up(g->n_t, kChunk);
     pl->nb2 = 2 * pl->nb;
@@ -270,15 +276,24 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         }
     }
 
-    // PSF kernel K[n][p] (n < T, p < NU; zero padding elsewhere)
-    std::vector<double> K((size_t)TP * NUP, 0.0);
+    // PSF kernel K[n][p] of each trajectory class (n < T, p < NU; zero padding
+    // elsewhere), class 1 being the raster's backward sweep:
+    // xi_n = a sin(phi_n) + dir S (n/T - 1/2), v_n = a phi' cos(phi_n) + dir S/T.
+    const size_t KE = (size_t)TP * NUP;
+    pl->k_elems = KE;
+    std::vector<double> K(KE * n_classes, 0.0);
     {
         const double om = 2.0 * kPi * pl->P / T;
-        for (int n = 0; n < T; ++n) {
-            double ph = om * n;
-            double xi = pl->a * std::sin(ph), v = pl->a * om * std::cos(ph);
-            for (int p = 0; p < NU; ++p)
-                K[(size_t)n * NUP + p] = v * langevin_deriv((xi - (p - cu)) / pl->w) / pl->w;
+        for (int cl = 0; cl < n_classes; ++cl) {
+            const double dir = cl == 0 ? 1.0 : -1.0, S = pl->raster_sweep;
+            double *Kc = &K[KE * cl];
+            for (int n = 0; n < T; ++n) {
+                double ph = om * n;
+                double xi = pl->a * std::sin(ph) + dir * S * ((double)n / T - 0.5);
+                double v = pl->a * om * std::cos(ph) + dir * S / T;
+                for (int p = 0; p < NU; ++p)
+                    Kc[(size_t)n * NUP + p] = v * langevin_deriv((xi - (p - cu)) / pl->w) / pl->w;
+            }
         }
     }
     // band DFT F[n][c] (real columns: 2j = Re, 2j+1 = Im)
@@ -327,16 +342,16 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     o_cs = place(sizeof(float2) * M);
     o_ax = place(sizeof(float) * M * NU);
     o_ay = place(sizeof(float) * M * NU);
-    o_kf = place(sizeof(float) * (size_t)TP * NUP);
+    o_kf = place(sizeof(float) * KE * n_classes);
     o_ff = place(sizeof(float) * (size_t)TP * NBP2);
     o_fa = place(sizeof(float) * (size_t)TP * NBP2);
-    o_ka = place(sizeof(float) * (size_t)TP * NUP);
+    o_ka = place(sizeof(float) * KE * n_classes);
     const size_t o_gt = precomp ? place(sizeof(float) * gt.size()) : 0;
     if (mixed) {
-        o_kf16 = place(sizeof(__half) * (size_t)TP * NUP);
+        o_kf16 = place(sizeof(__half) * KE * n_classes);
         o_ff16 = place(sizeof(__half) * (size_t)TP * NBP2);
         o_fa16 = place(sizeof(__half) * (size_t)TP * NBP2);
-        o_ka16 = place(sizeof(__half) * (size_t)TP * NUP);
+        o_ka16 = place(sizeof(__half) * KE * n_classes);
         o_cols = place(sizeof(float) * NBP2);
         o_bands = place(sizeof(float) * NBP2);
     }
@@ -351,13 +366,23 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     //  ka: adj GEMM2 B operand  K[t = 32c + tperm(s, l/32)][32pt + l%32]  [c][pt][s/4][l][s%4]
     // tperm(s, h) = 8(s/4) + 4h + s%4 is the time index that the 32x32 MFMA
     // result layout leaves in register s of lane half h.
-    std::vector<float> kf((size_t)TP * NUP), ff((size_t)TP * NBP2), fa((size_t)TP * NBP2), ka((size_t)TP * NUP);
+    std::vector<float> kf(KE * n_classes), ff((size_t)TP * NBP2), fa((size_t)TP * NBP2), ka(KE * n_classes);
     auto tperm = [](int s, int h) { return 8 * (s / 4) + 4 * h + (s % 4); };
+    for (int cl = 0; cl < n_classes; ++cl)
+        for (int c = 0; c < NC; ++c) {
+            const double *Kc = &K[KE * cl];
+            float *kfc = &kf[KE * cl], *kac = &ka[KE * cl];
+            for (int st = 0; st < NUP / 2; ++st)
+                for (int l = 0; l < 64; ++l)
+                    kfc[(((size_t)c * (NUP / 8) + st / 4) * 64 + l) * 4 + st % 4] =
+                        (float)Kc[(size_t)(32 * c + l % 32) * NUP + 2 * st + l / 32];
+            for (int pt = 0; pt < NUP / 32; ++pt)
+                for (int s = 0; s < 16; ++s)
+                    for (int l = 0; l < 64; ++l)
+                        kac[((((size_t)c * (NUP / 32) + pt) * 4 + s / 4) * 64 + l) * 4 + s % 4] =
+                            (float)Kc[(size_t)(32 * c + tperm(s, l / 32)) * NUP + 32 * pt + l % 32];
+        }
     for (int c = 0; c < NC; ++c) {
-        for (int st = 0; st < NUP / 2; ++st)
-            for (int l = 0; l < 64; ++l)
-                kf[(((size_t)c * (NUP / 8) + st / 4) * 64 + l) * 4 + st % 4] =
-                    (float)K[(size_t)(32 * c + l % 32) * NUP + 2 * st + l / 32];
         for (int ct = 0; ct < NCT; ++ct)
             for (int s = 0; s < 16; ++s)
                 for (int l = 0; l < 64; ++l)
@@ -367,11 +392,6 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             for (int l = 0; l < 64; ++l)
                 fa[(((size_t)c * (NBP2 / 8) + st / 4) * 64 + l) * 4 + st % 4] =
                     (float)F[(size_t)(32 * c + l % 32) * NBP2 + 2 * st + l / 32];
-        for (int pt = 0; pt < NUP / 32; ++pt)
-            for (int s = 0; s < 16; ++s)
-                for (int l = 0; l < 64; ++l)
-                    ka[((((size_t)c * (NUP / 32) + pt) * 4 + s / 4) * 64 + l) * 4 + s % 4] =
-                        (float)K[(size_t)(32 * c + tperm(s, l / 32)) * NUP + 32 * pt + l % 32];
     }
 
     // Mixed (fp16) tables with power-of-two scales.
@@ -389,12 +409,13 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         // its response to a unit source at each of a few detector positions.
         std::vector<double> bnorm(NB / (2 * pl->half_band + 1), 0.0);
         int nbands = (int)bnorm.size(), bw = 2 * pl->half_band + 1;
-        for (int probe = 1; probe <= 3; ++probe) {
-            int p = probe * NU / 4;
+        for (int probe = 0; probe < 3 * n_classes; ++probe) {
+            const int p = (probe % 3 + 1) * NU / 4;
+            const double *Kc = &K[KE * (probe / 3)];
             for (int j = 0; j < NB; ++j) {
                 double re = 0, im = 0;
                 for (int n = 0; n < T; ++n) {
-                    double kv = K[(size_t)n * NUP + p];
+                    double kv = Kc[(size_t)n * NUP + p];
                     re += kv * F[(size_t)n * NBP2 + 2 * j];
                     im += kv * F[(size_t)n * NBP2 + 2 * j + 1];
                 }
@@ -425,16 +446,27 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         //  ka16: adj GEMM2 B: K[t = 32c + 16h + tperm16(e, l/32)][32pt + l%32]   [c][pt][h][l][e]
         // tperm16(e, h) = 8(e/4) + 4h + e%4.
         auto tp16 = [](int e, int h) { return 8 * (e / 4) + 4 * h + (e % 4); };
-        kf16.resize((size_t)TP * NUP);
+        kf16.resize(KE * n_classes);
         ff16.resize((size_t)TP * NBP2);
         fa16.resize((size_t)TP * NBP2);
-        ka16.resize((size_t)TP * NUP);
+        ka16.resize(KE * n_classes);
+        for (int cl = 0; cl < n_classes; ++cl)
+            for (int c = 0; c < NC; ++c) {
+                const double *Kc = &K[KE * cl];
+                _Float16 *kfc = &kf16[KE * cl], *kac = &ka16[KE * cl];
+                for (int st = 0; st < NUP / 16; ++st)
+                    for (int l = 0; l < 64; ++l)
+                        for (int e2 = 0; e2 < 8; ++e2)
+                            kfc[(((size_t)c * (NUP / 16) + st) * 64 + l) * 8 + e2] =
+                                to_f16(Kc[(size_t)(32 * c + l % 32) * NUP + 16 * st + 8 * (l / 32) + e2] * ks);
+                for (int pt = 0; pt < NUP / 32; ++pt)
+                    for (int h = 0; h < 2; ++h)
+                        for (int l = 0; l < 64; ++l)
+                            for (int e2 = 0; e2 < 8; ++e2)
+                                kac[((((size_t)c * (NUP / 32) + pt) * 2 + h) * 64 + l) * 8 + e2] = to_f16(
+                                    Kc[(size_t)(32 * c + 16 * h + tp16(e2, l / 32)) * NUP + 32 * pt + l % 32] * ks);
+            }
         for (int c = 0; c < NC; ++c) {
-            for (int st = 0; st < NUP / 16; ++st)
-                for (int l = 0; l < 64; ++l)
-                    for (int e2 = 0; e2 < 8; ++e2)
-                        kf16[(((size_t)c * (NUP / 16) + st) * 64 + l) * 8 + e2] =
-                            to_f16(K[(size_t)(32 * c + l % 32) * NUP + 16 * st + 8 * (l / 32) + e2] * ks);
             for (int ct = 0; ct < NCT; ++ct)
                 for (int h = 0; h < 2; ++h)
                     for (int l = 0; l < 64; ++l)
@@ -448,12 +480,6 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
                         fa16[(((size_t)c * (NBP2 / 16) + st) * 64 + l) * 8 + e2] =
                             to_f16(F[(size_t)(32 * c + l % 32) * NBP2 + col] * fcol[col]);
                     }
-            for (int pt = 0; pt < NUP / 32; ++pt)
-                for (int h = 0; h < 2; ++h)
-                    for (int l = 0; l < 64; ++l)
-                        for (int e2 = 0; e2 < 8; ++e2)
-                            ka16[((((size_t)c * (NUP / 32) + pt) * 2 + h) * 64 + l) * 8 + e2] = to_f16(
-                                K[(size_t)(32 * c + 16 * h + tp16(e2, l / 32)) * NUP + 32 * pt + l % 32] * ks);
         }
         // undo factors applied to the adjoint: result = acc / (fs * ks * row_scale)
         (void)ef;
@@ -540,8 +566,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
         };
         int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2, pl->ngroups,
-                      pl->gct, precisions};
-        double dbl[] = {pl->P, pl->a, pl->w};
+                      pl->gct, precisions, n_classes};
+        double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep};
         mix(ints, sizeof(ints));
         mix(dbl, sizeof(dbl));
         if (g->rx_filter) mix(g->rx_filter, sizeof(float) * 2 * pl->nb);

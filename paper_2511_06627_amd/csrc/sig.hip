@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
     float R[NUP / 4];
     {
         const int p0 = bp.half * (NUP / 2);
-        const float *rin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride + p0 + h;
+        const float *rin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride + p0 + h;
 #pragma unroll
         for (int st = 0; st < NUP / 4; ++st) R[st] = (rok && p0 + 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
     }
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
     const int ctb = bp.group * 2 * GH + bp.half * GH;     // first column tile of this wave
     const int kst0 = bp.half * (NUP / 16);                 // first K float4 step of this half
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
-    const f32x4 *kf = (const f32x4 *)a.kf + lane;
+    const f32x4 *kf = (const f32x4 *)job.kf + lane;
     const f32x4 *ff = (const f32x4 *)a.ff + lane;
     auto load = [&](int cc, int i) -> f32x4 {
         if (i < NK) return kf[((size_t)cc * (NUP / 8) + kst0 + i) * 64];
@@ -170,6 +170,12 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
         }
     }
     if (bp.row0 >= job.rows) return;
+    long ln[16];   // buffer lines of this lane's 16 result rows
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
+        ln[j] = row < job.rows ? job_line(job, row) : 0;
+    }
     float *out = job.part + (size_t)bp.split * job.part_stride;
 #pragma unroll
     for (int g = 0; g < GH; ++g) {
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
-            if (row < job.rows) out[(size_t)row * a.nbp2 + col] = acc[g][j];
+            if (row < job.rows) out[(size_t)ln[j] * a.nbp2 + col] = acc[g][j];
         }
     }
 }
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
     // B operand of GEMM1: y[r][colbase + 2 st + h]
     float Y[16 * GH];
     {
-        const float *yin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride + colbase + h;
+        const float *yin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride + colbase + h;
 #pragma unroll
         for (int st = 0; st < 16 * GH; ++st) {
             const int col = colbase + 2 * st + h;
@@ -218,7 +224,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
 
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
     const f32x4 *fa = (const f32x4 *)a.fa + lane;
-    const f32x4 *ka = (const f32x4 *)a.ka + lane;
+    const f32x4 *ka = (const f32x4 *)job.ka + lane;
     auto load = [&](int cc, int i) -> f32x4 {
         if (i < NF) return fa[((size_t)cc * (a.nbp2 / 8) + colbase / 8 + i) * 64];
         const int j = i - NF, s4 = j / PTH, pt = j % PTH;
@@ -255,6 +261,12 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
         }
     }
     if (bp.row0 >= job.rows) return;
+    long ln[16];   // buffer lines of this lane's 16 result rows
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
+        ln[j] = row < job.rows ? job_line(job, row) : 0;
+    }
     float *out = job.part + (size_t)(bp.split * a.ngroups + bp.group) * job.part_stride;
 #pragma unroll
     for (int pt = 0; pt < PTH; ++pt) {
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
-            if (row < job.rows) out[(size_t)row * NUP + col] = racc[pt][j];
+            if (row < job.rows) out[(size_t)ln[j] * NUP + col] = racc[pt][j];
         }
     }
 }

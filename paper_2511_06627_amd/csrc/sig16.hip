@@ -148,8 +148,8 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 
     // this wave's half of the line, scaled by the line's power-of-two scale
     // (row_scale kernel), as fp16 B operands
-    const float *rin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride;
-    const float rs = rok ? job.row_scale[r] : 1.f;
+    const float *rin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride;
+    const float rs = rok ? job.row_scale[job_line(job, r)] : 1.f;
     f16x8 R[NKS];
     {
         const int p0 = bp.half * (NUP / 2);
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
     for (int g = 0; g < GH; ++g) acc[g] = 0.f;
 
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
-    const f16x8 *kg = (const f16x8 *)a.kf16;
+    const f16x8 *kg = (const f16x8 *)job.kf16;
     const f16x8 *fg = (const f16x8 *)a.ff16 + (size_t)bp.group * UB;
     const size_t fstride = (size_t)a.nct * 128;
     Slice<UA> sa;
@@ -203,6 +203,12 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
             for (int g = 0; g < GH; ++g) acc[g] = MFMA16(S16[hh], fb[(g * 2 + hh) * 64], acc[g]);
     }
     if (bp.row0 >= job.rows) return;
+    long ln[16];   // buffer lines of this lane's 16 result rows
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
+        ln[j] = row < job.rows ? job_line(job, row) : 0;
+    }
     float *out = job.part + (size_t)bp.split * job.part_stride;
     const int ctb = bp.group * 2 * GH + bp.half * GH;
 #pragma unroll
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
-            if (row < job.rows) out[(size_t)row * a.nbp2 + col] = acc[g][j];
+            if (row < job.rows) out[(size_t)ln[j] * a.nbp2 + col] = acc[g][j];
         }
     }
 }
@@ -237,8 +243,8 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     const int pt0 = bp.half * PTH;
 
     // the line's power-of-two scale over the band-scaled row (row_scale kernel)
-    const float *yin = (const float *)job.in + (size_t)(rok ? r : 0) * job.in_stride;
-    const float ys = rok ? job.row_scale[r] : 1.f;
+    const float *yin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride;
+    const float ys = rok ? job.row_scale[job_line(job, r)] : 1.f;
     f16x8 Y[NF];
 #pragma unroll
     for (int st = 0; st < NF; ++st)
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
     const size_t fstride = (size_t)a.nct * 128;
     const f16x8 *fg = (const f16x8 *)a.fa16 + (size_t)bp.group * UA;
-    const f16x8 *kg = (const f16x8 *)a.ka16;
+    const f16x8 *kg = (const f16x8 *)job.ka16;
     Slice<UA> sa;
     Slice<UB> sb;
     if (c0 < c1) {
@@ -289,6 +295,12 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
             for (int pt = 0; pt < PTH; ++pt) racc[pt] = MFMA16(G16[hh], kb[(pt * 2 + hh) * 64], racc[pt]);
     }
     if (bp.row0 >= job.rows) return;
+    long ln[16];   // buffer lines of this lane's 16 result rows
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
+        ln[j] = row < job.rows ? job_line(job, row) : 0;
+    }
     float *out = job.part + (size_t)(bp.split * a.ngroups + bp.group) * job.part_stride;
 #pragma unroll
     for (int pt = 0; pt < PTH; ++pt) {
@@ -296,7 +308,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
-            if (row < job.rows) out[(size_t)row * NUP + col] = racc[pt][j];
+            if (row < job.rows) out[(size_t)ln[j] * NUP + col] = racc[pt][j];
         }
     }
 }
