@@ -567,6 +567,31 @@ def main():
     log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * dtp / args.steps, ktp))
     del planp, wsp
 
+    # the same scan under a zig-zag raster (two PSF tables, per-line sweep
+    # direction): drive over a sixth of the fast axis, the focus field carrying
+    # the line across two thirds of it
+    ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
+    planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
+                 cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
+    wsr = planr.workspace("op")
+    raster = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale}
+    for prec in ("fp32", "mixed"):
+        def stepr():
+            planr.forward(x, precision=prec, out=yb, ws=wsr)
+            planr.adjoint(yb, precision=prec, out=xo, ws=wsr)
+
+        for _ in range(args.warmup):
+            stepr()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            stepr()
+        torch.cuda.synchronize()
+        dtr = time.perf_counter() - t0
+        raster[prec] = {"applies_per_s": round(args.steps / dtr, 2), "ms_per_step": round(1e3 * dtr / args.steps, 4)}
+    log("raster A^T A: %s" % raster)
+    del planr, wsr
+
     # CGLS iteration rate of the configured 50-iteration solve
     swk = plan.workspace("solve")
     plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
@@ -655,6 +680,7 @@ def main():
         "paper_solver": paper_solver,
         "mixed": mixed,
         "precomposed": precomposed,
+        "raster": raster,
         "serving": serve,
         "hdr": hdr,
         "oracle_small": cpu.get("oracle_small") if cpu is not None else None,

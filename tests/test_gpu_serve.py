@@ -22,23 +22,30 @@ def torch_mod():
     return torch
 
 
-# Two line classes (n_u, T, bands): A-class geometries differ in nz / M but
-# share line tables; B has another T.
+# Three line-table classes (n_u, T, bands, raster sweep S): A-class geometries
+# differ in nz / M but share line tables; B has another T; the R-class raster
+# scans (two PSF tables each, odd and even nz) share theirs.
 GEOS = {
-    "A1": (48, 48, 12, 6, 2048, 1, 12, 2),
-    "A2": (48, 48, 20, 9, 2048, 1, 12, 2),
-    "B1": (64, 64, 16, 8, 4096, 1, 16, 3),
+    "A1": (48, 48, 12, 6, 2048, 1, 12, 2, 0.0),
+    "A2": (48, 48, 20, 9, 2048, 1, 12, 2, 0.0),
+    "B1": (64, 64, 16, 8, 4096, 1, 16, 3, 0.0),
+    "R1": (48, 48, 7, 5, 2048, 1, 12, 2, 20.0),
+    "R2": (48, 48, 10, 6, 2048, 1, 12, 2, 20.0),
 }
 
 
 def _request(name, seed):
-    nx, ny, nz, M, T, klo, khi, D = GEOS[name]
+    nx, ny, nz, M, T, klo, khi, D, S = GEOS[name]
     P = T / 256 + 1 / 3
-    g = oop.normalised(oracle_geometry(nx, ny, nz, M, T, P, 3.0, klo, khi, D), iters_min=30, rtol=1e-9)
+    a = 8.0 if S else 0.0          # a raster scan's drive covers a third of the fast axis
+    g = oracle_geometry(nx, ny, nz, M, T, P, 3.0, klo, khi, D)
+    if S:
+        g.drive_amp, g.raster_sweep = a, S
+    g = oop.normalised(g, iters_min=30, rtol=1e-9)
     x = np.random.default_rng(seed).uniform(0, 1, (nz, ny, nx))
     b = oop.forward(g, x).astype(np.complex64)
     geo = dict(nx=nx, ny=ny, nz=nz, n_angles=M, n_t=T, drive_cycles=P, psf_width=3.0, harm_lo=klo, harm_hi=khi,
-               half_band=D, op_scale=g.op_scale)
+               half_band=D, op_scale=g.op_scale, drive_amp=a, raster_sweep=S)
     return g, geo, b
 
 
@@ -95,7 +102,7 @@ def test_continuous_batching_loop(torch_mod, reqs):
     results equal to the same requests solved alone."""
     from paper_2511_06627_amd.serve import ContinuousBatcher, GpuExecutor, Request, summarize
     rng = np.random.default_rng(3000)
-    names = ["A1", "B1", "A2", "A1", "B1", "A2"]
+    names = ["A1", "B1", "R1", "A2", "R2", "A1", "B1", "A2"]
     sched = dict(precision="mixed", refine_sweeps=2, inner_iters=4)
     rq = []
     t = 0.0
