@@ -11,6 +11,10 @@ Readings of the paper used here (each listed in the design doc):
 * The line integral of eq. ptheta2 is a unit-step Riemann sum over ray samples
   y_q = q - (Nr-1)/2, Nr the smallest integer >= sqrt(Nx^2+Ny^2) with the
   parity of Ny, so that at theta = 0 every sample falls on a voxel centre.
+* Tensor PSF coupling: FFL line (m, k) sees the rows k' with |k - k'| <= R
+  (``psf_rows``) of the same angle's projection through the x-x tensor PSF at
+  z-offset k - k' (rows one voxel apart); R >= Nz - 1 is the whole model, R = 0
+  the collinear one.
 * Raster trajectory classes: every angle repeats one scan sequence (Sec. 2.2,
   before eq. modelF1); under a zig-zag raster (Sec. 3.1) the sweep direction
   alternates from line to line, so z-row k sweeps forward when k is even and
@@ -42,6 +46,7 @@ class Geometry:
     theta: np.ndarray = None         # default m*pi/M
     rx_filter: np.ndarray = None     # complex D_Gamma on the kept bins, None = 1
     raster_sweep: float = 0.0        # focus-field shift per line in voxels (0 = none)
+    psf_rows: int = 0                # z-rows coupled by the tensor PSF on each side (0 = collinear)
 
     def __post_init__(self):
         if self.n_u is None:
@@ -76,6 +81,8 @@ class Geometry:
         operator: one slice, or two under a raster (even and odd rows sweep in
         opposite directions)."""
         g = Geometry(**{k: getattr(self, k) for k in self.__dataclass_fields__})
+        if self.psf_rows:
+            return g          # rows are coupled: no smaller equivalent
         g.nz = min(self.nz, 2) if self.raster_sweep else 1
         return g
 

@@ -39,6 +39,8 @@ def _per_class(g, rows_in, fn):
 
 def forward(g, x, precomposed=False):
     rt = projector.project(g, x).reshape(g.n_lines, g.n_u)
+    if precomposed and g.psf_rows:
+        return signal.coupled_apply(g, rt, signal.row_matrices(g)).reshape(g.n_angles, g.nz, g.n_bins)
     if precomposed:
         b = _per_class(g, rt, lambda c, r: r @ signal.line_matrix(g, c).T)
         return b.reshape(g.n_angles, g.nz, g.n_bins)
@@ -47,7 +49,9 @@ def forward(g, x, precomposed=False):
 
 def adjoint(g, y, precomposed=False):
     y = np.asarray(y, dtype=np.complex128).reshape(g.n_lines, g.n_bins)
-    if precomposed:
+    if precomposed and g.psf_rows:
+        lines = np.real(signal.coupled_apply(g, y, [np.conj(C) for C in signal.row_matrices(g)], adjoint=True))
+    elif precomposed:
         lines = _per_class(g, y, lambda c, r: np.real(r @ np.conj(signal.line_matrix(g, c))))
     else:
         lines = signal.adjoint(g, y)
@@ -61,6 +65,14 @@ class Operator:
         self.g = g
         self.precomposed = precomposed
         self.classes = signal.classes_present(g)
+        self.coupled = bool(g.psf_rows)
+        if self.coupled:
+            assert not g.raster_sweep
+            rows = range(signal.coupled_rows(g) + 1)
+            if precomposed:
+                self.Cd = signal.row_matrices(g)
+            else:
+                self.Kd = [signal.kernel_row(g, d) for d in rows]
         if precomposed:
             self.C = {c: signal.line_matrix(g, c) for c in self.classes}
         else:
@@ -91,9 +103,19 @@ class Operator:
         return out
 
     def _lines_fwd(self, rt):
+        if self.coupled and self.precomposed:
+            return signal.coupled_apply(self.g, rt, self.Cd)
+        if self.coupled:
+            s = signal.coupled_apply(self.g, rt, self.Kd)
+            return (s @ self.E_re) + 1j * (s @ self.E_im)
         return _per_class(self.g, rt, self._lines_fwd_class)
 
     def _lines_adj(self, y):
+        if self.coupled and self.precomposed:
+            return np.real(signal.coupled_apply(self.g, y, [np.conj(C) for C in self.Cd], adjoint=True))
+        if self.coupled:
+            h = np.ascontiguousarray(y.real) @ self.E_re.T + np.ascontiguousarray(y.imag) @ self.E_im.T
+            return signal.coupled_apply(self.g, h, self.Kd, adjoint=True)
         return _per_class(self.g, y, self._lines_adj_class)
 
     def forward(self, x):
@@ -142,7 +164,11 @@ def make_data(g, phantom, noise_level, noise_seed):
     rt = projector.project(g, phantom).reshape(g.n_lines, g.n_u)
     cl = signal.row_classes(g, g.n_lines)
 
+    s_all = signal.coupled_apply(g, rt, op.Kd) if op.coupled else None
+
     def clean(a):   # time signals of lines a .. a+511, each through its class's K
+        if s_all is not None:
+            return s_all[a:a + 512]
         s = np.empty((min(512, g.n_lines - a), g.n_t))
         for c in op.classes:
             m = cl[a:a + 512] == c

@@ -14,6 +14,13 @@ Passages followed
   h(u) = L'(u/w)/w with w = H_sat/G0 in voxels (collinear reduction).
 * Sinusoidal drive H_D = A sin(2 pi f0 t): eq. HD; FFL position
   xi(t) = a sin(phi(t)) follows from eq. H1 (H = G(xi - x)).
+* Tensor PSF across z-rows (Appendix B, eq. PSF, in the xz-plane where the 2D
+  FFL model of Sec. 2.2 acts): with the in-plane gradient of equal magnitude g
+  on both axes (zero trace with the FFL direction's zero gradient; the sign
+  pattern does not change the xx entry), drive and receive coil along the fast
+  axis, and d = (du, dz) the offset of the line centre from a point,
+  h_xx(d) = L'(r/w)/w du^2/r^2 + L(r/w) dz^2/r^3 with r = |d| and w = H_sat/g.
+  On the line's own row (dz = 0) it is the collinear L'(|du|/w)/w.
 * Raster (Sec. 3.1, the scanner's acquisition): a slow focus field moves the
   line across the field of view in a zig-zag, back and forth along the fast
   axis.  Reading: during one FFL line the centre moves at constant speed over
@@ -113,6 +120,31 @@ def langevin_deriv(x):
     e = np.exp(-2.0 * xc)
     out[c] = 1.0 / (xc * xc) - 4.0 * e / (1.0 - e) ** 2
     return out
+
+
+def psf_xx(du, dz, psf_width):
+    """h_xx(du, dz) of the tensor PSF (see the module notes), real du, one dz."""
+    du = np.asarray(du, dtype=np.float64)
+    w = psf_width
+    if dz == 0:
+        return langevin_deriv(du / w) / w
+    r2 = du * du + float(dz) * float(dz)
+    r = np.sqrt(r2)
+    return langevin_deriv(r / w) / w * (du * du / r2) + langevin(r / w) * (float(dz) * float(dz) / (r2 * r))
+
+
+def magnetisation_x(t, drive_cycles, n_t, drive_amp, psf_width, u, rho_line, op_scale, dz):
+    """x-component of the magnetisation of a row dz away from the line,
+    m_x(t) = c_A sum_p rho_p L(|d|/w) du/|d|, d = (xi(t) - u_p, dz): the unit
+    vector G d/|G d| of eq. PSF's derivation in the xz-plane.  t real or
+    complex; used only to pin psf_xx through s0 = dm/dt (eq. s01)."""
+    t = np.asarray(t)
+    omega = 2.0 * np.pi * drive_cycles / n_t
+    du = drive_amp * np.sin(omega * t)[..., None] - np.asarray(u)[None, :]
+    if dz == 0:
+        return op_scale * (langevin(du / psf_width) * np.asarray(rho_line)[None, :]).sum(axis=-1)
+    r = np.sqrt(du * du + float(dz) * float(dz))
+    return op_scale * (langevin(r / psf_width) * du / r * np.asarray(rho_line)[None, :]).sum(axis=-1)
 
 
 def trajectory(n_t, drive_cycles, drive_amp, sweep=0.0, direction=1.0):

@@ -7,7 +7,10 @@ Per FFL line l = (angle m, z-row k) with projection rho_theta[l, :]:
 1. Time signal (eq. stheta1 with the collinear PSF of Appendix B eq. PSF,
    B = I):  s[l, n] = c_A v_n sum_p rho_theta[l, p] L'((xi_n - u_p)/w) / w,
    with xi and v those of the line's trajectory class (one class, or two
-   under a raster: ``geometry.line_classes``).
+   under a raster: ``geometry.line_classes``).  With the tensor PSF coupling
+   rows (``psf_rows`` = R > 0) the sum also runs over the rows k' of the same
+   angle with |k - k'| <= R, through h_xx at z-offset k - k'
+   (``physics.psf_xx``, ``kernel_row``, ``coupled_apply``).
 2. Compression (eq. bcompress, eq. DCmodel, Appendix A):
    b[l, j] = D_Gamma[j] T^{-1/2} sum_n s[l, n] exp(+2 pi i omega_j n / T),
    the unitary DFT of Appendix A (plus sign, 1/sqrt(N)) restricted to the
@@ -31,7 +34,7 @@ precomposed vs time-domain path.
 import numpy as np
 
 from .geometry import detector_grid, kept_bins, line_classes
-from .physics import psf_kernel
+from .physics import psf_kernel, psf_xx, trajectory
 
 _LINE_BLOCK = 512  # lines per block, bounds the (lines x T) temporaries
 
@@ -58,6 +61,38 @@ def kernel(g, cls=0):
                       g.raster_sweep, direction)
 
 
+def kernel_row(g, d):
+    """K_d[n, p] = c_A v_n h_xx(xi_n - u_p, d): the table coupling a line to
+    the row d voxels away (tensor PSF; K_0 is the collinear ``kernel``)."""
+    xi, v = trajectory(g.n_t, g.drive_cycles, g.drive_amp)
+    du = xi[:, None] - detector_grid(g)[None, :]
+    return g.op_scale * v[:, None] * psf_xx(du, d, g.psf_width)
+
+
+def coupled_rows(g):
+    return min(g.psf_rows, g.nz - 1)
+
+
+def coupled_apply(g, rows, mats, adjoint=False):
+    """The row-coupled map over all L lines in line order: forward
+    out[m, k] = sum_{|d| <= R} rows[m, k + d] @ mats[|d|].T, adjoint its
+    transpose out[m, k + d] += rows[m, k] @ mats[|d|]."""
+    R = coupled_rows(g)
+    rr = rows.reshape(g.n_angles, g.nz, -1)
+    width = mats[0].shape[1] if adjoint else mats[0].shape[0]
+    out = np.zeros((g.n_angles, g.nz, width), dtype=np.result_type(rows, mats[0]))
+    for d in range(-R, R + 1):
+        lo, hi = max(0, -d), min(g.nz, g.nz - d)
+        if lo >= hi:
+            continue
+        M = mats[abs(d)]
+        if adjoint:
+            out[:, lo + d:hi + d] += rr[:, lo:hi] @ M
+        else:
+            out[:, lo:hi] += rr[:, lo + d:hi + d] @ M.T
+    return out.reshape(g.n_lines, width)
+
+
 def classes_present(g):
     return (0, 1) if g.raster_sweep and g.nz > 1 else (0,)
 
@@ -78,6 +113,9 @@ def time_signal(g, rho_theta, K=None):
     r = np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u)
     if K is not None:
         return r @ K.T
+    if g.psf_rows:
+        assert r.shape[0] == g.n_lines
+        return coupled_apply(g, r, [kernel_row(g, d) for d in range(coupled_rows(g) + 1)])
     cl = row_classes(g, r.shape[0])
     out = np.empty((r.shape[0], g.n_t))
     for c in classes_present(g):
@@ -95,8 +133,12 @@ def compress(g, s, E=None):
 def forward(g, rho_theta):
     """Lines (L, Nu) -> compressed data (L, nb), time-domain path, block over lines."""
     r = np.asarray(rho_theta, dtype=np.float64).reshape(-1, g.n_u)
-    cl = row_classes(g, r.shape[0])
     E = dft_matrix(g)
+    if g.psf_rows:
+        assert r.shape[0] == g.n_lines and not g.raster_sweep
+        s = coupled_apply(g, r, [kernel_row(g, d) for d in range(coupled_rows(g) + 1)])
+        return compress(g, s, E)
+    cl = row_classes(g, r.shape[0])
     out = np.empty((r.shape[0], g.n_bins), dtype=np.complex128)
     for c in classes_present(g):
         K = kernel(g, c)
@@ -110,8 +152,12 @@ def forward(g, rho_theta):
 def adjoint(g, y):
     """Compressed data (L, nb) -> lines (L, Nu): Re of the Hermitian transpose."""
     y = np.asarray(y, dtype=np.complex128).reshape(-1, g.n_bins)
-    cl = row_classes(g, y.shape[0])
     E = dft_matrix(g)
+    if g.psf_rows:
+        assert y.shape[0] == g.n_lines and not g.raster_sweep
+        h = np.real(y @ np.ascontiguousarray(np.conj(E).T))
+        return coupled_apply(g, h, [kernel_row(g, d) for d in range(coupled_rows(g) + 1)], adjoint=True)
+    cl = row_classes(g, y.shape[0])
     out = np.empty((y.shape[0], g.n_u), dtype=np.float64)
     for c in classes_present(g):
         K = kernel(g, c)
@@ -126,6 +172,12 @@ def adjoint(g, y):
 def line_matrix(g, cls=0):
     """C[j, p] = sum_n E[n, j] K[n, p]: the per-line operator of class cls, precomposed."""
     return dft_matrix(g).T @ kernel(g, cls)
+
+
+def row_matrices(g):
+    """C_d = E^T K_d, d = 0..R: the coupled model precomposed per row offset."""
+    E = dft_matrix(g)
+    return [E.T @ kernel_row(g, d) for d in range(coupled_rows(g) + 1)]
 
 
 def information_retained(s, bins):

@@ -133,3 +133,37 @@ def test_raster_trajectory_closed_form():
     assert np.max(np.abs(xi_b - xi0 + S * (n / T - 0.5))) < 1e-12
     assert abs(xi_f[0] - (xi0[0] - S / 2)) < 1e-12
     assert np.max(np.abs(v_f - v0 - S / T)) < 1e-15 and np.max(np.abs(v_b - v0 + S / T)) < 1e-15
+
+
+def test_tensor_psf_is_derivative_of_magnetisation_x():
+    """Rows dz away from the line: s_n = c_A v_n sum_p rho_p h_xx(xi_n - u_p, dz)
+    must be d/dt of the x-component of the magnetisation c_A sum rho L(|d|/w)
+    d_x/|d| (complex step), which pins both terms of eq. PSF's xx entry."""
+    g = Geometry(nx=24, ny=24, nz=1, n_angles=1, n_t=512, drive_cycles=3.7, psf_width=2.5,
+                 harm_lo=1, harm_hi=5, half_band=1, op_scale=1.1)
+    rng = np.random.default_rng(14)
+    rho = rng.uniform(0.0, 1.0, g.n_u)
+    u = detector_grid(g)
+    h = 1e-30
+    t = np.arange(g.n_t) + 1j * h
+    for dz in (0, 1, 2, 5, 9):
+        s = rho @ signal.kernel_row(g, dz).T
+        dm = physics.magnetisation_x(t, g.drive_cycles, g.n_t, g.drive_amp, g.psf_width, u, rho,
+                                     g.op_scale, dz).imag / h
+        assert np.max(np.abs(s - dm)) <= 1e-12 * np.max(np.abs(dm)), dz
+
+
+def test_tensor_psf_closed_forms():
+    """h_xx(0, dz) = L(|dz|/w)/|dz| (only the transverse term), symmetry in du
+    and dz, the collinear kernel on the row itself, and the saturated far
+    field h_xx(0, dz) -> 1/|dz|."""
+    w = 2.0
+    for dz in (1, 3, 7):
+        want = float(_mp_L(dz / w)) / dz
+        assert abs(physics.psf_xx(np.array([0.0]), dz, w)[0] - want) <= 1e-14 * want
+        assert abs(physics.psf_xx(np.array([0.0]), -dz, w)[0] - want) <= 1e-14 * want
+    du = np.linspace(-9, 9, 37)
+    assert np.array_equal(physics.psf_xx(du, 2, w), physics.psf_xx(-du, 2, w))
+    assert np.max(np.abs(physics.psf_xx(du, 0, w) - physics.langevin_deriv(du / w) / w)) == 0.0
+    far = physics.psf_xx(np.array([0.0]), 400, w)[0]
+    assert abs(far * 400 - 1.0) < 2 * w / 400

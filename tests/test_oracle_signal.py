@@ -159,3 +159,54 @@ def test_raster_signal_adjoint_identity_and_precomposed():
     cl = np.tile(np.arange(g.nz) % 2, g.n_angles)
     pre = np.where((cl == 0)[:, None], r @ signal.line_matrix(g, 0).T, r @ signal.line_matrix(g, 1).T)
     assert np.max(np.abs(fr - pre)) <= 1e-13 * np.max(np.abs(fr))
+
+
+def _brute_coupled_time_signal(g, rho):
+    """s[m, k, n] = c_A v_n sum_{k', p} rho[m, k', p] h_xx(xi_n - u_p, k - k'),
+    |k - k'| <= R, written out element by element."""
+    from oracle import physics
+    xi, v = physics.trajectory(g.n_t, g.drive_cycles, g.drive_amp)
+    u = detector_grid(g)
+    R = min(g.psf_rows, g.nz - 1)
+    s = np.zeros((g.n_angles, g.nz, g.n_t))
+    for m in range(g.n_angles):
+        for k in range(g.nz):
+            for k2 in range(g.nz):
+                if abs(k - k2) > R:
+                    continue
+                for p in range(g.n_u):
+                    h = physics.psf_xx(xi - u[p], k - k2, g.psf_width)
+                    s[m, k] += g.op_scale * v * h * rho[m, k2, p]
+    return s.reshape(g.n_lines, g.n_t)
+
+
+def test_tensor_coupled_time_signal_brute_force():
+    """The row-coupled time signal against the element formula, for the whole
+    model (R >= nz - 1) and a truncated one; R = 0 is the collinear signal."""
+    for R in (4, 1):
+        g = _geom(nx=8, ny=8, nz=4, n_angles=2, n_t=128, drive_cycles=128 / 32 + 1 / 3, harm_hi=3,
+                  half_band=1, psf_rows=R, op_scale=0.9)
+        rho = np.random.default_rng(15).uniform(0, 1, (g.n_angles, g.nz, g.n_u))
+        got = signal.time_signal(g, rho.reshape(g.n_lines, g.n_u))
+        want = _brute_coupled_time_signal(g, rho)
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want)), R
+    g0 = _geom(nx=8, ny=8, nz=4, n_angles=2, n_t=128, drive_cycles=128 / 32 + 1 / 3, harm_hi=3, half_band=1)
+    g1 = _geom(nx=8, ny=8, nz=4, n_angles=2, n_t=128, drive_cycles=128 / 32 + 1 / 3, harm_hi=3, half_band=1,
+               psf_rows=1)
+    rho = np.random.default_rng(16).uniform(0, 1, (g0.n_lines, g0.n_u))
+    s0 = signal.time_signal(g0, rho)
+    s1 = signal.time_signal(g1, rho)
+    assert np.max(np.abs(s1 - s0)) > 1e-3 * np.max(np.abs(s0))      # the coupling is not negligible
+
+
+def test_tensor_coupled_adjoint_and_precomposed():
+    g = _geom(nz=6, n_angles=2, psf_rows=2, op_scale=0.5)
+    rng = np.random.default_rng(17)
+    r = rng.standard_normal((g.n_lines, g.n_u))
+    y = rng.standard_normal((g.n_lines, g.n_bins)) + 1j * rng.standard_normal((g.n_lines, g.n_bins))
+    fr = signal.forward(g, r)
+    lhs = np.vdot(fr, y).real
+    rhs = np.vdot(r, signal.adjoint(g, y))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    pre = signal.coupled_apply(g, r, signal.row_matrices(g))
+    assert np.max(np.abs(fr - pre)) <= 1e-13 * np.max(np.abs(fr))
