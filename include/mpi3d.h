@@ -126,6 +126,17 @@ typedef struct {
                                     xi_n = a sin(2 pi P n/T) + c_n and v_n = xi' gains
                                     +-S/T.  With S != 0 and nz >= 2 the plan holds two
                                     PSF tables; MPI3D_PRECOMPOSED is then MPI3D_ENOTSUP */
+    int32_t psf_rows;            /* R >= 0: z-rows coupled by the tensor PSF on each side
+                                    (Appendix B eq. PSF, xx entry in the xz-plane of the 2D
+                                    FFL model of Sec. 2.2, in-plane gradient of equal
+                                    magnitude on both axes): line (m, k) also sees rows k'
+                                    of angle m with |k - k'| <= R through
+                                    h_xx(du, dz) = L'(r/w)/w du^2/r^2 + L(r/w) dz^2/r^3,
+                                    r = |(du, dz)|, dz = k - k'.  0 = the collinear PSF;
+                                    values above nz - 1 act as nz - 1 (the whole model).
+                                    R > 0 costs 2R + 1 signal passes per application and
+                                    is FP32 only: MPI3D_MIXED or MPI3D_PRECOMPOSED in
+                                    precisions, or raster_sweep != 0, is MPI3D_ENOTSUP */
 } mpi3d_geometry;
 
 typedef struct mpi3d_plan mpi3d_plan;

@@ -33,6 +33,7 @@ class Geometry(ctypes.Structure):
         ("op_scale", ctypes.c_double),
         ("precisions", ctypes.c_int32),
         ("raster_sweep", ctypes.c_double),
+        ("psf_rows", ctypes.c_int32),
     ]
 
 

@@ -92,42 +92,49 @@ static SigArgs sig_args(const mpi3d_plan *pl, bool serve)
 
 static int nsplit_of(const mpi3d_plan *pl, bool serve) { return serve ? pl->serve_nsplit : pl->nsplit; }
 
-// The kernel jobs of one line job, one per trajectory class: class c holds the
-// lines (m, k) with k % n_classes == c, i.e. per angle ceil((nz - c) /
-// n_classes) lines n_classes apart, and that class's PSF tables.
-static int class_jobs(const LineJob &lj, bool fwd, SigJob *out)
+// The kernel jobs of one line job: one per trajectory class and z-row offset
+// of the tensor PSF.  Class c holds the lines (m, k) with k % n_classes == c,
+// i.e. per angle ceil((nz - c) / n_classes) lines n_classes apart; offset pass
+// p reads line (m, k + d), d = p - psf_rows, through table |d| and writes its
+// own block of split partial sums, which the reductions add with the others.
+static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJob> &out)
 {
     const mpi3d_plan *pj = lj.pl;
-    const int nc = pj->n_classes;
-    for (int c = 0; c < nc; ++c) {
-        SigJob &sj = out[c];
-        sj = SigJob{};
-        sj.in = lj.in;
-        sj.in_stride = lj.in_stride;
-        sj.part = lj.w->part;
-        sj.part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
-        sj.row_scale = lj.w->rowscale;
-        const size_t ko = (size_t)c * pj->k_elems;
-        sj.kf = pj->kf + ko;
-        sj.ka = pj->ka + ko;
-        sj.kf16 = pj->kf16 ? pj->kf16 + ko : nullptr;
-        sj.ka16 = pj->ka16 ? pj->ka16 + ko : nullptr;
-        if (nc == 1) {
-            sj.rows = (int)pj->L;
-            sj.map_per = std::max(1, sj.rows);
-            sj.map_nz = 0;
-            sj.map_off = 0;
-            sj.map_step = 1;
-        } else {
-            const int per = (pj->nz - c + nc - 1) / nc;
-            sj.rows = pj->M * per;
-            sj.map_per = per;
-            sj.map_nz = pj->nz;
-            sj.map_off = c;
-            sj.map_step = nc;
+    const int nc = pj->n_classes, R = pj->psf_rows;
+    const long part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
+    const long pass_stride = (long)(serve ? pj->serve_nsplit : pj->nsplit) * (fwd ? 1 : pj->ngroups) * part_stride;
+    for (int c = 0; c < nc; ++c)
+        for (int pass = 0; pass < pj->n_passes; ++pass) {
+            const int d = pass - R;
+            SigJob sj{};
+            sj.in = lj.in;
+            sj.in_stride = lj.in_stride;
+            sj.part = lj.w->part + pass * pass_stride;
+            sj.part_stride = part_stride;
+            sj.row_scale = lj.w->rowscale;
+            const size_t ko = (size_t)(c * (R + 1) + (d < 0 ? -d : d)) * pj->k_elems;
+            sj.kf = pj->kf + ko;
+            sj.ka = pj->ka + ko;
+            sj.kf16 = pj->kf16 ? pj->kf16 + ko : nullptr;
+            sj.ka16 = pj->ka16 ? pj->ka16 + ko : nullptr;
+            if (nc == 1) {
+                sj.rows = (int)pj->L;
+                sj.map_per = std::max(1, sj.rows);
+                sj.map_nz = 0;
+                sj.map_off = 0;
+                sj.map_step = 1;
+            } else {
+                const int per = (pj->nz - c + nc - 1) / nc;
+                sj.rows = pj->M * per;
+                sj.map_per = per;
+                sj.map_nz = pj->nz;
+                sj.map_off = c;
+                sj.map_step = nc;
+            }
+            sj.in_dz = d;
+            sj.in_nz = pj->nz;
+            out.push_back(sj);
         }
-    }
-    return nc;
 }
 
 static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
@@ -145,6 +152,7 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
         tiles = 0;
         return MPI3D_OK;
     };
+    std::vector<SigJob> kj;
     for (int j = 0; j < n; ++j) {
         const mpi3d_plan *pj = jobs[j].pl;
         if (pj->line_key != pl->line_key) return MPI3D_EINVAL;
@@ -154,13 +162,13 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
             else TRY(launch_row_scale(pj->L, pj->nb2, jobs[j].in_stride, jobs[j].in, pj->band_scale,
                                       jobs[j].w->rowscale, st));
         }
-        if (nj + pj->n_classes > kMaxJobs) TRYRC(flush());
-        SigJob cj[2];
-        const int nc = class_jobs(jobs[j], fwd, cj);
-        for (int c = 0; c < nc; ++c) {
-            cj[c].tile0 = tiles;
-            tiles += (cj[c].rows + kRowsPerBlock - 1) / kRowsPerBlock;
-            a.jobs[nj++] = cj[c];
+        kj.clear();
+        line_jobs(jobs[j], fwd, serve, kj);
+        for (SigJob &sj : kj) {
+            if (nj == kMaxJobs) TRYRC(flush());
+            sj.tile0 = tiles;
+            tiles += (sj.rows + kRowsPerBlock - 1) / kRowsPerBlock;
+            a.jobs[nj++] = sj;
         }
     }
     return flush();
@@ -180,7 +188,7 @@ static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
                           double *norm_parts, int *nnorm, hipStream_t st)
 {
     const bool mixed = prec == MPI3D_MIXED;
-    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, nsplit_of(pl, serve), pl->L * pl->nbp2, w.part,
+    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->n_passes * nsplit_of(pl, serve), pl->L * pl->nbp2, w.part,
                           mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
                           norm_parts, nnorm, st));
     return MPI3D_OK;
@@ -192,7 +200,8 @@ static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
 {
     const bool mixed = prec == MPI3D_MIXED;
     const double scale = pl->op_scale * (mixed ? (double)pl->adj_scale16 : 1.0);
-    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride, nsplit_of(pl, serve) * pl->ngroups,
+    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride,
+                                    pl->n_passes * nsplit_of(pl, serve) * pl->ngroups,
                                     pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st));
     return MPI3D_OK;
 }
@@ -685,18 +694,20 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         (void)hipEventDestroy(e0);
         return MPI3D_EDEVICE;
     }
-    // signal kernels: every line in one launch, one job per trajectory class
+    // signal kernels: the first launch of a signal stage (every line, one job
+    // per trajectory class and z-row offset, up to the job table's size)
     SigArgs a = sig_args(pl, false);
     {
         const bool fwd = kernel == 2;
         const LineJob lj{pl, fwd ? w.rt : b, fwd ? pl->nup : pl->nb2, &w};
-        SigJob cj[2];
-        a.njobs = class_jobs(lj, fwd, cj);
+        std::vector<SigJob> kj;
+        line_jobs(lj, fwd, false, kj);
+        a.njobs = std::min((int)kj.size(), kMaxJobs);
         a.total_tiles = 0;
         for (int c = 0; c < a.njobs; ++c) {
-            cj[c].tile0 = a.total_tiles;
-            a.total_tiles += (cj[c].rows + kRowsPerBlock - 1) / kRowsPerBlock;
-            a.jobs[c] = cj[c];
+            kj[c].tile0 = a.total_tiles;
+            a.total_tiles += (kj[c].rows + kRowsPerBlock - 1) / kRowsPerBlock;
+            a.jobs[c] = kj[c];
         }
     }
     const bool mixed = precision == MPI3D_MIXED;

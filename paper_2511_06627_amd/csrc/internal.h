@@ -48,7 +48,19 @@ struct SigJob {
     // Job row r is line (r / map_per) * map_nz + map_off + map_step * (r % map_per)
     // of the buffers above (identity: map_per >= rows, map_off 0, map_step 1).
     int map_per, map_nz, map_off, map_step;
+    // Row coupling (tensor PSF): the input of line l = m * in_nz + k is line
+    // l + in_dz, or zero when row k + in_dz is outside [0, in_nz); 0 = none.
+    int in_dz, in_nz;
 };
+
+// Input line of job row r's line l (or -1 when the shifted row is outside
+// its angle's rows).
+__host__ __device__ inline long job_input_line(const SigJob &j, long l)
+{
+    if (j.in_dz == 0) return l;
+    const int k = (int)(l % j.in_nz) + j.in_dz;
+    return (k >= 0 && k < j.in_nz) ? l + j.in_dz : -1;
+}
 
 __host__ __device__ inline long job_line(const SigJob &j, int r)
 {
@@ -125,11 +137,13 @@ struct mpi3d_plan {
     size_t table_bytes;
     float2 *cs;
     float *ax, *ay;
-    // PSF tables kf, ka (kf16, ka16): n_classes consecutive copies of k_elems
-    // elements, one per trajectory class (two under a raster)
+    // PSF tables kf, ka (kf16, ka16): n_ktab consecutive copies of k_elems
+    // elements, one per trajectory class (two under a raster) or per z-row
+    // offset 0..psf_rows (tensor PSF)
     float *kf, *ff, *fa, *ka;
     __half *kf16, *ff16, *fa16, *ka16;
-    int n_classes;
+    int n_classes, psf_rows, n_ktab;
+    int n_passes;                 // signal passes per application: 2 psf_rows + 1
     size_t k_elems;
     double raster_sweep;
     float *col_scale;     // [nbp2] mixed forward output scale per column

@@ -51,6 +51,37 @@ double langevin_deriv(double x)
     return 1.0 / (x * x) - 4.0 * e / ((1.0 - e) * (1.0 - e));
 }
 
+// L(x) = coth x - 1/x.  For |x| < 0.5 the Maclaurin series
+// sum_{n>=1} 2^{2n} B_{2n} x^{2n-1} / (2n)!; for larger |x| the closed form,
+// where the two terms differ by at least 8% and nothing cancels badly.
+double langevin(double x)
+{
+    const double ax = std::fabs(x);
+    if (ax < 0.5) {
+        static const double bern[] = {1.0 / 6, -1.0 / 30, 1.0 / 42, -1.0 / 30, 5.0 / 66, -691.0 / 2730,
+                                      7.0 / 6, -3617.0 / 510, 43867.0 / 798, -174611.0 / 330};
+        double coef[10];
+        double fact = 1.0, pow4 = 1.0;
+        for (int n = 1; n <= 10; ++n) {
+            fact *= (2.0 * n - 1) * (2.0 * n);
+            pow4 *= 4.0;
+            coef[n - 1] = pow4 * bern[n - 1] / fact;
+        }
+        double x2 = x * x, acc = 0.0;
+        for (int n = 9; n >= 0; --n) acc = acc * x2 + coef[n];
+        return x * acc;
+    }
+    return 1.0 / std::tanh(x) - 1.0 / x;
+}
+
+// xx entry of the tensor PSF at in-plane offset (du, dz), dz != 0, with the
+// gradient magnitude equal on both axes: L'(r/w)/w du^2/r^2 + L(r/w) dz^2/r^3.
+double psf_xx(double du, double dz, double w)
+{
+    const double r2 = du * du + dz * dz, r = std::sqrt(r2);
+    return langevin_deriv(r / w) / w * (du * du / r2) + langevin(r / w) * (dz * dz / (r2 * r));
+}
+
 // double -> fp16, rounded once (clang's _Float16 conversion is correctly rounded)
 inline _Float16 to_f16(double v) { return (_Float16)v; }
 
@@ -136,6 +167,11 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED) | (1 << MPI3D_PRECOMPOSED))) return MPI3D_EINVAL;
     // the precomposed line matrix assumes one trajectory shared by every line
     if (n_classes > 1 && (precisions & (1 << MPI3D_PRECOMPOSED))) return MPI3D_ENOTSUP;
+    // tensor PSF row coupling: FP32 path only, without a raster
+    if (g->psf_rows < 0) return MPI3D_EINVAL;
+    const int psf_rows = std::min(g->psf_rows, g->nz - 1);
+    if (psf_rows > 0 && (n_classes > 1 || (precisions & ~(1 << MPI3D_FP32)))) return MPI3D_ENOTSUP;
+    const int n_ktab = n_classes * (psf_rows + 1);
 
     // kept bins, validated
     std::vector<long> bins;
@@ -165,6 +201,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->op_scale = g->op_scale;
     pl->precisions = precisions;
     pl->n_classes = n_classes;
+    pl->psf_rows = psf_rows;
+    pl->n_ktab = n_ktab;
+    pl->n_passes = 2 * psf_rows + 1;
     pl->raster_sweep = g->raster_sweep;
     pl->nup = round_up(nu, 64);
     pl->ntp = round_up(g->n_t, kChunk);
@@ -276,23 +315,29 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         }
     }
 
-    // PSF kernel K[n][p] of each trajectory class (n < T, p < NU; zero padding
-    // elsewhere), class 1 being the raster's backward sweep:
-    // xi_n = a sin(phi_n) + dir S (n/T - 1/2), v_n = a phi' cos(phi_n) + dir S/T.
+    // PSF kernel K[n][p] of every table (n < T, p < NU; zero padding
+    // elsewhere).  Table t = c (R + 1) + d: trajectory class c, class 1 being
+    // the raster's backward sweep, xi_n = a sin(phi_n) + dir S (n/T - 1/2),
+    // v_n = a phi' cos(phi_n) + dir S/T; and z-row offset d of the tensor PSF,
+    // d = 0 being the collinear L'(du/w)/w.
     const size_t KE = (size_t)TP * NUP;
     pl->k_elems = KE;
-    std::vector<double> K(KE * n_classes, 0.0);
+    std::vector<double> K(KE * n_ktab, 0.0);
     {
         const double om = 2.0 * kPi * pl->P / T;
-        for (int cl = 0; cl < n_classes; ++cl) {
+        for (int tb = 0; tb < n_ktab; ++tb) {
+            const int cl = tb / (psf_rows + 1), d = tb % (psf_rows + 1);
             const double dir = cl == 0 ? 1.0 : -1.0, S = pl->raster_sweep;
-            double *Kc = &K[KE * cl];
+            double *Kc = &K[KE * tb];
             for (int n = 0; n < T; ++n) {
                 double ph = om * n;
                 double xi = pl->a * std::sin(ph) + dir * S * ((double)n / T - 0.5);
                 double v = pl->a * om * std::cos(ph) + dir * S / T;
-                for (int p = 0; p < NU; ++p)
-                    Kc[(size_t)n * NUP + p] = v * langevin_deriv((xi - (p - cu)) / pl->w) / pl->w;
+                for (int p = 0; p < NU; ++p) {
+                    const double du = xi - (p - cu);
+                    Kc[(size_t)n * NUP + p] =
+                        v * (d == 0 ? langevin_deriv(du / pl->w) / pl->w : psf_xx(du, (double)d, pl->w));
+                }
             }
         }
     }
@@ -342,16 +387,16 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     o_cs = place(sizeof(float2) * M);
     o_ax = place(sizeof(float) * M * NU);
     o_ay = place(sizeof(float) * M * NU);
-    o_kf = place(sizeof(float) * KE * n_classes);
+    o_kf = place(sizeof(float) * KE * n_ktab);
     o_ff = place(sizeof(float) * (size_t)TP * NBP2);
     o_fa = place(sizeof(float) * (size_t)TP * NBP2);
-    o_ka = place(sizeof(float) * KE * n_classes);
+    o_ka = place(sizeof(float) * KE * n_ktab);
     const size_t o_gt = precomp ? place(sizeof(float) * gt.size()) : 0;
     if (mixed) {
-        o_kf16 = place(sizeof(__half) * KE * n_classes);
+        o_kf16 = place(sizeof(__half) * KE * n_ktab);
         o_ff16 = place(sizeof(__half) * (size_t)TP * NBP2);
         o_fa16 = place(sizeof(__half) * (size_t)TP * NBP2);
-        o_ka16 = place(sizeof(__half) * KE * n_classes);
+        o_ka16 = place(sizeof(__half) * KE * n_ktab);
         o_cols = place(sizeof(float) * NBP2);
         o_bands = place(sizeof(float) * NBP2);
     }
@@ -366,9 +411,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     //  ka: adj GEMM2 B operand  K[t = 32c + tperm(s, l/32)][32pt + l%32]  [c][pt][s/4][l][s%4]
     // tperm(s, h) = 8(s/4) + 4h + s%4 is the time index that the 32x32 MFMA
     // result layout leaves in register s of lane half h.
-    std::vector<float> kf(KE * n_classes), ff((size_t)TP * NBP2), fa((size_t)TP * NBP2), ka(KE * n_classes);
+    std::vector<float> kf(KE * n_ktab), ff((size_t)TP * NBP2), fa((size_t)TP * NBP2), ka(KE * n_ktab);
     auto tperm = [](int s, int h) { return 8 * (s / 4) + 4 * h + (s % 4); };
-    for (int cl = 0; cl < n_classes; ++cl)
+    for (int cl = 0; cl < n_ktab; ++cl)
         for (int c = 0; c < NC; ++c) {
             const double *Kc = &K[KE * cl];
             float *kfc = &kf[KE * cl], *kac = &ka[KE * cl];
@@ -409,7 +454,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         // its response to a unit source at each of a few detector positions.
         std::vector<double> bnorm(NB / (2 * pl->half_band + 1), 0.0);
         int nbands = (int)bnorm.size(), bw = 2 * pl->half_band + 1;
-        for (int probe = 0; probe < 3 * n_classes; ++probe) {
+        for (int probe = 0; probe < 3 * n_ktab; ++probe) {
             const int p = (probe % 3 + 1) * NU / 4;
             const double *Kc = &K[KE * (probe / 3)];
             for (int j = 0; j < NB; ++j) {
@@ -446,11 +491,11 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         //  ka16: adj GEMM2 B: K[t = 32c + 16h + tperm16(e, l/32)][32pt + l%32]   [c][pt][h][l][e]
         // tperm16(e, h) = 8(e/4) + 4h + e%4.
         auto tp16 = [](int e, int h) { return 8 * (e / 4) + 4 * h + (e % 4); };
-        kf16.resize(KE * n_classes);
+        kf16.resize(KE * n_ktab);
         ff16.resize((size_t)TP * NBP2);
         fa16.resize((size_t)TP * NBP2);
-        ka16.resize(KE * n_classes);
-        for (int cl = 0; cl < n_classes; ++cl)
+        ka16.resize(KE * n_ktab);
+        for (int cl = 0; cl < n_ktab; ++cl)
             for (int c = 0; c < NC; ++c) {
                 const double *Kc = &K[KE * cl];
                 _Float16 *kfc = &kf16[KE * cl], *kac = &ka16[KE * cl];
@@ -535,8 +580,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         auto put = [&](size_t bytes) { o = align256(o); size_t r = o; o += bytes; return r; };
         long parts_rows = std::max<long>(pl->nbp2, pl->nup);
         pl->ws_rt = put(sizeof(float) * pl->L * pl->nup);
-        pl->ws_part = put(sizeof(float) * (size_t)std::max(pl->nsplit, pl->serve_nsplit) * pl->ngroups * pl->L *
-                          parts_rows);
+        pl->ws_part = put(sizeof(float) * (size_t)pl->n_passes * std::max(pl->nsplit, pl->serve_nsplit) *
+                          pl->ngroups * pl->L * parts_rows);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
         pl->ws_rowscale = put(sizeof(float) * pl->L);
         pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
@@ -566,7 +611,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
         };
         int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2, pl->ngroups,
-                      pl->gct, precisions, n_classes};
+                      pl->gct, precisions, n_classes, psf_rows};
         double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep};
         mix(ints, sizeof(ints));
         mix(dbl, sizeof(dbl));

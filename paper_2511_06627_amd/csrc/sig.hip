@@ -113,6 +113,9 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
+    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
+    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    const bool iok = il >= 0;
     constexpr int NK = NUP / 16;          // K float4 loads per chunk (this half)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk
     constexpr int NL = NK + NF;
@@ -123,9 +126,9 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
     float R[NUP / 4];
     {
         const int p0 = bp.half * (NUP / 2);
-        const float *rin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride + p0 + h;
+        const float *rin = (const float *)job.in + (size_t)(iok ? il : 0) * job.in_stride + p0 + h;
 #pragma unroll
-        for (int st = 0; st < NUP / 4; ++st) R[st] = (rok && p0 + 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
+        for (int st = 0; st < NUP / 4; ++st) R[st] = (iok && p0 + 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
     }
     f32x16 acc[GH];
 #pragma unroll
@@ -199,6 +202,9 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
+    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
+    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    const bool iok = il >= 0;
     constexpr int PTH = NUP / 64;         // detector tiles per half
     constexpr int NF = 4 * GH;            // F float4 loads per chunk (GEMM1)
     constexpr int NK = 4 * PTH;           // K float4 loads per chunk (GEMM2)
@@ -211,11 +217,11 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
     // B operand of GEMM1: y[r][colbase + 2 st + h]
     float Y[16 * GH];
     {
-        const float *yin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride + colbase + h;
+        const float *yin = (const float *)job.in + (size_t)(iok ? il : 0) * job.in_stride + colbase + h;
 #pragma unroll
         for (int st = 0; st < 16 * GH; ++st) {
             const int col = colbase + 2 * st + h;
-            Y[st] = (rok && col < a.nb2) ? yin[2 * st] : 0.f;
+            Y[st] = (iok && col < a.nb2) ? yin[2 * st] : 0.f;
         }
     }
     f32x16 racc[PTH];

@@ -144,12 +144,15 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
     const int lane = tid & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
+    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
+    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    const bool iok = il >= 0;
     constexpr int NKS = NUP / 32;         // fp16 K steps per half (16 detector samples each)
 
     // this wave's half of the line, scaled by the line's power-of-two scale
     // (row_scale kernel), as fp16 B operands
-    const float *rin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride;
-    const float rs = rok ? job.row_scale[job_line(job, r)] : 1.f;
+    const float *rin = (const float *)job.in + (size_t)(iok ? il : 0) * job.in_stride;
+    const float rs = iok ? job.row_scale[il] : 1.f;
     f16x8 R[NKS];
     {
         const int p0 = bp.half * (NUP / 2);
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int p = p0 + 16 * st + 8 * h + e;
-                R[st][e] = (_Float16)((rok && p < a.nu) ? rin[p] * rs : 0.f);
+                R[st][e] = (_Float16)((iok && p < a.nu) ? rin[p] * rs : 0.f);
             }
     }
     f32x16 acc[GH];
@@ -237,21 +240,24 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     const int lane = tid & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
+    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
+    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    const bool iok = il >= 0;
     constexpr int PTH = NUP / 64;
     constexpr int NF = 2 * GH;            // fp16 F steps per chunk (16 columns each)
     const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;
     const int pt0 = bp.half * PTH;
 
     // the line's power-of-two scale over the band-scaled row (row_scale kernel)
-    const float *yin = (const float *)job.in + (size_t)(rok ? job_line(job, r) : 0) * job.in_stride;
-    const float ys = rok ? job.row_scale[job_line(job, r)] : 1.f;
+    const float *yin = (const float *)job.in + (size_t)(iok ? il : 0) * job.in_stride;
+    const float ys = iok ? job.row_scale[il] : 1.f;
     f16x8 Y[NF];
 #pragma unroll
     for (int st = 0; st < NF; ++st)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int col = colbase + 16 * st + 8 * h + e;
-            Y[st][e] = (_Float16)((rok && col < a.nb2) ? yin[col] * a.band_scale[col] * ys : 0.f);
+            Y[st][e] = (_Float16)((iok && col < a.nb2) ? yin[col] * a.band_scale[col] * ys : 0.f);
         }
     f32x16 racc[PTH];
 #pragma unroll

@@ -31,7 +31,7 @@ def _stream(stream):
 class Plan:
     def __init__(self, nx, ny, nz, n_angles, n_t, drive_cycles, psf_width, harm_lo, harm_hi, half_band,
                  op_scale, theta=None, n_u=0, drive_amp=0.0, rx_filter=None, precisions=("fp32",), device=0,
-                 raster_sweep=0.0):
+                 raster_sweep=0.0, psf_rows=0):
         lib = _lib.load()
         self.device = torch.device("cuda", device)
         g = _lib.Geometry()
@@ -57,8 +57,10 @@ class Plan:
             mask |= 1 << PRECISION[p]
         g.precisions = mask
         g.raster_sweep = raster_sweep
+        g.psf_rows = psf_rows
         self.precisions = tuple(precisions)
         self.raster_sweep = float(raster_sweep)
+        self.psf_rows = int(psf_rows)
         handle = ctypes.c_void_p()
         check("mpi3d_plan_create", lib.mpi3d_plan_create(ctypes.byref(g), device, ctypes.byref(handle)))
         self._h = handle

@@ -1,0 +1,141 @@
+"""GPU parity of the tensor-PSF operator (z-rows coupled through the xx entry
+of the tensor PSF, one signal pass per row offset) against the FP64 oracle.
+
+Tolerances: the FP32 bars of the collinear operator -- 1e-5 relative L2 for
+the operator, its stages and the converged CGLS solve.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry, operator as oop, signal as osig, solvers
+from helpers import rel_l2, random_volume, random_data
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+# name: (nx, ny, nz, M, T, P, w, k_lo, k_hi, D, R)
+CASES = {
+    # the whole model: every row of an angle coupled to every other (R = nz - 1)
+    "tensor_full": (32, 32, 6, 5, 1024, 1024 / 128 + 1 / 3, 2.0, 1, 12, 2, 5),
+    # ragged, truncated at two rows per side, odd nz
+    "tensor_r2": (40, 36, 9, 7, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1, 2),
+    # nine offsets in one launch with several line tiles per offset
+    "tensor_tiles": (64, 48, 20, 9, 2048, 2048 / 256 + 1 / 3, 3.0, 1, 14, 2, 4),
+}
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _geom(name, op_scale=1.0):
+    nx, ny, nz, M, T, P, w, klo, khi, D, R = CASES[name]
+    return geometry.Geometry(nx=nx, ny=ny, nz=nz, n_angles=M, n_t=T, drive_cycles=P, psf_width=w,
+                             harm_lo=klo, harm_hi=khi, half_band=D, op_scale=op_scale, psf_rows=R)
+
+
+def _plan(name, op_scale, precisions=("fp32",), **kw):
+    from paper_2511_06627_amd.plan import Plan
+    nx, ny, nz, M, T, P, w, klo, khi, D, R = CASES[name]
+    return Plan(nx, ny, nz, M, T, P, w, klo, khi, D, op_scale, precisions=precisions, psf_rows=R, **kw)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request, torch_mod):
+    _log("case %s" % request.param)
+    g = oop.normalised(_geom(request.param), iters_min=30, rtol=1e-9)
+    return request.param, g, _plan(request.param, g.op_scale)
+
+
+def _dev(torch_mod, a, dtype):
+    return torch_mod.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def test_tensor_forward_and_adjoint_parity(case, torch_mod):
+    name, g, plan = case
+    x = random_volume(g, 1)
+    y = random_data(g, 2)
+    ef = rel_l2(plan.forward(_dev(torch_mod, x, torch_mod.float32)).cpu().numpy(), oop.forward(g, x))
+    ea = rel_l2(plan.adjoint(_dev(torch_mod, y, torch_mod.complex64)).cpu().numpy(), oop.adjoint(g, y))
+    _log("%s rel err forward %.3e adjoint %.3e" % (name, ef, ea))
+    assert ef <= TOL32 and ea <= TOL32
+
+
+def test_tensor_signal_stages(case, torch_mod):
+    """The coupled signal stage alone, on random lines and data."""
+    name, g, plan = case
+    rng = np.random.default_rng(3)
+    rho = rng.standard_normal((g.n_angles, g.nz, g.n_u))
+    want = osig.forward(g, rho.reshape(g.n_lines, g.n_u)).reshape(g.n_angles, g.nz, g.n_bins)
+    ef = rel_l2(plan.signal_fwd(_dev(torch_mod, rho, torch_mod.float32)).cpu().numpy(), want)
+    y = random_data(g, 4)
+    want_a = osig.adjoint(g, y.reshape(g.n_lines, g.n_bins)).reshape(g.n_angles, g.nz, g.n_u)
+    ea = rel_l2(plan.signal_adj(_dev(torch_mod, y, torch_mod.complex64)).cpu().numpy(), want_a)
+    _log("%s signal stages rel err fwd %.3e adj %.3e" % (name, ef, ea))
+    assert ef <= TOL32 and ea <= TOL32
+
+
+def test_tensor_gpu_adjoint_identity(case, torch_mod):
+    name, g, plan = case
+    x = random_volume(g, 5)
+    y = random_data(g, 6)
+    ax = plan.forward(_dev(torch_mod, x, torch_mod.float32)).cpu().numpy().astype(np.complex128)
+    aty = plan.adjoint(_dev(torch_mod, y, torch_mod.complex64)).cpu().numpy().astype(np.float64)
+    lhs = np.vdot(ax, y.astype(np.complex64).astype(np.complex128)).real
+    rhs = float(np.vdot(x.astype(np.float32).astype(np.float64), aty))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(ax) * np.linalg.norm(y)
+
+
+def test_tensor_rows_really_couple(torch_mod):
+    """A volume on one slice lights every line within R rows of it and no other."""
+    name = "tensor_r2"
+    g = _geom(name, 1.0)
+    plan = _plan(name, 1.0)
+    x = np.zeros((g.nz, g.ny, g.nx))
+    x[4] = random_volume(g, 9)[4]
+    b = plan.forward(_dev(torch_mod, x, torch_mod.float32)).cpu().numpy()
+    lit = np.abs(b).max(axis=(0, 2)) > 0
+    assert lit.tolist() == [abs(k - 4) <= 2 for k in range(g.nz)]
+
+
+def test_tensor_rejects_other_variants(torch_mod):
+    from paper_2511_06627_amd._lib import Mpi3dError
+    for kw in (dict(precisions=("fp32", "mixed")), dict(precisions=("fp32", "precomposed")),
+               dict(raster_sweep=5.0)):
+        with pytest.raises(Mpi3dError):
+            _plan("tensor_r2", 1.0, **kw)
+
+
+def test_tensor_device_normalisation(torch_mod):
+    g = oop.normalised(_geom("tensor_full"), iters_min=30, rtol=1e-12)
+    plan = _plan("tensor_full", 0.0)
+    rel = abs(plan.op_scale - g.op_scale) / g.op_scale
+    _log("tensor_full device c_A %.9e (%d its) oracle %.9e rel %.2e"
+         % (plan.op_scale, plan.norm_iters, g.op_scale, rel))
+    assert rel <= 1e-5
+
+
+def test_tensor_cgls_reaches_minimiser(torch_mod):
+    name = "tensor_full"
+    g = oop.normalised(_geom(name), iters_min=30, rtol=1e-9)
+    rng = np.random.default_rng(8)
+    x_true = random_volume(g, 10) * (rng.uniform(0, 1, (g.nz, 1, 1)) > 0.3)
+    b, _ = oop.make_data(g, x_true, 0.01, 11)
+    lam = 1e-3
+    xs, n = solvers.reference_minimiser(oop.Operator(g, precomposed=True), b, lam, tol=1e-12)
+    plan = _plan(name, g.op_scale)
+    x, rep = plan.solve(_dev(torch_mod, b, torch_mod.complex64), lam, iters=max(80, n + 20))
+    err = rel_l2(x.cpu().numpy(), xs)
+    _log("tensor CGLS %d its vs x*: %.3e (oracle needed %d)" % (rep.iters_done, err, n))
+    assert rep.status == 0 and err <= TOL32
