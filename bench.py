@@ -592,6 +592,28 @@ def main():
     log("raster A^T A: %s" % raster)
     del planr, wsr
 
+    # the same scan with the tensor PSF coupling each z-row to three rows on
+    # either side (seven signal passes per application, FP32)
+    plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32",), psf_rows=3)
+    wst = plant.workspace("op")
+
+    def stept():
+        plant.forward(x, out=yb, ws=wst)
+        plant.adjoint(yb, out=xo, ws=wst)
+
+    for _ in range(args.warmup):
+        stept()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stept()
+    torch.cuda.synchronize()
+    dtt = time.perf_counter() - t0
+    tensor = {"psf_rows": 3, "signal_passes": 7, "applies_per_s": round(args.steps / dtt, 2),
+              "ms_per_step": round(1e3 * dtt / args.steps, 4)}
+    log("tensor PSF (R = 3) A^T A: %s" % tensor)
+    del plant, wst
+
     # CGLS iteration rate of the configured 50-iteration solve
     swk = plan.workspace("solve")
     plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
@@ -681,6 +703,7 @@ def main():
         "mixed": mixed,
         "precomposed": precomposed,
         "raster": raster,
+        "tensor_psf": tensor,
         "serving": serve,
         "hdr": hdr,
         "oracle_small": cpu.get("oracle_small") if cpu is not None else None,

@@ -76,9 +76,9 @@ class Plan:
         self._ws = None
 
     @classmethod
-    def from_config(cls, cfg, op_scale, precisions=("fp32",), device=0):
+    def from_config(cls, cfg, op_scale, precisions=("fp32",), device=0, **kw):
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width,
-                   cfg.harm_lo, cfg.harm_hi, cfg.half_band, op_scale, precisions=precisions, device=device)
+                   cfg.harm_lo, cfg.harm_hi, cfg.half_band, op_scale, precisions=precisions, device=device, **kw)
 
     def close(self):
         if getattr(self, "_h", None):
