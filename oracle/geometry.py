@@ -15,6 +15,11 @@ Readings of the paper used here (each listed in the design doc):
   (``psf_rows``) of the same angle's projection through the x-x tensor PSF at
   z-offset k - k' (rows one voxel apart); R >= Nz - 1 is the whole model, R = 0
   the collinear one.
+* Dual drive (Sec. 3.1: every angle is scanned with the drive along x and
+  again along z): the z-drive scan of angle m has one line per detector column
+  p, running across the z-rows k with samples at z_k = k - (Nz-1)/2 and drive
+  amplitude a_z (default Nz/2), through the same collinear PSF and bins.  Its
+  lines follow the x-drive lines in the data, m-major: line M*Nz + m*Nu + p.
 * Raster trajectory classes: every angle repeats one scan sequence (Sec. 2.2,
   before eq. modelF1); under a zig-zag raster (Sec. 3.1) the sweep direction
   alternates from line to line, so z-row k sweeps forward when k is even and
@@ -47,12 +52,17 @@ class Geometry:
     rx_filter: np.ndarray = None     # complex D_Gamma on the kept bins, None = 1
     raster_sweep: float = 0.0        # focus-field shift per line in voxels (0 = none)
     psf_rows: int = 0                # z-rows coupled by the tensor PSF on each side (0 = collinear)
+    drive_axes: int = 1              # 1: x-drive scan; 2: x- and z-drive scans (dual drive)
+    drive_amp_z: float = None        # z-drive amplitude in voxels, default Nz/2
 
     def __post_init__(self):
         if self.n_u is None:
             self.n_u = self.nx
         if self.drive_amp is None:
             self.drive_amp = self.n_u / 2.0
+        if self.drive_amp_z is None:
+            self.drive_amp_z = self.nz / 2.0
+        assert self.drive_axes in (1, 2)
         if self.theta is None:
             self.theta = np.arange(self.n_angles, dtype=np.float64) * np.pi / self.n_angles
         self.theta = np.asarray(self.theta, dtype=np.float64)
@@ -62,6 +72,15 @@ class Geometry:
     @property
     def n_lines(self):
         return self.n_angles * self.nz
+
+    @property
+    def n_z_lines(self):
+        """z-drive lines: one per angle and detector column (dual drive only)."""
+        return self.n_angles * self.n_u if self.drive_axes == 2 else 0
+
+    @property
+    def n_data_lines(self):
+        return self.n_lines + self.n_z_lines
 
     @property
     def n_bins(self):
@@ -81,8 +100,8 @@ class Geometry:
         operator: one slice, or two under a raster (even and odd rows sweep in
         opposite directions)."""
         g = Geometry(**{k: getattr(self, k) for k in self.__dataclass_fields__})
-        if self.psf_rows:
-            return g          # rows are coupled: no smaller equivalent
+        if self.psf_rows or self.drive_axes == 2:
+            return g          # rows are coupled (tensor PSF, z-drive lines): no smaller equivalent
         g.nz = min(self.nz, 2) if self.raster_sweep else 1
         return g
 

@@ -11,6 +11,8 @@ Test infrastructure only (see ``oracle/__init__``).
                   projector acts slice by slice) with the same block on every
                   slice of one trajectory class, so the norm is taken on one
                   slice, or on two under a raster.
+* Dual drive -- the z-drive lines follow the x-drive lines (``geometry``);
+                  A^T adds their transposed contributions to the projections.
 * ``make_data`` -- synthetic compressed data: clean time signal of a phantom,
                   plus white Gaussian noise in the time domain with standard
                   deviation level * max|s_clean|, then compression.
@@ -37,7 +39,22 @@ def _per_class(g, rows_in, fn):
     return out
 
 
+def _dual_forward(g, rt, lines_fwd, z_fwd):
+    """Dual drive: x-drive lines then z-drive lines, shape (L_x + L_z, nb)."""
+    bx = lines_fwd(rt.reshape(g.n_lines, g.n_u))
+    bz = z_fwd(signal.z_lines(g, rt))
+    return np.concatenate([bx.reshape(g.n_lines, g.n_bins), bz.reshape(g.n_z_lines, g.n_bins)])
+
+
+def _dual_adjoint(g, y, lines_adj, z_adj):
+    y = np.asarray(y, dtype=np.complex128).reshape(g.n_data_lines, g.n_bins)
+    lines = lines_adj(y[:g.n_lines]).reshape(g.n_angles, g.nz, g.n_u)
+    return lines + signal.z_lines_transpose(g, z_adj(y[g.n_lines:]))
+
+
 def forward(g, x, precomposed=False):
+    if g.drive_axes == 2:
+        return Operator(g, precomposed).forward(x)
     rt = projector.project(g, x).reshape(g.n_lines, g.n_u)
     if precomposed and g.psf_rows:
         return signal.coupled_apply(g, rt, signal.row_matrices(g)).reshape(g.n_angles, g.nz, g.n_bins)
@@ -48,6 +65,8 @@ def forward(g, x, precomposed=False):
 
 
 def adjoint(g, y, precomposed=False):
+    if g.drive_axes == 2:
+        return Operator(g, precomposed).adjoint(y)
     y = np.asarray(y, dtype=np.complex128).reshape(g.n_lines, g.n_bins)
     if precomposed and g.psf_rows:
         lines = np.real(signal.coupled_apply(g, y, [np.conj(C) for C in signal.row_matrices(g)], adjoint=True))
@@ -66,6 +85,14 @@ class Operator:
         self.precomposed = precomposed
         self.classes = signal.classes_present(g)
         self.coupled = bool(g.psf_rows)
+        self.dual = g.drive_axes == 2
+        if self.dual:
+            assert not g.psf_rows and not g.raster_sweep
+            Kz = signal.kernel_z(g)
+            if precomposed:
+                self.Cz = signal.dft_matrix(g).T @ Kz
+            else:
+                self.Kz = Kz
         if self.coupled:
             assert not g.raster_sweep
             rows = range(signal.coupled_rows(g) + 1)
@@ -118,13 +145,29 @@ class Operator:
             return signal.coupled_apply(self.g, h, self.Kd, adjoint=True)
         return _per_class(self.g, y, self._lines_adj_class)
 
+    def _z_fwd(self, zl):
+        if self.precomposed:
+            return zl @ self.Cz.T
+        s = zl @ self.Kz.T
+        return (s @ self.E_re) + 1j * (s @ self.E_im)
+
+    def _z_adj(self, y):
+        if self.precomposed:
+            return np.real(y @ np.conj(self.Cz))
+        h = np.ascontiguousarray(y.real) @ self.E_re.T + np.ascontiguousarray(y.imag) @ self.E_im.T
+        return h @ self.Kz
+
     def forward(self, x):
         g = self.g
         rt = projector.project(g, x).reshape(g.n_lines, g.n_u)
+        if self.dual:
+            return _dual_forward(g, rt, self._lines_fwd, self._z_fwd)
         return self._lines_fwd(rt).reshape(g.n_angles, g.nz, g.n_bins)
 
     def adjoint(self, y):
         g = self.g
+        if self.dual:
+            return projector.backproject(g, _dual_adjoint(g, y, self._lines_adj, self._z_adj))
         y = np.asarray(y, dtype=np.complex128).reshape(g.n_lines, g.n_bins)
         lines = self._lines_adj(y)
         return projector.backproject(g, lines.reshape(g.n_angles, g.nz, g.n_u))
@@ -154,7 +197,8 @@ def normalised(g, **kw):
 
 
 def make_data(g, phantom, noise_level, noise_seed):
-    """Compressed data b (M, Nz, nb) of a phantom with time-domain white noise.
+    """Compressed data b (M, Nz, nb) of a phantom with time-domain white noise
+    ((L_x + L_z, nb) with the dual drive).
 
     Also returns the noise standard deviation used.  Noise is drawn line block
     by line block from one PCG64 stream, in line order, so the result does
@@ -165,6 +209,8 @@ def make_data(g, phantom, noise_level, noise_seed):
     cl = signal.row_classes(g, g.n_lines)
 
     s_all = signal.coupled_apply(g, rt, op.Kd) if op.coupled else None
+    if op.dual:   # x-drive lines, then z-drive lines
+        s_all = np.concatenate([rt @ op.K[0].T, signal.z_lines(g, rt) @ op.Kz.T])
 
     def clean(a):   # time signals of lines a .. a+511, each through its class's K
         if s_all is not None:
@@ -176,13 +222,16 @@ def make_data(g, phantom, noise_level, noise_seed):
         return s
 
     s_max = 0.0
-    for a in range(0, g.n_lines, 512):
+    n_rows = g.n_data_lines
+    for a in range(0, n_rows, 512):
         s_max = max(s_max, float(np.abs(clean(a)).max()))
     sigma = noise_level * s_max
     rng = np.random.default_rng(noise_seed)
-    b = np.empty((g.n_lines, g.n_bins), dtype=np.complex128)
-    for a in range(0, g.n_lines, 512):
+    b = np.empty((n_rows, g.n_bins), dtype=np.complex128)
+    for a in range(0, n_rows, 512):
         s = clean(a)
         s = s + sigma * rng.standard_normal(s.shape)
         b[a:a + 512] = (s @ op.E_re) + 1j * (s @ op.E_im)
+    if op.dual:
+        return b, sigma
     return b.reshape(g.n_angles, g.nz, g.n_bins), sigma

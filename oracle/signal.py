@@ -93,6 +93,28 @@ def coupled_apply(g, rows, mats, adjoint=False):
     return out.reshape(g.n_lines, width)
 
 
+def z_grid(g):
+    """Sample positions of a z-drive line: the z-rows, centred."""
+    return np.arange(g.nz, dtype=np.float64) - (g.nz - 1) / 2.0
+
+
+def kernel_z(g):
+    """K of the z-drive lines: c_A v_n L'((xi_n - z_k)/w)/w with amplitude a_z, shape (T, Nz)."""
+    return psf_kernel(g.n_t, g.drive_cycles, g.drive_amp_z, g.psf_width, z_grid(g), g.op_scale)
+
+
+def z_lines(g, rho_theta):
+    """z-drive lines of the projections rho_theta (M, Nz, Nu): line m*Nu + p is the
+    column rho_theta[m, :, p], shape (M*Nu, Nz)."""
+    r = np.asarray(rho_theta).reshape(g.n_angles, g.nz, g.n_u)
+    return np.ascontiguousarray(r.transpose(0, 2, 1)).reshape(g.n_z_lines, g.nz)
+
+
+def z_lines_transpose(g, zl):
+    """Transpose of ``z_lines``: (M*Nu, Nz) -> (M, Nz, Nu)."""
+    return np.ascontiguousarray(np.asarray(zl).reshape(g.n_angles, g.n_u, g.nz).transpose(0, 2, 1))
+
+
 def classes_present(g):
     return (0, 1) if g.raster_sweep and g.nz > 1 else (0,)
 
