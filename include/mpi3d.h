@@ -137,6 +137,16 @@ typedef struct {
                                     R > 0 costs 2R + 1 signal passes per application and
                                     is FP32 only: MPI3D_MIXED or MPI3D_PRECOMPOSED in
                                     precisions, or raster_sweep != 0, is MPI3D_ENOTSUP */
+    int32_t drive_axes;          /* 1 (or 0): the x-drive scan.  2: every angle is also
+                                    scanned with the drive and receive coil along z
+                                    (Sec. 3.1): the z-drive scan of angle m has one line
+                                    per detector column p, across the z-rows k at
+                                    z_k = k - (nz-1)/2, same PSF, time grid and bins.
+                                    Its n_angles * n_u lines follow the x-drive lines in
+                                    b: line n_angles*nz + m*n_u + p.  Needs nz <= n_u;
+                                    with raster_sweep != 0, psf_rows > 0 or
+                                    MPI3D_PRECOMPOSED it is MPI3D_ENOTSUP */
+    double drive_amp_z;          /* z-drive amplitude in voxels; 0 = nz/2 */
 } mpi3d_geometry;
 
 typedef struct mpi3d_plan mpi3d_plan;
@@ -144,10 +154,11 @@ typedef struct mpi3d_plan mpi3d_plan;
 /* Sizes a caller needs to allocate buffers for a plan. */
 typedef struct {
     int64_t n_vox;              /* nx*ny*nz floats in a volume */
-    int64_t n_lines;            /* n_angles*nz FFL lines */
+    int64_t n_lines;            /* FFL lines: n_angles*nz, plus n_angles*n_u z-drive lines
+                                   with drive_axes = 2 */
     int64_t n_bins;             /* kept bins per line */
     int64_t n_data_floats;      /* 2*n_lines*n_bins floats in b */
-    int64_t n_proj_floats;      /* n_lines*n_u floats in a projection (mpi3d_project) */
+    int64_t n_proj_floats;      /* n_angles*nz*n_u floats in a projection (mpi3d_project) */
     int64_t op_ws_bytes;        /* workspace of mpi3d_forward/adjoint/signal_* */
     int64_t solve_ws_bytes;     /* workspace of mpi3d_solve / a serving state */
     int64_t table_bytes;        /* device memory held by the plan itself */
@@ -179,7 +190,10 @@ int mpi3d_adjoint(const mpi3d_plan *plan, int32_t precision, const float *b_dev,
  *   backproject  x_dev = P^T rho_dev
  *   signal_fwd   b_dev = A_DC rho_dev, line by line           (eq. DCmodel)
  *   signal_adj   rho_dev = Re(A_DC^H b_dev)
- * signal_* need op_ws_bytes of workspace; project/backproject need none. */
+ * signal_* take and give all n_lines lines of n_u floats (with drive_axes = 2
+ * the z-drive lines use their first nz floats; the rest must be zero on input
+ * and are zero on output).  signal_* need op_ws_bytes of workspace;
+ * project/backproject need none. */
 int mpi3d_project(const mpi3d_plan *plan, const float *x_dev, float *rho_dev, void *stream);
 int mpi3d_backproject(const mpi3d_plan *plan, const float *rho_dev, float *x_dev, void *stream);
 int mpi3d_signal_fwd(const mpi3d_plan *plan, int32_t precision, const float *rho_dev, float *b_dev,

@@ -34,6 +34,8 @@ class Geometry(ctypes.Structure):
         ("precisions", ctypes.c_int32),
         ("raster_sweep", ctypes.c_double),
         ("psf_rows", ctypes.c_int32),
+        ("drive_axes", ctypes.c_int32),
+        ("drive_amp_z", ctypes.c_double),
     ]
 
 

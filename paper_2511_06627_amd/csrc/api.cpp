@@ -92,19 +92,22 @@ static SigArgs sig_args(const mpi3d_plan *pl, bool serve)
 
 static int nsplit_of(const mpi3d_plan *pl, bool serve) { return serve ? pl->serve_nsplit : pl->nsplit; }
 
-// The kernel jobs of one line job: one per trajectory class and z-row offset
-// of the tensor PSF.  Class c holds the lines (m, k) with k % n_classes == c,
-// i.e. per angle ceil((nz - c) / n_classes) lines n_classes apart; offset pass
-// p reads line (m, k + d), d = p - psf_rows, through table |d| and writes its
-// own block of split partial sums, which the reductions add with the others.
+// The kernel jobs of one line job: one per line group (trajectory class of a
+// raster, or x- and z-drive lines) and z-row offset of the tensor PSF.  Group
+// g holds the lines of its map (class c: the lines (m, k) with k % n_classes
+// == c; dual drive: the x-drive lines, then the z-drive lines) and its PSF
+// table; offset pass p reads line (m, k + d), d = p - psf_rows, through table
+// |d| and writes its own block of split partial sums, which the reductions
+// add with the others.
 static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJob> &out)
 {
     const mpi3d_plan *pj = lj.pl;
-    const int nc = pj->n_classes, R = pj->psf_rows;
+    const int R = pj->psf_rows;
     const long part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
     const long pass_stride = (long)(serve ? pj->serve_nsplit : pj->nsplit) * (fwd ? 1 : pj->ngroups) * part_stride;
-    for (int c = 0; c < nc; ++c)
+    for (int gi = 0; gi < pj->n_line_groups; ++gi)
         for (int pass = 0; pass < pj->n_passes; ++pass) {
+            const mpi3d_plan::LineGroup &lg = pj->groups[gi];
             const int d = pass - R;
             SigJob sj{};
             sj.in = lj.in;
@@ -112,25 +115,16 @@ static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJo
             sj.part = lj.w->part + pass * pass_stride;
             sj.part_stride = part_stride;
             sj.row_scale = lj.w->rowscale;
-            const size_t ko = (size_t)(c * (R + 1) + (d < 0 ? -d : d)) * pj->k_elems;
+            const size_t ko = (size_t)(lg.table * (R + 1) + (d < 0 ? -d : d)) * pj->k_elems;
             sj.kf = pj->kf + ko;
             sj.ka = pj->ka + ko;
             sj.kf16 = pj->kf16 ? pj->kf16 + ko : nullptr;
             sj.ka16 = pj->ka16 ? pj->ka16 + ko : nullptr;
-            if (nc == 1) {
-                sj.rows = (int)pj->L;
-                sj.map_per = std::max(1, sj.rows);
-                sj.map_nz = 0;
-                sj.map_off = 0;
-                sj.map_step = 1;
-            } else {
-                const int per = (pj->nz - c + nc - 1) / nc;
-                sj.rows = pj->M * per;
-                sj.map_per = per;
-                sj.map_nz = pj->nz;
-                sj.map_off = c;
-                sj.map_step = nc;
-            }
+            sj.rows = lg.rows;
+            sj.map_per = lg.per;
+            sj.map_nz = lg.gnz;
+            sj.map_off = lg.off;
+            sj.map_step = lg.step;
             sj.in_dz = d;
             sj.in_nz = pj->nz;
             out.push_back(sj);

@@ -122,7 +122,10 @@ struct mpi3d_plan {
     int nb2;        // 2*nb real columns
     int nbp2;       // nb2 padded to 32
     int nct;        // nbp2 / 32
-    long L;         // lines
+    long L;         // lines: the x-drive lines, then the z-drive lines (dual drive)
+    long Lx, Lz;    // x-drive lines M*nz; z-drive lines M*nu (0 unless dual drive)
+    int drive_axes;
+    double a_z;     // z-drive amplitude
     long nvox;
     // signal kernel configuration
     int nchunks, cps, nsplit, ngroups, gct;
@@ -143,6 +146,13 @@ struct mpi3d_plan {
     float *kf, *ff, *fa, *ka;
     __half *kf16, *ff16, *fa16, *ka16;
     int n_classes, psf_rows, n_ktab;
+    // Line groups of one signal stage, each with its own PSF table: the
+    // trajectory classes of a raster, or the x- and z-drive lines.  Group g's
+    // job row r is line (r / per) * gnz + off + step * (r % per).
+    struct LineGroup {
+        int rows, per, gnz, off, step, table;
+    } groups[2];
+    int n_line_groups;
     int n_passes;                 // signal passes per application: 2 psf_rows + 1
     size_t k_elems;
     double raster_sweep;
@@ -160,9 +170,14 @@ struct mpi3d_plan {
 namespace mpi3d {
 
 // Launchers (return hipError_t of the launch).
+// The operator's projection into the workspace lines rt [L][nup]: the x-drive
+// lines, then (dual drive) the z-drive lines transposed from them.
 hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt,
                           hipStream_t st);
-hipError_t launch_backproject(const mpi3d_plan *pl, const float *rt, float *xo, const float *x_sub,
+// The operator's backprojection of the workspace lines rt: with the dual drive
+// the z-drive lines are first added, transposed, into the x-drive lines (rt
+// is modified).
+hipError_t launch_backproject(const mpi3d_plan *pl, float *rt, float *xo, const float *x_sub,
                               double lambda, double *norm_parts, int *nparts, hipStream_t st,
                               const float *x_add = nullptr);
 hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);

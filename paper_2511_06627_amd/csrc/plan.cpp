@@ -171,7 +171,13 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (g->psf_rows < 0) return MPI3D_EINVAL;
     const int psf_rows = std::min(g->psf_rows, g->nz - 1);
     if (psf_rows > 0 && (n_classes > 1 || (precisions & ~(1 << MPI3D_FP32)))) return MPI3D_ENOTSUP;
-    const int n_ktab = n_classes * (psf_rows + 1);
+    // dual drive: z-drive lines across the z-rows, as many entries as the
+    // x-drive lines hold (nz <= n_u), collinear only
+    const int drive_axes = g->drive_axes == 2 ? 2 : 1;
+    if (g->drive_axes < 0 || g->drive_axes > 2 || !(g->drive_amp_z >= 0)) return MPI3D_EINVAL;
+    if (drive_axes == 2 && (g->nz > nu || n_classes > 1 || psf_rows > 0 || (precisions & (1 << MPI3D_PRECOMPOSED))))
+        return MPI3D_ENOTSUP;
+    const int n_ktab = drive_axes == 2 ? 2 : n_classes * (psf_rows + 1);
 
     // kept bins, validated
     std::vector<long> bins;
@@ -210,7 +216,26 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->nb2 = 2 * pl->nb;
     pl->nbp2 = round_up(pl->nb2, kColTile);
     pl->nct = pl->nbp2 / kColTile;
-    pl->L = (long)pl->M * pl->nz;
+    pl->drive_axes = drive_axes;
+    pl->a_z = g->drive_amp_z > 0 ? g->drive_amp_z : g->nz / 2.0;
+    pl->Lx = (long)pl->M * pl->nz;
+    pl->Lz = drive_axes == 2 ? (long)pl->M * nu : 0;
+    pl->L = pl->Lx + pl->Lz;
+    // line groups of a signal stage (each with its own PSF table)
+    if (n_classes > 1) {
+        pl->n_line_groups = n_classes;
+        for (int c = 0; c < n_classes; ++c) {
+            const int per = (pl->nz - c + n_classes - 1) / n_classes;
+            pl->groups[c] = {pl->M * per, per, pl->nz, c, n_classes, c};
+        }
+    } else if (drive_axes == 2) {
+        pl->n_line_groups = 2;
+        pl->groups[0] = {(int)pl->Lx, (int)pl->Lx, 0, 0, 1, 0};
+        pl->groups[1] = {(int)pl->Lz, (int)pl->Lz, 0, (int)pl->Lx, 1, 1};
+    } else {
+        pl->n_line_groups = 1;
+        pl->groups[0] = {(int)pl->L, (int)std::max<long>(1, pl->L), 0, 0, 1, 0};
+    }
     pl->nvox = (long)pl->nx * pl->ny * pl->nz;
     pl->nchunks = pl->ntp / kChunk;
 
@@ -326,15 +351,20 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     {
         const double om = 2.0 * kPi * pl->P / T;
         for (int tb = 0; tb < n_ktab; ++tb) {
-            const int cl = tb / (psf_rows + 1), d = tb % (psf_rows + 1);
+            // the z-drive table (dual drive): amplitude a_z, samples at the
+            // centred z-rows, zero beyond nz
+            const bool zt = drive_axes == 2 && tb == 1;
+            const int cl = zt ? 0 : tb / (psf_rows + 1), d = zt ? 0 : tb % (psf_rows + 1);
             const double dir = cl == 0 ? 1.0 : -1.0, S = pl->raster_sweep;
+            const double amp = zt ? pl->a_z : pl->a, centre = zt ? 0.5 * (pl->nz - 1) : cu;
+            const int npts = zt ? pl->nz : NU;
             double *Kc = &K[KE * tb];
             for (int n = 0; n < T; ++n) {
                 double ph = om * n;
-                double xi = pl->a * std::sin(ph) + dir * S * ((double)n / T - 0.5);
-                double v = pl->a * om * std::cos(ph) + dir * S / T;
-                for (int p = 0; p < NU; ++p) {
-                    const double du = xi - (p - cu);
+                double xi = amp * std::sin(ph) + dir * S * ((double)n / T - 0.5);
+                double v = amp * om * std::cos(ph) + dir * S / T;
+                for (int p = 0; p < npts; ++p) {
+                    const double du = xi - (p - centre);
                     Kc[(size_t)n * NUP + p] =
                         v * (d == 0 ? langevin_deriv(du / pl->w) / pl->w : psf_xx(du, (double)d, pl->w));
                 }
@@ -611,8 +641,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
         };
         int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2, pl->ngroups,
-                      pl->gct, precisions, n_classes, psf_rows};
-        double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep};
+                      pl->gct, precisions, n_classes, psf_rows, drive_axes, drive_axes == 2 ? pl->nz : 0};
+        double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep, drive_axes == 2 ? pl->a_z : 0.0};
         mix(ints, sizeof(ints));
         mix(dbl, sizeof(dbl));
         if (g->rx_filter) mix(g->rx_filter, sizeof(float) * 2 * pl->nb);
@@ -656,7 +686,7 @@ extern "C" int mpi3d_plan_query(const mpi3d_plan *pl, mpi3d_plan_info *info)
     info->n_lines = pl->L;
     info->n_bins = pl->nb;
     info->n_data_floats = 2 * pl->L * pl->nb;
-    info->n_proj_floats = pl->L * pl->nu;
+    info->n_proj_floats = pl->Lx * pl->nu;
     info->op_ws_bytes = (int64_t)pl->op_ws_bytes;
     info->solve_ws_bytes = (int64_t)pl->solve_ws_bytes;
     info->table_bytes = (int64_t)pl->table_bytes;

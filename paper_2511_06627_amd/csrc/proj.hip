@@ -479,7 +479,60 @@ __global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride
     }
 }
 
+// Dual drive: z-drive line (m, p) of the workspace (line Lx + m*nu + p) holds
+// column p of the projections of angle m across the z-rows, zero beyond nz.
+// One block moves a 32 x 32 tile (rows k, columns p) of one angle through LDS
+// so both the read and the write are row-contiguous.
+constexpr int kTr = 32;
+
+__global__ __launch_bounds__(256) void zlines_kernel(float *rt, int nz, int nu, int nup, long Lx)
+{
+    __shared__ float tile[kTr][kTr + 1];
+    const int m = blockIdx.z, k0 = blockIdx.y * kTr, p0 = blockIdx.x * kTr;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+    for (int j = ty; j < kTr; j += 8) {
+        const int k = k0 + j, p = p0 + tx;
+        tile[j][tx] = (k < nz && p < nu) ? rt[((size_t)m * nz + k) * nup + p] : 0.f;
+    }
+    __syncthreads();
+    for (int j = ty; j < kTr; j += 8) {
+        const int p = p0 + j, k = k0 + tx;
+        if (p < nu && k < nup) rt[(size_t)(Lx + (long)m * nu + p) * nup + k] = tile[tx][j];
+    }
+}
+
+// Transpose of zlines_kernel, added: x-drive line (m, k), column p gains
+// element k of z-drive line (m, p).
+__global__ __launch_bounds__(256) void fold_zlines_kernel(float *rt, int nz, int nu, int nup, long Lx)
+{
+    __shared__ float tile[kTr][kTr + 1];
+    const int m = blockIdx.z, k0 = blockIdx.y * kTr, p0 = blockIdx.x * kTr;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < kTr; j += 8) {
+        const int p = p0 + j, k = k0 + tx;
+        tile[j][tx] = (p < nu && k < nz) ? rt[(size_t)(Lx + (long)m * nu + p) * nup + k] : 0.f;
+    }
+    __syncthreads();
+    for (int j = ty; j < kTr; j += 8) {
+        const int k = k0 + j, p = p0 + tx;
+        if (k < nz && p < nu) rt[((size_t)m * nz + k) * nup + p] += tile[tx][j];
+    }
+}
+
 }  // namespace
+
+static hipError_t launch_zlines(const mpi3d_plan *pl, float *rt, bool fold, hipStream_t st)
+{
+    // z-drive lines have nup entries (nz used), so the tiles cover nup rows k
+    // when writing them and nz when folding back
+    const int krows = fold ? pl->nz : pl->nup;
+    const dim3 grid((pl->nu + kTr - 1) / kTr, (krows + kTr - 1) / kTr, pl->M);
+    if (fold)
+        hipLaunchKernelGGL(fold_zlines_kernel, grid, dim3(256), 0, st, rt, pl->nz, pl->nu, pl->nup, pl->Lx);
+    else
+        hipLaunchKernelGGL(zlines_kernel, grid, dim3(256), 0, st, rt, pl->nz, pl->nu, pl->nup, pl->Lx);
+    return hipGetLastError();
+}
 
 static ProjArgs base_args(const mpi3d_plan *pl)
 {
@@ -532,8 +585,9 @@ hipError_t launch_project_strided(const mpi3d_plan *pl, const float *x, float *r
 // xb non-null: gather from the bf16 copy (mixed path)
 hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *xb, float *rt, hipStream_t st)
 {
-    if (xb) return launch_fwd<uint32_t>(pl, xb, pl->fwd16, rt, pl->nup, st);
-    return launch_fwd32(pl, x, rt, pl->nup, st);
+    hipError_t e = xb ? launch_fwd<uint32_t>(pl, xb, pl->fwd16, rt, pl->nup, st) : launch_fwd32(pl, x, rt, pl->nup, st);
+    if (e == hipSuccess && pl->drive_axes == 2) e = launch_zlines(pl, rt, false, st);
+    return e;
 }
 
 hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int in_stride, float *xo,
@@ -560,9 +614,13 @@ hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int
     return hipGetLastError();
 }
 
-hipError_t launch_backproject(const mpi3d_plan *pl, const float *rt, float *xo, const float *x_sub, double lambda,
+hipError_t launch_backproject(const mpi3d_plan *pl, float *rt, float *xo, const float *x_sub, double lambda,
                               double *norm_parts, int *nparts, hipStream_t st, const float *x_add)
 {
+    if (pl->drive_axes == 2) {
+        hipError_t e = launch_zlines(pl, rt, true, st);
+        if (e != hipSuccess) return e;
+    }
     return launch_backproject_strided(pl, rt, pl->nup, xo, x_sub, lambda, norm_parts, nparts, st, x_add);
 }
 

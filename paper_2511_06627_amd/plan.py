@@ -31,7 +31,7 @@ def _stream(stream):
 class Plan:
     def __init__(self, nx, ny, nz, n_angles, n_t, drive_cycles, psf_width, harm_lo, harm_hi, half_band,
                  op_scale, theta=None, n_u=0, drive_amp=0.0, rx_filter=None, precisions=("fp32",), device=0,
-                 raster_sweep=0.0, psf_rows=0):
+                 raster_sweep=0.0, psf_rows=0, drive_axes=1, drive_amp_z=0.0):
         lib = _lib.load()
         self.device = torch.device("cuda", device)
         g = _lib.Geometry()
@@ -58,6 +58,8 @@ class Plan:
         g.precisions = mask
         g.raster_sweep = raster_sweep
         g.psf_rows = psf_rows
+        g.drive_axes = drive_axes
+        g.drive_amp_z = drive_amp_z
         self.precisions = tuple(precisions)
         self.raster_sweep = float(raster_sweep)
         self.psf_rows = int(psf_rows)
@@ -71,8 +73,14 @@ class Plan:
         self.norm_iters = int(info.norm_iters)
         self.shape = (nz, ny, nx)
         self.n_u = n_u or nx
-        self.data_shape = (n_angles, nz, int(info.n_bins))
+        self.drive_axes = 2 if drive_axes == 2 else 1
+        if self.drive_axes == 2:    # x-drive lines, then z-drive lines
+            self.data_shape = (int(info.n_lines), int(info.n_bins))
+        else:
+            self.data_shape = (n_angles, nz, int(info.n_bins))
         self.proj_shape = (n_angles, nz, self.n_u)
+        # the signal stage's lines: the projections, plus the z-drive lines
+        self.lines_shape = (int(info.n_lines), self.n_u) if self.drive_axes == 2 else self.proj_shape
         self._ws = None
 
     @classmethod
@@ -154,7 +162,7 @@ class Plan:
 
     def signal_adj(self, b, precision="fp32", out=None, ws=None, stream=None):
         self._check_data(b)
-        out = torch.empty(self.proj_shape, dtype=torch.float32, device=self.device) if out is None else out
+        out = torch.empty(self.lines_shape, dtype=torch.float32, device=self.device) if out is None else out
         ws = self._op_ws(ws)
         check("mpi3d_signal_adj", _lib.load().mpi3d_signal_adj(self._h, PRECISION[precision], _ptr(b), _ptr(out),
                                                                 _ptr(ws), ws.numel(), _stream(stream)))

@@ -1,0 +1,164 @@
+"""GPU parity of the dual-drive scan (each angle scanned with the drive along x
+and again along z; the z-drive lines run across the z-rows at each detector
+column) against the FP64 oracle.
+
+Tolerances: the bars of the single-drive scan -- FP32 1e-5 relative L2, mixed
+operator 5e-3, mixed refinement 1e-4 of the FP64 minimiser.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry, operator as oop, signal as osig, solvers
+from helpers import rel_l2, random_volume
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL_MIX_OP = 5e-3
+TOL_MIXED = 1e-4
+
+# name: (nx, ny, nz, M, T, P, w, k_lo, k_hi, D)
+CASES = {
+    # ragged: n_u 40 -> 64, odd nz, 35 x-drive and 280 z-drive lines
+    "dual_ragged": (40, 36, 5, 7, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1),
+    # nz = n_u: z-drive lines as long as the x-drive ones, several tiles each
+    "dual_square": (48, 48, 48, 6, 2048, 2048 / 256 + 1 / 3, 3.0, 1, 12, 2),
+}
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _geom(name, op_scale=1.0):
+    nx, ny, nz, M, T, P, w, klo, khi, D = CASES[name]
+    return geometry.Geometry(nx=nx, ny=ny, nz=nz, n_angles=M, n_t=T, drive_cycles=P, psf_width=w,
+                             harm_lo=klo, harm_hi=khi, half_band=D, op_scale=op_scale, drive_axes=2)
+
+
+def _plan(name, op_scale, precisions=("fp32", "mixed"), **kw):
+    from paper_2511_06627_amd.plan import Plan
+    nx, ny, nz, M, T, P, w, klo, khi, D = CASES[name]
+    return Plan(nx, ny, nz, M, T, P, w, klo, khi, D, op_scale, precisions=precisions, drive_axes=2, **kw)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request, torch_mod):
+    _log("case %s" % request.param)
+    g = oop.normalised(_geom(request.param), iters_min=30, rtol=1e-9)
+    return request.param, g, _plan(request.param, g.op_scale)
+
+
+def _dev(torch_mod, a, dtype):
+    return torch_mod.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _data(g, seed):
+    rng = np.random.default_rng(seed)
+    shape = (g.n_data_lines, g.n_bins)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def test_dual_forward_and_adjoint_parity(case, torch_mod):
+    name, g, plan = case
+    x = random_volume(g, 1)
+    y = _data(g, 2)
+    want_f, want_a = oop.forward(g, x), oop.adjoint(g, y)
+    xd, yd = _dev(torch_mod, x, torch_mod.float32), _dev(torch_mod, y, torch_mod.complex64)
+    for prec, tol in (("fp32", TOL32), ("mixed", TOL_MIX_OP)):
+        ef = rel_l2(plan.forward(xd, precision=prec).cpu().numpy(), want_f)
+        ea = rel_l2(plan.adjoint(yd, precision=prec).cpu().numpy(), want_a)
+        _log("%s %s rel err forward %.3e adjoint %.3e" % (name, prec, ef, ea))
+        assert ef <= tol and ea <= tol
+
+
+def test_dual_signal_stages(case, torch_mod):
+    """The signal stage on all lines: the x-drive lines through the x table,
+    the z-drive lines (first nz entries used) through the z table."""
+    name, g, plan = case
+    rng = np.random.default_rng(3)
+    rt = rng.standard_normal((g.n_angles, g.nz, g.n_u))
+    lines = np.zeros((g.n_data_lines, g.n_u))
+    lines[:g.n_lines] = rt.reshape(g.n_lines, g.n_u)
+    lines[g.n_lines:, :g.nz] = osig.z_lines(g, rt)
+    op = oop.Operator(g)
+    want = np.concatenate([op._lines_fwd(rt.reshape(g.n_lines, g.n_u)), op._z_fwd(osig.z_lines(g, rt))])
+    ef = rel_l2(plan.signal_fwd(_dev(torch_mod, lines, torch_mod.float32)).cpu().numpy(), want)
+    y = _data(g, 4)
+    got = plan.signal_adj(_dev(torch_mod, y, torch_mod.complex64)).cpu().numpy()
+    ea_x = rel_l2(got[:g.n_lines], op._lines_adj(y[:g.n_lines]))
+    ea_z = rel_l2(got[g.n_lines:, :g.nz], op._z_adj(y[g.n_lines:]))
+    _log("%s signal stages rel err fwd %.3e adj x %.3e z %.3e" % (name, ef, ea_x, ea_z))
+    assert ef <= TOL32 and ea_x <= TOL32 and ea_z <= TOL32
+    assert np.all(got[g.n_lines:, g.nz:] == 0)
+
+
+def test_dual_gpu_adjoint_identity(case, torch_mod):
+    name, g, plan = case
+    x = random_volume(g, 5)
+    y = _data(g, 6)
+    ax = plan.forward(_dev(torch_mod, x, torch_mod.float32)).cpu().numpy().astype(np.complex128)
+    aty = plan.adjoint(_dev(torch_mod, y, torch_mod.complex64)).cpu().numpy().astype(np.float64)
+    lhs = np.vdot(ax, y.astype(np.complex64).astype(np.complex128)).real
+    rhs = float(np.vdot(x.astype(np.float32).astype(np.float64), aty))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(ax) * np.linalg.norm(y)
+
+
+def test_dual_x_half_is_the_single_drive_scan(torch_mod):
+    """The first n_angles * nz lines of a dual-drive forward are the
+    single-drive scan's data, bit for bit."""
+    from paper_2511_06627_amd.plan import Plan
+    nx, ny, nz, M, T, P, w, klo, khi, D = CASES["dual_ragged"]
+    pd = _plan("dual_ragged", 0.6, precisions=("fp32",))
+    ps = Plan(nx, ny, nz, M, T, P, w, klo, khi, D, 0.6)
+    x = _dev(torch_mod, random_volume(_geom("dual_ragged"), 7), torch_mod.float32)
+    bd = pd.forward(x)
+    bs = ps.forward(x)
+    assert torch_mod.equal(bd[:M * nz].reshape(bs.shape), bs)
+
+
+def test_dual_rejects_unsupported(torch_mod):
+    from paper_2511_06627_amd._lib import Mpi3dError
+    from paper_2511_06627_amd.plan import Plan
+    for kw in (dict(precisions=("fp32", "precomposed")), dict(raster_sweep=5.0), dict(psf_rows=1)):
+        with pytest.raises(Mpi3dError):
+            _plan("dual_ragged", 1.0, **kw)
+    with pytest.raises(Mpi3dError):      # nz > n_u
+        Plan(16, 16, 20, 4, 1024, 4.333, 2.0, 1, 6, 1, 1.0, drive_axes=2)
+
+
+def test_dual_device_normalisation(torch_mod):
+    g = oop.normalised(_geom("dual_ragged"), iters_min=30, rtol=1e-12)
+    plan = _plan("dual_ragged", 0.0, precisions=("fp32",))
+    rel = abs(plan.op_scale - g.op_scale) / g.op_scale
+    _log("dual_ragged device c_A %.9e (%d its) oracle %.9e rel %.2e"
+         % (plan.op_scale, plan.norm_iters, g.op_scale, rel))
+    assert rel <= 1e-5
+
+
+def test_dual_cgls_and_mixed_refinement_reach_minimiser(torch_mod):
+    name = "dual_ragged"
+    g = oop.normalised(_geom(name), iters_min=30, rtol=1e-9)
+    x_true = random_volume(g, 10)
+    b, _ = oop.make_data(g, x_true, 0.01, 11)
+    lam = 1e-3
+    xs, n = solvers.reference_minimiser(oop.Operator(g, precomposed=True), b, lam, tol=1e-12)
+    plan = _plan(name, g.op_scale)
+    bd = _dev(torch_mod, b, torch_mod.complex64)
+    x, rep = plan.solve(bd, lam, iters=max(80, n + 20))
+    err32 = rel_l2(x.cpu().numpy(), xs)
+    xm, repm = plan.solve(bd, lam, precision="mixed", refine_sweeps=5, inner_iters=20)
+    errm = rel_l2(xm.cpu().numpy(), xs)
+    _log("dual CGLS %d its vs x*: %.3e; mixed 5x20 %.3e (oracle needed %d)" % (rep.iters_done, err32, errm, n))
+    assert rep.status == 0 and repm.status == 0
+    assert err32 <= TOL32 and errm <= TOL_MIXED
