@@ -614,6 +614,29 @@ def main():
     log("tensor PSF (R = 3) A^T A: %s" % tensor)
     del plant, wst
 
+    # the same scan acquired with both drive directions: 36 x 192 z-drive
+    # lines (96 samples, padded to the x-drive lines' 192) after the x-drive ones
+    pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
+    wsd = pland.workspace("op")
+    ybd = torch.empty(pland.data_shape, dtype=torch.complex64, device="cuda")
+    dual = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale}
+    for prec in ("fp32", "mixed"):
+        def stepd():
+            pland.forward(x, precision=prec, out=ybd, ws=wsd)
+            pland.adjoint(ybd, precision=prec, out=xo, ws=wsd)
+
+        for _ in range(args.warmup):
+            stepd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            stepd()
+        torch.cuda.synchronize()
+        dtd = time.perf_counter() - t0
+        dual[prec] = {"applies_per_s": round(args.steps / dtd, 2), "ms_per_step": round(1e3 * dtd / args.steps, 4)}
+    log("dual drive A^T A: %s" % dual)
+    del pland, wsd, ybd
+
     # CGLS iteration rate of the configured 50-iteration solve
     swk = plan.workspace("solve")
     plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
@@ -704,6 +727,7 @@ def main():
         "precomposed": precomposed,
         "raster": raster,
         "tensor_psf": tensor,
+        "dual_drive": dual,
         "serving": serve,
         "hdr": hdr,
         "oracle_small": cpu.get("oracle_small") if cpu is not None else None,
