@@ -71,12 +71,14 @@ enum {
  * MFMA.  MIXED: projection gathers read bf16 copies of the volume and of the
  * line data, the signal contractions run on fp16 MFMA with fp32 accumulation,
  * per-line power-of-two scaling and per-harmonic-band scaling.  PRECOMPOSED:
- * every FFL line shares one trajectory, so A_DC = S D_Gamma F V E H B is one
- * real 2n_bins x n_u matrix G; the plan forms G = F^T K once in float64 on the
- * host, and the signal stage becomes a float32 library GEMM (rocBLAS) of the
- * projections with G (or its transpose) -- the same operator without forming
- * time signals, about (n_t (n_u + 2 n_bins)) / (2 n_bins n_u) times fewer
- * flops.  PRECOMPOSED serves mpi3d_forward, mpi3d_adjoint, mpi3d_signal_* and
+ * the lines of one PSF table share one trajectory, so A_DC = S D_Gamma F V E H B
+ * is one real 2n_bins x n_u matrix G per table (per raster sweep direction,
+ * tensor-PSF row offset, or drive axis); the plan forms G = F^T K once in
+ * float64 on the host, and the signal stage becomes float32 library GEMMs
+ * (rocBLAS) of the projections with each G (or its transpose), batched over
+ * the angles where a table's lines are strided or shifted -- the same operator
+ * without forming time signals, about (n_t (n_u + 2 n_bins)) / (2 n_bins n_u)
+ * times fewer flops.  PRECOMPOSED serves mpi3d_forward, mpi3d_adjoint, mpi3d_signal_* and
  * mpi3d_time_kernel; mpi3d_solve and serving states reject it
  * (MPI3D_ENOTSUP).  Calls with PRECOMPOSED on one plan must not run
  * concurrently from several host threads (they share the plan's GEMM handle). */
@@ -125,7 +127,7 @@ typedef struct {
                                     sequence for every angle (Sec. 2.2), so
                                     xi_n = a sin(2 pi P n/T) + c_n and v_n = xi' gains
                                     +-S/T.  With S != 0 and nz >= 2 the plan holds two
-                                    PSF tables; MPI3D_PRECOMPOSED is then MPI3D_ENOTSUP */
+                                    PSF tables (and two precomposed line matrices) */
     int32_t psf_rows;            /* R >= 0: z-rows coupled by the tensor PSF on each side
                                     (Appendix B eq. PSF, xx entry in the xz-plane of the 2D
                                     FFL model of Sec. 2.2, in-plane gradient of equal
@@ -134,8 +136,8 @@ typedef struct {
                                     h_xx(du, dz) = L'(r/w)/w du^2/r^2 + L(r/w) dz^2/r^3,
                                     r = |(du, dz)|, dz = k - k'.  0 = the collinear PSF;
                                     values above nz - 1 act as nz - 1 (the whole model).
-                                    R > 0 costs 2R + 1 signal passes per application and
-                                    is FP32 only: MPI3D_MIXED or MPI3D_PRECOMPOSED in
+                                    R > 0 costs 2R + 1 signal passes per application
+                                    (MPI3D_PRECOMPOSED: 2R + 1 GEMMs); MPI3D_MIXED in
                                     precisions, or raster_sweep != 0, is MPI3D_ENOTSUP */
     int32_t drive_axes;          /* 1 (or 0): the x-drive scan.  2: every angle is also
                                     scanned with the drive and receive coil along z
@@ -144,8 +146,8 @@ typedef struct {
                                     z_k = k - (nz-1)/2, same PSF, time grid and bins.
                                     Its n_angles * n_u lines follow the x-drive lines in
                                     b: line n_angles*nz + m*n_u + p.  Needs nz <= n_u;
-                                    with raster_sweep != 0, psf_rows > 0 or
-                                    MPI3D_PRECOMPOSED it is MPI3D_ENOTSUP */
+                                    with raster_sweep != 0 or psf_rows > 0 it is
+                                    MPI3D_ENOTSUP */
     double drive_amp_z;          /* z-drive amplitude in voxels; 0 = nz/2 */
 } mpi3d_geometry;
 

@@ -217,30 +217,96 @@ static int project_into(const mpi3d_plan *pl, int prec, const float *x, const ui
     return MPI3D_OK;
 }
 
-// Precomposed signal stage: data[L][2nb] = c_A * lines[L][ld_in] G^T, or
-// lines[L][ld_out] = c_A * data[L][2nb] G (plain float32 GEMMs).
-static int gemm_signal_fwd(const mpi3d_plan *pl, const float *lines, int ld_in, float *data, hipStream_t st)
+// Precomposed signal stage: data[l] = c_A G_t rho(l) for every line l, or
+// lines[l] = c_A sum G_t^T data(l), as float32 GEMMs (rocBLAS, column-major
+// views: data^T is 2nb x lines, lines^T n_u x lines).  One GEMM per line group
+// and z-row offset: a group of consecutive lines is one GEMM; a raster class
+// (every second z-row) and a tensor-PSF offset (rows shifted within each
+// angle) are batched over the angles with the rows' own strides.  Offset 0
+// runs first with beta = 0 and covers every line; the other offsets add.
+struct GemmRun {
+    int n;              // lines per angle (or all lines)
+    long in0, out0;     // first input / output line
+    int in_step, out_step;   // lines between consecutive rows
+    int batch;          // angles (1: one plain GEMM)
+    long batch_lines;   // lines between the angles' first rows
+    int table;
+    float beta;
+};
+
+static void gemm_runs(const mpi3d_plan *pl, bool fwd, std::vector<GemmRun> &runs)
+{
+    const int R = pl->psf_rows;
+    for (int gi = 0; gi < pl->n_line_groups; ++gi) {
+        const mpi3d_plan::LineGroup &lg = pl->groups[gi];
+        for (int k = 0; k <= 2 * R; ++k) {
+            const int d = k == 0 ? 0 : (k <= R ? k : R - k);   // 0, 1..R, -1..-R
+            GemmRun r{};
+            r.table = lg.table * (R + 1) + (d < 0 ? -d : d);
+            r.beta = d == 0 ? 0.f : 1.f;
+            if (lg.gnz == 0 && d == 0) {        // consecutive lines
+                r.n = lg.rows;
+                r.in0 = r.out0 = lg.off;
+                r.in_step = r.out_step = 1;
+                r.batch = 1;
+            } else if (d == 0) {                // raster class: rows off, off + step, ... of each angle
+                r.n = lg.per;
+                r.in0 = r.out0 = lg.off;
+                r.in_step = r.out_step = lg.step;
+                r.batch = pl->M;
+                r.batch_lines = lg.gnz;
+            } else {                            // tensor offset d: row k reads row k + d of its angle
+                // forward: out rows [lo, hi) read rows lo + d ...; adjoint:
+                // out rows k' gather data rows k' - d
+                const int lo = fwd ? std::max(0, -d) : std::max(0, d);
+                const int hi = fwd ? std::min(pl->nz, pl->nz - d) : std::min(pl->nz, pl->nz + d);
+                r.n = hi - lo;
+                r.out0 = lo;
+                r.in0 = fwd ? lo + d : lo - d;
+                r.in_step = r.out_step = 1;
+                r.batch = pl->M;
+                r.batch_lines = pl->nz;
+            }
+            if (r.n > 0) runs.push_back(r);
+        }
+    }
+}
+
+static int gemm_signal(const mpi3d_plan *pl, bool fwd, const float *in, int ld_in, float *out, int ld_out,
+                       hipStream_t st)
 {
     if (!pl->blas) return MPI3D_EINVAL;
-    const float alpha = (float)pl->op_scale, beta = 0.f;
+    const float alpha = (float)pl->op_scale;
     if (rocblas_set_stream(pl->blas, st) != rocblas_status_success) return MPI3D_EDEVICE;
-    // column-major: data^T (2nb x L) = Gt (2nb x n_u, ld 2nb) * lines^T (n_u x L, ld ld_in)
-    if (rocblas_sgemm(pl->blas, rocblas_operation_none, rocblas_operation_none, pl->nb2, (int)pl->L, pl->nu, &alpha,
-                      pl->gt, pl->nb2, lines, ld_in, &beta, data, pl->nb2) != rocblas_status_success)
-        return MPI3D_EDEVICE;
+    std::vector<GemmRun> runs;
+    gemm_runs(pl, fwd, runs);
+    for (const GemmRun &r : runs) {
+        const float *G = pl->gt + (size_t)r.table * pl->gt_elems;
+        const float *B = in + r.in0 * ld_in;
+        float *C = out + r.out0 * ld_out;
+        const long sb = r.batch_lines * ld_in, sc = r.batch_lines * ld_out;
+        rocblas_status stt;
+        if (fwd)   // data^T (2nb x n) = Gt (2nb x n_u, ld 2nb) * lines^T (n_u x n)
+            stt = rocblas_sgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, pl->nb2, r.n,
+                                                pl->nu, &alpha, G, pl->nb2, 0, B, r.in_step * ld_in, sb, &r.beta, C,
+                                                r.out_step * ld_out, sc, r.batch);
+        else       // lines^T (n_u x n) = Gt^T (n_u x 2nb) * data^T (2nb x n)
+            stt = rocblas_sgemm_strided_batched(pl->blas, rocblas_operation_transpose, rocblas_operation_none, pl->nu,
+                                                r.n, pl->nb2, &alpha, G, pl->nb2, 0, B, r.in_step * ld_in, sb, &r.beta,
+                                                C, r.out_step * ld_out, sc, r.batch);
+        if (stt != rocblas_status_success) return MPI3D_EDEVICE;
+    }
     return MPI3D_OK;
+}
+
+static int gemm_signal_fwd(const mpi3d_plan *pl, const float *lines, int ld_in, float *data, hipStream_t st)
+{
+    return gemm_signal(pl, true, lines, ld_in, data, pl->nb2, st);
 }
 
 static int gemm_signal_adj(const mpi3d_plan *pl, const float *data, float *lines, int ld_out, hipStream_t st)
 {
-    if (!pl->blas) return MPI3D_EINVAL;
-    const float alpha = (float)pl->op_scale, beta = 0.f;
-    if (rocblas_set_stream(pl->blas, st) != rocblas_status_success) return MPI3D_EDEVICE;
-    // column-major: lines^T (n_u x L) = Gt^T (n_u x 2nb) * data^T (2nb x L)
-    if (rocblas_sgemm(pl->blas, rocblas_operation_transpose, rocblas_operation_none, pl->nu, (int)pl->L, pl->nb2,
-                      &alpha, pl->gt, pl->nb2, data, pl->nb2, &beta, lines, ld_out) != rocblas_status_success)
-        return MPI3D_EDEVICE;
-    return MPI3D_OK;
+    return gemm_signal(pl, false, data, pl->nb2, lines, ld_out, st);
 }
 
 static int apply_forward(const mpi3d_plan *pl, int prec, const float *x, float *out, const OpWs &w, hipStream_t st)

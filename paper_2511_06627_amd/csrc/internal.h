@@ -159,7 +159,8 @@ struct mpi3d_plan {
     float *col_scale;     // [nbp2] mixed forward output scale per column
     float *band_scale;    // [nbp2] mixed adjoint input scale per column
     float adj_scale16;    // mixed adjoint output scale
-    float *gt = nullptr;  // precomposed: [n_up][2 nb] line matrix G^T (row-major)
+    float *gt = nullptr;  // precomposed: n_ktab line matrices G^T [n_up][2 nb] (row-major)
+    size_t gt_elems = 0;  // floats per line matrix
     rocblas_handle blas = nullptr;   // precomposed: GEMM handle
     // operator workspace layout (bytes from ws base)
     size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, op_ws_bytes;

@@ -165,18 +165,15 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
     int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
     if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED) | (1 << MPI3D_PRECOMPOSED))) return MPI3D_EINVAL;
-    // the precomposed line matrix assumes one trajectory shared by every line
-    if (n_classes > 1 && (precisions & (1 << MPI3D_PRECOMPOSED))) return MPI3D_ENOTSUP;
-    // tensor PSF row coupling: FP32 path only, without a raster
+    // tensor PSF row coupling: FP32 and precomposed variants, without a raster
     if (g->psf_rows < 0) return MPI3D_EINVAL;
     const int psf_rows = std::min(g->psf_rows, g->nz - 1);
-    if (psf_rows > 0 && (n_classes > 1 || (precisions & ~(1 << MPI3D_FP32)))) return MPI3D_ENOTSUP;
+    if (psf_rows > 0 && (n_classes > 1 || (precisions & (1 << MPI3D_MIXED)))) return MPI3D_ENOTSUP;
     // dual drive: z-drive lines across the z-rows, as many entries as the
     // x-drive lines hold (nz <= n_u), collinear only
     const int drive_axes = g->drive_axes == 2 ? 2 : 1;
     if (g->drive_axes < 0 || g->drive_axes > 2 || !(g->drive_amp_z >= 0)) return MPI3D_EINVAL;
-    if (drive_axes == 2 && (g->nz > nu || n_classes > 1 || psf_rows > 0 || (precisions & (1 << MPI3D_PRECOMPOSED))))
-        return MPI3D_ENOTSUP;
+    if (drive_axes == 2 && (g->nz > nu || n_classes > 1 || psf_rows > 0)) return MPI3D_ENOTSUP;
     const int n_ktab = drive_axes == 2 ? 2 : n_classes * (psf_rows + 1);
 
     // kept bins, validated
@@ -389,23 +386,28 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         }
     }
 
-    // precomposed line matrix Gt[p][c] = sum_n K[n][p] F[n][c] (the whole
-    // A_DC of one line, c_A aside), float64 accumulation
+    // precomposed line matrices Gt[p][c] = sum_n K[n][p] F[n][c] (the whole
+    // A_DC of one line, c_A aside), one per PSF table, float64 accumulation
     const bool precomp = precisions & (1 << MPI3D_PRECOMPOSED);
     std::vector<float> gt;
+    pl->gt_elems = (size_t)NUP * 2 * NB;
     if (precomp) {
         const int NB2 = 2 * NB;
-        std::vector<double> acc((size_t)NUP * NB2, 0.0);
-        for (int n = 0; n < T; ++n) {
-            const double *fr = &F[(size_t)n * NBP2];
-            for (int p = 0; p < NU; ++p) {
-                const double k = K[(size_t)n * NUP + p];
-                double *row = &acc[(size_t)p * NB2];
-                for (int c = 0; c < NB2; ++c) row[c] += k * fr[c];
+        gt.resize(pl->gt_elems * n_ktab);
+        std::vector<double> acc(pl->gt_elems);
+        for (int tb = 0; tb < n_ktab; ++tb) {
+            std::fill(acc.begin(), acc.end(), 0.0);
+            const double *Kc = &K[KE * tb];
+            for (int n = 0; n < T; ++n) {
+                const double *fr = &F[(size_t)n * NBP2];
+                for (int p = 0; p < NU; ++p) {
+                    const double k = Kc[(size_t)n * NUP + p];
+                    double *row = &acc[(size_t)p * NB2];
+                    for (int c = 0; c < NB2; ++c) row[c] += k * fr[c];
+                }
             }
+            for (size_t i = 0; i < acc.size(); ++i) gt[pl->gt_elems * tb + i] = (float)acc[i];
         }
-        gt.resize(acc.size());
-        for (size_t i = 0; i < acc.size(); ++i) gt[i] = (float)acc[i];
     }
 
     // ---- table layout in one device allocation -----------------------------

@@ -130,11 +130,25 @@ def test_dual_x_half_is_the_single_drive_scan(torch_mod):
 def test_dual_rejects_unsupported(torch_mod):
     from paper_2511_06627_amd._lib import Mpi3dError
     from paper_2511_06627_amd.plan import Plan
-    for kw in (dict(precisions=("fp32", "precomposed")), dict(raster_sweep=5.0), dict(psf_rows=1)):
+    for kw in (dict(raster_sweep=5.0), dict(psf_rows=1)):
         with pytest.raises(Mpi3dError):
             _plan("dual_ragged", 1.0, **kw)
     with pytest.raises(Mpi3dError):      # nz > n_u
         Plan(16, 16, 20, 4, 1024, 4.333, 2.0, 1, 6, 1, 1.0, drive_axes=2)
+
+
+def test_dual_precomposed(case, torch_mod):
+    """The precomposed variant: an x- and a z-drive line matrix, one GEMM each."""
+    name, g, _ = case
+    plan = _plan(name, g.op_scale, precisions=("fp32", "precomposed"))
+    x = random_volume(g, 16)
+    y = _data(g, 17)
+    ef = rel_l2(plan.forward(_dev(torch_mod, x, torch_mod.float32), precision="precomposed").cpu().numpy(),
+                oop.forward(g, x))
+    ea = rel_l2(plan.adjoint(_dev(torch_mod, y, torch_mod.complex64), precision="precomposed").cpu().numpy(),
+                oop.adjoint(g, y))
+    _log("%s precomposed rel err forward %.3e adjoint %.3e" % (name, ef, ea))
+    assert ef <= TOL32 and ea <= TOL32
 
 
 def test_dual_device_normalisation(torch_mod):

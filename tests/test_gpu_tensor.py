@@ -111,10 +111,25 @@ def test_tensor_rows_really_couple(torch_mod):
 
 def test_tensor_rejects_other_variants(torch_mod):
     from paper_2511_06627_amd._lib import Mpi3dError
-    for kw in (dict(precisions=("fp32", "mixed")), dict(precisions=("fp32", "precomposed")),
-               dict(raster_sweep=5.0)):
+    for kw in (dict(precisions=("fp32", "mixed")), dict(raster_sweep=5.0)):
         with pytest.raises(Mpi3dError):
             _plan("tensor_r2", 1.0, **kw)
+
+
+def test_tensor_precomposed(case, torch_mod):
+    """The precomposed variant: one line matrix per row offset, the offsets'
+    shifted rows as GEMMs batched over the angles."""
+    from paper_2511_06627_amd.plan import Plan
+    name, g, _ = case
+    plan = _plan(name, g.op_scale, precisions=("fp32", "precomposed"))
+    x = random_volume(g, 14)
+    y = random_data(g, 15)
+    ef = rel_l2(plan.forward(_dev(torch_mod, x, torch_mod.float32), precision="precomposed").cpu().numpy(),
+                oop.forward(g, x))
+    ea = rel_l2(plan.adjoint(_dev(torch_mod, y, torch_mod.complex64), precision="precomposed").cpu().numpy(),
+                oop.adjoint(g, y))
+    _log("%s precomposed rel err forward %.3e adjoint %.3e" % (name, ef, ea))
+    assert ef <= TOL32 and ea <= TOL32
 
 
 def test_tensor_device_normalisation(torch_mod):
