@@ -594,23 +594,23 @@ def main():
 
     # the same scan with the tensor PSF coupling each z-row to three rows on
     # either side (seven signal passes per application, FP32)
-    plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32",), psf_rows=3)
+    plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"), psf_rows=3)
     wst = plant.workspace("op")
+    tensor = {"psf_rows": 3, "signal_passes": 7}
+    for prec in ("fp32", "precomposed"):
+        def stept():
+            plant.forward(x, precision=prec, out=yb, ws=wst)
+            plant.adjoint(yb, precision=prec, out=xo, ws=wst)
 
-    def stept():
-        plant.forward(x, out=yb, ws=wst)
-        plant.adjoint(yb, out=xo, ws=wst)
-
-    for _ in range(args.warmup):
-        stept()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stept()
-    torch.cuda.synchronize()
-    dtt = time.perf_counter() - t0
-    tensor = {"psf_rows": 3, "signal_passes": 7, "applies_per_s": round(args.steps / dtt, 2),
-              "ms_per_step": round(1e3 * dtt / args.steps, 4)}
+        for _ in range(args.warmup):
+            stept()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            stept()
+        torch.cuda.synchronize()
+        dtt = time.perf_counter() - t0
+        tensor[prec] = {"applies_per_s": round(args.steps / dtt, 2), "ms_per_step": round(1e3 * dtt / args.steps, 4)}
     log("tensor PSF (R = 3) A^T A: %s" % tensor)
     del plant, wst
 
