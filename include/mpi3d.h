@@ -137,8 +137,8 @@ typedef struct {
                                     r = |(du, dz)|, dz = k - k'.  0 = the collinear PSF;
                                     values above nz - 1 act as nz - 1 (the whole model).
                                     R > 0 costs 2R + 1 signal passes per application
-                                    (MPI3D_PRECOMPOSED: 2R + 1 GEMMs); MPI3D_MIXED in
-                                    precisions, or raster_sweep != 0, is MPI3D_ENOTSUP */
+                                    (MPI3D_PRECOMPOSED: 2R + 1 GEMMs); with
+                                    raster_sweep != 0 it is MPI3D_ENOTSUP */
     int32_t drive_axes;          /* 1 (or 0): the x-drive scan.  2: every angle is also
                                     scanned with the drive and receive coil along z
                                     (Sec. 3.1): the z-drive scan of angle m has one line

@@ -184,7 +184,7 @@ static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
     const bool mixed = prec == MPI3D_MIXED;
     TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->n_passes * nsplit_of(pl, serve), pl->L * pl->nbp2, w.part,
                           mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
-                          norm_parts, nnorm, st));
+                          norm_parts, nnorm, st, RowPasses{pl->n_passes, pl->psf_rows, pl->nz}));
     return MPI3D_OK;
 }
 
@@ -196,7 +196,8 @@ static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
     const double scale = pl->op_scale * (mixed ? (double)pl->adj_scale16 : 1.0);
     TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride,
                                     pl->n_passes * nsplit_of(pl, serve) * pl->ngroups,
-                                    pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st));
+                                    pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st,
+                                    RowPasses{pl->n_passes, pl->psf_rows, pl->nz}));
     return MPI3D_OK;
 }
 

@@ -186,13 +186,20 @@ hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipSt
 int sig_fwd_supported(int nup, int gct, int precision);
 int sig_adj_supported(int nup, int gct, int precision);
 
-// Reductions and vector kernels (vec.hip)
+// Reductions and vector kernels (vec.hip).  The split reductions sum nparts
+// partial blocks; rp describes the tensor PSF's offset passes among them
+// (npass = 2 rows + 1 blocks of nparts / npass, pass p having read line
+// row + p - rows of the same angle's nz), which the mixed path's per-line
+// scales need (npass = 1: no coupling).
+struct RowPasses {
+    int npass, rows, nz;
+};
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
                              const float *row_scale, const float *col_scale, double scale, const float *b_sub,
-                             float *out, double *norm_parts, int *nnorm, hipStream_t st);
+                             float *out, double *norm_parts, int *nnorm, hipStream_t st, RowPasses rp);
 hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
                                        const float *part, const float *row_scale, double scale, float *out,
-                                       hipStream_t st);
+                                       hipStream_t st, RowPasses rp);
 hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st);
 hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
                             hipStream_t st);

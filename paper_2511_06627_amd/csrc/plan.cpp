@@ -165,10 +165,10 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
     int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
     if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED) | (1 << MPI3D_PRECOMPOSED))) return MPI3D_EINVAL;
-    // tensor PSF row coupling: FP32 and precomposed variants, without a raster
+    // tensor PSF row coupling: every precision, without a raster
     if (g->psf_rows < 0) return MPI3D_EINVAL;
     const int psf_rows = std::min(g->psf_rows, g->nz - 1);
-    if (psf_rows > 0 && (n_classes > 1 || (precisions & (1 << MPI3D_MIXED)))) return MPI3D_ENOTSUP;
+    if (psf_rows > 0 && n_classes > 1) return MPI3D_ENOTSUP;
     // dual drive: z-drive lines across the z-rows, as many entries as the
     // x-drive lines hold (nz <= n_u), collinear only
     const int drive_axes = g->drive_axes == 2 ? 2 : 1;

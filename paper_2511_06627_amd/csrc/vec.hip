@@ -48,12 +48,33 @@ __device__ __forceinline__ double sum_splits(const float *__restrict__ pp, int n
 }
 
 // out[row][c] = sign * sum_s part[s][row][c] * col_scale[c] / row_scale[row] (+ b_sub)
+// Sum of the split partials of one output element, undoing the mixed path's
+// per-line scale.  Without row coupling: the sum, divided by the line's own
+// scale.  With the tensor PSF's 2R + 1 offset passes (each a block of
+// nparts / npass splits, pass p having read line row + p - R): every pass's
+// sum divided by the scale of the line it read, in pass order.
+__device__ __forceinline__ double sum_unscaled(const float *__restrict__ pp, int nparts, long stride, long row,
+                                               const float *__restrict__ row_scale, RowPasses rp)
+{
+    if (!row_scale) return sum_splits(pp, nparts, stride);
+    if (rp.npass <= 1) return sum_splits(pp, nparts, stride) / (double)row_scale[row];
+    const int per = nparts / rp.npass;
+    const int k = (int)(row % rp.nz);
+    double v = 0.0;
+    for (int p = 0; p < rp.npass; ++p) {
+        const int d = p - rp.rows;
+        if (k + d < 0 || k + d >= rp.nz) continue;   // that pass read no line: its partials are zero
+        v += sum_splits(pp + (long)p * per * stride, per, stride) / (double)row_scale[row + d];
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2, int nbp2, int nparts,
                                                                long part_stride, const float *__restrict__ part,
                                                                const float *__restrict__ row_scale,
                                                                const float *__restrict__ col_scale, double scale,
                                                                const float *__restrict__ b_sub, float *out,
-                                                               double *norm_parts)
+                                                               double *norm_parts, RowPasses rp)
 {
     __shared__ double red[kThreads / 64];
     const long n = rows * nb2;
@@ -61,10 +82,9 @@ __global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2
     for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
         const long row = idx / nb2;
         const int c = (int)(idx - row * nb2);
-        const double v0 = sum_splits(part + row * nbp2 + c, nparts, part_stride);
+        const double v0 = sum_unscaled(part + row * nbp2 + c, nparts, part_stride, row, row_scale, rp);
         double v = v0 * scale;
         if (col_scale) v *= (double)col_scale[c];
-        if (row_scale) v /= (double)row_scale[row];
         if (b_sub) v = (double)b_sub[idx] - v;
         const float o = (float)v;
         out[idx] = o;
@@ -81,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
                                                                  int nparts, long part_stride,
                                                                  const float *__restrict__ part,
                                                                  const float *__restrict__ row_scale, double scale,
-                                                                 float *out)
+                                                                 float *out, RowPasses rp)
 {
     const long n = rows * out_stride;
     for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
@@ -89,9 +109,8 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
         const int p = (int)(idx - row * out_stride);
         float o = 0.f;
         if (p < nu) {
-            double v = sum_splits(part + row * nup + p, nparts, part_stride);
+            double v = sum_unscaled(part + row * nup + p, nparts, part_stride, row, row_scale, rp);
             v *= scale;
-            if (row_scale) v /= (double)row_scale[row];
             o = (float)v;
         }
         out[idx] = o;
@@ -351,22 +370,22 @@ int scal_slot_gamma0() { return S_GAMMA0; }
 
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
                              const float *row_scale, const float *col_scale, double scale, const float *b_sub,
-                             float *out, double *norm_parts, int *nnorm, hipStream_t st)
+                             float *out, double *norm_parts, int *nnorm, hipStream_t st, RowPasses rp)
 {
     const int g = grid_for(rows * nb2, kReduceBlocks);
     if (nnorm) *nnorm = g;
     hipLaunchKernelGGL(reduce_fwd_kernel, dim3(g), dim3(kThreads), 0, st, rows, nb2, nbp2, nparts, part_stride,
-                       part, row_scale, col_scale, scale, b_sub, out, norm_parts);
+                       part, row_scale, col_scale, scale, b_sub, out, norm_parts, rp);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
                                        const float *part, const float *row_scale, double scale, float *out,
-                                       hipStream_t st)
+                                       hipStream_t st, RowPasses rp)
 {
     const int g = grid_for(rows * out_stride, kReduceBlocks);
     hipLaunchKernelGGL(reduce_lines_kernel, dim3(g), dim3(kThreads), 0, st, rows, nu, nup, out_stride, nparts,
-                       part_stride, part, row_scale, scale, out);
+                       part_stride, part, row_scale, scale, out, rp);
     return hipGetLastError();
 }
 

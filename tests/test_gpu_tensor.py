@@ -1,8 +1,10 @@
 """GPU parity of the tensor-PSF operator (z-rows coupled through the xx entry
 of the tensor PSF, one signal pass per row offset) against the FP64 oracle.
 
-Tolerances: the FP32 bars of the collinear operator -- 1e-5 relative L2 for
-the operator, its stages and the converged CGLS solve.
+Tolerances: the bars of the collinear operator -- 1e-5 relative L2 for the
+FP32 operator, its stages and the converged CGLS solve; 5e-3 for the mixed
+operator (each offset pass's partial sums are unscaled by the scale of the
+line that pass read) and 1e-4 for mixed refinement.
 """
 import sys
 
@@ -15,6 +17,8 @@ from helpers import rel_l2, random_volume, random_data
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+TOL_MIX_OP = 5e-3
+TOL_MIXED = 1e-4
 
 # name: (nx, ny, nz, M, T, P, w, k_lo, k_hi, D, R)
 CASES = {
@@ -97,6 +101,19 @@ def test_tensor_gpu_adjoint_identity(case, torch_mod):
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(ax) * np.linalg.norm(y)
 
 
+def test_tensor_mixed_operator(case, torch_mod):
+    name, g, _ = case
+    plan = _plan(name, g.op_scale, precisions=("fp32", "mixed"))
+    x = random_volume(g, 18)
+    y = random_data(g, 19)
+    ef = rel_l2(plan.forward(_dev(torch_mod, x, torch_mod.float32), precision="mixed").cpu().numpy(),
+                oop.forward(g, x))
+    ea = rel_l2(plan.adjoint(_dev(torch_mod, y, torch_mod.complex64), precision="mixed").cpu().numpy(),
+                oop.adjoint(g, y))
+    _log("%s mixed rel err forward %.3e adjoint %.3e" % (name, ef, ea))
+    assert ef <= TOL_MIX_OP and ea <= TOL_MIX_OP
+
+
 def test_tensor_rows_really_couple(torch_mod):
     """A volume on one slice lights every line within R rows of it and no other."""
     name = "tensor_r2"
@@ -111,9 +128,8 @@ def test_tensor_rows_really_couple(torch_mod):
 
 def test_tensor_rejects_other_variants(torch_mod):
     from paper_2511_06627_amd._lib import Mpi3dError
-    for kw in (dict(precisions=("fp32", "mixed")), dict(raster_sweep=5.0)):
-        with pytest.raises(Mpi3dError):
-            _plan("tensor_r2", 1.0, **kw)
+    with pytest.raises(Mpi3dError):
+        _plan("tensor_r2", 1.0, raster_sweep=5.0)
 
 
 def test_tensor_precomposed(case, torch_mod):
@@ -149,8 +165,12 @@ def test_tensor_cgls_reaches_minimiser(torch_mod):
     b, _ = oop.make_data(g, x_true, 0.01, 11)
     lam = 1e-3
     xs, n = solvers.reference_minimiser(oop.Operator(g, precomposed=True), b, lam, tol=1e-12)
-    plan = _plan(name, g.op_scale)
-    x, rep = plan.solve(_dev(torch_mod, b, torch_mod.complex64), lam, iters=max(80, n + 20))
+    plan = _plan(name, g.op_scale, precisions=("fp32", "mixed"))
+    bd = _dev(torch_mod, b, torch_mod.complex64)
+    x, rep = plan.solve(bd, lam, iters=max(80, n + 20))
     err = rel_l2(x.cpu().numpy(), xs)
-    _log("tensor CGLS %d its vs x*: %.3e (oracle needed %d)" % (rep.iters_done, err, n))
+    xm, repm = plan.solve(bd, lam, precision="mixed", refine_sweeps=5, inner_iters=20)
+    errm = rel_l2(xm.cpu().numpy(), xs)
+    _log("tensor CGLS %d its vs x*: %.3e; mixed 5x20 %.3e (oracle needed %d)" % (rep.iters_done, err, errm, n))
     assert rep.status == 0 and err <= TOL32
+    assert repm.status == 0 and errm <= TOL_MIXED
