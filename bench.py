@@ -435,6 +435,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream and closed-loop capacity")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests in the serving stream (default 64)")
     ap.add_argument("--no-hdr", action="store_true", help="skip the high-dynamic-range scan")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the raster, tensor-PSF and dual-drive legs (their kernels run at other sizes)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="no oracle leg (for profiling runs): c_A estimated by the plan, data made on the device, "
                          "no cpu_baseline and no time-to-solve")
@@ -567,75 +569,77 @@ def main():
     log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * dtp / args.steps, ktp))
     del planp, wsp
 
-    # the same scan under a zig-zag raster (two PSF tables, per-line sweep
-    # direction): drive over a sixth of the fast axis, the focus field carrying
-    # the line across two thirds of it
-    ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
-    planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
-                 cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
-    wsr = planr.workspace("op")
-    raster = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale}
-    for prec in ("fp32", "mixed"):
-        def stepr():
-            planr.forward(x, precision=prec, out=yb, ws=wsr)
-            planr.adjoint(yb, precision=prec, out=xo, ws=wsr)
+    raster = tensor = dual = None
+    if not args.no_variants:
+        # the same scan under a zig-zag raster (two PSF tables, per-line sweep
+        # direction): drive over a sixth of the fast axis, the focus field carrying
+        # the line across two thirds of it
+        ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
+        planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
+                     cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
+        wsr = planr.workspace("op")
+        raster = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale}
+        for prec in ("fp32", "mixed"):
+            def stepr():
+                planr.forward(x, precision=prec, out=yb, ws=wsr)
+                planr.adjoint(yb, precision=prec, out=xo, ws=wsr)
 
-        for _ in range(args.warmup):
-            stepr()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            stepr()
-        torch.cuda.synchronize()
-        dtr = time.perf_counter() - t0
-        raster[prec] = {"applies_per_s": round(args.steps / dtr, 2), "ms_per_step": round(1e3 * dtr / args.steps, 4)}
-    log("raster A^T A: %s" % raster)
-    del planr, wsr
+            for _ in range(args.warmup):
+                stepr()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                stepr()
+            torch.cuda.synchronize()
+            dtr = time.perf_counter() - t0
+            raster[prec] = {"applies_per_s": round(args.steps / dtr, 2), "ms_per_step": round(1e3 * dtr / args.steps, 4)}
+        log("raster A^T A: %s" % raster)
+        del planr, wsr
 
-    # the same scan with the tensor PSF coupling each z-row to three rows on
-    # either side (seven signal passes per application, FP32)
-    plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"), psf_rows=3)
-    wst = plant.workspace("op")
-    tensor = {"psf_rows": 3, "signal_passes": 7}
-    for prec in ("fp32", "precomposed"):
-        def stept():
-            plant.forward(x, precision=prec, out=yb, ws=wst)
-            plant.adjoint(yb, precision=prec, out=xo, ws=wst)
+        # the same scan with the tensor PSF coupling each z-row to three rows on
+        # either side (seven signal passes per application, FP32)
+        plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"), psf_rows=3)
+        wst = plant.workspace("op")
+        tensor = {"psf_rows": 3, "signal_passes": 7}
+        for prec in ("fp32", "precomposed"):
+            def stept():
+                plant.forward(x, precision=prec, out=yb, ws=wst)
+                plant.adjoint(yb, precision=prec, out=xo, ws=wst)
 
-        for _ in range(args.warmup):
-            stept()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            stept()
-        torch.cuda.synchronize()
-        dtt = time.perf_counter() - t0
-        tensor[prec] = {"applies_per_s": round(args.steps / dtt, 2), "ms_per_step": round(1e3 * dtt / args.steps, 4)}
-    log("tensor PSF (R = 3) A^T A: %s" % tensor)
-    del plant, wst
+            for _ in range(args.warmup):
+                stept()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                stept()
+            torch.cuda.synchronize()
+            dtt = time.perf_counter() - t0
+            tensor[prec] = {"applies_per_s": round(args.steps / dtt, 2), "ms_per_step": round(1e3 * dtt / args.steps, 4)}
+        log("tensor PSF (R = 3) A^T A: %s" % tensor)
+        del plant, wst
 
-    # the same scan acquired with both drive directions: 36 x 192 z-drive
-    # lines (96 samples, padded to the x-drive lines' 192) after the x-drive ones
-    pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
-    wsd = pland.workspace("op")
-    ybd = torch.empty(pland.data_shape, dtype=torch.complex64, device="cuda")
-    dual = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale}
-    for prec in ("fp32", "mixed"):
-        def stepd():
-            pland.forward(x, precision=prec, out=ybd, ws=wsd)
-            pland.adjoint(ybd, precision=prec, out=xo, ws=wsd)
+        # the same scan acquired with both drive directions: 36 x 192 z-drive
+        # lines (96 samples, padded to the x-drive lines' 192) after the x-drive ones
+        pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
+        wsd = pland.workspace("op")
+        ybd = torch.empty(pland.data_shape, dtype=torch.complex64, device="cuda")
+        dual = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale}
+        for prec in ("fp32", "mixed"):
+            def stepd():
+                pland.forward(x, precision=prec, out=ybd, ws=wsd)
+                pland.adjoint(ybd, precision=prec, out=xo, ws=wsd)
 
-        for _ in range(args.warmup):
-            stepd()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            stepd()
-        torch.cuda.synchronize()
-        dtd = time.perf_counter() - t0
-        dual[prec] = {"applies_per_s": round(args.steps / dtd, 2), "ms_per_step": round(1e3 * dtd / args.steps, 4)}
-    log("dual drive A^T A: %s" % dual)
-    del pland, wsd, ybd
+            for _ in range(args.warmup):
+                stepd()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                stepd()
+            torch.cuda.synchronize()
+            dtd = time.perf_counter() - t0
+            dual[prec] = {"applies_per_s": round(args.steps / dtd, 2), "ms_per_step": round(1e3 * dtd / args.steps, 4)}
+        log("dual drive A^T A: %s" % dual)
+        del pland, wsd, ybd
 
     # CGLS iteration rate of the configured 50-iteration solve
     swk = plan.workspace("solve")
