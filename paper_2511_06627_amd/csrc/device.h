@@ -1,0 +1,71 @@
+// Device helpers shared by the kernel sources (proj.hip, sig.hip, sig16.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace mpi3d {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+// blockIdx -> logical block so that consecutive logical blocks share an XCD
+// (blocks are dealt to the 8 XCDs round-robin; XCD x receives
+// nblocks / 8 + (x < nblocks % 8) of them).
+__device__ __forceinline__ int xcd_logical(int bid, int nblocks)
+{
+    const int nx = 8;
+    int xcd = bid % nx, slot = bid / nx;
+    int per = nblocks / nx, rem = nblocks % nx;
+    return xcd * per + min(xcd, rem) + slot;
+}
+
+// Where a signal-kernel block and wave sit: the block covers kRowsPerBlock
+// lines (a tile) of one job, for one time split and one column group; wave
+// w is half w & 1 of pair w >> 1, which owns kRowsPerWave lines from row0.
+struct BlockPos {
+    int job, row0, split, group, half, pair;
+};
+
+__device__ __forceinline__ BlockPos locate(const SigArgs &a)
+{
+    BlockPos bp;
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int tile = lb % a.total_tiles;
+    const int sg = lb / a.total_tiles;
+    bp.group = sg % a.ngroups;
+    bp.split = sg / a.ngroups;
+    int jb = 0;
+    for (int j = 1; j < a.njobs; ++j)
+        if (tile >= a.jobs[j].tile0) jb = j;
+    bp.job = jb;
+    const int w = threadIdx.x >> 6;
+    bp.pair = w >> 1;
+    bp.half = w & 1;
+    bp.row0 = (tile - a.jobs[jb].tile0) * kRowsPerBlock + bp.pair * kRowsPerWave;
+    return bp;
+}
+
+// Swap partial time tiles within a pair: write mine, barrier, read the
+// partner's, and return lo + hi (the same operand order on both waves).  xs
+// holds two parities x kWaves pairs x 2 halves x 16 x 64 floats.
+__device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
+{
+    float *slot = xs + ((parity * kWaves + pair) * 2) * 16 * 64;
+    float *own = slot + half * 16 * 64;
+    const float *other = slot + (1 - half) * 16 * 64;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) own[j * 64 + lane] = mine[j];
+    __syncthreads();
+    f32x16 r;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const float o = other[j * 64 + lane];
+        r[j] = half == 0 ? mine[j] + o : o + mine[j];
+    }
+    return r;
+}
+
+}  // namespace
+
+}  // namespace mpi3d

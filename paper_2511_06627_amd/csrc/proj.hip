@@ -24,22 +24,11 @@
 
 #include <type_traits>
 
-#include "internal.h"
+#include "device.h"
 
 namespace mpi3d {
 
 namespace {
-
-// blockIdx -> logical block so that consecutive logical blocks share an XCD
-// (blocks are dealt to the 8 XCDs round-robin).
-__device__ __forceinline__ int xcd_logical(int bid, int nblocks)
-{
-    const int nx = 8;
-    int xcd = bid % nx, slot = bid / nx;
-    int per = nblocks / nx, rem = nblocks % nx;
-    // XCD x receives per + (x < rem) blocks
-    return xcd * per + min(xcd, rem) + slot;
-}
 
 // A ray sample's 2x2 footprint is the same in every z-slice, so a unit of
 // work may cover NS consecutive slices k0 .. k0 + NS - 1 whose values share

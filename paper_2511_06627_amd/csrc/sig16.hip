@@ -21,64 +21,15 @@
 // 16 h + 8(e/4) + 4(l/32) + e%4, and the second contraction's tables are
 // stored with that permutation.
 
-#include "internal.h"
+#include "device.h"
 
 namespace mpi3d {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-__device__ __forceinline__ int xcd_logical(int bid, int nblocks)
-{
-    const int nx = 8;
-    int xcd = bid % nx, slot = bid / nx;
-    int per = nblocks / nx, rem = nblocks % nx;
-    return xcd * per + min(xcd, rem) + slot;
-}
-
-struct BlockPos {
-    int job, row0, split, group, half, pair;
-};
-
-__device__ __forceinline__ BlockPos locate(const SigArgs &a)
-{
-    BlockPos bp;
-    const int lb = xcd_logical(blockIdx.x, gridDim.x);
-    const int tile = lb % a.total_tiles;
-    const int sg = lb / a.total_tiles;
-    bp.group = sg % a.ngroups;
-    bp.split = sg / a.ngroups;
-    int jb = 0;
-    for (int j = 1; j < a.njobs; ++j)
-        if (tile >= a.jobs[j].tile0) jb = j;
-    bp.job = jb;
-    const int w = threadIdx.x >> 6;
-    bp.pair = w >> 1;
-    bp.half = w & 1;
-    bp.row0 = (tile - a.jobs[jb].tile0) * kRowsPerBlock + bp.pair * kRowsPerWave;
-    return bp;
-}
-
 #define MFMA16(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_f16((a), (b), (c), 0, 0, 0)
-
-__device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
-{
-    float *slot = xs + ((parity * kWaves + pair) * 2) * 16 * 64;
-    float *own = slot + half * 16 * 64;
-    const float *other = slot + (1 - half) * 16 * 64;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) own[j * 64 + lane] = mine[j];
-    __syncthreads();
-    f32x16 r;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const float o = other[j * 64 + lane];
-        r[j] = half == 0 ? mine[j] + o : o + mine[j];
-    }
-    return r;
-}
 
 __device__ __forceinline__ f16x8 to_f16x8(const f32x16 &v, int base)
 {
