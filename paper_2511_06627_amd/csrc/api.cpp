@@ -66,6 +66,7 @@ OpWs carve_op(const mpi3d_plan *pl, void *ws)
     w.norm = (double *)(b + pl->ws_norm);
     w.rowscale = (float *)(b + pl->ws_rowscale);
     w.xb = (uint16_t *)(b + pl->ws_xb);
+    w.in16 = (uint16_t *)(b + pl->ws_in16);
     return w;
 }
 
@@ -112,6 +113,8 @@ static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJo
             SigJob sj{};
             sj.in = lj.in;
             sj.in_stride = lj.in_stride;
+            sj.in16 = lj.w->in16;
+            sj.in16_stride = pj->in16_cols;
             sj.part = lj.w->part + pass * pass_stride;
             sj.part_stride = part_stride;
             sj.row_scale = lj.w->rowscale;
@@ -129,6 +132,19 @@ static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJo
             sj.in_nz = pj->nz;
             out.push_back(sj);
         }
+}
+
+// Mixed signal stage input: per-line scales into w.rowscale and the scaled
+// lines as fp16 into w.in16 (forward: projections over n_u columns, zero to
+// nup; adjoint: band-scaled data over 2nb columns, zero to nbp2).
+static hipError_t row_scale16(const mpi3d_plan *pj, bool fwd, const float *in, int in_stride, const OpWs &w,
+                              hipStream_t st)
+{
+    if (fwd)
+        return launch_row_scale(pj->L, pj->nu, in_stride, in, nullptr, w.rowscale, w.in16, pj->nup, pj->in16_cols,
+                                st);
+    return launch_row_scale(pj->L, pj->nb2, in_stride, in, pj->band_scale, w.rowscale, w.in16, pj->nbp2,
+                            pj->in16_cols, st);
 }
 
 static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, hipStream_t st)
@@ -151,10 +167,8 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
         const mpi3d_plan *pj = jobs[j].pl;
         if (pj->line_key != pl->line_key) return MPI3D_EINVAL;
         if (prec == MPI3D_MIXED) {
-            // per-line power-of-two scales for the fp16 operands
-            if (fwd) TRY(launch_row_scale(pj->L, pj->nu, jobs[j].in_stride, jobs[j].in, nullptr, jobs[j].w->rowscale, st));
-            else TRY(launch_row_scale(pj->L, pj->nb2, jobs[j].in_stride, jobs[j].in, pj->band_scale,
-                                      jobs[j].w->rowscale, st));
+            // per-line power-of-two scales and the scaled fp16 operand lines
+            TRY(row_scale16(pj, fwd, jobs[j].in, jobs[j].in_stride, *jobs[j].w, st));
         }
         kj.clear();
         line_jobs(jobs[j], fwd, serve, kj);
@@ -773,6 +787,9 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
     }
     const bool mixed = precision == MPI3D_MIXED;
     hipError_t err = mixed && kernel == 0 ? launch_to_bf16(pl->nvox, x, w.xb, st) : hipSuccess;
+    // the mixed signal kernels read fp16 operand lines: prepared once, untimed
+    if (err == hipSuccess && mixed && kernel >= 2)
+        err = row_scale16(pl, kernel == 2, kernel == 2 ? w.rt : b, kernel == 2 ? pl->nup : pl->nb2, w, st);
     if (err == hipSuccess) err = hipEventRecord(e0, st);
     for (int i = 0; err == hipSuccess && i < repeats; ++i) {
         switch (kernel) {

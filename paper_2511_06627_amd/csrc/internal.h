@@ -44,6 +44,10 @@ struct SigJob {
     int rows;              // FFL lines of this job
     int tile0;             // first block-row tile of this job in the launch
     int in_stride;         // floats between consecutive input lines
+    // mixed: the input lines scaled and rounded to fp16 by the row_scale
+    // kernel (bits), zero-padded; input line il starts at in16 + il * in16_stride
+    const uint16_t *in16;
+    int in16_stride;
     long part_stride;      // floats between consecutive split (x group) partial blocks
     // Job row r is line (r / map_per) * map_nz + map_off + map_step * (r % map_per)
     // of the buffers above (identity: map_per >= rows, map_off 0, map_step 1).
@@ -163,7 +167,8 @@ struct mpi3d_plan {
     size_t gt_elems = 0;  // floats per line matrix
     rocblas_handle blas = nullptr;   // precomposed: GEMM handle
     // operator workspace layout (bytes from ws base)
-    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, op_ws_bytes;
+    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, op_ws_bytes;
+    int in16_cols;        // halves per fp16 operand line: max(nup, nbp2)
     // solver workspace layout
     size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, sw_v, solve_ws_bytes;
 };
@@ -201,8 +206,11 @@ hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_strid
                                        const float *part, const float *row_scale, double scale, float *out,
                                        hipStream_t st, RowPasses rp);
 hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st);
+// Per-line power-of-two scales of the fp16 contractions; with out16, also
+// the scaled lines rounded to fp16 ([rows][out16_stride] halves, columns
+// ncols..out16_cols-1 zero).
 hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
-                            hipStream_t st);
+                            uint16_t *out16, int out16_cols, int out16_stride, hipStream_t st);
 
 // CGLS scalar and vector steps.  `scal` holds the solve's float64 scalars.
 int scal_slots();
@@ -249,6 +257,7 @@ struct OpWs {
     double *norm;     // spare norm partials
     float *rowscale;  // [L] per-line scales of the fp16 path
     uint16_t *xb;     // bf16 copy of a volume (mixed path)
+    uint16_t *in16;   // [L][in16_cols] fp16 operand lines of the mixed signal stage
 };
 OpWs carve_op(const mpi3d_plan *pl, void *ws);
 int check_prec(const mpi3d_plan *pl, int32_t precision);

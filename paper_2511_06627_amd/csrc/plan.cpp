@@ -617,6 +617,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
         pl->ws_rowscale = put(sizeof(float) * pl->L);
         pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
+        pl->in16_cols = std::max(pl->nup, pl->nbp2);
+        pl->ws_in16 = put(mixed ? sizeof(uint16_t) * pl->L * pl->in16_cols : 0);
         pl->op_ws_bytes = align256(o);
     }
     {

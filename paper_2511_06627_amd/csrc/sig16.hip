@@ -100,20 +100,14 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
     const bool iok = il >= 0;
     constexpr int NKS = NUP / 32;         // fp16 K steps per half (16 detector samples each)
 
-    // this wave's half of the line, scaled by the line's power-of-two scale
-    // (row_scale kernel), as fp16 B operands
-    const float *rin = (const float *)job.in + (size_t)(iok ? il : 0) * job.in_stride;
-    const float rs = iok ? job.row_scale[il] : 1.f;
+    // this wave's half of the line as fp16 B operands: the line scaled by its
+    // power-of-two scale and rounded by the row_scale kernel (zero past n_u)
     f16x8 R[NKS];
     {
-        const int p0 = bp.half * (NUP / 2);
+        const f16x8 *rin = (const f16x8 *)(job.in16 + (size_t)(iok ? il : 0) * job.in16_stride +
+                                           bp.half * (NUP / 2) + 8 * h);
 #pragma unroll
-        for (int st = 0; st < NKS; ++st)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int p = p0 + 16 * st + 8 * h + e;
-                R[st][e] = (_Float16)((iok && p < a.nu) ? rin[p] * rs : 0.f);
-            }
+        for (int st = 0; st < NKS; ++st) R[st] = iok ? rin[2 * st] : f16x8(0);
     }
     f32x16 acc[GH];
 #pragma unroll
@@ -199,17 +193,15 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;
     const int pt0 = bp.half * PTH;
 
-    // the line's power-of-two scale over the band-scaled row (row_scale kernel)
-    const float *yin = (const float *)job.in + (size_t)(iok ? il : 0) * job.in_stride;
-    const float ys = iok ? job.row_scale[il] : 1.f;
+    // this wave's bins of the line as fp16 B operands: the band-scaled row
+    // times the line's power-of-two scale, rounded by the row_scale kernel
+    // (zero past 2 nb)
     f16x8 Y[NF];
+    {
+        const f16x8 *yin = (const f16x8 *)(job.in16 + (size_t)(iok ? il : 0) * job.in16_stride + colbase + 8 * h);
 #pragma unroll
-    for (int st = 0; st < NF; ++st)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int col = colbase + 16 * st + 8 * h + e;
-            Y[st][e] = (_Float16)((iok && col < a.nb2) ? yin[col] * a.band_scale[col] * ys : 0.f);
-        }
+        for (int st = 0; st < NF; ++st) Y[st] = iok ? yin[2 * st] : f16x8(0);
+    }
     f32x16 racc[PTH];
 #pragma unroll
     for (int pt = 0; pt < PTH; ++pt) racc[pt] = 0.f;

@@ -119,11 +119,15 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
 
 // Power-of-two line scales for the fp16 contractions: for each row,
 // s = 2^-e with max_c |in[row][c] * col_scale[c]| in [2^(e-1), 2^e), so the
-// scaled row's largest entry lies in [0.5, 1); 1 for an all-zero row.  One
-// wave per row.
+// scaled row's largest entry lies in [0.5, 1); 1 for an all-zero row.  With
+// out16 the row is also written as the fp16 operand the signal kernels read,
+// (in[row][c] * col_scale[c]) * s rounded to nearest, zero from column ncols
+// to out16_cols.  One wave per row.
 __global__ __launch_bounds__(kThreads) void row_scale_kernel(long rows, int ncols, int in_stride,
                                                               const float *__restrict__ in,
-                                                              const float *__restrict__ col_scale, float *out)
+                                                              const float *__restrict__ col_scale, float *out,
+                                                              uint16_t *__restrict__ out16, int out16_cols,
+                                                              int out16_stride)
 {
     const int lane = threadIdx.x & 63;
     const long row = (long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
@@ -132,16 +136,21 @@ __global__ __launch_bounds__(kThreads) void row_scale_kernel(long rows, int ncol
     float m = 0.f;
     for (int c = lane; c < ncols; c += 64) m = fmaxf(m, fabsf(col_scale ? p[c] * col_scale[c] : p[c]));
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if (lane == 0) {
-        float s = 1.f;
-        if (m > 0.f && isfinite(m)) {
-            // 2^-e brings the row maximum into [0.5, 1); capped so that rows
-            // of subnormal size get a finite scale (and a normal 1/scale)
-            int e;
-            frexpf(m, &e);
-            s = ldexpf(1.f, min(-e, 120));
-        }
-        out[row] = s;
+    float s = 1.f;
+    if (m > 0.f && isfinite(m)) {
+        // 2^-e brings the row maximum into [0.5, 1); capped so that rows
+        // of subnormal size get a finite scale (and a normal 1/scale)
+        int e;
+        frexpf(m, &e);
+        s = ldexpf(1.f, min(-e, 120));
+    }
+    if (lane == 0) out[row] = s;
+    if (!out16) return;
+    uint16_t *q = out16 + row * out16_stride;
+    for (int c = lane; c < out16_cols; c += 64) {
+        const float v = c < ncols ? (col_scale ? p[c] * col_scale[c] : p[c]) * s : 0.f;
+        const _Float16 hv = (_Float16)v;
+        q[c] = __builtin_bit_cast(uint16_t, hv);
     }
 }
 
@@ -392,11 +401,11 @@ hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_strid
 
 
 hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
-                            hipStream_t st)
+                            uint16_t *out16, int out16_cols, int out16_stride, hipStream_t st)
 {
     const long blocks = (rows + kThreads / 64 - 1) / (kThreads / 64);
     hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, rows, ncols, in_stride, in,
-                       col_scale, out);
+                       col_scale, out, out16, out16_cols, out16_stride);
     return hipGetLastError();
 }
 
