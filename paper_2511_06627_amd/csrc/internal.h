@@ -33,6 +33,10 @@ constexpr int kFwdThreads = 1024;                     // forward projection bloc
 // Rays a forward-projection thread owns: 4 with one slice per texel, 2 with
 // two (twice the accumulators and LDS operands per sample).
 constexpr int fwd_rays_per_thread(int slices) { return slices == 1 ? 4 : 2; }
+// Texels per LDS row of a staged slice: the grid row with a zero border on
+// both sides, rounded up to an odd count so that rays a row apart fall in
+// different LDS banks.
+constexpr int proj_pitch(int nx) { return (nx + 2) | 1; }
 
 // One batch segment of FFL lines sharing the same line tables.
 struct SigJob {

@@ -278,7 +278,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         auto fwd_config = [&](int slices, int texel_bytes, mpi3d::FwdConfig &fc) {
             const size_t lds = 160 * 1024;
             const int bases = pl->ny + 1;           // base rows -1 .. ny-1
-            const int max_rows = (int)(lds / ((size_t)(pl->nx + 2) * texel_bytes)) - 1;
+            const int max_rows = (int)(lds / ((size_t)mpi3d::proj_pitch(pl->nx) * texel_bytes)) - 1;
             if (max_rows < 2) return false;
             fc.slices = slices;
             fc.n_bands = (bases + max_rows - 1) / max_rows;

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, const
     const int ng = (a.nz + NS - 1) / NS;
     const long U = (long)ng * a.M;
     const long u0 = (long)lb * U / nb, u1 = (long)(lb + 1) * U / nb;
-    const int W = a.nx + 2;
+    const int W = proj_pitch(a.nx);
     const unsigned Wb = (unsigned)(W * sizeof(T));
     const int tid = threadIdx.x;
     for (long ku = u0; ku < u1;) {
@@ -550,7 +550,7 @@ static hipError_t launch_fwd(const mpi3d_plan *pl, const typename Texel<T>::V *v
     a.rt = rt;
     a.band_rows = fc.band_rows;
     a.n_bands = fc.n_bands;
-    const size_t lds = (size_t)(fc.band_rows + 1) * (pl->nx + 2) * sizeof(T);
+    const size_t lds = (size_t)(fc.band_rows + 1) * proj_pitch(pl->nx) * sizeof(T);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)proj_fwd_kernel<T>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
