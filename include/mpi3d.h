@@ -303,8 +303,11 @@ void mpi3d_state_destroy(mpi3d_state *state);
  *                                   outside the timed launches, and the bf16
  *                                   gather variant is timed)
  *   kernel 1  backprojection        reads the workspace, writes x_dev
- *   kernel 2  signal forward contraction (time signal + band DFT)
+ *   kernel 2  signal forward contraction (time signal + band DFT), reads
+ *             the workspace's projections
  *   kernel 3  signal adjoint contraction, reads b_dev
+ *             (MIXED, kernels 2 and 3: the per-line scales and fp16 operand
+ *             lines are prepared once, outside the timed launches)
  * The kernels' work does not depend on the values they read.  x_dev holds
  * n_vox floats, b_dev n_data_floats, ws_dev op_ws_bytes.
  */
