@@ -119,3 +119,94 @@ def test_momentum_gradient_with_finite_differences(problem):
     e = [np.linalg.norm(solvers.momentum_gradient(op, b, lam_fd, k, tau, nonneg=False, reg="fd") - xs)
          / np.linalg.norm(xs) for k in (200, 2000)]
     assert e[1] <= 1e-3 and e[1] < 0.2 * e[0], e
+
+
+def test_op_norm_equals_dense_spectral_norm(problem):
+    """The power-iteration norm against the dense matrix's largest singular
+    value: the normalised operator has ||A||_2 = 1 (Sec. 3.3).  A maps real
+    volumes to complex data and its norm is taken in the real inner product
+    Re(u^H v), so the matrix is [Re A; Im A] (the complex matrix's own 2-norm,
+    a maximum over complex x, is larger)."""
+    g, op, A, b, lam, xs = problem
+    assert abs(np.linalg.norm(np.concatenate([A.real, A.imag]), 2) - 1.0) <= 1e-9
+    # and the raw operator's norm is the reciprocal of the scale that normalised it
+    assert abs(operator.op_norm(g.with_scale(1.0)) * g.op_scale - 1.0) <= 1e-9
+
+
+def test_refinement_with_exact_inner_operator_is_restarted_cgls(problem):
+    """Refinement in correction form reduces to CGLS restarted every sweep when
+    the inner operator is the outer one (with and without the clamp).  The two
+    forms round differently: from the second sweep on, the restart gradient
+    A^T r0 - lam x is small next to its terms, so rounding differences of
+    relative size 1e-16 in it are amplified by CGLS (measured: 9e-12 after one
+    sweep of 4, 2e-4 after two).  So one sweep is compared at 1e-10, and
+    several sweeps at convergence against the dense minimiser."""
+    g, op, A, b, lam, xs = problem
+    for clamp in (False, True):
+        a = solvers.cgls_restarted(op, b, lam, 4, every=4, clamp=clamp)
+        r = solvers.refine(op, op, b, lam, 1, 4, clamp=clamp)
+        assert np.linalg.norm(r - a) <= 1e-10 * np.linalg.norm(a), clamp
+    x = solvers.refine(op, op, b, lam, 4, 40)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_refinement_reaches_minimiser_with_rounded_inner_operator(problem):
+    """An inner operator carrying 1e-3 relative errors still converges to the
+    exact minimiser: the outer residual is exact, so only the rate suffers."""
+    g, op, A, b, lam, xs = problem
+
+    class Rounded:
+        def __init__(self, o):
+            self.g, self.o, self.rng = o.g, o, np.random.default_rng(5)
+
+        def forward(self, x):
+            y = self.o.forward(x)
+            return y * (1 + 1e-3 * self.rng.standard_normal(y.shape))
+
+        def adjoint(self, y):
+            x = self.o.adjoint(y)
+            return x * (1 + 1e-3 * self.rng.standard_normal(x.shape))
+
+    x = solvers.refine(op, Rounded(op), b, lam, 12, 15)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+class _Dense2:
+    """A 2 x 2 real operator in the oracle's operator interface (one 1 x 2 slice)."""
+
+    class g:
+        nz, ny, nx = 1, 1, 2
+
+    A = np.array([[1.0, 0.5], [-0.25, 1.0]])
+
+    def forward(self, x):
+        return (self.A @ x.reshape(2)).astype(np.complex128).reshape(1, 1, 2)
+
+    def adjoint(self, y):
+        return np.real(self.A.T @ np.asarray(y).reshape(2)).reshape(1, 1, 2)
+
+
+def test_momentum_first_three_iterates_by_hand():
+    """eq. iters step by step on a 2 x 2 problem: x^0 = x^1 = 0, momentum
+    weights (k-1)/(k+2) = 0, 1/4, 2/5 for k = 1, 2, 3, gradient of
+    |Ay - b|^2 / 2 + lam |y|^2 / 2, then the projection onto x >= 0."""
+    op = _Dense2()
+    A = op.A
+    b = np.array([1.0, -0.5])
+    lam, tau = 0.1, 0.5
+
+    def step(y):
+        return np.maximum(y - tau * (A.T @ (A @ y - b) + lam * y), 0.0)
+
+    x1 = np.zeros(2)
+    x2 = step(x1 + 0.0 * (x1 - x1))
+    x3 = step(x2 + 0.25 * (x2 - x1))
+    x4 = step(x3 + 0.4 * (x3 - x2))
+    bc = b.astype(np.complex128).reshape(1, 1, 2)
+    for k, want in ((1, x2), (2, x3), (3, x4)):
+        got = solvers.momentum_gradient(op, bc, lam, k, tau, nonneg=True).reshape(2)
+        assert np.max(np.abs(got - want)) <= 1e-15, (k, got, want)
+    # the clamp acts here (the second unknown would go negative), so the
+    # nonnegative and unconstrained runs must differ
+    free = solvers.momentum_gradient(op, bc, lam, 3, tau, nonneg=False).reshape(2)
+    assert free.min() < 0.0 and x4.min() >= 0.0
