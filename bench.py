@@ -1,21 +1,28 @@
 """Benchmark of the compressed 3D FFL operator on one MI355X.
 
 Default run (python bench.py [--steps K] [--warmup W]):
-  workload  the realistic scan: 192 x 192 x 96 voxels, 36 FFL angles,
-            96 lines x 8192 time samples per angle, harmonics 1-31 +/- 3 bins
+  workload  the high-dynamic-range scan, the largest single-GPU workload:
+            256 x 256 x 128 voxels, 60 FFL angles, 128 lines x 16384 time
+            samples per angle, harmonics 1-47 +/- 3 bins, bright ellipsoid with
+            30 faint satellite blobs
   step      one application of A followed by A^T (mpi3d_forward then
             mpi3d_adjoint), FP32 path, inputs resident in HBM
   value     A^T A applications per second (K steps timed between two device
             synchronisations)
 Also reported: per-kernel device times from HIP events and the roofline of
 the dominant kernel (with HBM traffic from the committed counter summary while
-the kernel sources are unchanged); the mixed-precision and precomposed-line
-operators; the CGLS iteration rate; the paper's own solver; time-to-solve at
-1e-4 relative error against the FP64 minimiser (32^3 and the realistic scan,
-FP32 and mixed); the high-dynamic-range scan in both precisions against the
-oracle's stored solve; the serving stream (p50/p99) and closed-loop capacity
-at 1e-4; and the FP64 CPU oracle timed on this host (cpu_baseline leg).
+the kernel sources are unchanged), the mixed operator on the same scan, and
+its nonnegative solves in both precisions against the oracle's clusters; then
+the realistic 192 x 192 x 96 scan (FP32, mixed, precomposed-line operators;
+raster, tensor-PSF and dual-drive variants; CGLS rate; the paper's own
+solver; the configured mixed 3 x 20 schedule against x*; time-to-solve at 1e-4
+relative error against the FP64 minimiser, also on 32^3); the serving stream
+(p50/p99) and closed-loop capacity at 1e-4 against each request's
+FP64-converged reference; and the FP64 CPU oracle timed on this host
+(cpu_baseline leg: the time-domain oracle on a sample of the headline scan's
+z-slices, scaled to the whole scan).
 
+--headline-only runs only the headline scan's operator (profiling runs).
 Time-to-solve on the realistic scan needs its FP64 minimiser from the oracle
 (about a minute of host CPU); --no-tts skips it.
 One GPU only: --gpus N with N > 1 exits with a message.
@@ -71,7 +78,7 @@ def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=N
     x = phantom
     n = 0
     t0 = time.time()
-    while True:
+    while sample_seconds > 0:
         x = op.adjoint(op.forward(x))
         x /= np.linalg.norm(x)
         n += 1
@@ -79,11 +86,12 @@ def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=N
             break
     dt = time.time() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    out["cpu_baseline"] = {"value": n / dt, "unit": "A^T A applies/s", "cores": threads, "kind": "oracle",
-                           "sample": "%d applications of A then A^T (FP64 time-domain oracle, C projector with "
-                                     "OpenMP, BLAS contractions) at the full %s workload, %.1f s"
-                                     % (n, cfg.name, dt)}
-    log("oracle A^T A: %.3f /s on %d threads" % (n / dt, threads))
+    if n:
+        out["cpu_baseline"] = {"value": n / dt, "unit": "A^T A applies/s", "cores": threads, "kind": "oracle",
+                               "sample": "%d applications of A then A^T (FP64 time-domain oracle, C projector with "
+                                         "OpenMP, BLAS contractions) at the full %s workload, %.1f s"
+                                         % (n, cfg.name, dt)}
+        log("oracle A^T A: %.3f /s on %d threads" % (n / dt, threads))
 
     if small_cfg is not None:
         gs = geom(small_cfg)
@@ -114,27 +122,49 @@ def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=N
     return out
 
 
-def oracle_hdr_inputs():
-    """c_A and data of the high-dynamic-range scan from the oracle (same
-    recipe as its stored FP64 solve in tests/golden/hdr_reference.json)."""
+def hdr_cpu_leg(sample_slices=4, sample_seconds=15.0):
+    """Oracle leg of the headline scan: c_A, phantom and data (the same recipe
+    as the oracle's stored clusters in tests/golden/hdr_reference.json), and
+    the timed oracle.  The cpu_baseline sample: A then A^T of the time-domain
+    FP64 oracle (the form it defines) on `sample_slices` of the scan's 128
+    z-slices -- A acts slice by slice, so the whole scan costs 128 /
+    sample_slices times as much -- repeated for about `sample_seconds`, the
+    rate scaled to whole-scan applications per second."""
     import numpy as np
     from oracle import operator as oop
     from oracle.geometry import Geometry
     from paper_2511_06627_amd import configs
     c = configs.HDR_256
+    t0 = time.time()
     g = Geometry(nx=c.nx, ny=c.ny, nz=c.nz, n_angles=c.n_angles, n_t=c.n_t, drive_cycles=c.drive_cycles,
                  psf_width=c.psf_width, harm_lo=c.harm_lo, harm_hi=c.harm_hi, half_band=c.half_band)
     g = oop.normalised(g, iters_min=30, rtol=1e-9)
-    b, _ = oop.make_data(g, configs.make_phantom(c), c.noise, c.noise_seed)
-    # one oracle A^T A at this size, on its precomposed per-line form (the
-    # time-domain form takes minutes per application here); labelled so
-    op = oop.Operator(g, precomposed=True)
-    x = np.ones((c.nz, c.ny, c.nx))
+    phantom = configs.make_phantom(c)
+    b, _ = oop.make_data(g, phantom, c.noise, c.noise_seed)
+    log("oracle %s setup %.1fs" % (c.name, time.time() - t0))
+    gs = Geometry(**{**{k: getattr(g, k) for k in g.__dataclass_fields__}, "nz": sample_slices})
+    op = oop.Operator(gs)
+    k0 = (c.nz - sample_slices) // 2
+    x = phantom[k0:k0 + sample_slices].copy()
+    n = 0
     t0 = time.time()
-    op.adjoint(op.forward(x))
-    t_ata = time.time() - t0
-    return {"op_scale": g.op_scale, "b": b.astype(np.complex64),
-            "oracle": {"workload": c.name, "AtA_per_s_precomposed": round(1.0 / t_ata, 4)}}
+    while True:
+        x = op.adjoint(op.forward(x))
+        x /= np.linalg.norm(x)
+        n += 1
+        if n >= 2 and time.time() - t0 >= sample_seconds:
+            break
+    dt = time.time() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    value = n / dt * sample_slices / c.nz
+    cpu = {"value": value, "unit": "A^T A applies/s", "cores": threads, "kind": "oracle",
+           "sample": "%d applications of A then A^T of the FP64 time-domain oracle (C projector with OpenMP, BLAS "
+                     "contractions) on %d of the %d z-slices of the %s scan in %.1f s; A is block diagonal over "
+                     "z-slices, so the rate is scaled by %d/%d to whole-scan applications"
+                     % (n, sample_slices, c.nz, c.name, dt, sample_slices, c.nz)}
+    log("oracle A^T A (%s, %d-slice sample): %.4f whole-scan applies/s on %d threads"
+        % (c.name, sample_slices, value, threads))
+    return {"op_scale": g.op_scale, "b": b.astype(np.complex64), "phantom": phantom, "cpu_baseline": cpu}
 
 
 # ---------------------------------------------------------------------------
@@ -147,11 +177,55 @@ def signal_flops(cfg):
     return 2.0 * L * (cfg.n_u * cfg.n_t + 2 * cfg.n_bins * cfg.n_t)
 
 
+LDS_PEAK_GBS = 256 * 128 * 2.4      # 128 bytes per clock per CU, 256 CUs at 2.4 GHz (78.6 TB/s)
+
+
 def projection_bytes(cfg):
     """Per-angle-stream byte model of one projection: every angle reads the whole
-    volume once and writes its lines (fp32)."""
+    volume once and writes its lines (fp32).  The kernels stage each slice in
+    LDS once for many angles, so this is a model of a streaming design, not the
+    kernels' traffic (see projection_report)."""
     nvox = cfg.nx * cfg.ny * cfg.nz
     return 4.0 * (cfg.n_angles * nvox + cfg.n_lines * cfg.n_u)
+
+
+def projection_report(cfg, kernel, ms, measured_bytes, bf16=False):
+    """Projection / backprojection against three references:
+    * the per-angle-stream model (a design that streams the volume once per angle);
+    * compulsory HBM bytes (the volume and the lines once) and, when the
+      counter summary matches the sources, the measured HBM bytes;
+    * LDS: the bytes the kernel's gathers read from LDS, one bilinear footprint
+      of 4 texels per ray sample and slice (forward: 4 B per texel and slice in
+      fp32, 2 B in bf16) or 3 staged ray values per voxel, angle and slice
+      (backprojection, fp32, 4 B each), about n_angles * n_vox samples in all,
+      against the LDS peak of 128 B per clock per CU."""
+    nvox = cfg.nx * cfg.ny * cfg.nz
+    samples = float(cfg.n_angles) * nvox
+    if kernel == "project":
+        lds = samples * 4 * (2 if bf16 else 4)
+    else:
+        lds = samples * 3 * (2 if bf16 else 4)
+    pb = projection_bytes(cfg)
+    compulsory = (2 if bf16 and kernel == "project" else 4) * nvox + 4.0 * cfg.n_lines * cfg.n_u
+    t = ms * 1e-3
+    out = {"ms": round(ms, 4),
+           "model_stream_GBs": round(pb / t / 1e9, 1), "model_stream_frac": round(pb / t / 1e9 / HBM_PEAK_GBS, 4),
+           "compulsory_bytes": compulsory,
+           "lds_bytes": lds, "lds_GBs": round(lds / t / 1e9, 1), "lds_frac": round(lds / t / 1e9 / LDS_PEAK_GBS, 4)}
+    if measured_bytes:
+        out["hbm_bytes_measured"] = measured_bytes
+        out["hbm_GBs_measured"] = round(measured_bytes / t / 1e9, 1)
+        out["hbm_frac_measured"] = round(measured_bytes / t / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def signal_bytes(cfg, kernel):
+    """Algorithmic HBM bytes of one signal contraction: its input lines, its
+    output, the PSF table K (fp32, T x Nu) and a T-entry complex twiddle table
+    (the band DFT's values), each once.  Forward: lines 4 L Nu in, data
+    8 L nb out; adjoint the reverse."""
+    L = cfg.n_lines
+    return 4.0 * L * cfg.n_u + 8.0 * L * cfg.n_bins + 4.0 * cfg.n_t * cfg.n_u + 8.0 * cfg.n_t
 
 
 def step_times(torch, step, n=20):
@@ -180,15 +254,16 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
-    or None when the sources changed since the counters were taken."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain
+    copy's readings), or None when the sources changed since the counters were
+    taken or the summary has no such entry."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if rec.get("source_sha256") != kernel_source_hash():
+    rec = json.load(open(path)).get("workloads", {}).get(workload)
+    if not rec or rec.get("source_sha256") != kernel_source_hash():
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["hbm_bytes_per_launch"]
@@ -227,44 +302,47 @@ def time_to_solve(plan, torch, b, xstar, lam, precision="fp32"):
     return {"schedule": hit, "seconds": round(sorted(ts)[1], 5), "rel_err": errs[-1]}
 
 
-def hdr_leg(torch, inputs):
-    """The high-dynamic-range scan, FP32 (100 CGLS iterations, clamp + restart
-    every 10) and mixed (10 sweeps of 10, clamp after each): solve time, and
-    the faint blobs' recovered amplitudes against the FP64 oracle's solve."""
+def hdr_leg(torch, plan, inputs):
+    """The headline scan's nonnegative solves, FP32 (100 CGLS iterations, clamp
+    + restart every 10) and mixed (10 sweeps of 10, clamp after each): solve
+    time, and the iterate and the faint blobs' recovered amplitudes against the
+    mean of the oracle's cluster of the same schedule (the solve is chaotic
+    mid-run; tests/golden/make_hdr.py), with the exact oracle run's distance to
+    that mean beside them."""
     import numpy as np
     from paper_2511_06627_amd import configs, phantoms
-    from paper_2511_06627_amd.plan import Plan
     cfg = configs.HDR_256
     ref = json.load(open(os.path.join(ROOT, "tests", "golden", "hdr_reference.json")))
-    plan = Plan.from_config(cfg, inputs["op_scale"], precisions=("fp32", "mixed"))
     bd = torch.from_numpy(inputs["b"]).cuda()
     idx = np.array(ref["sample_index"])
-    want = np.array(ref["sample_value"])
-    amp_ref = np.array([bl["amp_oracle"] for bl in ref["blobs"]])
     amp_true = np.array([bl["amp_true"] for bl in ref["blobs"]])
     profiles = [phantoms._blob(cfg.shape, bl["centre_xyz"], bl["sigma"], 1.0) for bl in ref["blobs"]]
-    out = {"workload": "hdr_256x256x128: 60 angles, 128 lines x 16384 samples, harmonics 1-47 +/-3, "
-                       "bright ellipsoid + 30 faint blobs (1e-4..1e-2), 0.1% noise"}
+    out = {}
     schedules = {"fp32": dict(iters=cfg.iters, clamp_every=cfg.clamp_every),
                  "mixed": dict(precision="mixed", refine_sweeps=cfg.iters // cfg.clamp_every,
                                inner_iters=cfg.clamp_every, clamp_every=cfg.clamp_every)}
+    ws = plan.workspace("solve")
     for prec, kw in schedules.items():
-        plan.solve(bd, cfg.lam, report=False, **kw)
+        plan.solve(bd, cfg.lam, report=False, ws=ws, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, rep = plan.solve(bd, cfg.lam, **kw)
+        x, rep = plan.solve(bd, cfg.lam, ws=ws, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         xn = x.cpu().numpy().astype(np.float64)
         amp = np.array([float(np.vdot(xn, gb) / np.vdot(gb, gb)) for gb in profiles])
+        cl = ref["cluster"][prec]
+        mean = np.array(cl["sample_mean"])
+        amean = np.array(cl["amp_mean"])
         out[prec] = {"schedule": kw, "seconds": round(dt, 4), "status": rep.status,
-                     "samples_rel_l2_vs_oracle": float(np.linalg.norm(xn.ravel()[idx] - want) / np.linalg.norm(want)),
-                     "faint_amp_max_rel_err_vs_oracle": float(np.max(np.abs(amp - amp_ref) / np.abs(amp_ref))),
-                     "faint_amp_median_rel_err_vs_oracle": float(np.median(np.abs(amp - amp_ref) / np.abs(amp_ref))),
+                     "samples_to_cluster_mean": float(np.linalg.norm(xn.ravel()[idx] - mean) / np.linalg.norm(mean)),
+                     "cluster_radius": cl["sample_radius"],
+                     "exact_oracle_to_cluster_mean": cl["exact_sample_to_mean"],
+                     "faint_amp_max_rel_to_cluster": float(np.max(np.abs(amp - amean) / np.abs(amean))),
+                     "faint_amp_cluster_radius": cl["amp_radius_rel"],
                      "faint_amp_recovered_over_true_median": float(np.median(amp / amp_true))}
         log("hdr %s: %s" % (prec, out[prec]))
-    out["oracle_envelope"] = ref["envelope"]
-    out["oracle_timing"] = inputs["oracle"]
+    del ws
     return out
 
 
@@ -421,6 +499,326 @@ def serve_leg(torch, n_requests=None, stream=True):
     return out
 
 
+def realistic_leg(torch, args, cfg, small, cpu, inputs):
+    """The realistic 192 x 192 x 96 scan: FP32 and mixed operators, the
+    precomposed-line operator, the raster / tensor-PSF / dual-drive variants,
+    the CGLS rate, the paper's own solver, the configured mixed 3 x 20 solve
+    (against x* and against 60 FP32 iterations), and time-to-solve at 1e-4."""
+    import numpy as np
+    from paper_2511_06627_amd import configs
+    from paper_2511_06627_amd.plan import Plan
+    plan, x, b = inputs(cfg, cpu)
+    out = operator_leg(torch, plan, cfg, x, b, args.warmup, args.steps)
+    out["applies_per_s"] = round(1.0 / out["seconds_per_step"], 2)
+    yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
+    xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    if args.realistic_only:
+        return out
+
+    # the precomposed-line operator (same map, signal stage as two float32
+    # GEMMs with G = F^T K): A^T A rate and the GEMM times
+    planp = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"))
+    wsp = planp.workspace("op")
+
+    def stepp():
+        planp.forward(x, precision="precomposed", out=yb, ws=wsp)
+        planp.adjoint(yb, precision="precomposed", out=xo, ws=wsp)
+
+    sec, _ = timed_rate(torch, stepp, args.warmup, args.steps)
+    ktp = {k: planp.time_kernel(k, repeats=10, precision="precomposed", x=x, b=b, ws=wsp)
+           for k in ("signal_fwd", "signal_adj")}
+    out["precomposed"] = {"applies_per_s": round(1.0 / sec, 2), "ms_per_step": round(1e3 * sec, 4),
+                          "gemm_flops": 2.0 * cfg.n_lines * cfg.n_u * 2 * cfg.n_bins,
+                          "gemm_fwd_ms": round(ktp["signal_fwd"], 4), "gemm_adj_ms": round(ktp["signal_adj"], 4)}
+    log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * sec, ktp))
+    del planp, wsp
+
+    def rate_of(p, prec, data_shape=None):
+        yy = yb if data_shape is None else torch.empty(data_shape, dtype=torch.complex64, device="cuda")
+        ws = p.workspace("op")
+
+        def st():
+            p.forward(x, precision=prec, out=yy, ws=ws)
+            p.adjoint(yy, precision=prec, out=xo, ws=ws)
+
+        sec, _ = timed_rate(torch, st, args.warmup, args.steps)
+        return {"applies_per_s": round(1.0 / sec, 2), "ms_per_step": round(1e3 * sec, 4)}
+
+    if not args.no_variants:
+        # the same scan under a zig-zag raster (two PSF tables, per-line sweep
+        # direction): drive over a sixth of the fast axis, the focus field carrying
+        # the line across two thirds of it
+        ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
+        planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
+                     cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
+        out["raster"] = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale,
+                         "fp32": rate_of(planr, "fp32"), "mixed": rate_of(planr, "mixed")}
+        log("raster A^T A: %s" % out["raster"])
+        del planr
+        # the tensor PSF coupling each z-row to three rows on either side
+        plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "mixed", "precomposed"), psf_rows=3)
+        out["tensor_psf"] = {"psf_rows": 3, "fp32": rate_of(plant, "fp32"), "mixed": rate_of(plant, "mixed"),
+                             "precomposed": rate_of(plant, "precomposed")}
+        log("tensor PSF (R = 3) A^T A: %s" % out["tensor_psf"])
+        del plant
+        # both drive directions: 36 x 192 z-drive lines after the x-drive ones
+        pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
+        out["dual_drive"] = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale,
+                             "fp32": rate_of(pland, "fp32", pland.data_shape),
+                             "mixed": rate_of(pland, "mixed", pland.data_shape)}
+        log("dual drive A^T A: %s" % out["dual_drive"])
+        del pland
+
+    # CGLS iteration rate of the configured 50-iteration solve
+    swk = plan.workspace("solve")
+    plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = plan.solve(b, cfg.lam, iters=cfg.iters, ws=swk)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    out["cgls"] = {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
+                   "status": rep.status}
+    log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
+
+    # the paper's own solver (eq. iters): momentum gradient, finite-difference
+    # T, projection onto x >= 0 every iteration, 150 iterations; tau from
+    # power iteration on the device
+    plan.solve(b, cfg.lam, iters=2, solver="momentum", reg="fd", clamp_every=1, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, repm_p = plan.solve(b, cfg.lam, iters=150, solver="momentum", reg="fd", clamp_every=1, ws=swk)
+    torch.cuda.synchronize()
+    out["paper_solver"] = {"iters": 150, "reg": "finite differences", "lambda": cfg.lam,
+                           "seconds_incl_tau": round(time.perf_counter() - t0, 4), "status": repm_p.status}
+
+    # the configured mixed schedule (3 sweeps x 20 inner): against x* (when the
+    # oracle leg ran) and against 60 FP32 iterations
+    m2 = configs.MIXED_192
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xm, repm = plan.solve(b, m2.lam, precision="mixed", refine_sweeps=m2.refine_sweeps, inner_iters=m2.inner_iters,
+                          ws=swk)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    x60, _ = plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t_fp32_60 = time.perf_counter() - t0
+    rec = {"seconds": round(t_mixed, 4), "fp32_60_seconds": round(t_fp32_60, 4), "status": repm.status,
+           "rel_l2_vs_fp32_60": float(torch.linalg.vector_norm(xm - x60) / torch.linalg.vector_norm(x60))}
+    if cpu is not None and "xstar" in cpu:
+        xs = cpu["xstar"]
+        xn = np.linalg.norm(xs)
+        rec["rel_l2_vs_xstar"] = float(np.linalg.norm(xm.cpu().numpy() - xs) / xn)
+        rec["fp32_60_rel_l2_vs_xstar"] = float(np.linalg.norm(x60.cpu().numpy() - xs) / xn)
+    out["mixed"]["solve_3x20"] = rec
+    log("mixed 3x20 solve: %s" % rec)
+    del swk
+
+    tts = {}
+    if cpu is not None and not args.skip_small and "small" in cpu:
+        sm = cpu["small"]
+        psmall = Plan.from_config(small, sm["op_scale"], precisions=("fp32", "mixed"))
+        tts["parity_32cube"] = {p: time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, p)
+                                for p in ("fp32", "mixed")}
+    if cpu is not None and "xstar" in cpu:
+        tts[cfg.name] = {p: time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, p)
+                         for p in ("fp32", "mixed")}
+    out["time_to_solve"] = tts
+    if cpu is not None:
+        out["oracle_small"] = cpu.get("oracle_small")
+    return out
+
+
+def timed_rate(torch, step, warmup, steps):
+    """Wall time per step of `steps` steps after `warmup`, bracketed by device
+    synchronisations; returns (seconds per step, total seconds)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt / steps, dt
+
+
+def operator_leg(torch, plan, cfg, x, b, warmup, steps, with_mixed=True):
+    """A then A^T on one scan: FP32 rate (the step of the headline), per-kernel
+    device times, the dominant kernel's roofline, and the same for the mixed
+    operator."""
+    yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
+    xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    ws = plan.workspace("op")
+
+    def step():
+        plan.forward(x, out=yb, ws=ws)
+        plan.adjoint(yb, out=xo, ws=ws)
+
+    sec, dt = timed_rate(torch, step, warmup, steps)
+    log("%s A^T A: %.3f ms/step" % (cfg.name, 1e3 * sec))
+    out = {"seconds_per_step": sec, "total_s": dt, "step_ms": step_times(torch, step)}
+    kt = {k: plan.time_kernel(k, repeats=10, x=x, b=b, ws=ws)
+          for k in ("project", "signal_fwd", "signal_adj", "backproject")}
+    log("%s kernels (ms): %s" % (cfg.name, ", ".join("%s %.3f" % kv for kv in kt.items())))
+    fl = signal_flops(cfg)
+    dom = max(("signal_fwd", "signal_adj"), key=lambda k: kt[k])
+    achieved = fl / (kt[dom] * 1e-3) / 1e12
+    out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                       "traffic": measured_traffic(cfg.name, dom), "flops_per_launch": fl,
+                       "algorithmic_bytes_per_launch": signal_bytes(cfg, dom)}
+    kernels = {}
+    for k in ("signal_fwd", "signal_adj"):
+        a = fl / (kt[k] * 1e-3) / 1e12
+        kernels[k] = {"ms": round(kt[k], 4), "tflops": round(a, 2), "mfma_frac": round(a / FP32_PEAK_TFLOPS, 4),
+                      "hbm_bytes_measured": measured_traffic(cfg.name, k),
+                      "hbm_bytes_algorithmic": signal_bytes(cfg, k)}
+    for k in ("project", "backproject"):
+        kernels[k] = projection_report(cfg, k, kt[k], measured_traffic(cfg.name, k))
+    out["kernels"] = kernels
+    if not with_mixed:
+        return out
+
+    def step16():
+        plan.forward(x, precision="mixed", out=yb, ws=ws)
+        plan.adjoint(yb, precision="mixed", out=xo, ws=ws)
+
+    sec16, _ = timed_rate(torch, step16, warmup, steps)
+    kt16 = {k: plan.time_kernel(k, repeats=10, precision="mixed", x=x, b=b, ws=ws)
+            for k in ("project", "signal_fwd", "signal_adj", "backproject")}
+    mixed = {"applies_per_s": round(1.0 / sec16, 2), "ms_per_step": round(1e3 * sec16, 4),
+             "step_ms": step_times(torch, step16)}
+    for k, v in kt16.items():
+        if k in ("project", "backproject"):
+            mixed[k + "_bf16"] = projection_report(cfg, k, v, measured_traffic(cfg.name, k + "_mixed"), bf16=True)
+            continue
+        a16 = fl / (v * 1e-3) / 1e12
+        mixed[k] = {"ms": round(v, 4), "tflops": round(a16, 1), "mfma_frac_fp16": round(a16 / FP16_PEAK_TFLOPS, 4),
+                    "hbm_bytes_measured": measured_traffic(cfg.name, k + "_mixed")}
+    log("%s mixed A^T A: %.3f ms/step; kernels %s" % (cfg.name, 1e3 * sec16, kt16))
+    out["mixed"] = mixed
+    del ws
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Profile summaries: rocprofv3 output (under gpurun_out/) -> profiles/
+# ---------------------------------------------------------------------------
+KERNEL_KEYS = (("sig_fwd_f32", "signal_fwd"), ("sig_adj_f32", "signal_adj"), ("sig_fwd_f16", "signal_fwd_mixed"),
+               ("sig_adj_f16", "signal_adj_mixed"), ("proj_fwd_kernel<unsigned int>", "project_mixed"),
+               ("proj_fwd_kernel", "project"), ("proj_adj_bf16", "backproject_mixed"),
+               ("proj_adj_kernel", "backproject"))
+
+
+def kernel_key(name):
+    for frag, key in KERNEL_KEYS:
+        if frag in name:
+            return key
+    return None
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(path) as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit("no %s under %s" % (suffix, directory))
+    return rows
+
+
+def summarize_kernel_stats(directory, workload, command):
+    """profiles/kernel_stats_<workload>.md from a rocprofv3 --kernel-trace --stats run."""
+    rows = _csv_rows(directory, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["# Kernel statistics: %s" % workload, "", "Command (from the repository root, on one MI355X):", "",
+           "    " + command, "", "| kernel | calls | average (us) | min (us) | max (us) | share |",
+           "|---|---|---|---|---|---|"]
+    for r in rows[:25]:
+        name = r["Name"] if len(r["Name"]) < 110 else r["Name"][:107] + "..."
+        out.append("| `%s` | %s | %.1f | %.1f | %.1f | %.1f%% |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    path = os.path.join(ROOT, "profiles", "kernel_stats_%s.md" % workload)
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("wrote", path)
+
+
+def summarize_hbm(fetch_dir, write_dir, workload, commands, copy_mib=512):
+    """profiles/hbm_traffic.json (entry `workload`) and
+    profiles/hbm_traffic_<workload>.md from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE; KiB per dispatch).  Both are scaled by what they read for
+    the plain device copy of copy_mib MiB that bench.py runs first (read and
+    written once), so the result is HBM bytes per launch."""
+    import numpy as np
+
+    def per_kernel(directory, counter):
+        rows = [r for r in _csv_rows(directory, "counter_collection.csv") if r["Counter_Name"].startswith(counter)]
+        by = {}
+        for r in rows:
+            by.setdefault((r["Dispatch_Id"], r["Kernel_Name"]), 0.0)
+            by[(r["Dispatch_Id"], r["Kernel_Name"])] += float(r["Counter_Value"])
+        return by
+
+    f = per_kernel(fetch_dir, "FETCH_SIZE")
+    w = per_kernel(write_dir, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    cf = max(v for (d, n), v in f.items() if "copy" in n.lower())
+    cw = max(v for (d, n), v in w.items() if "copy" in n.lower())
+    fs, wsc = copy_kib / cf, copy_kib / cw
+    kern = {}
+    for src, key in ((f, "fetch"), (w, "write")):
+        for (d, n), v in src.items():
+            k = kernel_key(n)
+            if k is None:
+                continue
+            kern.setdefault(k, {"kernel": n, "fetch": [], "write": []})[key].append(v)
+    out = {}
+    for k, v in kern.items():
+        if not v["fetch"] or not v["write"]:
+            continue
+        fk, wk = float(np.mean(v["fetch"])), float(np.mean(v["write"]))
+        rb, wb = int(round(fk * 1024 * fs)), int(round(wk * 1024 * wsc))
+        out[k] = {"kernel": v["kernel"], "dispatches": len(v["fetch"]), "fetch_kib": round(fk, 1),
+                  "write_kib": round(wk, 1), "hbm_read_bytes": rb, "hbm_write_bytes": wb,
+                  "hbm_bytes_per_launch": rb + wb}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec.setdefault("workloads", {})
+    rec.pop("kernels", None)
+    rec["workloads"][workload] = {"commands": commands, "source_sha256": kernel_source_hash(),
+                                  "calibration": {"copy_kib": copy_kib, "fetch_kib": cf, "write_kib": cw,
+                                                  "fetch_scale": fs, "write_scale": wsc},
+                                  "kernels": out}
+    for k in ("workload", "commands", "calibration", "source_sha256"):
+        rec.pop(k, None)
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    lines = ["# HBM traffic per launch: %s" % workload, "",
+             "Two rocprofv3 counter runs (from the repository root, on one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Calibration: a plain device copy of %d MiB read FETCH_SIZE %.0f KiB and WRITE_SIZE %.0f KiB, so "
+              "fetch counts are scaled by %.4f and write counts by %.4f." % (copy_mib, cf, cw, fs, wsc), "",
+              "| kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM read (MB) | HBM write (MB) | total (MB) |",
+              "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(out.items()):
+        lines.append("| %s (`%s`) | %d | %.1f | %.1f | %.2f | %.2f | %.2f |" % (
+            k, v["kernel"][:80], v["dispatches"], v["fetch_kib"], v["write_kib"], v["hbm_read_bytes"] / 1e6,
+            v["hbm_write_bytes"] / 1e6, v["hbm_bytes_per_launch"] / 1e6))
+    md = os.path.join(ROOT, "profiles", "hbm_traffic_%s.md" % workload)
+    with open(md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", path, md)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -430,31 +828,50 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=512,
                     help="size of a plain device copy run once, the reference for HBM byte counters")
-    ap.add_argument("--skip-small", action="store_true",
-                    help="skip the 32^3 time-to-solve (keeps a profile to the realistic scan)")
+    ap.add_argument("--skip-small", action="store_true", help="skip the 32^3 time-to-solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream and closed-loop capacity")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests in the serving stream (default 64)")
-    ap.add_argument("--no-hdr", action="store_true", help="skip the high-dynamic-range scan")
+    ap.add_argument("--no-hdr-solve", action="store_true", help="skip the headline scan's nonnegative solves")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the raster, tensor-PSF and dual-drive legs (their kernels run at other sizes)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline scan's A then A^T (FP32 and mixed): for profiling runs")
+    ap.add_argument("--realistic-only", action="store_true",
+                    help="only the realistic scan's operator legs (profiling runs of its kernels)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="no oracle leg (for profiling runs): c_A estimated by the plan, data made on the device, "
-                         "no cpu_baseline and no time-to-solve")
+                         "no cpu_baseline, no time-to-solve and no solve comparisons")
+    ap.add_argument("--summarize-kernel-stats", metavar="DIR",
+                    help="write profiles/kernel_stats_<workload>.md from a rocprofv3 --stats output folder")
+    ap.add_argument("--summarize-hbm", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/hbm_traffic* from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output folders")
+    ap.add_argument("--workload", default="hdr_256x256x128", help="workload name for --summarize-*")
+    ap.add_argument("--command", action="append", default=[], help="profiling command(s) for --summarize-*")
     args = ap.parse_args()
+    if args.summarize_kernel_stats:
+        summarize_kernel_stats(args.summarize_kernel_stats, args.workload, " && ".join(args.command))
+        return
+    if args.summarize_hbm:
+        summarize_hbm(args.summarize_hbm[0], args.summarize_hbm[1], args.workload, args.command)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the operator is measured on one MI355X "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2511_06627_amd import configs
-    cfg = configs.REALISTIC_192
+    head = configs.HDR_256
+    real = configs.REALISTIC_192
     small = configs.PARITY_32
-    cpu = None
+    do_head = not args.realistic_only
+    do_extras = not args.headline_only
+    cpu_head = cpu_real = None
     if not args.no_cpu:
-        cpu = cpu_baseline_leg(cfg, want_minimiser=not args.no_tts, sample_seconds=args.cpu_seconds,
-                               small_cfg=None if args.skip_small else small)
-        if not args.no_hdr:
-            cpu["hdr"] = oracle_hdr_inputs()
+        if do_head:
+            cpu_head = hdr_cpu_leg(sample_seconds=args.cpu_seconds)
+        if do_extras:
+            cpu_real = cpu_baseline_leg(real, want_minimiser=not args.no_tts, sample_seconds=0.0,
+                                        small_cfg=None if args.skip_small else small)
 
     import numpy as np
     import torch
@@ -469,240 +886,48 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if cpu is not None:
-        plan = Plan.from_config(cfg, cpu["op_scale"], precisions=("fp32", "mixed"))
-        x = torch.from_numpy(cpu["phantom"]).float().cuda()
-        b = torch.from_numpy(cpu["b"]).cuda()
-    else:
+
+    def inputs(cfg, cpu):
+        if cpu is not None:
+            plan = Plan.from_config(cfg, cpu["op_scale"], precisions=("fp32", "mixed"))
+            return plan, torch.from_numpy(cpu["phantom"]).float().cuda(), torch.from_numpy(cpu["b"]).cuda()
         plan = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"))
         phantom = configs.make_phantom(cfg)
-        x = torch.from_numpy(phantom).float().cuda()
-        b = torch.from_numpy(device_data(torch, plan, phantom, cfg.noise, cfg.noise_seed)).cuda()
-    yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
-    xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
-    ws = plan.workspace("op")
+        return (plan, torch.from_numpy(phantom).float().cuda(),
+                torch.from_numpy(device_data(torch, plan, phantom, cfg.noise, cfg.noise_seed)).cuda())
 
-    def step():
-        plan.forward(x, out=yb, ws=ws)
-        plan.adjoint(yb, out=xo, ws=ws)
+    # ---- headline: the 256 x 256 x 128 scan, FP32 A then A^T ----------------
+    head_out = hdr = None
+    if do_head:
+        plan_h, x_h, b_h = inputs(head, cpu_head)
+        head_out = operator_leg(torch, plan_h, head, x_h, b_h, args.warmup, args.steps)
+        if cpu_head is not None and do_extras and not args.no_hdr_solve:
+            hdr = hdr_leg(torch, plan_h, cpu_head)
+        del plan_h, x_h, b_h
+        torch.cuda.empty_cache()
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = 1e3 * dt / args.steps
-    log("A^T A: %.3f ms/step" % ms_step)
-    st32 = step_times(torch, step)
-
-    # per-kernel device times (HIP events inside the library, on this stream)
-    kt = {k: plan.time_kernel(k, repeats=10, x=x, b=b, ws=ws)
-          for k in ("project", "signal_fwd", "signal_adj", "backproject")}
-    log("kernels (ms): " + ", ".join("%s %.3f" % kv for kv in kt.items()))
-    fl = signal_flops(cfg)
-    dom = max(("signal_fwd", "signal_adj"), key=lambda k: kt[k])
-    achieved = fl / (kt[dom] * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dom), "flops_per_launch": fl}
-    kernels = {}
-    for k in ("signal_fwd", "signal_adj"):
-        a = fl / (kt[k] * 1e-3) / 1e12
-        kernels[k] = {"ms": round(kt[k], 4), "tflops": round(a, 2), "mfma_frac": round(a / FP32_PEAK_TFLOPS, 4)}
-    pb = projection_bytes(cfg)
-    for k in ("project", "backproject"):
-        gbs = pb / (kt[k] * 1e-3) / 1e9
-        kernels[k] = {"ms": round(kt[k], 4), "per_angle_stream_GBs": round(gbs, 1),
-                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-
-    # mixed operator: A^T A rate and fp16 kernel times
-    def step16():
-        plan.forward(x, precision="mixed", out=yb, ws=ws)
-        plan.adjoint(yb, precision="mixed", out=xo, ws=ws)
-
-    for _ in range(args.warmup):
-        step16()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step16()
-    torch.cuda.synchronize()
-    dt16 = time.perf_counter() - t0
-    kt16 = {k: plan.time_kernel(k, repeats=10, precision="mixed", x=x, b=b, ws=ws)
-            for k in ("project", "signal_fwd", "signal_adj")}
-    mixed = {"applies_per_s": round(args.steps / dt16, 2), "ms_per_step": round(1e3 * dt16 / args.steps, 4),
-             "step_ms": step_times(torch, step16)}
-    for k, v in kt16.items():
-        if k == "project":
-            mixed["project_bf16"] = {"ms": round(v, 4), "per_angle_stream_GBs": round(pb / (v * 1e-3) / 1e9, 1)}
-            continue
-        a16 = fl / (v * 1e-3) / 1e12
-        mixed[k] = {"ms": round(v, 4), "tflops": round(a16, 1), "mfma_frac_fp16": round(a16 / FP16_PEAK_TFLOPS, 4)}
-    log("mixed A^T A: %.3f ms/step; kernels %s" % (1e3 * dt16 / args.steps, kt16))
-
-    # the precomposed-line operator (same map, signal stage as two float32
-    # GEMMs with G = F^T K): A^T A rate and the GEMM times
-    planp = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"))
-    wsp = planp.workspace("op")
-
-    def stepp():
-        planp.forward(x, precision="precomposed", out=yb, ws=wsp)
-        planp.adjoint(yb, precision="precomposed", out=xo, ws=wsp)
-
-    for _ in range(args.warmup):
-        stepp()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stepp()
-    torch.cuda.synchronize()
-    dtp = time.perf_counter() - t0
-    gemm_flops = 2.0 * cfg.n_lines * cfg.n_u * 2 * cfg.n_bins
-    ktp = {k: planp.time_kernel(k, repeats=10, precision="precomposed", x=x, b=b, ws=wsp)
-           for k in ("signal_fwd", "signal_adj")}
-    precomposed = {"applies_per_s": round(args.steps / dtp, 2), "ms_per_step": round(1e3 * dtp / args.steps, 4),
-                   "gemm_flops": gemm_flops,
-                   "gemm_fwd_ms": round(ktp["signal_fwd"], 4), "gemm_adj_ms": round(ktp["signal_adj"], 4)}
-    log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * dtp / args.steps, ktp))
-    del planp, wsp
-
-    raster = tensor = dual = None
-    if not args.no_variants:
-        # the same scan under a zig-zag raster (two PSF tables, per-line sweep
-        # direction): drive over a sixth of the fast axis, the focus field carrying
-        # the line across two thirds of it
-        ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
-        planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
-                     cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
-        wsr = planr.workspace("op")
-        raster = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale}
-        for prec in ("fp32", "mixed"):
-            def stepr():
-                planr.forward(x, precision=prec, out=yb, ws=wsr)
-                planr.adjoint(yb, precision=prec, out=xo, ws=wsr)
-
-            for _ in range(args.warmup):
-                stepr()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                stepr()
-            torch.cuda.synchronize()
-            dtr = time.perf_counter() - t0
-            raster[prec] = {"applies_per_s": round(args.steps / dtr, 2), "ms_per_step": round(1e3 * dtr / args.steps, 4)}
-        log("raster A^T A: %s" % raster)
-        del planr, wsr
-
-        # the same scan with the tensor PSF coupling each z-row to three rows on
-        # either side (seven signal passes per application, FP32)
-        plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"), psf_rows=3)
-        wst = plant.workspace("op")
-        tensor = {"psf_rows": 3, "signal_passes": 7}
-        for prec in ("fp32", "precomposed"):
-            def stept():
-                plant.forward(x, precision=prec, out=yb, ws=wst)
-                plant.adjoint(yb, precision=prec, out=xo, ws=wst)
-
-            for _ in range(args.warmup):
-                stept()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                stept()
-            torch.cuda.synchronize()
-            dtt = time.perf_counter() - t0
-            tensor[prec] = {"applies_per_s": round(args.steps / dtt, 2), "ms_per_step": round(1e3 * dtt / args.steps, 4)}
-        log("tensor PSF (R = 3) A^T A: %s" % tensor)
-        del plant, wst
-
-        # the same scan acquired with both drive directions: 36 x 192 z-drive
-        # lines (96 samples, padded to the x-drive lines' 192) after the x-drive ones
-        pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
-        wsd = pland.workspace("op")
-        ybd = torch.empty(pland.data_shape, dtype=torch.complex64, device="cuda")
-        dual = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale}
-        for prec in ("fp32", "mixed"):
-            def stepd():
-                pland.forward(x, precision=prec, out=ybd, ws=wsd)
-                pland.adjoint(ybd, precision=prec, out=xo, ws=wsd)
-
-            for _ in range(args.warmup):
-                stepd()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                stepd()
-            torch.cuda.synchronize()
-            dtd = time.perf_counter() - t0
-            dual[prec] = {"applies_per_s": round(args.steps / dtd, 2), "ms_per_step": round(1e3 * dtd / args.steps, 4)}
-        log("dual drive A^T A: %s" % dual)
-        del pland, wsd, ybd
-
-    # CGLS iteration rate of the configured 50-iteration solve
-    swk = plan.workspace("solve")
-    plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xs, rep = plan.solve(b, cfg.lam, iters=cfg.iters, ws=swk)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
-    log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
-
-    # the paper's own solver (eq. iters): momentum gradient, finite-difference
-    # T, projection onto x >= 0 every iteration, 150 iterations as in its
-    # reconstructions; tau from power iteration on the device
-    plan.solve(b, cfg.lam, iters=2, solver="momentum", reg="fd", clamp_every=1, ws=swk, report=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, repm_p = plan.solve(b, cfg.lam, iters=150, solver="momentum", reg="fd", clamp_every=1, ws=swk)
-    torch.cuda.synchronize()
-    t_paper = time.perf_counter() - t0
-    paper_solver = {"iters": 150, "reg": "finite differences", "lambda": cfg.lam, "seconds_incl_tau": round(t_paper, 4),
-                    "status": repm_p.status}
-    log("paper solver (momentum, FD, 150 its): %.3f s" % t_paper)
-
-    # mixed refinement solve (3 sweeps x 20 inner) against the 60-iteration FP32 solve
-    m2 = configs.MIXED_192
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xm, repm = plan.solve(b, m2.lam, precision="mixed", refine_sweeps=m2.refine_sweeps, inner_iters=m2.inner_iters,
-                          ws=swk)
-    torch.cuda.synchronize()
-    t_mixed = time.perf_counter() - t0
-    x60, _ = plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk, report=False)
-    torch.cuda.synchronize()
-    t_fp32_60 = time.perf_counter() - t0
-    dm = float(torch.linalg.vector_norm(xm - x60) / torch.linalg.vector_norm(x60))
-    mixed["solve_3x20"] = {"seconds": round(t_mixed, 4), "fp32_60_seconds": round(t_fp32_60, 4),
-                           "rel_l2_vs_fp32_60": dm, "status": repm.status}
-    log("mixed 3x20 solve %.4f s (fp32 60 its %.4f s), rel diff vs fp32 %.2e" % (t_mixed, t_fp32_60, dm))
-
-    # time-to-solve at 1e-4 relative error against the FP64 minimiser
-    tts = {}
-    if cpu is not None and not args.skip_small:
-        sm = cpu["small"]
-        psmall = Plan.from_config(small, sm["op_scale"], precisions=("fp32", "mixed"))
-        tts["parity_32cube"] = {p: time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, p)
-                                for p in ("fp32", "mixed")}
-    if cpu is not None and not args.no_tts:
-        tts[cfg.name] = {p: time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, p)
-                         for p in ("fp32", "mixed")}
-
-    hdr = None
-    if cpu is not None and not args.no_hdr:
-        hdr = hdr_leg(torch, cpu["hdr"])
+    # ---- the realistic 192 x 192 x 96 scan -----------------------------------
+    realistic = None
+    if do_extras:
+        realistic = realistic_leg(torch, args, real, small, cpu_real, inputs)
 
     serve = None
-    if not args.no_serve:
+    if do_extras and not args.no_serve and not args.realistic_only:
         serve = serve_leg(torch, args.serve_requests or None)
 
-    value = args.steps / dt
+    if do_head:
+        value = 1.0 / head_out["seconds_per_step"]
+        workload = ("hdr_256x256x128: 60 angles, 128 lines x 16384 samples per angle, harmonics 1-47 +/-3 bins, "
+                    "bright ellipsoid + 30 faint blobs (1e-4..1e-2), 0.1% noise")
+        ms_step = 1e3 * head_out["seconds_per_step"]
+        roofline = head_out["roofline"]
+        cpu_b = cpu_head["cpu_baseline"] if cpu_head is not None else None
+    else:
+        value = 1.0 / realistic["seconds_per_step"]
+        workload = "realistic_192x192x96 (headline scan skipped)"
+        ms_step = 1e3 * realistic["seconds_per_step"]
+        roofline = realistic["roofline"]
+        cpu_b = None
     line = {
         "metric": "A^T A applies/s + time-to-solve at 1e-4 rel err vs FP64; p50/p99 latency",
         "value": round(value, 3),
@@ -716,26 +941,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "realistic_192x192x96: 36 angles, 96 lines x 8192 samples per angle, "
-                               "harmonics 1-31 +/-3 bins, 40 blobs + ellipsoid phantom, 0.5% noise",
-                   "step": "A then A^T, FP32 path", "global_batch": 1, "parallelism": "single GPU"},
-        "step_ms": st32,
+        "config": {"workload": workload, "step": "A then A^T, FP32 path", "global_batch": 1,
+                   "parallelism": "single GPU"},
+        "step_ms": head_out["step_ms"] if head_out else None,
         "roofline": roofline,
-        "cpu_baseline": cpu["cpu_baseline"] if cpu is not None else None,
-        "kernels": kernels,
-        "cgls": {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
-                 "status": rep.status},
-        "time_to_solve": tts,
-        "paper_solver": paper_solver,
-        "mixed": mixed,
-        "precomposed": precomposed,
-        "raster": raster,
-        "tensor_psf": tensor,
-        "dual_drive": dual,
+        "cpu_baseline": cpu_b,
+        "kernels": head_out["kernels"] if head_out else None,
+        "mixed": head_out["mixed"] if head_out else None,
+        "hdr_solve": hdr,
+        "realistic": realistic,
         "serving": serve,
-        "hdr": hdr,
-        "oracle_small": cpu.get("oracle_small") if cpu is not None else None,
-        "gpu_over_cpu": round(value / cpu["cpu_baseline"]["value"], 1) if cpu is not None else None,
+        "gpu_over_cpu": round(value / cpu_b["value"], 1) if cpu_b else None,
     }
     print(json.dumps(line), flush=True)
 

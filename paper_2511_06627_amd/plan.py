@@ -109,6 +109,7 @@ class Plan:
             if self._ws is None:
                 self._ws = self.workspace("op")
             ws = self._ws
+        self._check_ws(ws, "op")
         return ws
 
     def _check_vol(self, x):
@@ -120,6 +121,19 @@ class Plan:
                 b.numel() * 2 != self.info.n_data_floats:
             raise ValueError("data must be a contiguous complex64 tensor of %s on %s" % (self.data_shape, self.device))
 
+    def _check_f32(self, t, shape, what):
+        n = int(np.prod(shape))
+        if t.dtype != torch.float32 or t.device != self.device or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("%s must be a contiguous float32 tensor of %s on %s" % (what, shape, self.device))
+
+    def _check_ws(self, ws, kind):
+        need = self.info.op_ws_bytes if kind == "op" else self.info.solve_ws_bytes
+        if ws.device != self.device or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous tensor on %s" % self.device)
+        if ws.numel() * ws.element_size() < need:
+            raise ValueError("workspace holds %d bytes, %d needed" % (ws.numel() * ws.element_size(), need))
+        return ws.numel() * ws.element_size()
+
     # ---- operator ------------------------------------------------------------
     def forward(self, x, precision="fp32", out=None, ws=None, stream=None):
         self._check_vol(x)
@@ -127,7 +141,7 @@ class Plan:
         self._check_data(out)
         ws = self._op_ws(ws)
         check("mpi3d_forward", _lib.load().mpi3d_forward(self._h, PRECISION[precision], _ptr(x), _ptr(out),
-                                                          _ptr(ws), ws.numel(), _stream(stream)))
+                                                          _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
         return out
 
     def adjoint(self, b, precision="fp32", out=None, ws=None, stream=None):
@@ -136,36 +150,39 @@ class Plan:
         self._check_vol(out)
         ws = self._op_ws(ws)
         check("mpi3d_adjoint", _lib.load().mpi3d_adjoint(self._h, PRECISION[precision], _ptr(b), _ptr(out),
-                                                          _ptr(ws), ws.numel(), _stream(stream)))
+                                                          _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
         return out
 
     def project(self, x, out=None, stream=None):
         self._check_vol(x)
         out = torch.empty(self.proj_shape, dtype=torch.float32, device=self.device) if out is None else out
+        self._check_f32(out, self.proj_shape, "projections")
         check("mpi3d_project", _lib.load().mpi3d_project(self._h, _ptr(x), _ptr(out), _stream(stream)))
         return out
 
     def backproject(self, rho, out=None, stream=None):
         out = torch.empty(self.shape, dtype=torch.float32, device=self.device) if out is None else out
         self._check_vol(out)
-        rho = rho.contiguous()
+        self._check_f32(rho, self.proj_shape, "projections")
         check("mpi3d_backproject", _lib.load().mpi3d_backproject(self._h, _ptr(rho), _ptr(out), _stream(stream)))
         return out
 
     def signal_fwd(self, rho, precision="fp32", out=None, ws=None, stream=None):
         out = torch.empty(self.data_shape, dtype=torch.complex64, device=self.device) if out is None else out
+        self._check_data(out)
+        self._check_f32(rho, self.lines_shape, "lines")
         ws = self._op_ws(ws)
-        rho = rho.contiguous()
         check("mpi3d_signal_fwd", _lib.load().mpi3d_signal_fwd(self._h, PRECISION[precision], _ptr(rho), _ptr(out),
-                                                                _ptr(ws), ws.numel(), _stream(stream)))
+                                                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
         return out
 
     def signal_adj(self, b, precision="fp32", out=None, ws=None, stream=None):
         self._check_data(b)
         out = torch.empty(self.lines_shape, dtype=torch.float32, device=self.device) if out is None else out
+        self._check_f32(out, self.lines_shape, "lines")
         ws = self._op_ws(ws)
         check("mpi3d_signal_adj", _lib.load().mpi3d_signal_adj(self._h, PRECISION[precision], _ptr(b), _ptr(out),
-                                                                _ptr(ws), ws.numel(), _stream(stream)))
+                                                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
         return out
 
     KERNELS = {"project": 0, "backproject": 1, "signal_fwd": 2, "signal_adj": 3}
@@ -174,10 +191,12 @@ class Plan:
         """Mean device time (ms) of one launch of an operator kernel, from HIP events."""
         x = torch.zeros(self.shape, dtype=torch.float32, device=self.device) if x is None else x
         b = torch.zeros(self.data_shape, dtype=torch.complex64, device=self.device) if b is None else b
+        self._check_vol(x)
+        self._check_data(b)
         ws = self._op_ws(ws)
         ms = ctypes.c_float()
         check("mpi3d_time_kernel", _lib.load().mpi3d_time_kernel(
-            self._h, self.KERNELS[kernel], PRECISION[precision], repeats, _ptr(x), _ptr(b), _ptr(ws), ws.numel(),
+            self._h, self.KERNELS[kernel], PRECISION[precision], repeats, _ptr(x), _ptr(b), _ptr(ws), ws.numel() * ws.element_size(),
             _stream(stream), ctypes.byref(ms)))
         return float(ms.value)
 
@@ -192,15 +211,20 @@ class Plan:
             x = torch.empty(self.shape, dtype=torch.float32, device=self.device)
         self._check_vol(x)
         ws = self.workspace("solve") if ws is None else ws
+        if ws.device != self.device or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous tensor on %s" % self.device)
         o = _lib.SolveOpts()
         o.lam, o.iters, o.clamp_every = lam, iters, clamp_every
         o.precision = PRECISION[precision]
         o.refine_sweeps, o.inner_iters = refine_sweeps, inner_iters
         o.x0_is_zero = 1 if x0_zero else 0
         o.solver, o.reg, o.tau = SOLVER[solver], REG[reg], tau
+        if history is not None and (history.dtype != torch.float64 or history.device != self.device
+                                    or not history.is_contiguous()):
+            raise ValueError("history must be a contiguous float64 tensor on %s" % self.device)
         rep = _lib.SolveReport() if report else None
         hptr = _ptr(history) if history is not None else ctypes.c_void_p()
-        check("mpi3d_solve", _lib.load().mpi3d_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), _ptr(ws), ws.numel(),
+        check("mpi3d_solve", _lib.load().mpi3d_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), _ptr(ws), ws.numel() * ws.element_size(),
                                                       hptr, ctypes.byref(rep) if rep is not None else None,
                                                       _stream(stream)))
         return x, rep
@@ -229,7 +253,7 @@ class State:
         o.x0_is_zero = 1 if self.x0_zero else 0
         h = ctypes.c_void_p()
         check("mpi3d_state_create", _lib.load().mpi3d_state_create(plan._h, _ptr(b), _ptr(self.x), ctypes.byref(o),
-                                                                    _ptr(self.ws), self.ws.numel(), ctypes.byref(h)))
+                                                                    _ptr(self.ws), self.ws.numel() * self.ws.element_size(), ctypes.byref(h)))
         self._h = h
 
     def progress(self):

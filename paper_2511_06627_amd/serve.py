@@ -8,9 +8,18 @@ by tick, advances every active solve by one step through one batched call
 kernel launches).  A request retires when its schedule is complete; its
 volume is copied to host memory on a side stream while the next ticks run.
 
+Budget accounting.  A request's footprint (solver workspace, data, volume)
+is charged from admission until its state is closed after the copy-out, and
+the device tables of each geometry's plan are charged from the admission of
+the first request of that geometry while the plan is cached.  When a request
+does not fit, cached plans that no live request uses are released (least
+recently used first) before it waits.
+
 The scheduling logic is independent of the GPU: it drives an ``executor``
 object (``GpuExecutor`` here; tests also drive a CPU one), so admission,
-batching and retirement can be exercised without a device.
+batching and retirement can be exercised without a device.  Executors
+provide footprint(r), plan_key(r), plan_bytes(r), release_plan(key), admit,
+step, done, start_copy_out, poll_copy_out and steps.
 """
 import heapq
 import time
@@ -65,13 +74,16 @@ class ContinuousBatcher:
     def run(self, requests):
         pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         for r in pending:
-            if self.ex.footprint(r) > self.budget:
-                raise ValueError("request %d needs %d bytes, more than the whole budget" % (r.rid, self.ex.footprint(r)))
+            need = self.ex.footprint(r) + self.ex.plan_bytes(r)
+            if need > self.budget:
+                raise ValueError("request %d needs %d bytes with its plan, more than the whole budget" % (r.rid, need))
         queue = []                # arrived, waiting: (arrival, rid, request)
         active = {}               # rid -> (handle, request, admit_s, footprint)
-        retiring = {}             # rid -> (token, request, admit_s)
+        retiring = {}             # rid -> (token, request, admit_s, footprint)
         outcomes = {}
+        charged = {}              # plan key -> (table bytes, live requests, last use)
         used = 0
+        self.peak_bytes = 0
         t0 = self.clock()
         i = 0
         while i < len(pending) or queue or active or retiring:
@@ -83,10 +95,24 @@ class ContinuousBatcher:
             while queue and len(active) < self.max_active:
                 r = queue[0][2]
                 fp = self.ex.footprint(r)
-                if used + fp > self.budget:
-                    break
+                key = self.ex.plan_key(r)
+                tables = 0 if key in charged else self.ex.plan_bytes(r)
+                if used + fp + tables > self.budget:
+                    # release idle cached plans, least recently used first
+                    idle = sorted((v[2], k) for k, v in charged.items() if v[1] == 0 and k != key)
+                    for _, k in idle:
+                        if used + fp + tables <= self.budget:
+                            break
+                        used -= charged.pop(k)[0]
+                        self.ex.release_plan(k)
+                        self.log.append((self.clock() - t0, "release_plan", -1))
+                    if used + fp + tables > self.budget:
+                        break
                 heapq.heappop(queue)
-                used += fp
+                used += fp + tables
+                nb, live, _ = charged.get(key, (tables, 0, 0))
+                charged[key] = (nb, live + 1, self.clock() - t0)
+                self.peak_bytes = max(self.peak_bytes, used)
                 active[r.rid] = (self.ex.admit(r), r, self.clock() - t0, fp)
                 self.log.append((self.clock() - t0, "admit", r.rid))
             if active:
@@ -95,14 +121,17 @@ class ContinuousBatcher:
                     h, r, admit_s, fp = active[rid]
                     if self.ex.done(h):
                         del active[rid]
-                        used -= fp
                         self.log.append((self.clock() - t0, "retire", rid))
-                        retiring[rid] = (self.ex.start_copy_out(h), r, admit_s)
+                        retiring[rid] = (self.ex.start_copy_out(h), r, admit_s, fp)
             for rid in list(retiring):
-                token, r, admit_s = retiring[rid]
-                x = self.ex.poll_copy_out(token)
+                token, r, admit_s, fp = retiring[rid]
+                x = self.ex.poll_copy_out(token)      # closes the state once the copy is done
                 if x is not None:
                     del retiring[rid]
+                    used -= fp
+                    key = self.ex.plan_key(r)
+                    nb, live, last = charged[key]
+                    charged[key] = (nb, live - 1, last)
                     t = self.clock() - t0
                     outcomes[rid] = Outcome(rid, r.arrival_s, admit_s, t, self.ex.steps(token), x)
                     self.log.append((t, "done", rid))
@@ -141,10 +170,22 @@ class GpuExecutor:
 
     def footprint(self, r):
         """Device bytes of one request: its solver workspace, data and volume
-        (plan tables are shared by the requests of one geometry and counted
-        once when the plan is created)."""
+        (plan tables are shared by the requests of one geometry: plan_bytes)."""
         p = self._plan(r.geometry)
         return int(p.info.solve_ws_bytes) + 4 * int(p.info.n_data_floats) + 4 * int(p.info.n_vox)
+
+    def plan_key(self, r):
+        return tuple(sorted(r.geometry.items()))
+
+    def plan_bytes(self, r):
+        """Device bytes held by the plan of the request's geometry (its tables)."""
+        return int(self._plan(r.geometry).info.table_bytes)
+
+    def release_plan(self, key):
+        p = self.plans.pop(key, None)
+        if p is not None:
+            self.torch.cuda.synchronize(self.device)
+            p.close()
 
     def admit(self, r):
         from .plan import State

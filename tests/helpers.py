@@ -64,6 +64,56 @@ class PerturbedOperator:
 FP32_OP_EPS = 1e-6
 
 
+# Relative error level of one mixed-operator application (fp16 tables, scaled
+# fp16 operand lines and time tile, bf16 gathers): the mixed operator tests
+# measure 7e-5 .. 3e-4 relative L2 on whole vectors.
+MIXED_OP_EPS = 2e-4
+
+
+class Cluster:
+    """Iterates of one schedule run on the oracle operator under independent
+    random relative errors of one operator error level, one run per seed.
+
+    CGLS is chaotic mid-run: any rounding moves the iterate away from the
+    exact-arithmetic run by much more than the rounding (the exact run is an
+    outlier), while runs with different rounding land close to one another.
+    So an implementation is compared with the runs' mean, and the bar is a
+    multiple of the cluster's radius: the largest distance of one run to the
+    mean, relative to the mean's norm (``pairwise`` is the largest distance
+    between two runs).  ``select`` picks what is compared (a sample of
+    voxels, say) from a full iterate."""
+
+    def __init__(self, runs, select=None):
+        sel = (lambda v: np.asarray(v).ravel()) if select is None else select
+        xs = [np.asarray(sel(x), dtype=np.float64) for x in runs]
+        self.mean = np.mean(xs, axis=0)
+        nm = np.linalg.norm(self.mean)
+        self.radius = max(float(np.linalg.norm(x - self.mean) / nm) for x in xs)
+        self.pairwise = max(float(np.linalg.norm(a - b) / nm) for i, a in enumerate(xs) for b in xs[i + 1:])
+        self.n = len(xs)
+
+    def distance(self, x):
+        return float(np.linalg.norm(np.asarray(x, dtype=np.float64).ravel() - self.mean.ravel())
+                     / np.linalg.norm(self.mean))
+
+
+def cgls_cluster(run, op, eps=FP32_OP_EPS, seeds=tuple(range(101, 109)), select=None):
+    """Cluster of run(perturbed op) over the seeds (see Cluster)."""
+    return Cluster([run(PerturbedOperator(op, eps, s)) for s in seeds], select)
+
+
+def mixed_cluster(run, op, seeds=tuple(range(201, 209)), select=None, eps_outer=FP32_OP_EPS,
+                  eps_inner=MIXED_OP_EPS):
+    """Cluster of refinement runs run(outer, inner): outer operator at the FP32
+    error level (the sweeps' residuals), inner operator at the mixed level."""
+    return Cluster([run(PerturbedOperator(op, eps_outer, s), PerturbedOperator(op, eps_inner, s + 5000))
+                    for s in seeds], select)
+
+
+# Bar of a same-schedule solve comparison, in cluster radii.
+CLUSTER_BAR = 4.0
+
+
 def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_OP_EPS):
     """Largest relative deviation between run(op) and run(perturbed op) over a
     few seeds: how far an implementation whose operator is accurate to about
@@ -71,3 +121,53 @@ def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_OP_EPS):
     ref = run(op)
     dev = max(rel_l2(run(PerturbedOperator(op, eps, s)), ref) for s in seeds)
     return ref, dev
+
+
+def band_errors(got, want, g, axis=-1):
+    """Relative L2 error of each kept harmonic band (the 2D + 1 bins around one
+    harmonic), over all lines: got/want complex data [..., n_bins]."""
+    bw = 2 * g.half_band + 1
+    got = np.moveaxis(np.asarray(got), axis, -1)
+    want = np.moveaxis(np.asarray(want), axis, -1)
+    return np.array([rel_l2(got[..., h * bw:(h + 1) * bw], want[..., h * bw:(h + 1) * bw])
+                     for h in range(g.n_bins // bw)])
+
+
+def band_confined_data(g, seed):
+    """Data whose slice k holds random values in harmonic band k mod n_bands
+    only: A is block diagonal over z-slices, so one adjoint call yields, slice
+    by slice, the adjoint of each band's data alone.  Returns (y, band of each
+    slice)."""
+    bw = 2 * g.half_band + 1
+    nbands = g.n_bins // bw
+    rng = np.random.default_rng(seed)
+    y = np.zeros((g.n_angles, g.nz, g.n_bins), dtype=np.complex128)
+    band = np.arange(g.nz) % nbands
+    for k in range(g.nz):
+        h = band[k]
+        y[:, k, h * bw:(h + 1) * bw] = rng.standard_normal((g.n_angles, bw)) + 1j * rng.standard_normal((g.n_angles, bw))
+    return y, band
+
+
+# Per-band bars.  FP32: 1e-4 per band.  Mixed forward: the time tile and the
+# band table are rounded to fp16 (unit roundoff 2^-11) relative to the whole
+# line's signal, so a weak band's own relative error grows as its share of the
+# signal shrinks: modelled (numpy fp16 rounding of the oracle's tables, lines
+# and time tile) at 4.4e-3 for harmonic 31 of the 192x192x96 scan and 1.2e-2
+# for harmonic 47 of the 256x256x128 scan; bar 3e-2.  Mixed adjoint: each
+# band's data is scaled toward unit size before rounding (per-band scaling),
+# so a band confined to its own data keeps the operator bar, 5e-3.  Dropping a
+# band, or scaling it wrongly, gives errors of order 1.
+BAND_TOL32 = 1e-4
+BAND_TOL16_FWD = 3e-2
+BAND_TOL16_ADJ = 5e-3
+
+
+def band_table(name, rows, harm_lo=1):
+    """Log lines of a per-harmonic error table: rows = {label: errors}."""
+    labels = list(rows)
+    n = len(next(iter(rows.values())))
+    out = ["%s per-harmonic rel err: harmonic | %s" % (name, " | ".join(labels))]
+    for h in range(n):
+        out.append("  %3d | %s" % (h + harm_lo, " | ".join("%.2e" % rows[k][h] for k in labels)))
+    return "\n".join(out)

@@ -14,7 +14,8 @@ import pytest
 
 from oracle import operator as oop, solvers
 from paper_2511_06627_amd import configs
-from helpers import oracle_geometry, config_geometry, rel_l2, random_volume, random_data
+from helpers import (oracle_geometry, config_geometry, rel_l2, random_volume, random_data, band_errors,
+                     band_confined_data, band_table, BAND_TOL32, BAND_TOL16_FWD, BAND_TOL16_ADJ, Cluster)
 
 pytestmark = pytest.mark.gpu
 TOL_OP16 = 5e-3
@@ -72,17 +73,51 @@ def test_mixed_adjoint(case, torch_mod):
     assert err <= TOL_OP16
 
 
-def test_mixed_adjoint_sees_weak_bands(case, torch_mod):
-    """Data confined to the weakest harmonic band: band scaling keeps the fp16
-    adjoint accurate even though that band is far below the line maximum."""
-    name, g, plan = case
+def _per_band(torch_mod, plan, g, x, y, slices=None, oracle_fwd=None, oracle_adj=None):
+    """Per-harmonic relative errors of A (on volume x) and of A^T on band-confined
+    data y (slice k holding band k mod n_bands only), both precisions.  With
+    `slices`, only those slices are compared (oracle_fwd / oracle_adj give the
+    oracle's result for one slice)."""
     bw = 2 * g.half_band + 1
-    y = np.zeros((g.n_angles, g.nz, g.n_bins), dtype=complex)
-    rng = np.random.default_rng(33)
-    y[..., -bw:] = 1e-3 * (rng.standard_normal((g.n_angles, g.nz, bw)) + 1j * rng.standard_normal((g.n_angles, g.nz, bw)))
-    y[..., :bw] = rng.standard_normal((g.n_angles, g.nz, bw))  # a strong first band on the same lines
-    got_full = plan.adjoint(_dev(torch_mod, y, torch_mod.complex64), precision="mixed").cpu().numpy()
-    assert rel_l2(got_full, oop.adjoint(g, y)) <= TOL_OP16
+    nbands = g.n_bins // bw
+    xd = _dev(torch_mod, x, torch_mod.float32)
+    yd = _dev(torch_mod, y, torch_mod.complex64)
+    ks = range(g.nz) if slices is None else slices
+    want_f = oop.forward(g, x) if slices is None else None
+    want_a = oop.adjoint(g, y) if slices is None else None
+    rows = {}
+    for prec in ("fp32", "mixed"):
+        got = plan.forward(xd, precision=prec).cpu().numpy()
+        if slices is None:
+            rows[prec + " A"] = band_errors(got, want_f, g)
+        else:
+            rows[prec + " A"] = band_errors(np.stack([got[:, k] for k in ks], 1),
+                                            np.stack([oracle_fwd(k) for k in ks], 1), g)
+        got = plan.adjoint(yd, precision=prec).cpu().numpy()
+        err = np.zeros(nbands)
+        for k in ks:
+            want_k = want_a[k] if slices is None else oracle_adj(k)
+            err[k % nbands] = max(err[k % nbands], rel_l2(got[k], want_k))
+        rows[prec + " A^T"] = err
+    return rows
+
+
+def _check_bands(rows):
+    assert np.all(rows["fp32 A"] <= BAND_TOL32) and np.all(rows["fp32 A^T"] <= BAND_TOL32)
+    assert np.all(rows["mixed A"] <= BAND_TOL16_FWD)
+    assert np.all(rows["mixed A^T"] <= BAND_TOL16_ADJ)
+
+
+def test_per_band_errors(case, torch_mod):
+    """Every harmonic band on its own: A's output per band, and A^T of data
+    confined to one band (no strong band beside it to hide in), FP32 and
+    mixed, against the oracle."""
+    name, g, plan = case
+    y, band = band_confined_data(g, 33)
+    assert len(set(band)) == g.n_bins // (2 * g.half_band + 1), "every band needs a slice"
+    rows = _per_band(torch_mod, plan, g, random_volume(g, 31), y)
+    _log(band_table(name, rows, g.harm_lo))
+    _check_bands(rows)
 
 
 def test_mixed_subnormal_rows_stay_finite(case, torch_mod):
@@ -161,3 +196,62 @@ def test_mixed_realistic_sampled(torch_mod):
         err = rel_l2(got[k], oop.adjoint(gs, y[:, k:k + 1, :])[0])
         _log("realistic mixed adjoint slice %d rel err %.3e" % (k, err))
         assert err <= TOL_OP16
+
+
+def test_mixed_realistic_per_band(torch_mod):
+    """Per-harmonic errors on the 192x192x96 scan (phantom volume for A; data
+    confined to band k mod 31 on slice k for A^T), sampled slices."""
+    from paper_2511_06627_amd.plan import Plan
+    cfg = configs.REALISTIC_192
+    _log("mixed case realistic_192x192x96 per band")
+    g = config_geometry(cfg)
+    gs = g.slice_geometry()
+    plan = Plan.from_config(cfg, g.op_scale, precisions=("fp32", "mixed"))
+    x = configs.make_phantom(cfg)
+    y, band = band_confined_data(g, 37)
+    opc = oop.Operator(gs, precomposed=True)
+    mass = x.sum(axis=(1, 2))
+    fwd_slices = (int(np.argmax(mass)), 7)
+    rows = _per_band(torch_mod, plan, g, x, y, slices=list(range(31)),
+                     oracle_fwd=lambda k: opc.forward(x[k:k + 1])[:, 0, :],
+                     oracle_adj=lambda k: opc.adjoint(y[:, k:k + 1, :])[0])
+    # A on the phantom: the organ's middle slice and one through blobs only
+    got = {p: plan.forward(_dev(torch_mod, x, torch_mod.float32), precision=p).cpu().numpy() for p in ("fp32", "mixed")}
+    for p in ("fp32", "mixed"):
+        rows[p + " A"] = band_errors(np.stack([got[p][:, k] for k in fwd_slices], 1),
+                                     np.stack([opc.forward(x[k:k + 1])[:, 0, :] for k in fwd_slices], 1), g)
+    _log(band_table(cfg.name, rows, g.harm_lo))
+    _check_bands(rows)
+
+
+def test_mixed_realistic_3x20(torch_mod):
+    """The configured mixed schedule on the 192x192x96 scan: 3 refinement
+    sweeps of 20 inner iterations, against the same schedule's oracle cluster
+    (tests/golden/cgls_clusters.json: sweep residuals at the FP32 operator's
+    error level, inner operator at the mixed one), within 4 cluster radii of
+    its mean on the sample voxels; the error against the FP64 minimiser x* is
+    stated beside it."""
+    import json
+    import os
+    from paper_2511_06627_amd.plan import Plan
+    cfg, m2 = configs.REALISTIC_192, configs.MIXED_192
+    _log("mixed case realistic_192x192x96 3x20")
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cgls_clusters.json")))
+    g = config_geometry(cfg)
+    assert abs(ref["op_scale"] - g.op_scale) <= 1e-9 * g.op_scale
+    b, _ = oop.make_data(g, configs.make_phantom(cfg), cfg.noise, cfg.noise_seed)
+    plan = Plan.from_config(cfg, g.op_scale, precisions=("fp32", "mixed"))
+    x, rep = plan.solve(torch_mod.from_numpy(b.astype(np.complex64)).cuda(), m2.lam, precision="mixed",
+                        refine_sweeps=m2.refine_sweeps, inner_iters=m2.inner_iters)
+    assert rep.status == 0
+    idx = np.array(ref["sample_index"])
+    got = x.cpu().numpy().ravel()[idx]
+    cl = ref["mixed3x20"]
+    mean = np.array(cl["sample_mean"])
+    err = float(np.linalg.norm(got - mean) / np.linalg.norm(mean))
+    xs = np.array(ref["xstar"]["sample"])
+    ex = float(np.linalg.norm(got - xs) / np.linalg.norm(xs))
+    tol = cl["bar_radii"] * cl["radius"]
+    _log("realistic mixed 3x20: GPU to cluster mean %.3e (radius %.3e, bar %.3e); GPU vs x* %.3e on the sample "
+         "(cluster mean vs x* over the volume %.3e)" % (err, cl["radius"], tol, ex, cl["mean_to_xstar_full"]))
+    assert err <= tol

@@ -26,14 +26,26 @@ class FakeClock:
 class OracleExecutor:
     """One oracle CGLS iteration per tick; each tick costs `tick_s` of clock."""
 
-    def __init__(self, clock, tick_s=0.01, fp_of=None):
+    def __init__(self, clock, tick_s=0.01, fp_of=None, plan_bytes_of=None):
         self.clock = clock
         self.tick_s = tick_s
         self.fp_of = fp_of or (lambda r: 100)
+        self.plan_bytes_of = plan_bytes_of or (lambda r: 0)
         self.batches = []
+        self.copies = 0
+        self.released = []
 
     def footprint(self, r):
         return self.fp_of(r)
+
+    def plan_key(self, r):
+        return tuple(sorted(r.geometry.items()))
+
+    def plan_bytes(self, r):
+        return self.plan_bytes_of(r)
+
+    def release_plan(self, key):
+        self.released.append(key)
 
     def admit(self, r):
         g = Geometry(**r.geometry)
@@ -54,6 +66,12 @@ class OracleExecutor:
         return h
 
     def poll_copy_out(self, token):
+        # the copy takes one poll to finish: the state (and its footprint)
+        # stays live for one more tick after it retires
+        self.copies += 1
+        if not token.get("copied"):
+            token["copied"] = True
+            return None
         return token["x"]
 
     def steps(self, token):
@@ -139,3 +157,43 @@ def test_fcfs_order_and_summary():
 def test_percentile():
     assert percentile([1, 2, 3, 4], 50) == 2.5
     assert percentile([5], 99) == 5
+
+
+def test_plan_tables_are_charged_to_the_budget():
+    """Geometries whose plans hold 50 bytes each, requests of 30 bytes, a
+    budget of 130: one plan and two requests fit (110), a second geometry's
+    request (50 + 30 more) does not until the first geometry's requests are
+    gone and its plan is released, so at most 130 bytes are ever in use."""
+    clock = FakeClock()
+    reqs = _requests(8)
+    geos = sorted({tuple(sorted(r.geometry.items())) for r in reqs})
+    assert len(geos) >= 2
+    ex = OracleExecutor(clock, fp_of=lambda r: 30, plan_bytes_of=lambda r: 50)
+    bat = ContinuousBatcher(ex, budget_bytes=130, max_active=8, clock=clock, sleep=clock.sleep)
+    out = bat.run(reqs)
+    assert len(out) == 8
+    assert bat.peak_bytes <= 130
+    # with plans charged, two 30-byte requests of two geometries (50 + 50 + 60)
+    # never run together
+    for b in ex.batches:
+        keys = {tuple(sorted(reqs[rid].geometry.items())) for rid in b}
+        assert len(keys) == 1 or len(b) <= 1, b
+    assert len(ex.released) >= 1
+    with pytest.raises(ValueError):
+        ContinuousBatcher(OracleExecutor(clock, fp_of=lambda r: 30, plan_bytes_of=lambda r: 101), budget_bytes=130,
+                          clock=clock, sleep=clock.sleep).run(reqs[:1])
+
+
+def test_footprint_held_until_the_copy_out_closes_the_state():
+    """A retired request keeps its footprint until its result has left the
+    device: with room for one request, the next is admitted only after the
+    previous one's copy-out completed."""
+    clock = FakeClock()
+    ex = OracleExecutor(clock, fp_of=lambda r: 60)
+    bat = ContinuousBatcher(ex, budget_bytes=100, max_active=8, clock=clock, sleep=clock.sleep)
+    bat.run(_requests(4))
+    ev = [(e, rid) for _, e, rid in bat.log]
+    for rid in range(1, 4):
+        admit = ev.index(("admit", rid))
+        assert any(e == "done" for e, _ in ev[:admit]), ev
+    assert bat.peak_bytes <= 100
