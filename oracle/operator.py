@@ -13,6 +13,9 @@ Test infrastructure only (see ``oracle/__init__``).
                   slice, or on two under a raster.
 * Dual drive -- the z-drive lines follow the x-drive lines (``geometry``);
                   A^T adds their transposed contributions to the projections.
+                  Under the tensor PSF the x-drive lines couple across z-rows
+                  and the z-drive lines across detector columns (the same
+                  tensor entry with the drive axis exchanged).
 * ``make_data`` -- synthetic compressed data: clean time signal of a phantom,
                   plus white Gaussian noise in the time domain with standard
                   deviation level * max|s_clean|, then compression.
@@ -87,12 +90,15 @@ class Operator:
         self.coupled = bool(g.psf_rows)
         self.dual = g.drive_axes == 2
         if self.dual:
-            assert not g.psf_rows and not g.raster_sweep
-            Kz = signal.kernel_z(g)
-            if precomposed:
-                self.Cz = signal.dft_matrix(g).T @ Kz
+            assert not g.raster_sweep
+            if g.psf_rows:
+                self.Mz = signal.z_column_matrices(g, precomposed)   # per column offset
             else:
-                self.Kz = Kz
+                Kz = signal.kernel_z(g)
+                if precomposed:
+                    self.Cz = signal.dft_matrix(g).T @ Kz
+                else:
+                    self.Kz = Kz
         if self.coupled:
             assert not g.raster_sweep
             rows = range(signal.coupled_rows(g) + 1)
@@ -146,12 +152,24 @@ class Operator:
         return _per_class(self.g, y, self._lines_adj_class)
 
     def _z_fwd(self, zl):
+        g = self.g
+        if self.coupled:   # z-drive lines coupled across the detector columns of their angle
+            if self.precomposed:
+                return signal.coupled_apply(g, zl, self.Mz, per=g.n_u)
+            s = signal.coupled_apply(g, zl, self.Mz, per=g.n_u)
+            return (s @ self.E_re) + 1j * (s @ self.E_im)
         if self.precomposed:
             return zl @ self.Cz.T
         s = zl @ self.Kz.T
         return (s @ self.E_re) + 1j * (s @ self.E_im)
 
     def _z_adj(self, y):
+        g = self.g
+        if self.coupled:
+            if self.precomposed:
+                return np.real(signal.coupled_apply(g, y, [np.conj(C) for C in self.Mz], adjoint=True, per=g.n_u))
+            h = np.ascontiguousarray(y.real) @ self.E_re.T + np.ascontiguousarray(y.imag) @ self.E_im.T
+            return signal.coupled_apply(g, h, self.Mz, adjoint=True, per=g.n_u)
         if self.precomposed:
             return np.real(y @ np.conj(self.Cz))
         h = np.ascontiguousarray(y.real) @ self.E_re.T + np.ascontiguousarray(y.imag) @ self.E_im.T
@@ -210,7 +228,11 @@ def make_data(g, phantom, noise_level, noise_seed):
 
     s_all = signal.coupled_apply(g, rt, op.Kd) if op.coupled else None
     if op.dual:   # x-drive lines, then z-drive lines
-        s_all = np.concatenate([rt @ op.K[0].T, signal.z_lines(g, rt) @ op.Kz.T])
+        zl = signal.z_lines(g, rt)
+        if op.coupled:
+            s_all = np.concatenate([s_all, signal.coupled_apply(g, zl, op.Mz, per=g.n_u)])
+        else:
+            s_all = np.concatenate([rt @ op.K[0].T, zl @ op.Kz.T])
 
     def clean(a):   # time signals of lines a .. a+511, each through its class's K
         if s_all is not None:

@@ -73,16 +73,23 @@ def coupled_rows(g):
     return min(g.psf_rows, g.nz - 1)
 
 
-def coupled_apply(g, rows, mats, adjoint=False):
-    """The row-coupled map over all L lines in line order: forward
+def coupled_columns(g):
+    """Detector columns coupled on each side to a z-drive line (tensor PSF)."""
+    return min(g.psf_rows, g.n_u - 1)
+
+
+def coupled_apply(g, rows, mats, adjoint=False, per=None):
+    """The row-coupled map over the lines of every angle in line order, `per`
+    lines an angle (default the z-rows): forward
     out[m, k] = sum_{|d| <= R} rows[m, k + d] @ mats[|d|].T, adjoint its
-    transpose out[m, k + d] += rows[m, k] @ mats[|d|]."""
-    R = coupled_rows(g)
-    rr = rows.reshape(g.n_angles, g.nz, -1)
+    transpose out[m, k + d] += rows[m, k] @ mats[|d|], R = len(mats) - 1."""
+    per = g.nz if per is None else per
+    R = len(mats) - 1
+    rr = rows.reshape(g.n_angles, per, -1)
     width = mats[0].shape[1] if adjoint else mats[0].shape[0]
-    out = np.zeros((g.n_angles, g.nz, width), dtype=np.result_type(rows, mats[0]))
+    out = np.zeros((g.n_angles, per, width), dtype=np.result_type(rows, mats[0]))
     for d in range(-R, R + 1):
-        lo, hi = max(0, -d), min(g.nz, g.nz - d)
+        lo, hi = max(0, -d), min(per, per - d)
         if lo >= hi:
             continue
         M = mats[abs(d)]
@@ -90,7 +97,7 @@ def coupled_apply(g, rows, mats, adjoint=False):
             out[:, lo + d:hi + d] += rr[:, lo:hi] @ M
         else:
             out[:, lo:hi] += rr[:, lo + d:hi + d] @ M.T
-    return out.reshape(g.n_lines, width)
+    return out.reshape(g.n_angles * per, width)
 
 
 def z_grid(g):
@@ -101,6 +108,27 @@ def z_grid(g):
 def kernel_z(g):
     """K of the z-drive lines: c_A v_n L'((xi_n - z_k)/w)/w with amplitude a_z, shape (T, Nz)."""
     return psf_kernel(g.n_t, g.drive_cycles, g.drive_amp_z, g.psf_width, z_grid(g), g.op_scale)
+
+
+def kernel_z_column(g, d):
+    """K_z,d[n, k] = c_A v_n h(xi_n - z_k, d): a z-drive line's coupling to the
+    detector column d voxels away under the tensor PSF.  With drive and
+    receive coil along z, the entry of eq. PSF is the xx entry with the two
+    axes exchanged: along-drive offset xi_n - z_k, transverse offset d
+    (``physics.psf_xx``); K_z,0 is ``kernel_z``."""
+    xi, v = trajectory(g.n_t, g.drive_cycles, g.drive_amp_z)
+    dz = xi[:, None] - z_grid(g)[None, :]
+    return g.op_scale * v[:, None] * psf_xx(dz, d, g.psf_width)
+
+
+def z_column_matrices(g, precomposed):
+    """The z-drive lines' tables per column offset d = 0..R (time domain), or
+    precomposed with the band DFT: E^T K_z,d."""
+    Ks = [kernel_z_column(g, d) for d in range(coupled_columns(g) + 1)]
+    if not precomposed:
+        return Ks
+    E = dft_matrix(g)
+    return [E.T @ K for K in Ks]
 
 
 def z_lines(g, rho_theta):

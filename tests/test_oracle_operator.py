@@ -216,3 +216,66 @@ def test_dual_drive_adjoint_precomposed_and_data():
     g1 = _dual(nz=5, drive_axes=1)
     ax1 = operator.forward(g1, x).reshape(g.n_lines, g.n_bins)
     assert np.max(np.abs(ax[:g.n_lines] - ax1)) <= 1e-13 * np.max(np.abs(ax1))
+
+
+def test_dual_drive_tensor_lines_are_derivatives_of_their_magnetisation():
+    """Both scans under the tensor PSF (Sec. 3.1 with Appendix B eq. PSF): every
+    x-drive line's signal is the time derivative of the x-magnetisation of the
+    z-rows within R of it, and every z-drive line's (m, p) that of the
+    z-magnetisation of the detector columns within R of p -- the same tensor
+    entry with the drive axis exchanged, m_z = c_A sum rho L(r/w) dz/r,
+    r = |(xi_z - z_k, p' - p)| -- at data line M*Nz + m*Nu + p (complex step)."""
+    from oracle import physics, signal
+    from oracle.geometry import detector_grid
+    for R in (2, 7):
+        g = _dual(nz=5, psf_rows=R)
+        rng = np.random.default_rng(31)
+        rt = rng.uniform(0, 1, (g.n_angles, g.nz, g.n_u))
+        op = operator.Operator(g)
+        s_x = signal.coupled_apply(g, rt.reshape(g.n_lines, g.n_u), op.Kd)
+        s_z = signal.coupled_apply(g, signal.z_lines(g, rt), op.Mz, per=g.n_u)
+        h = 1e-30
+        t = np.arange(g.n_t) + 1j * h
+        zg = np.arange(g.nz) - (g.nz - 1) / 2.0
+        Rx, Rz = min(R, g.nz - 1), min(R, g.n_u - 1)
+        for m in range(g.n_angles):
+            for k in range(g.nz):
+                dm = sum(physics.magnetisation_x(t, g.drive_cycles, g.n_t, g.drive_amp, g.psf_width, detector_grid(g),
+                                                 rt[m, k2], g.op_scale, k - k2).imag / h
+                         for k2 in range(g.nz) if abs(k - k2) <= Rx)
+                assert np.max(np.abs(s_x[m * g.nz + k] - dm)) <= 1e-12 * np.max(np.abs(dm))
+            for p in range(g.n_u):
+                dm = sum(physics.magnetisation_x(t, g.drive_cycles, g.n_t, g.nz / 2.0, g.psf_width, zg,
+                                                 rt[m, :, p2], g.op_scale, p - p2).imag / h
+                         for p2 in range(g.n_u) if abs(p - p2) <= Rz)
+                assert np.max(np.abs(s_z[m * g.n_u + p] - dm)) <= 1e-12 * np.max(np.abs(dm)), (R, m, p)
+
+
+def test_dual_drive_tensor_operator():
+    """Both scans under the tensor PSF: adjoint identity to 1e-12, precomposed =
+    time-domain, noise-free data = A x, the x-drive half equal to the
+    single-drive tensor operator, and the z-drive table at zero column offset
+    the collinear z-drive PSF (closed form h(along, 0) = L'(along/w)/w); the
+    coupling across columns is not negligible."""
+    from oracle import signal
+    g = _dual(nz=5, psf_rows=2)
+    rng = np.random.default_rng(32)
+    x = rng.standard_normal((g.nz, g.ny, g.nx))
+    y = rng.standard_normal((g.n_data_lines, g.n_bins)) + 1j * rng.standard_normal((g.n_data_lines, g.n_bins))
+    ax = operator.forward(g, x)
+    lhs = np.vdot(ax, y).real
+    assert abs(lhs - np.vdot(x, operator.adjoint(g, y))) <= 1e-12 * abs(lhs)
+    assert np.max(np.abs(operator.forward(g, x, precomposed=True) - ax)) <= 1e-12 * np.max(np.abs(ax))
+    ya = operator.adjoint(g, y)
+    assert np.max(np.abs(operator.adjoint(g, y, precomposed=True) - ya)) <= 1e-12 * np.max(np.abs(ya))
+    b, sigma = operator.make_data(g, np.abs(x), 0.0, 1)
+    assert sigma == 0.0 and np.max(np.abs(b - operator.forward(g, np.abs(x)))) <= 1e-12 * np.max(np.abs(b))
+    gx = _small()
+    gx = Geometry(**{**{k: getattr(gx, k) for k in gx.__dataclass_fields__}, "nz": 5, "psf_rows": 2})
+    ax1 = operator.forward(gx, x).reshape(g.n_lines, g.n_bins)
+    assert np.max(np.abs(ax[:g.n_lines] - ax1)) <= 1e-13 * np.max(np.abs(ax1))
+    Kz0 = signal.kernel_z_column(g, 0)
+    assert np.max(np.abs(Kz0 - signal.kernel_z(g))) <= 1e-14 * np.max(np.abs(Kz0))
+    g0 = _dual(nz=5)
+    az0 = operator.forward(g0, x)[g.n_lines:]
+    assert np.linalg.norm(ax[g.n_lines:] - az0) > 1e-3 * np.linalg.norm(az0)
