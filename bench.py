@@ -197,7 +197,8 @@ def projection_report(cfg, kernel, ms, measured_bytes, bf16=False):
     * LDS: the bytes the kernel's gathers read from LDS, one bilinear footprint
       of 4 texels per ray sample and slice (forward: 4 B per texel and slice in
       fp32, 2 B in bf16) or 3 staged ray values per voxel, angle and slice
-      (backprojection, fp32, 4 B each), about n_angles * n_vox samples in all,
+      (backprojection: 4 B each in fp32, 2 B in the mixed operator's fp16),
+      about n_angles * n_vox samples in all,
       against the LDS peak of 128 B per clock per CU."""
     nvox = cfg.nx * cfg.ny * cfg.nz
     samples = float(cfg.n_angles) * nvox
@@ -206,7 +207,9 @@ def projection_report(cfg, kernel, ms, measured_bytes, bf16=False):
     else:
         lds = samples * 3 * (2 if bf16 else 4)
     pb = projection_bytes(cfg)
-    compulsory = (2 if bf16 and kernel == "project" else 4) * nvox + 4.0 * cfg.n_lines * cfg.n_u
+    vol_b = 2 if bf16 and kernel == "project" else 4        # the mixed forward gathers a bf16 volume
+    line_b = 2 if bf16 and kernel == "backproject" else 4   # the mixed adjoint gathers fp16 lines
+    compulsory = vol_b * nvox + line_b * cfg.n_lines * cfg.n_u
     t = ms * 1e-3
     out = {"ms": round(ms, 4),
            "model_stream_GBs": round(pb / t / 1e9, 1), "model_stream_frac": round(pb / t / 1e9 / HBM_PEAK_GBS, 4),
@@ -306,9 +309,10 @@ def hdr_leg(torch, plan, inputs):
     """The headline scan's nonnegative solves, FP32 (100 CGLS iterations, clamp
     + restart every 10) and mixed (10 sweeps of 10, clamp after each): solve
     time, and the iterate and the faint blobs' recovered amplitudes against the
-    mean of the oracle's cluster of the same schedule (the solve is chaotic
-    mid-run; tests/golden/make_hdr.py), with the exact oracle run's distance to
-    that mean beside them."""
+    means of the oracle's clusters of the same schedule at the two ends of the
+    path's operator error range (the solve is chaotic mid-run;
+    tests/golden/make_hdr.py), with the exact oracle run's distance to those
+    means beside them."""
     import numpy as np
     from paper_2511_06627_amd import configs, phantoms
     cfg = configs.HDR_256
@@ -331,15 +335,18 @@ def hdr_leg(torch, plan, inputs):
         dt = time.perf_counter() - t0
         xn = x.cpu().numpy().astype(np.float64)
         amp = np.array([float(np.vdot(xn, gb) / np.vdot(gb, gb)) for gb in profiles])
-        cl = ref["cluster"][prec]
-        mean = np.array(cl["sample_mean"])
-        amean = np.array(cl["amp_mean"])
+        lo, hi = ref["cluster"][prec]
+        xs = xn.ravel()[idx]
+        alo, ahi = np.array(lo["amp_mean"]), np.array(hi["amp_mean"])
         out[prec] = {"schedule": kw, "seconds": round(dt, 4), "status": rep.status,
-                     "samples_to_cluster_mean": float(np.linalg.norm(xn.ravel()[idx] - mean) / np.linalg.norm(mean)),
-                     "cluster_radius": cl["sample_radius"],
-                     "exact_oracle_to_cluster_mean": cl["exact_sample_to_mean"],
-                     "faint_amp_max_rel_to_cluster": float(np.max(np.abs(amp - amean) / np.abs(amean))),
-                     "faint_amp_cluster_radius": cl["amp_radius_rel"],
+                     "samples_to_cluster_means": [float(np.linalg.norm(xs - np.array(c["sample_mean"]))
+                                                        / np.linalg.norm(c["sample_mean"])) for c in (lo, hi)],
+                     "cluster_radii": [lo["sample_radius"], hi["sample_radius"]],
+                     "cluster_eps": [lo["eps"], hi["eps"]],
+                     "exact_oracle_to_cluster_means": [lo["exact_sample_to_mean"], hi["exact_sample_to_mean"]],
+                     "faint_amp_max_rel_to_cluster_means": [float(np.max(np.abs(amp - a) / np.abs(a)))
+                                                            for a in (alo, ahi)],
+                     "faint_amp_cluster_radii": [lo["amp_radius_rel"], hi["amp_radius_rel"]],
                      "faint_amp_recovered_over_true_median": float(np.median(amp / amp_true))}
         log("hdr %s: %s" % (prec, out[prec]))
     del ws
@@ -353,6 +360,8 @@ def hdr_leg(torch, plan, inputs):
 # FP32 restart costs about two mixed iterations.
 MIXED_CANDIDATES = ((2, 25), (2, 30), (3, 20), (2, 35), (3, 25), (4, 20), (3, 30), (4, 25), (3, 40), (5, 30),
                     (6, 30))
+SERVE_REF_ITERS = 300      # FP32 CGLS iterations of a serving request's converged reference
+SERVE_TARGET = 8e-5        # schedule target: every request of a class within this of its reference
 
 
 def device_data(torch, plan, phantom, noise, seed):
@@ -439,53 +448,65 @@ def serve_leg(torch, n_requests=None, stream=True):
     # warm the executor's code paths once
     run(with_sched({k: dict(precision="mixed", refine_sweeps=1, inner_iters=2) for _, k in reqs}, 0.0)[:4])
 
+    # every request's reference: FP32 CGLS run to convergence (REF_ITERS
+    # iterations; tests/test_gpu_solve.py holds such solves within 1e-5 of
+    # the FP64 minimiser on serving classes)
+    ref = {}
+    for r, k in reqs:
+        bd = torch.from_numpy(r.b).cuda()
+        x, _ = plans[k].solve(bd, r.lam, iters=SERVE_REF_ITERS, report=False)
+        ref[r.rid] = x.cpu().numpy().astype(np.float64)
+
+    def errors(res):
+        return [float(np.linalg.norm(o.x - ref[o.rid]) / np.linalg.norm(ref[o.rid])) for o in res]
+
     # (1) the stream as configured: Poisson arrivals, mixed path, 2 sweeps x 20
     if stream:
         cfg_sched = {k: dict(precision="mixed", refine_sweeps=2, inner_iters=20) for _, k in reqs}
         res, summ = run(with_sched(cfg_sched))
-        out["stream_mixed_2x20"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}
-        log("serve stream (mixed 2x20): %s" % out["stream_mixed_2x20"])
+        rec = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}
+        e = errors(res)
+        rec.update({"rel_err_max": max(e), "rel_err_median": float(np.median(e))})
+        out["stream_mixed_2x20"] = rec
+        log("serve stream (mixed 2x20): %s" % rec)
 
-    # (2) per-class schedules at 1e-4 against a converged FP32 reference
-    # (150 CGLS iterations: the FP32 path's own accuracy floor, about 1e-6
-    # of the FP64 minimiser on the realistic scan)
-    ref = {}
+    # (2) per-class schedules that hold every request of the class within
+    # SERVE_TARGET of its reference (the cheapest FP32 iteration count, found
+    # by bisection on the class's worst request, and the cheapest refinement
+    # schedule in MIXED_CANDIDATES order), then the closed loop of all requests
+    by_class = {}
     for r, k in reqs:
-        p = plans[k]
-        bd = torch.from_numpy(r.b).cuda()
-        x, _ = p.solve(bd, r.lam, iters=150, report=False)
-        ref[r.rid] = x
-    first = {}
-    for r, k in reqs:
-        first.setdefault(k, r)
+        by_class.setdefault(k, []).append(r)
 
-    def err(p, r, **kw):
-        bd = torch.from_numpy(r.b).cuda()
-        x, _ = p.solve(bd, r.lam, report=False, **kw)
-        return float(torch.linalg.vector_norm(x - ref[r.rid]) / torch.linalg.vector_norm(ref[r.rid]))
+    def worst(p, rs, **kw):
+        e = 0.0
+        for r in rs:
+            x, _ = p.solve(torch.from_numpy(r.b).cuda(), r.lam, report=False, **kw)
+            xr = ref[r.rid]
+            e = max(e, float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)))
+        return e
 
     sched32, sched16 = {}, {}
-    for k, r in first.items():
+    for k, rs in by_class.items():
         p = plans[k]
-        lo, hi = 10, 150            # smallest FP32 iteration count at 1e-4 (bisection)
+        lo, hi = 10, 200            # smallest FP32 iteration count within the target (bisection)
         while hi - lo > 2:
             mid = (lo + hi) // 2
-            if err(p, r, iters=mid) <= 1e-4:
+            if worst(p, rs, iters=mid) <= SERVE_TARGET:
                 hi = mid
             else:
                 lo = mid
         sched32[k] = dict(precision="fp32", iters=hi)
-        sched16[k] = dict(precision="mixed", refine_sweeps=6, inner_iters=30)
+        sched16[k] = dict(precision="mixed", refine_sweeps=8, inner_iters=30)
         for sw, inner in MIXED_CANDIDATES:
-            if err(p, r, precision="mixed", refine_sweeps=sw, inner_iters=inner) <= 1e-4:
+            if worst(p, rs, precision="mixed", refine_sweeps=sw, inner_iters=inner) <= SERVE_TARGET:
                 sched16[k] = dict(precision="mixed", refine_sweeps=sw, inner_iters=inner)
                 break
     cap = {}
     for name, sched in (("fp32", sched32), ("mixed", sched16)):
         run(with_sched(sched, 0.0)[:8])
         res, summ = run(with_sched(sched, 0.0))
-        errs = [float(np.linalg.norm(o.x - ref[o.rid].cpu().numpy()) / np.linalg.norm(ref[o.rid].cpu().numpy()))
-                for o in res]
+        errs = errors(res)
         iters = [sched[k].get("iters", sched[k].get("refine_sweeps", 0) * sched[k].get("inner_iters", 0))
                  for _, k in reqs]
         cap[name] = {"solves_per_s": round(summ["solves_per_s"], 2), "makespan_s": round(summ["span_s"], 4),
@@ -495,141 +516,8 @@ def serve_leg(torch, n_requests=None, stream=True):
         log("serve closed loop %s: %s" % (name, cap[name]))
     out["closed_loop_at_1e-4"] = cap
     out["mixed_over_fp32"] = round(cap["mixed"]["solves_per_s"] / cap["fp32"]["solves_per_s"], 3)
-    out["reference"] = "FP32 CGLS, 150 iterations, per request"
-    return out
-
-
-def realistic_leg(torch, args, cfg, small, cpu, inputs):
-    """The realistic 192 x 192 x 96 scan: FP32 and mixed operators, the
-    precomposed-line operator, the raster / tensor-PSF / dual-drive variants,
-    the CGLS rate, the paper's own solver, the configured mixed 3 x 20 solve
-    (against x* and against 60 FP32 iterations), and time-to-solve at 1e-4."""
-    import numpy as np
-    from paper_2511_06627_amd import configs
-    from paper_2511_06627_amd.plan import Plan
-    plan, x, b = inputs(cfg, cpu)
-    out = operator_leg(torch, plan, cfg, x, b, args.warmup, args.steps)
-    out["applies_per_s"] = round(1.0 / out["seconds_per_step"], 2)
-    yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
-    xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
-    if args.realistic_only:
-        return out
-
-    # the precomposed-line operator (same map, signal stage as two float32
-    # GEMMs with G = F^T K): A^T A rate and the GEMM times
-    planp = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"))
-    wsp = planp.workspace("op")
-
-    def stepp():
-        planp.forward(x, precision="precomposed", out=yb, ws=wsp)
-        planp.adjoint(yb, precision="precomposed", out=xo, ws=wsp)
-
-    sec, _ = timed_rate(torch, stepp, args.warmup, args.steps)
-    ktp = {k: planp.time_kernel(k, repeats=10, precision="precomposed", x=x, b=b, ws=wsp)
-           for k in ("signal_fwd", "signal_adj")}
-    out["precomposed"] = {"applies_per_s": round(1.0 / sec, 2), "ms_per_step": round(1e3 * sec, 4),
-                          "gemm_flops": 2.0 * cfg.n_lines * cfg.n_u * 2 * cfg.n_bins,
-                          "gemm_fwd_ms": round(ktp["signal_fwd"], 4), "gemm_adj_ms": round(ktp["signal_adj"], 4)}
-    log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * sec, ktp))
-    del planp, wsp
-
-    def rate_of(p, prec, data_shape=None):
-        yy = yb if data_shape is None else torch.empty(data_shape, dtype=torch.complex64, device="cuda")
-        ws = p.workspace("op")
-
-        def st():
-            p.forward(x, precision=prec, out=yy, ws=ws)
-            p.adjoint(yy, precision=prec, out=xo, ws=ws)
-
-        sec, _ = timed_rate(torch, st, args.warmup, args.steps)
-        return {"applies_per_s": round(1.0 / sec, 2), "ms_per_step": round(1e3 * sec, 4)}
-
-    if not args.no_variants:
-        # the same scan under a zig-zag raster (two PSF tables, per-line sweep
-        # direction): drive over a sixth of the fast axis, the focus field carrying
-        # the line across two thirds of it
-        ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
-        planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
-                     cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
-        out["raster"] = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale,
-                         "fp32": rate_of(planr, "fp32"), "mixed": rate_of(planr, "mixed")}
-        log("raster A^T A: %s" % out["raster"])
-        del planr
-        # the tensor PSF coupling each z-row to three rows on either side
-        plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "mixed", "precomposed"), psf_rows=3)
-        out["tensor_psf"] = {"psf_rows": 3, "fp32": rate_of(plant, "fp32"), "mixed": rate_of(plant, "mixed"),
-                             "precomposed": rate_of(plant, "precomposed")}
-        log("tensor PSF (R = 3) A^T A: %s" % out["tensor_psf"])
-        del plant
-        # both drive directions: 36 x 192 z-drive lines after the x-drive ones
-        pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
-        out["dual_drive"] = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale,
-                             "fp32": rate_of(pland, "fp32", pland.data_shape),
-                             "mixed": rate_of(pland, "mixed", pland.data_shape)}
-        log("dual drive A^T A: %s" % out["dual_drive"])
-        del pland
-
-    # CGLS iteration rate of the configured 50-iteration solve
-    swk = plan.workspace("solve")
-    plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, rep = plan.solve(b, cfg.lam, iters=cfg.iters, ws=swk)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
-    out["cgls"] = {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
-                   "status": rep.status}
-    log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
-
-    # the paper's own solver (eq. iters): momentum gradient, finite-difference
-    # T, projection onto x >= 0 every iteration, 150 iterations; tau from
-    # power iteration on the device
-    plan.solve(b, cfg.lam, iters=2, solver="momentum", reg="fd", clamp_every=1, ws=swk, report=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, repm_p = plan.solve(b, cfg.lam, iters=150, solver="momentum", reg="fd", clamp_every=1, ws=swk)
-    torch.cuda.synchronize()
-    out["paper_solver"] = {"iters": 150, "reg": "finite differences", "lambda": cfg.lam,
-                           "seconds_incl_tau": round(time.perf_counter() - t0, 4), "status": repm_p.status}
-
-    # the configured mixed schedule (3 sweeps x 20 inner): against x* (when the
-    # oracle leg ran) and against 60 FP32 iterations
-    m2 = configs.MIXED_192
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xm, repm = plan.solve(b, m2.lam, precision="mixed", refine_sweeps=m2.refine_sweeps, inner_iters=m2.inner_iters,
-                          ws=swk)
-    torch.cuda.synchronize()
-    t_mixed = time.perf_counter() - t0
-    x60, _ = plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk, report=False)
-    torch.cuda.synchronize()
-    t_fp32_60 = time.perf_counter() - t0
-    rec = {"seconds": round(t_mixed, 4), "fp32_60_seconds": round(t_fp32_60, 4), "status": repm.status,
-           "rel_l2_vs_fp32_60": float(torch.linalg.vector_norm(xm - x60) / torch.linalg.vector_norm(x60))}
-    if cpu is not None and "xstar" in cpu:
-        xs = cpu["xstar"]
-        xn = np.linalg.norm(xs)
-        rec["rel_l2_vs_xstar"] = float(np.linalg.norm(xm.cpu().numpy() - xs) / xn)
-        rec["fp32_60_rel_l2_vs_xstar"] = float(np.linalg.norm(x60.cpu().numpy() - xs) / xn)
-    out["mixed"]["solve_3x20"] = rec
-    log("mixed 3x20 solve: %s" % rec)
-    del swk
-
-    tts = {}
-    if cpu is not None and not args.skip_small and "small" in cpu:
-        sm = cpu["small"]
-        psmall = Plan.from_config(small, sm["op_scale"], precisions=("fp32", "mixed"))
-        tts["parity_32cube"] = {p: time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, p)
-                                for p in ("fp32", "mixed")}
-    if cpu is not None and "xstar" in cpu:
-        tts[cfg.name] = {p: time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, p)
-                         for p in ("fp32", "mixed")}
-    out["time_to_solve"] = tts
-    if cpu is not None:
-        out["oracle_small"] = cpu.get("oracle_small")
+    out["reference"] = "FP32 CGLS, %d iterations, per request (converged)" % SERVE_REF_ITERS
+    out["schedule_target"] = SERVE_TARGET
     return out
 
 
@@ -711,7 +599,7 @@ def operator_leg(torch, plan, cfg, x, b, warmup, steps, with_mixed=True):
 # ---------------------------------------------------------------------------
 KERNEL_KEYS = (("sig_fwd_f32", "signal_fwd"), ("sig_adj_f32", "signal_adj"), ("sig_fwd_f16", "signal_fwd_mixed"),
                ("sig_adj_f16", "signal_adj_mixed"), ("proj_fwd_kernel<unsigned int>", "project_mixed"),
-               ("proj_fwd_kernel", "project"), ("proj_adj_bf16", "backproject_mixed"),
+               ("proj_fwd_kernel", "project"), ("proj_adj_f16", "backproject_mixed"),
                ("proj_adj_kernel", "backproject"))
 
 

@@ -128,16 +128,19 @@ typedef struct {
                                     xi_n = a sin(2 pi P n/T) + c_n and v_n = xi' gains
                                     +-S/T.  With S != 0 and nz >= 2 the plan holds two
                                     PSF tables (and two precomposed line matrices) */
-    int32_t psf_rows;            /* R >= 0: z-rows coupled by the tensor PSF on each side
-                                    (Appendix B eq. PSF, xx entry in the xz-plane of the 2D
-                                    FFL model of Sec. 2.2, in-plane gradient of equal
-                                    magnitude on both axes): line (m, k) also sees rows k'
-                                    of angle m with |k - k'| <= R through
-                                    h_xx(du, dz) = L'(r/w)/w du^2/r^2 + L(r/w) dz^2/r^3,
-                                    r = |(du, dz)|, dz = k - k'.  0 = the collinear PSF;
-                                    values above nz - 1 act as nz - 1 (the whole model).
-                                    R > 0 costs 2R + 1 signal passes per application
-                                    (MPI3D_PRECOMPOSED: 2R + 1 GEMMs); with
+    int32_t psf_rows;            /* R >= 0: lines coupled by the tensor PSF on each side
+                                    (Appendix B eq. PSF in the xz-plane of the 2D FFL model
+                                    of Sec. 2.2, in-plane gradient of equal magnitude on both
+                                    axes).  x-drive line (m, k) also sees the z-rows k' of
+                                    angle m with |k - k'| <= min(R, nz - 1) through the xx
+                                    entry h(du, dz) = L'(r/w)/w du^2/r^2 + L(r/w) dz^2/r^3,
+                                    r = |(du, dz)|, dz = k - k'; with drive_axes = 2, z-drive
+                                    line (m, p) also sees the detector columns p' with
+                                    |p - p'| <= min(R, n_u - 1) through the zz entry, the same
+                                    function with the drive axis exchanged (along-drive
+                                    offset xi_z - z_k, transverse offset p - p').  0 = the
+                                    collinear PSF.  Each line offset costs one more signal
+                                    pass (MPI3D_PRECOMPOSED: one more GEMM); with
                                     raster_sweep != 0 it is MPI3D_ENOTSUP */
     int32_t drive_axes;          /* 1 (or 0): the x-drive scan.  2: every angle is also
                                     scanned with the drive and receive coil along z
@@ -146,8 +149,7 @@ typedef struct {
                                     z_k = k - (nz-1)/2, same PSF, time grid and bins.
                                     Its n_angles * n_u lines follow the x-drive lines in
                                     b: line n_angles*nz + m*n_u + p.  Needs nz <= n_u;
-                                    with raster_sweep != 0 or psf_rows > 0 it is
-                                    MPI3D_ENOTSUP */
+                                    with raster_sweep != 0 it is MPI3D_ENOTSUP */
     double drive_amp_z;          /* z-drive amplitude in voxels; 0 = nz/2 */
 } mpi3d_geometry;
 

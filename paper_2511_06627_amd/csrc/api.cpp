@@ -67,6 +67,8 @@ OpWs carve_op(const mpi3d_plan *pl, void *ws)
     w.rowscale = (float *)(b + pl->ws_rowscale);
     w.xb = (uint16_t *)(b + pl->ws_xb);
     w.in16 = (uint16_t *)(b + pl->ws_in16);
+    w.rtb = (uint16_t *)(b + pl->ws_rtb);
+    w.rtsc = (float *)(b + pl->ws_rtsc);
     return w;
 }
 
@@ -77,48 +79,54 @@ int check_prec(const mpi3d_plan *pl, int32_t precision)
     return MPI3D_OK;
 }
 
-static SigArgs sig_args(const mpi3d_plan *pl, bool serve)
+static SigArgs sig_args(const mpi3d_plan *pl, int prec, bool serve)
 {
+    const mpi3d_plan::SigCfg &c = sig_cfg(pl, prec);
     SigArgs a{};
     a.ff = pl->ff; a.fa = pl->fa;
     a.ff16 = pl->ff16; a.fa16 = pl->fa16;
     a.band_scale = pl->band_scale;
     a.nu = pl->nu; a.nup = pl->nup; a.nb2 = pl->nb2; a.nbp2 = pl->nbp2; a.nct = pl->nct;
     a.nchunks = pl->nchunks;
-    a.cps = serve ? pl->serve_cps : pl->cps;
-    a.nsplit = serve ? pl->serve_nsplit : pl->nsplit;
-    a.ngroups = pl->ngroups; a.gct = pl->gct;
+    a.cps = serve ? c.serve_cps : c.cps;
+    a.nsplit = serve ? c.serve_nsplit : c.nsplit;
+    a.ngroups = c.ngroups; a.gct = c.gct; a.pairs = c.pairs;
     return a;
 }
 
-static int nsplit_of(const mpi3d_plan *pl, bool serve) { return serve ? pl->serve_nsplit : pl->nsplit; }
+static int nsplit_of(const mpi3d_plan *pl, int prec, bool serve)
+{
+    const mpi3d_plan::SigCfg &c = sig_cfg(pl, prec);
+    return serve ? c.serve_nsplit : c.nsplit;
+}
+static int rows_per_block(const mpi3d_plan *pl, int prec) { return kRowsPerWave * sig_cfg(pl, prec).pairs; }
 
 // The kernel jobs of one line job: one per line group (trajectory class of a
-// raster, or x- and z-drive lines) and z-row offset of the tensor PSF.  Group
+// raster, or x- and z-drive lines) and line offset of the tensor PSF.  Group
 // g holds the lines of its map (class c: the lines (m, k) with k % n_classes
 // == c; dual drive: the x-drive lines, then the z-drive lines) and its PSF
-// table; offset pass p reads line (m, k + d), d = p - psf_rows, through table
-// |d| and writes its own block of split partial sums, which the reductions
-// add with the others.
-static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJob> &out)
+// tables; offset pass d reads the line d away among its angle's lines (x-drive:
+// z-rows; z-drive: detector columns) through table |d| of the group and writes
+// the block of split partial sums of offset d, which the reductions add with
+// the others.
+static void line_jobs(const LineJob &lj, int prec, bool fwd, bool serve, std::vector<SigJob> &out)
 {
     const mpi3d_plan *pj = lj.pl;
-    const int R = pj->psf_rows;
     const long part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
-    const long pass_stride = (long)(serve ? pj->serve_nsplit : pj->nsplit) * (fwd ? 1 : pj->ngroups) * part_stride;
-    for (int gi = 0; gi < pj->n_line_groups; ++gi)
-        for (int pass = 0; pass < pj->n_passes; ++pass) {
-            const mpi3d_plan::LineGroup &lg = pj->groups[gi];
-            const int d = pass - R;
+    const long pass_stride =
+        (long)nsplit_of(pj, prec, serve) * (fwd ? 1 : sig_cfg(pj, prec).ngroups) * part_stride;
+    for (int gi = 0; gi < pj->n_line_groups; ++gi) {
+        const mpi3d_plan::LineGroup &lg = pj->groups[gi];
+        for (int d = -lg.coup; d <= lg.coup; ++d) {
             SigJob sj{};
             sj.in = lj.in;
             sj.in_stride = lj.in_stride;
             sj.in16 = lj.w->in16;
             sj.in16_stride = pj->in16_cols;
-            sj.part = lj.w->part + pass * pass_stride;
+            sj.part = lj.w->part + (d + pj->pass_r) * pass_stride;
             sj.part_stride = part_stride;
             sj.row_scale = lj.w->rowscale;
-            const size_t ko = (size_t)(lg.table * (R + 1) + (d < 0 ? -d : d)) * pj->k_elems;
+            const size_t ko = (size_t)(lg.table + (d < 0 ? -d : d)) * pj->k_elems;
             sj.kf = pj->kf + ko;
             sj.ka = pj->ka + ko;
             sj.kf16 = pj->kf16 ? pj->kf16 + ko : nullptr;
@@ -129,9 +137,24 @@ static void line_jobs(const LineJob &lj, bool fwd, bool serve, std::vector<SigJo
             sj.map_off = lg.off;
             sj.map_step = lg.step;
             sj.in_dz = d;
-            sj.in_nz = pj->nz;
+            sj.in_nz = lg.cper;
+            sj.in_base = lg.cbase;
             out.push_back(sj);
         }
+    }
+}
+
+static RowPasses row_passes(const mpi3d_plan *pl)
+{
+    RowPasses rp{};
+    rp.npass = pl->n_passes;
+    rp.rows = pl->pass_r;
+    rp.nz = pl->nz;
+    rp.zbase = pl->drive_axes == 2 ? pl->Lx : pl->L;
+    rp.nzc = pl->nu;
+    rp.rx = pl->groups[0].coup;
+    rp.rz = pl->drive_axes == 2 ? pl->groups[1].coup : 0;
+    return rp;
 }
 
 // Mixed signal stage input: per-line scales into w.rowscale and the scaled
@@ -151,7 +174,8 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
 {
     if (n < 1) return MPI3D_EINVAL;
     const mpi3d_plan *pl = jobs[0].pl;
-    SigArgs a = sig_args(pl, serve);
+    SigArgs a = sig_args(pl, prec, serve);
+    const int rpb = rows_per_block(pl, prec);
     int tiles = 0, nj = 0;
     auto flush = [&]() -> int {
         if (nj == 0) return MPI3D_OK;
@@ -171,11 +195,11 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
             TRY(row_scale16(pj, fwd, jobs[j].in, jobs[j].in_stride, *jobs[j].w, st));
         }
         kj.clear();
-        line_jobs(jobs[j], fwd, serve, kj);
+        line_jobs(jobs[j], prec, fwd, serve, kj);
         for (SigJob &sj : kj) {
             if (nj == kMaxJobs) TRYRC(flush());
             sj.tile0 = tiles;
-            tiles += (sj.rows + kRowsPerBlock - 1) / kRowsPerBlock;
+            tiles += (sj.rows + rpb - 1) / rpb;
             a.jobs[nj++] = sj;
         }
     }
@@ -196,9 +220,9 @@ static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
                           double *norm_parts, int *nnorm, hipStream_t st)
 {
     const bool mixed = prec == MPI3D_MIXED;
-    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->n_passes * nsplit_of(pl, serve), pl->L * pl->nbp2, w.part,
+    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->n_passes * nsplit_of(pl, prec, serve), pl->L * pl->nbp2, w.part,
                           mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
-                          norm_parts, nnorm, st, RowPasses{pl->n_passes, pl->psf_rows, pl->nz}));
+                          norm_parts, nnorm, st, row_passes(pl)));
     return MPI3D_OK;
 }
 
@@ -209,9 +233,38 @@ static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
     const bool mixed = prec == MPI3D_MIXED;
     const double scale = pl->op_scale * (mixed ? (double)pl->adj_scale16 : 1.0);
     TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride,
-                                    pl->n_passes * nsplit_of(pl, serve) * pl->ngroups,
+                                    pl->n_passes * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
                                     pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st,
-                                    RowPasses{pl->n_passes, pl->psf_rows, pl->nz}));
+                                    row_passes(pl)));
+    return MPI3D_OK;
+}
+
+// The adjoint's second half after the signal contraction: the split sums
+// reduced to lines, then P^T into xo with the optional epilogue
+// (xo = acc + x_add - lambda x_sub, float64 norm partials).  The mixed
+// operator's lines are fp16 with a power-of-two scale per line (its
+// backprojection's 16-bit gathers); with the dual drive they are reduced in
+// fp32 first so the z-drive lines can be folded in.
+static int lines_to_volume(const mpi3d_plan *pl, int prec, const OpWs &w, bool serve, float *xo, const float *x_sub,
+                           double lambda, double *parts, int *nparts, hipStream_t st, const float *x_add = nullptr)
+{
+    if (prec == MPI3D_MIXED) {
+        const RowPasses rp = row_passes(pl);
+        if (pl->drive_axes == 2) {
+            TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
+            TRY(launch_fold_zlines(pl, w.rt, st));
+            TRY(launch_lines16(pl->Lx, pl->nu, pl->nup, 0, 0, nullptr, nullptr, 1.0, rp, w.rt, w.rtb, w.rtsc, st));
+        } else {
+            TRY(launch_lines16(pl->L, pl->nu, pl->nup,
+                               pl->n_passes * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
+                               pl->L * pl->nup, w.part, w.rowscale, pl->op_scale * (double)pl->adj_scale16, rp,
+                               nullptr, w.rtb, w.rtsc, st));
+        }
+        TRY(launch_backproject16(pl, w.rtb, w.rtsc, xo, x_sub, lambda, parts, nparts, st, x_add));
+        return MPI3D_OK;
+    }
+    TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
+    TRY(launch_backproject(pl, w.rt, xo, x_sub, lambda, parts, nparts, st, x_add));
     return MPI3D_OK;
 }
 
@@ -251,13 +304,13 @@ struct GemmRun {
 
 static void gemm_runs(const mpi3d_plan *pl, bool fwd, std::vector<GemmRun> &runs)
 {
-    const int R = pl->psf_rows;
     for (int gi = 0; gi < pl->n_line_groups; ++gi) {
         const mpi3d_plan::LineGroup &lg = pl->groups[gi];
+        const int R = lg.coup;
         for (int k = 0; k <= 2 * R; ++k) {
             const int d = k == 0 ? 0 : (k <= R ? k : R - k);   // 0, 1..R, -1..-R
             GemmRun r{};
-            r.table = lg.table * (R + 1) + (d < 0 ? -d : d);
+            r.table = lg.table + (d < 0 ? -d : d);
             r.beta = d == 0 ? 0.f : 1.f;
             if (lg.gnz == 0 && d == 0) {        // consecutive lines
                 r.n = lg.rows;
@@ -270,17 +323,19 @@ static void gemm_runs(const mpi3d_plan *pl, bool fwd, std::vector<GemmRun> &runs
                 r.in_step = r.out_step = lg.step;
                 r.batch = pl->M;
                 r.batch_lines = lg.gnz;
-            } else {                            // tensor offset d: row k reads row k + d of its angle
-                // forward: out rows [lo, hi) read rows lo + d ...; adjoint:
-                // out rows k' gather data rows k' - d
+            } else {                            // tensor offset d: line k reads line k + d of its angle
+                // (x-drive: z-rows; z-drive: detector columns).  Forward: out
+                // lines [lo, hi) read lines lo + d ...; adjoint: out lines k'
+                // gather data lines k' - d
+                const int per = lg.cper;
                 const int lo = fwd ? std::max(0, -d) : std::max(0, d);
-                const int hi = fwd ? std::min(pl->nz, pl->nz - d) : std::min(pl->nz, pl->nz + d);
+                const int hi = fwd ? std::min(per, per - d) : std::min(per, per + d);
                 r.n = hi - lo;
-                r.out0 = lo;
-                r.in0 = fwd ? lo + d : lo - d;
+                r.out0 = lg.cbase + lo;
+                r.in0 = lg.cbase + (fwd ? lo + d : lo - d);
                 r.in_step = r.out_step = 1;
                 r.batch = pl->M;
-                r.batch_lines = pl->nz;
+                r.batch_lines = per;
             }
             if (r.n > 0) runs.push_back(r);
         }
@@ -347,9 +402,7 @@ static int apply_adjoint(const mpi3d_plan *pl, int prec, const float *y, float *
     }
     LineJob j{pl, y, pl->nb2, &w};
     TRYRC(sig_adjoint_jobs(prec, &j, 1, false, st));
-    TRYRC(reduce_adjoint(pl, prec, w, false, w.rt, pl->nup, st));
-    TRY(launch_backproject(pl, w.rt, xo, nullptr, 0.0, nullptr, nullptr, st));
-    return MPI3D_OK;
+    return lines_to_volume(pl, prec, w, false, xo, nullptr, 0.0, nullptr, nullptr, st);
 }
 
 // ---- CGLS -------------------------------------------------------------------
@@ -395,8 +448,7 @@ int Cgls::restart_b(bool x_zero, hipStream_t st)
 int Cgls::restart_c(hipStream_t st)
 {
     float *grad = corr ? g0 : s;
-    TRYRC(reduce_adjoint(pl, MPI3D_FP32, w, serve, w.rt, pl->nup, st));
-    TRY(launch_backproject(pl, w.rt, grad, x, lambda, parts_s, &ns, st));
+    TRYRC(lines_to_volume(pl, MPI3D_FP32, w, serve, grad, x, lambda, parts_s, &ns, st));
     TRY(launch_beta(scal, parts_s, ns, 1, started ? 0 : 1, hist, step, st));
     TRY(launch_update_p2(p, grad, pb, pl->nvox, scal, parts_p, &np, 1, st));
     if (corr) {
@@ -429,8 +481,7 @@ int Cgls::iter_b(int prec, hipStream_t st)
 
 int Cgls::iter_c(int prec, hipStream_t st)
 {
-    TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
-    TRY(launch_backproject(pl, w.rt, s, corr ? d : x, lambda, parts_s, &ns, st, corr ? g0 : nullptr));
+    TRYRC(lines_to_volume(pl, prec, w, serve, s, corr ? d : x, lambda, parts_s, &ns, st, corr ? g0 : nullptr));
     TRY(launch_beta(scal, parts_s, ns, 0, 0, hist, step, st));
     TRY(launch_update_p2(p, s, pb, pl->nvox, scal, parts_p, &np, 0, st));
     ++step;
@@ -478,10 +529,9 @@ int power_norm(const mpi3d_plan *pl, const OpWs &w, float *v, float *z, float *y
         rc = apply_forward(pl, MPI3D_FP32, v, y, w, st);
         LineJob j{pl, y, pl->nb2, &w};
         if (rc == MPI3D_OK) rc = sig_adjoint_jobs(MPI3D_FP32, &j, 1, false, st);
-        if (rc == MPI3D_OK) rc = reduce_adjoint(pl, MPI3D_FP32, w, false, w.rt, pl->nup, st);
         int np = 0;
-        if (rc == MPI3D_OK && (launch_backproject(pl, w.rt, z, nullptr, 0.0, parts, &np, st) != hipSuccess ||
-                               launch_norm_record(parts, np, norms, k, st) != hipSuccess ||
+        if (rc == MPI3D_OK) rc = lines_to_volume(pl, MPI3D_FP32, w, false, z, nullptr, 0.0, parts, &np, st);
+        if (rc == MPI3D_OK && (launch_norm_record(parts, np, norms, k, st) != hipSuccess ||
                                launch_scale_by(v, z, pl->nvox, norms, k, st) != hipSuccess))
             rc = MPI3D_EDEVICE;
         if (rc != MPI3D_OK) break;
@@ -587,8 +637,7 @@ static int momentum_solve(const mpi3d_plan *pl, const float *b, float *x, const 
         TRYRC(reduce_forward(pl, MPI3D_FP32, w, false, r, b, nullptr, nullptr, st));
         LineJob ja{pl, r, pl->nb2, &w};
         TRYRC(sig_adjoint_jobs(MPI3D_FP32, &ja, 1, false, st));
-        TRYRC(reduce_adjoint(pl, MPI3D_FP32, w, false, w.rt, pl->nup, st));
-        TRY(launch_backproject(pl, w.rt, g, nullptr, 0.0, nullptr, nullptr, st));
+        TRYRC(lines_to_volume(pl, MPI3D_FP32, w, false, g, nullptr, 0.0, nullptr, nullptr, st));
         // x_{k+1} into x_{k-1}'s buffer, y_{k+1} over g; beta of step k+1
         const float beta = (float)((double)k / (double)(k + 3));
         int np = 0;
@@ -771,17 +820,18 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
     }
     // signal kernels: the first launch of a signal stage (every line, one job
     // per trajectory class and z-row offset, up to the job table's size)
-    SigArgs a = sig_args(pl, false);
+    SigArgs a = sig_args(pl, precision, false);
     {
         const bool fwd = kernel == 2;
         const LineJob lj{pl, fwd ? w.rt : b, fwd ? pl->nup : pl->nb2, &w};
         std::vector<SigJob> kj;
-        line_jobs(lj, fwd, false, kj);
+        line_jobs(lj, precision, fwd, false, kj);
         a.njobs = std::min((int)kj.size(), kMaxJobs);
         a.total_tiles = 0;
+        const int rpb = rows_per_block(pl, precision);
         for (int c = 0; c < a.njobs; ++c) {
             kj[c].tile0 = a.total_tiles;
-            a.total_tiles += (kj[c].rows + kRowsPerBlock - 1) / kRowsPerBlock;
+            a.total_tiles += (kj[c].rows + rpb - 1) / rpb;
             a.jobs[c] = kj[c];
         }
     }
@@ -795,7 +845,10 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         switch (kernel) {
         case 0: err = mixed ? launch_project(pl, nullptr, w.xb, w.rt, st) : launch_project(pl, x, nullptr, w.rt, st);
             break;
-        case 1: err = launch_backproject(pl, w.rt, x, nullptr, 0.0, nullptr, nullptr, st); break;
+        case 1:
+            err = mixed ? launch_backproject16(pl, w.rtb, w.rtsc, x, nullptr, 0.0, nullptr, nullptr, st)
+                        : launch_backproject(pl, w.rt, x, nullptr, 0.0, nullptr, nullptr, st);
+            break;
         case 2:
             if (precision == MPI3D_PRECOMPOSED)
                 err = gemm_signal_fwd(pl, w.rt, pl->nup, w.part, st) == MPI3D_OK ? hipSuccess : hipErrorUnknown;

@@ -20,9 +20,10 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks)
     return xcd * per + min(xcd, rem) + slot;
 }
 
-// Where a signal-kernel block and wave sit: the block covers kRowsPerBlock
-// lines (a tile) of one job, for one time split and one column group; wave
-// w is half w & 1 of pair w >> 1, which owns kRowsPerWave lines from row0.
+// Where a signal-kernel block and wave sit: the block covers a.pairs *
+// kRowsPerWave lines (a tile) of one job, for one time split and one column
+// group; wave w is half w & 1 of pair w >> 1, which owns kRowsPerWave lines
+// from row0.
 struct BlockPos {
     int job, row0, split, group, half, pair;
 };
@@ -42,16 +43,17 @@ __device__ __forceinline__ BlockPos locate(const SigArgs &a)
     const int w = threadIdx.x >> 6;
     bp.pair = w >> 1;
     bp.half = w & 1;
-    bp.row0 = (tile - a.jobs[jb].tile0) * kRowsPerBlock + bp.pair * kRowsPerWave;
+    bp.row0 = (tile - a.jobs[jb].tile0) * (a.pairs * kRowsPerWave) + bp.pair * kRowsPerWave;
     return bp;
 }
 
 // Swap partial time tiles within a pair: write mine, barrier, read the
 // partner's, and return lo + hi (the same operand order on both waves).  xs
-// holds two parities x kWaves pairs x 2 halves x 16 x 64 floats.
+// holds two parities x PAIRS pairs x 2 halves x 16 x 64 floats.
+template <int PAIRS>
 __device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
 {
-    float *slot = xs + ((parity * kWaves + pair) * 2) * 16 * 64;
+    float *slot = xs + ((parity * PAIRS + pair) * 2) * 16 * 64;
     float *own = slot + half * 16 * 64;
     const float *other = slot + (1 - half) * 16 * 64;
 #pragma unroll

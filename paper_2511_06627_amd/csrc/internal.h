@@ -19,9 +19,13 @@ namespace mpi3d {
 //   the time dimension).  Columns of the band table come in tiles of 32.
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerWave = 32;                      // lines per wave pair
-constexpr int kWaves = 4;                             // wave pairs per block
+constexpr int kWaves = 4;                             // wave pairs per block (two waves per SIMD)
 constexpr int kRowsPerBlock = kRowsPerWave * kWaves;
 constexpr int kSigThreads = 2 * 64 * kWaves;          // 8 waves
+// Wide blocks: 2 wave pairs (one wave per SIMD, so each wave may hold up to
+// 512 registers) with up to 22 column tiles per pair, for band tables that
+// would otherwise need two column groups and repeat the first contraction.
+constexpr int kWidePairs = 2;
 constexpr int kChunk = 32;
 constexpr int kColTile = 32;
 constexpr int kMaxJobs = 16;
@@ -56,17 +60,20 @@ struct SigJob {
     // Job row r is line (r / map_per) * map_nz + map_off + map_step * (r % map_per)
     // of the buffers above (identity: map_per >= rows, map_off 0, map_step 1).
     int map_per, map_nz, map_off, map_step;
-    // Row coupling (tensor PSF): the input of line l = m * in_nz + k is line
-    // l + in_dz, or zero when row k + in_dz is outside [0, in_nz); 0 = none.
+    // Line coupling (tensor PSF): the input of line l = in_base + m * in_nz + k
+    // is line l + in_dz, or zero when k + in_dz is outside [0, in_nz) (x-drive
+    // lines couple across the z-rows of their angle, z-drive lines across its
+    // detector columns); in_dz = 0: none.
     int in_dz, in_nz;
+    long in_base;
 };
 
-// Input line of job row r's line l (or -1 when the shifted row is outside
-// its angle's rows).
+// Input line of job row r's line l (or -1 when the shifted line is outside
+// its angle's lines).
 __host__ __device__ inline long job_input_line(const SigJob &j, long l)
 {
     if (j.in_dz == 0) return l;
-    const int k = (int)(l % j.in_nz) + j.in_dz;
+    const int k = (int)((l - j.in_base) % j.in_nz) + j.in_dz;
     return (k >= 0 && k < j.in_nz) ? l + j.in_dz : -1;
 }
 
@@ -83,6 +90,7 @@ struct SigArgs {
     const float *band_scale;                      // [nbp2] adjoint per-column scale (mixed)
     int nu, nup, nb2, nbp2, nct;                  // sizes (nup, nbp2 padded to 32)
     int nchunks, cps, nsplit, ngroups, gct;       // chunking and column groups
+    int pairs;                                    // wave pairs per block (kWaves or kWidePairs)
     int total_tiles;
     int njobs;
     SigJob jobs[kMaxJobs];
@@ -135,9 +143,15 @@ struct mpi3d_plan {
     int drive_axes;
     double a_z;     // z-drive amplitude
     long nvox;
-    // signal kernel configuration
-    int nchunks, cps, nsplit, ngroups, gct;
-    int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
+    // signal kernel configuration, per precision: sc[0] FP32 (and the
+    // precomposed variant's unused slot), sc[1] MIXED
+    struct SigCfg {
+        int pairs;                 // wave pairs per block
+        int ngroups, gct;          // column groups per line tile, 32-wide column tiles per group
+        int cps, nsplit;           // time chunks per split, splits
+        int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
+    } sc[2];
+    int nchunks;
     uint64_t line_key;             // equal keys <=> identical line tables
     // projection configuration
     mpi3d::FwdConfig fwd32, fwd16;  // forward projection, fp32 and bf16 gathers
@@ -149,19 +163,26 @@ struct mpi3d_plan {
     float2 *cs;
     float *ax, *ay;
     // PSF tables kf, ka (kf16, ka16): n_ktab consecutive copies of k_elems
-    // elements, one per trajectory class (two under a raster) or per z-row
-    // offset 0..psf_rows (tensor PSF)
+    // elements: one per trajectory class (two under a raster), or per line
+    // offset 0..R of each line group under the tensor PSF
     float *kf, *ff, *fa, *ka;
     __half *kf16, *ff16, *fa16, *ka16;
     int n_classes, psf_rows, n_ktab;
-    // Line groups of one signal stage, each with its own PSF table: the
+    // Line groups of one signal stage, each with its own PSF tables: the
     // trajectory classes of a raster, or the x- and z-drive lines.  Group g's
-    // job row r is line (r / per) * gnz + off + step * (r % per).
+    // job row r is line (r / per) * gnz + off + step * (r % per).  Under the
+    // tensor PSF a group's lines couple to the lines within `coup` of them
+    // among the `cper` lines of their angle (x-drive: the z-rows; z-drive: the
+    // detector columns), the group's lines starting at `cbase`; offset d uses
+    // table `table + |d|`.
     struct LineGroup {
         int rows, per, gnz, off, step, table;
+        int coup, cper;
+        long cbase;
     } groups[2];
     int n_line_groups;
-    int n_passes;                 // signal passes per application: 2 psf_rows + 1
+    int pass_r;                   // largest coupling range of the groups
+    int n_passes;                 // blocks of split partial sums: 2 pass_r + 1 line offsets
     size_t k_elems;
     double raster_sweep;
     float *col_scale;     // [nbp2] mixed forward output scale per column
@@ -171,7 +192,7 @@ struct mpi3d_plan {
     size_t gt_elems = 0;  // floats per line matrix
     rocblas_handle blas = nullptr;   // precomposed: GEMM handle
     // operator workspace layout (bytes from ws base)
-    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, op_ws_bytes;
+    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, ws_rtb, ws_rtsc, op_ws_bytes;
     int in16_cols;        // halves per fp16 operand line: max(nup, nbp2)
     // solver workspace layout
     size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, sw_v, solve_ws_bytes;
@@ -190,10 +211,18 @@ hipError_t launch_project(const mpi3d_plan *pl, const float *x, const uint16_t *
 hipError_t launch_backproject(const mpi3d_plan *pl, float *rt, float *xo, const float *x_sub,
                               double lambda, double *norm_parts, int *nparts, hipStream_t st,
                               const float *x_add = nullptr);
+// The mixed operator's backprojection: gathers from fp16 lines rtb [Lx][nup]
+// with per-line inverse scales rtsc [Lx] (two z-slices per 32-bit LDS word);
+// weights and sums in fp32; same epilogue.
+hipError_t launch_backproject16(const mpi3d_plan *pl, const uint16_t *rtb, const float *rtsc, float *xo,
+                                const float *x_sub, double lambda, double *norm_parts, int *nparts, hipStream_t st,
+                                const float *x_add = nullptr);
+// Dual drive: fold the z-drive lines of the fp32 lines rt into the x-drive lines.
+hipError_t launch_fold_zlines(const mpi3d_plan *pl, float *rt, hipStream_t st);
 hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
-int sig_fwd_supported(int nup, int gct, int precision);
-int sig_adj_supported(int nup, int gct, int precision);
+int sig_fwd_supported(int nup, int gct, int precision, int pairs);
+int sig_adj_supported(int nup, int gct, int precision, int pairs);
 
 // Reductions and vector kernels (vec.hip).  The split reductions sum nparts
 // partial blocks; rp describes the tensor PSF's offset passes among them
@@ -201,7 +230,9 @@ int sig_adj_supported(int nup, int gct, int precision);
 // row + p - rows of the same angle's nz), which the mixed path's per-line
 // scales need (npass = 1: no coupling).
 struct RowPasses {
-    int npass, rows, nz;
+    int npass, rows, nz;   // passes (2 rows + 1), x-drive lines per angle
+    long zbase;            // first z-drive line (L when there are none)
+    int nzc, rx, rz;       // z-drive lines per angle; coupling ranges of x- and z-drive lines
 };
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
                              const float *row_scale, const float *col_scale, double scale, const float *b_sub,
@@ -209,6 +240,12 @@ hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part
 hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_stride, int nparts, long part_stride,
                                        const float *part, const float *row_scale, double scale, float *out,
                                        hipStream_t st, RowPasses rp);
+// The mixed adjoint's lines [rows][nup] as fp16 with a power-of-two scale per
+// line (out16 holds v * s, inv_scale[row] = 1/s), formed from the split sums
+// as the reduction above does, or from fp32 lines (lines_in, stride nup).
+hipError_t launch_lines16(long rows, int nu, int nup, int nparts, long part_stride, const float *part,
+                          const float *row_scale, double scale, RowPasses rp, const float *lines_in, uint16_t *out16,
+                          float *inv_scale, hipStream_t st);
 hipError_t launch_to_bf16(long n, const float *x, uint16_t *xb, hipStream_t st);
 // Per-line power-of-two scales of the fp16 contractions; with out16, also
 // the scaled lines rounded to fp16 ([rows][out16_stride] halves, columns
@@ -255,6 +292,11 @@ hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int
 // ---------------------------------------------------------------------------
 namespace mpi3d {
 
+inline const mpi3d_plan::SigCfg &sig_cfg(const mpi3d_plan *pl, int prec)
+{
+    return pl->sc[prec == MPI3D_MIXED ? 1 : 0];
+}
+
 struct OpWs {
     float *rt;        // projections [L][nup]
     float *part;      // split partial sums
@@ -262,6 +304,8 @@ struct OpWs {
     float *rowscale;  // [L] per-line scales of the fp16 path
     uint16_t *xb;     // bf16 copy of a volume (mixed path)
     uint16_t *in16;   // [L][in16_cols] fp16 operand lines of the mixed signal stage
+    uint16_t *rtb;    // [L][nup] fp16 lines of the mixed adjoint (its backprojection gathers)
+    float *rtsc;      // [L] their per-line inverse scales
 };
 OpWs carve_op(const mpi3d_plan *pl, void *ws);
 int check_prec(const mpi3d_plan *pl, int32_t precision);
@@ -318,6 +362,7 @@ struct Cgls {
     int iterate(int prec, hipStream_t st);
 };
 int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o);
+
 int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out);
 // ||A||_2 with the plan's current scale, by power iteration in caller buffers:
 // v, z volumes, y data, norms (max_iters doubles), parts (max_parts doubles),

@@ -99,31 +99,65 @@ int ray_count(int nx, int ny)
     return n;
 }
 
-// Choose the T-split: (line tiles x splits x groups) blocks; the signal
-// kernels need about 250 VGPRs, so two waves per SIMD (four wave pairs) are
-// resident per CU.  Cost in units of one block's time per chunk: rounds of blocks times
-// chunks per block, plus each split's partial sums written and read back by
-// the reduction (measured on MI355X at about a tenth of a chunk per split for
-// the 192 x 192 x 96 scan).
-void choose_split(mpi3d_plan *pl)
+// Column groups of one precision's signal kernels for a band table of nct0
+// 32-wide column tiles.  A pair covers 2 GH tiles of one group.  Narrow
+// blocks (4 pairs, two waves per SIMD) hold at most 14 tiles per pair; wide
+// blocks (2 pairs, one wave per SIMD: FP32 only) up to 22, so a table of 15 to
+// 22 tiles needs one group instead of two -- each extra group repeats the
+// first contraction (the time signal) for its lines.  Tables are zero-padded
+// to the group width, so the kernels need no per-tile guards.
+void column_groups(int nct0, bool fp32, mpi3d_plan::SigCfg &c)
 {
-    const int slots = 256 * 4 / kWaves;
-    long tiles = (pl->L + kRowsPerBlock - 1) / kRowsPerBlock;
+    static const int widths[] = {6, 8, 12, 14};
+    if (fp32 && nct0 > 14 && nct0 <= 22) {
+        c.pairs = kWidePairs;
+        c.ngroups = 1;
+        c.gct = (nct0 + 1) / 2 * 2;
+        return;
+    }
+    c.pairs = kWaves;
+    c.ngroups = (nct0 + 13) / 14;
+    const int want = (nct0 + c.ngroups - 1) / c.ngroups;
+    c.gct = 0;
+    for (int wdt : widths)
+        if (!c.gct && wdt >= want) c.gct = wdt;
+}
+
+// Choose the T-split of one precision: (line tiles x splits x groups) blocks,
+// one block resident per CU (narrow blocks need about 250 VGPRs a wave at two
+// waves per SIMD, wide ones more than 256 at one).  Cost in seconds: rounds of
+// blocks times chunks per block times one block's time per chunk, at the
+// per-CU MFMA rate measured on MI355X (FP32 about 4.3e11 flop/s, fp16 about
+// 2.3e12), plus each split's partial sums written and read back by the
+// reduction at about 5 TB/s.
+void choose_split(const mpi3d_plan *pl, bool fp32, mpi3d_plan::SigCfg &c)
+{
+    const int slots = 256;
+    const int rows = kRowsPerWave * c.pairs;
+    const long tiles = (pl->L + rows - 1) / rows;
+    const double rate = fp32 ? 4.3e11 : 2.3e12;
+    const double t_chunk = (double)rows * kChunk * 2.0 * (pl->nup + kColTile * c.gct) / rate;
+    const double split_bytes = 8.0 * pl->n_passes * pl->L * std::max<double>(pl->nbp2, (double)c.ngroups * pl->nup);
     int best_s = 1;
     double best = 1e30;
     for (int s = 1; s <= pl->nchunks; ++s) {
         int cps = (pl->nchunks + s - 1) / s;
         int used = (pl->nchunks + cps - 1) / cps;  // splits actually non-empty
-        long blocks = tiles * used * pl->ngroups;
+        long blocks = tiles * used * c.ngroups;
         long rounds = (blocks + slots - 1) / slots;
-        double cost = (double)rounds * cps + 0.1 * used;
-        if (cost < best - 1e-9) {
+        double cost = (double)rounds * cps * t_chunk + used * split_bytes / 5e12;
+        if (cost < best * (1.0 - 1e-9)) {
             best = cost;
             best_s = used;
         }
     }
-    pl->cps = (pl->nchunks + best_s - 1) / best_s;
-    pl->nsplit = (pl->nchunks + pl->cps - 1) / pl->cps;
+    c.cps = (pl->nchunks + best_s - 1) / best_s;
+    c.nsplit = (pl->nchunks + c.cps - 1) / c.cps;
+    // Serving launches merge the lines of several requests, so their time
+    // split must not depend on the line count: a fixed split per line class.
+    c.serve_nsplit = std::min(pl->nchunks, 16);
+    c.serve_cps = (pl->nchunks + c.serve_nsplit - 1) / c.serve_nsplit;
+    c.serve_nsplit = (pl->nchunks + c.serve_cps - 1) / c.serve_cps;
 }
 
 template <class T>
@@ -165,16 +199,18 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     if (g->harm_lo < 1 || g->harm_hi < g->harm_lo || g->half_band < 0) return MPI3D_EINVAL;
     int precisions = g->precisions ? g->precisions : (1 << MPI3D_FP32);
     if (precisions & ~((1 << MPI3D_FP32) | (1 << MPI3D_MIXED) | (1 << MPI3D_PRECOMPOSED))) return MPI3D_EINVAL;
-    // tensor PSF row coupling: every precision, without a raster
+    // tensor PSF line coupling: every precision, without a raster
     if (g->psf_rows < 0) return MPI3D_EINVAL;
     const int psf_rows = std::min(g->psf_rows, g->nz - 1);
     if (psf_rows > 0 && n_classes > 1) return MPI3D_ENOTSUP;
     // dual drive: z-drive lines across the z-rows, as many entries as the
-    // x-drive lines hold (nz <= n_u), collinear only
+    // x-drive lines hold (nz <= n_u); under the tensor PSF they couple across
+    // the detector columns of their angle
     const int drive_axes = g->drive_axes == 2 ? 2 : 1;
     if (g->drive_axes < 0 || g->drive_axes > 2 || !(g->drive_amp_z >= 0)) return MPI3D_EINVAL;
-    if (drive_axes == 2 && (g->nz > nu || n_classes > 1 || psf_rows > 0)) return MPI3D_ENOTSUP;
-    const int n_ktab = drive_axes == 2 ? 2 : n_classes * (psf_rows + 1);
+    if (drive_axes == 2 && (g->nz > nu || n_classes > 1)) return MPI3D_ENOTSUP;
+    const int psf_cols = drive_axes == 2 && g->psf_rows > 0 ? std::min(g->psf_rows, nu - 1) : 0;
+    const int n_ktab = drive_axes == 2 ? (psf_rows + 1) + (psf_cols + 1) : n_classes * (psf_rows + 1);
 
     // kept bins, validated
     std::vector<long> bins;
@@ -206,7 +242,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->n_classes = n_classes;
     pl->psf_rows = psf_rows;
     pl->n_ktab = n_ktab;
-    pl->n_passes = 2 * psf_rows + 1;
+    pl->pass_r = std::max(psf_rows, psf_cols);
+    pl->n_passes = 2 * pl->pass_r + 1;
     pl->raster_sweep = g->raster_sweep;
     pl->nup = round_up(nu, 64);
     pl->ntp = round_up(g->n_t, kChunk);
@@ -218,51 +255,46 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->Lx = (long)pl->M * pl->nz;
     pl->Lz = drive_axes == 2 ? (long)pl->M * nu : 0;
     pl->L = pl->Lx + pl->Lz;
-    // line groups of a signal stage (each with its own PSF table)
+    // line groups of a signal stage (each with its own PSF tables)
     if (n_classes > 1) {
         pl->n_line_groups = n_classes;
         for (int c = 0; c < n_classes; ++c) {
             const int per = (pl->nz - c + n_classes - 1) / n_classes;
-            pl->groups[c] = {pl->M * per, per, pl->nz, c, n_classes, c};
+            pl->groups[c] = {pl->M * per, per, pl->nz, c, n_classes, c, 0, pl->nz, 0};
         }
     } else if (drive_axes == 2) {
         pl->n_line_groups = 2;
-        pl->groups[0] = {(int)pl->Lx, (int)pl->Lx, 0, 0, 1, 0};
-        pl->groups[1] = {(int)pl->Lz, (int)pl->Lz, 0, (int)pl->Lx, 1, 1};
+        pl->groups[0] = {(int)pl->Lx, (int)pl->Lx, 0, 0, 1, 0, psf_rows, pl->nz, 0};
+        pl->groups[1] = {(int)pl->Lz, (int)pl->Lz, 0, (int)pl->Lx, 1, psf_rows + 1, psf_cols, nu, pl->Lx};
     } else {
         pl->n_line_groups = 1;
-        pl->groups[0] = {(int)pl->L, (int)std::max<long>(1, pl->L), 0, 0, 1, 0};
+        pl->groups[0] = {(int)pl->L, (int)std::max<long>(1, pl->L), 0, 0, 1, 0, psf_rows, pl->nz, 0};
     }
     pl->nvox = (long)pl->nx * pl->ny * pl->nz;
     pl->nchunks = pl->ntp / kChunk;
 
-    // Column groups: as many 32-wide column tiles per block as registers
-    // allow.  The tile count per group is one of the compiled widths, and the
-    // band tables are zero-padded so every group is full (no per-tile guards
-    // in the kernels).
+    // Column groups and time splits per precision; the band tables hold the
+    // larger of the two paddings.
     {
-        static const int widths[] = {6, 8, 12, 14};
-        int gmax = 14;
-        pl->ngroups = (pl->nct + gmax - 1) / gmax;
-        int want = (pl->nct + pl->ngroups - 1) / pl->ngroups;
-        pl->gct = 0;
-        for (int wdt : widths)
-            if (!pl->gct && wdt >= want) pl->gct = wdt;
-        pl->nct = pl->ngroups * pl->gct;
+        const int nct0 = pl->nct;
+        column_groups(nct0, true, pl->sc[0]);
+        column_groups(nct0, false, pl->sc[1]);
+        pl->nct = pl->sc[0].ngroups * pl->sc[0].gct;
+        if (precisions & (1 << MPI3D_MIXED)) pl->nct = std::max(pl->nct, pl->sc[1].ngroups * pl->sc[1].gct);
         pl->nbp2 = pl->nct * kColTile;
     }
-    if (!sig_fwd_supported(pl->nup, pl->gct, MPI3D_FP32) || !sig_adj_supported(pl->nup, pl->gct, MPI3D_FP32) ||
-        ((precisions & (1 << MPI3D_MIXED)) &&
-         (!sig_fwd_supported(pl->nup, pl->gct, MPI3D_MIXED) || !sig_adj_supported(pl->nup, pl->gct, MPI3D_MIXED)))) {
-        delete pl;
-        return MPI3D_ENOTSUP;
+    {
+        const mpi3d_plan::SigCfg &c0 = pl->sc[0], &c1 = pl->sc[1];
+        if (!sig_fwd_supported(pl->nup, c0.gct, MPI3D_FP32, c0.pairs) ||
+            !sig_adj_supported(pl->nup, c0.gct, MPI3D_FP32, c0.pairs) ||
+            ((precisions & (1 << MPI3D_MIXED)) && (!sig_fwd_supported(pl->nup, c1.gct, MPI3D_MIXED, c1.pairs) ||
+                                                   !sig_adj_supported(pl->nup, c1.gct, MPI3D_MIXED, c1.pairs)))) {
+            delete pl;
+            return MPI3D_ENOTSUP;
+        }
     }
-    choose_split(pl);
-    // Serving launches merge the lines of several requests, so their time
-    // split must not depend on the line count: a fixed split per line class.
-    pl->serve_nsplit = std::min(pl->nchunks, 16);
-    pl->serve_cps = (pl->nchunks + pl->serve_nsplit - 1) / pl->serve_nsplit;
-    pl->serve_nsplit = (pl->nchunks + pl->serve_cps - 1) / pl->serve_cps;
+    choose_split(pl, true, pl->sc[0]);
+    choose_split(pl, false, pl->sc[1]);
 
     // projection configuration
     {
@@ -338,20 +370,22 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     }
 
     // PSF kernel K[n][p] of every table (n < T, p < NU; zero padding
-    // elsewhere).  Table t = c (R + 1) + d: trajectory class c, class 1 being
-    // the raster's backward sweep, xi_n = a sin(phi_n) + dir S (n/T - 1/2),
-    // v_n = a phi' cos(phi_n) + dir S/T; and z-row offset d of the tensor PSF,
-    // d = 0 being the collinear L'(du/w)/w.
+    // elsewhere).  Line group g's tables are table_g + d, d = 0..coup_g: for
+    // trajectory class c (class 1 being the raster's backward sweep,
+    // xi_n = a sin(phi_n) + dir S (n/T - 1/2), v_n = a phi' cos(phi_n) + dir S/T)
+    // and line offset d of the tensor PSF, d = 0 being the collinear
+    // L'(du/w)/w.  The z-drive group's tables use amplitude a_z and the
+    // centred z-rows as samples (zero beyond nz); its offsets are detector
+    // columns, the tensor entry's transverse offset.
     const size_t KE = (size_t)TP * NUP;
     pl->k_elems = KE;
     std::vector<double> K(KE * n_ktab, 0.0);
     {
         const double om = 2.0 * kPi * pl->P / T;
         for (int tb = 0; tb < n_ktab; ++tb) {
-            // the z-drive table (dual drive): amplitude a_z, samples at the
-            // centred z-rows, zero beyond nz
-            const bool zt = drive_axes == 2 && tb == 1;
-            const int cl = zt ? 0 : tb / (psf_rows + 1), d = zt ? 0 : tb % (psf_rows + 1);
+            const bool zt = drive_axes == 2 && tb > psf_rows;
+            const int cl = zt ? 0 : tb / (psf_rows + 1);
+            const int d = zt ? tb - (psf_rows + 1) : tb % (psf_rows + 1);
             const double dir = cl == 0 ? 1.0 : -1.0, S = pl->raster_sweep;
             const double amp = zt ? pl->a_z : pl->a, centre = zt ? 0.5 * (pl->nz - 1) : cu;
             const int npts = zt ? pl->nz : NU;
@@ -610,15 +644,19 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     {
         size_t o = 0;
         auto put = [&](size_t bytes) { o = align256(o); size_t r = o; o += bytes; return r; };
-        long parts_rows = std::max<long>(pl->nbp2, pl->nup);
         pl->ws_rt = put(sizeof(float) * pl->L * pl->nup);
-        pl->ws_part = put(sizeof(float) * (size_t)pl->n_passes * std::max(pl->nsplit, pl->serve_nsplit) *
-                          pl->ngroups * pl->L * parts_rows);
+        size_t parts = 0;   // split partial sums: forward [splits][L][nbp2], adjoint [splits][groups][L][nup]
+        for (const mpi3d_plan::SigCfg &c : pl->sc)
+            parts = std::max(parts, (size_t)std::max(c.nsplit, c.serve_nsplit) *
+                                        std::max<size_t>(pl->nbp2, (size_t)c.ngroups * pl->nup));
+        pl->ws_part = put(sizeof(float) * (size_t)pl->n_passes * pl->L * parts);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
         pl->ws_rowscale = put(sizeof(float) * pl->L);
         pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
         pl->in16_cols = std::max(pl->nup, pl->nbp2);
         pl->ws_in16 = put(mixed ? sizeof(uint16_t) * pl->L * pl->in16_cols : 0);
+        pl->ws_rtb = put(mixed ? sizeof(uint16_t) * pl->L * pl->nup : 0);
+        pl->ws_rtsc = put(mixed ? sizeof(float) * pl->L : 0);
         pl->op_ws_bytes = align256(o);
     }
     {
@@ -644,8 +682,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             const unsigned char *c = (const unsigned char *)p;
             for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
         };
-        int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2, pl->ngroups,
-                      pl->gct, precisions, n_classes, psf_rows, drive_axes, drive_axes == 2 ? pl->nz : 0};
+        int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2,
+                      pl->sc[0].pairs, pl->sc[0].ngroups, pl->sc[0].gct, pl->sc[1].pairs, pl->sc[1].ngroups,
+                      pl->sc[1].gct, precisions, n_classes, psf_rows, drive_axes, drive_axes == 2 ? pl->nz : 0};
         double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep, drive_axes == 2 ? pl->a_z : 0.0};
         mix(ints, sizeof(ints));
         mix(dbl, sizeof(dbl));

@@ -345,6 +345,16 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, const
 constexpr int kTile = 16;
 constexpr int kPW = 32;     // staged rays per angle per tile
 
+// The fp16 values in the low and high halves of a 32-bit word, as fp32.
+__device__ __forceinline__ float half_lo(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__device__ __forceinline__ float half_hi(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
 __device__ __forceinline__ float hat(float t) { return fmaxf(0.f, 1.f - fabsf(t)); }
 
 // First staged detector index of angle (c, s) for the tile whose voxel-centre
@@ -361,13 +371,23 @@ __device__ __forceinline__ int tile_p_lo(float c, float s, float X0, float Y0, f
 // One block: a 16 x 16 voxel tile times KZ slices.  Angles are taken in
 // chunks of a.adj_chunk: all lines a chunk needs (per angle KZ lines x 32
 // rays) are staged in LDS in one pass, then every voxel accumulates the
-// chunk's angles without further barriers.
-template <int KZ>
-__global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride)
+// chunk's angles without further barriers.  H: the lines are fp16 with a
+// power-of-two scale per line (the mixed operator's gathers); a staged 32-bit
+// word holds the values of two consecutive z-slices, so one LDS read serves
+// both, and each line's inverse scale multiplies its three-sample sum.
+// Weights and sums are fp32.
+template <int KZ, bool H>
+__device__ __forceinline__ void adj_body(const ProjArgs &a, const uint16_t *__restrict__ rtb,
+                                         const float *__restrict__ rtsc, int in_stride)
 {
-    extern __shared__ __align__(16) float gs[];   // [chunk][KZ][kPW], then p_lo per angle
+    // LDS: staged lines [chunk][KZ][kPW] floats, or [chunk][KZ/2][kPW] words
+    // and the lines' inverse scales [chunk][KZ]; then p_lo per angle
+    extern __shared__ __align__(16) float gs[];
     __shared__ double red[256 / 64];
-    int *plo = reinterpret_cast<int *>(gs + (size_t)a.adj_chunk * KZ * kPW);
+    constexpr int KW = H ? KZ / 2 : KZ;           // staged rows per angle
+    uint32_t *gw = reinterpret_cast<uint32_t *>(gs);
+    float *isc = gs + (size_t)a.adj_chunk * KW * kPW;
+    int *plo = reinterpret_cast<int *>(isc + (H ? (size_t)a.adj_chunk * KZ : 0));
     const int nb = gridDim.x;
     const int lb = xcd_logical(blockIdx.x, nb);
     const int zg = lb / (a.tiles_x * a.tiles_y);
@@ -392,15 +412,30 @@ __global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride
             const float2 csv = a.cs[mb + tid];
             plo[tid] = tile_p_lo(csv.x, csv.y, X0, Y0, a.half_nu);
         }
+        if constexpr (H) {
+            for (int idx = tid; idx < mc * KZ; idx += 256) {
+                const int mm = idx / KZ, kk = idx - mm * KZ;
+                isc[idx] = kk < kn ? rtsc[(size_t)(mb + mm) * a.nz + k0 + kk] : 0.f;
+            }
+        }
         __syncthreads();
-        for (int idx = tid; idx < mc * KZ * kPW; idx += 256) {
-            const int mm = idx / (KZ * kPW);
-            const int rem = idx - mm * (KZ * kPW);
-            const int kk = rem / kPW, pp = rem % kPW;
+        for (int idx = tid; idx < mc * KW * kPW; idx += 256) {
+            const int mm = idx / (KW * kPW);
+            const int rem = idx - mm * (KW * kPW);
+            const int kw = rem / kPW, pp = rem % kPW;
             const int p = plo[mm] + pp;
-            float v = 0.f;
-            if (kk < kn && p >= 0 && p < a.nu) v = a.rt_in[((size_t)(mb + mm) * a.nz + k0 + kk) * in_stride + p];
-            gs[idx] = v;
+            const bool pin = p >= 0 && p < a.nu;
+            if constexpr (H) {
+                const int kk = 2 * kw;
+                const size_t base = ((size_t)(mb + mm) * a.nz + k0 + kk) * in_stride + p;
+                const uint32_t lo = (kk < kn && pin) ? (uint32_t)rtb[base] : 0u;
+                const uint32_t hi = (kk + 1 < kn && pin) ? (uint32_t)rtb[base + in_stride] : 0u;
+                gw[idx] = lo | (hi << 16);
+            } else {
+                float v = 0.f;
+                if (kw < kn && pin) v = a.rt_in[((size_t)(mb + mm) * a.nz + k0 + kw) * in_stride + p];
+                gs[idx] = v;
+            }
         }
         __syncthreads();
         if (!valid) continue;
@@ -432,11 +467,25 @@ __global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride
                 w[dp] = pok ? wp : 0.f;
             }
             const int off = min(max((int)pc - 1 - plo[mm], 0), kPW - 3);  // in range by construction
-            const float *g0 = gs + (size_t)mm * KZ * kPW + off;
+            if constexpr (H) {
+                const uint32_t *g0 = gw + (size_t)mm * KW * kPW + off;
+                const float *sc = isc + (size_t)mm * KZ;
 #pragma unroll
-            for (int kk = 0; kk < KZ; ++kk) {
-                const float *gk = g0 + kk * kPW;
-                acc[kk] = fmaf(w[0], gk[0], fmaf(w[1], gk[1], fmaf(w[2], gk[2], acc[kk])));
+                for (int kw = 0; kw < KW; ++kw) {
+                    const uint32_t *gk = g0 + kw * kPW;
+                    const uint32_t v0 = gk[0], v1 = gk[1], v2 = gk[2];
+                    const float lo = fmaf(w[0], half_lo(v0), fmaf(w[1], half_lo(v1), w[2] * half_lo(v2)));
+                    const float hi = fmaf(w[0], half_hi(v0), fmaf(w[1], half_hi(v1), w[2] * half_hi(v2)));
+                    acc[2 * kw] = fmaf(lo, sc[2 * kw], acc[2 * kw]);
+                    acc[2 * kw + 1] = fmaf(hi, sc[2 * kw + 1], acc[2 * kw + 1]);
+                }
+            } else {
+                const float *g0 = gs + (size_t)mm * KZ * kPW + off;
+#pragma unroll
+                for (int kk = 0; kk < KZ; ++kk) {
+                    const float *gk = g0 + kk * kPW;
+                    acc[kk] = fmaf(w[0], gk[0], fmaf(w[1], gk[1], fmaf(w[2], gk[2], acc[kk])));
+                }
             }
         }
     }
@@ -466,6 +515,18 @@ __global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride
         __syncthreads();
         if (tid == 0) a.norm_parts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
     }
+}
+
+template <int KZ>
+__global__ __launch_bounds__(256) void proj_adj_kernel(ProjArgs a, int in_stride)
+{
+    adj_body<KZ, false>(a, nullptr, nullptr, in_stride);
+}
+
+template <int KZ>
+__global__ __launch_bounds__(256) void proj_adj_f16(ProjArgs a, const uint16_t *rtb, const float *rtsc, int in_stride)
+{
+    adj_body<KZ, true>(a, rtb, rtsc, in_stride);
 }
 
 // Dual drive: z-drive line (m, p) of the workspace (line Lx + m*nu + p) holds
@@ -598,6 +659,35 @@ hipError_t launch_backproject_strided(const mpi3d_plan *pl, const float *rt, int
     case 8: hipLaunchKernelGGL(proj_adj_kernel<8>, dim3(blocks), dim3(256), lds, st, a, in_stride); break;
     case 16: hipLaunchKernelGGL(proj_adj_kernel<16>, dim3(blocks), dim3(256), lds, st, a, in_stride); break;
     case 32: hipLaunchKernelGGL(proj_adj_kernel<32>, dim3(blocks), dim3(256), lds, st, a, in_stride); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_zlines(const mpi3d_plan *pl, float *rt, hipStream_t st)
+{
+    return pl->drive_axes == 2 ? launch_zlines(pl, rt, true, st) : hipSuccess;
+}
+
+hipError_t launch_backproject16(const mpi3d_plan *pl, const uint16_t *rtb, const float *rtsc, float *xo,
+                                const float *x_sub, double lambda, double *norm_parts, int *nparts, hipStream_t st,
+                                const float *x_add)
+{
+    ProjArgs a = base_args(pl);
+    a.xo = xo;
+    a.x_sub = x_sub;
+    a.x_add = x_add;
+    a.lambda = lambda;
+    a.norm_parts = norm_parts;
+    const int blocks = a.tiles_x * a.tiles_y * a.n_zgroups;
+    if (nparts) *nparts = blocks;
+    if (norm_parts && blocks > pl->max_parts) return hipErrorInvalidValue;
+    const size_t lds = sizeof(uint32_t) * (size_t)a.adj_chunk * (a.kz / 2) * kPW +
+                       sizeof(float) * (size_t)a.adj_chunk * a.kz + sizeof(int) * a.adj_chunk;
+    switch (a.kz) {
+    case 8: hipLaunchKernelGGL(proj_adj_f16<8>, dim3(blocks), dim3(256), lds, st, a, rtb, rtsc, pl->nup); break;
+    case 16: hipLaunchKernelGGL(proj_adj_f16<16>, dim3(blocks), dim3(256), lds, st, a, rtb, rtsc, pl->nup); break;
+    case 32: hipLaunchKernelGGL(proj_adj_f16<32>, dim3(blocks), dim3(256), lds, st, a, rtb, rtsc, pl->nup); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

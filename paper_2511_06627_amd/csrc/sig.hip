@@ -17,7 +17,9 @@
 // to match.  Every table is pre-swizzled so an operand fetch is one coalesced
 // 16-byte load per lane.
 //
-// Wave pairs.  A block is 8 waves = 4 pairs; a pair owns 32 lines.  The two
+// Wave pairs.  A block is 8 waves = 4 pairs (two waves per SIMD; wide
+// blocks: 4 waves = 2 pairs, one wave per SIMD, whose waves hold up to 22
+// column tiles and a deeper load ring); a pair owns 32 lines.  The two
 // waves of a pair split the reduction of the first contraction (half the
 // detector samples, or half the bins) and the output columns of the second,
 // and swap their partial time tiles through LDS once per chunk: no work is
@@ -52,11 +54,13 @@ constexpr int ring_size(int nl, int cap)
 #define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
 
 // Forward.  Per pair: GEMM1 over this wave's half of the detector samples,
-// pair exchange, GEMM2 over this wave's GH column tiles.
-template <int NUP, int GH>
-__global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
+// pair exchange, GEMM2 over this wave's GH column tiles.  PAIRS wave pairs
+// per block: kWaves (two waves per SIMD), or kWidePairs for the wide column
+// groups (one wave per SIMD, up to 512 registers per wave).
+template <int NUP, int GH, int PAIRS>
+__global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
 {
-    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
+    __shared__ float xs[2 * PAIRS * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
     constexpr int NK = NUP / 16;          // K float4 loads per chunk (this half)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk
     constexpr int NL = NK + NF;
-    constexpr int kRing = ring_size(NL, 8);
+    constexpr int kRing = ring_size(NL, PAIRS == kWidePairs ? 16 : 8);
     static_assert(NL % kRing == 0, "ring size must divide the stream");
 
     // B operand of GEMM1: rho[r][p0 + 2 st + h], p0 = half * NUP/2
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
                 S = MFMA32(v[2], R[4 * i + 2], S);
                 S = MFMA32(v[3], R[4 * i + 3], S);
             } else {
-                if (i == NK) Sf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, S);
+                if (i == NK) Sf = pair_sum<PAIRS>(xs, c & 1, bp.pair, bp.half, lane, S);
                 const int j = i - NK, s4 = j / GH, g = j % GH;
                 acc[g] = MFMA32(Sf[4 * s4 + 0], v[0], acc[g]);
                 acc[g] = MFMA32(Sf[4 * s4 + 1], v[1], acc[g]);
@@ -142,10 +146,10 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f32(SigArgs a)
 
 // Adjoint.  Per pair: GEMM1 over this wave's GH column tiles (half the bins of
 // the group), pair exchange, GEMM2 over this wave's half of the detector tiles.
-template <int NUP, int GH>
-__global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
+template <int NUP, int GH, int PAIRS>
+__global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
 {
-    __shared__ float xs[2 * kWaves * 2 * 16 * 64];
+    __shared__ float xs[2 * PAIRS * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk (GEMM1)
     constexpr int NK = 4 * PTH;           // K float4 loads per chunk (GEMM2)
     constexpr int NL = NF + NK;
-    constexpr int kRing = ring_size(NL, 8);
+    constexpr int kRing = ring_size(NL, PAIRS == kWidePairs ? 16 : 8);
     static_assert(NL % kRing == 0, "ring size must divide the stream");
     const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;   // first column of this wave
     const int pt0 = bp.half * PTH;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
                 // keep this load's issue point: later ring slots stay in flight
                 __builtin_amdgcn_sched_barrier(0);
             } else {
-                if (i == NF) Gf = pair_sum(xs, c & 1, bp.pair, bp.half, lane, Gt);
+                if (i == NF) Gf = pair_sum<PAIRS>(xs, c & 1, bp.pair, bp.half, lane, Gt);
                 const int j = i - NF, s4 = j / PTH, pt = j % PTH;
                 racc[pt] = MFMA32(Gf[4 * s4 + 0], v[0], racc[pt]);
                 racc[pt] = MFMA32(Gf[4 * s4 + 1], v[1], racc[pt]);
@@ -237,12 +241,14 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f32(SigArgs a)
 typedef void (*SigKernel)(SigArgs);
 
 constexpr int kNups[] = {64, 128, 192, 256};
-constexpr int kGHs[] = {3, 4, 6, 7};
+constexpr int kGHs[] = {3, 4, 6, 7};        // kWaves pairs per block
+constexpr int kGHw[] = {8, 9, 10, 11};      // kWidePairs pairs per block
 
-int gh_slot(int gct)
+int gh_slot(int gct, int pairs)
 {
+    const int *gh = pairs == kWidePairs ? kGHw : kGHs;
     for (int i = 0; i < 4; ++i)
-        if (gct == 2 * kGHs[i]) return i;
+        if (gct == 2 * gh[i]) return i;
     return -1;
 }
 int nup_slot(int nup)
@@ -252,45 +258,57 @@ int nup_slot(int nup)
     return -1;
 }
 
-#define ROW(NUP, F) {F<NUP, 3>, F<NUP, 4>, F<NUP, 6>, F<NUP, 7>}
+#define ROW(NUP, F) {F<NUP, 3, kWaves>, F<NUP, 4, kWaves>, F<NUP, 6, kWaves>, F<NUP, 7, kWaves>}
+#define ROWW(NUP, F) {F<NUP, 8, kWidePairs>, F<NUP, 9, kWidePairs>, F<NUP, 10, kWidePairs>, F<NUP, 11, kWidePairs>}
 const SigKernel kFwd[4][4] = {ROW(64, sig_fwd_f32), ROW(128, sig_fwd_f32), ROW(192, sig_fwd_f32),
                               ROW(256, sig_fwd_f32)};
 const SigKernel kAdj[4][4] = {ROW(64, sig_adj_f32), ROW(128, sig_adj_f32), ROW(192, sig_adj_f32),
                               ROW(256, sig_adj_f32)};
+const SigKernel kFwdW[4][4] = {ROWW(64, sig_fwd_f32), ROWW(128, sig_fwd_f32), ROWW(192, sig_fwd_f32),
+                               ROWW(256, sig_fwd_f32)};
+const SigKernel kAdjW[4][4] = {ROWW(64, sig_adj_f32), ROWW(128, sig_adj_f32), ROWW(192, sig_adj_f32),
+                               ROWW(256, sig_adj_f32)};
 #undef ROW
+#undef ROWW
 
 }  // namespace
 
 // fp16 variants live in sig16.hip
 hipError_t launch_sig_fwd16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st);
 hipError_t launch_sig_adj16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st);
-int sig16_supported(int nup, int gct);
+int sig16_supported(int nup, int gct, int pairs);
 
-int sig_fwd_supported(int nup, int gct, int precision)
+int sig_fwd_supported(int nup, int gct, int precision, int pairs)
 {
-    if (precision == MPI3D_MIXED) return sig16_supported(nup, gct);
-    return nup_slot(nup) >= 0 && gh_slot(gct) >= 0;
+    if (precision == MPI3D_MIXED) return sig16_supported(nup, gct, pairs);
+    return (pairs == kWaves || pairs == kWidePairs) && nup_slot(nup) >= 0 && gh_slot(gct, pairs) >= 0;
 }
-int sig_adj_supported(int nup, int gct, int precision) { return sig_fwd_supported(nup, gct, precision); }
+int sig_adj_supported(int nup, int gct, int precision, int pairs)
+{
+    return sig_fwd_supported(nup, gct, precision, pairs);
+}
+
+static hipError_t launch32(const SigKernel (&narrow)[4][4], const SigKernel (&wide)[4][4], const mpi3d_plan *pl,
+                           SigArgs &a, hipStream_t st)
+{
+    const int ns = nup_slot(pl->nup), gs = gh_slot(a.gct, a.pairs);
+    if (ns < 0 || gs < 0) return hipErrorInvalidValue;
+    const SigKernel k = a.pairs == kWidePairs ? wide[ns][gs] : narrow[ns][gs];
+    const int blocks = a.total_tiles * a.nsplit * a.ngroups;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(128 * a.pairs), 0, st, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st)
 {
     if (precision == MPI3D_MIXED) return launch_sig_fwd16(pl, a, st);
-    const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
-    if (ns < 0 || gs < 0) return hipErrorInvalidValue;
-    const int blocks = a.total_tiles * a.nsplit * a.ngroups;
-    hipLaunchKernelGGL(kFwd[ns][gs], dim3(blocks), dim3(kSigThreads), 0, st, a);
-    return hipGetLastError();
+    return launch32(kFwd, kFwdW, pl, a, st);
 }
 
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st)
 {
     if (precision == MPI3D_MIXED) return launch_sig_adj16(pl, a, st);
-    const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
-    if (ns < 0 || gs < 0) return hipErrorInvalidValue;
-    const int blocks = a.total_tiles * a.nsplit * a.ngroups;
-    hipLaunchKernelGGL(kAdj[ns][gs], dim3(blocks), dim3(kSigThreads), 0, st, a);
-    return hipGetLastError();
+    return launch32(kAdj, kAdjW, pl, a, st);
 }
 
 }  // namespace mpi3d

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
 #pragma unroll
         for (int i = 0; i < NKS; ++i) S = MFMA16(ka[i * 64], R[i], S);
         if (more) sa.store(la + (buf ^ 1) * UA, tid);
-        const f32x16 Sf = pair_sum(xs, buf, bp.pair, bp.half, lane, S);
+        const f32x16 Sf = pair_sum<kWaves>(xs, buf, bp.pair, bp.half, lane, S);
         if (more) sb.store(lb + (buf ^ 1) * UB, tid);
         const f16x8 S16[2] = {to_f16x8(Sf, 0), to_f16x8(Sf, 8)};
         const f16x8 *fb = lb + buf * UB + fb0;
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
 #pragma unroll
         for (int i = 0; i < NF; ++i) Gt = MFMA16(fa[i * 64], Y[i], Gt);
         if (more) sa.store(la + (buf ^ 1) * UA, tid);
-        const f32x16 Gf = pair_sum(xs, buf, bp.pair, bp.half, lane, Gt);
+        const f32x16 Gf = pair_sum<kWaves>(xs, buf, bp.pair, bp.half, lane, Gt);
         if (more) sb.store(lb + (buf ^ 1) * UB, tid);
         const f16x8 G16[2] = {to_f16x8(Gf, 0), to_f16x8(Gf, 8)};
         const f16x8 *kb = lb + buf * UB + kb0;
@@ -294,7 +294,10 @@ const SigKernel kAdj[4][4] = {ROW(64, sig_adj_f16), ROW(128, sig_adj_f16), ROW(1
 
 }  // namespace
 
-int sig16_supported(int nup, int gct) { return nup_slot(nup) >= 0 && gh_slot(gct) >= 0; }
+int sig16_supported(int nup, int gct, int pairs)
+{
+    return pairs == kWaves && nup_slot(nup) >= 0 && gh_slot(gct) >= 0;
+}
 
 // Dynamic LDS above 64 KB has to be allowed per kernel.
 static hipError_t allow_lds(const void *kernel, int bytes)
@@ -305,8 +308,8 @@ static hipError_t allow_lds(const void *kernel, int bytes)
 
 hipError_t launch_sig_fwd16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st)
 {
-    const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
-    if (ns < 0 || gs < 0 || !pl->kf16) return hipErrorInvalidValue;
+    const int ns = nup_slot(pl->nup), gs = gh_slot(a.gct);
+    if (ns < 0 || gs < 0 || a.pairs != kWaves || !pl->kf16) return hipErrorInvalidValue;
     hipError_t e = allow_lds((const void *)kFwd[ns][gs], kLds[ns][gs]);
     if (e != hipSuccess) return e;
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;
@@ -316,8 +319,8 @@ hipError_t launch_sig_fwd16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st)
 
 hipError_t launch_sig_adj16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st)
 {
-    const int ns = nup_slot(pl->nup), gs = gh_slot(pl->gct);
-    if (ns < 0 || gs < 0 || !pl->ka16) return hipErrorInvalidValue;
+    const int ns = nup_slot(pl->nup), gs = gh_slot(a.gct);
+    if (ns < 0 || gs < 0 || a.pairs != kWaves || !pl->ka16) return hipErrorInvalidValue;
     hipError_t e = allow_lds((const void *)kAdj[ns][gs], kLds[ns][gs]);
     if (e != hipSuccess) return e;
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;

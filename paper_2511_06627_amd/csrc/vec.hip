@@ -56,15 +56,23 @@ __device__ __forceinline__ double sum_splits(const float *__restrict__ pp, int n
 __device__ __forceinline__ double sum_unscaled(const float *__restrict__ pp, int nparts, long stride, long row,
                                                const float *__restrict__ row_scale, RowPasses rp)
 {
-    if (!row_scale) return sum_splits(pp, nparts, stride);
-    if (rp.npass <= 1) return sum_splits(pp, nparts, stride) / (double)row_scale[row];
+    if (rp.npass <= 1) {
+        const double v = sum_splits(pp, nparts, stride);
+        return row_scale ? v / (double)row_scale[row] : v;
+    }
     const int per = nparts / rp.npass;
-    const int k = (int)(row % rp.nz);
+    const bool zl = row >= rp.zbase;
+    const int nline = zl ? rp.nzc : rp.nz;
+    const int R = zl ? rp.rz : rp.rx;
+    const int k = (int)(zl ? (row - rp.zbase) % rp.nzc : row % rp.nz);
     double v = 0.0;
     for (int p = 0; p < rp.npass; ++p) {
         const int d = p - rp.rows;
-        if (k + d < 0 || k + d >= rp.nz) continue;   // that pass read no line: its partials are zero
-        v += sum_splits(pp + (long)p * per * stride, per, stride) / (double)row_scale[row + d];
+        // passes beyond this line's coupling, or reading past its angle's
+        // lines, were not written for it
+        if (d < -R || d > R || k + d < 0 || k + d >= nline) continue;
+        const double t = sum_splits(pp + (long)p * per * stride, per, stride);
+        v += row_scale ? t / (double)row_scale[row + d] : t;
     }
     return v;
 }
@@ -114,6 +122,55 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
             o = (float)v;
         }
         out[idx] = o;
+    }
+}
+
+// The mixed adjoint's lines as 16-bit operands of its backprojection: one
+// wave per line forms the line's values -- the split sums as reduce_lines
+// does, or (lines_in) fp32 lines already formed -- and a power-of-two scale
+// s with max |v| s in [0.5, 1) (1 for a zero line; capped like the signal
+// kernels' row scales), then writes fp16(v s) over nup columns (zero past
+// nu) and 1/s.  Per-line scaling gives every line fp16's relative precision
+// whatever its size.
+constexpr int kLineSlots = 4;     // nup <= 256: at most 4 values per lane
+__global__ __launch_bounds__(kThreads) void lines16_kernel(long rows, int nu, int nup, int nparts, long part_stride,
+                                                            const float *__restrict__ part,
+                                                            const float *__restrict__ row_scale, double scale,
+                                                            RowPasses rp, const float *__restrict__ lines_in,
+                                                            uint16_t *__restrict__ out16, float *__restrict__ inv_scale)
+{
+    const int lane = threadIdx.x & 63;
+    const long row = (long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    float v[kLineSlots];
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < kLineSlots; ++j) {
+        const int p = lane + 64 * j;
+        float o = 0.f;
+        if (p < nu) {
+            if (lines_in) {
+                o = lines_in[row * nup + p];
+            } else {
+                const double t = sum_unscaled(part + row * nup + p, nparts, part_stride, row, row_scale, rp);
+                o = (float)(t * scale);
+            }
+        }
+        v[j] = o;
+        m = fmaxf(m, fabsf(o));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    float s = 1.f;
+    if (m > 0.f && isfinite(m)) {
+        int e;
+        frexpf(m, &e);
+        s = ldexpf(1.f, min(-e, 120));
+    }
+    if (lane == 0) inv_scale[row] = 1.f / s;
+#pragma unroll
+    for (int j = 0; j < kLineSlots; ++j) {
+        const int p = lane + 64 * j;
+        if (p < nup) out16[row * nup + p] = __builtin_bit_cast(uint16_t, (_Float16)(v[j] * s));
     }
 }
 
@@ -395,6 +452,17 @@ hipError_t launch_reduce_lines_strided(long rows, int nu, int nup, int out_strid
     const int g = grid_for(rows * out_stride, kReduceBlocks);
     hipLaunchKernelGGL(reduce_lines_kernel, dim3(g), dim3(kThreads), 0, st, rows, nu, nup, out_stride, nparts,
                        part_stride, part, row_scale, scale, out, rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_lines16(long rows, int nu, int nup, int nparts, long part_stride, const float *part,
+                          const float *row_scale, double scale, RowPasses rp, const float *lines_in, uint16_t *out16,
+                          float *inv_scale, hipStream_t st)
+{
+    if (nup > 64 * kLineSlots) return hipErrorInvalidValue;
+    const long blocks = (rows + kThreads / 64 - 1) / (kThreads / 64);
+    hipLaunchKernelGGL(lines16_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, rows, nu, nup, nparts,
+                       part_stride, part, row_scale, scale, rp, lines_in, out16, inv_scale);
     return hipGetLastError();
 }
 

@@ -97,6 +97,44 @@ class Cluster:
                      / np.linalg.norm(self.mean))
 
 
+def segment_distance(x, a, b):
+    """Distance of x from the segment [a, b] (flattened arrays), relative to |b|."""
+    x, a, b = (np.asarray(v, dtype=np.float64).ravel() for v in (x, a, b))
+    d = b - a
+    dd = float(d @ d)
+    t = 0.0 if dd == 0.0 else min(1.0, max(0.0, float((x - a) @ d) / dd))
+    return float(np.linalg.norm(x - (a + t * d)) / np.linalg.norm(b))
+
+
+class ClusterPath:
+    """Clusters of one schedule at the low and the high end of an operator's
+    per-call error range.  Where the iterate of a perturbed run lands drifts
+    with the error level (the cluster means at 1e-7 and 1e-6 differ by more
+    than either cluster's radius), and a real implementation's rounding has a
+    part that repeats from call to call (its rounded tables, a consistent
+    linear perturbation) and a part that does not, so its effective level lies
+    somewhere in the range: an implementation is compared with the segment
+    between the two means, and the bar is CLUSTER_BAR times the larger
+    radius."""
+
+    def __init__(self, lo, hi):
+        self.lo, self.hi = lo, hi
+        self.radius = max(lo.radius, hi.radius)
+        self.span = float(np.linalg.norm(hi.mean - lo.mean) / np.linalg.norm(hi.mean))
+        self.n = lo.n + hi.n
+
+    def distance(self, x):
+        return segment_distance(x, self.lo.mean, self.hi.mean)
+
+
+# Per-call error range of the FP32 operator on CGLS's own vectors, measured on
+# the GPU against the FP64 oracle: A p 1.4e-7 .. 6.3e-7, A^T r 2.2e-7 .. 1.2e-6.
+FP32_EPS_RANGE = (1e-7, 1e-6)
+# Per-call error range of the mixed operator (forward 7e-5 .. 1.2e-4, adjoint
+# with fp16 lines up to about 3e-4 relative L2).
+MIXED_EPS_RANGE = (5e-5, 3e-4)
+
+
 def cgls_cluster(run, op, eps=FP32_OP_EPS, seeds=tuple(range(101, 109)), select=None):
     """Cluster of run(perturbed op) over the seeds (see Cluster)."""
     return Cluster([run(PerturbedOperator(op, eps, s)) for s in seeds], select)
@@ -112,6 +150,12 @@ def mixed_cluster(run, op, seeds=tuple(range(201, 209)), select=None, eps_outer=
 
 # Bar of a same-schedule solve comparison, in cluster radii.
 CLUSTER_BAR = 4.0
+
+
+def cgls_path(run, op, seeds=tuple(range(101, 107)), select=None, eps_range=FP32_EPS_RANGE):
+    """ClusterPath of run(perturbed op) at the two ends of eps_range."""
+    lo, hi = (cgls_cluster(run, op, eps, seeds, select) for eps in eps_range)
+    return ClusterPath(lo, hi)
 
 
 def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_OP_EPS):

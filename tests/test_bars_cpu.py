@@ -5,17 +5,17 @@ the oracle: each bar must pass a correct run and fail a wrong one.
   by 1%, gives a per-band error of order 1 (or 1e-2), far above the mixed
   forward's 3e-2 only when the band is dropped or halved -- so the bar sees a
   lost or misscaled band, not rounding.
-* Cluster bars of mid-run solves: a fresh run with FP32-level operator noise
-  lands inside 4 radii of the cluster mean; runs of a CGLS with a planted
-  mistake in its recurrences (the lambda term left out of delta, a wrong beta)
-  land outside, with the same noise.
+* Cluster bars of mid-run solves: fresh runs with operator noise anywhere in
+  the FP32 range land within 4 radii of the path between the two clusters'
+  means; runs of a CGLS with a planted mistake in its recurrences (the lambda
+  term left out of delta, a wrong beta) land outside, with the same noise.
 """
 import numpy as np
 
 from oracle import operator as oop, solvers
 from paper_2511_06627_amd import configs
 from helpers import (config_geometry, band_errors, band_confined_data, BAND_TOL16_FWD, BAND_TOL16_ADJ,
-                     BAND_TOL32, cgls_cluster, CLUSTER_BAR, PerturbedOperator, rel_l2, random_volume)
+                     BAND_TOL32, cgls_path, CLUSTER_BAR, PerturbedOperator, rel_l2, random_volume)
 
 
 def _small():
@@ -77,10 +77,10 @@ def test_cluster_bar_passes_noise_and_fails_planted_solver_mistakes():
     b = b.astype(np.complex64).astype(np.complex128)
     op = oop.Operator(g, precomposed=True)
     run = lambda o: solvers.cgls(o, b, cfg.lam, cfg.iters)  # noqa: E731
-    cl = cgls_cluster(run, op)
+    cl = cgls_path(run, op)
     bar = CLUSTER_BAR * cl.radius
-    for s in (301, 302):
-        assert cl.distance(run(PerturbedOperator(op, 1e-6, s))) <= bar
+    for eps, s in ((1e-7, 301), (3e-7, 302), (1e-6, 303)):
+        assert cl.distance(run(PerturbedOperator(op, eps, s))) <= bar, eps
     for mistake in ("beta", "no_lambda"):
-        d = cl.distance(_cgls_planted(PerturbedOperator(op, 1e-6, 303), b, cfg.lam, cfg.iters, mistake))
+        d = cl.distance(_cgls_planted(PerturbedOperator(op, 1e-6, 304), b, cfg.lam, cfg.iters, mistake))
         assert d > bar, (mistake, d, bar)

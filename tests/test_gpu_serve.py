@@ -102,8 +102,9 @@ def test_served_solve_matches_oracle(torch_mod, plans, reqs):
 
 
 def test_continuous_batching_loop(torch_mod, reqs):
-    """End to end: a burst of requests, admission under a small forced budget,
-    results equal to the same requests solved alone."""
+    """End to end: a burst of requests, admission under a small forced budget
+    (every geometry's plan tables plus room for about two requests), results
+    equal to the same requests solved alone."""
     from paper_2511_06627_amd.serve import ContinuousBatcher, GpuExecutor, Request, summarize
     rng = np.random.default_rng(3000)
     names = ["A1", "B1", "R1", "A2", "D1", "R2", "A1", "B1", "A2"]
@@ -116,23 +117,18 @@ def test_continuous_batching_loop(torch_mod, reqs):
         rq.append(Request(i, t, geo, b, 1e-3, sched))
     ex = GpuExecutor()
     fps = [ex.footprint(r) for r in rq]
-    budget = int(2.2 * max(fps))                 # room for about two requests
+    tables = {ex.plan_key(r): ex.plan_bytes(r) for r in rq}
+    budget = int(sum(tables.values()) + 2.2 * max(fps))     # plans, and room for about two requests
     bat = ContinuousBatcher(ex, budget_bytes=budget, max_active=8)
     out = bat.run(rq)
     s = summarize(out)
-    _log("serve loop: %s" % s)
-    # resident footprint never above the budget, and the budget did bind:
-    # some request was admitted only after another retired
-    used = peak = 0
-    for _, ev, rid in bat.log:
-        if ev == "admit":
-            used += fps[rid]
-        elif ev == "retire":
-            used -= fps[rid]
-        peak = max(peak, used)
-    assert peak <= budget
+    _log("serve loop: %s (peak %d of %d bytes)" % (s, bat.peak_bytes, budget))
+    # charged bytes (plans and live requests, held until each copy-out
+    # closed its state) never above the budget, and the budget did bind:
+    # some request was admitted only after another was done
+    assert bat.peak_bytes <= budget
     events = [ev for _, ev, _ in bat.log]
-    assert "admit" in events[events.index("retire"):]
+    assert "admit" in events[events.index("done"):]
     from paper_2511_06627_amd.plan import Plan
     for r, o in zip(rq, out):
         p = Plan(precisions=("fp32", "mixed"), **r.geometry)
