@@ -38,7 +38,8 @@
  *   finishes unless stated otherwise.
  * - No entry point allocates device memory except mpi3d_plan_create (its
  *   tables).  Operator and solver scratch comes from a caller workspace whose
- *   size mpi3d_plan_query reports, so an HBM footprint is known up front.
+ *   size mpi3d_plan_query reports, so an HBM footprint is known up front
+ *   (mpi3d_forward_noalloc uses the library's static scratch array instead).
  * - Layouts.  Volume x: float32 [nz][ny][nx], x index fastest.  Data b:
  *   complex64 as interleaved float pairs (re, im), [n_angles][nz][n_bins];
  *   kept bins ordered harmonic-major, offset-minor (see mpi3d_geometry).
@@ -184,6 +185,22 @@ int mpi3d_plan_query(const mpi3d_plan *plan, mpi3d_plan_info *info);
  * at least op_ws_bytes of device memory, 256-byte aligned. */
 int mpi3d_forward(const mpi3d_plan *plan, int32_t precision, const float *x_dev, float *b_dev,
                   void *ws_dev, size_t ws_bytes, void *stream);
+
+/* No-allocation forward, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  b_dev = A x_dev as mpi3d_forward computes it (same kernels,
+ * same order, the same bits), with the operator workspace taken from a static
+ * device array of MPI3D_NOALLOC_SCRATCH_BYTES per GPU that the library holds
+ * until the process ends; the call allocates nothing.  Plans whose
+ * op_ws_bytes exceed that size get MPI3D_ENOMEM (nothing is enqueued);
+ * MPI3D_PRECOMPOSED gets MPI3D_ENOTSUP (its library GEMMs may allocate).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (concurrent streams or host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe.  The array keeps the last
+ * call's contents, none of which a later call reads before writing it. */
+#define MPI3D_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int mpi3d_forward_noalloc(const mpi3d_plan *plan, int32_t precision, const float *x_dev, float *b_dev,
+                          void *stream);
 
 /* x_dev = A^T b_dev = Re(A^H b_dev).  Same workspace rule as mpi3d_forward. */
 int mpi3d_adjoint(const mpi3d_plan *plan, int32_t precision, const float *b_dev, float *x_dev,

@@ -14,6 +14,8 @@ MPI3D_FP32 = 0
 MPI3D_MIXED = 1
 MPI3D_PRECOMPOSED = 2
 
+NOALLOC_SCRATCH_BYTES = 128 << 20      # MPI3D_NOALLOC_SCRATCH_BYTES
+
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSUP", -5: "ENONFINITE"}
 
 
@@ -74,6 +76,7 @@ _SIGS = {
     "mpi3d_plan_query": (_I, [_VP, ctypes.POINTER(PlanInfo)]),
     "mpi3d_forward": (_I, [_VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "mpi3d_adjoint": (_I, [_VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "mpi3d_forward_noalloc": (_I, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "mpi3d_project": (_I, [_VP, _VP, _VP, _VP]),
     "mpi3d_backproject": (_I, [_VP, _VP, _VP, _VP]),
     "mpi3d_signal_fwd": (_I, [_VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),

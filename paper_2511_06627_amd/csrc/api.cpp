@@ -665,6 +665,12 @@ static int momentum_solve(const mpi3d_plan *pl, const float *b, float *x, const 
     return MPI3D_OK;
 }
 
+int forward_ws(const mpi3d_plan *pl, int prec, const float *x, float *b, void *ws, hipStream_t st)
+{
+    OpWs w = carve_op(pl, ws);
+    return apply_forward(pl, prec, x, b, w, st);
+}
+
 int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o)
 {
     if (!o) return MPI3D_EINVAL;

@@ -362,7 +362,11 @@ struct Cgls {
     int iterate(int prec, hipStream_t st);
 };
 int validate_opts(const mpi3d_plan *pl, const mpi3d_solve_opts *o);
-
+// b = A x with the operator workspace at ws (op_ws_bytes, 256-byte aligned).
+int forward_ws(const mpi3d_plan *pl, int prec, const float *x, float *b, void *ws, hipStream_t st);
+// Records the device address of the no-allocation entry point's scratch array
+// on `device` (which must be current); idempotent.
+int scratch_setup(int device);
 int estimate_op_norm(mpi3d_plan *pl, double rtol, int max_iters, double *norm_out, int *iters_out);
 // ||A||_2 with the plan's current scale, by power iteration in caller buffers:
 // v, z volumes, y data, norms (max_iters doubles), parts (max_parts doubles),

@@ -691,6 +691,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         if (g->rx_filter) mix(g->rx_filter, sizeof(float) * 2 * pl->nb);
         pl->line_key = h;
     }
+    // the no-allocation entry point's scratch address on this device (a
+    // failure here is reported by that entry point itself)
+    (void)scratch_setup(device);
     pl->norm_iters = 0;
     if (g->op_scale == 0.0) {
         // c_A = 1 / ||A||_2, estimated on the device
