@@ -707,6 +707,45 @@ def summarize_hbm(fetch_dir, write_dir, workload, commands, copy_mib=512):
     print("wrote", path, md)
 
 
+def summarize_sq(directory, workload, command):
+    """profiles/mfma_lds_counters_<workload>.md from a rocprofv3 --pmc run of
+    SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_MFMA SQ_INSTS_LDS SQ_ACTIVE_INST_LDS
+    SQ_LDS_BANK_CONFLICT SQ_INSTS_VALU GRBM_GUI_ACTIVE: per dispatch, averaged
+    over each kernel's dispatches.  GRBM_GUI_ACTIVE is summed over the 8 XCDs,
+    so its per-XCD value is the kernel's duration in GPU cycles; MFMA
+    utilisation = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024 SIMDs); the
+    bank-conflict ratio = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS."""
+    import numpy as np
+    rows = _csv_rows(directory, "counter_collection.csv")
+    per = {}
+    for r in rows:
+        k = kernel_key(r["Kernel_Name"])
+        if k is None:
+            continue
+        d = per.setdefault(k, {}).setdefault(r["Dispatch_Id"], {})
+        name = r["Counter_Name"]
+        d[name] = d.get(name, 0.0) + float(r["Counter_Value"])
+    names = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS",
+             "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_VALU", "GRBM_GUI_ACTIVE")
+    out = ["# MFMA and LDS counters: %s" % workload, "", "Command (from the repository root, on one MI355X):", "",
+           "    " + command, "", summarize_sq.__doc__.split("\n\n")[0].replace("\n    ", "\n"), "",
+           "| kernel | dispatches | GPU cycles | MFMA instr | MFMA util | LDS instr | LDS active cycles | "
+           "bank-conflict cycles | conflict / active | VALU instr |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(per):
+        ds = list(per[k].values())
+        m = {n: float(np.mean([d.get(n, 0.0) for d in ds])) for n in names}
+        cyc = m["GRBM_GUI_ACTIVE"] / 8.0
+        util = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * 1024) if cyc else 0.0
+        ratio = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_ACTIVE_INST_LDS"] if m["SQ_ACTIVE_INST_LDS"] else 0.0
+        out.append("| %s | %d | %.0f | %.0f | %.1f%% | %.0f | %.0f | %.0f | %.2f | %.0f |" % (
+            k, len(ds), cyc, m["SQ_INSTS_MFMA"], 100 * util, m["SQ_INSTS_LDS"], m["SQ_ACTIVE_INST_LDS"],
+            m["SQ_LDS_BANK_CONFLICT"], ratio, m["SQ_INSTS_VALU"]))
+    path = os.path.join(ROOT, "profiles", "mfma_lds_counters_%s.md" % workload)
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("wrote", path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -733,11 +772,16 @@ def main():
                     help="write profiles/kernel_stats_<workload>.md from a rocprofv3 --stats output folder")
     ap.add_argument("--summarize-hbm", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/hbm_traffic* from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output folders")
+    ap.add_argument("--summarize-sq", metavar="DIR",
+                    help="write profiles/mfma_lds_counters_<workload>.md from a rocprofv3 --pmc SQ counter folder")
     ap.add_argument("--workload", default="hdr_256x256x128", help="workload name for --summarize-*")
     ap.add_argument("--command", action="append", default=[], help="profiling command(s) for --summarize-*")
     args = ap.parse_args()
     if args.summarize_kernel_stats:
         summarize_kernel_stats(args.summarize_kernel_stats, args.workload, " && ".join(args.command))
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq, args.workload, " && ".join(args.command))
         return
     if args.summarize_hbm:
         summarize_hbm(args.summarize_hbm[0], args.summarize_hbm[1], args.workload, args.command)

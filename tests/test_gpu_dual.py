@@ -124,7 +124,9 @@ def test_dual_gpu_adjoint_identity(case, torch_mod):
 
 def test_dual_x_half_is_the_single_drive_scan(torch_mod):
     """The first n_angles * nz lines of a dual-drive forward are the
-    single-drive scan's data, bit for bit."""
+    single-drive scan's data: bit for bit with the collinear PSF; under the
+    tensor PSF the two plans may split time differently (their line counts
+    differ), so there the same values to FP32 rounding."""
     from paper_2511_06627_amd.plan import Plan
     for name in ("dual_ragged", "dual_tensor_ragged"):
         nx, ny, nz, M, T, P, w, klo, khi, D, R = CASES[name]
@@ -133,7 +135,11 @@ def test_dual_x_half_is_the_single_drive_scan(torch_mod):
         x = _dev(torch_mod, random_volume(_geom(name), 7), torch_mod.float32)
         bd = pd.forward(x)
         bs = ps.forward(x)
-        assert torch_mod.equal(bd[:M * nz].reshape(bs.shape), bs), name
+        if R == 0:
+            assert torch_mod.equal(bd[:M * nz].reshape(bs.shape), bs), name
+        else:
+            err = float(torch_mod.linalg.vector_norm(bd[:M * nz].reshape(bs.shape) - bs) / torch_mod.linalg.vector_norm(bs))
+            assert err <= 1e-6, (name, err)
 
 
 def test_dual_rejects_unsupported(torch_mod):
