@@ -521,6 +521,148 @@ def serve_leg(torch, n_requests=None, stream=True):
     return out
 
 
+def realistic_leg(torch, args, cfg, small, cpu, inputs):
+    """The realistic 192 x 192 x 96 scan: FP32 and mixed operators, the
+    precomposed-line operator, the raster / tensor-PSF / dual-drive variants,
+    the CGLS rate, the paper's own solver, the configured mixed 3 x 20 solve
+    (against x* and against 60 FP32 iterations), and time-to-solve at 1e-4."""
+    import numpy as np
+    from paper_2511_06627_amd import configs
+    from paper_2511_06627_amd.plan import Plan
+    plan, x, b = inputs(cfg, cpu)
+    out = operator_leg(torch, plan, cfg, x, b, args.warmup, args.steps)
+    out["applies_per_s"] = round(1.0 / out["seconds_per_step"], 2)
+    yb = torch.empty(plan.data_shape, dtype=torch.complex64, device="cuda")
+    xo = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    if args.realistic_only:
+        return out
+
+    # the precomposed-line operator (same map, signal stage as two float32
+    # GEMMs with G = F^T K): A^T A rate and the GEMM times
+    planp = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "precomposed"))
+    wsp = planp.workspace("op")
+
+    def stepp():
+        planp.forward(x, precision="precomposed", out=yb, ws=wsp)
+        planp.adjoint(yb, precision="precomposed", out=xo, ws=wsp)
+
+    sec, _ = timed_rate(torch, stepp, args.warmup, args.steps)
+    ktp = {k: planp.time_kernel(k, repeats=10, precision="precomposed", x=x, b=b, ws=wsp)
+           for k in ("signal_fwd", "signal_adj")}
+    out["precomposed"] = {"applies_per_s": round(1.0 / sec, 2), "ms_per_step": round(1e3 * sec, 4),
+                          "gemm_flops": 2.0 * cfg.n_lines * cfg.n_u * 2 * cfg.n_bins,
+                          "gemm_fwd_ms": round(ktp["signal_fwd"], 4), "gemm_adj_ms": round(ktp["signal_adj"], 4)}
+    log("precomposed A^T A: %.3f ms/step; GEMMs %s" % (1e3 * sec, ktp))
+    del planp, wsp
+
+    def rate_of(p, prec, data_shape=None):
+        yy = yb if data_shape is None else torch.empty(data_shape, dtype=torch.complex64, device="cuda")
+        ws = p.workspace("op")
+
+        def st():
+            p.forward(x, precision=prec, out=yy, ws=ws)
+            p.adjoint(yy, precision=prec, out=xo, ws=ws)
+
+        sec, _ = timed_rate(torch, st, args.warmup, args.steps)
+        return {"applies_per_s": round(1.0 / sec, 2), "ms_per_step": round(1e3 * sec, 4)}
+
+    if not args.no_variants:
+        # the same scan under a zig-zag raster (two PSF tables, per-line sweep
+        # direction): drive over a sixth of the fast axis, the focus field carrying
+        # the line across two thirds of it
+        ra, rs = cfg.n_u / 6.0, 2.0 * cfg.n_u / 3.0
+        planr = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.n_angles, cfg.n_t, cfg.drive_cycles, cfg.psf_width, cfg.harm_lo,
+                     cfg.harm_hi, cfg.half_band, 0.0, drive_amp=ra, raster_sweep=rs, precisions=("fp32", "mixed"))
+        out["raster"] = {"drive_amp": ra, "sweep": rs, "op_scale": planr.op_scale,
+                         "fp32": rate_of(planr, "fp32"), "mixed": rate_of(planr, "mixed")}
+        log("raster A^T A: %s" % out["raster"])
+        del planr
+        # the tensor PSF coupling each z-row to three rows on either side
+        plant = Plan.from_config(cfg, plan.op_scale, precisions=("fp32", "mixed", "precomposed"), psf_rows=3)
+        out["tensor_psf"] = {"psf_rows": 3, "fp32": rate_of(plant, "fp32"), "mixed": rate_of(plant, "mixed"),
+                             "precomposed": rate_of(plant, "precomposed")}
+        log("tensor PSF (R = 3) A^T A: %s" % out["tensor_psf"])
+        del plant
+        # both drive directions: 36 x 192 z-drive lines after the x-drive ones
+        pland = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2)
+        out["dual_drive"] = {"z_lines": int(pland.info.n_lines) - cfg.n_lines, "op_scale": pland.op_scale,
+                             "fp32": rate_of(pland, "fp32", pland.data_shape),
+                             "mixed": rate_of(pland, "mixed", pland.data_shape)}
+        log("dual drive A^T A: %s" % out["dual_drive"])
+        del pland
+        # both drives under the tensor PSF: x-drive lines coupled across three
+        # z-rows on either side, z-drive lines across three detector columns
+        plantd = Plan.from_config(cfg, 0.0, precisions=("fp32", "mixed"), drive_axes=2, psf_rows=3)
+        out["tensor_dual"] = {"psf_rows": 3, "z_lines": int(plantd.info.n_lines) - cfg.n_lines,
+                              "fp32": rate_of(plantd, "fp32", plantd.data_shape),
+                              "mixed": rate_of(plantd, "mixed", plantd.data_shape)}
+        log("tensor PSF + dual drive A^T A: %s" % out["tensor_dual"])
+        del plantd
+
+    # CGLS iteration rate of the configured 50-iteration solve
+    swk = plan.workspace("solve")
+    plan.solve(b, cfg.lam, iters=2, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = plan.solve(b, cfg.lam, iters=cfg.iters, ws=swk)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    out["cgls"] = {"iters": cfg.iters, "seconds": round(t_solve, 4), "iters_per_s": round(cfg.iters / t_solve, 2),
+                   "status": rep.status}
+    log("CGLS %d iterations: %.3f s" % (cfg.iters, t_solve))
+
+    # the paper's own solver (eq. iters): momentum gradient, finite-difference
+    # T, projection onto x >= 0 every iteration, 150 iterations; tau from
+    # power iteration on the device
+    plan.solve(b, cfg.lam, iters=2, solver="momentum", reg="fd", clamp_every=1, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, repm_p = plan.solve(b, cfg.lam, iters=150, solver="momentum", reg="fd", clamp_every=1, ws=swk)
+    torch.cuda.synchronize()
+    out["paper_solver"] = {"iters": 150, "reg": "finite differences", "lambda": cfg.lam,
+                           "seconds_incl_tau": round(time.perf_counter() - t0, 4), "status": repm_p.status}
+
+    # the configured mixed schedule (3 sweeps x 20 inner): against x* (when the
+    # oracle leg ran) and against 60 FP32 iterations
+    m2 = configs.MIXED_192
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xm, repm = plan.solve(b, m2.lam, precision="mixed", refine_sweeps=m2.refine_sweeps, inner_iters=m2.inner_iters,
+                          ws=swk)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    x60, _ = plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve(b, m2.lam, iters=m2.refine_sweeps * m2.inner_iters, ws=swk, report=False)
+    torch.cuda.synchronize()
+    t_fp32_60 = time.perf_counter() - t0
+    rec = {"seconds": round(t_mixed, 4), "fp32_60_seconds": round(t_fp32_60, 4), "status": repm.status,
+           "rel_l2_vs_fp32_60": float(torch.linalg.vector_norm(xm - x60) / torch.linalg.vector_norm(x60))}
+    if cpu is not None and "xstar" in cpu:
+        xs = cpu["xstar"]
+        xn = np.linalg.norm(xs)
+        rec["rel_l2_vs_xstar"] = float(np.linalg.norm(xm.cpu().numpy() - xs) / xn)
+        rec["fp32_60_rel_l2_vs_xstar"] = float(np.linalg.norm(x60.cpu().numpy() - xs) / xn)
+    out["mixed"]["solve_3x20"] = rec
+    log("mixed 3x20 solve: %s" % rec)
+    del swk
+
+    tts = {}
+    if cpu is not None and not args.skip_small and "small" in cpu:
+        sm = cpu["small"]
+        psmall = Plan.from_config(small, sm["op_scale"], precisions=("fp32", "mixed"))
+        tts["parity_32cube"] = {p: time_to_solve(psmall, torch, sm["b"], sm["xstar"], small.lam, p)
+                                for p in ("fp32", "mixed")}
+    if cpu is not None and "xstar" in cpu:
+        tts[cfg.name] = {p: time_to_solve(plan, torch, cpu["b"], cpu["xstar"], cfg.lam, p)
+                         for p in ("fp32", "mixed")}
+    out["time_to_solve"] = tts
+    if cpu is not None:
+        out["oracle_small"] = cpu.get("oracle_small")
+    return out
+
+
 def timed_rate(torch, step, warmup, steps):
     """Wall time per step of `steps` steps after `warmup`, bracketed by device
     synchronisations; returns (seconds per step, total seconds)."""
