@@ -42,7 +42,9 @@ __device__ __forceinline__ f16x8 to_f16x8(const f32x16 &v, int base)
 // Per-chunk table staging.  The block copies each time chunk's table slices
 // (GEMM1's and GEMM2's) from HBM/L2 into LDS once, with every thread moving a
 // few 16-byte units; the waves then read their operand fragments from LDS.
-// Without it each of the four pairs would fetch the same slices itself.
+// Without it each of the four pairs would fetch the same slices itself.  A
+// slice is loaded into registers two chunks before it is used and written to
+// LDS during the chunk before.
 //   A slice (GEMM1 operands), double-buffered: chunk c+1 is written before the
 //     pair barrier of chunk c, whose GEMM1 no longer reads that buffer (it
 //     last served chunk c-1, finished before the barrier of chunk c-1).
@@ -108,6 +110,11 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
                                            bp.half * (NUP / 2) + 8 * h);
 #pragma unroll
         for (int st = 0; st < NKS; ++st) R[st] = iok ? rin[2 * st] : f16x8(0);
+        // complete these loads here: inside the time loop the only memory
+        // loads in flight are then the next chunk's table slices, which the
+        // first contraction does not wait for
+#pragma unroll
+        for (int st = 0; st < NKS; ++st) asm volatile("" ::"v"(R[st]));
     }
     f32x16 acc[GH];
 #pragma unroll
@@ -117,39 +124,53 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
     const f16x8 *kg = (const f16x8 *)job.kf16;
     const f16x8 *fg = (const f16x8 *)a.ff16 + (size_t)bp.group * UB;
     const size_t fstride = (size_t)a.nct * 128;
-    Slice<UA> sa;
-    Slice<UB> sb;
+    // table slices in registers: chunk c + 1 (loaded during chunk c - 1,
+    // stored to LDS during chunk c) and chunk c + 2 (loaded during chunk c),
+    // so a load has a whole chunk to arrive
+    Slice<UA> sa, sa2;
+    Slice<UB> sb, sb2;
     if (c0 < c1) {
         sa.load(kg + (size_t)c0 * UA, tid);
         sb.load(fg + (size_t)c0 * fstride, tid);
         sa.store(la + (c0 & 1) * UA, tid);
         sb.store(lb + (c0 & 1) * UB, tid);
     }
+    if (c0 + 1 < c1) {
+        sa.load(kg + (size_t)(c0 + 1) * UA, tid);
+        sb.load(fg + (size_t)(c0 + 1) * fstride, tid);
+    }
     __syncthreads();
     const int ka0 = bp.half * NKS * 64 + lane;           // this wave's first K fragment
     const int fb0 = bp.half * GH * 128 + lane;           // this wave's first F fragment
 
-    for (int c = c0; c < c1; ++c) {
+    // one chunk: (ra, rb) hold chunk c + 1's slices, (na, nb) receive c + 2's;
+    // the loop alternates the two register sets, so no slice is copied
+    auto chunk = [&](int c, Slice<UA> &ra, Slice<UB> &rb, Slice<UA> &na, Slice<UB> &nb) {
         const int buf = c & 1;
         const bool more = c + 1 < c1;
-        if (more) {
-            sa.load(kg + (size_t)(c + 1) * UA, tid);
-            sb.load(fg + (size_t)(c + 1) * fstride, tid);
-        }
+        const int cn = min(c + 2, c1 - 1);               // loaded whether needed or not: no branch
+        na.load(kg + (size_t)cn * UA, tid);
+        nb.load(fg + (size_t)cn * fstride, tid);
         const f16x8 *ka = la + buf * UA + ka0;
         f32x16 S = 0.f;
 #pragma unroll
         for (int i = 0; i < NKS; ++i) S = MFMA16(ka[i * 64], R[i], S);
-        if (more) sa.store(la + (buf ^ 1) * UA, tid);
+        if (more) ra.store(la + (buf ^ 1) * UA, tid);
         const f32x16 Sf = pair_sum<kWaves>(xs, buf, bp.pair, bp.half, lane, S);
-        if (more) sb.store(lb + (buf ^ 1) * UB, tid);
+        if (more) rb.store(lb + (buf ^ 1) * UB, tid);
         const f16x8 S16[2] = {to_f16x8(Sf, 0), to_f16x8(Sf, 8)};
         const f16x8 *fb = lb + buf * UB + fb0;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
             for (int g = 0; g < GH; ++g) acc[g] = MFMA16(S16[hh], fb[(g * 2 + hh) * 64], acc[g]);
+    };
+    int c = c0;
+    for (; c + 1 < c1; c += 2) {
+        chunk(c, sa, sb, sa2, sb2);
+        chunk(c + 1, sa2, sb2, sa, sb);
     }
+    if (c < c1) chunk(c, sa, sb, sa2, sb2);
     if (bp.row0 >= job.rows) return;
     long ln[16];   // buffer lines of this lane's 16 result rows
 #pragma unroll
@@ -201,6 +222,9 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
         const f16x8 *yin = (const f16x8 *)(job.in16 + (size_t)(iok ? il : 0) * job.in16_stride + colbase + 8 * h);
 #pragma unroll
         for (int st = 0; st < NF; ++st) Y[st] = iok ? yin[2 * st] : f16x8(0);
+        // complete these loads before the time loop (see sig_fwd_f16)
+#pragma unroll
+        for (int st = 0; st < NF; ++st) asm volatile("" ::"v"(Y[st]));
     }
     f32x16 racc[PTH];
 #pragma unroll
@@ -210,39 +234,50 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     const size_t fstride = (size_t)a.nct * 128;
     const f16x8 *fg = (const f16x8 *)a.fa16 + (size_t)bp.group * UA;
     const f16x8 *kg = (const f16x8 *)job.ka16;
-    Slice<UA> sa;
-    Slice<UB> sb;
+    // table slices in registers two chunks ahead (see sig_fwd_f16)
+    Slice<UA> sa, sa2;
+    Slice<UB> sb, sb2;
     if (c0 < c1) {
         sa.load(fg + (size_t)c0 * fstride, tid);
         sb.load(kg + (size_t)c0 * UB, tid);
         sa.store(la + (c0 & 1) * UA, tid);
         sb.store(lb + (c0 & 1) * UB, tid);
     }
+    if (c0 + 1 < c1) {
+        sa.load(fg + (size_t)(c0 + 1) * fstride, tid);
+        sb.load(kg + (size_t)(c0 + 1) * UB, tid);
+    }
     __syncthreads();
     const int fa0 = bp.half * NF * 64 + lane;            // this wave's first F fragment
     const int kb0 = pt0 * 128 + lane;                    // this wave's first K fragment
 
-    for (int c = c0; c < c1; ++c) {
+    // one chunk, alternating two register sets of slices (see sig_fwd_f16)
+    auto chunk = [&](int c, Slice<UA> &ra, Slice<UB> &rb, Slice<UA> &na, Slice<UB> &nb) {
         const int buf = c & 1;
         const bool more = c + 1 < c1;
-        if (more) {
-            sa.load(fg + (size_t)(c + 1) * fstride, tid);
-            sb.load(kg + (size_t)(c + 1) * UB, tid);
-        }
+        const int cn = min(c + 2, c1 - 1);               // loaded whether needed or not: no branch
+        na.load(fg + (size_t)cn * fstride, tid);
+        nb.load(kg + (size_t)cn * UB, tid);
         const f16x8 *fa = la + buf * UA + fa0;
         f32x16 Gt = 0.f;
 #pragma unroll
         for (int i = 0; i < NF; ++i) Gt = MFMA16(fa[i * 64], Y[i], Gt);
-        if (more) sa.store(la + (buf ^ 1) * UA, tid);
+        if (more) ra.store(la + (buf ^ 1) * UA, tid);
         const f32x16 Gf = pair_sum<kWaves>(xs, buf, bp.pair, bp.half, lane, Gt);
-        if (more) sb.store(lb + (buf ^ 1) * UB, tid);
+        if (more) rb.store(lb + (buf ^ 1) * UB, tid);
         const f16x8 G16[2] = {to_f16x8(Gf, 0), to_f16x8(Gf, 8)};
         const f16x8 *kb = lb + buf * UB + kb0;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
             for (int pt = 0; pt < PTH; ++pt) racc[pt] = MFMA16(G16[hh], kb[(pt * 2 + hh) * 64], racc[pt]);
+    };
+    int c = c0;
+    for (; c + 1 < c1; c += 2) {
+        chunk(c, sa, sb, sa2, sb2);
+        chunk(c + 1, sa2, sb2, sa, sb);
     }
+    if (c < c1) chunk(c, sa, sb, sa2, sb2);
     if (bp.row0 >= job.rows) return;
     long ln[16];   // buffer lines of this lane's 16 result rows
 #pragma unroll
