@@ -189,7 +189,7 @@ def projection_bytes(cfg):
     return 4.0 * (cfg.n_angles * nvox + cfg.n_lines * cfg.n_u)
 
 
-def projection_report(cfg, kernel, ms, measured_bytes, bf16=False):
+def projection_report(cfg, kernel, ms, measured_bytes, half=False):
     """Projection / backprojection against three references:
     * the per-angle-stream model (a design that streams the volume once per angle);
     * compulsory HBM bytes (the volume and the lines once) and, when the
@@ -203,12 +203,12 @@ def projection_report(cfg, kernel, ms, measured_bytes, bf16=False):
     nvox = cfg.nx * cfg.ny * cfg.nz
     samples = float(cfg.n_angles) * nvox
     if kernel == "project":
-        lds = samples * 4 * (2 if bf16 else 4)
+        lds = samples * 4 * (2 if half else 4)
     else:
-        lds = samples * 3 * (2 if bf16 else 4)
+        lds = samples * 3 * (2 if half else 4)
     pb = projection_bytes(cfg)
-    vol_b = 2 if bf16 and kernel == "project" else 4        # the mixed forward gathers a bf16 volume
-    line_b = 2 if bf16 and kernel == "backproject" else 4   # the mixed adjoint gathers fp16 lines
+    vol_b = 2 if half and kernel == "project" else 4        # the mixed forward gathers a bf16 volume
+    line_b = 2 if half and kernel == "backproject" else 4   # the mixed adjoint gathers fp16 lines
     compulsory = vol_b * nvox + line_b * cfg.n_lines * cfg.n_u
     t = ms * 1e-3
     out = {"ms": round(ms, 4),
@@ -725,7 +725,9 @@ def operator_leg(torch, plan, cfg, x, b, warmup, steps, with_mixed=True):
              "step_ms": step_times(torch, step16)}
     for k, v in kt16.items():
         if k in ("project", "backproject"):
-            mixed[k + "_bf16"] = projection_report(cfg, k, v, measured_traffic(cfg.name, k + "_mixed"), bf16=True)
+            # 16-bit gathers: a bf16 volume forward, fp16 lines backward
+            mixed[k + ("_bf16" if k == "project" else "_f16")] = projection_report(
+                cfg, k, v, measured_traffic(cfg.name, k + "_mixed"), half=True)
             continue
         a16 = fl / (v * 1e-3) / 1e12
         mixed[k] = {"ms": round(v, 4), "tflops": round(a16, 1), "mfma_frac_fp16": round(a16 / FP16_PEAK_TFLOPS, 4),

@@ -122,6 +122,9 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
                 acc[g] = MFMA32(Sf[4 * s4 + 1], v[1], acc[g]);
                 acc[g] = MFMA32(Sf[4 * s4 + 2], v[2], acc[g]);
                 acc[g] = MFMA32(Sf[4 * s4 + 3], v[3], acc[g]);
+                // one wave per SIMD: keep this load's issue point so the
+                // ring's later slots stay in flight through the long stream
+                if constexpr (PAIRS == kWidePairs) __builtin_amdgcn_sched_barrier(0);
             }
         }
     }

@@ -158,15 +158,6 @@ def cgls_path(run, op, seeds=tuple(range(101, 107)), select=None, eps_range=FP32
     return ClusterPath(lo, hi)
 
 
-def fp32_envelope(run, op, seeds=(11, 12, 13), eps=FP32_OP_EPS):
-    """Largest relative deviation between run(op) and run(perturbed op) over a
-    few seeds: how far an implementation whose operator is accurate to about
-    eps can drift from the FP64 iterate on this schedule."""
-    ref = run(op)
-    dev = max(rel_l2(run(PerturbedOperator(op, eps, s)), ref) for s in seeds)
-    return ref, dev
-
-
 def band_errors(got, want, g, axis=-1):
     """Relative L2 error of each kept harmonic band (the 2D + 1 bins around one
     harmonic), over all lines: got/want complex data [..., n_bins]."""
