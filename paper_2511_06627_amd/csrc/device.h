@@ -53,17 +53,21 @@ __device__ __forceinline__ BlockPos locate(const SigArgs &a)
 template <int PAIRS>
 __device__ __forceinline__ f32x16 pair_sum(float *xs, int parity, int pair, int half, int lane, const f32x16 &mine)
 {
-    float *slot = xs + ((parity * PAIRS + pair) * 2) * 16 * 64;
-    float *own = slot + half * 16 * 64;
-    const float *other = slot + (1 - half) * 16 * 64;
+    // 16-byte words, word q of lane l at q * 64 + l: four 128-bit LDS
+    // accesses each way, consecutive lanes on consecutive words
+    typedef float f32x4v __attribute__((ext_vector_type(4)));
+    f32x4v *slot = reinterpret_cast<f32x4v *>(xs) + ((parity * PAIRS + pair) * 2) * 4 * 64;
+    f32x4v *own = slot + half * 4 * 64;
+    const f32x4v *other = slot + (1 - half) * 4 * 64;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) own[j * 64 + lane] = mine[j];
+    for (int q = 0; q < 4; ++q) own[q * 64 + lane] = f32x4v{mine[4 * q], mine[4 * q + 1], mine[4 * q + 2], mine[4 * q + 3]};
     __syncthreads();
     f32x16 r;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const float o = other[j * 64 + lane];
-        r[j] = half == 0 ? mine[j] + o : o + mine[j];
+    for (int q = 0; q < 4; ++q) {
+        const f32x4v o = other[q * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[4 * q + e] = half == 0 ? mine[4 * q + e] + o[e] : o[e] + mine[4 * q + e];
     }
     return r;
 }

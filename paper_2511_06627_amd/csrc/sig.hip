@@ -60,7 +60,7 @@ constexpr int ring_size(int nl, int cap)
 template <int NUP, int GH, int PAIRS>
 __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
 {
-    __shared__ float xs[2 * PAIRS * 2 * 16 * 64];
+    __shared__ __align__(16) float xs[2 * PAIRS * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
 template <int NUP, int GH, int PAIRS>
 __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
 {
-    __shared__ float xs[2 * PAIRS * 2 * 16 * 64];
+    __shared__ __align__(16) float xs[2 * PAIRS * 2 * 16 * 64];
     const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;

@@ -39,6 +39,26 @@ __device__ __forceinline__ f16x8 to_f16x8(const f32x16 &v, int base)
     return r;
 }
 
+// N products whose table operands come from LDS: fragment j is read WIN
+// products ahead of its use, and a scheduling barrier after every product
+// keeps that distance, so an LDS read's latency is covered by the products
+// in between instead of stalling the one that needs it.
+template <int N, int WIN, class Frag, class Prod>
+__device__ __forceinline__ void lds_pipelined(Frag frag, Prod prod)
+{
+    constexpr int W = WIN < N ? WIN : N;
+    f16x8 w[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) w[j] = frag(j);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const f16x8 f = w[j % W];
+        if (j + W < N) w[j % W] = frag(j + W);
+        prod(j, f);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Per-chunk table staging.  The block copies each time chunk's table slices
 // (GEMM1's and GEMM2's) from HBM/L2 into LDS once, with every thread moving a
 // few 16-byte units; the waves then read their operand fragments from LDS.
@@ -153,17 +173,16 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
         nb.load(fg + (size_t)cn * fstride, tid);
         const f16x8 *ka = la + buf * UA + ka0;
         f32x16 S = 0.f;
-#pragma unroll
-        for (int i = 0; i < NKS; ++i) S = MFMA16(ka[i * 64], R[i], S);
+        // GH = 7 leaves no registers for eight fragments in flight at NUP = 256
+        lds_pipelined<NKS, GH >= 7 ? 4 : 8>([&](int i) { return ka[i * 64]; },
+                                            [&](int i, const f16x8 &f) { S = MFMA16(f, R[i], S); });
         if (more) ra.store(la + (buf ^ 1) * UA, tid);
         const f32x16 Sf = pair_sum<kWaves>(xs, buf, bp.pair, bp.half, lane, S);
         if (more) rb.store(lb + (buf ^ 1) * UB, tid);
         const f16x8 S16[2] = {to_f16x8(Sf, 0), to_f16x8(Sf, 8)};
         const f16x8 *fb = lb + buf * UB + fb0;
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-            for (int g = 0; g < GH; ++g) acc[g] = MFMA16(S16[hh], fb[(g * 2 + hh) * 64], acc[g]);
+        lds_pipelined<2 * GH, 4>([&](int j) { return fb[((j % GH) * 2 + j / GH) * 64]; },
+                                 [&](int j, const f16x8 &f) { acc[j % GH] = MFMA16(S16[j / GH], f, acc[j % GH]); });
     };
     int c = c0;
     for (; c + 1 < c1; c += 2) {
@@ -260,17 +279,14 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
         nb.load(kg + (size_t)cn * UB, tid);
         const f16x8 *fa = la + buf * UA + fa0;
         f32x16 Gt = 0.f;
-#pragma unroll
-        for (int i = 0; i < NF; ++i) Gt = MFMA16(fa[i * 64], Y[i], Gt);
+        lds_pipelined<NF, 6>([&](int i) { return fa[i * 64]; }, [&](int i, const f16x8 &f) { Gt = MFMA16(f, Y[i], Gt); });
         if (more) ra.store(la + (buf ^ 1) * UA, tid);
         const f32x16 Gf = pair_sum<kWaves>(xs, buf, bp.pair, bp.half, lane, Gt);
         if (more) rb.store(lb + (buf ^ 1) * UB, tid);
         const f16x8 G16[2] = {to_f16x8(Gf, 0), to_f16x8(Gf, 8)};
         const f16x8 *kb = lb + buf * UB + kb0;
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-            for (int pt = 0; pt < PTH; ++pt) racc[pt] = MFMA16(G16[hh], kb[(pt * 2 + hh) * 64], racc[pt]);
+        lds_pipelined<2 * PTH, 4>([&](int j) { return kb[((j % PTH) * 2 + j / PTH) * 64]; },
+                                  [&](int j, const f16x8 &f) { racc[j % PTH] = MFMA16(G16[j / PTH], f, racc[j % PTH]); });
     };
     int c = c0;
     for (; c + 1 < c1; c += 2) {
