@@ -23,7 +23,7 @@ Schedules:
              |s| <= 1e-12 |s_0|), so a test can state the schedule's error
              against x*.
 
-Usage: python tests/golden/make_clusters.py   (about 30 minutes on 8 cores)
+Usage: python tests/golden/make_clusters.py   (about 80 minutes on 8 cores)
 """
 import json
 import os
@@ -61,9 +61,7 @@ def path(lo, hi):
             "span": float(np.linalg.norm(mhi - mlo) / np.linalg.norm(mhi))}
 
 
-def main():
-    cfg = configs.REALISTIC_192
-    m2 = configs.MIXED_192
+def main(cfg=configs.REALISTIC_192, m2=configs.MIXED_192, dest=os.path.join(HERE, "cgls_clusters.json")):
     t0 = time.time()
     g = config_geometry(cfg)
     b, _ = oop.make_data(g, configs.make_phantom(cfg), cfg.noise, cfg.noise_seed)
@@ -109,11 +107,12 @@ def main():
     xs, its = timed(lambda: solvers.reference_minimiser(op, b, cfg.lam, tol=1e-12), "minimiser")
     out["xstar"] = {"tol": 1e-12, "iters": its, "sample": xs.ravel()[idx].tolist(),
                     "norm": float(np.linalg.norm(xs))}
+    xsf = xs.ravel()
     for name, (_, m) in zip(("lo", "hi"), levels):
-        out["mixed3x20"][name]["mean_to_xstar_full"] = float(np.linalg.norm(m - xs) / np.linalg.norm(xs))
+        out["mixed3x20"][name]["mean_to_xstar_full"] = float(np.linalg.norm(m.ravel() - xsf) / np.linalg.norm(xsf))
     print("mixed 3x20 cluster means vs x*: %.3e / %.3e" % (out["mixed3x20"]["lo"]["mean_to_xstar_full"],
                                                             out["mixed3x20"]["hi"]["mean_to_xstar_full"]), flush=True)
-    with open(os.path.join(HERE, "cgls_clusters.json"), "w") as f:
+    with open(dest, "w") as f:
         json.dump(out, f)
     print("done %.1fs" % (time.time() - t0), flush=True)
 

@@ -61,8 +61,7 @@ def amplitudes(x, blobs, shape):
     return np.array(out)
 
 
-def main():
-    cfg = configs.HDR_256
+def main(cfg=configs.HDR_256, dest=os.path.join(HERE, "hdr_reference.json")):
     t0 = time.time()
     g = config_geometry(cfg)
     ph = configs.make_phantom(cfg)
@@ -127,7 +126,7 @@ def main():
                    "amp_oracle": float(ao)} for (c, sg, a), ao in zip(blobs, amp)],
         "cluster": clusters,
     }
-    with open(os.path.join(HERE, "hdr_reference.json"), "w") as f:
+    with open(dest, "w") as f:
         json.dump(rec, f)
     print("done %.1fs" % (time.time() - t0), flush=True)
 
