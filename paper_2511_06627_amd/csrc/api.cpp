@@ -69,6 +69,7 @@ OpWs carve_op(const mpi3d_plan *pl, void *ws)
     w.in16 = (uint16_t *)(b + pl->ws_in16);
     w.rtb = (uint16_t *)(b + pl->ws_rtb);
     w.rtsc = (float *)(b + pl->ws_rtsc);
+    w.sig = (float *)(b + pl->ws_sig);
     return w;
 }
 
@@ -102,31 +103,32 @@ static int nsplit_of(const mpi3d_plan *pl, int prec, bool serve)
 static int rows_per_block(const mpi3d_plan *pl, int prec) { return kRowsPerWave * sig_cfg(pl, prec).pairs; }
 
 // The kernel jobs of one line job: one per line group (trajectory class of a
-// raster, or x- and z-drive lines) and line offset of the tensor PSF.  Group
-// g holds the lines of its map (class c: the lines (m, k) with k % n_classes
-// == c; dual drive: the x-drive lines, then the z-drive lines) and its PSF
-// tables; offset pass d reads the line d away among its angle's lines (x-drive:
-// z-rows; z-drive: detector columns) through table |d| of the group and writes
-// the block of split partial sums of offset d, which the reductions add with
-// the others.
+// raster, or x- and z-drive lines) and tensor-PSF pass.  Group g holds the
+// lines of its map (class c: the lines (m, k) with k % n_classes == c; dual
+// drive: the x-drive lines, then the z-drive lines) and its PSF tables.  Pass
+// e = 0..coup uses the group's table e and writes the block of split partial
+// sums of pass e: forward, it reads the symmetric line sums sigma_e (w->sig,
+// or the lines themselves without coupling); adjoint, every pass reads the
+// data and the reduction hands pass e of line l to lines l - e and l + e.
 static void line_jobs(const LineJob &lj, int prec, bool fwd, bool serve, std::vector<SigJob> &out)
 {
     const mpi3d_plan *pj = lj.pl;
     const long part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
     const long pass_stride =
         (long)nsplit_of(pj, prec, serve) * (fwd ? 1 : sig_cfg(pj, prec).ngroups) * part_stride;
+    const bool sym = fwd && pj->n_passes > 1;
     for (int gi = 0; gi < pj->n_line_groups; ++gi) {
         const mpi3d_plan::LineGroup &lg = pj->groups[gi];
-        for (int d = -lg.coup; d <= lg.coup; ++d) {
+        for (int e = 0; e <= lg.coup; ++e) {
             SigJob sj{};
-            sj.in = lj.in;
-            sj.in_stride = lj.in_stride;
-            sj.in16 = lj.w->in16;
+            sj.in = sym ? (const void *)(lj.w->sig + (size_t)e * pj->L * pj->nup) : (const void *)lj.in;
+            sj.in_stride = sym ? pj->nup : lj.in_stride;
+            sj.in16 = lj.w->in16 + (sym ? (size_t)e * pj->L * pj->in16_cols : 0);
             sj.in16_stride = pj->in16_cols;
-            sj.part = lj.w->part + (d + pj->pass_r) * pass_stride;
+            sj.part = lj.w->part + e * pass_stride;
             sj.part_stride = part_stride;
             sj.row_scale = lj.w->rowscale;
-            const size_t ko = (size_t)(lg.table + (d < 0 ? -d : d)) * pj->k_elems;
+            const size_t ko = (size_t)(lg.table + e) * pj->k_elems;
             sj.kf = pj->kf + ko;
             sj.ka = pj->ka + ko;
             sj.kf16 = pj->kf16 ? pj->kf16 + ko : nullptr;
@@ -136,24 +138,23 @@ static void line_jobs(const LineJob &lj, int prec, bool fwd, bool serve, std::ve
             sj.map_nz = lg.gnz;
             sj.map_off = lg.off;
             sj.map_step = lg.step;
-            sj.in_dz = d;
-            sj.in_nz = lg.cper;
-            sj.in_base = lg.cbase;
             out.push_back(sj);
         }
     }
 }
 
-static RowPasses row_passes(const mpi3d_plan *pl)
+static RowPasses row_passes(const mpi3d_plan *pl, bool fwd)
 {
     RowPasses rp{};
     rp.npass = pl->n_passes;
-    rp.rows = pl->pass_r;
     rp.nz = pl->nz;
     rp.zbase = pl->drive_axes == 2 ? pl->Lx : pl->L;
     rp.nzc = pl->nu;
     rp.rx = pl->groups[0].coup;
     rp.rz = pl->drive_axes == 2 ? pl->groups[1].coup : 0;
+    rp.lines = pl->L;
+    rp.pitch = fwd ? pl->nbp2 : pl->nup;
+    rp.fwd = fwd ? 1 : 0;
     return rp;
 }
 
@@ -163,6 +164,9 @@ static RowPasses row_passes(const mpi3d_plan *pl)
 static hipError_t row_scale16(const mpi3d_plan *pj, bool fwd, const float *in, int in_stride, const OpWs &w,
                               hipStream_t st)
 {
+    if (fwd && pj->n_passes > 1)   // every pass's symmetric line sums
+        return launch_row_scale(pj->n_passes * pj->L, pj->nu, pj->nup, w.sig, nullptr, w.rowscale, w.in16, pj->nup,
+                                pj->in16_cols, st);
     if (fwd)
         return launch_row_scale(pj->L, pj->nu, in_stride, in, nullptr, w.rowscale, w.in16, pj->nup, pj->in16_cols,
                                 st);
@@ -190,6 +194,11 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
     for (int j = 0; j < n; ++j) {
         const mpi3d_plan *pj = jobs[j].pl;
         if (pj->line_key != pl->line_key) return MPI3D_EINVAL;
+        if (fwd && pj->n_passes > 1) {
+            // tensor PSF: the symmetric line sums every forward pass reads
+            TRY(launch_sym_lines(jobs[j].in, jobs[j].in_stride, pj->nu, pj->nup, row_passes(pj, true),
+                                 jobs[j].w->sig, st));
+        }
         if (prec == MPI3D_MIXED) {
             // per-line power-of-two scales and the scaled fp16 operand lines
             TRY(row_scale16(pj, fwd, jobs[j].in, jobs[j].in_stride, *jobs[j].w, st));
@@ -222,7 +231,7 @@ static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
     const bool mixed = prec == MPI3D_MIXED;
     TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->n_passes * nsplit_of(pl, prec, serve), pl->L * pl->nbp2, w.part,
                           mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
-                          norm_parts, nnorm, st, row_passes(pl)));
+                          norm_parts, nnorm, st, row_passes(pl, true)));
     return MPI3D_OK;
 }
 
@@ -235,7 +244,7 @@ static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
     TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride,
                                     pl->n_passes * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
                                     pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st,
-                                    row_passes(pl)));
+                                    row_passes(pl, false)));
     return MPI3D_OK;
 }
 
@@ -249,7 +258,7 @@ static int lines_to_volume(const mpi3d_plan *pl, int prec, const OpWs &w, bool s
                            double lambda, double *parts, int *nparts, hipStream_t st, const float *x_add = nullptr)
 {
     if (prec == MPI3D_MIXED) {
-        const RowPasses rp = row_passes(pl);
+        const RowPasses rp = row_passes(pl, false);
         if (pl->drive_axes == 2) {
             TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
             TRY(launch_fold_zlines(pl, w.rt, st));

@@ -44,7 +44,9 @@ constexpr int proj_pitch(int nx) { return (nx + 2) | 1; }
 
 // One batch segment of FFL lines sharing the same line tables.
 struct SigJob {
-    const void *in;        // fwd: projections [lines][nup] (f32); adj: data [lines][2nb] (f32)
+    // fwd: projections [lines][nup], or one tensor-PSF pass's symmetric line
+    // sums (f32); adj: data [lines][2nb] (f32)
+    const void *in;
     float *part;           // partial sums per line, see kernels
     float *row_scale;      // mixed: per-line power-of-two scale (row_scale kernel)
     const float *kf, *ka;  // this job's PSF tables (fp32; its lines' trajectory class)
@@ -60,22 +62,7 @@ struct SigJob {
     // Job row r is line (r / map_per) * map_nz + map_off + map_step * (r % map_per)
     // of the buffers above (identity: map_per >= rows, map_off 0, map_step 1).
     int map_per, map_nz, map_off, map_step;
-    // Line coupling (tensor PSF): the input of line l = in_base + m * in_nz + k
-    // is line l + in_dz, or zero when k + in_dz is outside [0, in_nz) (x-drive
-    // lines couple across the z-rows of their angle, z-drive lines across its
-    // detector columns); in_dz = 0: none.
-    int in_dz, in_nz;
-    long in_base;
 };
-
-// Input line of job row r's line l (or -1 when the shifted line is outside
-// its angle's lines).
-__host__ __device__ inline long job_input_line(const SigJob &j, long l)
-{
-    if (j.in_dz == 0) return l;
-    const int k = (int)((l - j.in_base) % j.in_nz) + j.in_dz;
-    return (k >= 0 && k < j.in_nz) ? l + j.in_dz : -1;
-}
 
 __host__ __device__ inline long job_line(const SigJob &j, int r)
 {
@@ -173,8 +160,12 @@ struct mpi3d_plan {
     // job row r is line (r / per) * gnz + off + step * (r % per).  Under the
     // tensor PSF a group's lines couple to the lines within `coup` of them
     // among the `cper` lines of their angle (x-drive: the z-rows; z-drive: the
-    // detector columns), the group's lines starting at `cbase`; offset d uses
-    // table `table + |d|`.
+    // detector columns), the group's lines starting at `cbase`.  The PSF entry
+    // of offset d depends on |d| only (table `table + |d|`), so the signal
+    // stage runs one pass per e = 0..coup: pass e contracts table e with the
+    // symmetric sums sigma_e(l) = rho(l + e) + rho(l - e) (sigma_0 = rho; a
+    // line outside the angle counts as zero), and its adjoint pass hands
+    // line l's result to lines l + e and l - e in the reduction.
     struct LineGroup {
         int rows, per, gnz, off, step, table;
         int coup, cper;
@@ -182,7 +173,7 @@ struct mpi3d_plan {
     } groups[2];
     int n_line_groups;
     int pass_r;                   // largest coupling range of the groups
-    int n_passes;                 // blocks of split partial sums: 2 pass_r + 1 line offsets
+    int n_passes;                 // blocks of split partial sums: pass_r + 1 (e = 0..pass_r)
     size_t k_elems;
     double raster_sweep;
     float *col_scale;     // [nbp2] mixed forward output scale per column
@@ -192,7 +183,7 @@ struct mpi3d_plan {
     size_t gt_elems = 0;  // floats per line matrix
     rocblas_handle blas = nullptr;   // precomposed: GEMM handle
     // operator workspace layout (bytes from ws base)
-    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, ws_rtb, ws_rtsc, op_ws_bytes;
+    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, ws_rtb, ws_rtsc, ws_sig, op_ws_bytes;
     int in16_cols;        // halves per fp16 operand line: max(nup, nbp2)
     // solver workspace layout
     size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, sw_v, solve_ws_bytes;
@@ -225,15 +216,25 @@ int sig_fwd_supported(int nup, int gct, int precision, int pairs);
 int sig_adj_supported(int nup, int gct, int precision, int pairs);
 
 // Reductions and vector kernels (vec.hip).  The split reductions sum nparts
-// partial blocks; rp describes the tensor PSF's offset passes among them
-// (npass = 2 rows + 1 blocks of nparts / npass, pass p having read line
-// row + p - rows of the same angle's nz), which the mixed path's per-line
-// scales need (npass = 1: no coupling).
+// partial blocks; rp describes the tensor PSF's passes among them (npass
+// blocks of nparts / npass, pass e = 0..npass-1 for offset e; npass = 1: no
+// coupling).  Forward: line l's value is the sum of its passes e <= its
+// group's coupling range.  Adjoint: line l collects pass 0 of line l and
+// pass e of lines l - e and l + e of its angle.  Row scales (mixed path) are
+// those of the lines each pass read: forward [npass][lines], adjoint [lines].
 struct RowPasses {
-    int npass, rows, nz;   // passes (2 rows + 1), x-drive lines per angle
-    long zbase;            // first z-drive line (L when there are none)
+    int npass, nz;         // passes; x-drive lines per angle
+    long zbase;            // first z-drive line (lines when there are none)
     int nzc, rx, rz;       // z-drive lines per angle; coupling ranges of x- and z-drive lines
+    long lines;            // lines per pass
+    int pitch;             // floats between consecutive lines of a partial block
+    int fwd;               // 1: forward reduction, 0: adjoint
 };
+// The forward passes' inputs: sig[e][l] = rho(l + e) + rho(l - e) within l's
+// angle (sig[0] = rho), over nup columns (zero past nu), for e = 0..npass-1
+// (zero beyond the line's coupling range); rho has stride in_stride.
+hipError_t launch_sym_lines(const float *rho, int in_stride, int nu, int nup, RowPasses rp, float *sig,
+                            hipStream_t st);
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
                              const float *row_scale, const float *col_scale, double scale, const float *b_sub,
                              float *out, double *norm_parts, int *nnorm, hipStream_t st, RowPasses rp);
@@ -301,9 +302,10 @@ struct OpWs {
     float *rt;        // projections [L][nup]
     float *part;      // split partial sums
     double *norm;     // spare norm partials
-    float *rowscale;  // [L] per-line scales of the fp16 path
+    float *rowscale;  // [n_passes][L] per-line scales of the fp16 path (adjoint: [L])
     uint16_t *xb;     // bf16 copy of a volume (mixed path)
-    uint16_t *in16;   // [L][in16_cols] fp16 operand lines of the mixed signal stage
+    uint16_t *in16;   // [n_passes][L][in16_cols] fp16 operand lines of the mixed signal stage
+    float *sig;       // [n_passes][L][nup] tensor PSF: the passes' symmetric line sums (forward)
     uint16_t *rtb;    // [L][nup] fp16 lines of the mixed adjoint (its backprojection gathers)
     float *rtsc;      // [L] their per-line inverse scales
 };

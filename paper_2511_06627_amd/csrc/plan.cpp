@@ -243,7 +243,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     pl->psf_rows = psf_rows;
     pl->n_ktab = n_ktab;
     pl->pass_r = std::max(psf_rows, psf_cols);
-    pl->n_passes = 2 * pl->pass_r + 1;
+    pl->n_passes = pl->pass_r + 1;
     pl->raster_sweep = g->raster_sweep;
     pl->nup = round_up(nu, 64);
     pl->ntp = round_up(g->n_t, kChunk);
@@ -651,12 +651,16 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
                                         std::max<size_t>(pl->nbp2, (size_t)c.ngroups * pl->nup));
         pl->ws_part = put(sizeof(float) * (size_t)pl->n_passes * pl->L * parts);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
-        pl->ws_rowscale = put(sizeof(float) * pl->L);
+        // per tensor-PSF pass: the forward's symmetric line sums, their
+        // scales and fp16 operands (one block each without coupling)
+        const size_t np = pl->n_passes;
+        pl->ws_rowscale = put(sizeof(float) * np * pl->L);
         pl->ws_xb = put(mixed ? sizeof(uint16_t) * pl->nvox : 0);
         pl->in16_cols = std::max(pl->nup, pl->nbp2);
-        pl->ws_in16 = put(mixed ? sizeof(uint16_t) * pl->L * pl->in16_cols : 0);
+        pl->ws_in16 = put(mixed ? sizeof(uint16_t) * np * pl->L * pl->in16_cols : 0);
         pl->ws_rtb = put(mixed ? sizeof(uint16_t) * pl->L * pl->nup : 0);
         pl->ws_rtsc = put(mixed ? sizeof(float) * pl->L : 0);
+        pl->ws_sig = put(np > 1 ? sizeof(float) * np * pl->L * pl->nup : 0);
         pl->op_ws_bytes = align256(o);
     }
     {

@@ -66,8 +66,8 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
-    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
-    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    // input line of this lane's row (-1: past the job's rows, zero input)
+    const long il = rok ? job_line(job, r) : -1;
     const bool iok = il >= 0;
     constexpr int NK = NUP / 16;          // K float4 loads per chunk (this half)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk
@@ -158,8 +158,8 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
-    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
-    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    // input line of this lane's row (-1: past the job's rows, zero input)
+    const long il = rok ? job_line(job, r) : -1;
     const bool iok = il >= 0;
     constexpr int PTH = NUP / 64;         // detector tiles per half
     constexpr int NF = 4 * GH;            // F float4 loads per chunk (GEMM1)

@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kSigThreads) void sig_fwd_f16(SigArgs a)
     const int lane = tid & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
-    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
-    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    // input line of this lane's row (-1: past the job's rows, zero input)
+    const long il = rok ? job_line(job, r) : -1;
     const bool iok = il >= 0;
     constexpr int NKS = NUP / 32;         // fp16 K steps per half (16 detector samples each)
 
@@ -225,8 +225,8 @@ __global__ __launch_bounds__(kSigThreads) void sig_adj_f16(SigArgs a)
     const int lane = tid & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
     const bool rok = r < job.rows;
-    // input line of this lane's row (-1: a coupled row outside its angle, zero input)
-    const long il = rok ? job_input_line(job, job_line(job, r)) : -1;
+    // input line of this lane's row (-1: past the job's rows, zero input)
+    const long il = rok ? job_line(job, r) : -1;
     const bool iok = il >= 0;
     constexpr int PTH = NUP / 64;
     constexpr int NF = 2 * GH;            // fp16 F steps per chunk (16 columns each)

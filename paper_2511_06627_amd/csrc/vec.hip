@@ -47,12 +47,14 @@ __device__ __forceinline__ double sum_splits(const float *__restrict__ pp, int n
     return v;
 }
 
-// out[row][c] = sign * sum_s part[s][row][c] * col_scale[c] / row_scale[row] (+ b_sub)
 // Sum of the split partials of one output element, undoing the mixed path's
 // per-line scale.  Without row coupling: the sum, divided by the line's own
-// scale.  With the tensor PSF's 2R + 1 offset passes (each a block of
-// nparts / npass splits, pass p having read line row + p - R): every pass's
-// sum divided by the scale of the line it read, in pass order.
+// scale.  With the tensor PSF's passes (npass blocks of nparts / npass
+// splits, pass e for offset e): forward, the line's passes e up to its
+// coupling range, each divided by the scale of the symmetric sum that pass
+// read (row_scale[e * lines + row]); adjoint, pass 0 of the line itself and
+// pass e of the lines e before and after it within its angle, each divided
+// by the scale of that line's data (row_scale[line]).  In pass order.
 __device__ __forceinline__ double sum_unscaled(const float *__restrict__ pp, int nparts, long stride, long row,
                                                const float *__restrict__ row_scale, RowPasses rp)
 {
@@ -63,20 +65,27 @@ __device__ __forceinline__ double sum_unscaled(const float *__restrict__ pp, int
     const int per = nparts / rp.npass;
     const bool zl = row >= rp.zbase;
     const int nline = zl ? rp.nzc : rp.nz;
-    const int R = zl ? rp.rz : rp.rx;
+    const int R = min(zl ? rp.rz : rp.rx, rp.npass - 1);
     const int k = (int)(zl ? (row - rp.zbase) % rp.nzc : row % rp.nz);
     double v = 0.0;
-    for (int p = 0; p < rp.npass; ++p) {
-        const int d = p - rp.rows;
-        // passes beyond this line's coupling, or reading past its angle's
-        // lines, were not written for it
-        if (d < -R || d > R || k + d < 0 || k + d >= nline) continue;
-        const double t = sum_splits(pp + (long)p * per * stride, per, stride);
-        v += row_scale ? t / (double)row_scale[row + d] : t;
+    for (int e = 0; e <= R; ++e) {
+        const float *pe = pp + (long)e * per * stride;
+        if (rp.fwd) {
+            const double t = sum_splits(pe, per, stride);
+            v += row_scale ? t / (double)row_scale[(long)e * rp.lines + row] : t;
+            continue;
+        }
+        for (int sg = e == 0 ? 1 : -1; sg <= 1; sg += 2) {
+            const int d = sg * e;
+            if (k + d < 0 || k + d >= nline) continue;
+            const double t = sum_splits(pe + (long)d * rp.pitch, per, stride);
+            v += row_scale ? t / (double)row_scale[row + d] : t;
+        }
     }
     return v;
 }
 
+// out[row][c] = sign * sum_s part[s][row][c] * col_scale[c] / row_scale[row] (+ b_sub)
 __global__ __launch_bounds__(kThreads) void reduce_fwd_kernel(long rows, int nb2, int nbp2, int nparts,
                                                                long part_stride, const float *__restrict__ part,
                                                                const float *__restrict__ row_scale,
@@ -122,6 +131,38 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
             o = (float)v;
         }
         out[idx] = o;
+    }
+}
+
+// The tensor PSF's forward pass inputs: sig[e][row] = rho(row + e) +
+// rho(row - e) for the lines of row's angle (rows outside it count as zero;
+// sig[0] = rho), zero for e beyond the row's coupling range and for columns
+// past nu.
+__global__ __launch_bounds__(kThreads) void sym_lines_kernel(const float *__restrict__ rho, int in_stride, int nu,
+                                                              int nup, RowPasses rp, float *__restrict__ sig)
+{
+    const long n = (long)rp.npass * rp.lines * nup;
+    for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
+        const int p = (int)(idx % nup);
+        const long t = idx / nup;
+        const long row = t % rp.lines;
+        const int e = (int)(t / rp.lines);
+        float v = 0.f;
+        if (p < nu) {
+            if (e == 0) {
+                v = rho[row * in_stride + p];
+            } else {
+                const bool zl = row >= rp.zbase;
+                const int nline = zl ? rp.nzc : rp.nz;
+                const int R = zl ? rp.rz : rp.rx;
+                const int k = (int)(zl ? (row - rp.zbase) % rp.nzc : row % rp.nz);
+                if (e <= R) {
+                    if (k + e < nline) v += rho[(row + e) * in_stride + p];
+                    if (k - e >= 0) v += rho[(row - e) * in_stride + p];
+                }
+            }
+        }
+        sig[idx] = v;
     }
 }
 
@@ -467,6 +508,14 @@ hipError_t launch_lines16(long rows, int nu, int nup, int nparts, long part_stri
 }
 
 
+
+hipError_t launch_sym_lines(const float *rho, int in_stride, int nu, int nup, RowPasses rp, float *sig,
+                            hipStream_t st)
+{
+    const int g = grid_for((long)rp.npass * rp.lines * nup, kReduceBlocks);
+    hipLaunchKernelGGL(sym_lines_kernel, dim3(g), dim3(kThreads), 0, st, rho, in_stride, nu, nup, rp, sig);
+    return hipGetLastError();
+}
 
 hipError_t launch_row_scale(long rows, int ncols, int in_stride, const float *in, const float *col_scale, float *out,
                             uint16_t *out16, int out16_cols, int out16_stride, hipStream_t st)
