@@ -140,8 +140,9 @@ typedef struct {
                                     |p - p'| <= min(R, n_u - 1) through the zz entry, the same
                                     function with the drive axis exchanged (along-drive
                                     offset xi_z - z_k, transverse offset p - p').  0 = the
-                                    collinear PSF.  Each line offset costs one more signal
-                                    pass (MPI3D_PRECOMPOSED: one more GEMM); with
+                                    collinear PSF.  h depends on |dz| only, so the time-domain
+                                    path runs R + 1 signal passes over symmetric line sums
+                                    (MPI3D_PRECOMPOSED: one GEMM per offset); with
                                     raster_sweep != 0 it is MPI3D_ENOTSUP */
     int32_t drive_axes;          /* 1 (or 0): the x-drive scan.  2: every angle is also
                                     scanned with the drive and receive coil along z

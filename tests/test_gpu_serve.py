@@ -22,22 +22,27 @@ def torch_mod():
     return torch
 
 
-# Line-table classes (n_u, T, bands, raster sweep S, drive axes): A-class
-# geometries differ in nz / M but share line tables; B has another T; the
-# R-class raster scans (two PSF tables each, odd and even nz) share theirs; D1
-# is a dual-drive scan (x- and z-drive lines).
+# Line-table classes (n_u, T, bands, raster sweep S, drive axes, tensor-PSF
+# rows R): A-class geometries differ in nz / M but share line tables; B has
+# another T; the R-class raster scans (two PSF tables each, odd and even nz)
+# share theirs; D1 is a dual-drive scan (x- and z-drive lines); the T-class
+# tensor-PSF scans (R + 1 symmetric passes, their line sums in each request's
+# own workspace) share theirs, one with both drives.
 GEOS = {
-    "A1": (48, 48, 12, 6, 2048, 1, 12, 2, 0.0, 1),
-    "A2": (48, 48, 20, 9, 2048, 1, 12, 2, 0.0, 1),
-    "B1": (64, 64, 16, 8, 4096, 1, 16, 3, 0.0, 1),
-    "R1": (48, 48, 7, 5, 2048, 1, 12, 2, 20.0, 1),
-    "R2": (48, 48, 10, 6, 2048, 1, 12, 2, 20.0, 1),
-    "D1": (48, 48, 12, 5, 2048, 1, 12, 2, 0.0, 2),
+    "A1": (48, 48, 12, 6, 2048, 1, 12, 2, 0.0, 1, 0),
+    "A2": (48, 48, 20, 9, 2048, 1, 12, 2, 0.0, 1, 0),
+    "B1": (64, 64, 16, 8, 4096, 1, 16, 3, 0.0, 1, 0),
+    "R1": (48, 48, 7, 5, 2048, 1, 12, 2, 20.0, 1, 0),
+    "R2": (48, 48, 10, 6, 2048, 1, 12, 2, 20.0, 1, 0),
+    "D1": (48, 48, 12, 5, 2048, 1, 12, 2, 0.0, 2, 0),
+    "T1": (48, 48, 9, 5, 2048, 1, 12, 2, 0.0, 1, 2),
+    "T2": (48, 48, 13, 4, 2048, 1, 12, 2, 0.0, 1, 2),
+    "T3": (48, 48, 11, 4, 2048, 1, 12, 2, 0.0, 2, 2),
 }
 
 
 def _request(name, seed):
-    nx, ny, nz, M, T, klo, khi, D, S, axes = GEOS[name]
+    nx, ny, nz, M, T, klo, khi, D, S, axes, R = GEOS[name]
     P = T / 256 + 1 / 3
     a = 8.0 if S else 0.0          # a raster scan's drive covers a third of the fast axis
     g = oracle_geometry(nx, ny, nz, M, T, P, 3.0, klo, khi, D)
@@ -45,11 +50,12 @@ def _request(name, seed):
         g.drive_amp, g.raster_sweep = a, S
     if axes == 2:
         g.drive_axes, g.drive_amp_z = 2, nz / 2.0
+    g.psf_rows = R
     g = oop.normalised(g, iters_min=30, rtol=1e-9)
     x = np.random.default_rng(seed).uniform(0, 1, (nz, ny, nx))
     b = oop.forward(g, x).astype(np.complex64)
     geo = dict(nx=nx, ny=ny, nz=nz, n_angles=M, n_t=T, drive_cycles=P, psf_width=3.0, harm_lo=klo, harm_hi=khi,
-               half_band=D, op_scale=g.op_scale, drive_amp=a, raster_sweep=S, drive_axes=axes)
+               half_band=D, op_scale=g.op_scale, drive_amp=a, raster_sweep=S, drive_axes=axes, psf_rows=R)
     return g, geo, b
 
 
@@ -107,7 +113,7 @@ def test_continuous_batching_loop(torch_mod, reqs):
     equal to the same requests solved alone."""
     from paper_2511_06627_amd.serve import ContinuousBatcher, GpuExecutor, Request, summarize
     rng = np.random.default_rng(3000)
-    names = ["A1", "B1", "R1", "A2", "D1", "R2", "A1", "B1", "A2"]
+    names = ["A1", "B1", "R1", "T1", "A2", "D1", "T3", "R2", "A1", "T2", "B1", "A2"]
     sched = dict(precision="mixed", refine_sweeps=2, inner_iters=4)
     rq = []
     t = 0.0
@@ -134,29 +140,3 @@ def test_continuous_batching_loop(torch_mod, reqs):
         p = Plan(precisions=("fp32", "mixed"), **r.geometry)
         alone = _run_states(torch_mod, {"x": p}, ["x"], {"x": (None, r.geometry, r.b)}, sched)["x"]
         assert np.array_equal(o.x, alone.cpu().numpy()), r.rid
-
-
-def test_tensor_psf_request_served_fp32(torch_mod, plans, reqs):
-    """A tensor-PSF scan (2R + 1 signal passes per application) served in a
-    batch with others: bitwise the same as alone, and the oracle's CGLS."""
-    from paper_2511_06627_amd.plan import Plan
-    nx, ny, nz, M, T = 40, 40, 8, 5, 2048
-    P = T / 256 + 1 / 3
-    g = oracle_geometry(nx, ny, nz, M, T, P, 3.0, 1, 12, 2)
-    g.psf_rows = 2
-    g = oop.normalised(g, iters_min=30, rtol=1e-9)
-    b = oop.forward(g, np.random.default_rng(9).uniform(0, 1, (nz, ny, nx))).astype(np.complex64)
-    geo = dict(nx=nx, ny=ny, nz=nz, n_angles=M, n_t=T, drive_cycles=P, psf_width=3.0, harm_lo=1, harm_hi=12,
-               half_band=2, op_scale=g.op_scale, psf_rows=2)
-    allp = dict(plans)
-    allp["T1"] = Plan(precisions=("fp32",), **geo)
-    allr = dict(reqs)
-    allr["T1"] = (g, geo, b)
-    sched = dict(precision="fp32", iters=4)
-    alone = _run_states(torch_mod, allp, ["T1"], allr, sched)["T1"]
-    mixed = _run_states(torch_mod, allp, ["A1", "T1", "D1"], allr, sched)["T1"]
-    assert torch_mod.equal(alone, mixed)
-    want = solvers.cgls(oop.Operator(g, precomposed=True), b.astype(np.complex128), 1e-3, 4)
-    err = rel_l2(alone.cpu().numpy(), want)
-    _log("served tensor cgls 4 rel err %.3e" % err)
-    assert err <= 1e-5
