@@ -118,6 +118,7 @@ def cpu_baseline_leg(cfg, want_minimiser=False, sample_seconds=15.0, small_cfg=N
         xs, it = solvers.reference_minimiser(oop.Operator(g, precomposed=True), out["b"].astype(np.complex128),
                                              cfg.lam, tol=1e-9)
         out["xstar"], out["xstar_iters"] = xs, it
+        out["xstar_seconds"] = round(time.time() - t0, 2)
         log("oracle minimiser: %d CGLS iterations, %.1fs" % (it, time.time() - t0))
     return out
 
@@ -667,6 +668,10 @@ def realistic_leg(torch, args, cfg, small, cpu, inputs):
     out["time_to_solve"] = tts
     if cpu is not None:
         out["oracle_small"] = cpu.get("oracle_small")
+        # the oracle beside it on this scan: its A then A^T rate (time-domain
+        # form, a few applications) and its minimiser solve (CGLS to 1e-9)
+        out["oracle"] = {"AtA": cpu.get("cpu_baseline"), "minimiser_cgls_iters": cpu.get("xstar_iters"),
+                         "minimiser_seconds": cpu.get("xstar_seconds")}
     return out
 
 
@@ -953,7 +958,7 @@ def main():
         if do_head:
             cpu_head = hdr_cpu_leg(sample_seconds=args.cpu_seconds)
         if do_extras:
-            cpu_real = cpu_baseline_leg(real, want_minimiser=not args.no_tts, sample_seconds=0.0,
+            cpu_real = cpu_baseline_leg(real, want_minimiser=not args.no_tts, sample_seconds=5.0,
                                         small_cfg=None if args.skip_small else small)
 
     import numpy as np
