@@ -302,8 +302,13 @@ int mpi3d_solve(const mpi3d_plan *plan, const float *b_dev, float *x_dev, const 
  * between states whose plans have the same line geometry (n_u, n_t, bins,
  * psf, drive): their FFL lines are concatenated into one launch.  Each
  * line's arithmetic does not depend on which other states share the launch,
- * so a request's result is bitwise the same alone or batched.  States run CGLS
- * schedules (solver MOMENTUM is MPI3D_ENOTSUP here).
+ * so a request's result is bitwise the same alone or batched.  Groups of
+ * different line geometry, step kind or precision touch disjoint states and
+ * run on up to four streams: `stream` and a per-device pool of non-blocking
+ * streams created on first use (default priority), which wait for `stream`
+ * at the step's start and which `stream` waits for at its end, so the step
+ * is ordered on `stream`.  Steps on one device must not overlap.  States run
+ * CGLS schedules (solver MOMENTUM is MPI3D_ENOTSUP here).
  */
 typedef struct mpi3d_state mpi3d_state;
 int mpi3d_state_create(const mpi3d_plan *plan, const float *b_dev, float *x_dev,

@@ -11,6 +11,7 @@
 // arithmetic depends only on its own data and the class tables, so a
 // request's iterates are bitwise the same whether it runs alone or batched.
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -174,6 +175,53 @@ int run_group(mpi3d_state *const *g, int n, StepKind kind, int prec, hipStream_t
 
 }  // namespace
 
+namespace {
+
+// Groups of one batch step touch disjoint states (each request owns its
+// data, volume and workspace; plan tables are only read), so they may run
+// concurrently: group g goes to stream g % kServeStreams of the step, stream
+// 0 being the caller's and the others a per-device pool of non-blocking
+// streams at the default priority.  The pool streams first wait for the
+// caller's stream (an event recorded at the step's start) and the caller's
+// stream then waits for each of them (an event recorded after its last
+// group), so to the caller the step is ordered on `stream` as before.  Small
+// requests, whose launches fill few CUs, then overlap with other classes.
+constexpr int kServeStreams = 4;
+
+struct StreamPool {
+    bool ready = false, failed = false;
+    hipStream_t s[kServeStreams - 1] = {};
+    hipEvent_t start = nullptr;
+    hipEvent_t done[kServeStreams - 1] = {};
+};
+
+std::mutex g_pool_mu;
+StreamPool g_pools[64];
+
+// The current device's pool (created on first use), or null when it cannot
+// be created: the step then runs on the caller's stream alone.
+StreamPool *stream_pool(int dev)
+{
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    StreamPool &p = g_pools[dev];
+    if (p.failed) return nullptr;
+    if (!p.ready) {
+        bool ok = hipEventCreateWithFlags(&p.start, hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; ok && k < kServeStreams - 1; ++k)
+            ok = hipStreamCreateWithFlags(&p.s[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&p.done[k], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            p.failed = true;
+            return nullptr;
+        }
+        p.ready = true;
+    }
+    return &p;
+}
+
+}  // namespace
+
 extern "C" int mpi3d_batch_step(mpi3d_state *const *states, int32_t n, void *stream)
 {
     if (n < 0 || (n > 0 && !states)) return MPI3D_EINVAL;
@@ -190,28 +238,53 @@ extern "C" int mpi3d_batch_step(mpi3d_state *const *states, int32_t n, void *str
     if (prev != dev) (void)hipSetDevice(dev);
     hipStream_t st = (hipStream_t)stream;
 
+    // the step's groups: states of one line class, step kind and precision
+    struct Group {
+        std::vector<mpi3d_state *> s;
+        StepKind kind;
+        int prec;
+    };
+    std::vector<Group> groups;
     std::vector<char> taken(n, 0);
-    int rc = MPI3D_OK;
-    for (int i = 0; i < n && rc == MPI3D_OK; ++i) {
+    for (int i = 0; i < n; ++i) {
         if (taken[i]) continue;
         int prec_i = 0;
         const StepKind kind = states[i]->next(&prec_i);
         taken[i] = 1;
         if (kind == STEP_NONE) continue;
-        mpi3d_state *group[kMaxJobs];
-        int ng = 0;
-        group[ng++] = states[i];
-        for (int j = i + 1; j < n && ng < kMaxJobs; ++j) {
+        Group g{{states[i]}, kind, prec_i};
+        for (int j = i + 1; j < n && (int)g.s.size() < kMaxJobs; ++j) {
             if (taken[j]) continue;
             int prec_j = 0;
             const StepKind kj = states[j]->next(&prec_j);
             if (kj == kind && prec_j == prec_i && states[j]->pl->line_key == states[i]->pl->line_key) {
-                group[ng++] = states[j];
+                g.s.push_back(states[j]);
                 taken[j] = 1;
             }
         }
-        rc = run_group(group, ng, kind, prec_i, st);
-        for (int k = 0; k < ng; ++k) ++group[k]->steps;
+        groups.push_back(std::move(g));
+    }
+
+    StreamPool *pool = groups.size() > 1 ? stream_pool(dev) : nullptr;
+    const int nst = pool ? std::min<int>(kServeStreams, (int)groups.size()) : 1;
+    int rc = MPI3D_OK;
+    if (nst > 1) {
+        if (hipEventRecord(pool->start, st) != hipSuccess) rc = MPI3D_EDEVICE;
+        for (int k = 1; rc == MPI3D_OK && k < nst; ++k)
+            if (hipStreamWaitEvent(pool->s[k - 1], pool->start, 0) != hipSuccess) rc = MPI3D_EDEVICE;
+    }
+    for (size_t gi = 0; gi < groups.size() && rc == MPI3D_OK; ++gi) {
+        Group &g = groups[gi];
+        const int k = (int)(gi % nst);
+        rc = run_group(g.s.data(), (int)g.s.size(), g.kind, g.prec, k == 0 ? st : pool->s[k - 1]);
+        for (mpi3d_state *s : g.s) ++s->steps;
+    }
+    // join: the caller's stream waits for every pool stream used (also after
+    // a failure, so nothing enqueued stays unordered)
+    for (int k = 1; k < nst; ++k) {
+        if (hipEventRecord(pool->done[k - 1], pool->s[k - 1]) != hipSuccess ||
+            hipStreamWaitEvent(st, pool->done[k - 1], 0) != hipSuccess)
+            rc = rc ? rc : MPI3D_EDEVICE;
     }
     if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
     return rc;
