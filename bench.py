@@ -245,14 +245,20 @@ def step_times(torch, step, n=20):
     return {"median": round(float(np.median(ts)), 4), "p99": round(float(np.percentile(ts, 99)), 4), "n": n}
 
 
+# Library sources that do not take part in an operator application (the
+# serving scheduler, the no-allocation entry point): outside the hash below.
+HASH_EXCLUDED = ("serve.cpp", "noalloc.cpp")
+
+
 def kernel_source_hash():
-    """sha256 over the library's kernel and launch sources: HBM traffic taken
-    from counters is only valid for the code it was measured on."""
+    """sha256 over the library's kernel and launch sources of the operator
+    (kernels, launch configuration, line jobs): HBM traffic taken from
+    counters is only valid for the code it was measured on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2511_06627_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".cpp", ".h")):
+        if name.endswith((".hip", ".cpp", ".h")) and name not in HASH_EXCLUDED:
             h.update(name.encode())
             h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()
