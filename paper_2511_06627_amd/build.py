@@ -18,7 +18,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # keep the compiler away from packed fp32 vector ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
-SOURCES = ["plan.cpp", "api.cpp", "serve.cpp", "noalloc.cpp", "proj.hip", "sig.hip", "sig16.hip", "vec.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "serve.cpp", "noalloc.cpp", "proj.hip", "sig.hip", "sig16.hip", "vec.hip", "gemm.hip"]
 
 
 def _compile(src):
@@ -36,8 +36,7 @@ def build(verbose=True):
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-L/opt/rocm/lib", "-lrocblas",
-                                                                                       "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-6000:])

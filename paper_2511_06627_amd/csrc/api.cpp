@@ -295,8 +295,8 @@ static int project_into(const mpi3d_plan *pl, int prec, const float *x, const ui
 }
 
 // Precomposed signal stage: data[l] = c_A G_t rho(l) for every line l, or
-// lines[l] = c_A sum G_t^T data(l), as float32 GEMMs (rocBLAS, column-major
-// views: data^T is 2nb x lines, lines^T n_u x lines).  One GEMM per line group
+// lines[l] = c_A sum G_t^T data(l), as float32 MFMA GEMMs (gemm.hip) over
+// runs of lines.  One GEMM per line group
 // and z-row offset: a group of consecutive lines is one GEMM; a raster class
 // (every second z-row) and a tensor-PSF offset (rows shifted within each
 // angle) are batched over the angles with the rows' own strides.  Offset 0
@@ -354,26 +354,31 @@ static void gemm_runs(const mpi3d_plan *pl, bool fwd, std::vector<GemmRun> &runs
 static int gemm_signal(const mpi3d_plan *pl, bool fwd, const float *in, int ld_in, float *out, int ld_out,
                        hipStream_t st)
 {
-    if (!pl->blas) return MPI3D_EINVAL;
-    const float alpha = (float)pl->op_scale;
-    if (rocblas_set_stream(pl->blas, st) != rocblas_status_success) return MPI3D_EDEVICE;
+    if (!pl->gt || !pl->gta) return MPI3D_EINVAL;
     std::vector<GemmRun> runs;
     gemm_runs(pl, fwd, runs);
     for (const GemmRun &r : runs) {
-        const float *G = pl->gt + (size_t)r.table * pl->gt_elems;
-        const float *B = in + r.in0 * ld_in;
-        float *C = out + r.out0 * ld_out;
-        const long sb = r.batch_lines * ld_in, sc = r.batch_lines * ld_out;
-        rocblas_status stt;
-        if (fwd)   // data^T (2nb x n) = Gt (2nb x n_u, ld 2nb) * lines^T (n_u x n)
-            stt = rocblas_sgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, pl->nb2, r.n,
-                                                pl->nu, &alpha, G, pl->nb2, 0, B, r.in_step * ld_in, sb, &r.beta, C,
-                                                r.out_step * ld_out, sc, r.batch);
-        else       // lines^T (n_u x n) = Gt^T (n_u x 2nb) * data^T (2nb x n)
-            stt = rocblas_sgemm_strided_batched(pl->blas, rocblas_operation_transpose, rocblas_operation_none, pl->nu,
-                                                r.n, pl->nb2, &alpha, G, pl->nb2, 0, B, r.in_step * ld_in, sb, &r.beta,
-                                                C, r.out_step * ld_out, sc, r.batch);
-        if (stt != rocblas_status_success) return MPI3D_EDEVICE;
+        LineGemm g{};
+        // forward: data (2nb per line) = lines (n_u) x G^T [n_up][2nb];
+        // adjoint: lines (n_u per line) = data (2nb) x G [2nb][n_up]
+        g.a = in;
+        g.lda = ld_in;
+        g.w = (fwd ? pl->gt : pl->gta) + (size_t)r.table * pl->gt_elems;
+        g.ldw = fwd ? pl->nb2 : pl->nup;
+        g.c = out;
+        g.ldc = ld_out;
+        g.n = r.n;
+        g.m = fwd ? pl->nb2 : pl->nu;
+        g.k = fwd ? pl->nu : pl->nb2;
+        g.batch = r.batch;
+        g.in0 = r.in0;
+        g.out0 = r.out0;
+        g.batch_lines = r.batch_lines;
+        g.in_step = r.in_step;
+        g.out_step = r.out_step;
+        g.alpha = (float)pl->op_scale;
+        g.beta = r.beta;
+        TRY(launch_line_gemm(g, st));
     }
     return MPI3D_OK;
 }

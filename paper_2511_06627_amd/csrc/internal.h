@@ -4,7 +4,6 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
-#include <rocblas/rocblas.h>
 #include <cstddef>
 #include <cstdint>
 
@@ -180,8 +179,8 @@ struct mpi3d_plan {
     float *band_scale;    // [nbp2] mixed adjoint input scale per column
     float adj_scale16;    // mixed adjoint output scale
     float *gt = nullptr;  // precomposed: n_ktab line matrices G^T [n_up][2 nb] (row-major)
+    float *gta = nullptr; // and their transposes G [2 nb][n_up] (the adjoint's operand)
     size_t gt_elems = 0;  // floats per line matrix
-    rocblas_handle blas = nullptr;   // precomposed: GEMM handle
     // operator workspace layout (bytes from ws base)
     size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, ws_rtb, ws_rtsc, ws_sig, op_ws_bytes;
     int in16_cols;        // halves per fp16 operand line: max(nup, nbp2)
@@ -214,6 +213,26 @@ hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipSt
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
 int sig_fwd_supported(int nup, int gct, int precision, int pairs);
 int sig_adj_supported(int nup, int gct, int precision, int pairs);
+
+// Precomposed signal stage (gemm.hip): C[i][j] = alpha sum_q A_i[q] W[q][j]
+// (+ beta C[i][j] when beta != 0) for i < n, j < m, q < k, over `batch`
+// blocks of rows: row i of block b reads line in0 + b batch_lines +
+// i in_step of a (stride lda floats) and writes line out0 + b batch_lines +
+// i out_step of c (stride ldc); W is row-major with row stride ldw.
+struct LineGemm {
+    const float *a;
+    long lda;
+    const float *w;
+    int ldw;
+    float *c;
+    long ldc;
+    int n, m, k;
+    int batch;
+    long in0, out0, batch_lines;
+    int in_step, out_step;
+    float alpha, beta;
+};
+hipError_t launch_line_gemm(const LineGemm &g, hipStream_t st);
 
 // Reductions and vector kernels (vec.hip).  The split reductions sum nparts
 // partial blocks; rp describes the tensor PSF's passes among them (npass

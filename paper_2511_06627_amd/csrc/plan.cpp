@@ -458,6 +458,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     o_fa = place(sizeof(float) * (size_t)TP * NBP2);
     o_ka = place(sizeof(float) * KE * n_ktab);
     const size_t o_gt = precomp ? place(sizeof(float) * gt.size()) : 0;
+    const size_t o_gta = precomp ? place(sizeof(float) * gt.size()) : 0;
     if (mixed) {
         o_kf16 = place(sizeof(__half) * KE * n_ktab);
         o_ff16 = place(sizeof(__half) * (size_t)TP * NBP2);
@@ -616,8 +617,16 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     ok = ok && hipMemcpy(pl->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (precomp) {
         pl->gt = (float *)(tb + o_gt);
+        pl->gta = (float *)(tb + o_gta);
+        // G = (G^T)^T per table, [2nb][n_up]: the adjoint GEMM's operand rows
+        std::vector<float> gta(gt.size());
+        const size_t NB2 = 2 * (size_t)NB;
+        for (int tb2 = 0; tb2 < n_ktab; ++tb2)
+            for (size_t p = 0; p < (size_t)NUP; ++p)
+                for (size_t c = 0; c < NB2; ++c)
+                    gta[pl->gt_elems * tb2 + c * NUP + p] = gt[pl->gt_elems * tb2 + p * NB2 + c];
         ok = ok && hipMemcpy(pl->gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice) == hipSuccess;
-        ok = ok && rocblas_create_handle(&pl->blas) == rocblas_status_success;
+        ok = ok && hipMemcpy(pl->gta, gta.data(), sizeof(float) * gta.size(), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (mixed) {
         pl->kf16 = (__half *)(tb + o_kf16);
@@ -634,7 +643,6 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         ok = ok && hipMemcpy(pl->band_scale, band_scale.data(), sizeof(float) * NBP2, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
-        if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
         (void)hipFree(pl->tables);
         delete pl;
         return MPI3D_EDEVICE;
@@ -705,8 +713,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         int its = 0;
         const int rc = estimate_op_norm(pl, 1e-7, 1000, &nrm, &its);
         if (rc != MPI3D_OK) {
-            if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
-            (void)hipFree(pl->tables);
+                (void)hipFree(pl->tables);
             delete pl;
             return rc;
         }
@@ -723,7 +730,6 @@ extern "C" void mpi3d_plan_destroy(mpi3d_plan *pl)
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(pl->device);
-    if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
     (void)hipFree(pl->tables);
     (void)hipSetDevice(prev);
     delete pl;
