@@ -69,20 +69,20 @@ enum {
 };
 
 /* Operator precision.  FP32: projection in fp32, signal contractions on fp32
- * MFMA.  MIXED: projection gathers read bf16 copies of the volume and of the
- * line data, the signal contractions run on fp16 MFMA with fp32 accumulation,
- * per-line power-of-two scaling and per-harmonic-band scaling.  PRECOMPOSED:
+ * MFMA.  MIXED: the projection gathers a bf16 copy of the volume, the
+ * backprojection fp16 lines with a power-of-two scale per line, and the
+ * signal contractions run on fp16 MFMA with fp32 accumulation, per-line
+ * power-of-two scaling and per-harmonic-band scaling.  PRECOMPOSED:
  * the lines of one PSF table share one trajectory, so A_DC = S D_Gamma F V E H B
  * is one real 2n_bins x n_u matrix G per table (per raster sweep direction,
  * tensor-PSF row offset, or drive axis); the plan forms G = F^T K once in
- * float64 on the host, and the signal stage becomes float32 library GEMMs
- * (rocBLAS) of the projections with each G (or its transpose), batched over
- * the angles where a table's lines are strided or shifted -- the same operator
- * without forming time signals, about (n_t (n_u + 2 n_bins)) / (2 n_bins n_u)
- * times fewer flops.  PRECOMPOSED serves mpi3d_forward, mpi3d_adjoint, mpi3d_signal_* and
- * mpi3d_time_kernel; mpi3d_solve and serving states reject it
- * (MPI3D_ENOTSUP).  Calls with PRECOMPOSED on one plan must not run
- * concurrently from several host threads (they share the plan's GEMM handle). */
+ * float64 on the host, and the signal stage becomes float32 MFMA GEMMs of
+ * the projections with each G (or its transpose), batched over the angles
+ * where a table's lines are strided or shifted -- the same operator without
+ * forming time signals, about (n_t (n_u + 2 n_bins)) / (2 n_bins n_u) times
+ * fewer flops.  PRECOMPOSED serves mpi3d_forward, mpi3d_adjoint,
+ * mpi3d_signal_* and mpi3d_time_kernel; mpi3d_solve and serving states reject
+ * it (MPI3D_ENOTSUP). */
 enum { MPI3D_FP32 = 0, MPI3D_MIXED = 1, MPI3D_PRECOMPOSED = 2 };
 
 /*

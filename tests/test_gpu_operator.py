@@ -25,6 +25,8 @@ CASES = {
     "ragged": (40, 36, 5, 7, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1),
     # several line tiles with a ragged last one, 7 column tiles, non-square slice
     "multi_tile": (64, 48, 20, 9, 4096, 4096 / 256 + 1 / 3, 3.0, 1, 20, 2),
+    # odd detector width (the precomposed stage reads its lines one float at a time)
+    "odd_u": (41, 30, 3, 5, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1),
     # n_u = 128 (the remaining compiled detector width) with 13 harmonics
     "mid_128": (128, 96, 4, 5, 2048, 2048 / 256 + 1 / 3, 2.5, 1, 13, 2),
     # a slice too large for LDS (staged in two row bands), with the 90 degree
@@ -227,7 +229,7 @@ def test_receive_filter_and_harmonics_from_two(torch_mod):
         assert ef <= tol and ea <= tol
 
 
-@pytest.mark.parametrize("name", ["parity_32", "ragged", "mid_128"])
+@pytest.mark.parametrize("name", ["parity_32", "ragged", "odd_u", "mid_128"])
 def test_precomposed_operator(name, torch_mod):
     """The precomposed-line operator (G = F^T K formed once per plan, the signal
     stage as float32 GEMMs) is the same linear map: A, A^T and the signal stages
