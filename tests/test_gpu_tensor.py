@@ -1,10 +1,12 @@
 """GPU parity of the tensor-PSF operator (z-rows coupled through the xx entry
-of the tensor PSF, one signal pass per row offset) against the FP64 oracle.
+of the tensor PSF; R + 1 signal passes, pass e over the symmetric sums of the
+rows e above and below) against the FP64 oracle.
 
 Tolerances: the bars of the collinear operator -- 1e-5 relative L2 for the
 FP32 operator, its stages and the converged CGLS solve; 5e-3 for the mixed
-operator (each offset pass's partial sums are unscaled by the scale of the
-line that pass read) and 1e-4 for mixed refinement.
+operator (each pass's partial sums are unscaled by the scale of the line
+sums that pass read, and in the adjoint by that of the data line) and 1e-4
+for mixed refinement.
 """
 import sys
 
@@ -26,7 +28,7 @@ CASES = {
     "tensor_full": (32, 32, 6, 5, 1024, 1024 / 128 + 1 / 3, 2.0, 1, 12, 2, 5),
     # ragged, truncated at two rows per side, odd nz
     "tensor_r2": (40, 36, 9, 7, 1504, 1504 / 256 + 1 / 3, 2.0, 1, 9, 1, 2),
-    # nine offsets in one launch with several line tiles per offset
+    # five passes (offsets up to 4) in one launch with several line tiles per pass
     "tensor_tiles": (64, 48, 20, 9, 2048, 2048 / 256 + 1 / 3, 3.0, 1, 14, 2, 4),
 }
 
