@@ -88,6 +88,10 @@ static SigArgs sig_args(const mpi3d_plan *pl, int prec, bool serve)
     a.ff16 = pl->ff16; a.fa16 = pl->fa16;
     a.band_scale = pl->band_scale;
     a.nu = pl->nu; a.nup = pl->nup; a.nb2 = pl->nb2; a.nbp2 = pl->nbp2; a.nct = pl->nct;
+    if (fused_pass(pl, prec)) {   // virtual lines of (R + 1) nup samples, every one of them used
+        a.nu = a.nup = pl->nupf;
+        a.fused = 1;
+    }
     a.nchunks = pl->nchunks;
     a.cps = serve ? c.serve_cps : c.cps;
     a.nsplit = serve ? c.serve_nsplit : c.nsplit;
@@ -113,12 +117,32 @@ static int rows_per_block(const mpi3d_plan *pl, int prec) { return kRowsPerWave 
 static void line_jobs(const LineJob &lj, int prec, bool fwd, bool serve, std::vector<SigJob> &out)
 {
     const mpi3d_plan *pj = lj.pl;
-    const long part_stride = pj->L * (fwd ? pj->nbp2 : pj->nup);
+    const bool fz = fused_pass(pj, prec);
+    const long part_stride = pj->L * (fwd ? pj->nbp2 : (fz ? pj->nupf : pj->nup));
     const long pass_stride =
         (long)nsplit_of(pj, prec, serve) * (fwd ? 1 : sig_cfg(pj, prec).ngroups) * part_stride;
     const bool sym = fwd && pj->n_passes > 1;
     for (int gi = 0; gi < pj->n_line_groups; ++gi) {
         const mpi3d_plan::LineGroup &lg = pj->groups[gi];
+        if (fz) {
+            // one job: the group's R + 1 tables concatenated; forward input the
+            // virtual lines of symmetric sums, adjoint input the data
+            SigJob sj{};
+            sj.in = fwd ? (const void *)lj.w->sig : (const void *)lj.in;
+            sj.in_stride = fwd ? pj->nupf : lj.in_stride;
+            sj.part = lj.w->part;
+            sj.part_stride = part_stride;
+            const size_t ko = (size_t)gi * pj->n_passes * pj->k_elems;
+            sj.kf = pj->kff + ko;
+            sj.ka = pj->kaf + ko;
+            sj.rows = lg.rows;
+            sj.map_per = lg.per;
+            sj.map_nz = lg.gnz;
+            sj.map_off = lg.off;
+            sj.map_step = lg.step;
+            out.push_back(sj);
+            continue;
+        }
         for (int e = 0; e <= lg.coup; ++e) {
             SigJob sj{};
             sj.in = sym ? (const void *)(lj.w->sig + (size_t)e * pj->L * pj->nup) : (const void *)lj.in;
@@ -143,7 +167,10 @@ static void line_jobs(const LineJob &lj, int prec, bool fwd, bool serve, std::ve
     }
 }
 
-static RowPasses row_passes(const mpi3d_plan *pl, bool fwd)
+// The tensor PSF's passes as the reductions of one precision see them (a
+// fused FP32 forward has a single pass; its adjoint holds every pass in each
+// line of its partial sums).
+static RowPasses row_passes(const mpi3d_plan *pl, bool fwd, int prec)
 {
     RowPasses rp{};
     rp.npass = pl->n_passes;
@@ -155,6 +182,14 @@ static RowPasses row_passes(const mpi3d_plan *pl, bool fwd)
     rp.lines = pl->L;
     rp.pitch = fwd ? pl->nbp2 : pl->nup;
     rp.fwd = fwd ? 1 : 0;
+    if (fused_pass(pl, prec)) {
+        if (fwd) {
+            rp.npass = 1;
+        } else {
+            rp.pitch = pl->nupf;
+            rp.pass_cols = pl->nup;
+        }
+    }
     return rp;
 }
 
@@ -195,9 +230,11 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
         const mpi3d_plan *pj = jobs[j].pl;
         if (pj->line_key != pl->line_key) return MPI3D_EINVAL;
         if (fwd && pj->n_passes > 1) {
-            // tensor PSF: the symmetric line sums every forward pass reads
-            TRY(launch_sym_lines(jobs[j].in, jobs[j].in_stride, pj->nu, pj->nup, row_passes(pj, true),
-                                 jobs[j].w->sig, st));
+            // tensor PSF: the symmetric line sums the forward reads -- blocks
+            // per pass, or (fused) one virtual line of R + 1 sums per line
+            const bool fz = fused_pass(pj, prec);
+            TRY(launch_sym_lines(jobs[j].in, jobs[j].in_stride, pj->nu, pj->nup, row_passes(pj, true, MPI3D_MIXED),
+                                 jobs[j].w->sig, fz ? pj->nup : pj->L * pj->nup, fz ? pj->nupf : pj->nup, st));
         }
         if (prec == MPI3D_MIXED) {
             // per-line power-of-two scales and the scaled fp16 operand lines
@@ -229,9 +266,10 @@ static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
                           double *norm_parts, int *nnorm, hipStream_t st)
 {
     const bool mixed = prec == MPI3D_MIXED;
-    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, pl->n_passes * nsplit_of(pl, prec, serve), pl->L * pl->nbp2, w.part,
+    const int npass = fused_pass(pl, prec) ? 1 : pl->n_passes;
+    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, npass * nsplit_of(pl, prec, serve), pl->L * pl->nbp2, w.part,
                           mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
-                          norm_parts, nnorm, st, row_passes(pl, true)));
+                          norm_parts, nnorm, st, row_passes(pl, true, prec)));
     return MPI3D_OK;
 }
 
@@ -241,10 +279,12 @@ static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
 {
     const bool mixed = prec == MPI3D_MIXED;
     const double scale = pl->op_scale * (mixed ? (double)pl->adj_scale16 : 1.0);
-    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pl->nup, out_stride,
-                                    pl->n_passes * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
-                                    pl->L * pl->nup, w.part, mixed ? w.rowscale : nullptr, scale, out, st,
-                                    row_passes(pl, false)));
+    const bool fz = fused_pass(pl, prec);
+    const int pitch = fz ? pl->nupf : pl->nup;   // floats per line of the partial sums
+    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pitch, out_stride,
+                                    (fz ? 1 : pl->n_passes) * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
+                                    pl->L * pitch, w.part, mixed ? w.rowscale : nullptr, scale, out, st,
+                                    row_passes(pl, false, prec)));
     return MPI3D_OK;
 }
 
@@ -258,7 +298,7 @@ static int lines_to_volume(const mpi3d_plan *pl, int prec, const OpWs &w, bool s
                            double lambda, double *parts, int *nparts, hipStream_t st, const float *x_add = nullptr)
 {
     if (prec == MPI3D_MIXED) {
-        const RowPasses rp = row_passes(pl, false);
+        const RowPasses rp = row_passes(pl, false, prec);
         if (pl->drive_axes == 2) {
             TRYRC(reduce_adjoint(pl, prec, w, serve, w.rt, pl->nup, st));
             TRY(launch_fold_zlines(pl, w.rt, st));

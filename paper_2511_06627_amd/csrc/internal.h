@@ -77,6 +77,7 @@ struct SigArgs {
     int nu, nup, nb2, nbp2, nct;                  // sizes (nup, nbp2 padded to 32)
     int nchunks, cps, nsplit, ngroups, gct;       // chunking and column groups
     int pairs;                                    // wave pairs per block (kWaves or kWidePairs)
+    int fused;                                    // FP32 tensor PSF in one pass: nup is (R + 1) n_up
     int total_tiles;
     int njobs;
     SigJob jobs[kMaxJobs];
@@ -137,6 +138,17 @@ struct mpi3d_plan {
         int cps, nsplit;           // time chunks per split, splits
         int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
     } sc[2];
+    // FP32 tensor PSF in one fused pass per line group: the forward's first
+    // contraction runs over the R + 1 symmetric line sums of a line laid end
+    // to end (a virtual line of nupf = (R + 1) nup samples) against the
+    // group's R + 1 tables concatenated per time chunk (kff, kaf: tables
+    // table_g .. table_g + R), so the band DFT runs once; the adjoint's second
+    // contraction writes all R + 1 offsets of a line at once.  Wide blocks;
+    // scf is its launch configuration.
+    bool fused = false;
+    int nupf = 0;
+    SigCfg scf{};
+    float *kff = nullptr, *kaf = nullptr;   // [group][chunk][nupf x 32] swizzled like kf / ka
     int nchunks;
     uint64_t line_key;             // equal keys <=> identical line tables
     // projection configuration
@@ -213,6 +225,7 @@ hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipSt
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st);
 int sig_fwd_supported(int nup, int gct, int precision, int pairs);
 int sig_adj_supported(int nup, int gct, int precision, int pairs);
+int sig_fused_supported(int nupf, int gct);
 
 // Precomposed signal stage (gemm.hip): C[i][j] = alpha sum_q A_i[q] W[q][j]
 // (+ beta C[i][j] when beta != 0) for i < n, j < m, q < k, over `batch`
@@ -248,12 +261,16 @@ struct RowPasses {
     long lines;            // lines per pass
     int pitch;             // floats between consecutive lines of a partial block
     int fwd;               // 1: forward reduction, 0: adjoint
+    int pass_cols;         // fused adjoint (FP32): pass e is columns e pass_cols .. of each line
+                           // of every partial block (0: passes are blocks of their own)
 };
 // The forward passes' inputs: sig[e][l] = rho(l + e) + rho(l - e) within l's
 // angle (sig[0] = rho), over nup columns (zero past nu), for e = 0..npass-1
 // (zero beyond the line's coupling range); rho has stride in_stride.
+// Layout: sig[e][l] starts at e * pass_stride + l * line_stride (passes:
+// L nup and nup; the fused pass: nup and (R + 1) nup, a virtual line per l).
 hipError_t launch_sym_lines(const float *rho, int in_stride, int nu, int nup, RowPasses rp, float *sig,
-                            hipStream_t st);
+                            long pass_stride, long line_stride, hipStream_t st);
 hipError_t launch_reduce_fwd(long rows, int nb2, int nbp2, int nparts, long part_stride, const float *part,
                              const float *row_scale, const float *col_scale, double scale, const float *b_sub,
                              float *out, double *norm_parts, int *nnorm, hipStream_t st, RowPasses rp);
@@ -314,8 +331,10 @@ namespace mpi3d {
 
 inline const mpi3d_plan::SigCfg &sig_cfg(const mpi3d_plan *pl, int prec)
 {
-    return pl->sc[prec == MPI3D_MIXED ? 1 : 0];
+    if (prec == MPI3D_MIXED) return pl->sc[1];
+    return pl->fused ? pl->scf : pl->sc[0];
 }
+inline bool fused_pass(const mpi3d_plan *pl, int prec) { return pl->fused && prec != MPI3D_MIXED; }
 
 struct OpWs {
     float *rt;        // projections [L][nup]

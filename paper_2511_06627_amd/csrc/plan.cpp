@@ -130,14 +130,14 @@ void column_groups(int nct0, bool fp32, mpi3d_plan::SigCfg &c)
 // per-CU MFMA rate measured on MI355X (FP32 about 4.3e11 flop/s, fp16 about
 // 2.3e12), plus each split's partial sums written and read back by the
 // reduction at about 5 TB/s.
-void choose_split(const mpi3d_plan *pl, bool fp32, mpi3d_plan::SigCfg &c)
+void choose_split(const mpi3d_plan *pl, bool fp32, mpi3d_plan::SigCfg &c, int nup, int passes)
 {
     const int slots = 256;
     const int rows = kRowsPerWave * c.pairs;
     const long tiles = (pl->L + rows - 1) / rows;
     const double rate = fp32 ? 4.3e11 : 2.3e12;
-    const double t_chunk = (double)rows * kChunk * 2.0 * (pl->nup + kColTile * c.gct) / rate;
-    const double split_bytes = 8.0 * pl->n_passes * pl->L * std::max<double>(pl->nbp2, (double)c.ngroups * pl->nup);
+    const double t_chunk = (double)rows * kChunk * 2.0 * (nup + kColTile * c.gct) / rate;
+    const double split_bytes = 8.0 * passes * pl->L * std::max<double>(pl->nbp2, (double)c.ngroups * nup);
     int best_s = 1;
     double best = 1e30;
     for (int s = 1; s <= pl->nchunks; ++s) {
@@ -281,6 +281,18 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         column_groups(nct0, false, pl->sc[1]);
         pl->nct = pl->sc[0].ngroups * pl->sc[0].gct;
         if (precisions & (1 << MPI3D_MIXED)) pl->nct = std::max(pl->nct, pl->sc[1].ngroups * pl->sc[1].gct);
+        // FP32 tensor PSF in one fused pass, where a kernel fits: every line
+        // group coupled over the same R, a virtual line of a compiled width,
+        // the band table in one wide group of 14 or 16 column tiles
+        bool same_r = pl->pass_r > 0;
+        for (int gi = 0; gi < pl->n_line_groups; ++gi) same_r = same_r && pl->groups[gi].coup == pl->pass_r;
+        const int nupf = (pl->pass_r + 1) * pl->nup, gctf = 2 * std::max(7, (nct0 + 1) / 2);
+        if (same_r && nct0 <= 16 && sig_fused_supported(nupf, gctf)) {
+            pl->fused = true;
+            pl->nupf = nupf;
+            pl->scf = mpi3d_plan::SigCfg{kWidePairs, 1, gctf, 0, 0, 0, 0};
+            pl->nct = std::max(pl->nct, gctf);
+        }
         pl->nbp2 = pl->nct * kColTile;
     }
     {
@@ -293,8 +305,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             return MPI3D_ENOTSUP;
         }
     }
-    choose_split(pl, true, pl->sc[0]);
-    choose_split(pl, false, pl->sc[1]);
+    choose_split(pl, true, pl->sc[0], pl->nup, pl->n_passes);
+    choose_split(pl, false, pl->sc[1], pl->nup, pl->n_passes);
+    if (pl->fused) choose_split(pl, true, pl->scf, pl->nupf, 1);
 
     // projection configuration
     {
@@ -457,6 +470,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     o_ff = place(sizeof(float) * (size_t)TP * NBP2);
     o_fa = place(sizeof(float) * (size_t)TP * NBP2);
     o_ka = place(sizeof(float) * KE * n_ktab);
+    const size_t KEF = KE * pl->n_passes * pl->n_line_groups;   // fused tables, all groups
+    const size_t o_kff = pl->fused ? place(sizeof(float) * KEF) : 0;
+    const size_t o_kaf = pl->fused ? place(sizeof(float) * KEF) : 0;
     const size_t o_gt = precomp ? place(sizeof(float) * gt.size()) : 0;
     const size_t o_gta = precomp ? place(sizeof(float) * gt.size()) : 0;
     if (mixed) {
@@ -615,6 +631,28 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     ok = ok && hipMemcpy(pl->ff, ff.data(), sizeof(float) * ff.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(pl->fa, fa.data(), sizeof(float) * fa.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(pl->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (pl->fused) {
+        // group g's tables table_g .. table_g + R side by side per time chunk:
+        // a chunk of kf / ka holds NUP x 32 floats for detector samples (kf:
+        // 8 per float4 step, ka: 32 per column tile) in the order the kernels
+        // walk them, so concatenating the chunks of consecutive offsets is the
+        // layout of one table of NUP (R + 1) samples
+        std::vector<float> kff(KEF), kaf(KEF);
+        const size_t CB = (size_t)NUP * 32;   // floats per chunk of one table
+        const int NP = pl->n_passes;
+        for (int gi = 0; gi < pl->n_line_groups; ++gi)
+            for (int c = 0; c < NC; ++c)
+                for (int e2 = 0; e2 < NP; ++e2) {
+                    const size_t src = (size_t)(pl->groups[gi].table + e2) * KE + c * CB;
+                    const size_t dst = ((size_t)gi * NP * NC + (size_t)c * NP + e2) * CB;
+                    std::copy(&kf[src], &kf[src] + CB, &kff[dst]);
+                    std::copy(&ka[src], &ka[src] + CB, &kaf[dst]);
+                }
+        pl->kff = (float *)(tb + o_kff);
+        pl->kaf = (float *)(tb + o_kaf);
+        ok = ok && hipMemcpy(pl->kff, kff.data(), sizeof(float) * KEF, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(pl->kaf, kaf.data(), sizeof(float) * KEF, hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (precomp) {
         pl->gt = (float *)(tb + o_gt);
         pl->gta = (float *)(tb + o_gta);
@@ -657,7 +695,11 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         for (const mpi3d_plan::SigCfg &c : pl->sc)
             parts = std::max(parts, (size_t)std::max(c.nsplit, c.serve_nsplit) *
                                         std::max<size_t>(pl->nbp2, (size_t)c.ngroups * pl->nup));
-        pl->ws_part = put(sizeof(float) * (size_t)pl->n_passes * pl->L * parts);
+        size_t part_floats = (size_t)pl->n_passes * pl->L * parts;
+        if (pl->fused)   // one pass; adjoint lines of nupf
+            part_floats = std::max(part_floats, (size_t)pl->L * std::max(pl->scf.nsplit, pl->scf.serve_nsplit) *
+                                                    std::max<size_t>(pl->nbp2, (size_t)pl->nupf));
+        pl->ws_part = put(sizeof(float) * part_floats);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
         // per tensor-PSF pass: the forward's symmetric line sums, their
         // scales and fp16 operands (one block each without coupling)
@@ -696,7 +738,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         };
         int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2,
                       pl->sc[0].pairs, pl->sc[0].ngroups, pl->sc[0].gct, pl->sc[1].pairs, pl->sc[1].ngroups,
-                      pl->sc[1].gct, precisions, n_classes, psf_rows, drive_axes, drive_axes == 2 ? pl->nz : 0};
+                      pl->sc[1].gct, precisions, n_classes, psf_rows, drive_axes, drive_axes == 2 ? pl->nz : 0,
+                      pl->fused ? pl->nupf : 0, pl->fused ? pl->scf.gct : 0};
         double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep, drive_axes == 2 ? pl->a_z : 0.0};
         mix(ints, sizeof(ints));
         mix(dbl, sizeof(dbl));

@@ -43,13 +43,17 @@ namespace {
 
 // Table loads kept in flight per wave.  The ring slot of stream element i is
 // i % ring, and the stream restarts every chunk, so the ring size must divide
-// the per-chunk stream length: the largest divisor of it not above a cap.
-constexpr int ring_size(int nl, int cap)
+// the per-chunk stream length: the largest divisor of it not above a cap, or,
+// when that is below half the cap, the cap itself with the stream padded to
+// a multiple of it by slots that load nothing.
+constexpr int ring_div(int nl, int cap)
 {
     for (int r = cap; r > 1; --r)
         if (nl % r == 0) return r;
     return 1;
 }
+constexpr int ring_size(int nl, int cap) { return 2 * ring_div(nl, cap) >= cap ? ring_div(nl, cap) : cap; }
+constexpr int padded_stream(int nl, int ring) { return (nl + ring - 1) / ring * ring; }
 
 #define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
 
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
     constexpr int NF = 4 * GH;            // F float4 loads per chunk
     constexpr int NL = NK + NF;
     constexpr int kRing = ring_size(NL, PAIRS == kWidePairs ? 16 : 8);
-    static_assert(NL % kRing == 0, "ring size must divide the stream");
+    constexpr int NLP = padded_stream(NL, kRing);        // stream slots per chunk (NL used)
 
     // B operand of GEMM1: rho[r][p0 + 2 st + h], p0 = half * NUP/2
     float R[NUP / 4];
@@ -100,16 +104,22 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
     f32x4 ring[kRing];
     const int cfirst = min(c0, a.nchunks - 1);
 #pragma unroll
-    for (int d = 0; d < kRing; ++d) ring[d] = load(cfirst, d);
+    for (int d = 0; d < kRing; ++d) ring[d] = d < NL ? load(cfirst, d) : f32x4{};
 
     for (int c = c0; c < c1; ++c) {
         const int cnext = min(c + 1, c1 - 1);
         f32x16 S = 0.f;
         f32x16 Sf;
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
+        for (int i = 0; i < NLP; ++i) {
             const f32x4 v = ring[i % kRing];
-            ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
+            const int nx = i + kRing;                    // the stream slot this ring slot takes next
+            if (nx < NLP) {
+                if (nx < NL) ring[i % kRing] = load(c, nx);
+            } else if (nx - NLP < NL) {
+                ring[i % kRing] = load(cnext, nx - NLP);
+            }
+            if (i >= NL) continue;                       // a padding slot
             if (i < NK) {
                 S = MFMA32(v[0], R[4 * i + 0], S);
                 S = MFMA32(v[1], R[4 * i + 1], S);
@@ -166,7 +176,7 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
     constexpr int NK = 4 * PTH;           // K float4 loads per chunk (GEMM2)
     constexpr int NL = NF + NK;
     constexpr int kRing = ring_size(NL, PAIRS == kWidePairs ? 16 : 8);
-    static_assert(NL % kRing == 0, "ring size must divide the stream");
+    constexpr int NLP = padded_stream(NL, kRing);        // stream slots per chunk (NL used)
     const int colbase = (bp.group * 2 * GH + bp.half * GH) * 32;   // first column of this wave
     const int pt0 = bp.half * PTH;
 
@@ -195,16 +205,22 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
     f32x4 ring[kRing];
     const int cfirst = min(c0, a.nchunks - 1);
 #pragma unroll
-    for (int d = 0; d < kRing; ++d) ring[d] = load(cfirst, d);
+    for (int d = 0; d < kRing; ++d) ring[d] = d < NL ? load(cfirst, d) : f32x4{};
 
     for (int c = c0; c < c1; ++c) {
         const int cnext = min(c + 1, c1 - 1);
         f32x16 Gt = 0.f;
         f32x16 Gf;
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
+        for (int i = 0; i < NLP; ++i) {
             const f32x4 v = ring[i % kRing];
-            ring[i % kRing] = (i + kRing < NL) ? load(c, i + kRing) : load(cnext, i + kRing - NL);
+            const int nx = i + kRing;                    // the stream slot this ring slot takes next
+            if (nx < NLP) {
+                if (nx < NL) ring[i % kRing] = load(c, nx);
+            } else if (nx - NLP < NL) {
+                ring[i % kRing] = load(cnext, nx - NLP);
+            }
+            if (i >= NL) continue;                       // a padding slot
             if (i < NF) {
                 Gt = MFMA32(v[0], Y[4 * i + 0], Gt);
                 Gt = MFMA32(v[1], Y[4 * i + 1], Gt);
@@ -271,10 +287,37 @@ const SigKernel kFwdW[4][4] = {ROWW(64, sig_fwd_f32), ROWW(128, sig_fwd_f32), RO
                                ROWW(256, sig_fwd_f32)};
 const SigKernel kAdjW[4][4] = {ROWW(64, sig_adj_f32), ROWW(128, sig_adj_f32), ROWW(192, sig_adj_f32),
                                ROWW(256, sig_adj_f32)};
+// Fused tensor-PSF passes (FP32): the first contraction runs over all R + 1
+// symmetric line sums of a line at once (a virtual line of (R + 1) n_up
+// samples), in wide blocks for the registers.
+constexpr int kNupF[] = {192, 256, 384, 512, 768};
+constexpr int kGHf[] = {7, 8};
+#define ROWF(NUP, F) {F<NUP, 7, kWidePairs>, F<NUP, 8, kWidePairs>}
+const SigKernel kFwdF[5][2] = {ROWF(192, sig_fwd_f32), ROWF(256, sig_fwd_f32), ROWF(384, sig_fwd_f32),
+                               ROWF(512, sig_fwd_f32), ROWF(768, sig_fwd_f32)};
+const SigKernel kAdjF[5][2] = {ROWF(192, sig_adj_f32), ROWF(256, sig_adj_f32), ROWF(384, sig_adj_f32),
+                               ROWF(512, sig_adj_f32), ROWF(768, sig_adj_f32)};
 #undef ROW
 #undef ROWW
+#undef ROWF
+
+int fused_slots(int nupf, int gct, int *ns, int *gs)
+{
+    *ns = *gs = -1;
+    for (int i = 0; i < 5; ++i)
+        if (nupf == kNupF[i]) *ns = i;
+    for (int i = 0; i < 2; ++i)
+        if (gct == 2 * kGHf[i]) *gs = i;
+    return *ns >= 0 && *gs >= 0;
+}
 
 }  // namespace
+
+int sig_fused_supported(int nupf, int gct)
+{
+    int ns, gs;
+    return fused_slots(nupf, gct, &ns, &gs);
+}
 
 // fp16 variants live in sig16.hip
 hipError_t launch_sig_fwd16(const mpi3d_plan *pl, SigArgs &a, hipStream_t st);
@@ -291,12 +334,19 @@ int sig_adj_supported(int nup, int gct, int precision, int pairs)
     return sig_fwd_supported(nup, gct, precision, pairs);
 }
 
-static hipError_t launch32(const SigKernel (&narrow)[4][4], const SigKernel (&wide)[4][4], const mpi3d_plan *pl,
-                           SigArgs &a, hipStream_t st)
+static hipError_t launch32(const SigKernel (&narrow)[4][4], const SigKernel (&wide)[4][4],
+                           const SigKernel (&fused)[5][2], SigArgs &a, hipStream_t st)
 {
-    const int ns = nup_slot(pl->nup), gs = gh_slot(a.gct, a.pairs);
-    if (ns < 0 || gs < 0) return hipErrorInvalidValue;
-    const SigKernel k = a.pairs == kWidePairs ? wide[ns][gs] : narrow[ns][gs];
+    SigKernel k = nullptr;
+    if (a.fused) {
+        int ns, gs;
+        if (a.pairs != kWidePairs || !fused_slots(a.nup, a.gct, &ns, &gs)) return hipErrorInvalidValue;
+        k = fused[ns][gs];
+    } else {
+        const int ns = nup_slot(a.nup), gs = gh_slot(a.gct, a.pairs);
+        if (ns < 0 || gs < 0) return hipErrorInvalidValue;
+        k = a.pairs == kWidePairs ? wide[ns][gs] : narrow[ns][gs];
+    }
     const int blocks = a.total_tiles * a.nsplit * a.ngroups;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(128 * a.pairs), 0, st, a);
     return hipGetLastError();
@@ -305,13 +355,13 @@ static hipError_t launch32(const SigKernel (&narrow)[4][4], const SigKernel (&wi
 hipError_t launch_sig_fwd(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st)
 {
     if (precision == MPI3D_MIXED) return launch_sig_fwd16(pl, a, st);
-    return launch32(kFwd, kFwdW, pl, a, st);
+    return launch32(kFwd, kFwdW, kFwdF, a, st);
 }
 
 hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipStream_t st)
 {
     if (precision == MPI3D_MIXED) return launch_sig_adj16(pl, a, st);
-    return launch32(kAdj, kAdjW, pl, a, st);
+    return launch32(kAdj, kAdjW, kAdjF, a, st);
 }
 
 }  // namespace mpi3d

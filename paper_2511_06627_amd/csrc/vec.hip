@@ -62,14 +62,17 @@ __device__ __forceinline__ double sum_unscaled(const float *__restrict__ pp, int
         const double v = sum_splits(pp, nparts, stride);
         return row_scale ? v / (double)row_scale[row] : v;
     }
-    const int per = nparts / rp.npass;
+    // passes: blocks of nparts / npass splits; the fused adjoint: every split
+    // holds all passes, pass e at column offset e pass_cols of each line
+    const int per = rp.pass_cols ? nparts : nparts / rp.npass;
+    const long pass_off = rp.pass_cols ? (long)rp.pass_cols : (long)per * stride;
     const bool zl = row >= rp.zbase;
     const int nline = zl ? rp.nzc : rp.nz;
     const int R = min(zl ? rp.rz : rp.rx, rp.npass - 1);
     const int k = (int)(zl ? (row - rp.zbase) % rp.nzc : row % rp.nz);
     double v = 0.0;
     for (int e = 0; e <= R; ++e) {
-        const float *pe = pp + (long)e * per * stride;
+        const float *pe = pp + (long)e * pass_off;
         if (rp.fwd) {
             const double t = sum_splits(pe, per, stride);
             v += row_scale ? t / (double)row_scale[(long)e * rp.lines + row] : t;
@@ -139,7 +142,8 @@ __global__ __launch_bounds__(kThreads) void reduce_lines_kernel(long rows, int n
 // sig[0] = rho), zero for e beyond the row's coupling range and for columns
 // past nu.
 __global__ __launch_bounds__(kThreads) void sym_lines_kernel(const float *__restrict__ rho, int in_stride, int nu,
-                                                              int nup, RowPasses rp, float *__restrict__ sig)
+                                                              int nup, RowPasses rp, float *__restrict__ sig,
+                                                              long pass_stride, long line_stride)
 {
     const long n = (long)rp.npass * rp.lines * nup;
     for (long idx = (long)blockIdx.x * kThreads + threadIdx.x; idx < n; idx += (long)gridDim.x * kThreads) {
@@ -147,6 +151,7 @@ __global__ __launch_bounds__(kThreads) void sym_lines_kernel(const float *__rest
         const long t = idx / nup;
         const long row = t % rp.lines;
         const int e = (int)(t / rp.lines);
+        const long o = e * pass_stride + row * line_stride + p;
         float v = 0.f;
         if (p < nu) {
             if (e == 0) {
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void sym_lines_kernel(const float *__rest
                 }
             }
         }
-        sig[idx] = v;
+        sig[o] = v;
     }
 }
 
@@ -510,10 +515,11 @@ hipError_t launch_lines16(long rows, int nu, int nup, int nparts, long part_stri
 
 
 hipError_t launch_sym_lines(const float *rho, int in_stride, int nu, int nup, RowPasses rp, float *sig,
-                            hipStream_t st)
+                            long pass_stride, long line_stride, hipStream_t st)
 {
     const int g = grid_for((long)rp.npass * rp.lines * nup, kReduceBlocks);
-    hipLaunchKernelGGL(sym_lines_kernel, dim3(g), dim3(kThreads), 0, st, rho, in_stride, nu, nup, rp, sig);
+    hipLaunchKernelGGL(sym_lines_kernel, dim3(g), dim3(kThreads), 0, st, rho, in_stride, nu, nup, rp, sig,
+                       pass_stride, line_stride);
     return hipGetLastError();
 }
 
