@@ -235,6 +235,8 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
                 racc[pt] = MFMA32(Gf[4 * s4 + 1], v[1], racc[pt]);
                 racc[pt] = MFMA32(Gf[4 * s4 + 2], v[2], racc[pt]);
                 racc[pt] = MFMA32(Gf[4 * s4 + 3], v[3], racc[pt]);
+                // one wave per SIMD: the PSF-table stream too keeps its loads in flight
+                if constexpr (PAIRS == kWidePairs) __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
