@@ -125,6 +125,9 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
                 S = MFMA32(v[1], R[4 * i + 1], S);
                 S = MFMA32(v[2], R[4 * i + 2], S);
                 S = MFMA32(v[3], R[4 * i + 3], S);
+                // a long PSF-table stream (the fused tensor pass's 48 and more
+                // loads per chunk) keeps its loads in flight as well
+                if constexpr (PAIRS == kWidePairs && NK >= 32) __builtin_amdgcn_sched_barrier(0);
             } else {
                 if (i == NK) Sf = pair_sum<PAIRS>(xs, c & 1, bp.pair, bp.half, lane, S);
                 const int j = i - NK, s4 = j / GH, g = j % GH;
