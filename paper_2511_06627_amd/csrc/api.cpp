@@ -96,6 +96,8 @@ static SigArgs sig_args(const mpi3d_plan *pl, int prec, bool serve)
     a.cps = serve ? c.serve_cps : c.cps;
     a.nsplit = serve ? c.serve_nsplit : c.nsplit;
     a.ngroups = c.ngroups; a.gct = c.gct; a.pairs = c.pairs;
+    a.tail_c0 = serve ? 0 : c.tail_c0;
+    a.tail_tpb = serve ? 0 : c.tail_tpb;
     return a;
 }
 

@@ -47,6 +47,60 @@ __device__ __forceinline__ BlockPos locate(const SigArgs &a)
     return bp;
 }
 
+// The work of an FP32 signal-kernel block: tiles tile0 .. tile0 + ntiles - 1
+// of column group `group` over time chunks [c0, c1), written to partial-sum
+// slot `slot`.  The first total_tiles x main splits x ngroups logical blocks
+// take one tile and one split of cps chunks each; with a tail (tail_c0 > 0,
+// the main splits covering [0, tail_c0)), the remaining blocks take tail_tpb
+// tiles each over [tail_c0, nchunks) into the last slot, so every block does
+// about the same number of chunks on 256 CUs.
+struct BlockWork {
+    int tile0, ntiles, group, slot, c0, c1;
+};
+
+__device__ __forceinline__ BlockWork block_work(const SigArgs &a)
+{
+    BlockWork w;
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int msplit = a.tail_c0 > 0 ? a.nsplit - 1 : a.nsplit;
+    const int nmain = a.total_tiles * msplit * a.ngroups;
+    if (lb < nmain) {
+        w.tile0 = lb % a.total_tiles;
+        w.ntiles = 1;
+        const int sg = lb / a.total_tiles;
+        w.group = sg % a.ngroups;
+        w.slot = sg / a.ngroups;
+        w.c0 = w.slot * a.cps;
+        w.c1 = min(w.c0 + a.cps, a.tail_c0 > 0 ? a.tail_c0 : a.nchunks);
+    } else {
+        const int tb = lb - nmain;
+        w.group = tb % a.ngroups;
+        w.tile0 = (tb / a.ngroups) * a.tail_tpb;
+        w.ntiles = min(a.tail_tpb, a.total_tiles - w.tile0);
+        w.slot = msplit;
+        w.c0 = a.tail_c0;
+        w.c1 = a.nchunks;
+    }
+    return w;
+}
+
+// The position of this wave in tile `tile` (see locate).
+__device__ __forceinline__ BlockPos tile_pos(const SigArgs &a, int tile, int slot, int group)
+{
+    BlockPos bp;
+    bp.group = group;
+    bp.split = slot;
+    int jb = 0;
+    for (int j = 1; j < a.njobs; ++j)
+        if (tile >= a.jobs[j].tile0) jb = j;
+    bp.job = jb;
+    const int w = threadIdx.x >> 6;
+    bp.pair = w >> 1;
+    bp.half = w & 1;
+    bp.row0 = (tile - a.jobs[jb].tile0) * (a.pairs * kRowsPerWave) + bp.pair * kRowsPerWave;
+    return bp;
+}
+
 // Swap partial time tiles within a pair: write mine, barrier, read the
 // partner's, and return lo + hi (the same operand order on both waves).  xs
 // holds two parities x PAIRS pairs x 2 halves x 16 x 64 floats.

@@ -78,6 +78,7 @@ struct SigArgs {
     int nchunks, cps, nsplit, ngroups, gct;       // chunking and column groups
     int pairs;                                    // wave pairs per block (kWaves or kWidePairs)
     int fused;                                    // FP32 tensor PSF in one pass: nup is (R + 1) n_up
+    int tail_c0, tail_tpb;                        // FP32 tail split (0: none), see block_work
     int total_tiles;
     int njobs;
     SigJob jobs[kMaxJobs];
@@ -135,7 +136,8 @@ struct mpi3d_plan {
     struct SigCfg {
         int pairs;                 // wave pairs per block
         int ngroups, gct;          // column groups per line tile, 32-wide column tiles per group
-        int cps, nsplit;           // time chunks per split, splits
+        int cps, nsplit;           // time chunks per split, splits (a tail counting as one)
+        int tail_c0, tail_tpb;     // FP32: tail split over chunks [tail_c0, nchunks), tail_tpb tiles a block (0: none)
         int serve_cps, serve_nsplit;   // fixed time split of merged serving launches
     } sc[2];
     // FP32 tensor PSF in one fused pass per line group: the forward's first

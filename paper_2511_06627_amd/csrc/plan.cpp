@@ -153,6 +153,29 @@ void choose_split(const mpi3d_plan *pl, bool fp32, mpi3d_plan::SigCfg &c, int nu
     }
     c.cps = (pl->nchunks + best_s - 1) / best_s;
     c.nsplit = (pl->nchunks + c.cps - 1) / c.cps;
+    c.tail_c0 = c.tail_tpb = 0;
+    // FP32 wide blocks (one per CU): a tail split can even the load when the
+    // tiles times the splits leave CUs idle -- s splits of w chunks per tile,
+    // and the remaining r = nchunks - s w chunks of every tile gathered
+    // tail_tpb tiles to a block, all in one round of blocks
+    if (fp32 && c.pairs == kWidePairs) {
+        const long per_group = slots / c.ngroups;
+        for (int w = (int)((tiles * pl->nchunks + per_group - 1) / per_group); w < pl->nchunks; ++w) {
+            const int s = pl->nchunks / w, r = pl->nchunks - s * w;
+            if (r == 0) continue;
+            const int tpb = std::max(1, w / r);
+            const long blocks = (tiles * s + (tiles + tpb - 1) / tpb) * c.ngroups;
+            if (blocks > slots) continue;
+            const double cost = std::max(w, tpb * r) * t_chunk + (s + 1) * split_bytes / 5e12;
+            if (cost < best * (1.0 - 1e-9)) {
+                best = cost;
+                c.cps = w;
+                c.nsplit = s + 1;
+                c.tail_c0 = s * w;
+                c.tail_tpb = tpb;
+            }
+        }
+    }
     // Serving launches merge the lines of several requests, so their time
     // split must not depend on the line count: a fixed split per line class.
     c.serve_nsplit = std::min(pl->nchunks, 16);
@@ -290,7 +313,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         if (same_r && nct0 <= 16 && sig_fused_supported(nupf, gctf)) {
             pl->fused = true;
             pl->nupf = nupf;
-            pl->scf = mpi3d_plan::SigCfg{kWidePairs, 1, gctf, 0, 0, 0, 0};
+            pl->scf = mpi3d_plan::SigCfg{kWidePairs, 1, gctf, 0, 0, 0, 0, 0, 0};
             pl->nct = std::max(pl->nct, gctf);
         }
         pl->nbp2 = pl->nct * kColTile;

@@ -62,10 +62,8 @@ constexpr int padded_stream(int nl, int ring) { return (nl + ring - 1) / ring * 
 // per block: kWaves (two waves per SIMD), or kWidePairs for the wide column
 // groups (one wave per SIMD, up to 512 registers per wave).
 template <int NUP, int GH, int PAIRS>
-__global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
+__device__ __forceinline__ void fwd_tile(const SigArgs &a, const BlockPos &bp, int c0, int c1, float *xs)
 {
-    __shared__ __align__(16) float xs[2 * PAIRS * 2 * 16 * 64];
-    const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
@@ -93,7 +91,6 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
 
     const int ctb = bp.group * 2 * GH + bp.half * GH;     // first column tile of this wave
     const int kst0 = bp.half * (NUP / 16);                 // first K float4 step of this half
-    const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
     const f32x4 *kf = (const f32x4 *)job.kf + lane;
     const f32x4 *ff = (const f32x4 *)a.ff + lane;
     auto load = [&](int cc, int i) -> f32x4 {
@@ -160,13 +157,22 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
     }
 }
 
+template <int NUP, int GH, int PAIRS>
+__global__ __launch_bounds__(128 * PAIRS) void sig_fwd_f32(SigArgs a)
+{
+    __shared__ __align__(16) float xs[2 * PAIRS * 2 * 16 * 64];
+    const BlockWork bw = block_work(a);
+    for (int k = 0; k < bw.ntiles; ++k) {
+        if (k) __syncthreads();   // the previous tile's last exchange is read
+        fwd_tile<NUP, GH, PAIRS>(a, tile_pos(a, bw.tile0 + k, bw.slot, bw.group), bw.c0, bw.c1, xs);
+    }
+}
+
 // Adjoint.  Per pair: GEMM1 over this wave's GH column tiles (half the bins of
 // the group), pair exchange, GEMM2 over this wave's half of the detector tiles.
 template <int NUP, int GH, int PAIRS>
-__global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
+__device__ __forceinline__ void adj_tile(const SigArgs &a, const BlockPos &bp, int c0, int c1, float *xs)
 {
-    __shared__ __align__(16) float xs[2 * PAIRS * 2 * 16 * 64];
-    const BlockPos bp = locate(a);
     const SigJob job = a.jobs[bp.job];
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const int r = bp.row0 + (lane & 31);
@@ -197,7 +203,6 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
 #pragma unroll
     for (int pt = 0; pt < PTH; ++pt) racc[pt] = 0.f;
 
-    const int c0 = bp.split * a.cps, c1 = min(c0 + a.cps, a.nchunks);
     const f32x4 *fa = (const f32x4 *)a.fa + lane;
     const f32x4 *ka = (const f32x4 *)job.ka + lane;
     auto load = [&](int cc, int i) -> f32x4 {
@@ -259,6 +264,17 @@ __global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
             const int row = bp.row0 + 8 * (j / 4) + 4 * h + (j % 4);
             if (row < job.rows) out[(size_t)ln[j] * NUP + col] = racc[pt][j];
         }
+    }
+}
+
+template <int NUP, int GH, int PAIRS>
+__global__ __launch_bounds__(128 * PAIRS) void sig_adj_f32(SigArgs a)
+{
+    __shared__ __align__(16) float xs[2 * PAIRS * 2 * 16 * 64];
+    const BlockWork bw = block_work(a);
+    for (int k = 0; k < bw.ntiles; ++k) {
+        if (k) __syncthreads();   // the previous tile's last exchange is read
+        adj_tile<NUP, GH, PAIRS>(a, tile_pos(a, bw.tile0 + k, bw.slot, bw.group), bw.c0, bw.c1, xs);
     }
 }
 
@@ -352,7 +368,13 @@ static hipError_t launch32(const SigKernel (&narrow)[4][4], const SigKernel (&wi
         if (ns < 0 || gs < 0) return hipErrorInvalidValue;
         k = a.pairs == kWidePairs ? wide[ns][gs] : narrow[ns][gs];
     }
-    const int blocks = a.total_tiles * a.nsplit * a.ngroups;
+    // main splits (one tile each), then the tail blocks (tail_tpb tiles each)
+    int blocks = a.total_tiles * a.nsplit * a.ngroups;
+    if (a.tail_c0 > 0) {
+        if (a.tail_tpb < 1 || a.nsplit < 2 || a.tail_c0 != (a.nsplit - 1) * a.cps || a.tail_c0 >= a.nchunks)
+            return hipErrorInvalidValue;
+        blocks = (a.total_tiles * (a.nsplit - 1) + (a.total_tiles + a.tail_tpb - 1) / a.tail_tpb) * a.ngroups;
+    }
     hipLaunchKernelGGL(k, dim3(blocks), dim3(128 * a.pairs), 0, st, a);
     return hipGetLastError();
 }
