@@ -85,30 +85,89 @@ __device__ __forceinline__ void fetch(const T *p, int W, float (&t)[4][NS])
     load(p + W + 1, t[3]);
 }
 
-__device__ __forceinline__ float voxel(const float *slice, int nx, int ny, int gj, int gi)
+// Staging.  LDS row r of a band holds grid row jb0 + r and LDS column col
+// holds grid column col - 1; columns 0 and nx + 1 .. W - 1 are zero borders,
+// written once per block.  A thread stages runs of VW consecutive voxels of
+// one row (VW = 4 where every row start is aligned to a VW-voxel vector load,
+// else 1), U runs at a time with all their global loads issued before the
+// first LDS store: a band then costs a few memory latencies, not one per
+// texel.
+template <typename V, int VW>
+struct Run {
+    V v[VW];
+};
+
+template <typename V, int VW>
+__device__ __forceinline__ Run<V, VW> load_run(const V *p)
 {
-    return (slice && gj >= 0 && gj < ny && gi >= 0 && gi < nx) ? slice[(size_t)gj * nx + gi] : 0.f;
+    Run<V, VW> r;
+    if constexpr (VW == 1) {
+        r.v[0] = *p;
+    } else {
+        typedef V vec __attribute__((ext_vector_type(VW)));
+        const vec q = *reinterpret_cast<const vec *>(p);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) r.v[j] = q[j];
+    }
+    return r;
 }
 
-__device__ __forceinline__ uint32_t voxel(const uint16_t *slice, int nx, int ny, int gj, int gi)
+// The texel of voxel j of the runs a (slice k0) and b (slice k0 + 1); a
+// run not in the grid (ia / ib false) contributes zeros.
+template <typename T, typename V, int VW>
+__device__ __forceinline__ T make_texel(const Run<V, VW> &ra, const Run<V, VW> &rb, bool ia, bool ib, int j)
 {
-    return (slice && gj >= 0 && gj < ny && gi >= 0 && gi < nx) ? (uint32_t)slice[(size_t)gj * nx + gi] : 0u;
+    if constexpr (std::is_same_v<T, float>) {
+        return ia ? ra.v[j] : 0.f;
+    } else if constexpr (std::is_same_v<T, float2>) {
+        return make_float2(ia ? ra.v[j] : 0.f, ib ? rb.v[j] : 0.f);
+    } else {
+        return (ia ? (uint32_t)ra.v[j] : 0u) | ((ib ? (uint32_t)rb.v[j] : 0u) << 16);
+    }
 }
 
-__device__ __forceinline__ void stage(float *d, const float *s0, const float *, int nx, int ny, int gj, int gi)
+// Stages LDS rows 0 .. rows - 1 (grid rows jb0 ..) of the slice group (s0,
+// s1; s1 is read only where has1), LDS columns 1 .. nx.  Thread tid starts
+// at run (r0, c0) of the row-major run order and steps by kFwdThreads runs,
+// (dr, dc) rows and runs at a time.
+template <typename T, int VW, int U>
+__device__ __forceinline__ void stage_band(T *lds, const typename Texel<T>::V *s0, const typename Texel<T>::V *s1,
+                                           bool has1, int nx, int ny, int W, int jb0, int rows, int r0, int c0,
+                                           int dr, int dc, int tid)
 {
-    *d = voxel(s0, nx, ny, gj, gi);
-}
-
-__device__ __forceinline__ void stage(float2 *d, const float *s0, const float *s1, int nx, int ny, int gj, int gi)
-{
-    *d = make_float2(voxel(s0, nx, ny, gj, gi), voxel(s1, nx, ny, gj, gi));
-}
-
-__device__ __forceinline__ void stage(uint32_t *d, const uint16_t *s0, const uint16_t *s1, int nx, int ny, int gj,
-                                      int gi)
-{
-    *d = voxel(s0, nx, ny, gj, gi) | (voxel(s1, nx, ny, gj, gi) << 16);
+    using V = typename Texel<T>::V;
+    constexpr int NS = Texel<T>::NS;
+    const int runs = nx / VW;
+    const int total = rows * runs;
+    int r = r0, c = c0;
+    for (int e0 = tid; e0 < total; e0 += U * kFwdThreads) {
+        Run<V, VW> ra[U], rb[U];
+        int dst[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int gj = jb0 + r;
+            const bool live = e0 + u * kFwdThreads < total;
+            in[u] = live && (unsigned)gj < (unsigned)ny;
+            // out-of-grid runs load row 0 of the slice (in bounds) and are dropped
+            const size_t off = (size_t)(in[u] ? gj : 0) * nx + (size_t)c * VW;
+            ra[u] = load_run<V, VW>(s0 + off);
+            if constexpr (NS == 2) rb[u] = load_run<V, VW>((has1 ? s1 : s0) + off);
+            dst[u] = live ? r * W + 1 + c * VW : -1;
+            c += dc;
+            r += dr;
+            if (c >= runs) {
+                c -= runs;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (dst[u] < 0) continue;
+#pragma unroll
+            for (int j = 0; j < VW; ++j) lds[dst[u] + j] = make_texel<T, V, VW>(ra[u], rb[u], in[u], in[u] && has1, j);
+        }
+    }
 }
 
 // Adds the bilinear interpolant of the footprint t at fractional offsets
@@ -224,6 +283,19 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, const
     const int W = proj_pitch(a.nx);
     const unsigned Wb = (unsigned)(W * sizeof(T));
     const int tid = threadIdx.x;
+    // zero borders of every LDS row a band uses
+    const int border = W - a.nx;
+    for (int idx = tid; idx < (a.band_rows + 1) * border; idx += kFwdThreads) {
+        const int r = idx / border, b = idx - r * border;
+        lds[r * W + (b == 0 ? 0 : a.nx + b)] = T{};
+    }
+    // run positions of this thread for the vector (4 voxels) and scalar stagings
+    const bool vec = a.nx % 4 == 0 && reinterpret_cast<uintptr_t>(vol) % (4 * sizeof(V)) == 0;
+    const int v_runs = max(1, a.nx / 4), s_runs = a.nx;
+    const int v_r0 = tid / v_runs, v_c0 = tid - v_r0 * v_runs, v_dr = kFwdThreads / v_runs,
+              v_dc = kFwdThreads - v_dr * v_runs;
+    const int s_r0 = tid / s_runs, s_c0 = tid - s_r0 * s_runs, s_dr = kFwdThreads / s_runs,
+              s_dc = kFwdThreads - s_dr * s_runs;
     for (long ku = u0; ku < u1;) {
         const int g = (int)(ku / a.M);
         const int m0 = (int)(ku - (long)g * a.M);
@@ -238,17 +310,18 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, const
 #pragma unroll
             for (int k = 0; k < NS; ++k) acc[r][k] = 0.f;
         const V *s0 = vol + (size_t)k0 * a.nx * a.ny;
-        const V *s1 = ns > 1 ? s0 + (size_t)a.nx * a.ny : nullptr;
+        const V *s1 = s0 + (size_t)(ns > 1 ? a.nx * a.ny : 0);
         for (int band = 0; band < a.n_bands; ++band) {
             const int jb0 = -1 + band * a.band_rows;               // first base row
             const int jb1 = min(jb0 + a.band_rows, a.ny);          // one past last base row
             const int nbase = jb1 - jb0;
             const int rows = nbase + 1;                            // LDS rows: grid rows jb0..jb1
             __syncthreads();
-            for (int idx = tid; idx < rows * W; idx += kFwdThreads) {
-                const int r = idx / W, col = idx - r * W;
-                stage(lds + idx, s0, s1, a.nx, a.ny, jb0 + r, col - 1);
-            }
+            if (vec)
+                stage_band<T, 4, (NS == 2 && sizeof(V) == 4 ? 4 : 8)>(lds, s0, s1, ns > 1, a.nx, a.ny, W, jb0, rows,
+                                                                       v_r0, v_c0, v_dr, v_dc, tid);
+            else
+                stage_band<T, 1, 8>(lds, s0, s1, ns > 1, a.nx, a.ny, W, jb0, rows, s_r0, s_c0, s_dr, s_dc, tid);
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < kMaxRaysPerThread; ++i) {
@@ -344,6 +417,7 @@ __global__ __launch_bounds__(kFwdThreads) void proj_fwd_kernel(ProjArgs a, const
 
 constexpr int kTile = 16;
 constexpr int kPW = 32;     // staged rays per angle per tile
+constexpr int kAdjStage = 8;   // staged entries per thread per round of loads
 
 // The fp16 values in the low and high halves of a 32-bit word, as fp32.
 __device__ __forceinline__ float half_lo(uint32_t w)
@@ -419,22 +493,42 @@ __device__ __forceinline__ void adj_body(const ProjArgs &a, const uint16_t *__re
             }
         }
         __syncthreads();
-        for (int idx = tid; idx < mc * KW * kPW; idx += 256) {
-            const int mm = idx / (KW * kPW);
-            const int rem = idx - mm * (KW * kPW);
-            const int kw = rem / kPW, pp = rem % kPW;
-            const int p = plo[mm] + pp;
-            const bool pin = p >= 0 && p < a.nu;
-            if constexpr (H) {
+        if constexpr (H) {
+            for (int idx = tid; idx < mc * KW * kPW; idx += 256) {
+                const int mm = idx / (KW * kPW);
+                const int rem = idx - mm * (KW * kPW);
+                const int kw = rem / kPW, pp = rem % kPW;
+                const int p = plo[mm] + pp;
+                const bool pin = p >= 0 && p < a.nu;
                 const int kk = 2 * kw;
                 const size_t base = ((size_t)(mb + mm) * a.nz + k0 + kk) * in_stride + p;
                 const uint32_t lo = (kk < kn && pin) ? (uint32_t)rtb[base] : 0u;
                 const uint32_t hi = (kk + 1 < kn && pin) ? (uint32_t)rtb[base + in_stride] : 0u;
                 gw[idx] = lo | (hi << 16);
-            } else {
-                float v = 0.f;
-                if (kw < kn && pin) v = a.rt_in[((size_t)(mb + mm) * a.nz + k0 + kw) * in_stride + p];
-                gs[idx] = v;
+            }
+        } else {
+            // kAdjStage entries per thread at a time, all loads issued before
+            // the first LDS store (an entry outside the lines reads line 0 and
+            // stores zero).  Stores are unconditional so the loads stay
+            // together: a slot past the end repeats the last entry, value
+            // included.
+            const int total = mc * KW * kPW;
+            for (int idx0 = tid; idx0 < total; idx0 += 256 * kAdjStage) {
+                float v[kAdjStage];
+                bool ok[kAdjStage];
+#pragma unroll
+                for (int u = 0; u < kAdjStage; ++u) {
+                    const int idx = min(idx0 + 256 * u, total - 1);
+                    const int mm = idx / (KW * kPW);
+                    const int rem = idx - mm * (KW * kPW);
+                    const int kw = rem / kPW, pp = rem % kPW;
+                    const int p = plo[mm] + pp;
+                    const size_t base = ((size_t)(mb + mm) * a.nz + k0 + kw) * in_stride + p;
+                    ok[u] = p >= 0 && p < a.nu && kw < kn;
+                    v[u] = a.rt_in[ok[u] ? base : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < kAdjStage; ++u) gs[min(idx0 + 256 * u, total - 1)] = ok[u] ? v[u] : 0.f;
             }
         }
         __syncthreads();
