@@ -172,6 +172,10 @@ typedef struct {
     int32_t n_r;                /* ray samples per projection ray */
     int32_t norm_iters;         /* power iterations that estimated op_scale; 0 = given */
     double op_scale;            /* c_A in use */
+    int32_t dft_cycles;         /* FP32 band DFT factored over blocks of this many drive-cycle
+                                   samples C (T = C P: a C-point sum at the residues of the kept
+                                   bins mod C, then a P-point sum per bin); 0 = one dense
+                                   contraction over all T samples */
 } mpi3d_plan_info;
 
 /* Validates the geometry, builds the FP64 host tables (angles, trajectory,

@@ -18,7 +18,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # keep the compiler away from packed fp32 vector ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
-SOURCES = ["plan.cpp", "api.cpp", "serve.cpp", "noalloc.cpp", "proj.hip", "sig.hip", "sig16.hip", "vec.hip", "gemm.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "serve.cpp", "noalloc.cpp", "proj.hip", "sig.hip", "sig16.hip", "sigfac.hip", "vec.hip", "gemm.hip"]
 
 
 def _compile(src):

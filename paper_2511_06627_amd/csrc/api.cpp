@@ -70,6 +70,7 @@ OpWs carve_op(const mpi3d_plan *pl, void *ws)
     w.rtb = (uint16_t *)(b + pl->ws_rtb);
     w.rtsc = (float *)(b + pl->ws_rtsc);
     w.sig = (float *)(b + pl->ws_sig);
+    w.fac = (float *)(b + pl->ws_fac);
     return w;
 }
 
@@ -107,6 +108,51 @@ static int nsplit_of(const mpi3d_plan *pl, int prec, bool serve)
     return serve ? c.serve_nsplit : c.nsplit;
 }
 static int rows_per_block(const mpi3d_plan *pl, int prec) { return kRowsPerWave * sig_cfg(pl, prec).pairs; }
+
+// The FP32 signal stage of plans with the band DFT factored over drive cycles.
+static bool fac_on(const mpi3d_plan *pl, int prec) { return prec == MPI3D_FP32 && pl->fac.on; }
+
+// Split partial-sum blocks the reductions add: forward (nbp2 columns a line),
+// adjoint (nup or nupf columns a line).
+static int fwd_parts(const mpi3d_plan *pl, int prec, bool serve)
+{
+    if (fac_on(pl, prec)) return 1;
+    return (fused_pass(pl, prec) ? 1 : pl->n_passes) * nsplit_of(pl, prec, serve);
+}
+static int adj_parts(const mpi3d_plan *pl, int prec, bool serve)
+{
+    if (fac_on(pl, prec)) return pl->fac.nsplit;
+    return (fused_pass(pl, prec) ? 1 : pl->n_passes) * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups;
+}
+
+static FacArgs fac_args(const LineJob &lj)
+{
+    const mpi3d_plan *pj = lj.pl;
+    const mpi3d_plan::Fac &f = pj->fac;
+    const mpi3d_plan::LineGroup &lg = pj->groups[0];
+    FacArgs a{};
+    a.job.in = lj.in;
+    a.job.in_stride = lj.in_stride;
+    a.job.part = lj.w->part;
+    a.job.part_stride = pj->L * pj->nup;
+    a.job.kf = f.kf;
+    a.job.ka = f.ka;
+    a.job.rows = lg.rows;
+    a.job.map_per = lg.per;
+    a.job.map_nz = lg.gnz;
+    a.job.map_off = lg.off;
+    a.job.map_step = lg.step;
+    a.ef = f.ef; a.ea = f.ea; a.wf = f.wf; a.wa = f.wa;
+    a.uq = f.uq; a.ubin = f.ubin; a.qbin = f.qbin; a.qsteps = f.qsteps;
+    a.y = lj.w->fac;
+    a.ylines = (lg.rows + 31) / 32 * 32;
+    a.nu = pj->nu; a.nup = pj->nup; a.nbp2 = pj->nbp2;
+    a.P = f.P; a.Pp = f.Pp; a.cj = f.cj;
+    a.yc = 2 * f.zst; a.zst = f.zst; a.R = f.R; a.U = f.U; a.rct = f.rct;
+    a.nsplit = f.nsplit; a.usplit = f.usplit; a.nzstage = f.nzstage;
+    a.tiles = (lg.rows + 31) / 32;
+    return a;
+}
 
 // The kernel jobs of one line job: one per line group (trajectory class of a
 // raster, or x- and z-drive lines) and tensor-PSF pass.  Group g holds the
@@ -215,6 +261,14 @@ static int sig_jobs(bool fwd, int prec, const LineJob *jobs, int n, bool serve, 
 {
     if (n < 1) return MPI3D_EINVAL;
     const mpi3d_plan *pl = jobs[0].pl;
+    if (fac_on(pl, prec)) {
+        // one factored stage per line job (its own phase sums in its workspace)
+        for (int j = 0; j < n; ++j) {
+            if (jobs[j].pl->line_key != pl->line_key || !jobs[j].pl->fac.on) return MPI3D_EINVAL;
+            TRY(fwd ? launch_fac_fwd(fac_args(jobs[j]), st) : launch_fac_adj(fac_args(jobs[j]), st));
+        }
+        return MPI3D_OK;
+    }
     SigArgs a = sig_args(pl, prec, serve);
     const int rpb = rows_per_block(pl, prec);
     int tiles = 0, nj = 0;
@@ -268,8 +322,7 @@ static int reduce_forward(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
                           double *norm_parts, int *nnorm, hipStream_t st)
 {
     const bool mixed = prec == MPI3D_MIXED;
-    const int npass = fused_pass(pl, prec) ? 1 : pl->n_passes;
-    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, npass * nsplit_of(pl, prec, serve), pl->L * pl->nbp2, w.part,
+    TRY(launch_reduce_fwd(pl->L, pl->nb2, pl->nbp2, fwd_parts(pl, prec, serve), pl->L * pl->nbp2, w.part,
                           mixed ? w.rowscale : nullptr, mixed ? pl->col_scale : nullptr, pl->op_scale, b_sub, out,
                           norm_parts, nnorm, st, row_passes(pl, true, prec)));
     return MPI3D_OK;
@@ -283,8 +336,7 @@ static int reduce_adjoint(const mpi3d_plan *pl, int prec, const OpWs &w, bool se
     const double scale = pl->op_scale * (mixed ? (double)pl->adj_scale16 : 1.0);
     const bool fz = fused_pass(pl, prec);
     const int pitch = fz ? pl->nupf : pl->nup;   // floats per line of the partial sums
-    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pitch, out_stride,
-                                    (fz ? 1 : pl->n_passes) * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
+    TRY(launch_reduce_lines_strided(pl->L, pl->nu, pitch, out_stride, adj_parts(pl, prec, serve),
                                     pl->L * pitch, w.part, mixed ? w.rowscale : nullptr, scale, out, st,
                                     row_passes(pl, false, prec)));
     return MPI3D_OK;
@@ -306,9 +358,7 @@ static int lines_to_volume(const mpi3d_plan *pl, int prec, const OpWs &w, bool s
             TRY(launch_fold_zlines(pl, w.rt, st));
             TRY(launch_lines16(pl->Lx, pl->nu, pl->nup, 0, 0, nullptr, nullptr, 1.0, rp, w.rt, w.rtb, w.rtsc, st));
         } else {
-            TRY(launch_lines16(pl->L, pl->nu, pl->nup,
-                               pl->n_passes * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups,
-                               pl->L * pl->nup, w.part, w.rowscale, pl->op_scale * (double)pl->adj_scale16, rp,
+            TRY(launch_lines16(pl->L, pl->nu, pl->nup, adj_parts(pl, prec, serve), pl->L * pl->nup, w.part, w.rowscale, pl->op_scale * (double)pl->adj_scale16, rp,
                                nullptr, w.rtb, w.rtsc, st));
         }
         TRY(launch_backproject16(pl, w.rtb, w.rtsc, xo, x_sub, lambda, parts, nparts, st, x_add));

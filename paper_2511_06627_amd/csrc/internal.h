@@ -69,6 +69,37 @@ __host__ __device__ inline long job_line(const SigJob &j, int r)
     return (long)g * j.map_nz + j.map_off + (long)j.map_step * (r - g * j.map_per);
 }
 
+// The band DFT factored over drive cycles (FP32 scans with one PSF table and
+// one line group): time t = n1 + P n2 with n1 < P, n2 < C, T = C P, C a
+// multiple of 32.  The R distinct residues q of the kept bins mod C take
+// 2 zst columns (re/im per residue, zst = R rounded up to 4) of the per-line
+// phase sums Y (forward) and Z (adjoint), [line][P][2 zst] floats in the
+// workspace (plus one spare line).  The forward's outer sum runs over units of at most 16 bins of
+// one residue; the adjoint's over each residue's bins, at most kQMax.
+constexpr int kFacWaves = 8;        // waves (32-line tiles) per block of the line-tile kernels
+constexpr int kQMax = 24;           // bins per residue (adjoint outer sum, register operands)
+constexpr int kMaxFacSplit = 4;     // forward outer-sum blocks per line tile (40 units each)
+
+struct FacArgs {
+    SigJob job;              // input lines, partial sums (part, part_stride), row map; kf / ka: the PSF
+                             // tables with their time rows in chunk order (n1, 32-cycle block)
+    const float *ef, *ea;    // residue DFT: forward B operand, adjoint A operand (swizzled)
+    const float *wf, *wa;    // outer sums: forward per unit, adjoint per residue and 16-phase stage
+    const int *uq;           // [U] residue of unit u
+    const int *ubin;         // [U][16] bins of unit u (-1: none)
+    const int *qbin;         // [R][kQMax] bins of residue q (-1: none)
+    const int *qsteps;       // [R] bins of residue q rounded up to 4
+    float *y;                // phase sums Y or Z by job row, [ylines + 1][P][yc] (ylines = 32 tiles; the
+                             // last row a spare the forward writes its columns past yc to)
+    int ylines;
+    int nu, nup, nbp2;
+    int P, Pp, cj;           // phases, phases rounded up to 8, 32-cycle blocks per phase (C / 32)
+    int yc, zst, R, U, rct;  // yc = 2 zst; rct: 32-column tiles of the residue DFT (1 or 2)
+    int nsplit, usplit;      // phase ranges of the line-tile kernels; unit split of the forward outer sum
+    int nzstage;             // 16-phase stages of the adjoint outer sum
+    int tiles;               // 32-line tiles of the job
+};
+
 struct SigArgs {
     // tables (device); the PSF tables are per job
     const float *ff, *fa;                         // fp32 swizzled DFT tables
@@ -152,6 +183,14 @@ struct mpi3d_plan {
     SigCfg scf{};
     float *kff = nullptr, *kaf = nullptr;   // [group][chunk][nupf x 32] swizzled like kf / ka
     int nchunks;
+    // FP32 band DFT factored over drive cycles (see FacArgs): chosen at plan
+    // time when it pays; tables in the plan's allocation
+    struct Fac {
+        bool on = false;
+        int C, P, Pp, cj, R, zst, U, rct, nsplit, usplit, nzstage;
+        float *kf, *ka, *ef, *ea, *wf, *wa;
+        int *uq, *ubin, *qbin, *qsteps;
+    } fac;
     uint64_t line_key;             // equal keys <=> identical line tables
     // projection configuration
     mpi3d::FwdConfig fwd32, fwd16;  // forward projection, fp32 and bf16 gathers
@@ -196,7 +235,7 @@ struct mpi3d_plan {
     float *gta = nullptr; // and their transposes G [2 nb][n_up] (the adjoint's operand)
     size_t gt_elems = 0;  // floats per line matrix
     // operator workspace layout (bytes from ws base)
-    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, ws_rtb, ws_rtsc, ws_sig, op_ws_bytes;
+    size_t ws_rt, ws_part, ws_norm, ws_rowscale, ws_xb, ws_in16, ws_rtb, ws_rtsc, ws_sig, ws_fac, op_ws_bytes;
     int in16_cols;        // halves per fp16 operand line: max(nup, nbp2)
     // solver workspace layout
     size_t sw_op, sw_r, sw_q, sw_s, sw_p, sw_scal, sw_parts, sw_d, sw_g, sw_v, solve_ws_bytes;
@@ -228,6 +267,12 @@ hipError_t launch_sig_adj(const mpi3d_plan *pl, int precision, SigArgs &a, hipSt
 int sig_fwd_supported(int nup, int gct, int precision, int pairs);
 int sig_adj_supported(int nup, int gct, int precision, int pairs);
 int sig_fused_supported(int nupf, int gct);
+// Factored band DFT (sigfac.hip): forward writes Y then the job's partial
+// sums (one split, nbp2 columns); adjoint writes Z then nsplit splits of
+// nup-column partial sums.
+int fac_supported(int nup, int rct, int zst, int cj);
+hipError_t launch_fac_fwd(const FacArgs &a, hipStream_t st);
+hipError_t launch_fac_adj(const FacArgs &a, hipStream_t st);
 
 // Precomposed signal stage (gemm.hip): C[i][j] = alpha sum_q A_i[q] W[q][j]
 // (+ beta C[i][j] when beta != 0) for i < n, j < m, q < k, over `batch`
@@ -348,6 +393,7 @@ struct OpWs {
     float *sig;       // [n_passes][L][nup] tensor PSF: the passes' symmetric line sums (forward)
     uint16_t *rtb;    // [L][nup] fp16 lines of the mixed adjoint (its backprojection gathers)
     float *rtsc;      // [L] their per-line inverse scales
+    float *fac;       // [32 ceil(L / 32) + 1][P][2 zst] phase sums of the factored band DFT (FP32)
 };
 OpWs carve_op(const mpi3d_plan *pl, void *ws);
 int check_prec(const mpi3d_plan *pl, int32_t precision);

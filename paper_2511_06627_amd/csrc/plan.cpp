@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -480,6 +481,163 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         }
     }
 
+    // ---- band DFT factored over drive cycles (FP32) --------------------------
+    // t = n1 + P n2 (T = C P, C = 32 or 64): the kept bin omega_j
+    // contributes e^{2 pi i omega_j n1 / T} e^{2 pi i (omega_j mod C) n2 / C},
+    // so the forward first sums each phase n1's C cycles against the R distinct
+    // residues (omega_j mod C), then each bin's P phases.  Taken when its MFMA
+    // work per line, T (n_up + 32 rct) + 64 P U, is under 3/4 of the dense
+    // T (n_up + nbp2); C minimises it.
+    std::vector<float> fkf, fka, fef, fea, fwf, fwa;
+    std::vector<int> fuq, fubin, fqbin, fqsteps;
+    if ((precisions & (1 << MPI3D_FP32)) && !pl->fused && pl->n_passes == 1 && pl->n_line_groups == 1 &&
+        n_ktab == 1 && T % 32 == 0) {
+        double best = 0.75 * (double)T * (NUP + NBP2);
+        int bestC = 0;
+        for (int C = 32; C <= T && C <= 64; C += 32) {
+            if (T % C) continue;
+            std::vector<int> cnt(C, 0);
+            for (int j = 0; j < NB; ++j) ++cnt[bins[j] % C];
+            int R = 0, U = 0, mx = 0;
+            for (int r = 0; r < C; ++r)
+                if (cnt[r]) {
+                    ++R;
+                    U += (cnt[r] + 15) / 16;
+                    mx = std::max(mx, cnt[r]);
+                }
+            const int zst = (R + 3) / 4 * 4, rct = (2 * zst + 31) / 32;
+            const int P = T / C;
+            if (R > 24 || mx > kQMax || U > 40 * kMaxFacSplit || !fac_supported(NUP, rct, zst, C / 32) ||
+                (double)((pl->L + 31) / 32 * 32 + 1) * P * 2 * zst >= 2147483647.0)
+                continue;
+            const double cost = (double)T * (NUP + 32 * rct) + 64.0 * (P + 7) / 8 * 8 * U;
+            if (cost < best) {
+                best = cost;
+                bestC = C;
+            }
+        }
+        if (bestC) {
+            mpi3d_plan::Fac &f = pl->fac;
+            f.on = true;
+            f.C = bestC;
+            f.P = T / bestC;
+            f.Pp = (f.P + 7) / 8 * 8;
+            f.cj = bestC / 32;
+            f.nzstage = (f.P + 15) / 16;
+            // residues ascending; units: a residue's bins (ascending) 16 at a time
+            std::vector<int> slot(bestC, -1), res;
+            for (int j = 0; j < NB; ++j) slot[bins[j] % bestC] = 0;
+            for (int r = 0; r < bestC; ++r)
+                if (slot[r] == 0) {
+                    slot[r] = (int)res.size();
+                    res.push_back(r);
+                }
+            f.R = (int)res.size();
+            f.zst = (f.R + 3) / 4 * 4;
+            f.rct = (2 * f.zst + 31) / 32;
+            std::vector<std::vector<int>> qb(f.R);
+            for (int j = 0; j < NB; ++j) qb[slot[bins[j] % bestC]].push_back(j);
+            fqbin.assign((size_t)f.R * kQMax, -1);
+            fqsteps.assign(f.R, 0);
+            for (int q = 0; q < f.R; ++q) {
+                for (size_t i = 0; i < qb[q].size(); ++i) fqbin[(size_t)q * kQMax + i] = qb[q][i];
+                fqsteps[q] = ((int)qb[q].size() + 3) / 4 * 4;
+                for (size_t i0 = 0; i0 < qb[q].size(); i0 += 16) {
+                    fuq.push_back(q);
+                    for (size_t i = 0; i < 16; ++i) fubin.push_back(i0 + i < qb[q].size() ? qb[q][i0 + i] : -1);
+                }
+            }
+            f.U = (int)fuq.size();
+            f.usplit = (f.U + 39) / 40;
+            // phase ranges of the line-tile kernels: 8 tiles a block, one block
+            // a CU; the fewest splits within 2% of the best time per phase
+            const long tgroups = ((pl->L + 31) / 32 + kFacWaves - 1) / kFacWaves;
+            auto per_phase = [&](int ns) { return (double)((tgroups * ns + 255) / 256) / ns; };
+            double pbest = 1e30;
+            for (int ns = 1; ns <= std::min(f.P, 64); ++ns) pbest = std::min(pbest, per_phase(ns));
+            f.nsplit = 1;
+            while (f.nsplit < std::min(f.P, 64) && per_phase(f.nsplit) > 1.02 * pbest) ++f.nsplit;
+            // tables
+            const int C = bestC, P = f.P, CJ = f.cj, ZST = f.zst, RCT = f.rct, YC = 2 * ZST;
+            auto tperm = [](int s2, int h) { return 8 * (s2 / 4) + 4 * h + (s2 % 4); };
+            auto tof = [&](int c, int i) { return (c / CJ) + P * (32 * (c % CJ) + i); };   // chunk row -> time
+            const double *K0 = &K[0];
+            fkf.assign(KE, 0.f);
+            fka.assign(KE, 0.f);
+            for (int c = 0; c < P * CJ; ++c) {
+                for (int st = 0; st < NUP / 2; ++st)
+                    for (int l = 0; l < 64; ++l)
+                        fkf[(((size_t)c * (NUP / 8) + st / 4) * 64 + l) * 4 + st % 4] =
+                            (float)K0[(size_t)tof(c, l % 32) * NUP + 2 * st + l / 32];
+                for (int pt = 0; pt < NUP / 32; ++pt)
+                    for (int s2 = 0; s2 < 16; ++s2)
+                        for (int l = 0; l < 64; ++l)
+                            fka[((((size_t)c * (NUP / 32) + pt) * 4 + s2 / 4) * 64 + l) * 4 + s2 % 4] =
+                                (float)K0[(size_t)tof(c, tperm(s2, l / 32)) * NUP + 32 * pt + l % 32];
+            }
+            // E[n2][2q] = cos, E[n2][2q + 1] = sin of 2 pi (r_q n2 mod C) / C
+            auto E = [&](int n2, int col) -> double {
+                if (col >= 2 * f.R) return 0.0;
+                const long ph = (long)res[col / 2] * n2 % C;
+                const double a = 2.0 * kPi * (double)ph / C;
+                return col % 2 ? std::sin(a) : std::cos(a);
+            };
+            fef.assign((size_t)C * 32 * RCT, 0.f);
+            for (int j = 0; j < CJ; ++j)
+                for (int g2 = 0; g2 < RCT; ++g2)
+                    for (int s2 = 0; s2 < 16; ++s2)
+                        for (int l = 0; l < 64; ++l)
+                            fef[((((size_t)j * RCT + g2) * 4 + s2 / 4) * 64 + l) * 4 + s2 % 4] =
+                                (float)E(32 * j + tperm(s2, l / 32), 32 * g2 + l % 32);
+            fea.assign((size_t)C * YC, 0.f);
+            for (int j = 0; j < CJ; ++j)
+                for (int st = 0; st < ZST; ++st)
+                    for (int l = 0; l < 64; ++l)
+                        fea[(((size_t)j * (ZST / 4) + st / 4) * 64 + l) * 4 + st % 4] =
+                            (float)E(32 * j + l % 32, 2 * st + l / 32);
+            // G_j[n1] = D_j e^{2 pi i (omega_j n1 mod T) / T} / sqrt(T)
+            const double inv = 1.0 / std::sqrt((double)T);
+            auto G = [&](int j, int n1, double &gr, double &gi) {
+                double dre = 1.0, dim = 0.0;
+                if (g->rx_filter) { dre = g->rx_filter[2 * j]; dim = g->rx_filter[2 * j + 1]; }
+                const long ph = (long)(((unsigned long long)bins[j] * (unsigned long long)n1) % (unsigned long long)T);
+                const double a = 2.0 * kPi * (double)ph / T;
+                gr = (dre * std::cos(a) - dim * std::sin(a)) * inv;
+                gi = (dre * std::sin(a) + dim * std::cos(a)) * inv;
+            };
+            // forward outer B operand: k = (n1 = st, re/im of Y = l / 32), column
+            // l % 32 = (bin slot, re/im of b)
+            fwf.assign((size_t)f.U * f.Pp * 64, 0.f);
+            for (int u = 0; u < f.U; ++u)
+                for (int st = 0; st < P; ++st)
+                    for (int l = 0; l < 64; ++l) {
+                        const int col = l % 32, jb = fubin[(size_t)u * 16 + col / 2];
+                        if (jb < 0) continue;
+                        double gr, gi;
+                        G(jb, st, gr, gi);
+                        const int cy = l / 32, cb = col % 2;
+                        const double v = cb == 0 ? (cy == 0 ? gr : -gi) : (cy == 0 ? gi : gr);
+                        fwf[(((size_t)u * (f.Pp / 4) + st / 4) * 64 + l) * 4 + st % 4] = (float)v;
+                    }
+            // adjoint outer B operand: k = (bin slot st, re/im of the data =
+            // l / 32), column l % 32 = (phase stg 16 + col / 2, re/im of Z)
+            fwa.assign((size_t)f.R * f.nzstage * kQMax * 64, 0.f);
+            for (int q = 0; q < f.R; ++q)
+                for (int stg = 0; stg < f.nzstage; ++stg)
+                    for (int st = 0; st < kQMax; ++st)
+                        for (int l = 0; l < 64; ++l) {
+                            const int jb = fqbin[(size_t)q * kQMax + st], col = l % 32, n1 = 16 * stg + col / 2;
+                            if (jb < 0 || n1 >= P) continue;
+                            double gr, gi;
+                            G(jb, n1, gr, gi);
+                            const int cd = l / 32, cz = col % 2;
+                            const double v = cz == 0 ? (cd == 0 ? gr : gi) : (cd == 0 ? -gi : gr);
+                            fwa[((((size_t)q * f.nzstage + stg) * (kQMax / 4) + st / 4) * 64 + l) * 4 + st % 4] =
+                                (float)v;
+                        }
+        }
+    }
+
     // ---- table layout in one device allocation -----------------------------
     bool mixed = precisions & (1 << MPI3D_MIXED);
     size_t off = 0;
@@ -498,6 +656,17 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
     const size_t o_kaf = pl->fused ? place(sizeof(float) * KEF) : 0;
     const size_t o_gt = precomp ? place(sizeof(float) * gt.size()) : 0;
     const size_t o_gta = precomp ? place(sizeof(float) * gt.size()) : 0;
+    const bool fac = pl->fac.on;
+    const size_t o_fkf = fac ? place(sizeof(float) * fkf.size()) : 0;
+    const size_t o_fka = fac ? place(sizeof(float) * fka.size()) : 0;
+    const size_t o_fef = fac ? place(sizeof(float) * fef.size()) : 0;
+    const size_t o_fea = fac ? place(sizeof(float) * fea.size()) : 0;
+    const size_t o_fwf = fac ? place(sizeof(float) * fwf.size()) : 0;
+    const size_t o_fwa = fac ? place(sizeof(float) * fwa.size()) : 0;
+    const size_t o_fuq = fac ? place(sizeof(int) * fuq.size()) : 0;
+    const size_t o_fubin = fac ? place(sizeof(int) * fubin.size()) : 0;
+    const size_t o_fqbin = fac ? place(sizeof(int) * fqbin.size()) : 0;
+    const size_t o_fqsteps = fac ? place(sizeof(int) * fqsteps.size()) : 0;
     if (mixed) {
         o_kf16 = place(sizeof(__half) * KE * n_ktab);
         o_ff16 = place(sizeof(__half) * (size_t)TP * NBP2);
@@ -676,6 +845,23 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         ok = ok && hipMemcpy(pl->kff, kff.data(), sizeof(float) * KEF, hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && hipMemcpy(pl->kaf, kaf.data(), sizeof(float) * KEF, hipMemcpyHostToDevice) == hipSuccess;
     }
+    if (fac) {
+        mpi3d_plan::Fac &f = pl->fac;
+        auto up = [&](auto *&dst, size_t o, const auto &v) {
+            dst = reinterpret_cast<std::remove_reference_t<decltype(dst)>>(tb + o);
+            ok = ok && hipMemcpy(dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice) == hipSuccess;
+        };
+        up(f.kf, o_fkf, fkf);
+        up(f.ka, o_fka, fka);
+        up(f.ef, o_fef, fef);
+        up(f.ea, o_fea, fea);
+        up(f.wf, o_fwf, fwf);
+        up(f.wa, o_fwa, fwa);
+        up(f.uq, o_fuq, fuq);
+        up(f.ubin, o_fubin, fubin);
+        up(f.qbin, o_fqbin, fqbin);
+        up(f.qsteps, o_fqsteps, fqsteps);
+    }
     if (precomp) {
         pl->gt = (float *)(tb + o_gt);
         pl->gta = (float *)(tb + o_gta);
@@ -722,6 +908,8 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         if (pl->fused)   // one pass; adjoint lines of nupf
             part_floats = std::max(part_floats, (size_t)pl->L * std::max(pl->scf.nsplit, pl->scf.serve_nsplit) *
                                                     std::max<size_t>(pl->nbp2, (size_t)pl->nupf));
+        if (pl->fac.on)   // adjoint: nsplit blocks of nup-column lines
+            part_floats = std::max(part_floats, (size_t)pl->fac.nsplit * pl->L * std::max(pl->nup, pl->nbp2));
         pl->ws_part = put(sizeof(float) * part_floats);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
         // per tensor-PSF pass: the forward's symmetric line sums, their
@@ -734,6 +922,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         pl->ws_rtb = put(mixed ? sizeof(uint16_t) * pl->L * pl->nup : 0);
         pl->ws_rtsc = put(mixed ? sizeof(float) * pl->L : 0);
         pl->ws_sig = put(np > 1 ? sizeof(float) * np * pl->L * pl->nup : 0);
+        pl->ws_fac = put(pl->fac.on ? sizeof(float) * ((pl->L + 31) / 32 * 32 + 1) * pl->fac.P * 2 * pl->fac.zst : 0);
         pl->op_ws_bytes = align256(o);
     }
     {
@@ -816,5 +1005,6 @@ extern "C" int mpi3d_plan_query(const mpi3d_plan *pl, mpi3d_plan_info *info)
     info->n_r = pl->nr;
     info->norm_iters = pl->norm_iters;
     info->op_scale = pl->op_scale;
+    info->dft_cycles = pl->fac.on ? pl->fac.C : 0;
     return MPI3D_OK;
 }

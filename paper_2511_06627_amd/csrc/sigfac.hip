@@ -1,0 +1,558 @@
+// The band DFT factored over drive cycles (FP32, gfx950 v_mfma_f32_32x32x2_f32).
+//
+// The kept bins omega_j (eq. bcompress) are integers, so with time t = n1 + P n2
+// (n1 < P, n2 < C, T = C P) the DFT phase splits exactly:
+//   omega_j t = omega_j n1 + (omega_j mod C) T n2 / C   (mod T),
+// and the band DFT of a line's time signal s (Appendix A, eq. DCmodel)
+//   b[j] = sum_t s[t] D_j e^{+2 pi i omega_j t / T} / sqrt(T)
+// becomes two short sums: a C-point DFT over the drive cycles at the R
+// distinct residues r_q of the kept bins mod C,
+//   Y_q[n1] = sum_n2 s[n1 + P n2] e^{+2 pi i r_q n2 / C},
+// then, per bin, a P-point sum over the phase within a cycle,
+//   b[j] = sum_n1 G_j[n1] Y_q(j)[n1],   G_j[n1] = D_j e^{+2 pi i omega_j n1 / T} / sqrt(T).
+// When the harmonics are bunched (R small against the 2 nb kept columns) this
+// replaces the T x 2nb contraction by T x 2R and P x 4nb ones.  The adjoint is
+// the exact transpose of both steps.
+//
+// Forward: fac_fwd_kernel runs the PSF contraction of a line tile chunk by
+// chunk (a chunk: 32 cycles n2 of one phase n1, PSF tables with their time
+// rows in that order) and feeds each 32 x 32 (time x line) result straight
+// into the residue DFT (table E), writing Y[row][n1][2q + re/im] once the C
+// cycles of a phase are in (Y and Z rows are the job's rows); fac_fwd_out_kernel then forms b per line tile
+// through LDS-staged Y, one 32-column MFMA tile per unit of at most 16 bins
+// of one residue.  Adjoint: fac_adj_in_kernel forms Z[row][n1][re/im][q]
+// from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
+// contraction's transpose, accumulating the lines over its phases (split
+// partial sums added in a fixed order afterwards).
+//
+// MFMA operand conventions as in sig.hip: lane l supplies A[l % 32][l / 32]
+// and B[l / 32][l % 32]; result register s of lane l holds row
+// 8(s/4) + 4(l/32) + s%4, column l%32.  Every table is pre-swizzled so a lane
+// fetches the operands of four consecutive MFMA steps with one 16-byte load.
+
+#include "device.h"
+
+namespace mpi3d {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+#define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
+
+// Table loads in flight per wave (a ring over the per-chunk load stream; its
+// size divides the stream length, padded with slots that load nothing).
+constexpr int fac_ring(int nl)
+{
+    for (int r = 8; r > 1; --r)
+        if (nl % r == 0) return 2 * r >= 8 ? r : 8;
+    return 8;
+}
+constexpr int fac_padded(int nl, int ring) { return (nl + ring - 1) / ring * ring; }
+
+// Wave position of the two line-tile kernels: a block of kFacWaves waves
+// covers kFacWaves consecutive 32-line tiles for one range of phases n1
+// (split); consecutive logical blocks share a range, so they share the PSF
+// table chunks in their XCD's L2.
+struct FacPos {
+    int tile, n1a, n1b, split;
+};
+
+__device__ __forceinline__ FacPos fac_pos(const FacArgs &a)
+{
+    const int nb = gridDim.x;
+    const int lb = xcd_logical(blockIdx.x, nb);
+    const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
+    FacPos p;
+    p.split = lb / tgroups;
+    p.tile = (lb - p.split * tgroups) * kFacWaves + (int)(threadIdx.x >> 6);
+    p.n1a = (int)((long)p.split * a.P / a.nsplit);
+    p.n1b = (int)((long)(p.split + 1) * a.P / a.nsplit);
+    return p;
+}
+
+// Forward, per wave: 32 lines, phases [n1a, n1b).  Chunk c = n1 CJ + j holds
+// the times n1 + P (32 j + i), i < 32.  A phase is straight-line code (its CJ
+// chunks, then the Y stores), and every store is unconditional -- Y rows are
+// the job's rows (rows past the job hold the results of zero lines) and
+// columns past yc go to the spare row a.ylines -- so the table loads of the
+// ring stay in flight across phases.
+template <int NUP, int RCT, int CJ>
+__global__ __launch_bounds__(64 * kFacWaves) void fac_fwd_kernel(FacArgs a)
+{
+    const FacPos fp = fac_pos(a);
+    if (fp.tile >= a.tiles || fp.n1a >= fp.n1b) return;
+    const SigJob &job = a.job;
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int row0 = fp.tile * 32;
+    const int r = row0 + (lane & 31);
+    const long il = r < job.rows ? job_line(job, r) : -1;
+    constexpr int NK = NUP / 8;           // PSF-table float4 loads per chunk
+    constexpr int NE = 4 * RCT;           // E-table float4 loads per chunk
+    constexpr int NL = NK + NE;
+    constexpr int kRing = fac_ring(NL);
+    constexpr int NLP = fac_padded(NL, kRing);
+
+    // B operand of the PSF contraction: rho[r][2 st + h]
+    float R[NUP / 2];
+    {
+        const float *rin = (const float *)job.in + (size_t)(il >= 0 ? il : 0) * job.in_stride + h;
+#pragma unroll
+        for (int st = 0; st < NUP / 2; ++st) R[st] = (il >= 0 && 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
+    }
+    // Y offset (floats) of this lane's first result row; result register j
+    // is row 8(j/4) + j%4 past it.  Per tile, the lane's column (or its place
+    // in the spare row when past yc).
+    const int ystride = a.P * a.yc;
+    const int ybase = (row0 + 4 * h) * ystride;
+    int ycol[RCT];
+    bool yok[RCT];
+#pragma unroll
+    for (int g = 0; g < RCT; ++g) {
+        const int col = 32 * g + (lane & 31);
+        yok[g] = col < a.yc;
+        ycol[g] = yok[g] ? ybase + col : a.ylines * ystride + col % a.yc;
+    }
+
+    const f32x4 *kf = (const f32x4 *)job.kf + lane;
+    const f32x4 *ef = (const f32x4 *)a.ef + lane;
+    auto load = [&](int cc, int i) -> f32x4 {
+        if (i < NK) return kf[((size_t)cc * NK + i) * 64];
+        return ef[((size_t)(cc % CJ) * NE + (i - NK)) * 64];
+    };
+    const int c1 = fp.n1b * CJ;
+    f32x4 ring[kRing];
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) ring[d] = d < NL ? load(fp.n1a * CJ, d) : f32x4{};
+    f32x16 acc[RCT];
+#pragma unroll
+    for (int g = 0; g < RCT; ++g) acc[g] = 0.f;
+
+    for (int n1 = fp.n1a; n1 < fp.n1b; ++n1) {
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+            const int c = n1 * CJ + j;
+            const int cnext = min(c + 1, c1 - 1);
+            f32x16 S = 0.f;
+#pragma unroll
+            for (int i = 0; i < NLP; ++i) {
+                const f32x4 v = ring[i % kRing];
+                const int nx = i + kRing;
+                if (nx < NLP) {
+                    if (nx < NL) ring[i % kRing] = load(c, nx);
+                } else if (nx - NLP < NL) {
+                    ring[i % kRing] = load(cnext, nx - NLP);
+                }
+                if (i >= NL) continue;
+                if (i < NK) {
+                    S = MFMA32(v[0], R[4 * i + 0], S);
+                    S = MFMA32(v[1], R[4 * i + 1], S);
+                    S = MFMA32(v[2], R[4 * i + 2], S);
+                    S = MFMA32(v[3], R[4 * i + 3], S);
+                } else {
+                    const int jj = i - NK, g = jj / 4, s4 = jj % 4;
+                    acc[g] = MFMA32(S[4 * s4 + 0], v[0], acc[g]);
+                    acc[g] = MFMA32(S[4 * s4 + 1], v[1], acc[g]);
+                    acc[g] = MFMA32(S[4 * s4 + 2], v[2], acc[g]);
+                    acc[g] = MFMA32(S[4 * s4 + 3], v[3], acc[g]);
+                }
+                // keep each load where the ring issues it, so kRing of them stay in flight
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // the C cycles of phase n1 are in
+        const int nof = n1 * a.yc;
+#pragma unroll
+        for (int g = 0; g < RCT; ++g) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                a.y[ycol[g] + (yok[g] ? (8 * (j / 4) + (j % 4)) * ystride + nof : 0)] = acc[g][j];
+            acc[g] = 0.f;
+        }
+    }
+}
+
+// Forward outer sum, one block of kOutWaves waves per 32-line tile and unit
+// split.  Y of the tile is staged kOutStage phases at a time in LDS as
+// [line][slot][phase] (line pitch yc kOutStage + 4 floats), column col in
+// slot (col % 4) yc/4 + col / 4, so a lane's A operands for a stage are two
+// 16-byte reads.  Thread t < 32 yc/4 stages line t / (yc/4), columns
+// 4 (t % (yc/4)) .. + 3: its 8 phase loads are 16-byte row pieces (a wave's
+// are contiguous) and each column's 8 phases two 16-byte LDS stores,
+// neighbouring threads 32 bytes apart.  The next stage's values and tables
+// are requested before this stage's MFMAs.  Wave w takes units
+// us + usplit (w + kOutWaves i).
+constexpr int kOutStage = 8;
+constexpr int kOutWaves = 8;
+constexpr int kUnitsPerWave = 5;
+
+__global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
+{
+    extern __shared__ __align__(16) float ys[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
+    const int tile = blockIdx.x, us = blockIdx.y, nus = gridDim.y;
+    const SigJob &job = a.job;
+    const int row0 = tile * 32;
+    const int pitch = a.yc * kOutStage + 4;
+    const int c4n = a.yc / 4;
+    const bool stager = tid < 32 * c4n;
+    const int sli = stager ? tid / c4n : 0, sc4 = stager ? tid % c4n : 0;
+    const int goff = ((row0 + sli) * a.P) * a.yc + 4 * sc4;     // phase 0 of this thread's run
+    float *lbase = ys + sli * pitch + sc4 * kOutStage;          // column 4 sc4 + e at + e c4n kOutStage
+    auto stage_load = [&](int n1s, f32x4 (&v)[kOutStage]) {
+#pragma unroll
+        for (int k = 0; k < kOutStage; ++k) {
+            const bool ok = stager && n1s + k < a.P;   // a phase past P reads as zero
+            const f32x4 t = *reinterpret_cast<const f32x4 *>(a.y + (ok ? goff + (n1s + k) * a.yc : 0));
+            v[k] = ok ? t : f32x4{};
+        }
+    };
+    f32x16 acc[kUnitsPerWave];
+#pragma unroll
+    for (int i = 0; i < kUnitsPerWave; ++i) acc[i] = 0.f;
+    int uu[kUnitsPerWave], aoff[kUnitsPerWave];
+#pragma unroll
+    for (int i = 0; i < kUnitsPerWave; ++i) {
+        uu[i] = us + nus * (wave + kOutWaves * i);
+        const int col = 2 * (uu[i] < a.U ? a.uq[uu[i]] : 0) + h;
+        aoff[i] = (lane & 31) * pitch + ((col % 4) * c4n + col / 4) * kOutStage;
+    }
+    const int nstage = (a.P + kOutStage - 1) / kOutStage;
+    // table operands of stage n1s / kOutStage for this wave's units
+    auto table_load = [&](int n1s, f32x4 (&b0)[kUnitsPerWave], f32x4 (&b1)[kUnitsPerWave]) {
+#pragma unroll
+        for (int i = 0; i < kUnitsPerWave; ++i) {
+            const int u = uu[i] < a.U ? uu[i] : 0;
+            const f32x4 *w = (const f32x4 *)a.wf + ((size_t)u * (a.Pp / 4) + n1s / 4) * 64 + lane;
+            b0[i] = w[0];
+            b1[i] = w[64];
+        }
+    };
+    f32x4 pf[kOutStage], b0[kUnitsPerWave], b1[kUnitsPerWave], n0[kUnitsPerWave], n1v[kUnitsPerWave];
+    table_load(0, b0, b1);
+    stage_load(0, pf);
+    for (int stg = 0; stg < nstage; ++stg) {
+        const int n1s = stg * kOutStage;
+        __syncthreads();   // the previous stage is consumed
+        if (stager) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float *d = lbase + e * c4n * kOutStage;
+                *reinterpret_cast<f32x4 *>(d) = f32x4{pf[0][e], pf[1][e], pf[2][e], pf[3][e]};
+                *reinterpret_cast<f32x4 *>(d + 4) = f32x4{pf[4][e], pf[5][e], pf[6][e], pf[7][e]};
+            }
+        }
+        __syncthreads();
+        // the next stage's operands load during this stage's products (tables
+        // first: this stage's were requested before its staged values, so
+        // they are in once those are)
+        const int nn = min(n1s + kOutStage, (nstage - 1) * kOutStage);
+        table_load(nn, n0, n1v);
+        if (stg + 1 < nstage) stage_load(nn, pf);
+#pragma unroll
+        for (int i = 0; i < kUnitsPerWave; ++i) {
+            if (uu[i] >= a.U) break;
+            const float *src = ys + aoff[i];
+            const f32x4 a0 = *reinterpret_cast<const f32x4 *>(src);
+            const f32x4 a1 = *reinterpret_cast<const f32x4 *>(src + 4);
+            acc[i] = MFMA32(a0[0], b0[i][0], acc[i]);
+            acc[i] = MFMA32(a0[1], b0[i][1], acc[i]);
+            acc[i] = MFMA32(a0[2], b0[i][2], acc[i]);
+            acc[i] = MFMA32(a0[3], b0[i][3], acc[i]);
+            acc[i] = MFMA32(a1[0], b1[i][0], acc[i]);
+            acc[i] = MFMA32(a1[1], b1[i][1], acc[i]);
+            acc[i] = MFMA32(a1[2], b1[i][2], acc[i]);
+            acc[i] = MFMA32(a1[3], b1[i][3], acc[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kUnitsPerWave; ++i) {
+            b0[i] = n0[i];
+            b1[i] = n1v[i];
+        }
+    }
+    // column l%32 of unit u: bin slot col/2, re/im col%2
+#pragma unroll
+    for (int i = 0; i < kUnitsPerWave; ++i) {
+        const int u = uu[i];
+        if (u >= a.U) break;
+        const int col = lane & 31;
+        const int jb = a.ubin[u * 16 + col / 2];
+        if (jb < 0) continue;
+        const int oc = 2 * jb + (col & 1);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int row = row0 + 8 * (j / 4) + 4 * h + (j % 4);
+            if (row < job.rows) job.part[(size_t)job_line(job, row) * a.nbp2 + oc] = acc[i][j];
+        }
+    }
+}
+
+// Adjoint outer sum: Z[line][n1][re/im][q] from the data, one block of
+// kInWaves waves per 32-line tile; stages of 16 phases (a 32-column MFMA tile:
+// phase col/2, re/im col%2) collected in LDS and written out row-contiguous.
+// Wave w takes residues w + kInWaves i; its data operands (the bins of those
+// residues, kQMax steps each) stay in registers, and a stage's table operands
+// are all requested before its first MFMA.
+constexpr int kZStage = 16;
+constexpr int kInWaves = 8;
+constexpr int kResPerWave = 3;
+
+__global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
+{
+    extern __shared__ __align__(16) float zs[];   // [32 lines][kZStage phases][zc + 4]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const SigJob &job = a.job;
+    const int row0 = tile * 32;
+    const int r = row0 + (lane & 31);
+    const long il = r < job.rows ? job_line(job, r) : -1;
+    const int zc = 2 * a.zst, zp = zc + 4;   // Z columns; LDS row pitch (padded against bank conflicts)
+    int qq[kResPerWave], qs[kResPerWave];
+#pragma unroll
+    for (int i = 0; i < kResPerWave; ++i) {
+        qq[i] = wave + kInWaves * i;
+        qs[i] = qq[i] < a.R ? a.qsteps[qq[i]] : 0;
+    }
+    // A operands: y[r][2 qbin[q][st] + h]
+    float Yv[kResPerWave][kQMax];
+    {
+        const float *yin = (const float *)job.in + (size_t)(il >= 0 ? il : 0) * job.in_stride + h;
+#pragma unroll
+        for (int i = 0; i < kResPerWave; ++i) {
+#pragma unroll
+            for (int st = 0; st < kQMax; ++st) {
+                const int jb = qq[i] < a.R ? a.qbin[qq[i] * kQMax + st] : -1;
+                Yv[i][st] = (il >= 0 && jb >= 0) ? yin[2 * jb] : 0.f;
+            }
+        }
+    }
+    // the padding columns q >= R are never written: zero the stage once
+    for (int f = tid; f < 32 * kZStage * zp; f += 64 * kInWaves) zs[f] = 0.f;
+    const int nstage = (a.P + kZStage - 1) / kZStage;
+    const int c4n = zc / 4;
+    // table operands of stage stg for this wave's residues
+    auto table_load = [&](int stg, f32x4 (&b)[kResPerWave][kQMax / 4]) {
+#pragma unroll
+        for (int i = 0; i < kResPerWave; ++i) {
+            const int q = qq[i] < a.R ? qq[i] : 0;
+            const f32x4 *w = (const f32x4 *)a.wa + ((size_t)(q * a.nzstage + stg) * (kQMax / 4)) * 64 + lane;
+#pragma unroll
+            for (int s4 = 0; s4 < kQMax / 4; ++s4) b[i][s4] = w[s4 * 64];
+        }
+    };
+    f32x4 b[kResPerWave][kQMax / 4], bn[kResPerWave][kQMax / 4];
+    table_load(0, b);
+    for (int stg = 0; stg < nstage; ++stg) {
+        table_load(min(stg + 1, nstage - 1), bn);   // the next stage's, during this one
+        __syncthreads();   // the previous stage is written out (and the zeros are in)
+#pragma unroll
+        for (int i = 0; i < kResPerWave; ++i) {
+            if (qq[i] >= a.R) break;
+            f32x16 acc = 0.f;
+#pragma unroll
+            for (int s4 = 0; s4 < kQMax / 4; ++s4) {
+                if (4 * s4 >= qs[i]) break;
+                acc = MFMA32(Yv[i][4 * s4 + 0], b[i][s4][0], acc);
+                acc = MFMA32(Yv[i][4 * s4 + 1], b[i][s4][1], acc);
+                acc = MFMA32(Yv[i][4 * s4 + 2], b[i][s4][2], acc);
+                acc = MFMA32(Yv[i][4 * s4 + 3], b[i][s4][3], acc);
+            }
+            const int col = lane & 31, n1l = col / 2, cr = col & 1;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int li = 8 * (j / 4) + 4 * h + (j % 4);
+                zs[(li * kZStage + n1l) * zp + cr * a.zst + qq[i]] = acc[j];
+            }
+        }
+        __syncthreads();
+        // the stage's rows (line, phase) are zc contiguous floats in Z
+        const int n1s = stg * kZStage;
+        for (int f = tid; f < 32 * kZStage * c4n; f += 64 * kInWaves) {
+            const int c4 = f % c4n, rest = f / c4n, n1l = rest % kZStage, li = rest / kZStage;
+            const int row = row0 + li, n1 = n1s + n1l;
+            if (n1 < a.P) {
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(zs + (li * kZStage + n1l) * zp + 4 * c4);
+                *reinterpret_cast<f32x4 *>(a.y + ((size_t)row * a.P + n1) * zc + 4 * c4) = v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kResPerWave; ++i)
+#pragma unroll
+            for (int s4 = 0; s4 < kQMax / 4; ++s4) b[i][s4] = bn[i][s4];
+    }
+}
+
+// Adjoint, per wave: 32 lines, phases [n1a, n1b): for each chunk the residue
+// DFT's transpose (A = E[time n2][col], B = Z[line][col]) then the PSF
+// contraction's transpose into the lines; split partial sums per phase range.
+// A phase is straight-line code: the next phase's Z operands are requested
+// before its CJ chunks.
+template <int NUP, int ZST, int CJ>
+__global__ __launch_bounds__(64 * kFacWaves) void fac_adj_kernel(FacArgs a)
+{
+    const FacPos fp = fac_pos(a);
+    if (fp.tile >= a.tiles || fp.n1a >= fp.n1b) return;
+    const SigJob &job = a.job;
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int row0 = fp.tile * 32;
+    const int r = row0 + (lane & 31);
+    const long il = r < job.rows ? job_line(job, r) : -1;
+    constexpr int PT = NUP / 32;          // detector tiles
+    constexpr int NE = ZST / 4;           // E-table float4 loads per chunk
+    constexpr int NK = 4 * PT;            // PSF-table float4 loads per chunk
+    constexpr int NL = NE + NK;
+    constexpr int kRing = fac_ring(NL);
+    constexpr int NLP = fac_padded(NL, kRing);
+    constexpr int ZC = 2 * ZST;
+
+    f32x16 racc[PT];
+#pragma unroll
+    for (int pt = 0; pt < PT; ++pt) racc[pt] = 0.f;
+    const f32x4 *ea = (const f32x4 *)a.ea + lane;
+    const f32x4 *ka = (const f32x4 *)job.ka + lane;
+    auto load = [&](int cc, int i) -> f32x4 {
+        if (i < NE) return ea[((size_t)(cc % CJ) * NE + i) * 64];
+        const int j = i - NE, s4 = j / PT, pt = j % PT;
+        return ka[(((size_t)cc * PT + pt) * 4 + s4) * 64];
+    };
+    // B operand of the residue DFT's transpose: Z[r][n1][h][st], st < ZST (Z rows
+    // are the job's rows; those past the job hold zeros)
+    const float *zrow = a.y + (size_t)r * a.P * ZC + h * ZST;
+    auto zload = [&](int n1, f32x4 (&zb)[ZST / 4]) {
+#pragma unroll
+        for (int i = 0; i < ZST / 4; ++i) zb[i] = *reinterpret_cast<const f32x4 *>(zrow + (size_t)n1 * ZC + 4 * i);
+    };
+    f32x4 zb[ZST / 4], zn[ZST / 4];
+    zload(fp.n1a, zb);
+    const int c1 = fp.n1b * CJ;
+    f32x4 ring[kRing];
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) ring[d] = d < NL ? load(fp.n1a * CJ, d) : f32x4{};
+
+    for (int n1 = fp.n1a; n1 < fp.n1b; ++n1) {
+        zload(min(n1 + 1, fp.n1b - 1), zn);   // the next phase's operands
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+            const int c = n1 * CJ + j;
+            const int cnext = min(c + 1, c1 - 1);
+            f32x16 G = 0.f;
+#pragma unroll
+            for (int i = 0; i < NLP; ++i) {
+                const f32x4 v = ring[i % kRing];
+                const int nx = i + kRing;
+                if (nx < NLP) {
+                    if (nx < NL) ring[i % kRing] = load(c, nx);
+                } else if (nx - NLP < NL) {
+                    ring[i % kRing] = load(cnext, nx - NLP);
+                }
+                if (i >= NL) continue;
+                if (i < NE) {
+                    G = MFMA32(v[0], zb[i][0], G);
+                    G = MFMA32(v[1], zb[i][1], G);
+                    G = MFMA32(v[2], zb[i][2], G);
+                    G = MFMA32(v[3], zb[i][3], G);
+                } else {
+                    const int jj = i - NE, s4 = jj / PT, pt = jj % PT;
+                    racc[pt] = MFMA32(G[4 * s4 + 0], v[0], racc[pt]);
+                    racc[pt] = MFMA32(G[4 * s4 + 1], v[1], racc[pt]);
+                    racc[pt] = MFMA32(G[4 * s4 + 2], v[2], racc[pt]);
+                    racc[pt] = MFMA32(G[4 * s4 + 3], v[3], racc[pt]);
+                }
+                __builtin_amdgcn_sched_barrier(0);   // the ring's loads stay in flight
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ZST / 4; ++i) zb[i] = zn[i];
+    }
+    float *out = job.part + (size_t)fp.split * job.part_stride;
+#pragma unroll
+    for (int pt = 0; pt < PT; ++pt) {
+        const int col = pt * 32 + (lane & 31);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int row = row0 + 8 * (j / 4) + 4 * h + (j % 4);
+            if (row < job.rows) out[(size_t)job_line(job, row) * NUP + col] = racc[pt][j];
+        }
+    }
+}
+
+typedef void (*FacKernel)(FacArgs);
+constexpr int kFacNups[] = {64, 128, 192, 256};
+#define FAC_FWD_ROW(NUP)                                                                                     \
+    {{fac_fwd_kernel<NUP, 1, 1>, fac_fwd_kernel<NUP, 1, 2>}, {fac_fwd_kernel<NUP, 2, 1>, fac_fwd_kernel<NUP, 2, 2>}}
+const FacKernel kFacFwd[4][2][2] = {FAC_FWD_ROW(64), FAC_FWD_ROW(128), FAC_FWD_ROW(192), FAC_FWD_ROW(256)};
+#undef FAC_FWD_ROW
+#define FAC_ADJ_Z(NUP, Z) {fac_adj_kernel<NUP, Z, 1>, fac_adj_kernel<NUP, Z, 2>}
+#define FAC_ADJ_ROW(NUP)                                                                                     \
+    {FAC_ADJ_Z(NUP, 4), FAC_ADJ_Z(NUP, 8), FAC_ADJ_Z(NUP, 12), FAC_ADJ_Z(NUP, 16), FAC_ADJ_Z(NUP, 20),         \
+     FAC_ADJ_Z(NUP, 24), FAC_ADJ_Z(NUP, 28), FAC_ADJ_Z(NUP, 32)}
+const FacKernel kFacAdj[4][8][2] = {FAC_ADJ_ROW(64), FAC_ADJ_ROW(128), FAC_ADJ_ROW(192), FAC_ADJ_ROW(256)};
+#undef FAC_ADJ_ROW
+#undef FAC_ADJ_Z
+
+int fac_nup_slot(int nup)
+{
+    for (int i = 0; i < 4; ++i)
+        if (kFacNups[i] == nup) return i;
+    return -1;
+}
+
+}  // namespace
+
+int fac_supported(int nup, int rct, int zst, int cj)
+{
+    return fac_nup_slot(nup) >= 0 && rct >= 1 && rct <= 2 && zst >= 4 && zst <= 32 && zst % 4 == 0 && cj >= 1 &&
+           cj <= 2;
+}
+
+static bool fac_args_ok(const FacArgs &a)
+{
+    return a.tiles > 0 && a.P > 0 && a.cj > 0 && a.nsplit >= 1 && a.nsplit <= a.P && a.yc % 4 == 0 &&
+           a.yc == 2 * a.zst && a.yc <= 32 * a.rct && a.R <= kInWaves * kResPerWave && a.R <= a.zst && a.yc <= 64 &&
+           a.Pp % kOutStage == 0 && a.Pp >= a.P && a.nzstage * kZStage >= a.P &&
+           fac_supported(a.nup, a.rct, a.zst, a.cj) && a.job.rows <= a.tiles * 32 &&
+           a.ylines >= a.tiles * 32 && (long)(a.ylines + 1) * a.P * a.yc < 0x7fffffffL;
+}
+
+hipError_t launch_fac_fwd(const FacArgs &a, hipStream_t st)
+{
+    if (a.job.rows <= 0) return hipSuccess;
+    if (!fac_args_ok(a) || a.usplit < 1 || a.usplit > kMaxFacSplit ||
+        a.U > kOutWaves * kUnitsPerWave * a.usplit)
+        return hipErrorInvalidValue;
+    const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
+    hipLaunchKernelGGL(kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1], dim3(tgroups * a.nsplit),
+                       dim3(64 * kFacWaves), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(float) * 32 * (size_t)(a.yc * kOutStage + 4);
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)fac_fwd_out_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fac_fwd_out_kernel, dim3(a.tiles, a.usplit), dim3(64 * kOutWaves), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fac_adj(const FacArgs &a, hipStream_t st)
+{
+    if (a.job.rows <= 0) return hipSuccess;
+    if (!fac_args_ok(a)) return hipErrorInvalidValue;
+    const size_t lds = sizeof(float) * 32 * (size_t)kZStage * (2 * a.zst + 4);
+    hipError_t e = hipSuccess;
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)fac_adj_in_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles), dim3(64 * kInWaves), lds, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
+    hipLaunchKernelGGL(kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1], dim3(tgroups * a.nsplit),
+                       dim3(64 * kFacWaves), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace mpi3d

@@ -71,6 +71,7 @@ class Plan:
         self.info = info
         self.op_scale = float(info.op_scale)      # c_A in use (estimated when 0 was passed)
         self.norm_iters = int(info.norm_iters)
+        self.dft_cycles = int(info.dft_cycles)   # FP32 band DFT factored over C-sample blocks (0: dense)
         self.shape = (nz, ny, nx)
         self.n_u = n_u or nx
         self.drive_axes = 2 if drive_axes == 2 else 1

@@ -124,9 +124,12 @@ def test_dual_gpu_adjoint_identity(case, torch_mod):
 
 def test_dual_x_half_is_the_single_drive_scan(torch_mod):
     """The first n_angles * nz lines of a dual-drive forward are the
-    single-drive scan's data: bit for bit with the collinear PSF; under the
-    tensor PSF the two plans may split time differently (their line counts
-    differ), so there the same values to FP32 rounding."""
+    single-drive scan's data: bit for bit when both plans run the same signal
+    kernels (collinear PSF, dense band DFT); otherwise the same values to FP32
+    rounding -- under the tensor PSF the two plans may split time differently
+    (their line counts differ), and a single-drive plan may take the band DFT
+    factored over drive cycles, which a dual-drive plan (two line groups) does
+    not."""
     from paper_2511_06627_amd.plan import Plan
     for name in ("dual_ragged", "dual_tensor_ragged"):
         nx, ny, nz, M, T, P, w, klo, khi, D, R = CASES[name]
@@ -135,7 +138,7 @@ def test_dual_x_half_is_the_single_drive_scan(torch_mod):
         x = _dev(torch_mod, random_volume(_geom(name), 7), torch_mod.float32)
         bd = pd.forward(x)
         bs = ps.forward(x)
-        if R == 0:
+        if R == 0 and ps.dft_cycles == 0:
             assert torch_mod.equal(bd[:M * nz].reshape(bs.shape), bs), name
         else:
             err = float(torch_mod.linalg.vector_norm(bd[:M * nz].reshape(bs.shape) - bs) / torch_mod.linalg.vector_norm(bs))
