@@ -178,6 +178,33 @@ def signal_flops(cfg):
     return 2.0 * L * (cfg.n_u * cfg.n_t + 2 * cfg.n_bins * cfg.n_t)
 
 
+def fac_flops(cfg, plan, kernel):
+    """Algorithmic flops of one launch of a kernel of the band DFT factored over
+    drive cycles (t = n1 + P n2, T = C P, R residues of the kept bins mod C),
+    real arithmetic over all L lines:
+      fac_fwd / fac_adj       2 L T (Nu + 2R): the PSF contraction and the
+                              C-point residue DFT (real signal, complex twiddles);
+      fac_fwd_out / fac_adj_in 8 L P nb: each bin's P-point complex sum."""
+    L, T = cfg.n_lines, cfg.n_t
+    P = T // plan.dft_cycles
+    if kernel in ("fac_fwd", "fac_adj"):
+        return 2.0 * L * T * (cfg.n_u + 2 * plan.dft_residues)
+    return 8.0 * L * P * cfg.n_bins
+
+
+def fac_bytes(cfg, plan, kernel):
+    """Algorithmic HBM bytes of one launch of a factored band-DFT kernel: its
+    inputs and outputs once (lines 4 L Nu, phase sums 4 L P 2R, data 8 L nb)
+    and its tables once (PSF table 4 T Nu and residue twiddles 8 C R for the
+    contraction kernels; per-bin phase twiddles 8 P nb for the outer sums)."""
+    L, T, C, R = cfg.n_lines, cfg.n_t, plan.dft_cycles, plan.dft_residues
+    P = T // C
+    phase = 4.0 * L * P * 2 * R
+    if kernel in ("fac_fwd", "fac_adj"):
+        return 4.0 * L * cfg.n_u + phase + 4.0 * T * cfg.n_u + 8.0 * C * R
+    return phase + 8.0 * L * cfg.n_bins + 8.0 * P * cfg.n_bins
+
+
 LDS_PEAK_GBS = 256 * 128 * 2.4      # 128 bytes per clock per CU, 256 CUs at 2.4 GHz (78.6 TB/s)
 
 
@@ -714,18 +741,47 @@ def operator_leg(torch, plan, cfg, x, b, warmup, steps, with_mixed=True):
           for k in ("project", "signal_fwd", "signal_adj", "backproject")}
     log("%s kernels (ms): %s" % (cfg.name, ", ".join("%s %.3f" % kv for kv in kt.items())))
     fl = signal_flops(cfg)
-    dom = max(("signal_fwd", "signal_adj"), key=lambda k: kt[k])
-    achieved = fl / (kt[dom] * 1e-3) / 1e12
-    out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                       "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                       "traffic": measured_traffic(cfg.name, dom), "flops_per_launch": fl,
-                       "algorithmic_bytes_per_launch": signal_bytes(cfg, dom)}
     kernels = {}
-    for k in ("signal_fwd", "signal_adj"):
-        a = fl / (kt[k] * 1e-3) / 1e12
-        kernels[k] = {"ms": round(kt[k], 4), "tflops": round(a, 2), "mfma_frac": round(a / FP32_PEAK_TFLOPS, 4),
-                      "hbm_bytes_measured": measured_traffic(cfg.name, k),
-                      "hbm_bytes_algorithmic": signal_bytes(cfg, k)}
+    if plan.dft_cycles:
+        # the band DFT factored over drive cycles: two kernels a stage; the
+        # roofline is that of the dominant one, on its own algorithmic flops
+        facs = ("fac_fwd", "fac_fwd_out", "fac_adj_in", "fac_adj")
+        kf = {k: plan.time_kernel(k, repeats=10, x=x, b=b, ws=ws) for k in facs}
+        log("%s factored band DFT (C = %d, %d residues) kernels (ms): %s"
+            % (cfg.name, plan.dft_cycles, plan.dft_residues, ", ".join("%s %.3f" % kv for kv in kf.items())))
+        dom = max(("fac_fwd", "fac_adj"), key=lambda k: kf[k])
+        fd = fac_flops(cfg, plan, dom)
+        achieved = fd / (kf[dom] * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                           "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                           "traffic": measured_traffic(cfg.name, dom), "flops_per_launch": fd,
+                           "algorithmic_bytes_per_launch": fac_bytes(cfg, plan, dom)}
+        for k in facs:
+            fk = fac_flops(cfg, plan, k)
+            a = fk / (kf[k] * 1e-3) / 1e12
+            kernels[k] = {"ms": round(kf[k], 4), "flops": fk, "tflops": round(a, 2),
+                          "mfma_frac": round(a / FP32_PEAK_TFLOPS, 4),
+                          "hbm_bytes_measured": measured_traffic(cfg.name, k),
+                          "hbm_bytes_algorithmic": fac_bytes(cfg, plan, k)}
+        stage = {"signal_fwd": ("fac_fwd", "fac_fwd_out"), "signal_adj": ("fac_adj_in", "fac_adj")}
+        for k, parts in stage.items():
+            fs = sum(fac_flops(cfg, plan, p) for p in parts)
+            kernels[k] = {"ms": round(kt[k], 4), "kernels": list(parts), "flops": fs,
+                          "tflops": round(fs / (kt[k] * 1e-3) / 1e12, 2),
+                          "dense_equivalent_tflops": round(fl / (kt[k] * 1e-3) / 1e12, 2),
+                          "dft_cycles": plan.dft_cycles, "dft_residues": plan.dft_residues}
+    else:
+        dom = max(("signal_fwd", "signal_adj"), key=lambda k: kt[k])
+        achieved = fl / (kt[dom] * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                           "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                           "traffic": measured_traffic(cfg.name, dom), "flops_per_launch": fl,
+                           "algorithmic_bytes_per_launch": signal_bytes(cfg, dom)}
+        for k in ("signal_fwd", "signal_adj"):
+            a = fl / (kt[k] * 1e-3) / 1e12
+            kernels[k] = {"ms": round(kt[k], 4), "tflops": round(a, 2), "mfma_frac": round(a / FP32_PEAK_TFLOPS, 4),
+                          "hbm_bytes_measured": measured_traffic(cfg.name, k),
+                          "hbm_bytes_algorithmic": signal_bytes(cfg, k)}
     for k in ("project", "backproject"):
         kernels[k] = projection_report(cfg, k, kt[k], measured_traffic(cfg.name, k))
     out["kernels"] = kernels
@@ -759,7 +815,9 @@ def operator_leg(torch, plan, cfg, x, b, warmup, steps, with_mixed=True):
 # ---------------------------------------------------------------------------
 # Profile summaries: rocprofv3 output (under gpurun_out/) -> profiles/
 # ---------------------------------------------------------------------------
-KERNEL_KEYS = (("sig_fwd_f32", "signal_fwd"), ("sig_adj_f32", "signal_adj"), ("sig_fwd_f16", "signal_fwd_mixed"),
+KERNEL_KEYS = (("fac_fwd_kernel", "fac_fwd"), ("fac_fwd_out_kernel", "fac_fwd_out"), ("fac_adj_in_kernel", "fac_adj_in"),
+               ("fac_adj_kernel", "fac_adj"),
+               ("sig_fwd_f32", "signal_fwd"), ("sig_adj_f32", "signal_adj"), ("sig_fwd_f16", "signal_fwd_mixed"),
                ("sig_adj_f16", "signal_adj_mixed"), ("proj_fwd_kernel<unsigned int>", "project_mixed"),
                ("proj_fwd_kernel", "project"), ("proj_adj_f16", "backproject_mixed"),
                ("proj_adj_kernel", "backproject"))

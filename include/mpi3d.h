@@ -176,6 +176,7 @@ typedef struct {
                                    samples C (T = C P: a C-point sum at the residues of the kept
                                    bins mod C, then a P-point sum per bin); 0 = one dense
                                    contraction over all T samples */
+    int32_t dft_residues;       /* distinct residues of the kept bins mod C (0 when dense) */
 } mpi3d_plan_info;
 
 /* Validates the geometry, builds the FP64 host tables (angles, trajectory,
@@ -333,10 +334,19 @@ void mpi3d_state_destroy(mpi3d_state *state);
  *                                   gather variant is timed)
  *   kernel 1  backprojection        reads the workspace, writes x_dev
  *   kernel 2  signal forward contraction (time signal + band DFT), reads
- *             the workspace's projections
- *   kernel 3  signal adjoint contraction, reads b_dev
+ *             the workspace's projections (an FP32 plan that factors the band
+ *             DFT over drive cycles, dft_cycles > 0: its two launches,
+ *             kernels 4 and 5)
+ *   kernel 3  signal adjoint contraction, reads b_dev (factored: kernels 6
+ *             and 7)
  *             (MIXED, kernels 2 and 3: the per-line scales and fp16 operand
  *             lines are prepared once, outside the timed launches)
+ *   kernels 4-7, FP32 plans with dft_cycles > 0 only (else MPI3D_EINVAL):
+ *   kernel 4  forward PSF contraction + C-point residue DFT (writes the
+ *             workspace's phase sums)
+ *   kernel 5  forward P-point outer sum per bin (reads the phase sums)
+ *   kernel 6  adjoint outer sum (reads b_dev, writes the phase sums)
+ *   kernel 7  adjoint residue DFT + PSF contraction (reads the phase sums)
  * The kernels' work does not depend on the values they read.  x_dev holds
  * n_vox floats, b_dev n_data_floats, ws_dev op_ws_bytes.
  */

@@ -48,7 +48,7 @@ class PlanInfo(ctypes.Structure):
         ("op_ws_bytes", ctypes.c_int64), ("solve_ws_bytes", ctypes.c_int64),
         ("table_bytes", ctypes.c_int64), ("history_doubles", ctypes.c_int64),
         ("n_r", ctypes.c_int32), ("norm_iters", ctypes.c_int32), ("op_scale", ctypes.c_double),
-        ("dft_cycles", ctypes.c_int32),
+        ("dft_cycles", ctypes.c_int32), ("dft_residues", ctypes.c_int32),
     ]
 
 

@@ -918,8 +918,9 @@ extern "C" int mpi3d_solve(const mpi3d_plan *pl, const float *b, float *x, const
 extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t precision, int32_t repeats, float *x,
                                  const float *b, void *ws, size_t ws_bytes, void *stream, float *avg_ms)
 {
-    if (!pl || !x || !b || !avg_ms || repeats < 1 || kernel < 0 || kernel > 3) return MPI3D_EINVAL;
+    if (!pl || !x || !b || !avg_ms || repeats < 1 || kernel < 0 || kernel > 7) return MPI3D_EINVAL;
     TRYRC(check_prec(pl, precision));
+    if (kernel >= 4 && !fac_on(pl, precision)) return MPI3D_EINVAL;
     TRYRC(ws_ok(ws, ws_bytes, pl->op_ws_bytes));
     DeviceGuard dg(pl->device);
     hipStream_t st = (hipStream_t)stream;
@@ -947,6 +948,9 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
             a.jobs[c] = kj[c];
         }
     }
+    // the factored band DFT's stages and kernels (FP32 plans that take it)
+    const FacArgs fwd_fac = fac_on(pl, precision) ? fac_args(LineJob{pl, w.rt, pl->nup, &w}) : FacArgs{};
+    const FacArgs adj_fac = fac_on(pl, precision) ? fac_args(LineJob{pl, b, pl->nb2, &w}) : FacArgs{};
     const bool mixed = precision == MPI3D_MIXED;
     hipError_t err = mixed && kernel == 0 ? launch_to_bf16(pl->nvox, x, w.xb, st) : hipSuccess;
     // the mixed signal kernels read fp16 operand lines: prepared once, untimed
@@ -964,15 +968,23 @@ extern "C" int mpi3d_time_kernel(const mpi3d_plan *pl, int32_t kernel, int32_t p
         case 2:
             if (precision == MPI3D_PRECOMPOSED)
                 err = gemm_signal_fwd(pl, w.rt, pl->nup, w.part, st) == MPI3D_OK ? hipSuccess : hipErrorUnknown;
+            else if (fac_on(pl, precision))
+                err = launch_fac_fwd(fwd_fac, st);
             else
                 err = launch_sig_fwd(pl, precision, a, st);
             break;
-        default:
+        case 3:
             if (precision == MPI3D_PRECOMPOSED)
                 err = gemm_signal_adj(pl, b, w.rt, pl->nup, st) == MPI3D_OK ? hipSuccess : hipErrorUnknown;
+            else if (fac_on(pl, precision))
+                err = launch_fac_adj(adj_fac, st);
             else
                 err = launch_sig_adj(pl, precision, a, st);
             break;
+        case 4: err = launch_fac_part(fwd_fac, kFacFwdInner, st); break;
+        case 5: err = launch_fac_part(fwd_fac, kFacFwdOuter, st); break;
+        case 6: err = launch_fac_part(adj_fac, kFacAdjOuter, st); break;
+        default: err = launch_fac_part(adj_fac, kFacAdjInner, st); break;
         }
     }
     if (err == hipSuccess) err = hipEventRecord(e1, st);

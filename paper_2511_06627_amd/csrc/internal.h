@@ -78,6 +78,7 @@ __host__ __device__ inline long job_line(const SigJob &j, int r)
 // one residue; the adjoint's over each residue's bins, at most kQMax.
 constexpr int kFacWaves = 8;        // waves (32-line tiles) per block of the line-tile kernels
 constexpr int kQMax = 24;           // bins per residue (adjoint outer sum, register operands)
+constexpr int kFacInWaves = 8;      // waves of the adjoint outer sum; wave w takes residues w + 8 i
 constexpr int kMaxFacSplit = 4;     // forward outer-sum blocks per line tile (40 units each)
 
 struct FacArgs {
@@ -273,6 +274,10 @@ int sig_fused_supported(int nupf, int gct);
 int fac_supported(int nup, int rct, int zst, int cj);
 hipError_t launch_fac_fwd(const FacArgs &a, hipStream_t st);
 hipError_t launch_fac_adj(const FacArgs &a, hipStream_t st);
+// one kernel of those stages: forward PSF contraction + residue DFT, forward
+// outer sum, adjoint outer sum, adjoint residue DFT + PSF contraction
+enum { kFacFwdInner = 0, kFacFwdOuter = 1, kFacAdjOuter = 2, kFacAdjInner = 3 };
+hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st);
 
 // Precomposed signal stage (gemm.hip): C[i][j] = alpha sum_q A_i[q] W[q][j]
 // (+ beta C[i][j] when beta != 0) for i < n, j < m, q < k, over `batch`

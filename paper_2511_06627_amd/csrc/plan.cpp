@@ -524,13 +524,33 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             f.Pp = (f.P + 7) / 8 * 8;
             f.cj = bestC / 32;
             f.nzstage = (f.P + 15) / 16;
-            // residues ascending; units: a residue's bins (ascending) 16 at a time
-            std::vector<int> slot(bestC, -1), res;
-            for (int j = 0; j < NB; ++j) slot[bins[j] % bestC] = 0;
+            // Residue order: the adjoint outer sum's wave w takes residues
+            // w, w + 8, w + 16 (so waves w < R % 8 take one more when 8 does
+            // not divide R) and spends a step per bin, so residues are dealt
+            // largest first to the least loaded wave with room, and numbered
+            // by (wave, turn).  Units: a residue's bins (ascending) 16 at a time.
+            std::vector<int> cnt(bestC, 0), byc;
+            for (int j = 0; j < NB; ++j) ++cnt[bins[j] % bestC];
             for (int r = 0; r < bestC; ++r)
-                if (slot[r] == 0) {
-                    slot[r] = (int)res.size();
-                    res.push_back(r);
+                if (cnt[r]) byc.push_back(r);
+            std::stable_sort(byc.begin(), byc.end(), [&](int x, int y) { return cnt[x] > cnt[y]; });
+            const int nw = kFacInWaves, nr = (int)byc.size();
+            std::vector<std::vector<int>> wres(nw);
+            std::vector<int> load(nw, 0), room(nw);
+            for (int w = 0; w < nw; ++w) room[w] = nr / nw + (w < nr % nw ? 1 : 0);
+            for (int r : byc) {
+                int best = -1;
+                for (int w = 0; w < nw; ++w)
+                    if ((int)wres[w].size() < room[w] && (best < 0 || load[w] < load[best])) best = w;
+                wres[best].push_back(r);
+                load[best] += (cnt[r] + 3) / 4 * 4;
+            }
+            std::vector<int> slot(bestC, -1), res(byc.size(), -1);
+            for (int w = 0; w < nw; ++w)
+                for (size_t i = 0; i < wres[w].size(); ++i) {
+                    const int q = w + nw * (int)i;
+                    res[q] = wres[w][i];
+                    slot[wres[w][i]] = q;
                 }
             f.R = (int)res.size();
             f.zst = (f.R + 3) / 4 * 4;
@@ -1006,5 +1026,6 @@ extern "C" int mpi3d_plan_query(const mpi3d_plan *pl, mpi3d_plan_info *info)
     info->norm_iters = pl->norm_iters;
     info->op_scale = pl->op_scale;
     info->dft_cycles = pl->fac.on ? pl->fac.C : 0;
+    info->dft_residues = pl->fac.on ? pl->fac.R : 0;
     return MPI3D_OK;
 }

@@ -173,14 +173,15 @@ __global__ __launch_bounds__(64 * kFacWaves) void fac_fwd_kernel(FacArgs a)
 }
 
 // Forward outer sum, one block of kOutWaves waves per 32-line tile and unit
-// split.  Y of the tile is staged kOutStage phases at a time in LDS as
-// [line][slot][phase] (line pitch yc kOutStage + 4 floats), column col in
+// split.  Y of the tile is staged kOutStage phases at a time in LDS (two
+// buffers) as [line][slot][phase] (line pitch yc kOutStage + 4 floats), column col in
 // slot (col % 4) yc/4 + col / 4, so a lane's A operands for a stage are two
 // 16-byte reads.  Thread t < 32 yc/4 stages line t / (yc/4), columns
 // 4 (t % (yc/4)) .. + 3: its 8 phase loads are 16-byte row pieces (a wave's
 // are contiguous) and each column's 8 phases two 16-byte LDS stores,
-// neighbouring threads 32 bytes apart.  The next stage's values and tables
-// are requested before this stage's MFMAs.  Wave w takes units
+// neighbouring threads 32 bytes apart.  Stage s + 1's values are requested
+// before stage s's MFMAs and stored to the other buffer after them; its
+// tables are requested before them too.  Wave w takes units
 // us + usplit (w + kOutWaves i).
 constexpr int kOutStage = 8;
 constexpr int kOutWaves = 8;
@@ -228,31 +229,33 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
             b1[i] = w[64];
         }
     };
+    // two LDS stage buffers: stage s + 1 is written to the other one while
+    // stage s's products read this one, one barrier a stage
+    const int bufsz = 32 * pitch;
+    auto stage_store = [&](int buf, const f32x4 (&v)[kOutStage]) {
+        if (!stager) return;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float *d = lbase + buf * bufsz + e * c4n * kOutStage;
+            *reinterpret_cast<f32x4 *>(d) = f32x4{v[0][e], v[1][e], v[2][e], v[3][e]};
+            *reinterpret_cast<f32x4 *>(d + 4) = f32x4{v[4][e], v[5][e], v[6][e], v[7][e]};
+        }
+    };
     f32x4 pf[kOutStage], b0[kUnitsPerWave], b1[kUnitsPerWave], n0[kUnitsPerWave], n1v[kUnitsPerWave];
     table_load(0, b0, b1);
     stage_load(0, pf);
+    stage_store(0, pf);
+    if (nstage > 1) stage_load(kOutStage, pf);
     for (int stg = 0; stg < nstage; ++stg) {
         const int n1s = stg * kOutStage;
-        __syncthreads();   // the previous stage is consumed
-        if (stager) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float *d = lbase + e * c4n * kOutStage;
-                *reinterpret_cast<f32x4 *>(d) = f32x4{pf[0][e], pf[1][e], pf[2][e], pf[3][e]};
-                *reinterpret_cast<f32x4 *>(d + 4) = f32x4{pf[4][e], pf[5][e], pf[6][e], pf[7][e]};
-            }
-        }
-        __syncthreads();
-        // the next stage's operands load during this stage's products (tables
-        // first: this stage's were requested before its staged values, so
-        // they are in once those are)
-        const int nn = min(n1s + kOutStage, (nstage - 1) * kOutStage);
-        table_load(nn, n0, n1v);
-        if (stg + 1 < nstage) stage_load(nn, pf);
+        __syncthreads();   // stage stg is in its buffer; the other buffer's stage is consumed
+        // the next stage's tables load during this stage's products (its staged
+        // values are in flight already)
+        table_load(min(n1s + kOutStage, (nstage - 1) * kOutStage), n0, n1v);
 #pragma unroll
         for (int i = 0; i < kUnitsPerWave; ++i) {
             if (uu[i] >= a.U) break;
-            const float *src = ys + aoff[i];
+            const float *src = ys + (stg & 1) * bufsz + aoff[i];
             const f32x4 a0 = *reinterpret_cast<const f32x4 *>(src);
             const f32x4 a1 = *reinterpret_cast<const f32x4 *>(src + 4);
             acc[i] = MFMA32(a0[0], b0[i][0], acc[i]);
@@ -268,6 +271,10 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
         for (int i = 0; i < kUnitsPerWave; ++i) {
             b0[i] = n0[i];
             b1[i] = n1v[i];
+        }
+        if (stg + 1 < nstage) {
+            stage_store((stg + 1) & 1, pf);
+            if (stg + 2 < nstage) stage_load(n1s + 2 * kOutStage, pf);
         }
     }
     // column l%32 of unit u: bin slot col/2, re/im col%2
@@ -294,19 +301,20 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 // residues, kQMax steps each) stay in registers, and a stage's table operands
 // are all requested before its first MFMA.
 constexpr int kZStage = 16;
-constexpr int kInWaves = 8;
+constexpr int kInWaves = kFacInWaves;
 constexpr int kResPerWave = 3;
 
 __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
 {
-    extern __shared__ __align__(16) float zs[];   // [32 lines][kZStage phases][zc + 4]
+    extern __shared__ __align__(16) float zs[];   // [32 lines (pitch lp)][kZStage phases][zc + 4]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
     const int tile = blockIdx.x;
     const SigJob &job = a.job;
     const int row0 = tile * 32;
     const int r = row0 + (lane & 31);
     const long il = r < job.rows ? job_line(job, r) : -1;
-    const int zc = 2 * a.zst, zp = zc + 4;   // Z columns; LDS row pitch (padded against bank conflicts)
+    // Z columns; LDS row and line pitches (padded against bank conflicts)
+    const int zc = 2 * a.zst, zp = zc + 4, lp = kZStage * zp + 8;
     int qq[kResPerWave], qs[kResPerWave];
 #pragma unroll
     for (int i = 0; i < kResPerWave; ++i) {
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
         }
     }
     // the padding columns q >= R are never written: zero the stage once
-    for (int f = tid; f < 32 * kZStage * zp; f += 64 * kInWaves) zs[f] = 0.f;
+    for (int f = tid; f < 32 * lp; f += 64 * kInWaves) zs[f] = 0.f;
     const int nstage = (a.P + kZStage - 1) / kZStage;
     const int c4n = zc / 4;
     // table operands of stage stg for this wave's residues
@@ -361,7 +369,7 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int li = 8 * (j / 4) + 4 * h + (j % 4);
-                zs[(li * kZStage + n1l) * zp + cr * a.zst + qq[i]] = acc[j];
+                zs[li * lp + n1l * zp + cr * a.zst + qq[i]] = acc[j];
             }
         }
         __syncthreads();
@@ -371,7 +379,7 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
             const int c4 = f % c4n, rest = f / c4n, n1l = rest % kZStage, li = rest / kZStage;
             const int row = row0 + li, n1 = n1s + n1l;
             if (n1 < a.P) {
-                const f32x4 v = *reinterpret_cast<const f32x4 *>(zs + (li * kZStage + n1l) * zp + 4 * c4);
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(zs + li * lp + n1l * zp + 4 * c4);
                 *reinterpret_cast<f32x4 *>(a.y + ((size_t)row * a.P + n1) * zc + 4 * c4) = v;
             }
         }
@@ -514,45 +522,57 @@ static bool fac_args_ok(const FacArgs &a)
            a.ylines >= a.tiles * 32 && (long)(a.ylines + 1) * a.P * a.yc < 0x7fffffffL;
 }
 
-hipError_t launch_fac_fwd(const FacArgs &a, hipStream_t st)
+hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
 {
     if (a.job.rows <= 0) return hipSuccess;
-    if (!fac_args_ok(a) || a.usplit < 1 || a.usplit > kMaxFacSplit ||
-        a.U > kOutWaves * kUnitsPerWave * a.usplit)
-        return hipErrorInvalidValue;
+    if (!fac_args_ok(a) || part < 0 || part > 3) return hipErrorInvalidValue;
     const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
-    hipLaunchKernelGGL(kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1], dim3(tgroups * a.nsplit),
-                       dim3(64 * kFacWaves), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t lds = sizeof(float) * 32 * (size_t)(a.yc * kOutStage + 4);
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)fac_fwd_out_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
-        if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    switch (part) {
+    case kFacFwdInner:
+        hipLaunchKernelGGL(kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1], dim3(tgroups * a.nsplit),
+                           dim3(64 * kFacWaves), 0, st, a);
+        break;
+    case kFacFwdOuter: {
+        if (a.usplit < 1 || a.usplit > kMaxFacSplit || a.U > kOutWaves * kUnitsPerWave * a.usplit)
+            return hipErrorInvalidValue;
+        const size_t lds = 2 * sizeof(float) * 32 * (size_t)(a.yc * kOutStage + 4);
+        if (lds > 64 * 1024) {
+            e = hipFuncSetAttribute((const void *)fac_fwd_out_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(fac_fwd_out_kernel, dim3(a.tiles, a.usplit), dim3(64 * kOutWaves), lds, st, a);
+        break;
     }
-    hipLaunchKernelGGL(fac_fwd_out_kernel, dim3(a.tiles, a.usplit), dim3(64 * kOutWaves), lds, st, a);
+    case kFacAdjOuter: {
+        const size_t lds = sizeof(float) * 32 * ((size_t)kZStage * (2 * a.zst + 4) + 8);
+        if (lds > 64 * 1024) {
+            e = hipFuncSetAttribute((const void *)fac_adj_in_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles), dim3(64 * kInWaves), lds, st, a);
+        break;
+    }
+    default:
+        hipLaunchKernelGGL(kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1], dim3(tgroups * a.nsplit),
+                           dim3(64 * kFacWaves), 0, st, a);
+        break;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_fac_fwd(const FacArgs &a, hipStream_t st)
+{
+    hipError_t e = launch_fac_part(a, kFacFwdInner, st);
+    return e == hipSuccess ? launch_fac_part(a, kFacFwdOuter, st) : e;
 }
 
 hipError_t launch_fac_adj(const FacArgs &a, hipStream_t st)
 {
-    if (a.job.rows <= 0) return hipSuccess;
-    if (!fac_args_ok(a)) return hipErrorInvalidValue;
-    const size_t lds = sizeof(float) * 32 * (size_t)kZStage * (2 * a.zst + 4);
-    hipError_t e = hipSuccess;
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)fac_adj_in_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles), dim3(64 * kInWaves), lds, st, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
-    hipLaunchKernelGGL(kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1], dim3(tgroups * a.nsplit),
-                       dim3(64 * kFacWaves), 0, st, a);
-    return hipGetLastError();
+    hipError_t e = launch_fac_part(a, kFacAdjOuter, st);
+    return e == hipSuccess ? launch_fac_part(a, kFacAdjInner, st) : e;
 }
 
 }  // namespace mpi3d

@@ -72,6 +72,7 @@ class Plan:
         self.op_scale = float(info.op_scale)      # c_A in use (estimated when 0 was passed)
         self.norm_iters = int(info.norm_iters)
         self.dft_cycles = int(info.dft_cycles)   # FP32 band DFT factored over C-sample blocks (0: dense)
+        self.dft_residues = int(info.dft_residues)
         self.shape = (nz, ny, nx)
         self.n_u = n_u or nx
         self.drive_axes = 2 if drive_axes == 2 else 1
@@ -186,7 +187,9 @@ class Plan:
                                                                 _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
         return out
 
-    KERNELS = {"project": 0, "backproject": 1, "signal_fwd": 2, "signal_adj": 3}
+    KERNELS = {"project": 0, "backproject": 1, "signal_fwd": 2, "signal_adj": 3,
+               # the factored band DFT's kernels (FP32 plans with dft_cycles > 0)
+               "fac_fwd": 4, "fac_fwd_out": 5, "fac_adj_in": 6, "fac_adj": 7}
 
     def time_kernel(self, kernel, repeats=10, precision="fp32", x=None, b=None, ws=None, stream=None):
         """Mean device time (ms) of one launch of an operator kernel, from HIP events."""
