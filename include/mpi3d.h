@@ -198,10 +198,10 @@ int mpi3d_forward(const mpi3d_plan *plan, int32_t precision, const float *x_dev,
  * same order, the same bits), with the operator workspace taken from a static
  * device array of MPI3D_NOALLOC_SCRATCH_BYTES per GPU that the library holds
  * until the process ends; the call allocates nothing.  Plans whose
- * op_ws_bytes exceed that size get MPI3D_ENOMEM (nothing is enqueued);
- * MPI3D_PRECOMPOSED gets MPI3D_ENOTSUP (its library GEMMs may allocate).
- * Every call on one GPU uses that GPU's one array: calls that overlap on a
- * GPU (concurrent streams or host threads) race and must be serialised by the
+ * op_ws_bytes exceed that size get MPI3D_ENOMEM (nothing is enqueued).  All
+ * three precisions are served.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on a GPU (concurrent streams or host threads)
+ * race and must be serialised by the
  * caller; consecutive calls on one stream are safe.  The array keeps the last
  * call's contents, none of which a later call reads before writing it. */
 #define MPI3D_NOALLOC_SCRATCH_BYTES (128ull << 20)

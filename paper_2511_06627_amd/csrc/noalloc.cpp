@@ -64,8 +64,6 @@ extern "C" int mpi3d_forward_noalloc(const mpi3d_plan *pl, int32_t precision, co
     if (!pl || !x || !b) return MPI3D_EINVAL;
     const int rc = mpi3d::check_prec(pl, precision);
     if (rc) return rc;
-    // the precomposed variant runs library GEMMs, which may allocate
-    if (precision == MPI3D_PRECOMPOSED) return MPI3D_ENOTSUP;
     if (pl->op_ws_bytes > kScratchBytes) return MPI3D_ENOMEM;
     if (pl->device < 0 || pl->device >= kMaxDevices) return MPI3D_EINVAL;
     CurrentDevice cd(pl->device);

@@ -2,8 +2,8 @@
 library's static scratch array instead of a caller workspace.
 
 Checked against mpi3d_forward with a caller workspace (the same kernels in the
-same order: equal bit for bit) and against the FP64 oracle, in FP32 and mixed
-precision, on two calls in a row whose second input is smaller (the array
+same order: equal bit for bit) and against the FP64 oracle, in FP32, mixed
+and precomposed precision, on two calls in a row whose second input is smaller (the array
 keeps the first call's contents); a plan whose workspace exceeds the array is
 refused before anything is enqueued.
 """
@@ -52,11 +52,11 @@ def test_noalloc_forward_matches_workspace_forward(torch_mod):
         _log("noalloc case %d: %dx%dx%d, %d angles, T %d" % (i, nx, ny, nz, M, T))
         g = _case(nx, ny, nz, M, T, khi, D)
         plan = Plan(nx, ny, nz, M, T, g.drive_cycles, g.psf_width, 1, khi, D, g.op_scale,
-                    precisions=("fp32", "mixed"))
+                    precisions=("fp32", "mixed", "precomposed"))
         x = random_volume(g, 50 + i)
         xd = torch_mod.from_numpy(x).float().cuda()
         want = oop.forward(g, x)
-        for prec, tol in (("fp32", 1e-5), ("mixed", 5e-3)):
+        for prec, tol in (("fp32", 1e-5), ("mixed", 5e-3), ("precomposed", 1e-5)):
             ref = plan.forward(xd, precision=prec)
             out = torch_mod.full(plan.data_shape, float("nan"), dtype=torch_mod.complex64, device="cuda")
             rc = _noalloc(plan, prec, xd, out, torch_mod)
@@ -83,5 +83,4 @@ def test_noalloc_refuses_what_does_not_fit(torch_mod):
     small = Plan(16, 16, 2, 2, 512, 512 / 256 + 1 / 3 + 1, 2.0, 1, 2, 0, 1.0, precisions=("fp32", "precomposed"))
     xs = torch_mod.zeros(small.shape, dtype=torch_mod.float32, device="cuda")
     os_ = torch_mod.zeros(small.data_shape, dtype=torch_mod.complex64, device="cuda")
-    assert _noalloc(small, "precomposed", xs, os_, torch_mod) == -4   # MPI3D_ENOTSUP
     assert _noalloc(small, "mixed", xs, os_, torch_mod) == -1         # no mixed tables: EINVAL
