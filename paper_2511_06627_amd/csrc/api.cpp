@@ -116,7 +116,7 @@ static bool fac_on(const mpi3d_plan *pl, int prec) { return prec == MPI3D_FP32 &
 // adjoint (nup or nupf columns a line).
 static int fwd_parts(const mpi3d_plan *pl, int prec, bool serve)
 {
-    if (fac_on(pl, prec)) return 1;
+    if (fac_on(pl, prec)) return pl->fac.psplit;
     return (fused_pass(pl, prec) ? 1 : pl->n_passes) * nsplit_of(pl, prec, serve);
 }
 static int adj_parts(const mpi3d_plan *pl, int prec, bool serve)
@@ -150,6 +150,8 @@ static FacArgs fac_args(const LineJob &lj)
     a.P = f.P; a.Pp = f.Pp; a.cj = f.cj;
     a.yc = 2 * f.zst; a.zst = f.zst; a.R = f.R; a.U = f.U; a.rct = f.rct;
     a.nsplit = f.nsplit; a.usplit = f.usplit; a.nzstage = f.nzstage;
+    a.psplit = f.psplit; a.zsplit = f.zsplit;
+    a.fwd_part_stride = pj->L * pj->nbp2;
     a.tiles = (lg.rows + 31) / 32;
     return a;
 }

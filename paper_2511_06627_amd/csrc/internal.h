@@ -97,6 +97,9 @@ struct FacArgs {
     int P, Pp, cj;           // phases, phases rounded up to 8, 32-cycle blocks per phase (C / 32)
     int yc, zst, R, U, rct;  // yc = 2 zst; rct: 32-column tiles of the residue DFT (1 or 2)
     int nsplit, usplit;      // phase ranges of the line-tile kernels; unit split of the forward outer sum
+    int psplit, zsplit;      // stage ranges of the forward outer sum (partial sums each) and of the
+                             // adjoint outer sum (disjoint phases of Z)
+    long fwd_part_stride;    // floats between the forward outer sum's partial-sum blocks
     int nzstage;             // 16-phase stages of the adjoint outer sum
     int tiles;               // 32-line tiles of the job
 };
@@ -188,7 +191,7 @@ struct mpi3d_plan {
     // time when it pays; tables in the plan's allocation
     struct Fac {
         bool on = false;
-        int C, P, Pp, cj, R, zst, U, rct, nsplit, usplit, nzstage;
+        int C, P, Pp, cj, R, zst, U, rct, nsplit, usplit, psplit, zsplit, nzstage;
         float *kf, *ka, *ef, *ea, *wf, *wa;
         int *uq, *ubin, *qbin, *qsteps;
     } fac;

@@ -569,6 +569,11 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             }
             f.U = (int)fuq.size();
             f.usplit = (f.U + 39) / 40;
+            // the outer sums' blocks: one per line tile (and unit split); small
+            // scans also split the phase stages so about 256 blocks run
+            const long tiles = (pl->L + 31) / 32;
+            f.psplit = (int)std::max<long>(1, std::min<long>({4, 256 / (tiles * f.usplit), (f.P + 7) / 8}));
+            f.zsplit = (int)std::max<long>(1, std::min<long>({4, 256 / tiles, (f.P + 15) / 16}));
             // phase ranges of the line-tile kernels: 8 tiles a block, one block
             // a CU; the fewest splits within 2% of the best time per phase
             const long tgroups = ((pl->L + 31) / 32 + kFacWaves - 1) / kFacWaves;
@@ -928,8 +933,9 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         if (pl->fused)   // one pass; adjoint lines of nupf
             part_floats = std::max(part_floats, (size_t)pl->L * std::max(pl->scf.nsplit, pl->scf.serve_nsplit) *
                                                     std::max<size_t>(pl->nbp2, (size_t)pl->nupf));
-        if (pl->fac.on)   // adjoint: nsplit blocks of nup-column lines
-            part_floats = std::max(part_floats, (size_t)pl->fac.nsplit * pl->L * std::max(pl->nup, pl->nbp2));
+        if (pl->fac.on)   // adjoint: nsplit blocks of nup-column lines; forward: psplit of nbp2 columns
+            part_floats = std::max(part_floats, (size_t)std::max(pl->fac.nsplit, pl->fac.psplit) * pl->L *
+                                                    std::max(pl->nup, pl->nbp2));
         pl->ws_part = put(sizeof(float) * part_floats);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);
         // per tensor-PSF pass: the forward's symmetric line sums, their

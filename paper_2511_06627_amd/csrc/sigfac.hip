@@ -191,7 +191,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 {
     extern __shared__ __align__(16) float ys[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
-    const int tile = blockIdx.x, us = blockIdx.y, nus = gridDim.y;
+    const int tile = blockIdx.x, us = blockIdx.y, nus = gridDim.y, ps = blockIdx.z;
     const SigJob &job = a.job;
     const int row0 = tile * 32;
     const int pitch = a.yc * kOutStage + 4;
@@ -218,7 +218,9 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
         const int col = 2 * (uu[i] < a.U ? a.uq[uu[i]] : 0) + h;
         aoff[i] = (lane & 31) * pitch + ((col % 4) * c4n + col / 4) * kOutStage;
     }
-    const int nstage = (a.P + kOutStage - 1) / kOutStage;
+    // this block's stages [s0, s1): range ps of psplit
+    const int nst = (a.P + kOutStage - 1) / kOutStage;
+    const int s0 = (int)((long)ps * nst / a.psplit), s1 = (int)((long)(ps + 1) * nst / a.psplit);
     // table operands of stage n1s / kOutStage for this wave's units
     auto table_load = [&](int n1s, f32x4 (&b0)[kUnitsPerWave], f32x4 (&b1)[kUnitsPerWave]) {
 #pragma unroll
@@ -242,16 +244,16 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
         }
     };
     f32x4 pf[kOutStage], b0[kUnitsPerWave], b1[kUnitsPerWave], n0[kUnitsPerWave], n1v[kUnitsPerWave];
-    table_load(0, b0, b1);
-    stage_load(0, pf);
-    stage_store(0, pf);
-    if (nstage > 1) stage_load(kOutStage, pf);
-    for (int stg = 0; stg < nstage; ++stg) {
+    table_load(s0 * kOutStage, b0, b1);
+    stage_load(s0 * kOutStage, pf);
+    stage_store(s0 & 1, pf);
+    if (s0 + 1 < s1) stage_load((s0 + 1) * kOutStage, pf);
+    for (int stg = s0; stg < s1; ++stg) {
         const int n1s = stg * kOutStage;
         __syncthreads();   // stage stg is in its buffer; the other buffer's stage is consumed
         // the next stage's tables load during this stage's products (its staged
         // values are in flight already)
-        table_load(min(n1s + kOutStage, (nstage - 1) * kOutStage), n0, n1v);
+        table_load(min(n1s + kOutStage, (s1 - 1) * kOutStage), n0, n1v);
 #pragma unroll
         for (int i = 0; i < kUnitsPerWave; ++i) {
             if (uu[i] >= a.U) break;
@@ -272,9 +274,9 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
             b0[i] = n0[i];
             b1[i] = n1v[i];
         }
-        if (stg + 1 < nstage) {
+        if (stg + 1 < s1) {
             stage_store((stg + 1) & 1, pf);
-            if (stg + 2 < nstage) stage_load(n1s + 2 * kOutStage, pf);
+            if (stg + 2 < s1) stage_load(n1s + 2 * kOutStage, pf);
         }
     }
     // column l%32 of unit u: bin slot col/2, re/im col%2
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = row0 + 8 * (j / 4) + 4 * h + (j % 4);
-            if (row < job.rows) job.part[(size_t)job_line(job, row) * a.nbp2 + oc] = acc[i][j];
+            if (row < job.rows) job.part[ps * a.fwd_part_stride + (size_t)job_line(job, row) * a.nbp2 + oc] = acc[i][j];
         }
     }
 }
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
 {
     extern __shared__ __align__(16) float zs[];   // [32 lines (pitch lp)][kZStage phases][zc + 4]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x, zsp = blockIdx.y;
     const SigJob &job = a.job;
     const int row0 = tile * 32;
     const int r = row0 + (lane & 31);
@@ -336,7 +338,9 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
     }
     // the padding columns q >= R are never written: zero the stage once
     for (int f = tid; f < 32 * lp; f += 64 * kInWaves) zs[f] = 0.f;
-    const int nstage = (a.P + kZStage - 1) / kZStage;
+    // this block's stages [s0, s1): range zsp of zsplit
+    const int nst = (a.P + kZStage - 1) / kZStage;
+    const int s0 = (int)((long)zsp * nst / a.zsplit), s1 = (int)((long)(zsp + 1) * nst / a.zsplit);
     const int c4n = zc / 4;
     // table operands of stage stg for this wave's residues
     auto table_load = [&](int stg, f32x4 (&b)[kResPerWave][kQMax / 4]) {
@@ -349,9 +353,9 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
         }
     };
     f32x4 b[kResPerWave][kQMax / 4], bn[kResPerWave][kQMax / 4];
-    table_load(0, b);
-    for (int stg = 0; stg < nstage; ++stg) {
-        table_load(min(stg + 1, nstage - 1), bn);   // the next stage's, during this one
+    table_load(s0, b);
+    for (int stg = s0; stg < s1; ++stg) {
+        table_load(min(stg + 1, s1 - 1), bn);   // the next stage's, during this one
         __syncthreads();   // the previous stage is written out (and the zeros are in)
 #pragma unroll
         for (int i = 0; i < kResPerWave; ++i) {
@@ -519,7 +523,8 @@ static bool fac_args_ok(const FacArgs &a)
            a.yc == 2 * a.zst && a.yc <= 32 * a.rct && a.R <= kInWaves * kResPerWave && a.R <= a.zst && a.yc <= 64 &&
            a.Pp % kOutStage == 0 && a.Pp >= a.P && a.nzstage * kZStage >= a.P &&
            fac_supported(a.nup, a.rct, a.zst, a.cj) && a.job.rows <= a.tiles * 32 &&
-           a.ylines >= a.tiles * 32 && (long)(a.ylines + 1) * a.P * a.yc < 0x7fffffffL;
+           a.ylines >= a.tiles * 32 && (long)(a.ylines + 1) * a.P * a.yc < 0x7fffffffL && a.psplit >= 1 &&
+           a.psplit <= (a.P + kOutStage - 1) / kOutStage && a.zsplit >= 1 && a.zsplit <= a.nzstage;
 }
 
 hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
@@ -542,7 +547,7 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
                                     (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(fac_fwd_out_kernel, dim3(a.tiles, a.usplit), dim3(64 * kOutWaves), lds, st, a);
+        hipLaunchKernelGGL(fac_fwd_out_kernel, dim3(a.tiles, a.usplit, a.psplit), dim3(64 * kOutWaves), lds, st, a);
         break;
     }
     case kFacAdjOuter: {
@@ -552,7 +557,7 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
                                     (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles), dim3(64 * kInWaves), lds, st, a);
+        hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles, a.zsplit), dim3(64 * kInWaves), lds, st, a);
         break;
     }
     default:
