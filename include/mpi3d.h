@@ -69,7 +69,11 @@ enum {
 };
 
 /* Operator precision.  FP32: projection in fp32, signal contractions on fp32
- * MFMA.  MIXED: the projection gathers a bf16 copy of the volume, the
+ * MFMA; with one PSF table and one line group the plan may factor the band
+ * DFT over drive cycles (Appendix A's sum regrouped exactly over t = n1 + P n2,
+ * T = C P: a C-point DFT at the residues of the kept bins mod C, then a P-point
+ * sum per bin; mpi3d_plan_info.dft_cycles), when that needs less MFMA work --
+ * the same operator with the sums in another order.  MIXED: the projection gathers a bf16 copy of the volume, the
  * backprojection fp16 lines with a power-of-two scale per line, and the
  * signal contractions run on fp16 MFMA with fp32 accumulation, per-line
  * power-of-two scaling and per-harmonic-band scaling.  PRECOMPOSED:
