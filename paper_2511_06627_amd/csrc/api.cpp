@@ -360,7 +360,8 @@ static int lines_to_volume(const mpi3d_plan *pl, int prec, const OpWs &w, bool s
             TRY(launch_fold_zlines(pl, w.rt, st));
             TRY(launch_lines16(pl->Lx, pl->nu, pl->nup, 0, 0, nullptr, nullptr, 1.0, rp, w.rt, w.rtb, w.rtsc, st));
         } else {
-            TRY(launch_lines16(pl->L, pl->nu, pl->nup, adj_parts(pl, prec, serve), pl->L * pl->nup, w.part, w.rowscale, pl->op_scale * (double)pl->adj_scale16, rp,
+            TRY(launch_lines16(pl->L, pl->nu, pl->nup, adj_parts(pl, prec, serve), pl->L * pl->nup, w.part,
+                               w.rowscale, pl->op_scale * (double)pl->adj_scale16, rp,
                                nullptr, w.rtb, w.rtsc, st));
         }
         TRY(launch_backproject16(pl, w.rtb, w.rtsc, xo, x_sub, lambda, parts, nparts, st, x_add));

@@ -18,10 +18,10 @@
 // chunk (a chunk: 32 cycles n2 of one phase n1, PSF tables with their time
 // rows in that order) and feeds each 32 x 32 (time x line) result straight
 // into the residue DFT (table E), writing Y[row][n1][2q + re/im] once the C
-// cycles of a phase are in (Y and Z rows are the job's rows); fac_fwd_out_kernel then forms b per line tile
-// through LDS-staged Y, one 32-column MFMA tile per unit of at most 16 bins
-// of one residue.  Adjoint: fac_adj_in_kernel forms Z[row][n1][re/im][q]
-// from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
+// cycles of a phase are in (Y and Z rows are the job's rows);
+// fac_fwd_out_kernel then forms b per line tile through LDS-staged Y, one
+// 32-column MFMA tile per unit of at most 16 bins of one residue.  Adjoint:
+// fac_adj_in_kernel forms Z[row][n1][re/im][q] from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
 // contraction's transpose, accumulating the lines over its phases (split
 // partial sums added in a fixed order afterwards).
 //
@@ -172,11 +172,11 @@ __global__ __launch_bounds__(64 * kFacWaves) void fac_fwd_kernel(FacArgs a)
     }
 }
 
-// Forward outer sum, one block of kOutWaves waves per 32-line tile and unit
-// split.  Y of the tile is staged kOutStage phases at a time in LDS (two
-// buffers) as [line][slot][phase] (line pitch yc kOutStage + 4 floats), column col in
-// slot (col % 4) yc/4 + col / 4, so a lane's A operands for a stage are two
-// 16-byte reads.  Thread t < 32 yc/4 stages line t / (yc/4), columns
+// Forward outer sum, one block of kOutWaves waves per 32-line tile, unit
+// split and stage range (partial sums ps).  Y of the tile is staged kOutStage
+// phases at a time in LDS (two buffers) as [line][slot][phase] (line pitch
+// yc kOutStage + 4 floats), column col in slot (col % 4) yc/4 + col / 4, so a
+// lane's A operands for a stage are two 16-byte reads.  Thread t < 32 yc/4 stages line t / (yc/4), columns
 // 4 (t % (yc/4)) .. + 3: its 8 phase loads are 16-byte row pieces (a wave's
 // are contiguous) and each column's 8 phases two 16-byte LDS stores,
 // neighbouring threads 32 bytes apart.  Stage s + 1's values are requested
@@ -296,12 +296,13 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
     }
 }
 
-// Adjoint outer sum: Z[line][n1][re/im][q] from the data, one block of
-// kInWaves waves per 32-line tile; stages of 16 phases (a 32-column MFMA tile:
-// phase col/2, re/im col%2) collected in LDS and written out row-contiguous.
-// Wave w takes residues w + kInWaves i; its data operands (the bins of those
-// residues, kQMax steps each) stay in registers, and a stage's table operands
-// are all requested before its first MFMA.
+// Adjoint outer sum: Z[row][n1][re/im][q] from the data, one block of
+// kInWaves waves per 32-line tile and stage range; stages of 16 phases (a
+// 32-column MFMA tile: phase col/2, re/im col%2) collected in LDS and written
+// out row-contiguous.  Wave w takes residues w + kInWaves i (the plan numbers
+// the residues so the waves' bin counts balance); its data operands (the bins
+// of those residues, up to kQMax steps each) stay in registers, and each
+// stage's table operands are requested during the stage before.
 constexpr int kZStage = 16;
 constexpr int kInWaves = kFacInWaves;
 constexpr int kResPerWave = 3;
