@@ -813,7 +813,7 @@ def operator_leg(torch, plan, cfg, x, b, warmup, steps, with_mixed=True):
 
 
 # ---------------------------------------------------------------------------
-# Profile summaries: rocprofv3 output (under gpurun_out/) -> profiles/
+# Profile summaries: rocprofv3 output directories -> profiles/
 # ---------------------------------------------------------------------------
 KERNEL_KEYS = (("fac_fwd_kernel", "fac_fwd"), ("fac_fwd_out_kernel", "fac_fwd_out"), ("fac_adj_in_kernel", "fac_adj_in"),
                ("fac_adj_kernel", "fac_adj"),
