@@ -121,7 +121,7 @@ static int fwd_parts(const mpi3d_plan *pl, int prec, bool serve)
 }
 static int adj_parts(const mpi3d_plan *pl, int prec, bool serve)
 {
-    if (fac_on(pl, prec)) return pl->fac.nsplit;
+    if (fac_on(pl, prec)) return pl->fac.nsplit_adj;
     return (fused_pass(pl, prec) ? 1 : pl->n_passes) * nsplit_of(pl, prec, serve) * sig_cfg(pl, prec).ngroups;
 }
 
@@ -149,7 +149,7 @@ static FacArgs fac_args(const LineJob &lj)
     a.nu = pj->nu; a.nup = pj->nup; a.nbp2 = pj->nbp2;
     a.P = f.P; a.Pp = f.Pp; a.cj = f.cj;
     a.yc = 2 * f.zst; a.zst = f.zst; a.R = f.R; a.U = f.U; a.rct = f.rct;
-    a.nsplit = f.nsplit; a.usplit = f.usplit; a.nzstage = f.nzstage;
+    a.nsplit = f.nsplit; a.nsplit_adj = f.nsplit_adj; a.usplit = f.usplit; a.nzstage = f.nzstage;
     a.psplit = f.psplit; a.zsplit = f.zsplit;
     a.fwd_part_stride = pj->L * pj->nbp2;
     a.tiles = (lg.rows + 31) / 32;

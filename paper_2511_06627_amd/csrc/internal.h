@@ -76,7 +76,8 @@ __host__ __device__ inline long job_line(const SigJob &j, int r)
 // phase sums Y (forward) and Z (adjoint), [line][P][2 zst] floats in the
 // workspace (plus one spare line).  The forward's outer sum runs over units of at most 16 bins of
 // one residue; the adjoint's over each residue's bins, at most kQMax.
-constexpr int kFacWaves = 8;        // waves (32-line tiles) per block of the line-tile kernels
+constexpr int kFacWavesFwd = 8;     // waves (32-line tiles) per block: forward line-tile kernel (two per SIMD)
+constexpr int kFacWavesAdj = 4;     // adjoint line-tile kernel (one per SIMD, a deeper load ring)
 constexpr int kQMax = 24;           // bins per residue (adjoint outer sum, register operands)
 constexpr int kFacInWaves = 8;      // waves of the adjoint outer sum; wave w takes residues w + 8 i
 constexpr int kMaxFacSplit = 4;     // forward outer-sum blocks per line tile (40 units each)
@@ -96,7 +97,8 @@ struct FacArgs {
     int nu, nup, nbp2;
     int P, Pp, cj;           // phases, phases rounded up to 8, 32-cycle blocks per phase (C / 32)
     int yc, zst, R, U, rct;  // yc = 2 zst; rct: 32-column tiles of the residue DFT (1 or 2)
-    int nsplit, usplit;      // phase ranges of the line-tile kernels; unit split of the forward outer sum
+    int nsplit, nsplit_adj;  // phase ranges of the forward and adjoint line-tile kernels
+    int usplit;              // unit split of the forward outer sum
     int psplit, zsplit;      // stage ranges of the forward outer sum (partial sums each) and of the
                              // adjoint outer sum (disjoint phases of Z)
     long fwd_part_stride;    // floats between the forward outer sum's partial-sum blocks
@@ -191,7 +193,7 @@ struct mpi3d_plan {
     // time when it pays; tables in the plan's allocation
     struct Fac {
         bool on = false;
-        int C, P, Pp, cj, R, zst, U, rct, nsplit, usplit, psplit, zsplit, nzstage;
+        int C, P, Pp, cj, R, zst, U, rct, nsplit, nsplit_adj, usplit, psplit, zsplit, nzstage;
         float *kf, *ka, *ef, *ea, *wf, *wa;
         int *uq, *ubin, *qbin, *qsteps;
     } fac;
@@ -272,8 +274,8 @@ int sig_fwd_supported(int nup, int gct, int precision, int pairs);
 int sig_adj_supported(int nup, int gct, int precision, int pairs);
 int sig_fused_supported(int nupf, int gct);
 // Factored band DFT (sigfac.hip): forward writes Y then the job's partial
-// sums (one split, nbp2 columns); adjoint writes Z then nsplit splits of
-// nup-column partial sums.
+// sums (psplit blocks of nbp2 columns); adjoint writes Z then nsplit_adj
+// splits of nup-column partial sums.
 int fac_supported(int nup, int rct, int zst, int cj);
 hipError_t launch_fac_fwd(const FacArgs &a, hipStream_t st);
 hipError_t launch_fac_adj(const FacArgs &a, hipStream_t st);

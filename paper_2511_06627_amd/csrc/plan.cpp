@@ -574,14 +574,20 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             const long tiles = (pl->L + 31) / 32;
             f.psplit = (int)std::max<long>(1, std::min<long>({4, 256 / (tiles * f.usplit), (f.P + 7) / 8}));
             f.zsplit = (int)std::max<long>(1, std::min<long>({4, 256 / tiles, (f.P + 15) / 16}));
-            // phase ranges of the line-tile kernels: 8 tiles a block, one block
-            // a CU; the fewest splits within 2% of the best time per phase
-            const long tgroups = ((pl->L + 31) / 32 + kFacWaves - 1) / kFacWaves;
-            auto per_phase = [&](int ns) { return (double)((tgroups * ns + 255) / 256) / ns; };
-            double pbest = 1e30;
-            for (int ns = 1; ns <= std::min(f.P, 64); ++ns) pbest = std::min(pbest, per_phase(ns));
-            f.nsplit = 1;
-            while (f.nsplit < std::min(f.P, 64) && per_phase(f.nsplit) > 1.02 * pbest) ++f.nsplit;
+            // phase ranges of the line-tile kernels (forward 8 tiles a block,
+            // adjoint 4; one block a CU either way): the fewest splits within
+            // 2% of the best time per phase
+            auto splits = [&](int waves) {
+                const long tgroups = ((pl->L + 31) / 32 + waves - 1) / waves;
+                auto per_phase = [&](int ns) { return (double)((tgroups * ns + 255) / 256) / ns; };
+                double pbest = 1e30;
+                for (int ns = 1; ns <= std::min(f.P, 64); ++ns) pbest = std::min(pbest, per_phase(ns));
+                int ns = 1;
+                while (ns < std::min(f.P, 64) && per_phase(ns) > 1.02 * pbest) ++ns;
+                return ns;
+            };
+            f.nsplit = splits(kFacWavesFwd);
+            f.nsplit_adj = splits(kFacWavesAdj);
             // tables
             const int C = bestC, P = f.P, CJ = f.cj, ZST = f.zst, RCT = f.rct, YC = 2 * ZST;
             auto tperm = [](int s2, int h) { return 8 * (s2 / 4) + 4 * h + (s2 % 4); };
@@ -934,7 +940,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             part_floats = std::max(part_floats, (size_t)pl->L * std::max(pl->scf.nsplit, pl->scf.serve_nsplit) *
                                                     std::max<size_t>(pl->nbp2, (size_t)pl->nupf));
         if (pl->fac.on)   // adjoint: nsplit blocks of nup-column lines; forward: psplit of nbp2 columns
-            part_floats = std::max(part_floats, (size_t)std::max(pl->fac.nsplit, pl->fac.psplit) * pl->L *
+            part_floats = std::max(part_floats, (size_t)std::max(pl->fac.nsplit_adj, pl->fac.psplit) * pl->L *
                                                     std::max(pl->nup, pl->nbp2));
         pl->ws_part = put(sizeof(float) * part_floats);
         pl->ws_norm = put(sizeof(double) * pl->max_parts);

@@ -41,33 +41,35 @@ namespace {
 #define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
 
 // Table loads in flight per wave (a ring over the per-chunk load stream; its
-// size divides the stream length, padded with slots that load nothing).
-constexpr int fac_ring(int nl)
+// size divides the stream length, padded with slots that load nothing): up to
+// 8 for the forward (two waves per SIMD), 16 for the adjoint (one).
+constexpr int fac_ring(int nl, int cap)
 {
-    for (int r = 8; r > 1; --r)
-        if (nl % r == 0) return 2 * r >= 8 ? r : 8;
-    return 8;
+    for (int r = cap; r > 1; --r)
+        if (nl % r == 0) return 2 * r >= cap ? r : cap;
+    return cap;
 }
 constexpr int fac_padded(int nl, int ring) { return (nl + ring - 1) / ring * ring; }
 
-// Wave position of the two line-tile kernels: a block of kFacWaves waves
-// covers kFacWaves consecutive 32-line tiles for one range of phases n1
-// (split); consecutive logical blocks share a range, so they share the PSF
-// table chunks in their XCD's L2.
+// Wave position of the two line-tile kernels: a block of WAVES waves covers
+// WAVES consecutive 32-line tiles for one of nsplit ranges of phases n1;
+// consecutive logical blocks share a range, so they share the PSF table chunks
+// in their XCD's L2.
 struct FacPos {
     int tile, n1a, n1b, split;
 };
 
-__device__ __forceinline__ FacPos fac_pos(const FacArgs &a)
+template <int WAVES>
+__device__ __forceinline__ FacPos fac_pos(const FacArgs &a, int nsplit)
 {
     const int nb = gridDim.x;
     const int lb = xcd_logical(blockIdx.x, nb);
-    const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
+    const int tgroups = (a.tiles + WAVES - 1) / WAVES;
     FacPos p;
     p.split = lb / tgroups;
-    p.tile = (lb - p.split * tgroups) * kFacWaves + (int)(threadIdx.x >> 6);
-    p.n1a = (int)((long)p.split * a.P / a.nsplit);
-    p.n1b = (int)((long)(p.split + 1) * a.P / a.nsplit);
+    p.tile = (lb - p.split * tgroups) * WAVES + (int)(threadIdx.x >> 6);
+    p.n1a = (int)((long)p.split * a.P / nsplit);
+    p.n1b = (int)((long)(p.split + 1) * a.P / nsplit);
     return p;
 }
 
@@ -78,9 +80,9 @@ __device__ __forceinline__ FacPos fac_pos(const FacArgs &a)
 // columns past yc go to the spare row a.ylines -- so the table loads of the
 // ring stay in flight across phases.
 template <int NUP, int RCT, int CJ>
-__global__ __launch_bounds__(64 * kFacWaves) void fac_fwd_kernel(FacArgs a)
+__global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 {
-    const FacPos fp = fac_pos(a);
+    const FacPos fp = fac_pos<kFacWavesFwd>(a, a.nsplit);
     if (fp.tile >= a.tiles || fp.n1a >= fp.n1b) return;
     const SigJob &job = a.job;
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(64 * kFacWaves) void fac_fwd_kernel(FacArgs a)
     constexpr int NK = NUP / 8;           // PSF-table float4 loads per chunk
     constexpr int NE = 4 * RCT;           // E-table float4 loads per chunk
     constexpr int NL = NK + NE;
-    constexpr int kRing = fac_ring(NL);
+    constexpr int kRing = fac_ring(NL, 8);
     constexpr int NLP = fac_padded(NL, kRing);
 
     // B operand of the PSF contraction: rho[r][2 st + h]
@@ -401,9 +403,9 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
 // A phase is straight-line code: the next phase's Z operands are requested
 // before its CJ chunks.
 template <int NUP, int ZST, int CJ>
-__global__ __launch_bounds__(64 * kFacWaves) void fac_adj_kernel(FacArgs a)
+__global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
 {
-    const FacPos fp = fac_pos(a);
+    const FacPos fp = fac_pos<kFacWavesAdj>(a, a.nsplit_adj);
     if (fp.tile >= a.tiles || fp.n1a >= fp.n1b) return;
     const SigJob &job = a.job;
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(64 * kFacWaves) void fac_adj_kernel(FacArgs a)
     constexpr int NE = ZST / 4;           // E-table float4 loads per chunk
     constexpr int NK = 4 * PT;            // PSF-table float4 loads per chunk
     constexpr int NL = NE + NK;
-    constexpr int kRing = fac_ring(NL);
+    constexpr int kRing = fac_ring(NL, 16);
     constexpr int NLP = fac_padded(NL, kRing);
     constexpr int ZC = 2 * ZST;
 
@@ -520,7 +522,8 @@ int fac_supported(int nup, int rct, int zst, int cj)
 
 static bool fac_args_ok(const FacArgs &a)
 {
-    return a.tiles > 0 && a.P > 0 && a.cj > 0 && a.nsplit >= 1 && a.nsplit <= a.P && a.yc % 4 == 0 &&
+    return a.tiles > 0 && a.P > 0 && a.cj > 0 && a.nsplit >= 1 && a.nsplit <= a.P && a.nsplit_adj >= 1 &&
+           a.nsplit_adj <= a.P && a.yc % 4 == 0 &&
            a.yc == 2 * a.zst && a.yc <= 32 * a.rct && a.R <= kInWaves * kResPerWave && a.R <= a.zst && a.yc <= 64 &&
            a.Pp % kOutStage == 0 && a.Pp >= a.P && a.nzstage * kZStage >= a.P &&
            fac_supported(a.nup, a.rct, a.zst, a.cj) && a.job.rows <= a.tiles * 32 &&
@@ -532,12 +535,12 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
 {
     if (a.job.rows <= 0) return hipSuccess;
     if (!fac_args_ok(a) || part < 0 || part > 3) return hipErrorInvalidValue;
-    const int tgroups = (a.tiles + kFacWaves - 1) / kFacWaves;
     hipError_t e = hipSuccess;
     switch (part) {
     case kFacFwdInner:
-        hipLaunchKernelGGL(kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1], dim3(tgroups * a.nsplit),
-                           dim3(64 * kFacWaves), 0, st, a);
+        hipLaunchKernelGGL(kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1],
+                           dim3((a.tiles + kFacWavesFwd - 1) / kFacWavesFwd * a.nsplit), dim3(64 * kFacWavesFwd), 0,
+                           st, a);
         break;
     case kFacFwdOuter: {
         if (a.usplit < 1 || a.usplit > kMaxFacSplit || a.U > kOutWaves * kUnitsPerWave * a.usplit)
@@ -562,8 +565,9 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
         break;
     }
     default:
-        hipLaunchKernelGGL(kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1], dim3(tgroups * a.nsplit),
-                           dim3(64 * kFacWaves), 0, st, a);
+        hipLaunchKernelGGL(kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1],
+                           dim3((a.tiles + kFacWavesAdj - 1) / kFacWavesAdj * a.nsplit_adj), dim3(64 * kFacWavesAdj),
+                           0, st, a);
         break;
     }
     return hipGetLastError();
