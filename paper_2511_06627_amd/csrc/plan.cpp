@@ -983,7 +983,7 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
         int ints[] = {pl->nu, pl->nup, pl->nt, pl->harm_lo, pl->harm_hi, pl->half_band, pl->nbp2,
                       pl->sc[0].pairs, pl->sc[0].ngroups, pl->sc[0].gct, pl->sc[1].pairs, pl->sc[1].ngroups,
                       pl->sc[1].gct, precisions, n_classes, psf_rows, drive_axes, drive_axes == 2 ? pl->nz : 0,
-                      pl->fused ? pl->nupf : 0, pl->fused ? pl->scf.gct : 0};
+                      pl->fused ? pl->nupf : 0, pl->fused ? pl->scf.gct : 0, pl->fac.on ? pl->fac.C : 0};
         double dbl[] = {pl->P, pl->a, pl->w, pl->raster_sweep, drive_axes == 2 ? pl->a_z : 0.0};
         mix(ints, sizeof(ints));
         mix(dbl, sizeof(dbl));
