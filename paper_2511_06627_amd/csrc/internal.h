@@ -76,8 +76,9 @@ __host__ __device__ inline long job_line(const SigJob &j, int r)
 // phase sums Y (forward) and Z (adjoint), [line][P][2 zst] floats in the
 // workspace (plus one spare line).  The forward's outer sum runs over units of at most 16 bins of
 // one residue; the adjoint's over each residue's bins, at most kQMax.
-constexpr int kFacWavesFwd = 8;     // waves (32-line tiles) per block: forward line-tile kernel (two per SIMD)
-constexpr int kFacWavesAdj = 4;     // adjoint line-tile kernel (one per SIMD, a deeper load ring)
+constexpr int kFacWavesFwd = 8;     // waves (32-line tiles) per block of the forward line-tile kernel
+                                    // (two per SIMD: one hides the other's wait at the chunk barrier)
+constexpr int kFacWavesAdj = 8;     // and of the adjoint line-tile kernel
 constexpr int kQMax = 24;           // bins per residue (adjoint outer sum, register operands)
 constexpr int kFacInWaves = 8;      // waves of the adjoint outer sum; wave w takes residues w + 8 i
 constexpr int kMaxFacSplit = 4;     // forward outer-sum blocks per line tile (40 units each)

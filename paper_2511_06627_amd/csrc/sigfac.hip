@@ -40,17 +40,6 @@ namespace {
 
 #define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
 
-// Table loads in flight per wave (a ring over the per-chunk load stream; its
-// size divides the stream length, padded with slots that load nothing): up to
-// 8 for the forward (two waves per SIMD), 16 for the adjoint (one).
-constexpr int fac_ring(int nl, int cap)
-{
-    for (int r = cap; r > 1; --r)
-        if (nl % r == 0) return 2 * r >= cap ? r : cap;
-    return cap;
-}
-constexpr int fac_padded(int nl, int ring) { return (nl + ring - 1) / ring * ring; }
-
 // Wave position of the two line-tile kernels: a block of WAVES waves covers
 // WAVES consecutive 32-line tiles for one of nsplit ranges of phases n1;
 // consecutive logical blocks share a range, so they share the PSF table chunks
@@ -74,26 +63,33 @@ __device__ __forceinline__ FacPos fac_pos(const FacArgs &a, int nsplit)
 }
 
 // Forward, per wave: 32 lines, phases [n1a, n1b).  Chunk c = n1 CJ + j holds
-// the times n1 + P (32 j + i), i < 32.  A phase is straight-line code (its CJ
-// chunks, then the Y stores), and every store is unconditional -- Y rows are
-// the job's rows (rows past the job hold the results of zero lines) and
-// columns past yc go to the spare row a.ylines -- so the table loads of the
-// ring stay in flight across phases.
+// the times n1 + P (32 j + i), i < 32.  The block's waves walk the same
+// phases, so each PSF-table chunk is staged once per block in LDS (two
+// buffers: chunk c + 1 is stored while chunk c is used, chunk c + 2 already
+// requested into registers; one barrier a chunk), and the residue DFT table
+// sits in LDS for the whole launch.  A wave past the last tile still stages.
+// Each phase's Y stores are unconditional -- Y rows are the job's rows (rows
+// past the job hold the results of zero lines) and columns past yc go to the
+// spare row a.ylines.
 template <int NUP, int RCT, int CJ>
 __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 {
+    // LDS: two PSF-table chunk buffers (NK x 64 16-byte words each), then the
+    // residue DFT table (CJ x NE x 64 words)
+    extern __shared__ __align__(16) f32x4 lk[];
     const FacPos fp = fac_pos<kFacWavesFwd>(a, a.nsplit);
-    if (fp.tile >= a.tiles || fp.n1a >= fp.n1b) return;
+    if (fp.n1a >= fp.n1b) return;                 // the whole block
+    const bool active = fp.tile < a.tiles;        // a wave past the last tile still stages
     const SigJob &job = a.job;
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5;
     const int row0 = fp.tile * 32;
     const int r = row0 + (lane & 31);
-    const long il = r < job.rows ? job_line(job, r) : -1;
-    constexpr int NK = NUP / 8;           // PSF-table float4 loads per chunk
-    constexpr int NE = 4 * RCT;           // E-table float4 loads per chunk
-    constexpr int NL = NK + NE;
-    constexpr int kRing = fac_ring(NL, 8);
-    constexpr int NLP = fac_padded(NL, kRing);
+    const long il = active && r < job.rows ? job_line(job, r) : -1;
+    constexpr int NK = NUP / 8;           // PSF-table words per lane per chunk
+    constexpr int NE = 4 * RCT;           // E-table words per lane per chunk
+    constexpr int CW = NK * 64;           // words per chunk
+    constexpr int KPT = CW / (64 * kFacWavesFwd);   // chunk words a thread stages
+    f32x4 *ebuf = lk + 2 * CW;
 
     // B operand of the PSF contraction: rho[r][2 st + h]
     float R[NUP / 2];
@@ -102,9 +98,6 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 #pragma unroll
         for (int st = 0; st < NUP / 2; ++st) R[st] = (il >= 0 && 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
     }
-    // Y offset (floats) of this lane's first result row; result register j
-    // is row 8(j/4) + j%4 past it.  Per tile, the lane's column (or its place
-    // in the spare row when past yc).
     const int ystride = a.P * a.yc;
     const int ybase = (row0 + 4 * h) * ystride;
     int ycol[RCT];
@@ -116,16 +109,23 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
         ycol[g] = yok[g] ? ybase + col : a.ylines * ystride + col % a.yc;
     }
 
-    const f32x4 *kf = (const f32x4 *)job.kf + lane;
-    const f32x4 *ef = (const f32x4 *)a.ef + lane;
-    auto load = [&](int cc, int i) -> f32x4 {
-        if (i < NK) return kf[((size_t)cc * NK + i) * 64];
-        return ef[((size_t)(cc % CJ) * NE + (i - NK)) * 64];
-    };
-    const int c1 = fp.n1b * CJ;
-    f32x4 ring[kRing];
+    const f32x4 *kf = (const f32x4 *)job.kf;
+    const f32x4 *ef = (const f32x4 *)a.ef;
+    for (int idx = tid; idx < CJ * NE * 64; idx += 64 * kFacWavesFwd) ebuf[idx] = ef[idx];
+    const int c0 = fp.n1a * CJ, c1 = fp.n1b * CJ;
+    f32x4 pk[KPT];
+    auto chunk_load = [&](int cc) {
 #pragma unroll
-    for (int d = 0; d < kRing; ++d) ring[d] = d < NL ? load(fp.n1a * CJ, d) : f32x4{};
+        for (int k = 0; k < KPT; ++k) pk[k] = kf[(size_t)cc * CW + tid + 64 * kFacWavesFwd * k];
+    };
+    auto chunk_store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) lk[buf * CW + tid + 64 * kFacWavesFwd * k] = pk[k];
+    };
+    chunk_load(c0);
+    chunk_store(c0 & 1);
+    if (c0 + 1 < c1) chunk_load(c0 + 1);
+    __syncthreads();
     f32x16 acc[RCT];
 #pragma unroll
     for (int g = 0; g < RCT; ++g) acc[g] = 0.f;
@@ -134,42 +134,45 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
             const int c = n1 * CJ + j;
-            const int cnext = min(c + 1, c1 - 1);
-            f32x16 S = 0.f;
+            if (active) {
+                const f32x4 *kb = lk + (c & 1) * CW + lane;
+                f32x16 S = 0.f;
 #pragma unroll
-            for (int i = 0; i < NLP; ++i) {
-                const f32x4 v = ring[i % kRing];
-                const int nx = i + kRing;
-                if (nx < NLP) {
-                    if (nx < NL) ring[i % kRing] = load(c, nx);
-                } else if (nx - NLP < NL) {
-                    ring[i % kRing] = load(cnext, nx - NLP);
-                }
-                if (i >= NL) continue;
-                if (i < NK) {
+                for (int i = 0; i < NK; ++i) {
+                    const f32x4 v = kb[i * 64];
                     S = MFMA32(v[0], R[4 * i + 0], S);
                     S = MFMA32(v[1], R[4 * i + 1], S);
                     S = MFMA32(v[2], R[4 * i + 2], S);
                     S = MFMA32(v[3], R[4 * i + 3], S);
-                } else {
-                    const int jj = i - NK, g = jj / 4, s4 = jj % 4;
+                }
+                const f32x4 *eb = ebuf + j * NE * 64 + lane;
+#pragma unroll
+                for (int jj = 0; jj < NE; ++jj) {
+                    const f32x4 v = eb[jj * 64];
+                    const int g = jj / 4, s4 = jj % 4;
                     acc[g] = MFMA32(S[4 * s4 + 0], v[0], acc[g]);
                     acc[g] = MFMA32(S[4 * s4 + 1], v[1], acc[g]);
                     acc[g] = MFMA32(S[4 * s4 + 2], v[2], acc[g]);
                     acc[g] = MFMA32(S[4 * s4 + 3], v[3], acc[g]);
                 }
-                // keep each load where the ring issues it, so kRing of them stay in flight
-                __builtin_amdgcn_sched_barrier(0);
             }
+            // chunk c + 1 goes to the buffer chunk c - 1 left (read by every
+            // wave before the last barrier); chunk c + 2 is requested
+            if (c + 1 < c1) {
+                chunk_store((c + 1) & 1);
+                if (c + 2 < c1) chunk_load(c + 2);
+            }
+            __syncthreads();
         }
-        // the C cycles of phase n1 are in
-        const int nof = n1 * a.yc;
+        if (active) {
+            const int nof = n1 * a.yc;
 #pragma unroll
-        for (int g = 0; g < RCT; ++g) {
+            for (int g = 0; g < RCT; ++g) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                a.y[ycol[g] + (yok[g] ? (8 * (j / 4) + (j % 4)) * ystride + nof : 0)] = acc[g][j];
-            acc[g] = 0.f;
+                for (int j = 0; j < 16; ++j)
+                    a.y[ycol[g] + (yok[g] ? (8 * (j / 4) + (j % 4)) * ystride + nof : 0)] = acc[g][j];
+                acc[g] = 0.f;
+            }
         }
     }
 }
@@ -400,85 +403,97 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
 // Adjoint, per wave: 32 lines, phases [n1a, n1b): for each chunk the residue
 // DFT's transpose (A = E[time n2][col], B = Z[line][col]) then the PSF
 // contraction's transpose into the lines; split partial sums per phase range.
-// A phase is straight-line code: the next phase's Z operands are requested
-// before its CJ chunks.
+// The PSF-table chunks are staged once per block in LDS as in the forward,
+// the residue DFT table sits in LDS, and the next phase's Z operands are
+// requested before its CJ chunks.
 template <int NUP, int ZST, int CJ>
 __global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
 {
+    extern __shared__ __align__(16) f32x4 lk[];
     const FacPos fp = fac_pos<kFacWavesAdj>(a, a.nsplit_adj);
-    if (fp.tile >= a.tiles || fp.n1a >= fp.n1b) return;
+    if (fp.n1a >= fp.n1b) return;                 // the whole block
+    const bool active = fp.tile < a.tiles;        // a wave past the last tile still stages
     const SigJob &job = a.job;
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5;
     const int row0 = fp.tile * 32;
     const int r = row0 + (lane & 31);
-    const long il = r < job.rows ? job_line(job, r) : -1;
     constexpr int PT = NUP / 32;          // detector tiles
-    constexpr int NE = ZST / 4;           // E-table float4 loads per chunk
-    constexpr int NK = 4 * PT;            // PSF-table float4 loads per chunk
-    constexpr int NL = NE + NK;
-    constexpr int kRing = fac_ring(NL, 16);
-    constexpr int NLP = fac_padded(NL, kRing);
+    constexpr int NE = ZST / 4;           // E-table words per lane per chunk
+    constexpr int NK = 4 * PT;            // PSF-table words per lane per chunk
+    constexpr int CW = NK * 64;           // words per chunk
+    constexpr int KPT = CW / (64 * kFacWavesAdj);
     constexpr int ZC = 2 * ZST;
+    f32x4 *ebuf = lk + 2 * CW;
 
     f32x16 racc[PT];
 #pragma unroll
     for (int pt = 0; pt < PT; ++pt) racc[pt] = 0.f;
-    const f32x4 *ea = (const f32x4 *)a.ea + lane;
-    const f32x4 *ka = (const f32x4 *)job.ka + lane;
-    auto load = [&](int cc, int i) -> f32x4 {
-        if (i < NE) return ea[((size_t)(cc % CJ) * NE + i) * 64];
-        const int j = i - NE, s4 = j / PT, pt = j % PT;
-        return ka[(((size_t)cc * PT + pt) * 4 + s4) * 64];
-    };
+    const f32x4 *ka = (const f32x4 *)job.ka;
+    const f32x4 *ea = (const f32x4 *)a.ea;
+    for (int idx = tid; idx < CJ * NE * 64; idx += 64 * kFacWavesAdj) ebuf[idx] = ea[idx];
     // B operand of the residue DFT's transpose: Z[r][n1][h][st], st < ZST (Z rows
     // are the job's rows; those past the job hold zeros)
-    const float *zrow = a.y + (size_t)r * a.P * ZC + h * ZST;
+    const float *zrow = a.y + (size_t)(active ? r : 0) * a.P * ZC + h * ZST;
     auto zload = [&](int n1, f32x4 (&zb)[ZST / 4]) {
 #pragma unroll
         for (int i = 0; i < ZST / 4; ++i) zb[i] = *reinterpret_cast<const f32x4 *>(zrow + (size_t)n1 * ZC + 4 * i);
     };
+    const int c0 = fp.n1a * CJ, c1 = fp.n1b * CJ;
+    f32x4 pk[KPT];
+    auto chunk_load = [&](int cc) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) pk[k] = ka[(size_t)cc * CW + tid + 64 * kFacWavesAdj * k];
+    };
+    auto chunk_store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) lk[buf * CW + tid + 64 * kFacWavesAdj * k] = pk[k];
+    };
     f32x4 zb[ZST / 4], zn[ZST / 4];
     zload(fp.n1a, zb);
-    const int c1 = fp.n1b * CJ;
-    f32x4 ring[kRing];
-#pragma unroll
-    for (int d = 0; d < kRing; ++d) ring[d] = d < NL ? load(fp.n1a * CJ, d) : f32x4{};
+    chunk_load(c0);
+    chunk_store(c0 & 1);
+    if (c0 + 1 < c1) chunk_load(c0 + 1);
+    __syncthreads();
 
     for (int n1 = fp.n1a; n1 < fp.n1b; ++n1) {
         zload(min(n1 + 1, fp.n1b - 1), zn);   // the next phase's operands
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
             const int c = n1 * CJ + j;
-            const int cnext = min(c + 1, c1 - 1);
-            f32x16 G = 0.f;
+            if (active) {
+                const f32x4 *eb = ebuf + j * NE * 64 + lane;
+                f32x16 G = 0.f;
 #pragma unroll
-            for (int i = 0; i < NLP; ++i) {
-                const f32x4 v = ring[i % kRing];
-                const int nx = i + kRing;
-                if (nx < NLP) {
-                    if (nx < NL) ring[i % kRing] = load(c, nx);
-                } else if (nx - NLP < NL) {
-                    ring[i % kRing] = load(cnext, nx - NLP);
-                }
-                if (i >= NL) continue;
-                if (i < NE) {
+                for (int i = 0; i < NE; ++i) {
+                    const f32x4 v = eb[i * 64];
                     G = MFMA32(v[0], zb[i][0], G);
                     G = MFMA32(v[1], zb[i][1], G);
                     G = MFMA32(v[2], zb[i][2], G);
                     G = MFMA32(v[3], zb[i][3], G);
-                } else {
-                    const int jj = i - NE, s4 = jj / PT, pt = jj % PT;
+                }
+                const f32x4 *kb = lk + (c & 1) * CW + lane;
+#pragma unroll
+                for (int jj = 0; jj < NK; ++jj) {
+                    const int s4 = jj / PT, pt = jj % PT;
+                    const f32x4 v = kb[(pt * 4 + s4) * 64];
                     racc[pt] = MFMA32(G[4 * s4 + 0], v[0], racc[pt]);
                     racc[pt] = MFMA32(G[4 * s4 + 1], v[1], racc[pt]);
                     racc[pt] = MFMA32(G[4 * s4 + 2], v[2], racc[pt]);
                     racc[pt] = MFMA32(G[4 * s4 + 3], v[3], racc[pt]);
                 }
-                __builtin_amdgcn_sched_barrier(0);   // the ring's loads stay in flight
             }
+            // chunk c + 1 goes to the buffer chunk c - 1 left (read by every
+            // wave before the last barrier); chunk c + 2 is requested
+            if (c + 1 < c1) {
+                chunk_store((c + 1) & 1);
+                if (c + 2 < c1) chunk_load(c + 2);
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < ZST / 4; ++i) zb[i] = zn[i];
     }
+    if (!active) return;
     float *out = job.part + (size_t)fp.split * job.part_stride;
 #pragma unroll
     for (int pt = 0; pt < PT; ++pt) {
@@ -537,11 +552,17 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
     if (!fac_args_ok(a) || part < 0 || part > 3) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     switch (part) {
-    case kFacFwdInner:
-        hipLaunchKernelGGL(kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1],
-                           dim3((a.tiles + kFacWavesFwd - 1) / kFacWavesFwd * a.nsplit), dim3(64 * kFacWavesFwd), 0,
-                           st, a);
+    case kFacFwdInner: {
+        const size_t lds = 16 * 64 * (size_t)(2 * a.nup / 8 + a.cj * 4 * a.rct);
+        const FacKernel k = kFacFwd[fac_nup_slot(a.nup)][a.rct - 1][a.cj - 1];
+        if (lds > 64 * 1024) {
+            e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k, dim3((a.tiles + kFacWavesFwd - 1) / kFacWavesFwd * a.nsplit), dim3(64 * kFacWavesFwd),
+                           lds, st, a);
         break;
+    }
     case kFacFwdOuter: {
         if (a.usplit < 1 || a.usplit > kMaxFacSplit || a.U > kOutWaves * kUnitsPerWave * a.usplit)
             return hipErrorInvalidValue;
@@ -564,11 +585,17 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
         hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles, a.zsplit), dim3(64 * kInWaves), lds, st, a);
         break;
     }
-    default:
-        hipLaunchKernelGGL(kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1],
-                           dim3((a.tiles + kFacWavesAdj - 1) / kFacWavesAdj * a.nsplit_adj), dim3(64 * kFacWavesAdj),
-                           0, st, a);
+    default: {
+        const size_t lds = 16 * 64 * (size_t)(2 * a.nup / 8 + a.cj * a.zst / 4);
+        const FacKernel k = kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1];
+        if (lds > 64 * 1024) {
+            e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k, dim3((a.tiles + kFacWavesAdj - 1) / kFacWavesAdj * a.nsplit_adj), dim3(64 * kFacWavesAdj),
+                           lds, st, a);
         break;
+    }
     }
     return hipGetLastError();
 }
