@@ -125,10 +125,10 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
     chunk_load(c0);
     chunk_store(c0 & 1);
     if (c0 + 1 < c1) chunk_load(c0 + 1);
-    __syncthreads();
     f32x16 acc[RCT];
 #pragma unroll
     for (int g = 0; g < RCT; ++g) acc[g] = 0.f;
+    __syncthreads();
 
     for (int n1 = fp.n1a; n1 < fp.n1b; ++n1) {
 #pragma unroll
@@ -220,7 +220,8 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 #pragma unroll
     for (int i = 0; i < kUnitsPerWave; ++i) {
         uu[i] = us + nus * (wave + kOutWaves * i);
-        const int col = 2 * (uu[i] < a.U ? a.uq[uu[i]] : 0) + h;
+        const int q = a.uq[uu[i] < a.U ? uu[i] : 0];   // unconditional: the five loads overlap
+        const int col = 2 * (uu[i] < a.U ? q : 0) + h;
         aoff[i] = (lane & 31) * pitch + ((col % 4) * c4n + col / 4) * kOutStage;
     }
     // this block's stages [s0, s1): range ps of psplit
@@ -307,8 +308,11 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 // out row-contiguous.  Wave w takes residues w + kInWaves i (the plan numbers
 // the residues so the waves' bin counts balance); its data operands (the bins
 // of those residues, up to kQMax steps each) stay in registers, and each
-// stage's table operands are requested during the stage before.
+// stage's table operands are requested during the stage before and waited
+// for before that stage's stores are issued: the vector memory counter
+// retires in order, so a later wait would also wait for the stores.
 constexpr int kZStage = 16;
+constexpr int kWaitVmcnt0 = 0x0f70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited for
 constexpr int kInWaves = kFacInWaves;
 constexpr int kResPerWave = 3;
 
@@ -329,16 +333,23 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
         qq[i] = wave + kInWaves * i;
         qs[i] = qq[i] < a.R ? a.qsteps[qq[i]] : 0;
     }
-    // A operands: y[r][2 qbin[q][st] + h]
+    // A operands: y[r][2 qbin[q][st] + h].  Per residue the bin numbers are
+    // requested together, then the data (clamped addresses, masked values), so
+    // the loads overlap instead of each data load waiting for its bin number.
     float Yv[kResPerWave][kQMax];
     {
         const float *yin = (const float *)job.in + (size_t)(il >= 0 ? il : 0) * job.in_stride + h;
 #pragma unroll
         for (int i = 0; i < kResPerWave; ++i) {
+            const int *qb = a.qbin + (qq[i] < a.R ? qq[i] : 0) * kQMax;
+            int jb[kQMax];
+#pragma unroll
+            for (int st = 0; st < kQMax; ++st) jb[st] = qb[st];
 #pragma unroll
             for (int st = 0; st < kQMax; ++st) {
-                const int jb = qq[i] < a.R ? a.qbin[qq[i] * kQMax + st] : -1;
-                Yv[i][st] = (il >= 0 && jb >= 0) ? yin[2 * jb] : 0.f;
+                const bool ok = qq[i] < a.R && il >= 0 && jb[st] >= 0;
+                const float v = yin[2 * (jb[st] >= 0 ? jb[st] : 0)];
+                Yv[i][st] = ok ? v : 0.f;
             }
         }
     }
@@ -360,6 +371,7 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
     };
     f32x4 b[kResPerWave][kQMax / 4], bn[kResPerWave][kQMax / 4];
     table_load(s0, b);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // (so no stage waits for an earlier stage's stores)
     for (int stg = s0; stg < s1; ++stg) {
         table_load(min(stg + 1, s1 - 1), bn);   // the next stage's, during this one
         __syncthreads();   // the previous stage is written out (and the zeros are in)
@@ -382,6 +394,7 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
                 zs[li * lp + n1l * zp + cr * a.zst + qq[i]] = acc[j];
             }
         }
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the next stage's tables are in
         __syncthreads();
         // the stage's rows (line, phase) are zc contiguous floats in Z
         const int n1s = stg * kZStage;
