@@ -179,38 +179,83 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 
 // Forward outer sum, one block of kOutWaves waves per 32-line tile, unit
 // split and stage range (partial sums ps).  Y of the tile is staged kOutStage
-// phases at a time in LDS (two buffers) as [line][slot][phase] (line pitch
-// yc kOutStage + 4 floats), column col in slot (col % 4) yc/4 + col / 4, so a
-// lane's A operands for a stage are two 16-byte reads.  Thread t < 32 yc/4 stages line t / (yc/4), columns
-// 4 (t % (yc/4)) .. + 3: its 8 phase loads are 16-byte row pieces (a wave's
-// are contiguous) and each column's 8 phases two 16-byte LDS stores,
-// neighbouring threads 32 bytes apart.  Stage s + 1's values are requested
-// before stage s's MFMAs and stored to the other buffer after them; its
-// tables are requested before them too.  Wave w takes units
-// us + usplit (w + kOutWaves i).
+// phases at a time in LDS in its memory order, [line][phase][column] (line
+// pitch yc kOutStage + 4 floats): a line's stage is one contiguous run of
+// memory, moved straight to LDS by global_load_lds (16 bytes a lane, no
+// registers), and a lane's A operands for a stage are 8 single reads (one per
+// phase).  With three buffers (two where three do not fit) stages s + 1 and
+// s + 2 are in flight while stage s's products run.  A 16-byte piece of a
+// phase past P reads the same columns of phase P - 1, whose table entries are
+// zero.  Block barriers here carry no memory fence: a fence would wait for
+// every stage in flight; each wave instead waits for its own loads of the
+// next stage (vmcnt) and its LDS reads (lgkmcnt) before the barrier.  Wave w
+// stages lines 4w .. 4w + 3 and takes units us + usplit (w + kOutWaves i).
 constexpr int kOutStage = 8;
 constexpr int kOutWaves = 8;
 constexpr int kUnitsPerWave = 5;
 
+constexpr int fac_out_pitch(int zst) { return 2 * zst * kOutStage + 4; }
+constexpr int fac_out_bufs(int zst) { return 3 * 32 * fac_out_pitch(zst) * 4 <= 160 * 1024 ? 3 : 2; }
+
+// s_waitcnt vmcnt(n) lgkmcnt(0) (expcnt not waited for), n < 64
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+
+__device__ __forceinline__ void block_barrier_nofence() { asm volatile("s_barrier" ::: "memory"); }
+
+// 16 bytes a lane from src to LDS at dst + 16 lane (dst wave-uniform).  A
+// function of its own: written inside the kernel template, this gfx950-only
+// form made the host pass drop the kernel's launch stubs without a message.
+__device__ __forceinline__ void dma16(const float *src, float *dst) { __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0); }
+
+// First piece of run r of a line's stage of PIECES 16-byte pieces
+template <int PIECES>
+constexpr int fac_run_start(int r)
+{
+    return PIECES % 64 == 0 || PIECES < 64 || 64 * r + 64 <= PIECES ? 64 * r : PIECES - 64;
+}
+
+template <int ZST>
 __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 {
     extern __shared__ __align__(16) float ys[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
+    constexpr int yc = 2 * ZST, pitch = fac_out_pitch(ZST), NBUF = fac_out_bufs(ZST);
+    constexpr int PIECES = yc * kOutStage / 4;              // 16-byte pieces of a line's stage
+    constexpr int RUNS = (PIECES + 63) / 64;                // instructions per line and stage
+    constexpr int LPW = 32 / kOutWaves;                     // lines a wave stages
+    constexpr int bufsz = 32 * pitch;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
     const int tile = blockIdx.x, us = blockIdx.y, nus = gridDim.y, ps = blockIdx.z;
     const SigJob &job = a.job;
     const int row0 = tile * 32;
-    const int pitch = a.yc * kOutStage + 4;
-    const int c4n = a.yc / 4;
-    const bool stager = tid < 32 * c4n;
-    const int sli = stager ? tid / c4n : 0, sc4 = stager ? tid % c4n : 0;
-    const int goff = ((row0 + sli) * a.P) * a.yc + 4 * sc4;     // phase 0 of this thread's run
-    float *lbase = ys + sli * pitch + sc4 * kOutStage;          // column 4 sc4 + e at + e c4n kOutStage
-    auto stage_load = [&](int n1s, f32x4 (&v)[kOutStage]) {
+    // Run r moves 64 pieces from fac_run_start(r); where a line's stage is at
+    // least 64 pieces the last run ends at its last piece (overlapping the run
+    // before with the same values), so every run is a whole, unconditional
+    // instruction.
+    // this lane's piece of run r: phase pph[r], first column pcol[r]
+    int pph[RUNS], pcol[RUNS];
 #pragma unroll
-        for (int k = 0; k < kOutStage; ++k) {
-            const bool ok = stager && n1s + k < a.P;   // a phase past P reads as zero
-            const f32x4 t = *reinterpret_cast<const f32x4 *>(a.y + (ok ? goff + (n1s + k) * a.yc : 0));
-            v[k] = ok ? t : f32x4{};
+    for (int r = 0; r < RUNS; ++r) {
+        const int f = 4 * (fac_run_start<PIECES>(r) + lane);
+        pph[r] = f / yc;
+        pcol[r] = f % yc;
+    }
+    const float *yl = a.y + (size_t)(row0 + LPW * wave) * a.P * yc;   // the wave's first line
+    auto stage_dma = [&](int stg, int buf) {
+        float *dst = ys + buf * bufsz + LPW * wave * pitch;
+#pragma unroll
+        for (int r = 0; r < RUNS; ++r) {
+            const int n1 = min(stg * kOutStage + pph[r], a.P - 1);
+            const float *src = yl + n1 * yc + pcol[r];
+#pragma unroll
+            for (int l = 0; l < LPW; ++l) {
+                if (PIECES >= 64 || lane < PIECES)
+                    dma16(src + (size_t)l * a.P * yc, dst + l * pitch + 4 * fac_run_start<PIECES>(r));
+            }
         }
     };
     f32x16 acc[kUnitsPerWave];
@@ -222,7 +267,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
         uu[i] = us + nus * (wave + kOutWaves * i);
         const int q = a.uq[uu[i] < a.U ? uu[i] : 0];   // unconditional: the five loads overlap
         const int col = 2 * (uu[i] < a.U ? q : 0) + h;
-        aoff[i] = (lane & 31) * pitch + ((col % 4) * c4n + col / 4) * kOutStage;
+        aoff[i] = (lane & 31) * pitch + col;
     }
     // this block's stages [s0, s1): range ps of psplit
     const int nst = (a.P + kOutStage - 1) / kOutStage;
@@ -237,54 +282,52 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
             b1[i] = w[64];
         }
     };
-    // two LDS stage buffers: stage s + 1 is written to the other one while
-    // stage s's products read this one, one barrier a stage
-    const int bufsz = 32 * pitch;
-    auto stage_store = [&](int buf, const f32x4 (&v)[kOutStage]) {
-        if (!stager) return;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            float *d = lbase + buf * bufsz + e * c4n * kOutStage;
-            *reinterpret_cast<f32x4 *>(d) = f32x4{v[0][e], v[1][e], v[2][e], v[3][e]};
-            *reinterpret_cast<f32x4 *>(d + 4) = f32x4{v[4][e], v[5][e], v[6][e], v[7][e]};
-        }
-    };
-    f32x4 pf[kOutStage], b0[kUnitsPerWave], b1[kUnitsPerWave], n0[kUnitsPerWave], n1v[kUnitsPerWave];
+    f32x4 b0[kUnitsPerWave], b1[kUnitsPerWave], n0[kUnitsPerWave], n1v[kUnitsPerWave];
     table_load(s0 * kOutStage, b0, b1);
-    stage_load(s0 * kOutStage, pf);
-    stage_store(s0 & 1, pf);
-    if (s0 + 1 < s1) stage_load((s0 + 1) * kOutStage, pf);
+    __builtin_amdgcn_sched_barrier(0);   // ahead of the stage loads: in by the first wait
+    // stages s0 .. s0 + NBUF - 2 requested (stage numbers past the range
+    // repeat its last stage, so every wait below counts the same loads)
+#pragma unroll
+    for (int k = 0; k < NBUF - 1; ++k) stage_dma(min(s0 + k, s1 - 1), (s0 + k) % NBUF);
+    wait_vm_lgkm<(NBUF - 2) * LPW * RUNS>();   // stage s0 is in
+    block_barrier_nofence();
     for (int stg = s0; stg < s1; ++stg) {
         const int n1s = stg * kOutStage;
-        __syncthreads();   // stage stg is in its buffer; the other buffer's stage is consumed
-        // the next stage's tables load during this stage's products (its staged
-        // values are in flight already)
         table_load(min(n1s + kOutStage, (s1 - 1) * kOutStage), n0, n1v);
+        __builtin_amdgcn_sched_barrier(0);
+        // stage stg + NBUF - 1 to the buffer stage stg - 1 left (every wave is
+        // past its products: the barrier at the end of the last stage)
+        stage_dma(min(stg + NBUF - 1, s1 - 1), (stg + NBUF - 1) % NBUF);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < kUnitsPerWave; ++i) {
             if (uu[i] >= a.U) break;
-            const float *src = ys + (stg & 1) * bufsz + aoff[i];
-            const f32x4 a0 = *reinterpret_cast<const f32x4 *>(src);
-            const f32x4 a1 = *reinterpret_cast<const f32x4 *>(src + 4);
-            acc[i] = MFMA32(a0[0], b0[i][0], acc[i]);
-            acc[i] = MFMA32(a0[1], b0[i][1], acc[i]);
-            acc[i] = MFMA32(a0[2], b0[i][2], acc[i]);
-            acc[i] = MFMA32(a0[3], b0[i][3], acc[i]);
-            acc[i] = MFMA32(a1[0], b1[i][0], acc[i]);
-            acc[i] = MFMA32(a1[1], b1[i][1], acc[i]);
-            acc[i] = MFMA32(a1[2], b1[i][2], acc[i]);
-            acc[i] = MFMA32(a1[3], b1[i][3], acc[i]);
+            const float *src = ys + (stg % NBUF) * bufsz + aoff[i];
+            float av[kOutStage];
+#pragma unroll
+            for (int k = 0; k < kOutStage; ++k) av[k] = src[k * yc];
+            acc[i] = MFMA32(av[0], b0[i][0], acc[i]);
+            acc[i] = MFMA32(av[1], b0[i][1], acc[i]);
+            acc[i] = MFMA32(av[2], b0[i][2], acc[i]);
+            acc[i] = MFMA32(av[3], b0[i][3], acc[i]);
+            acc[i] = MFMA32(av[4], b1[i][0], acc[i]);
+            acc[i] = MFMA32(av[5], b1[i][1], acc[i]);
+            acc[i] = MFMA32(av[6], b1[i][2], acc[i]);
+            acc[i] = MFMA32(av[7], b1[i][3], acc[i]);
         }
 #pragma unroll
         for (int i = 0; i < kUnitsPerWave; ++i) {
             b0[i] = n0[i];
             b1[i] = n1v[i];
         }
-        if (stg + 1 < s1) {
-            stage_store((stg + 1) & 1, pf);
-            if (stg + 2 < s1) stage_load(n1s + 2 * kOutStage, pf);
-        }
+        // stage stg + 1 is in (only the NBUF - 2 later stages' loads may be
+        // outstanding), and this wave's LDS reads are done
+        wait_vm_lgkm<(NBUF - 2) * LPW * RUNS>();
+        block_barrier_nofence();
     }
+    // the repeated last-stage loads still in flight land before the block
+    // ends and its LDS is handed to another block
+    wait_vm_lgkm<0>();
     // column l%32 of unit u: bin slot col/2, re/im col%2
 #pragma unroll
     for (int i = 0; i < kUnitsPerWave; ++i) {
@@ -520,6 +563,14 @@ __global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
 }
 
 typedef void (*FacKernel)(FacArgs);
+struct FacOut {
+    FacKernel fn;
+    int nbuf;
+};
+#define FAC_OUT(Z) {fac_fwd_out_kernel<Z>, fac_out_bufs(Z)}
+const FacOut kFacFwdOut[8] = {FAC_OUT(4),  FAC_OUT(8),  FAC_OUT(12), FAC_OUT(16),
+                              FAC_OUT(20), FAC_OUT(24), FAC_OUT(28), FAC_OUT(32)};
+#undef FAC_OUT
 constexpr int kFacNups[] = {64, 128, 192, 256};
 #define FAC_FWD_ROW(NUP)                                                                                     \
     {{fac_fwd_kernel<NUP, 1, 1>, fac_fwd_kernel<NUP, 1, 2>}, {fac_fwd_kernel<NUP, 2, 1>, fac_fwd_kernel<NUP, 2, 2>}}
@@ -579,13 +630,13 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
     case kFacFwdOuter: {
         if (a.usplit < 1 || a.usplit > kMaxFacSplit || a.U > kOutWaves * kUnitsPerWave * a.usplit)
             return hipErrorInvalidValue;
-        const size_t lds = 2 * sizeof(float) * 32 * (size_t)(a.yc * kOutStage + 4);
+        const FacOut &k = kFacFwdOut[a.zst / 4 - 1];
+        const size_t lds = sizeof(float) * 32 * (size_t)k.nbuf * fac_out_pitch(a.zst);
         if (lds > 64 * 1024) {
-            e = hipFuncSetAttribute((const void *)fac_fwd_out_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds);
+            e = hipFuncSetAttribute((const void *)k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(fac_fwd_out_kernel, dim3(a.tiles, a.usplit, a.psplit), dim3(64 * kOutWaves), lds, st, a);
+        hipLaunchKernelGGL(k.fn, dim3(a.tiles, a.usplit, a.psplit), dim3(64 * kOutWaves), lds, st, a);
         break;
     }
     case kFacAdjOuter: {
