@@ -6,7 +6,10 @@ when it needs less MFMA work than the dense band DFT.  These geometries are
 chosen to take it and to cover its edges: a ragged last line tile, a phase
 count P that is not a multiple of the kernels' 8- and 16-phase stages, one and
 two 32-column residue tiles, C = 32 and C = 64 (one and two 32-cycle chunks
-per phase), n_u padded to 64 and 128, and a receive filter.  Each forward and
+per phase), n_u padded to 64 and 128, a receive filter, and the three ways the
+forward outer sum moves a line's 8-phase stage of Y into LDS (under 64
+16-byte pieces: one partial instruction, R = 12; exactly 64, R = 14; over 64:
+a last run overlapping the one before, R = 22).  Each forward and
 adjoint is compared with the FP64 oracle (which evaluates the dense
 definition) at the FP32 tolerance of the other operator tests; the full-size
 factored scans are covered by the realistic and high-resolution tests.
