@@ -21,7 +21,7 @@
 // cycles of a phase are in (Y and Z rows are the job's rows);
 // fac_fwd_out_kernel then forms b per line tile through LDS-staged Y, one
 // 32-column MFMA tile per unit of at most 16 bins of one residue.  Adjoint:
-// fac_adj_in_kernel forms Z[row][n1][re/im][q] from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
+// fac_adj_in_kernel forms Z (per line tile [n1][re/im][q][line]) from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
 // contraction's transpose, accumulating the lines over its phases (split
 // partial sums added in a fixed order afterwards).
 //
@@ -345,15 +345,19 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
     }
 }
 
-// Adjoint outer sum: Z[row][n1][re/im][q] from the data, one block of
-// kInWaves waves per 32-line tile and stage range; stages of 16 phases (a
-// 32-column MFMA tile: phase col/2, re/im col%2) collected in LDS and written
-// out row-contiguous.  Wave w takes residues w + kInWaves i (the plan numbers
-// the residues so the waves' bin counts balance); its data operands (the bins
-// of those residues, up to kQMax steps each) stay in registers, and each
-// stage's table operands are requested during the stage before and waited
-// for before that stage's stores are issued: the vector memory counter
-// retires in order, so a later wait would also wait for the stores.
+// Adjoint outer sum: Z from the data, one block of kInWaves waves per 32-line
+// tile and stage range; stages of 16 phases (a 32-column MFMA tile: phase
+// col/2, re/im col%2).  Z is laid out per line tile as [phase][re/im][q][32
+// lines], the MFMA result's own order: a lane's 16 results for residue q are
+// four runs of four consecutive lines, written as 16-byte stores straight from
+// the accumulator (no LDS, no barriers).  Wave w takes residue slots
+// w + kInWaves i (the plan numbers the residues so the waves' bin counts
+// balance); slots in [R, zst) are written as zeros, and slots past zst and
+// phases past P go to the spare row, so every stage issues the same stores and
+// its products wait for its own table loads, never for earlier stores.  The
+// data operands (the bins of the wave's residues, up to kQMax steps each) stay
+// in registers, and each stage's table operands are requested during the
+// stage before.
 constexpr int kZStage = 16;
 constexpr int kWaitVmcnt0 = 0x0f70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited for
 constexpr int kInWaves = kFacInWaves;
@@ -361,15 +365,13 @@ constexpr int kResPerWave = 3;
 
 __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
 {
-    extern __shared__ __align__(16) float zs[];   // [32 lines (pitch lp)][kZStage phases][zc + 4]
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
     const int tile = blockIdx.x, zsp = blockIdx.y;
     const SigJob &job = a.job;
     const int row0 = tile * 32;
     const int r = row0 + (lane & 31);
     const long il = r < job.rows ? job_line(job, r) : -1;
-    // Z columns; LDS row and line pitches (padded against bank conflicts)
-    const int zc = 2 * a.zst, zp = zc + 4, lp = kZStage * zp + 8;
+    const int zst = a.zst;
     int qq[kResPerWave], qs[kResPerWave];
 #pragma unroll
     for (int i = 0; i < kResPerWave; ++i) {
@@ -396,12 +398,9 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
             }
         }
     }
-    // the padding columns q >= R are never written: zero the stage once
-    for (int f = tid; f < 32 * lp; f += 64 * kInWaves) zs[f] = 0.f;
     // this block's stages [s0, s1): range zsp of zsplit
     const int nst = (a.P + kZStage - 1) / kZStage;
     const int s0 = (int)((long)zsp * nst / a.zsplit), s1 = (int)((long)(zsp + 1) * nst / a.zsplit);
-    const int c4n = zc / 4;
     // table operands of stage stg for this wave's residues
     auto table_load = [&](int stg, f32x4 (&b)[kResPerWave][kQMax / 4]) {
 #pragma unroll
@@ -412,42 +411,37 @@ __global__ __launch_bounds__(64 * kInWaves) void fac_adj_in_kernel(FacArgs a)
             for (int s4 = 0; s4 < kQMax / 4; ++s4) b[i][s4] = w[s4 * 64];
         }
     };
+    // this tile's Z, and the spare row (phase 0) for the stores that carry nothing
+    float *const zt = a.y + (size_t)tile * 32 * a.P * 2 * zst + 4 * h;
+    float *const spare = a.y + (size_t)a.ylines * a.P * 2 * zst + 4 * h;
+    const int col = lane & 31, n1l = col >> 1, cr = col & 1;
     f32x4 b[kResPerWave][kQMax / 4], bn[kResPerWave][kQMax / 4];
     table_load(s0, b);
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // (so no stage waits for an earlier stage's stores)
     for (int stg = s0; stg < s1; ++stg) {
         table_load(min(stg + 1, s1 - 1), bn);   // the next stage's, during this one
-        __syncthreads();   // the previous stage is written out (and the zeros are in)
+        const int n1 = stg * kZStage + n1l;
 #pragma unroll
         for (int i = 0; i < kResPerWave; ++i) {
-            if (qq[i] >= a.R) break;
             f32x16 acc = 0.f;
+            if (qq[i] < a.R) {
 #pragma unroll
-            for (int s4 = 0; s4 < kQMax / 4; ++s4) {
-                if (4 * s4 >= qs[i]) break;
-                acc = MFMA32(Yv[i][4 * s4 + 0], b[i][s4][0], acc);
-                acc = MFMA32(Yv[i][4 * s4 + 1], b[i][s4][1], acc);
-                acc = MFMA32(Yv[i][4 * s4 + 2], b[i][s4][2], acc);
-                acc = MFMA32(Yv[i][4 * s4 + 3], b[i][s4][3], acc);
+                for (int s4 = 0; s4 < kQMax / 4; ++s4) {
+                    if (4 * s4 >= qs[i]) break;
+                    acc = MFMA32(Yv[i][4 * s4 + 0], b[i][s4][0], acc);
+                    acc = MFMA32(Yv[i][4 * s4 + 1], b[i][s4][1], acc);
+                    acc = MFMA32(Yv[i][4 * s4 + 2], b[i][s4][2], acc);
+                    acc = MFMA32(Yv[i][4 * s4 + 3], b[i][s4][3], acc);
+                }
             }
-            const int col = lane & 31, n1l = col / 2, cr = col & 1;
+            // lines 8 J + 4 h .. + 3 of column (n1, re/im cr), residue slot qq[i];
+            // the stores that carry nothing all go to the spare row's first 8 floats
+            const bool real = n1 < a.P && qq[i] < zst;
+            float *d = real ? zt + ((size_t)(n1 * 2 + cr) * zst + qq[i]) * 32 : spare;
+            const int js = real ? 8 : 0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int li = 8 * (j / 4) + 4 * h + (j % 4);
-                zs[li * lp + n1l * zp + cr * a.zst + qq[i]] = acc[j];
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the next stage's tables are in
-        __syncthreads();
-        // the stage's rows (line, phase) are zc contiguous floats in Z
-        const int n1s = stg * kZStage;
-        for (int f = tid; f < 32 * kZStage * c4n; f += 64 * kInWaves) {
-            const int c4 = f % c4n, rest = f / c4n, n1l = rest % kZStage, li = rest / kZStage;
-            const int row = row0 + li, n1 = n1s + n1l;
-            if (n1 < a.P) {
-                const f32x4 v = *reinterpret_cast<const f32x4 *>(zs + li * lp + n1l * zp + 4 * c4);
-                *reinterpret_cast<f32x4 *>(a.y + ((size_t)row * a.P + n1) * zc + 4 * c4) = v;
-            }
+            for (int J = 0; J < 4; ++J)
+                *reinterpret_cast<f32x4 *>(d + js * J) = f32x4{acc[4 * J], acc[4 * J + 1], acc[4 * J + 2], acc[4 * J + 3]};
         }
 #pragma unroll
         for (int i = 0; i < kResPerWave; ++i)
@@ -487,12 +481,14 @@ __global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
     const f32x4 *ka = (const f32x4 *)job.ka;
     const f32x4 *ea = (const f32x4 *)a.ea;
     for (int idx = tid; idx < CJ * NE * 64; idx += 64 * kFacWavesAdj) ebuf[idx] = ea[idx];
-    // B operand of the residue DFT's transpose: Z[r][n1][h][st], st < ZST (Z rows
-    // are the job's rows; those past the job hold zeros)
-    const float *zrow = a.y + (size_t)(active ? r : 0) * a.P * ZC + h * ZST;
-    auto zload = [&](int n1, f32x4 (&zb)[ZST / 4]) {
+    // B operand of the residue DFT's transpose: Z of this line tile, laid out
+    // [phase][re/im][q][32 lines]: line r, half h, columns st < ZST (lines past
+    // the job hold zeros).  A lane's ZST values of a phase are single floats
+    // 128 bytes apart; the wave's loads of one st are two 128-byte runs.
+    const float *zrow = a.y + (size_t)(active ? fp.tile : 0) * 32 * a.P * ZC + h * ZST * 32 + (lane & 31);
+    auto zload = [&](int n1, float (&zb)[ZST]) {
 #pragma unroll
-        for (int i = 0; i < ZST / 4; ++i) zb[i] = *reinterpret_cast<const f32x4 *>(zrow + (size_t)n1 * ZC + 4 * i);
+        for (int st = 0; st < ZST; ++st) zb[st] = zrow[(size_t)n1 * ZC * 32 + st * 32];
     };
     const int c0 = fp.n1a * CJ, c1 = fp.n1b * CJ;
     f32x4 pk[KPT];
@@ -504,7 +500,7 @@ __global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
 #pragma unroll
         for (int k = 0; k < KPT; ++k) lk[buf * CW + tid + 64 * kFacWavesAdj * k] = pk[k];
     };
-    f32x4 zb[ZST / 4], zn[ZST / 4];
+    float zb[ZST], zn[ZST];
     zload(fp.n1a, zb);
     chunk_load(c0);
     chunk_store(c0 & 1);
@@ -522,10 +518,10 @@ __global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
 #pragma unroll
                 for (int i = 0; i < NE; ++i) {
                     const f32x4 v = eb[i * 64];
-                    G = MFMA32(v[0], zb[i][0], G);
-                    G = MFMA32(v[1], zb[i][1], G);
-                    G = MFMA32(v[2], zb[i][2], G);
-                    G = MFMA32(v[3], zb[i][3], G);
+                    G = MFMA32(v[0], zb[4 * i + 0], G);
+                    G = MFMA32(v[1], zb[4 * i + 1], G);
+                    G = MFMA32(v[2], zb[4 * i + 2], G);
+                    G = MFMA32(v[3], zb[4 * i + 3], G);
                 }
                 const f32x4 *kb = lk + (c & 1) * CW + lane;
 #pragma unroll
@@ -547,7 +543,7 @@ __global__ __launch_bounds__(64 * kFacWavesAdj) void fac_adj_kernel(FacArgs a)
             __syncthreads();
         }
 #pragma unroll
-        for (int i = 0; i < ZST / 4; ++i) zb[i] = zn[i];
+        for (int st = 0; st < ZST; ++st) zb[st] = zn[st];
     }
     if (!active) return;
     float *out = job.part + (size_t)fp.split * job.part_stride;
@@ -639,16 +635,9 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
         hipLaunchKernelGGL(k.fn, dim3(a.tiles, a.usplit, a.psplit), dim3(64 * kOutWaves), lds, st, a);
         break;
     }
-    case kFacAdjOuter: {
-        const size_t lds = sizeof(float) * 32 * ((size_t)kZStage * (2 * a.zst + 4) + 8);
-        if (lds > 64 * 1024) {
-            e = hipFuncSetAttribute((const void *)fac_adj_in_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds);
-            if (e != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles, a.zsplit), dim3(64 * kInWaves), lds, st, a);
+    case kFacAdjOuter:
+        hipLaunchKernelGGL(fac_adj_in_kernel, dim3(a.tiles, a.zsplit), dim3(64 * kInWaves), 0, st, a);
         break;
-    }
     default: {
         const size_t lds = 16 * 64 * (size_t)(2 * a.nup / 8 + a.cj * a.zst / 4);
         const FacKernel k = kFacAdj[fac_nup_slot(a.nup)][a.zst / 4 - 1][a.cj - 1];
