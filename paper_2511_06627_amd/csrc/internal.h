@@ -92,9 +92,9 @@ struct FacArgs {
     const int *ubin;         // [U][16] bins of unit u (-1: none)
     const int *qbin;         // [R][kQMax] bins of residue q (-1: none)
     const int *qsteps;       // [R] bins of residue q rounded up to 4
-    float *y;                // phase sums: Y by job row, [ylines + 1][P][yc]; Z per 32-line tile,
-                             // [P][re/im][zst][32 lines] (ylines = 32 tiles); then a spare row taking
-                             // the stores that carry nothing
+    float *y;                // phase sums Y or Z per 32-line tile, [P][yc][32 lines] (for Z the
+                             // columns are [re/im][zst]); ylines = 32 tiles; then a spare row of
+                             // P yc floats taking the stores that carry nothing
     int ylines;
     int nu, nup, nbp2;
     int P, Pp, cj;           // phases, phases rounded up to 8, 32-cycle blocks per phase (C / 32)

@@ -19,7 +19,8 @@
 // rows in that order) and feeds each 32 x 32 (time x line) result straight
 // into the residue DFT (table E), writing Y[row][n1][2q + re/im] once the C
 // cycles of a phase are in (Y and Z rows are the job's rows);
-// fac_fwd_out_kernel then forms b per line tile through LDS-staged Y, one
+// fac_fwd_out_kernel then forms b per line tile through LDS-staged Y (Y and Z
+// per line tile as [phase][column][line]), one
 // 32-column MFMA tile per unit of at most 16 bins of one residue.  Adjoint:
 // fac_adj_in_kernel forms Z (per line tile [n1][re/im][q][line]) from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
 // contraction's transpose, accumulating the lines over its phases (split
@@ -68,9 +69,10 @@ __device__ __forceinline__ FacPos fac_pos(const FacArgs &a, int nsplit)
 // buffers: chunk c + 1 is stored while chunk c is used, chunk c + 2 already
 // requested into registers; one barrier a chunk), and the residue DFT table
 // sits in LDS for the whole launch.  A wave past the last tile still stages.
-// Each phase's Y stores are unconditional -- Y rows are the job's rows (rows
-// past the job hold the results of zero lines) and columns past yc go to the
-// spare row a.ylines.
+// Y is laid out per line tile as [phase][column][32 lines] (lines past the
+// job hold the results of zero lines): a lane's 16 results of a column are
+// four 16-byte runs of lines.  Each phase's stores are unconditional; columns
+// past yc go to the spare row's first 8 floats.
 template <int NUP, int RCT, int CJ>
 __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 {
@@ -98,15 +100,16 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 #pragma unroll
         for (int st = 0; st < NUP / 2; ++st) R[st] = (il >= 0 && 2 * st + h < a.nu) ? rin[2 * st] : 0.f;
     }
-    const int ystride = a.P * a.yc;
-    const int ybase = (row0 + 4 * h) * ystride;
-    int ycol[RCT];
-    bool yok[RCT];
+    // this lane's column of residue tile g in the wave's Y tile, or the spare row
+    float *ycol[RCT];
+    int ystep[RCT], jstep[RCT];
 #pragma unroll
     for (int g = 0; g < RCT; ++g) {
         const int col = 32 * g + (lane & 31);
-        yok[g] = col < a.yc;
-        ycol[g] = yok[g] ? ybase + col : a.ylines * ystride + col % a.yc;
+        const bool ok = col < a.yc;
+        ycol[g] = a.y + (ok ? ((size_t)fp.tile * a.P * a.yc + col) * 32 : (size_t)a.ylines * a.P * a.yc) + 4 * h;
+        ystep[g] = ok ? a.yc * 32 : 0;   // per phase
+        jstep[g] = ok ? 8 : 0;           // per run of 4 lines
     }
 
     const f32x4 *kf = (const f32x4 *)job.kf;
@@ -165,12 +168,13 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
             __syncthreads();
         }
         if (active) {
-            const int nof = n1 * a.yc;
 #pragma unroll
             for (int g = 0; g < RCT; ++g) {
+                float *d = ycol[g] + (size_t)n1 * ystep[g];
 #pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    a.y[ycol[g] + (yok[g] ? (8 * (j / 4) + (j % 4)) * ystride + nof : 0)] = acc[g][j];
+                for (int J = 0; J < 4; ++J)
+                    *reinterpret_cast<f32x4 *>(d + J * jstep[g]) =
+                        f32x4{acc[g][4 * J], acc[g][4 * J + 1], acc[g][4 * J + 2], acc[g][4 * J + 3]};
                 acc[g] = 0.f;
             }
         }
@@ -178,24 +182,23 @@ __global__ __launch_bounds__(64 * kFacWavesFwd) void fac_fwd_kernel(FacArgs a)
 }
 
 // Forward outer sum, one block of kOutWaves waves per 32-line tile, unit
-// split and stage range (partial sums ps).  Y of the tile is staged kOutStage
-// phases at a time in LDS in its memory order, [line][phase][column] (line
-// pitch yc kOutStage + 4 floats): a line's stage is one contiguous run of
-// memory, moved straight to LDS by global_load_lds (16 bytes a lane, no
-// registers), and a lane's A operands for a stage are 8 single reads (one per
-// phase).  With three buffers (two where three do not fit) stages s + 1 and
-// s + 2 are in flight while stage s's products run.  A 16-byte piece of a
-// phase past P reads the same columns of phase P - 1, whose table entries are
-// zero.  Block barriers here carry no memory fence: a fence would wait for
-// every stage in flight; each wave instead waits for its own loads of the
-// next stage (vmcnt) and its LDS reads (lgkmcnt) before the barrier.  Wave w
-// stages lines 4w .. 4w + 3 and takes units us + usplit (w + kOutWaves i).
+// split and stage range (partial sums ps).  A stage of kOutStage phases of the
+// tile's Y ([phase][column][32 lines]) is one contiguous block of memory, moved
+// straight to LDS in that order by global_load_lds (16 bytes a lane, no
+// registers; pieces of phases past P read phase P - 1, whose table entries are
+// zero), and a lane's A operands for a stage are 8 single reads (one per
+// phase) that the wave spreads over all 64 banks (32 consecutive lines per
+// half-wave, the halves 32 floats apart).  With three buffers (two where three
+// do not fit) stages s + 1 and s + 2 are in flight while stage s's products
+// run.  Block barriers here carry no memory fence: a fence would wait for
+// every stage in flight; each wave instead waits for its own loads of the next
+// stage (vmcnt) and its LDS reads (lgkmcnt) before the barrier.  Wave w takes
+// units us + usplit (w + kOutWaves i).
 constexpr int kOutStage = 8;
 constexpr int kOutWaves = 8;
 constexpr int kUnitsPerWave = 5;
 
-constexpr int fac_out_pitch(int zst) { return 2 * zst * kOutStage + 4; }
-constexpr int fac_out_bufs(int zst) { return 3 * 32 * fac_out_pitch(zst) * 4 <= 160 * 1024 ? 3 : 2; }
+constexpr int fac_out_bufs(int zst) { return 3 * kOutStage * 2 * zst * 32 * 4 <= 160 * 1024 ? 3 : 2; }
 
 // s_waitcnt vmcnt(n) lgkmcnt(0) (expcnt not waited for), n < 64
 template <int N>
@@ -212,50 +215,32 @@ __device__ __forceinline__ void block_barrier_nofence() { asm volatile("s_barrie
 // form made the host pass drop the kernel's launch stubs without a message.
 __device__ __forceinline__ void dma16(const float *src, float *dst) { __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0); }
 
-// First piece of run r of a line's stage of PIECES 16-byte pieces
-template <int PIECES>
-constexpr int fac_run_start(int r)
-{
-    return PIECES % 64 == 0 || PIECES < 64 || 64 * r + 64 <= PIECES ? 64 * r : PIECES - 64;
-}
-
 template <int ZST>
 __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
 {
     extern __shared__ __align__(16) float ys[];
-    constexpr int yc = 2 * ZST, pitch = fac_out_pitch(ZST), NBUF = fac_out_bufs(ZST);
-    constexpr int PIECES = yc * kOutStage / 4;              // 16-byte pieces of a line's stage
-    constexpr int RUNS = (PIECES + 63) / 64;                // instructions per line and stage
-    constexpr int LPW = 32 / kOutWaves;                     // lines a wave stages
-    constexpr int bufsz = 32 * pitch;
+    constexpr int yc = 2 * ZST, NBUF = fac_out_bufs(ZST);
+    constexpr int bufsz = kOutStage * yc * 32;              // floats of a stage
+    constexpr int RPW = bufsz / (4 * 64 * kOutWaves);       // 64-piece runs a wave moves per stage
+    static_assert(bufsz % (4 * 64 * kOutWaves) == 0, "whole runs");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
     const int tile = blockIdx.x, us = blockIdx.y, nus = gridDim.y, ps = blockIdx.z;
     const SigJob &job = a.job;
     const int row0 = tile * 32;
-    // Run r moves 64 pieces from fac_run_start(r); where a line's stage is at
-    // least 64 pieces the last run ends at its last piece (overlapping the run
-    // before with the same values), so every run is a whole, unconditional
-    // instruction.
-    // this lane's piece of run r: phase pph[r], first column pcol[r]
-    int pph[RUNS], pcol[RUNS];
+    // run k of wave w moves floats 4 (64 (kOutWaves k + w) + lane) .. + 3 of the stage
+    int pph[RPW], poff[RPW];
 #pragma unroll
-    for (int r = 0; r < RUNS; ++r) {
-        const int f = 4 * (fac_run_start<PIECES>(r) + lane);
-        pph[r] = f / yc;
-        pcol[r] = f % yc;
+    for (int k = 0; k < RPW; ++k) {
+        const int f = 4 * (64 * (kOutWaves * k + wave) + lane);
+        pph[k] = f / (yc * 32);
+        poff[k] = f - pph[k] * (yc * 32);
     }
-    const float *yl = a.y + (size_t)(row0 + LPW * wave) * a.P * yc;   // the wave's first line
+    const float *yt = a.y + (size_t)tile * a.P * yc * 32;
     auto stage_dma = [&](int stg, int buf) {
-        float *dst = ys + buf * bufsz + LPW * wave * pitch;
 #pragma unroll
-        for (int r = 0; r < RUNS; ++r) {
-            const int n1 = min(stg * kOutStage + pph[r], a.P - 1);
-            const float *src = yl + n1 * yc + pcol[r];
-#pragma unroll
-            for (int l = 0; l < LPW; ++l) {
-                if (PIECES >= 64 || lane < PIECES)
-                    dma16(src + (size_t)l * a.P * yc, dst + l * pitch + 4 * fac_run_start<PIECES>(r));
-            }
+        for (int k = 0; k < RPW; ++k) {
+            const int n1 = min(stg * kOutStage + pph[k], a.P - 1);
+            dma16(yt + (size_t)n1 * yc * 32 + poff[k], ys + buf * bufsz + 256 * (kOutWaves * k + wave));
         }
     };
     f32x16 acc[kUnitsPerWave];
@@ -267,7 +252,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
         uu[i] = us + nus * (wave + kOutWaves * i);
         const int q = a.uq[uu[i] < a.U ? uu[i] : 0];   // unconditional: the five loads overlap
         const int col = 2 * (uu[i] < a.U ? q : 0) + h;
-        aoff[i] = (lane & 31) * pitch + col;
+        aoff[i] = col * 32 + (lane & 31);
     }
     // this block's stages [s0, s1): range ps of psplit
     const int nst = (a.P + kOutStage - 1) / kOutStage;
@@ -289,7 +274,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
     // repeat its last stage, so every wait below counts the same loads)
 #pragma unroll
     for (int k = 0; k < NBUF - 1; ++k) stage_dma(min(s0 + k, s1 - 1), (s0 + k) % NBUF);
-    wait_vm_lgkm<(NBUF - 2) * LPW * RUNS>();   // stage s0 is in
+    wait_vm_lgkm<(NBUF - 2) * RPW>();   // stage s0 is in
     block_barrier_nofence();
     for (int stg = s0; stg < s1; ++stg) {
         const int n1s = stg * kOutStage;
@@ -305,7 +290,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
             const float *src = ys + (stg % NBUF) * bufsz + aoff[i];
             float av[kOutStage];
 #pragma unroll
-            for (int k = 0; k < kOutStage; ++k) av[k] = src[k * yc];
+            for (int k = 0; k < kOutStage; ++k) av[k] = src[k * yc * 32];
             acc[i] = MFMA32(av[0], b0[i][0], acc[i]);
             acc[i] = MFMA32(av[1], b0[i][1], acc[i]);
             acc[i] = MFMA32(av[2], b0[i][2], acc[i]);
@@ -322,7 +307,7 @@ __global__ __launch_bounds__(64 * kOutWaves) void fac_fwd_out_kernel(FacArgs a)
         }
         // stage stg + 1 is in (only the NBUF - 2 later stages' loads may be
         // outstanding), and this wave's LDS reads are done
-        wait_vm_lgkm<(NBUF - 2) * LPW * RUNS>();
+        wait_vm_lgkm<(NBUF - 2) * RPW>();
         block_barrier_nofence();
     }
     // the repeated last-stage loads still in flight land before the block
@@ -627,7 +612,7 @@ hipError_t launch_fac_part(const FacArgs &a, int part, hipStream_t st)
         if (a.usplit < 1 || a.usplit > kMaxFacSplit || a.U > kOutWaves * kUnitsPerWave * a.usplit)
             return hipErrorInvalidValue;
         const FacOut &k = kFacFwdOut[a.zst / 4 - 1];
-        const size_t lds = sizeof(float) * 32 * (size_t)k.nbuf * fac_out_pitch(a.zst);
+        const size_t lds = sizeof(float) * (size_t)k.nbuf * kOutStage * 2 * a.zst * 32;
         if (lds > 64 * 1024) {
             e = hipFuncSetAttribute((const void *)k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
