@@ -72,10 +72,11 @@ __host__ __device__ inline long job_line(const SigJob &j, int r)
 // The band DFT factored over drive cycles (FP32 scans with one PSF table and
 // one line group): time t = n1 + P n2 with n1 < P, n2 < C, T = C P, C a
 // multiple of 32.  The R distinct residues q of the kept bins mod C take
-// 2 zst columns (re/im per residue, zst = R rounded up to 4) of the per-line
-// phase sums Y (forward) and Z (adjoint), [line][P][2 zst] floats in the
-// workspace (plus one spare line).  The forward's outer sum runs over units of at most 16 bins of
-// one residue; the adjoint's over each residue's bins, at most kQMax.
+// 2 zst columns (re/im per residue, zst = R rounded up to 4) of the phase
+// sums Y (forward) and Z (adjoint), per 32-line tile [P][2 zst][32 lines]
+// floats in the workspace (plus one spare line of P 2 zst floats).  The
+// forward's outer sum runs over units of at most 16 bins of one residue; the
+// adjoint's over each residue's bins, at most kQMax.
 constexpr int kFacWavesFwd = 8;     // waves (32-line tiles) per block of the forward line-tile kernel
                                     // (two per SIMD: one hides the other's wait at the chunk barrier)
 constexpr int kFacWavesAdj = 8;     // and of the adjoint line-tile kernel
@@ -405,7 +406,8 @@ struct OpWs {
     float *sig;       // [n_passes][L][nup] tensor PSF: the passes' symmetric line sums (forward)
     uint16_t *rtb;    // [L][nup] fp16 lines of the mixed adjoint (its backprojection gathers)
     float *rtsc;      // [L] their per-line inverse scales
-    float *fac;       // [32 ceil(L / 32) + 1][P][2 zst] phase sums of the factored band DFT (FP32)
+    float *fac;       // phase sums of the factored band DFT (FP32): ceil(L / 32) tiles of
+                      // [P][2 zst][32 lines], then a spare line of P 2 zst floats
 };
 OpWs carve_op(const mpi3d_plan *pl, void *ws);
 int check_prec(const mpi3d_plan *pl, int32_t precision);

@@ -17,14 +17,15 @@
 // Forward: fac_fwd_kernel runs the PSF contraction of a line tile chunk by
 // chunk (a chunk: 32 cycles n2 of one phase n1, PSF tables with their time
 // rows in that order) and feeds each 32 x 32 (time x line) result straight
-// into the residue DFT (table E), writing Y[row][n1][2q + re/im] once the C
-// cycles of a phase are in (Y and Z rows are the job's rows);
-// fac_fwd_out_kernel then forms b per line tile through LDS-staged Y (Y and Z
-// per line tile as [phase][column][line]), one
-// 32-column MFMA tile per unit of at most 16 bins of one residue.  Adjoint:
-// fac_adj_in_kernel forms Z (per line tile [n1][re/im][q][line]) from the data, fac_adj_kernel runs the residue DFT's transpose and the PSF
-// contraction's transpose, accumulating the lines over its phases (split
-// partial sums added in a fixed order afterwards).
+// into the residue DFT (table E), storing the phase sums Y once the C cycles
+// of a phase are in; fac_fwd_out_kernel then forms b per line tile from
+// LDS-staged Y, one 32-column MFMA tile per unit of at most 16 bins of one
+// residue.  Adjoint: fac_adj_in_kernel forms the phase sums Z from the data,
+// fac_adj_kernel runs the residue DFT's transpose and the PSF contraction's
+// transpose, accumulating the lines over its phases (split partial sums
+// added in a fixed order afterwards).  Y and Z are laid out per 32-line tile
+// as [phase][column][line] (Y's columns 2q + re/im, Z's re/im zst + q), the
+// order of an MFMA result's lines.
 //
 // MFMA operand conventions as in sig.hip: lane l supplies A[l % 32][l / 32]
 // and B[l / 32][l % 32]; result register s of lane l holds row
