@@ -574,12 +574,14 @@ extern "C" int mpi3d_plan_create(const mpi3d_geometry *g, int device, mpi3d_plan
             const long tiles = (pl->L + 31) / 32;
             f.psplit = (int)std::max<long>(1, std::min<long>({4, 256 / (tiles * f.usplit), (f.P + 7) / 8}));
             f.zsplit = (int)std::max<long>(1, std::min<long>({4, 256 / tiles, (f.P + 15) / 16}));
-            // phase ranges of the line-tile kernels (forward 8 tiles a block,
-            // adjoint 4; one block a CU either way): the fewest splits within
-            // 2% of the best time per phase
+            // phase ranges of the line-tile kernels (8 tiles a block, one block a
+            // CU): the fewest splits within 2% of the best time, counted as
+            // rounds of 256 blocks times the phases of the longest range
             auto splits = [&](int waves) {
                 const long tgroups = ((pl->L + 31) / 32 + waves - 1) / waves;
-                auto per_phase = [&](int ns) { return (double)((tgroups * ns + 255) / 256) / ns; };
+                auto per_phase = [&](int ns) {
+                    return (double)((tgroups * ns + 255) / 256) * (double)((f.P + ns - 1) / ns) / f.P;
+                };
                 double pbest = 1e30;
                 for (int ns = 1; ns <= std::min(f.P, 64); ++ns) pbest = std::min(pbest, per_phase(ns));
                 int ns = 1;
